@@ -1,0 +1,190 @@
+"""ctypes wrapper around the plain C oracle (``pll_oracle.c``).
+
+Test infrastructure only: see the package docstring.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pll_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+COUNTER_NAMES = [
+    "n", "t_bp", "entries", "bp_used", "roots", "visited", "labeled", "edges",
+    "bp_pruned", "normal_tests", "label_scanned", "root_staged", "bp_reached",
+    "bp_edges", "bp_e0", "bp_e1", "max_dist",
+]
+
+_ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "distance out of range"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle error {code}: {_ERRORS.get(code, 'unknown')}")
+        self.code = code
+
+
+def build_library(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, -O2)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _configure(lib):
+    if True:
+        P = C.c_void_p
+        lib.orc_build.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, C.POINTER(C.c_void_p)]
+        lib.orc_build.restype = C.c_int
+        lib.orc_query.argtypes = [C.c_void_p, P, C.c_int64, P]
+        lib.orc_query.restype = C.c_int
+        lib.orc_free.argtypes = [C.c_void_p]
+        lib.orc_free.restype = None
+        lib.orc_ncounters.argtypes = []
+        lib.orc_ncounters.restype = C.c_int32
+        lib.orc_counters.argtypes = [C.c_void_p, P, C.c_int32]
+        lib.orc_counters.restype = C.c_int
+        lib.orc_num_entries.argtypes = [C.c_void_p]
+        lib.orc_num_entries.restype = C.c_int64
+        lib.orc_export.argtypes = [C.c_void_p] + [P] * 10
+        lib.orc_export.restype = C.c_int
+        lib.orc_query_parts.argtypes = [C.c_void_p, P, C.c_int64, P, P]
+        lib.orc_query_parts.restype = C.c_int
+        lib.orc_root_counts.argtypes = [C.c_void_p, P, P]
+        lib.orc_root_counts.restype = C.c_int
+    return lib
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        _lib = _configure(C.CDLL(build_library()))
+    return _lib
+
+
+def load_variant(source: str, workdir: str):
+    """Compile a modified copy of the oracle source (for tests that plant a
+    mistake in the oracle and check that the pins catch it)."""
+    import hashlib
+    tag = hashlib.sha256(source.encode()).hexdigest()[:16]
+    src = os.path.join(workdir, f"orc_{tag}.c")
+    lib = os.path.join(workdir, f"liborc_{tag}.so")
+    with open(src, "w") as f:
+        f.write(source)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, src])
+    return _configure(C.CDLL(lib))
+
+
+def source_text() -> str:
+    with open(_SRC) as f:
+        return f.read()
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class OracleIndex:
+    """Exported oracle index: vertices in rank order, no sentinels."""
+    n: int
+    t_bp: int
+    off: np.ndarray      # int64[n+1]
+    hub: np.ndarray      # uint32[entries] (ranks)
+    dist: np.ndarray     # uint8[entries]
+    bp_d: np.ndarray     # uint8[n, t_bp]
+    bp_m1: np.ndarray    # uint64[n, t_bp]
+    bp_0: np.ndarray     # uint64[n, t_bp]
+    rank: np.ndarray     # int32[n]: rank of input id
+    bp_root: np.ndarray  # int32[t_bp]: rank of root, -1 if empty
+    bp_nsel: np.ndarray  # int32[t_bp]
+    bp_sel: np.ndarray   # int32[t_bp, 64]: ranks of chosen neighbours
+    counters: dict = field(default_factory=dict)
+    root_visited: np.ndarray | None = None  # int32[n] per rank (pruned phase)
+    root_labeled: np.ndarray | None = None  # int32[n] per rank
+    _handle: C.c_void_p | None = None
+
+    def label(self, r: int):
+        """(hubs, dists) of the vertex of rank r."""
+        a, b = int(self.off[r]), int(self.off[r + 1])
+        return self.hub[a:b], self.dist[a:b]
+
+    _lib: object = None
+
+    def close(self):
+        if self._handle is not None:
+            (self._lib or _load()).orc_free(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None) -> OracleIndex:
+    lib = lib or _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n = len(order)
+    if len(row_ptr) != n + 1:
+        raise OracleError(-1)
+    h = C.c_void_p()
+    rc = lib.orc_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp),
+                       1 if check_symmetric else 0, C.byref(h))
+    if rc != 0:
+        raise OracleError(rc)
+    ne = lib.orc_num_entries(h)
+    tb = max(int(t_bp), 0)
+    idx = OracleIndex(
+        n=n, t_bp=tb,
+        off=np.zeros(n + 1, np.int64), hub=np.zeros(ne, np.uint32), dist=np.zeros(ne, np.uint8),
+        bp_d=np.zeros((n, tb), np.uint8), bp_m1=np.zeros((n, tb), np.uint64),
+        bp_0=np.zeros((n, tb), np.uint64), rank=np.zeros(n, np.int32),
+        bp_root=np.zeros(tb, np.int32), bp_nsel=np.zeros(tb, np.int32),
+        bp_sel=np.zeros((tb, 64), np.int32), _handle=h)
+    idx._lib = lib
+    lib.orc_export(h, _ptr(idx.off), _ptr(idx.hub), _ptr(idx.dist), _ptr(idx.bp_d),
+                   _ptr(idx.bp_m1), _ptr(idx.bp_0), _ptr(idx.rank), _ptr(idx.bp_root),
+                   _ptr(idx.bp_nsel), _ptr(idx.bp_sel))
+    nc = lib.orc_ncounters()
+    cnt = np.zeros(nc, np.int64)
+    lib.orc_counters(h, _ptr(cnt), nc)
+    idx.counters = {k: int(v) for k, v in zip(COUNTER_NAMES, cnt)}
+    idx.root_visited = np.zeros(n, np.int32)
+    idx.root_labeled = np.zeros(n, np.int32)
+    lib.orc_root_counts(h, _ptr(idx.root_visited), _ptr(idx.root_labeled))
+    return idx
+
+
+def query(idx: OracleIndex, pairs) -> np.ndarray:
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(len(pairs), np.uint8)
+    rc = (idx._lib or _load()).orc_query(idx._handle, _ptr(pairs), len(pairs), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+def query_parts(idx: OracleIndex, pairs) -> tuple[np.ndarray, np.ndarray]:
+    """(bit-parallel part, normal-label part) of each query, unclamped ints."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    a = np.zeros(len(pairs), np.int32)
+    b = np.zeros(len(pairs), np.int32)
+    rc = (idx._lib or _load()).orc_query_parts(idx._handle, _ptr(pairs), len(pairs), _ptr(a), _ptr(b))
+    if rc != 0:
+        raise OracleError(rc)
+    return a, b

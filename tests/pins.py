@@ -1,0 +1,209 @@
+"""The oracle's pins, as reusable checks.
+
+Each check compares the oracle against something the paper or plain
+mathematics fixes, computed here by a different route (see ``brute``).  They
+return a list of human-readable failures, so the same checks can be pointed at
+a deliberately broken copy of the oracle to show they catch it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import brute
+import oracle
+from paper_1304_4661_amd import gen
+
+INF = 255
+
+
+def bp_used_ranks(ix) -> list[int]:
+    used = []
+    for i in range(ix.t_bp):
+        if ix.bp_root[i] >= 0:
+            used.append(int(ix.bp_root[i]))
+            used.extend(int(x) for x in ix.bp_sel[i, : ix.bp_nsel[i]])
+    return used
+
+
+def labels_of(ix) -> list[dict[int, int]]:
+    out = []
+    for r in range(ix.n):
+        h, d = ix.label(r)
+        out.append({int(a): int(b) for a, b in zip(h, d)})
+    return out
+
+
+def check_queries_vs_apsp(ix, g, D, lib=None) -> list[str]:
+    """Corollary of Theorem 4.1: the index answers exact distances."""
+    n = g.n
+    if n == 0:
+        return []
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    got = oracle.query(ix, pairs).astype(np.int64).reshape(n, n)
+    bad = np.argwhere(got != np.minimum(D, INF))
+    return [f"query({a},{b}) = {got[a, b]} != d = {D[a, b]}" for a, b in bad[:5]]
+
+
+def check_bp_selection(ix, g, order) -> list[str]:
+    """Greedy choice of Section 5.4: root = lowest rank not used before; S_r =
+    its unused neighbours, lowest ranks first, at most 64."""
+    fails = []
+    n = g.n
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    used = set()
+    for i in range(ix.t_bp):
+        free = [r for r in range(n) if r not in used]
+        r = int(ix.bp_root[i])
+        if not free:
+            if r != -1 or ix.bp_nsel[i] != 0:
+                fails.append(f"slot {i} should be empty")
+            continue
+        if r != free[0]:
+            fails.append(f"slot {i}: root {r} != lowest unused {free[0]}")
+            return fails
+        used.add(r)
+        v = order[r]
+        nb = sorted(int(rank[w]) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]])
+        want = [w for w in nb if w not in used][:64]
+        got = [int(x) for x in ix.bp_sel[i, : ix.bp_nsel[i]]]
+        if got != want:
+            fails.append(f"slot {i}: S_r {got} != {want}")
+        used.update(want)
+    return fails
+
+
+def check_bp_closed_form(ix, g, order, D) -> list[str]:
+    """Section 5.1 definitions of d, S^{-1} and S^{0}."""
+    if ix.t_bp == 0 or g.n == 0:
+        return []
+    Dr = D[np.ix_(order, order)]
+    roots = [int(r) for r in ix.bp_root]
+    sels = [list(ix.bp_sel[i, : ix.bp_nsel[i]]) for i in range(ix.t_bp)]
+    d, m1, m0 = brute.bp_closed_form(Dr, roots, sels)
+    fails = []
+    for name, a, b in (("bp_d", ix.bp_d, d), ("bp_m1", ix.bp_m1, m1), ("bp_0", ix.bp_0, m0)):
+        if not np.array_equal(a, b):
+            w = np.argwhere(a != b)[0]
+            fails.append(f"{name}[{w[0]},{w[1]}] = {a[w[0], w[1]]} != {b[w[0], w[1]]}")
+    return fails
+
+
+def check_canonical_labels(ix, g, order) -> list[str]:
+    """Normal labels equal their shortest-path-set characterisation."""
+    want = brute.canonical_labels(g.row_ptr, g.col, order, bp_used_ranks(ix))
+    got = labels_of(ix)
+    fails = []
+    for r in range(g.n):
+        if got[r] != want[r]:
+            fails.append(f"L(rank {r}) = {sorted(got[r].items())} != {sorted(want[r].items())}")
+            if len(fails) > 3:
+                break
+    # sortedness: hubs strictly increasing inside each label (Section 4.5.1)
+    for r in range(g.n):
+        h, _ = ix.label(r)
+        if len(h) > 1 and np.any(np.diff(h.astype(np.int64)) <= 0):
+            fails.append(f"L(rank {r}) not sorted")
+            break
+    return fails
+
+
+def check_query_parts(ix, g, order, D) -> list[str]:
+    """Bit-parallel part = explicit minimum over {r} and S_r (Section 5.3);
+    normal part = 2-hop query over the labels (Section 3.3)."""
+    n = g.n
+    if n == 0:
+        return []
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    bp, nm = oracle.query_parts(ix, pairs)
+    bp = bp.reshape(n, n)
+    nm = nm.reshape(n, n)
+    fails = []
+    Dr = D[np.ix_(order, order)]
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    # explicit bit-parallel minimum, per slot with both ends reached
+    want = np.full((n, n), INF, np.int64)
+    for i in range(ix.t_bp):
+        r = int(ix.bp_root[i])
+        if r < 0:
+            continue
+        hubs = [r] + [int(x) for x in ix.bp_sel[i, : ix.bp_nsel[i]]]
+        reach = Dr[r] < INF
+        H = Dr[hubs]  # rank space
+        via = (H[:, :, None] + H[:, None, :]).min(0)
+        via = np.where(reach[:, None] & reach[None, :], via, INF)
+        want = np.minimum(want, via)
+    want_id = want[np.ix_(rank, rank)]
+    got_bp = np.minimum(bp, INF)
+    if not np.array_equal(got_bp, np.minimum(want_id, INF)):
+        a, b = np.argwhere(got_bp != np.minimum(want_id, INF))[0]
+        fails.append(f"bp part ({a},{b}) = {got_bp[a, b]} != {want_id[a, b]}")
+    L = labels_of(ix)
+    for a in range(n):
+        for b in range(n):
+            w = brute.label_query(L[rank[a]], L[rank[b]])
+            if min(nm[a, b], INF) != w:
+                fails.append(f"normal part ({a},{b}) = {nm[a, b]} != {w}")
+                return fails
+    return fails
+
+
+def check_visited_counter(ix, g, order) -> list[str]:
+    """Visited set of root k is {v_k} plus the neighbours of the vertices it
+    labels, so the visited counter is fixed by the final labels."""
+    n = g.n
+    rank = np.empty(n, np.int64)
+    rank[order] = np.arange(n)
+    used = set(bp_used_ranks(ix))
+    A = [[] for _ in range(n)]
+    for r in range(n):
+        h, _ = ix.label(r)
+        for x in h:
+            A[int(x)].append(r)
+    total = 0
+    edges = 0
+    for k in range(n):
+        if k in used:
+            continue
+        vis = {k}
+        for r in A[k]:
+            v = order[r]
+            nb = g.col[g.row_ptr[v]:g.row_ptr[v + 1]]
+            vis.update(int(rank[w]) for w in nb)
+            edges += len(nb)
+        total += len(vis)
+    fails = []
+    if ix.counters["visited"] != total:
+        fails.append(f"visited counter {ix.counters['visited']} != {total}")
+    if ix.counters["edges"] != edges:
+        fails.append(f"edges counter {ix.counters['edges']} != {edges}")
+    if ix.counters["labeled"] != int(ix.off[-1]):
+        fails.append("labeled counter != entries")
+    return fails
+
+
+ALL = (check_queries_vs_apsp, check_bp_selection, check_bp_closed_form,
+       check_canonical_labels, check_query_parts, check_visited_counter)
+
+
+def run_all(g, order, t_bp, lib=None, checks=ALL) -> list[str]:
+    ix = oracle.build(g.row_ptr, g.col, order, t_bp, lib=lib)
+    D = brute.apsp(g.row_ptr, g.col)
+    fails = []
+    for c in checks:
+        if c is check_queries_vs_apsp:
+            fails += c(ix, g, D)
+        elif c is check_bp_selection:
+            fails += c(ix, g, order)
+        elif c in (check_bp_closed_form, check_query_parts):
+            fails += c(ix, g, order, D)
+        else:
+            fails += c(ix, g, order)
+    return fails
+
+
+def degree(g):
+    return gen.degree_order(g)

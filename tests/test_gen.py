@@ -1,0 +1,71 @@
+"""Input generators: determinism and the CSR conventions every input obeys."""
+import numpy as np
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import connected_components
+
+from paper_1304_4661_amd import gen
+
+
+def _check_csr(g):
+    rp, col = g.row_ptr, g.col
+    assert rp.dtype == np.int32 and col.dtype == np.int32
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == len(col)
+    src = np.repeat(np.arange(g.n), np.diff(rp))
+    assert np.all(src != col), "self-loop"
+    for v in range(0, g.n, max(1, g.n // 50)):
+        row = col[rp[v]:rp[v + 1]]
+        assert np.all(np.diff(row) > 0), "row not strictly sorted"
+    a = csr_matrix((np.ones(len(col)), col, rp), shape=(g.n, g.n))
+    assert (a != a.T).nnz == 0, "not symmetric"
+
+
+def test_ba_shape_and_determinism():
+    g = gen.ba_graph(500, 4, 3)
+    _check_csr(g)
+    assert g.m == 4 * (500 - 4)
+    a = csr_matrix((np.ones(len(g.col)), g.col, g.row_ptr), shape=(g.n, g.n))
+    assert connected_components(a, directed=False)[0] == 1
+    g2 = gen.ba_graph(500, 4, 3)
+    assert gen.csr_sha256(g) == gen.csr_sha256(g2)
+    assert gen.csr_sha256(g) != gen.csr_sha256(gen.ba_graph(500, 4, 4))
+
+
+def test_ba2000_named_workload():
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    assert g.n == 2000 and g.m == 7984 and t_bp == 16
+    assert pairs.shape == (100_000, 2) and pairs.min() >= 0 and pairs.max() < 2000
+
+
+def test_rmat_cleanup():
+    g = gen.rmat_graph(12, seed=9)
+    _check_csr(g)
+    a = csr_matrix((np.ones(len(g.col)), g.col, g.row_ptr), shape=(g.n, g.n))
+    assert connected_components(a, directed=False)[0] == 1
+    assert g.n <= 4096 and g.m <= 16 * 4096
+    assert gen.csr_sha256(g) == gen.csr_sha256(gen.rmat_graph(12, seed=9))
+
+
+def test_rmat_quadrant_probabilities():
+    u, v = gen.rmat_edges(1, 1 << 16, 0.57, 0.19, 0.19, seed=1)
+    q = np.bincount(u * 2 + v, minlength=4) / len(u)
+    assert np.allclose(q, [0.57, 0.19, 0.19, 0.05], atol=0.01)
+
+
+def test_degree_order_ties_by_id():
+    from graphs import from_edges
+    g = from_edges(5, [(0, 1), (2, 3), (2, 4), (1, 3)])
+    # degrees: 1,2,2,2,1
+    assert gen.degree_order(g).tolist() == [1, 2, 3, 0, 4]
+
+
+def test_batch_spec_and_pack():
+    spec = gen.batch_spec(8, n_lo=50, n_hi=400)
+    assert len(spec) == 8 and all(50 <= n <= 400 and 2 <= m <= 8 for n, m, _ in spec)
+    gs = [gen.ba_graph(n, m, s) for n, m, s in spec]
+    vtx_off, rp, col, order = gen.pack_batch(gs)
+    assert vtx_off[-1] == sum(g.n for g in gs)
+    for i, g in enumerate(gs):
+        a, b = vtx_off[i], vtx_off[i + 1]
+        assert np.array_equal(rp[a:b + 1] - rp[a], g.row_ptr)
+        assert np.array_equal(col[rp[a]:rp[b]] - a, g.col)
+        assert np.array_equal(order[a:b], gen.degree_order(g))

@@ -1,0 +1,259 @@
+"""Pins of the CPU oracle against brute force, closed forms and invariants.
+
+The oracle is only trusted as a parity reference because of these tests.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import brute
+import graphs
+import oracle
+import pins
+from paper_1304_4661_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+INF = 255
+FAMILIES = graphs.families()
+
+
+@pytest.mark.parametrize("name,g", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("t_bp", [0, 1, 2, 5, 64])
+def test_pins_degree_order(name, g, t_bp):
+    fails = pins.run_all(g, gen.degree_order(g), t_bp)
+    assert not fails, fails
+
+
+@pytest.mark.parametrize("name,g", FAMILIES[:10], ids=[f[0] for f in FAMILIES[:10]])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_pins_random_order(name, g, seed):
+    # correctness must not depend on the order (Section 4.4: any order works)
+    fails = pins.run_all(g, gen.random_order(g.n, seed), 3)
+    assert not fails, fails
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("fname", ["hand_g6_t0.json", "hand_g6_t1.json"])
+def test_golden_hand_derived(fname):
+    fx = _golden(fname)
+    g = graphs.from_edges(fx["n"], fx["edges"])
+    order = np.array(fx["order"], np.int32)
+    assert np.array_equal(order, gen.degree_order(g))
+    ix = oracle.build(g.row_ptr, g.col, order, fx["t_bp"])
+    got = [[[int(h), int(d)] for h, d in zip(*ix.label(r))] for r in range(g.n)]
+    assert got == fx["labels_by_rank"]
+    if "bp_d_by_rank" in fx:
+        assert ix.bp_d[:, 0].tolist() == fx["bp_d_by_rank"]
+        assert ix.bp_m1[:, 0].tolist() == fx["bp_m1_by_rank"]
+        assert ix.bp_0[:, 0].tolist() == fx["bp_0_by_rank"]
+        assert ix.bp_root.tolist() == fx["bp_root"]
+        assert [list(ix.bp_sel[i, : ix.bp_nsel[i]]) for i in range(ix.t_bp)] == fx["bp_sel"]
+    if "visited_per_rank" in fx:
+        assert ix.root_visited.tolist() == fx["visited_per_rank"]
+    q = np.array([[a, b] for a, b, _ in fx["queries"]], np.int32)
+    assert oracle.query(ix, q).tolist() == [c for _, _, c in fx["queries"]]
+
+
+def test_closed_form_complete_graph():
+    # K_n with t_bp = 0 and id ties: L(v_i) = {(j,1): j<i} + {(i,0)}
+    n = 9
+    g = graphs.complete(n)
+    ix = oracle.build(g.row_ptr, g.col, gen.degree_order(g), 0)
+    for i in range(n):
+        h, d = ix.label(i)
+        assert h.tolist() == list(range(i + 1))
+        assert d.tolist() == [1] * i + [0]
+
+
+def test_closed_form_star():
+    n = 20
+    g = graphs.star(n)
+    ix = oracle.build(g.row_ptr, g.col, gen.degree_order(g), 0)
+    assert [list(x) for x in zip(*ix.label(0))] == [[0, 0]]
+    for r in range(1, n):
+        h, d = ix.label(r)
+        assert h.tolist() == [0, r] and d.tolist() == [1, 0]
+
+
+def test_closed_form_star_all_bit_parallel():
+    # one slot covers the centre and all <= 64 leaves: every normal label is
+    # empty and the bit-parallel labels alone answer every query
+    n = 60
+    g = graphs.star(n)
+    ix = oracle.build(g.row_ptr, g.col, gen.degree_order(g), 1)
+    assert ix.off[-1] == 0
+    assert ix.bp_nsel[0] == n - 1
+    pairs = np.array([[0, 5], [5, 9], [7, 7], [0, 0]], np.int32)
+    assert oracle.query(ix, pairs).tolist() == [1, 2, 0, 0]
+
+
+def test_closed_form_path():
+    # path 0-1-...-(n-1), t_bp = 0: interior ids 1..n-2 get ranks 0..n-3,
+    # then vertex 0 (rank n-2) and vertex n-1 (rank n-1).  Interior u keeps
+    # every hub h <= u; vertex 0 keeps rank 0 (vertex 1) and itself; vertex
+    # n-1 keeps every interior hub and itself.
+    n = 12
+    g = graphs.path(n)
+    order = gen.degree_order(g)
+    assert order.tolist() == list(range(1, n - 1)) + [0, n - 1]
+    ix = oracle.build(g.row_ptr, g.col, order, 0)
+    for u in range(1, n - 1):
+        h, d = ix.label(u - 1)
+        assert h.tolist() == [x - 1 for x in range(1, u + 1)]
+        assert d.tolist() == [u - x for x in range(1, u + 1)]
+    h, d = ix.label(n - 2)
+    assert h.tolist() == [0, n - 2] and d.tolist() == [1, 0]
+    h, d = ix.label(n - 1)
+    assert h.tolist() == list(range(0, n - 2)) + [n - 1]
+    assert d.tolist() == [n - 1 - x for x in range(1, n - 1)] + [0]
+
+
+def test_prefix_exactness_theorem_4_1():
+    # QUERY over labels of the first k roots equals the naive landmark answer
+    # min over i < k of d(s, v_i) + d(v_i, t), for every k (t_bp = 0)
+    for g in (graphs.erdos_renyi(25, 0.15, 9), gen.ba_graph(30, 2, 5), graphs.grid(3, 5)):
+        order = gen.degree_order(g)
+        ix = oracle.build(g.row_ptr, g.col, order, 0)
+        D = brute.apsp(g.row_ptr, g.col)
+        Dr = D[np.ix_(order, order)]
+        L = pins.labels_of(ix)
+        n = g.n
+        for k in range(1, n + 1):
+            Lk = [{h: d for h, d in lab.items() if h < k} for lab in L]
+            naive = np.full((n, n), INF, np.int64)
+            for i in range(k):
+                naive = np.minimum(naive, Dr[i][:, None] + Dr[i][None, :])
+            naive = np.minimum(naive, INF)
+            for a in range(n):
+                for b in range(n):
+                    assert brute.label_query(Lk[a], Lk[b]) == naive[a, b], (k, a, b)
+
+
+def test_minimality_theorem_4_2():
+    # t_bp = 0: removing any single entry (v_j, d) from L(v_i) breaks the
+    # query between v_i and v_j
+    for g in (graphs.erdos_renyi(20, 0.2, 2), gen.ba_graph(25, 2, 3), graphs.cycle(9)):
+        order = gen.degree_order(g)
+        ix = oracle.build(g.row_ptr, g.col, order, 0)
+        D = brute.apsp(g.row_ptr, g.col)
+        Dr = D[np.ix_(order, order)]
+        L = pins.labels_of(ix)
+        for i in range(g.n):
+            for j in list(L[i]):
+                Li = dict(L[i])
+                del Li[j]
+                if i == j:
+                    assert brute.label_query(Li, L[j] if j != i else Li) != 0
+                else:
+                    assert brute.label_query(Li, L[j]) != Dr[i, j]
+
+
+def test_invariants_and_tbp_monotonicity():
+    g = gen.ba_graph(600, 3, 21)
+    order = gen.degree_order(g)
+    prev = None
+    for t in (0, 1, 2, 4, 8, 16):
+        ix = oracle.build(g.row_ptr, g.col, order, t)
+        used = set(pins.bp_used_ranks(ix))
+        L = pins.labels_of(ix)
+        for r in range(g.n):
+            h, d = ix.label(r)
+            if r in used:
+                assert len(h) == 0
+                continue
+            assert h[-1] == r and d[-1] == 0
+            assert np.all(np.diff(h.astype(np.int64)) > 0)
+            assert np.all(d[:-1] >= 1)
+        if prev is not None:
+            pix, pL = prev
+            # bit-parallel slots are a prefix of the larger run
+            assert np.array_equal(ix.bp_root[: pix.t_bp], pix.bp_root)
+            assert np.array_equal(ix.bp_d[:, : pix.t_bp], pix.bp_d)
+            # normal labels shrink as more vertices become bit-parallel
+            for r in range(g.n):
+                assert set(L[r].items()) <= set(pL[r].items())
+        prev = (ix, L)
+        rng = np.random.Generator(np.random.PCG64(t))
+        p = rng.integers(0, g.n, (500, 2)).astype(np.int32)
+        a = oracle.query(ix, p)
+        b = oracle.query(ix, p[:, ::-1].copy())
+        assert np.array_equal(a, b)
+        same = np.stack([p[:, 0], p[:, 0]], 1)
+        assert np.all(oracle.query(ix, same) == 0)
+
+
+def test_range_error_path():
+    # distances up to 254 fit in 8 bits; 255 does not (255 stands for infinity)
+    g = graphs.path(256)  # max distance from the first root: 254
+    ix = oracle.build(g.row_ptr, g.col, gen.degree_order(g), 0)
+    assert ix.counters["max_dist"] == 254
+    # answers are clamped: d(0,255) = 255 reads as 255, like "unreachable"
+    q = oracle.query(ix, np.array([[1, 255], [0, 255], [0, 254]], np.int32))
+    assert q.tolist() == [254, 255, 254]
+    g2 = graphs.path(257)
+    for t in (0, 1):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.build(g2.row_ptr, g2.col, gen.degree_order(g2), t)
+        assert e.value.code == -3
+
+
+def test_validation_errors():
+    g = graphs.cycle(5)
+    order = gen.degree_order(g)
+    bad_order = order.copy()
+    bad_order[0] = bad_order[1]
+    with pytest.raises(oracle.OracleError):
+        oracle.build(g.row_ptr, g.col, bad_order, 0)
+    col = g.col.copy()
+    col[0] = 0  # self-loop at vertex 0
+    with pytest.raises(oracle.OracleError):
+        oracle.build(g.row_ptr, col, order, 0)
+    col = g.col.copy()
+    col[0] = 7
+    with pytest.raises(oracle.OracleError):
+        oracle.build(g.row_ptr, col, order, 0)
+    rp = g.row_ptr.copy()
+    rp[2] = rp[3] + 1
+    with pytest.raises(oracle.OracleError):
+        oracle.build(rp, g.col, order, 0)
+    # asymmetric: drop one direction of an edge
+    asym = graphs.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    rp = asym.row_ptr.copy()
+    col = asym.col.copy()
+    col = np.delete(col, 0)
+    rp[1:] -= 1
+    rp[0] = 0
+    with pytest.raises(oracle.OracleError):
+        oracle.build(rp, col, np.arange(4, dtype=np.int32), 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.build(g.row_ptr, g.col, order, -1)
+    ix = oracle.build(g.row_ptr, g.col, order, 0)
+    with pytest.raises(oracle.OracleError):
+        oracle.query(ix, np.array([[0, 5]], np.int32))
+
+
+def test_empty_graph():
+    g = graphs.empty(0)
+    ix = oracle.build(g.row_ptr, g.col, np.zeros(0, np.int32), 4)
+    assert ix.n == 0 and ix.off.tolist() == [0]
+    assert oracle.query(ix, np.zeros((0, 2), np.int32)).shape == (0,)
+
+
+@pytest.mark.slow
+def test_ba2000_all_pairs_and_canonical():
+    # the small named workload: BA n=2000, m=4, t_bp=16; every one of the
+    # 4M pairs against BFS, every label against its characterisation
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ix = oracle.build(g.row_ptr, g.col, order, t_bp)
+    D = brute.apsp(g.row_ptr, g.col)
+    assert not pins.check_queries_vs_apsp(ix, g, D)
+    assert not pins.check_bp_selection(ix, g, order)
+    assert not pins.check_bp_closed_form(ix, g, order, D)
+    assert not pins.check_canonical_labels(ix, g, order)
+    assert not pins.check_visited_counter(ix, g, order)
