@@ -1,0 +1,169 @@
+/*
+ * pll.h -- C ABI of the MI355X (gfx950) Pruned Landmark Labeling library.
+ *
+ * Method: T. Akiba, Y. Iwata, Y. Yoshida, "Fast Exact Shortest-Path Distance
+ * Queries on Large Networks by Pruned Landmark Labeling", SIGMOD 2013.
+ *
+ * The library builds a 2-hop distance-labeling index of an undirected,
+ * unweighted graph (bit-parallel labels, Section 5, plus pruned-BFS labels,
+ * Section 4) on one GPU and answers exact distance queries from it
+ * (Sections 3.3 and 5.3).  Every step of the build and of the query runs in
+ * the library's own HIP kernels; the index stays in device memory.
+ *
+ * Conventions shared by all entry points
+ *   - Only fixed-width C types cross the ABI.  No C++ exception escapes.
+ *   - Return value: PLL_OK (0) or a negative PLL_E_* code.  A failed call
+ *     leaks nothing and leaves every output untouched (*out stays NULL).
+ *   - Vertex ids are int32 in [0, n).  "Rank" is the position of a vertex in
+ *     the caller's order (order[rank] = id); hubs are stored as ranks
+ *     (Section 4.5.1, "Sorting Labels").
+ *   - Distances are uint8.  255 (PLL_INF) means "unreachable"; a query whose
+ *     exact distance is 255 or more also reads 255.  A build in which some
+ *     stored distance would reach 255 fails with PLL_E_RANGE.
+ *   - stream: a hipStream_t, or NULL for the null stream.
+ *   - Not thread-safe against pll_free of the same index; queries on one
+ *     index may run concurrently from several host threads and streams.
+ */
+#ifndef PLL_H_
+#define PLL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pll_index pll_index; /* opaque; owns the index's device memory */
+
+enum {
+  PLL_OK = 0,
+  PLL_E_INVAL = -1,       /* bad argument, detected before any device work */
+  PLL_E_NOMEM = -2,       /* host or device allocation failed */
+  PLL_E_RANGE = -3,       /* a stored distance would reach 255 */
+  PLL_E_DEVICE = -4,      /* a HIP call failed */
+  PLL_E_UNSUPPORTED = -5  /* valid request this build does not handle */
+};
+
+#define PLL_INF 255u
+#define PLL_MAX_TBP 64 /* bit-parallel slots: one 64-bit word per set (b = 64) */
+
+/* flags */
+#define PLL_DEVICE_PTRS 1u /* pll_query*: pairs and out are device pointers */
+#define PLL_VALIDATE 2u    /* pll_build*: also check that the graph is symmetric */
+#define PLL_SYNC 4u        /* block until the call's device work is complete */
+#define PLL_PLAIN 8u       /* plain forms: build one root at a time (no
+                              concurrent roots); query one thread per pair */
+
+/*
+ * Build the index of one graph (Algorithm 2 with the bit-parallel phase of
+ * Section 5.4 in front).
+ *   n        number of vertices (>= 0)
+ *   row_ptr  host int32[n+1], CSR row offsets: row_ptr[0] = 0, non-decreasing
+ *   col      host int32[row_ptr[n]], neighbour ids; the graph must be
+ *            symmetric (each edge in both rows) with no self-loops;
+ *            repeated edges are allowed
+ *   order    host int32[n], a permutation: order[i] is the vertex of rank i
+ *            (Section 4.4; pruned BFSs run in this order)
+ *   t_bp     number of bit-parallel roots, 0..PLL_MAX_TBP (Section 5.4: the
+ *            root is the lowest-rank unused vertex, its up to 64 lowest-rank
+ *            unused neighbours form S_r; an exhausted slot stays empty)
+ *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC
+ *   out      receives the new index on success
+ * The inputs are copied; the caller may free them when the call returns.
+ * Errors: PLL_E_INVAL (bad CSR, self-loop, out-of-range id, order not a
+ * permutation, t_bp outside 0..64, asymmetric graph under PLL_VALIDATE),
+ * PLL_E_RANGE, PLL_E_NOMEM, PLL_E_DEVICE.  The build always synchronises
+ * the stream before returning.
+ */
+int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+              int32_t t_bp, uint32_t flags, void *stream, pll_index **out);
+
+/*
+ * Answer q distance queries (Section 3.3 merge join over the normal labels,
+ * Section 5.3 bit-parallel rule): out[i] = min(d(pairs[2i], pairs[2i+1]), 255).
+ *   pairs  int32[2q], ids (s0,t0,s1,t1,...); host memory, or device memory
+ *          under PLL_DEVICE_PTRS
+ *   out    uint8[q], same memory kind as pairs
+ *   flags  PLL_DEVICE_PTRS, PLL_SYNC, PLL_PLAIN
+ * Host pointers: validated on the host, copied, and the call synchronises.
+ * Device pointers: a validation kernel runs first; if any id is out of range
+ * nothing is written and the error is returned by this call under PLL_SYNC,
+ * else by the next pll_sync on the index.  The caller keeps device buffers
+ * alive until the stream passes the call.
+ * Errors: PLL_E_INVAL (null index, q < 0, id out of range), PLL_E_NOMEM,
+ * PLL_E_DEVICE.
+ */
+int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+              uint32_t flags, void *stream);
+
+/*
+ * Wait for the index's work on stream and return (and clear) the error
+ * recorded by earlier asynchronous pll_query calls with device pointers.
+ */
+int pll_sync(const pll_index *idx, void *stream);
+
+/*
+ * Sizes of one graph of the index for pll_export: vertices, normal label
+ * entries (no sentinels) and bit-parallel slots.  graph is 0 for an index
+ * made by pll_build.  Any pointer may be NULL.
+ */
+int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *entries,
+                     int32_t *t_bp);
+
+/*
+ * Copy one graph's index to host memory in the canonical layout used for
+ * bit-exact comparison: vertices in rank order; off int64[n+1] (off[0] = 0),
+ * hub uint32[entries] (hub ranks, ascending within each vertex), dist
+ * uint8[entries], no sentinels (Section 4.5.2 keeps a sentinel in storage
+ * only); bp_d uint8[n][t_bp], bp_m1 / bp_0 uint64[n][t_bp] (the S^{-1} and
+ * S^{0} sets of Section 5.1, bit j = j-th chosen neighbour in ascending rank).
+ * Any output pointer may be NULL to skip that array.  rank: int32[n] id->rank.
+ */
+int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
+               uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);
+
+/*
+ * Work counters of the build (PLL_STAT_* below), for reporting and for the
+ * algorithmic-byte model.  Copies min(ncounters, PLL_NSTATS) values.
+ */
+enum {
+  PLL_STAT_N = 0,        /* vertices */
+  PLL_STAT_TBP,          /* bit-parallel slots */
+  PLL_STAT_ENTRIES,      /* normal label entries, no sentinels */
+  PLL_STAT_BP_USED,      /* vertices used as bit-parallel roots or neighbours */
+  PLL_STAT_ROOTS,        /* pruned BFSs run */
+  PLL_STAT_VISITED,      /* (root, vertex) visits of the pruned phase */
+  PLL_STAT_CANDIDATES,   /* labels appended before cleaning */
+  PLL_STAT_WINDOWS,      /* root windows */
+  PLL_STAT_RETRIES,      /* windows re-run smaller after overflow */
+  PLL_STAT_BP_VISITED,   /* (slot, vertex) visits of the bit-parallel phase */
+  PLL_STAT_LEVELS,       /* level kernels launched */
+  PLL_STAT_INDEX_BYTES,  /* device bytes of the finished index */
+  PLL_STAT_BUILD_NS,     /* wall time of the build, ns */
+  PLL_STAT_BP_NS,        /* bit-parallel phase, ns */
+  PLL_STAT_PRUNED_NS,    /* pruned phase, ns */
+  PLL_NSTATS
+};
+int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
+
+/* Release the index and all its device memory.  NULL is ignored. */
+void pll_free(pll_index *idx);
+
+/* Static description of an error code. */
+const char *pll_strerror(int code);
+
+/*
+ * Tuning knobs (process-wide): "window" (max concurrent roots, 1..1024),
+ * "group" (lanes per frontier vertex: 4,8,16,32,64), "chunk" (edges a
+ * group expands inline before handing the rest to whole waves), "qgroup"
+ * (lanes per query pair: 16, 32, 64).  Returns PLL_E_INVAL for an unknown
+ * key or value.
+ */
+int pll_set_tuning(const char *key, int64_t value);
+int64_t pll_get_tuning(const char *key);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PLL_H_ */

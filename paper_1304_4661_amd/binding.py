@@ -1,0 +1,186 @@
+"""Python binding of ``libpll.so`` (the C ABI in include/pll.h).
+
+Argument marshalling only: every step of the build and of the queries runs in
+the library's HIP kernels.  If the library is missing this module raises; there
+is no CPU fallback.  PyTorch is used only to hand device buffers and streams to
+the library (``query_device``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpll.so")
+
+OK, E_INVAL, E_NOMEM, E_RANGE, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+INF = 255
+MAX_TBP = 64
+DEVICE_PTRS, VALIDATE, SYNC, PLAIN = 1, 2, 4, 8
+
+STAT_NAMES = [
+    "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
+    "retries", "bp_visited", "levels", "index_bytes", "build_ns", "bp_ns", "pruned_ns",
+]
+
+EXPORTED = [
+    "pll_build", "pll_query", "pll_sync", "pll_export_sizes", "pll_export", "pll_stats",
+    "pll_free", "pll_strerror", "pll_set_tuning", "pll_get_tuning",
+]
+
+
+class PllError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = _lib().pll_strerror(code).decode() if _LIB is not None else str(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+        self.code = code
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        lib.pll_build.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, P, C.POINTER(C.c_void_p)]
+        lib.pll_build.restype = C.c_int
+        lib.pll_query.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
+        lib.pll_query.restype = C.c_int
+        lib.pll_sync.argtypes = [P, P]
+        lib.pll_sync.restype = C.c_int
+        lib.pll_export_sizes.argtypes = [P, C.c_int32, P, P, P]
+        lib.pll_export_sizes.restype = C.c_int
+        lib.pll_export.argtypes = [P, C.c_int32, P, P, P, P, P, P, P]
+        lib.pll_export.restype = C.c_int
+        lib.pll_stats.argtypes = [P, C.c_int32, P, C.c_int32]
+        lib.pll_stats.restype = C.c_int
+        lib.pll_free.argtypes = [P]
+        lib.pll_free.restype = None
+        lib.pll_strerror.argtypes = [C.c_int]
+        lib.pll_strerror.restype = C.c_char_p
+        lib.pll_set_tuning.argtypes = [C.c_char_p, C.c_int64]
+        lib.pll_set_tuning.restype = C.c_int
+        lib.pll_get_tuning.argtypes = [C.c_char_p]
+        lib.pll_get_tuning.restype = C.c_int64
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        raise PllError(rc, what)
+
+
+def set_tuning(key: str, value: int):
+    _check(_lib().pll_set_tuning(key.encode(), int(value)), f"set_tuning({key})")
+
+
+def get_tuning(key: str) -> int:
+    return int(_lib().pll_get_tuning(key.encode()))
+
+
+class Index:
+    """A device-resident index made by :func:`build`."""
+
+    def __init__(self, handle: C.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib().pll_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query(self, pairs, plain: bool = False) -> np.ndarray:
+        """Host arrays in and out: ``pairs`` int32[q, 2] ids -> uint8[q]."""
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros(len(pairs), np.uint8)
+        flags = PLAIN if plain else 0
+        _check(_lib().pll_query(self._h, _ptr(pairs), len(pairs), _ptr(out), flags, None), "query")
+        return out
+
+    def query_device(self, pairs, out, stream=None, plain: bool = False, sync: bool = False):
+        """Device tensors (torch): ``pairs`` int32 [q, 2] and ``out`` uint8 [q]
+        on the GPU; runs on ``stream`` (a torch stream, default current)."""
+        import torch
+
+        assert pairs.dtype == torch.int32 and out.dtype == torch.uint8
+        assert pairs.is_cuda and out.is_cuda and pairs.is_contiguous() and out.is_contiguous()
+        q = out.numel()
+        assert pairs.numel() == 2 * q
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        flags = DEVICE_PTRS | (PLAIN if plain else 0) | (SYNC if sync else 0)
+        _check(_lib().pll_query(self._h, C.c_void_p(pairs.data_ptr()), q,
+                                C.c_void_p(out.data_ptr()), flags,
+                                C.c_void_p(stream.cuda_stream)), "query_device")
+
+    def sync(self, stream=None):
+        s = None if stream is None else C.c_void_p(stream.cuda_stream)
+        _check(_lib().pll_sync(self._h, s), "sync")
+
+    def sizes(self):
+        n, e, t = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(_lib().pll_export_sizes(self._h, 0, C.byref(n), C.byref(e), C.byref(t)), "sizes")
+        return n.value, e.value, t.value
+
+    def export(self) -> dict:
+        """Canonical host copy: rank order, no sentinels (see include/pll.h)."""
+        n, e, t = self.sizes()
+        out = {
+            "off": np.zeros(n + 1, np.int64), "hub": np.zeros(e, np.uint32),
+            "dist": np.zeros(e, np.uint8), "bp_d": np.zeros((n, t), np.uint8),
+            "bp_m1": np.zeros((n, t), np.uint64), "bp_0": np.zeros((n, t), np.uint64),
+            "rank": np.zeros(n, np.int32),
+        }
+        _check(_lib().pll_export(self._h, 0, *(_ptr(out[k]) for k in
+                                                ("off", "hub", "dist", "bp_d", "bp_m1", "bp_0",
+                                                 "rank"))), "export")
+        return out
+
+    def stats(self) -> dict:
+        c = np.zeros(len(STAT_NAMES), np.int64)
+        _check(_lib().pll_stats(self._h, 0, _ptr(c), len(c)), "stats")
+        return {k: int(v) for k, v in zip(STAT_NAMES, c)}
+
+
+def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = False,
+          stream=None) -> Index:
+    """Build the index of one graph (host CSR and order, see include/pll.h)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n = len(order)
+    if len(row_ptr) != n + 1:
+        raise PllError(E_INVAL, "build: row_ptr length")
+    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0)
+    h = C.c_void_p()
+    s = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = _lib().pll_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp), flags, s,
+                          C.byref(h))
+    _check(rc, "build")
+    return Index(h)

@@ -1,0 +1,675 @@
+// Host side of the C ABI (include/pll.h): argument validation, device
+// memory, the level loops of both BFS phases, the root-window loop of the
+// pruned phase, finalisation, queries, export and statistics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pll_internal.h"
+
+using namespace pll;
+
+namespace {
+
+struct Tuning {
+  int window = 1024;  // concurrent roots of the pruned phase
+  int group = 16;     // lanes per frontier entry
+  int chunk = 256;    // edges expanded inline before splitting into tasks
+  int qgroup = 64;    // lanes per query pair
+  int levels_per_sync = 4;
+};
+Tuning g_tune;
+std::mutex g_tune_mu;
+
+Tuning tuning() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return g_tune;
+}
+
+// Thrown internally, turned into a return code at the ABI boundary.
+struct Fail {
+  int code;
+};
+
+void check(hipError_t e) {
+  if (e == hipErrorOutOfMemory) throw Fail{PLL_E_NOMEM};
+  if (e != hipSuccess) throw Fail{PLL_E_DEVICE};
+}
+
+// Owning device buffer.
+template <typename T>
+struct DBuf {
+  T *p = nullptr;
+  size_t count = 0;
+  DBuf() = default;
+  explicit DBuf(size_t c) { alloc(c); }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : p(o.p), count(o.count) {
+    o.p = nullptr;
+    o.count = 0;
+  }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      count = o.count;
+      o.p = nullptr;
+      o.count = 0;
+    }
+    return *this;
+  }
+  void alloc(size_t c) {
+    reset();
+    count = c;
+    size_t bytes = std::max<size_t>(c * sizeof(T), 1);
+    hipError_t e = hipMalloc((void **)&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      count = 0;
+      (void)hipGetLastError();
+      throw Fail{e == hipErrorOutOfMemory ? PLL_E_NOMEM : PLL_E_DEVICE};
+    }
+  }
+  void reset() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    count = 0;
+  }
+  ~DBuf() { reset(); }
+  size_t bytes() const { return count * sizeof(T); }
+};
+
+template <typename T>
+void h2d(T *dst, const T *src, size_t count, hipStream_t st) {
+  if (count) check(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+}
+template <typename T>
+void d2h(T *dst, const T *src, size_t count, hipStream_t st) {
+  if (count) check(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+template <typename T>
+void fill(DBuf<T> &b, int byte, hipStream_t st) {
+  if (b.count) check(hipMemsetAsync(b.p, byte, b.bytes(), st));
+}
+
+using Clock = std::chrono::steady_clock;
+int64_t ns_since(Clock::time_point t0) {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+struct pll_index {
+  int32_t n = 0, t = 0;
+  DBuf<int32_t> rank;  // id -> rank
+  DBuf<uint8_t> bpd;   // [n][t]
+  DBuf<uint64_t> bpm;  // [n][t][2]
+  DBuf<int64_t> off;   // [n+1], sentinel-inclusive CSR
+  DBuf<uint32_t> hub;
+  DBuf<uint8_t> dist;
+  DBuf<int32_t> err;  // sticky error of asynchronous device-pointer queries
+  int64_t entries = 0;
+  int64_t stats[PLL_NSTATS] = {};
+  std::vector<int32_t> bp_root, bp_nsel, bp_sel;
+
+  DIndex view() const {
+    DIndex v;
+    v.n = n;
+    v.t = t;
+    v.rank = rank.p;
+    v.bpd = bpd.p;
+    v.bpm = bpm.p;
+    v.off = off.p;
+    v.hub = hub.p;
+    v.dist = dist.p;
+    return v;
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Validation (before any device work).
+
+int validate_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+                   int32_t t_bp, bool symmetric) {
+  if (n < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP) return PLL_E_INVAL;
+  if (n == 0) return PLL_OK;
+  if (!row_ptr || !order) return PLL_E_INVAL;
+  if (row_ptr[0] != 0) return PLL_E_INVAL;
+  for (int32_t v = 0; v < n; v++)
+    if (row_ptr[v + 1] < row_ptr[v]) return PLL_E_INVAL;
+  const int64_t nnz = row_ptr[n];
+  if (nnz > 0 && !col) return PLL_E_INVAL;
+  for (int32_t v = 0; v < n; v++)
+    for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++)
+      if (col[j] < 0 || col[j] >= n || col[j] == v) return PLL_E_INVAL;
+  std::vector<char> seen((size_t)n, 0);
+  for (int32_t i = 0; i < n; i++) {
+    if (order[i] < 0 || order[i] >= n || seen[order[i]]) return PLL_E_INVAL;
+    seen[order[i]] = 1;
+  }
+  if (symmetric) {
+    std::vector<int32_t> sorted(col, col + nnz);
+    for (int32_t v = 0; v < n; v++) std::sort(sorted.begin() + row_ptr[v], sorted.begin() + row_ptr[v + 1]);
+    for (int32_t v = 0; v < n; v++)
+      for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++) {
+        const int32_t w = sorted[j];
+        if (!std::binary_search(sorted.begin() + row_ptr[w], sorted.begin() + row_ptr[w + 1], v))
+          return PLL_E_INVAL;
+      }
+  }
+  return PLL_OK;
+}
+
+// Reads a LevelCtl back to the host (synchronising the stream).
+void read_ctl(LevelCtl *h, const LevelCtl *d, hipStream_t st) {
+  check(hipMemcpyAsync(h, d, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
+  check(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// The build of one graph, in rank space, into `ix`.
+
+struct Builder {
+  hipStream_t st;
+  Tuning tu;
+  bool plain;
+  int32_t n, t, nwords;
+  int64_t nnz;
+  DBuf<int64_t> row;
+  DBuf<int32_t> col;
+  DBuf<uint8_t> used;
+  int64_t stat_levels = 0, stat_bp_visited = 0, stat_visited = 0, stat_cand = 0,
+          stat_windows = 0, stat_retries = 0, stat_roots = 0;
+
+  DGraph graph() const { return DGraph{n, nwords, row.p, col.p}; }
+
+  // a1: rank[order[i]] = i; rank-space CSR
+  void relabel(const int32_t *h_row, const int32_t *h_col, const int32_t *h_order,
+               pll_index *ix) {
+    DBuf<int32_t> in_row((size_t)n + 1), in_col((size_t)std::max<int64_t>(nnz, 1)),
+        order((size_t)n);
+    h2d(in_row.p, h_row, (size_t)n + 1, st);
+    h2d(in_col.p, h_col, (size_t)nnz, st);
+    h2d(order.p, h_order, (size_t)n, st);
+    ix->rank.alloc((size_t)n);
+    check(launch_iota_rank(order.p, ix->rank.p, n, st));
+    DBuf<int64_t> deg((size_t)n), tmp((size_t)scan_tmp_elems(n));
+    row.alloc((size_t)n + 1);
+    col.alloc((size_t)std::max<int64_t>(nnz, 1));
+    check(launch_degrees(in_row.p, order.p, deg.p, n, st));
+    check(launch_exclusive_scan(deg.p, row.p, n, tmp.p, st));
+    check(launch_relabel_cols(in_row.p, in_col.p, order.p, ix->rank.p, row.p, col.p, n, st));
+    check(hipStreamSynchronize(st));
+  }
+
+  // a2 + a3: bit-parallel roots and BFSs
+  void bit_parallel(pll_index *ix) {
+    used.alloc((size_t)n);
+    fill(used, 0, st);
+    ix->bpd.alloc((size_t)n * t);
+    ix->bpm.alloc((size_t)n * t * 2);
+    ix->bp_root.assign((size_t)t, -1);
+    ix->bp_nsel.assign((size_t)t, 0);
+    ix->bp_sel.assign((size_t)t * 64, -1);
+    if (t == 0) return;
+    DBuf<uint32_t> used_bits((size_t)nwords), tmp_bits((size_t)nwords);
+    DBuf<int32_t> root((size_t)t), nsel((size_t)t), sel((size_t)t * 64);
+    fill(used_bits, 0, st);
+    fill(tmp_bits, 0, st);
+    fill(sel, 0xFF, st);
+    check(launch_bp_select(graph(), t, used_bits.p, tmp_bits.p, used.p, root.p, nsel.p, sel.p,
+                           st));
+    d2h(ix->bp_root.data(), root.p, (size_t)t, st);
+    d2h(ix->bp_nsel.data(), nsel.p, (size_t)t, st);
+    d2h(ix->bp_sel.data(), sel.p, (size_t)t * 64, st);
+    check(hipStreamSynchronize(st));
+
+    // slot-major working arrays
+    DBuf<uint8_t> bd((size_t)t * n);
+    DBuf<uint64_t> bs1((size_t)t * n), bs0((size_t)t * n);
+    DBuf<uint32_t> vis((size_t)t * nwords);
+    fill(bd, 0xFF, st);
+    fill(bs1, 0, st);
+    fill(bs0, 0, st);
+    fill(vis, 0, st);
+    // frontier: every (slot, vertex) is visited at most once
+    const int64_t fcap = std::max<int64_t>((int64_t)t * n, 1);
+    const int64_t hcap = std::max<int64_t>((int64_t)t * (nnz / tu.chunk + 1), 1);
+    DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap);
+    DBuf<int32_t> h1((size_t)hcap * 3), h2((size_t)hcap * 3);
+    DBuf<LevelCtl> ctl(1);
+    // levels 0 and 1 start with the roots and their chosen neighbours
+    std::vector<int32_t> s0, v0, s1, v1;
+    for (int32_t i = 0; i < t; i++) {
+      if (ix->bp_root[i] < 0) continue;
+      s0.push_back(i);
+      v0.push_back(ix->bp_root[i]);
+      for (int32_t j = 0; j < ix->bp_nsel[i]; j++) {
+        s1.push_back(i);
+        v1.push_back(ix->bp_sel[(size_t)i * 64 + j]);
+      }
+    }
+    std::vector<int32_t> fs(s0), fvv(v0);
+    fs.insert(fs.end(), s1.begin(), s1.end());
+    fvv.insert(fvv.end(), v1.begin(), v1.end());
+    h2d(fslot.p, fs.data(), fs.size(), st);
+    h2d(fv.p, fvv.data(), fvv.size(), st);
+    LevelCtl h{};
+    h.cnt[0] = s0.size();
+    h.cnt[1] = s1.size();
+    h.base[0] = 0;
+    h.base[1] = s0.size();
+    check(hipMemcpyAsync(ctl.p, &h, sizeof(LevelCtl), hipMemcpyHostToDevice, st));
+    DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
+                h2.p, h2.p + hcap, h2.p + 2 * hcap, ctl.p};
+    check(launch_bp_init(graph(), t, root.p, nsel.p, sel.p, nullptr, bd.p, bs1.p, vis.p, f, st));
+    int L = 0;
+    bool done = s0.empty();
+    while (!done) {
+      const int upto = std::min(L + tu.levels_per_sync, kMaxLevels - 1);
+      for (; L < upto; L++) {
+        check(launch_bp_level(graph(), t, L, tu.group, tu.chunk, bd.p, bs1.p, bs0.p, vis.p, f,
+                              st));
+        stat_levels++;
+      }
+      read_ctl(&h, ctl.p, st);
+      if (h.flags & kFlagRange) throw Fail{PLL_E_RANGE};
+      if (h.flags) throw Fail{PLL_E_NOMEM};
+      if (h.cnt[L] == 0 || L >= kMaxLevels - 1) done = true;
+    }
+    for (int i = 0; i < kMaxLevels + 2; i++) stat_bp_visited += (int64_t)h.cnt[i];
+    check(launch_bp_finish(n, t, bd.p, bs1.p, bs0.p, ix->bpd.p, ix->bpm.p, st));
+    check(hipStreamSynchronize(st));
+  }
+
+  // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR
+  void pruned(pll_index *ix) {
+    const int wmax = plain ? 1 : std::max(1, std::min(tu.window, kMaxWindow));
+    const int words = (wmax + 63) / 64;
+    const int64_t wstride = (int64_t)words * 64;
+    // growing label store
+    DBuf<int64_t> soff((size_t)n);
+    DBuf<int32_t> slen((size_t)n), scap((size_t)n);
+    fill(soff, 0, st);
+    fill(slen, 0, st);
+    fill(scap, 0, st);
+    int64_t pool_cap = std::max<int64_t>(16 * (int64_t)n, 1 << 16);
+    DBuf<uint32_t> phub((size_t)pool_cap);
+    DBuf<uint8_t> pdist((size_t)pool_cap);
+    DBuf<unsigned long long> top(1);
+    fill(top, 0, st);
+    // window state
+    DBuf<uint32_t> vis((size_t)wmax * nwords);
+    DBuf<uint8_t> T((size_t)wmax * n), wd((size_t)n * wstride);
+    DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words);
+    fill(vis, 0, st);
+    fill(T, 0xFF, st);
+    fill(wd, 0xFF, st);
+    fill(cmask, 0, st);
+    fill(kmask, 0, st);
+    const int64_t fcap = std::max<int64_t>(2 * (int64_t)n + 64,
+                                           std::min<int64_t>((int64_t)wmax * n, 96ll << 20));
+    const int64_t hcap = std::max<int64_t>((int64_t)n + nnz / tu.chunk + 64,
+                                           std::min<int64_t>((int64_t)wmax * (nnz / tu.chunk + 1),
+                                                             16ll << 20));
+    const int64_t ccap = std::max<int64_t>((int64_t)n + 64,
+                                           std::min<int64_t>((int64_t)wmax * n, 32ll << 20));
+    DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap), h1((size_t)hcap * 3);
+    DBuf<int32_t> cu((size_t)ccap), cj((size_t)ccap);
+    DBuf<uint8_t> cd((size_t)ccap), cdes((size_t)ccap);
+    DBuf<LevelCtl> ctl(1);
+    DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
+                nullptr, nullptr, nullptr, ctl.p};
+    DBp bp{t, ix->bpd.p, ix->bpm.p};
+    LevelCtl h{};
+    int64_t entries_bound = 0;
+    unsigned long long htop = 0;
+
+    int32_t s = 0;
+    int W = wmax;
+    while (s < n) {
+      const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
+      const int32_t nr = e - s;
+      DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
+      DWindow w{s, nr, words, vis.p, T.p, wd.p, cmask.p, kmask.p, cu.p, cj.p, cd.p, cdes.p, ccap,
+                used.p};
+      check(launch_win_reset_ctl(ctl.p, st));
+      check(launch_win_init(graph(), w, sto, f, nr, st));
+      int d = 0;
+      bool done = false;
+      while (!done) {
+        const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
+        for (; d < upto; d++) {
+          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.chunk, st));
+          stat_levels++;
+        }
+        read_ctl(&h, ctl.p, st);
+        check(hipMemcpyAsync(&htop, top.p, sizeof(htop), hipMemcpyDeviceToHost, st));
+        check(hipStreamSynchronize(st));
+        if (h.flags || h.cnt[d] == 0 || d >= kMaxLevels - 1) done = true;
+      }
+      int64_t nvisited = 0;
+      for (int i = 0; i <= d; i++) nvisited += (int64_t)h.cnt[i];
+      const int64_t ncand = std::min<int64_t>((int64_t)h.ccnt, ccap);
+      if (h.flags) {
+        // undo the window and run it again with fewer roots
+        check(launch_win_reset(graph(), w, sto, f, nr, std::min(nvisited, fcap), st));
+        check(launch_win_abort(graph(), w, ncand, st));
+        if (h.flags & kFlagOvfFrontier) fill(vis, 0, st);
+        check(hipStreamSynchronize(st));
+        if (W == 1) throw Fail{(h.flags & kFlagRange) ? PLL_E_RANGE : PLL_E_NOMEM};
+        W = std::max(1, W / 4);
+        stat_retries++;
+        continue;
+      }
+      // make sure the commit can grow every touched label without running
+      // out of pool: each vertex takes at most 2*(len+new)+32 slots
+      const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
+      if (pool_cap - (int64_t)htop < need) {
+        const int64_t ncap = std::max<int64_t>(2 * pool_cap, (int64_t)htop + 2 * need);
+        DBuf<uint32_t> nh((size_t)ncap);
+        DBuf<uint8_t> nd((size_t)ncap);
+        check(hipMemcpyAsync(nh.p, phub.p, (size_t)htop * sizeof(uint32_t),
+                             hipMemcpyDeviceToDevice, st));
+        check(hipMemcpyAsync(nd.p, pdist.p, (size_t)htop, hipMemcpyDeviceToDevice, st));
+        check(hipStreamSynchronize(st));
+        phub = std::move(nh);
+        pdist = std::move(nd);
+        pool_cap = ncap;
+        sto = DStore{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
+      }
+      check(launch_win_reset(graph(), w, sto, f, nr, nvisited, st));
+      check(launch_win_clean(w, ncand, st));
+      check(launch_win_commit(w, sto, ncand, st));
+      entries_bound += ncand;
+      stat_visited += (int64_t)h.visited;
+      stat_cand += ncand;
+      stat_windows++;
+      s = e;
+      if (W < wmax) W = std::min(wmax, W * 2);
+    }
+    check(hipStreamSynchronize(st));
+    {
+      std::vector<uint8_t> hused((size_t)n);
+      d2h(hused.data(), used.p, (size_t)n, st);
+      check(hipStreamSynchronize(st));
+      for (uint8_t x : hused) stat_roots += x ? 0 : 1;
+    }
+
+    // a5: final CSR with sentinels
+    DBuf<int64_t> cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
+    ix->off.alloc((size_t)n + 1);
+    check(launch_final_count(slen.p, cnt.p, n, st));
+    check(launch_exclusive_scan(cnt.p, ix->off.p, n, tmp.p, st));
+    int64_t total = 0;
+    if (n > 0) d2h(&total, ix->off.p + n, 1, st);
+    check(hipStreamSynchronize(st));
+    ix->hub.alloc((size_t)std::max<int64_t>(total, 1));
+    ix->dist.alloc((size_t)std::max<int64_t>(total, 1));
+    DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
+    check(launch_final_copy(sto, ix->off.p, ix->hub.p, ix->dist.p, n, st));
+    check(hipStreamSynchronize(st));
+    ix->entries = total - n;
+  }
+};
+
+int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+              int32_t t_bp, uint32_t flags, hipStream_t st, pll_index *ix) {
+  const auto t0 = Clock::now();
+  Builder b;
+  b.st = st;
+  b.tu = tuning();
+  b.plain = (flags & PLL_PLAIN) != 0;
+  b.n = n;
+  b.t = t_bp;
+  b.nwords = (n + 31) / 32;
+  b.nnz = n > 0 ? row_ptr[n] : 0;
+  ix->n = n;
+  ix->t = t_bp;
+  b.relabel(row_ptr, col, order, ix);
+  const auto t1 = Clock::now();
+  b.bit_parallel(ix);
+  const int64_t bp_ns = ns_since(t1);
+  const auto t2 = Clock::now();
+  b.pruned(ix);
+  const int64_t pr_ns = ns_since(t2);
+  ix->err.alloc(1);
+  check(hipMemsetAsync(ix->err.p, 0, sizeof(int32_t), st));
+  check(hipStreamSynchronize(st));
+  int64_t bp_used = 0;
+  for (int32_t i = 0; i < t_bp; i++) bp_used += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
+  int64_t *S = ix->stats;
+  S[PLL_STAT_N] = n;
+  S[PLL_STAT_TBP] = t_bp;
+  S[PLL_STAT_ENTRIES] = ix->entries;
+  S[PLL_STAT_BP_USED] = bp_used;
+  S[PLL_STAT_ROOTS] = b.stat_roots;
+  S[PLL_STAT_VISITED] = b.stat_visited;
+  S[PLL_STAT_CANDIDATES] = b.stat_cand;
+  S[PLL_STAT_WINDOWS] = b.stat_windows;
+  S[PLL_STAT_RETRIES] = b.stat_retries;
+  S[PLL_STAT_BP_VISITED] = b.stat_bp_visited;
+  S[PLL_STAT_LEVELS] = b.stat_levels;
+  S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->bpd.bytes() + ix->bpm.bytes() +
+                                      ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes());
+  S[PLL_STAT_BP_NS] = bp_ns;
+  S[PLL_STAT_PRUNED_NS] = pr_ns;
+  S[PLL_STAT_BUILD_NS] = ns_since(t0);
+  return PLL_OK;
+}
+
+template <typename F>
+int guarded(F &&fn) {
+  try {
+    return fn();
+  } catch (const Fail &f) {
+    (void)hipGetLastError();
+    return f.code;
+  } catch (const std::bad_alloc &) {
+    return PLL_E_NOMEM;
+  } catch (...) {
+    return PLL_E_DEVICE;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+
+extern "C" {
+
+int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+              int32_t t_bp, uint32_t flags, void *stream, pll_index **out) {
+  if (!out) return PLL_E_INVAL;
+  *out = nullptr;
+  int rc = validate_graph(n, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
+  if (rc != PLL_OK) return rc;
+  pll_index *ix = new (std::nothrow) pll_index();
+  if (!ix) return PLL_E_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  rc = guarded([&] { return build_one(n, row_ptr, col, order, t_bp, flags, st, ix); });
+  if (rc != PLL_OK) {
+    (void)hipStreamSynchronize(st);
+    delete ix;
+    return rc;
+  }
+  *out = ix;
+  return PLL_OK;
+}
+
+int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out, uint32_t flags,
+              void *stream) {
+  if (!idx || q < 0) return PLL_E_INVAL;
+  if (q == 0) return PLL_OK;
+  if (!pairs || !out) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Tuning tu = tuning();
+  const bool plain = (flags & PLL_PLAIN) != 0;
+  if (!(flags & PLL_DEVICE_PTRS)) {
+    for (int64_t i = 0; i < 2 * q; i++)
+      if (pairs[i] < 0 || pairs[i] >= idx->n) return PLL_E_INVAL;
+    return guarded([&] {
+      DBuf<int32_t> dp((size_t)(2 * q));
+      DBuf<uint8_t> dout((size_t)q);
+      h2d(dp.p, pairs, (size_t)(2 * q), st);
+      check(launch_query(idx->view(), dp.p, q, dout.p, nullptr, plain, tu.qgroup, st));
+      d2h(out, dout.p, (size_t)q, st);
+      check(hipStreamSynchronize(st));
+      return PLL_OK;
+    });
+  }
+  return guarded([&] {
+    int32_t *err = nullptr;
+    check(hipMallocAsync((void **)&err, sizeof(int32_t), st));
+    check(hipMemsetAsync(err, 0, sizeof(int32_t), st));
+    check(launch_validate_pairs(pairs, q, idx->n, err, st));
+    check(launch_query(idx->view(), pairs, q, out, err, plain, tu.qgroup, st));
+    int32_t herr = 0;
+    if (flags & PLL_SYNC) {
+      check(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      check(hipFreeAsync(err, st));
+      check(hipStreamSynchronize(st));
+      return herr ? PLL_E_INVAL : PLL_OK;
+    }
+    // fold this call's verdict into the index's sticky error
+    check(launch_or_flag(err, idx->err.p, st));
+    check(hipFreeAsync(err, st));
+    return PLL_OK;
+  });
+}
+
+int pll_sync(const pll_index *idx, void *stream) {
+  if (!idx) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  return guarded([&] {
+    int32_t herr = 0;
+    check(hipMemcpyAsync(&herr, idx->err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    check(hipMemsetAsync(idx->err.p, 0, sizeof(int32_t), st));
+    check(hipStreamSynchronize(st));
+    return herr ? PLL_E_INVAL : PLL_OK;
+  });
+}
+
+int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *entries,
+                     int32_t *t_bp) {
+  if (!idx || graph != 0) return PLL_E_INVAL;
+  if (n) *n = idx->n;
+  if (entries) *entries = idx->entries;
+  if (t_bp) *t_bp = idx->t;
+  return PLL_OK;
+}
+
+int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
+               uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank) {
+  if (!idx || graph != 0) return PLL_E_INVAL;
+  return guarded([&] {
+    const int32_t n = idx->n, t = idx->t;
+    const int64_t tot = idx->entries + n;
+    std::vector<int64_t> hoff((size_t)n + 1);
+    std::vector<uint32_t> hh((size_t)std::max<int64_t>(tot, 1));
+    std::vector<uint8_t> hd((size_t)std::max<int64_t>(tot, 1));
+    hipStream_t st = nullptr;
+    d2h(hoff.data(), idx->off.p, (size_t)n + 1, st);
+    if (hub) d2h(hh.data(), idx->hub.p, (size_t)tot, st);
+    if (dist) d2h(hd.data(), idx->dist.p, (size_t)tot, st);
+    check(hipStreamSynchronize(st));
+    int64_t e = 0;
+    for (int32_t r = 0; r < n; r++) {
+      const int64_t a = hoff[r], b = hoff[r + 1] - 1;  // drop the sentinel
+      if (off) off[r] = e;
+      for (int64_t x = a; x < b; x++, e++) {
+        if (hub) hub[e] = hh[x];
+        if (dist) dist[e] = hd[x];
+      }
+    }
+    if (off) off[n] = e;
+    const size_t nb = (size_t)n * t;
+    if (bp_d && nb) d2h(bp_d, idx->bpd.p, nb, st);
+    if ((bp_m1 || bp_0) && nb) {
+      std::vector<uint64_t> m(nb * 2);
+      d2h(m.data(), idx->bpm.p, nb * 2, st);
+      check(hipStreamSynchronize(st));
+      for (size_t i = 0; i < nb; i++) {
+        if (bp_m1) bp_m1[i] = m[2 * i];
+        if (bp_0) bp_0[i] = m[2 * i + 1];
+      }
+    }
+    if (rank && n) d2h(rank, idx->rank.p, (size_t)n, st);
+    check(hipStreamSynchronize(st));
+    return PLL_OK;
+  });
+}
+
+int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters) {
+  if (!idx || graph != 0 || !counters || ncounters < 0) return PLL_E_INVAL;
+  for (int32_t i = 0; i < ncounters && i < PLL_NSTATS; i++) counters[i] = idx->stats[i];
+  return PLL_OK;
+}
+
+void pll_free(pll_index *idx) { delete idx; }
+
+const char *pll_strerror(int code) {
+  switch (code) {
+    case PLL_OK: return "ok";
+    case PLL_E_INVAL: return "invalid argument";
+    case PLL_E_NOMEM: return "out of memory";
+    case PLL_E_RANGE: return "a distance does not fit in 8 bits (255 or more)";
+    case PLL_E_DEVICE: return "HIP device error";
+    case PLL_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown error";
+  }
+}
+
+int pll_set_tuning(const char *key, int64_t value) {
+  if (!key) return PLL_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string k(key);
+  auto pow2_in = [](int64_t v, int64_t lo, int64_t hi) {
+    return v >= lo && v <= hi && (v & (v - 1)) == 0;
+  };
+  if (k == "window") {
+    if (value < 1 || value > kMaxWindow) return PLL_E_INVAL;
+    g_tune.window = (int)value;
+  } else if (k == "group") {
+    if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
+    g_tune.group = (int)value;
+  } else if (k == "chunk") {
+    if (value < 64 || value > (1 << 20)) return PLL_E_INVAL;
+    g_tune.chunk = (int)value;
+  } else if (k == "qgroup") {
+    if (!pow2_in(value, 16, 64)) return PLL_E_INVAL;
+    g_tune.qgroup = (int)value;
+  } else if (k == "levels_per_sync") {
+    if (value < 1 || value > 64) return PLL_E_INVAL;
+    g_tune.levels_per_sync = (int)value;
+  } else {
+    return PLL_E_INVAL;
+  }
+  return PLL_OK;
+}
+
+int64_t pll_get_tuning(const char *key) {
+  if (!key) return PLL_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const std::string k(key);
+  if (k == "window") return g_tune.window;
+  if (k == "group") return g_tune.group;
+  if (k == "chunk") return g_tune.chunk;
+  if (k == "qgroup") return g_tune.qgroup;
+  if (k == "levels_per_sync") return g_tune.levels_per_sync;
+  return PLL_E_INVAL;
+}
+
+}  // extern "C"

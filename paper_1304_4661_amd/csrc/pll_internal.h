@@ -1,0 +1,233 @@
+// Internal declarations of the gfx950 Pruned Landmark Labeling library:
+// device-side helpers, the device data structures and the kernel launchers.
+// Nothing here is part of the public ABI (include/pll.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pll.h"
+
+namespace pll {
+
+constexpr uint8_t kInf8 = 255;           // "infinity" in 8-bit distances
+constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // hub of the storage-only sentinel
+constexpr int kWave = 64;                // CDNA wavefront width
+constexpr int kMaxLevels = 256;          // BFS levels 0..254 are storable
+constexpr int kMaxWindow = 1024;         // concurrent roots (bits per vertex mask)
+
+// ---------------------------------------------------------------------------
+// Wave helpers (64-wide wavefronts).
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t lanes_below_mask() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Wave-aggregated append: every active lane with pred gets a distinct slot
+// in [*ctr, *ctr + count), with one atomic per wave.  Returns -1 for lanes
+// without pred.
+__device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *ctr) {
+  uint64_t m = __ballot(pred);
+  if (m == 0) return -1;
+  int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane_id() == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  if (!pred) return -1;
+  return (int64_t)(base + (unsigned long long)__popcll(m & lanes_below_mask()));
+}
+
+// Groups of G consecutive lanes inside a wave.
+template <int G>
+struct Group {
+  static_assert(G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
+  __device__ __forceinline__ static int rank() { return lane_id() & (G - 1); }
+  __device__ __forceinline__ static int base() { return lane_id() & ~(G - 1); }
+  __device__ __forceinline__ static uint64_t mask() {
+    return G == 64 ? ~0ull : (((1ull << G) - 1) << base());
+  }
+  // true on every lane of the group if pred holds on any active lane of it
+  __device__ __forceinline__ static bool any(bool pred) {
+    return (__ballot(pred) & mask()) != 0;
+  }
+  __device__ __forceinline__ static uint64_t or_reduce(uint64_t v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v |= __shfl_xor(v, o, G);
+    return v;
+  }
+  __device__ __forceinline__ static int min_reduce(int v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      int w = __shfl_xor(v, o, G);
+      v = w < v ? w : v;
+    }
+    return v;
+  }
+};
+
+// Agent-scope relaxed atomic load/store (bypass the non-coherent vector L1).
+template <typename T>
+__device__ __forceinline__ T ld_acquire_agent(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_relaxed_agent(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Distance through one bit-parallel slot (Section 5.3): d_s + d_t, minus 2
+// if S^{-1}(s) and S^{-1}(t) meet, else minus 1 if S^{0}(s) meets S^{-1}(t)
+// or S^{-1}(s) meets S^{0}(t).
+__device__ __forceinline__ int bp_pair_dist(int ds, uint64_t m1s, uint64_t m0s, int dt,
+                                            uint64_t m1t, uint64_t m0t) {
+  int td = ds + dt;
+  if (m1s & m1t)
+    td -= 2;
+  else if ((m0s & m1t) | (m1s & m0t))
+    td -= 1;
+  return td;
+}
+
+// ---------------------------------------------------------------------------
+// Device data structures.
+
+// Graph in rank space: vertex r is the vertex of rank r; neighbour lists
+// hold ranks.
+struct DGraph {
+  int32_t n;
+  int32_t nwords;      // (n + 31) / 32
+  const int64_t *row;  // [n+1]
+  const int32_t *col;  // [row[n]]
+};
+
+// Bit-parallel labels, vertex-major: for vertex v and slot i, d[v*t+i] and
+// m[2*(v*t+i)] = S^{-1}, m[2*(v*t+i)+1] = S^{0}.
+struct DBp {
+  int32_t t;
+  const uint8_t *d;
+  const uint64_t *m;
+};
+
+// Per-level control block of a level-synchronous frontier whose levels are
+// stored one after another: level L occupies [base[L], base[L] + cnt[L]).
+struct LevelCtl {
+  unsigned long long cnt[kMaxLevels + 2];
+  unsigned long long base[kMaxLevels + 2];
+  unsigned long long hcnt[kMaxLevels + 2];  // heavy expansion tasks per level
+  unsigned long long hcnt2[kMaxLevels + 2]; // second task list (bit-parallel E1)
+  unsigned long long ccnt;                  // candidate labels of the window
+  unsigned long long visited;               // total visits (statistics)
+  int32_t flags;
+  int32_t pad;
+};
+
+enum : int32_t {
+  kFlagOvfFrontier = 1,
+  kFlagOvfHeavy = 2,
+  kFlagOvfCand = 4,
+  kFlagRange = 8,  // a vertex at distance 255 would be labeled (or reached, BP)
+  kOverflowFlags = kFlagOvfFrontier | kFlagOvfHeavy | kFlagOvfCand,
+};
+
+// Growing label store used during the build: label of rank r lives at
+// hub/dist[off[r] .. off[r]+len[r]) inside a pool; cap[r] slots reserved.
+struct DStore {
+  int64_t *off;
+  int32_t *len;
+  int32_t *cap;
+  uint32_t *hub;
+  uint8_t *dist;
+  unsigned long long *top;  // pool bump pointer (device)
+  int64_t pool_cap;
+};
+
+// Frontier and task buffers shared by both BFS phases.
+struct DFrontier {
+  int32_t *slot;  // root slot (window-relative) or bit-parallel slot
+  int32_t *v;     // vertex rank
+  int64_t cap;
+  int32_t *hslot, *hv, *hchunk;  // heavy tasks: chunks of long adjacency lists
+  int64_t hcap;
+  int32_t *h2slot, *h2v, *h2chunk;
+  LevelCtl *ctl;
+};
+
+// State of one window of concurrently processed roots [s, s + W).
+struct DWindow {
+  int32_t s, W, words;  // words: mask words per vertex (row stride of wd is words*64)
+  uint32_t *vis;        // [W][nwords] visited bits per root slot
+  uint8_t *T;           // [W][n] root labels scattered by hub (Section 4.5.1)
+  uint8_t *wd;          // [n][words*64] distance from window root j, or 255
+  uint64_t *cmask;      // [n][words] window roots that labeled the vertex
+  uint64_t *kmask;      // [n][words] ... and whose label survived cleaning
+  int32_t *cu;          // candidate vertex
+  int32_t *cj;          // candidate root slot
+  uint8_t *cd;          // candidate distance
+  uint8_t *cdes;        // 1 if this candidate commits its vertex's row
+  int64_t ccap;
+  const uint8_t *used;  // [n] 1 for bit-parallel roots and neighbours
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (return hipError_t of the launch).
+
+hipError_t launch_iota_rank(const int32_t *order, int32_t *rank, int32_t n, hipStream_t st);
+hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *deg, int32_t n,
+                          hipStream_t st);
+hipError_t launch_relabel_cols(const int32_t *in_row, const int32_t *in_col, const int32_t *order,
+                               const int32_t *rank, const int64_t *row, int32_t *col, int32_t n,
+                               hipStream_t st);
+// exclusive scan of int64 in[0..n) into out[0..n], out[n] = total; tmp must
+// hold scan_tmp_elems(n) int64
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
+                                 hipStream_t st);
+
+hipError_t launch_bp_select(DGraph g, int32_t t, uint32_t *used_bits, uint32_t *tmp_bits,
+                            uint8_t *used_bytes, int32_t *root, int32_t *nsel, int32_t *sel,
+                            hipStream_t st);
+hipError_t launch_bp_init(DGraph g, int32_t t, const int32_t *root, const int32_t *nsel,
+                          const int32_t *sel, const int32_t *sel_pos, uint8_t *bd, uint64_t *bs1,
+                          uint32_t *vis, DFrontier f, hipStream_t st);
+hipError_t launch_bp_level(DGraph g, int32_t t, int L, int group, int chunk, uint8_t *bd,
+                           uint64_t *bs1, uint64_t *bs0, uint32_t *vis, DFrontier f,
+                           hipStream_t st);
+hipError_t launch_bp_finish(int32_t n, int32_t t, const uint8_t *bd, const uint64_t *bs1,
+                            const uint64_t *bs0, uint8_t *d, uint64_t *m, hipStream_t st);
+
+hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
+hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
+                           hipStream_t st);
+hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
+                            int chunk, hipStream_t st);
+hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
+                            int64_t nvisited, hipStream_t st);
+hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);
+hipError_t launch_win_clean(DWindow w, int64_t ncand, hipStream_t st);
+hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
+hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
+hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
+                             int32_t n, hipStream_t st);
+
+// Queries: ranks of ids, bit-parallel labels, final CSR labels with sentinel.
+struct DIndex {
+  int32_t n;
+  int32_t t;
+  const int32_t *rank;
+  const uint8_t *bpd;
+  const uint64_t *bpm;
+  const int64_t *off;
+  const uint32_t *hub;
+  const uint8_t *dist;
+};
+hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err,
+                                 hipStream_t st);
+hipError_t launch_or_flag(const int32_t *src, int32_t *dst, hipStream_t st);
+hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
+                        const int32_t *err, bool plain, int qgroup, hipStream_t st);
+
+}  // namespace pll

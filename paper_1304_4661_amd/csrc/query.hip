@@ -1,0 +1,172 @@
+// Distance queries over the finished index.
+//
+// QUERY(s, t) = min of (a) the bit-parallel estimate of every slot both ends
+// reach (Section 5.3) and (b) min over common hubs h of d(h,s) + d(h,t)
+// (Section 3.3), clamped to 255.  Labels are sorted by hub rank and end in a
+// sentinel (Section 4.5.2), so (b) is a merge join.
+//
+// Plain form: one thread per pair, the merge walked one entry at a time.
+// Batched form: a group of G lanes per pair.  The bit-parallel slots are
+// spread over the lanes, and only slots whose lower bound d_s + d_t - 2 can
+// beat the best plain root estimate fetch their 16-byte set words.  The merge
+// loads G hubs of each label at once and finds the common hubs of the two
+// chunks by a per-lane binary search through the other chunk held in lanes
+// (cross-lane reads), then advances the chunk(s) that end first.
+#include "pll_internal.h"
+
+namespace pll {
+
+namespace {
+
+__global__ void k_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = pairs[i];
+    if (v < 0 || v >= n) atomicOr(err, 1);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_query_plain(DIndex ix, const int32_t *pairs, int64_t q,
+                                                     uint8_t *out, const int32_t *err) {
+  if (err && *err) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    int best = kInf8;
+    const int32_t t = ix.t;
+    for (int32_t k = 0; k < t; k++) {
+      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
+      if (ds == kInf8 || dt == kInf8) continue;
+      const uint64_t *ms = ix.bpm + 2 * ((int64_t)rs * t + k);
+      const uint64_t *mt = ix.bpm + 2 * ((int64_t)rt * t + k);
+      const int v = bp_pair_dist(ds, ms[0], ms[1], dt, mt[0], mt[1]);
+      best = v < best ? v : best;
+    }
+    int64_t a = ix.off[rs], b = ix.off[rt];
+    for (;;) {
+      const uint32_t ha = ix.hub[a], hb = ix.hub[b];
+      if (ha == hb) {
+        if (ha == kSentinel) break;
+        const int v = (int)ix.dist[a] + (int)ix.dist[b];
+        best = v < best ? v : best;
+        a++;
+        b++;
+      } else if (ha < hb) {
+        a++;
+      } else {
+        b++;
+      }
+    }
+    out[i] = (uint8_t)(best < (int)kInf8 ? best : (int)kInf8);
+  }
+}
+
+template <int G>
+__global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *pairs, int64_t q,
+                                                     uint8_t *out, const int32_t *err) {
+  if (err && *err) return;
+  const int gr = Group<G>::rank();
+  const int gb = Group<G>::base();
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int32_t t = ix.t;
+  for (int64_t i = gid; i < q; i += ngroups) {
+    const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    // (a) bit-parallel: lower bound first, sets only where they can matter
+    int ub = kInf8;
+    for (int32_t k = gr; k < t; k += G) {
+      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
+      if (ds != kInf8 && dt != kInf8) ub = ds + dt < ub ? ds + dt : ub;
+    }
+    ub = Group<G>::min_reduce(ub);
+    int best = ub;
+    for (int32_t k = gr; k < t; k += G) {
+      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
+      if (ds != kInf8 && dt != kInf8 && ds + dt - 2 < best) {
+        const uint64_t *ms = ix.bpm + 2 * ((int64_t)rs * t + k);
+        const uint64_t *mt = ix.bpm + 2 * ((int64_t)rt * t + k);
+        const int v = bp_pair_dist(ds, ms[0], ms[1], dt, mt[0], mt[1]);
+        best = v < best ? v : best;
+      }
+    }
+    // (b) merge join by chunks of G entries
+    int64_t a = ix.off[rs], b = ix.off[rt];
+    for (;;) {
+      const uint32_t ha = ix.hub[a + gr < ix.off[rs + 1] ? a + gr : ix.off[rs + 1] - 1];
+      const uint32_t hb = ix.hub[b + gr < ix.off[rt + 1] ? b + gr : ix.off[rt + 1] - 1];
+      // position of ha among this group's hb values (sorted): binary search
+      // (halving search: lo ends at the first index with hb >= ha, or G-1)
+      int lo = 0;
+#pragma unroll
+      for (int s = G / 2; s >= 1; s >>= 1) {
+        const uint32_t hm = __shfl(hb, gb + lo + s - 1);
+        if (hm < ha) lo += s;
+      }
+      const int pos = lo;
+      const uint32_t hf = __shfl(hb, gb + pos);
+      if (hf == ha && ha != kSentinel) {
+        const int v = (int)ix.dist[a + gr] + (int)ix.dist[b + pos];
+        best = v < best ? v : best;
+      }
+      const uint32_t lastA = __shfl(ha, gb + G - 1), lastB = __shfl(hb, gb + G - 1);
+      if (lastA == kSentinel && lastB == kSentinel) break;
+      if (lastA <= lastB) a += G;
+      if (lastB <= lastA) b += G;
+    }
+    best = Group<G>::min_reduce(best);
+    if (gr == 0) out[i] = (uint8_t)(best < (int)kInf8 ? best : (int)kInf8);
+  }
+}
+
+__global__ void k_or_flag(const int32_t *src, int32_t *dst) {
+  if (threadIdx.x == 0 && *src) atomicOr(dst, *src);
+}
+
+unsigned grid_for(int64_t items, int per_block, int64_t cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err,
+                                 hipStream_t st) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_pairs, dim3(grid_for(2 * q, 256, 4096)), dim3(256), 0, st, pairs,
+                     q, n, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_or_flag(const int32_t *src, int32_t *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, st, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
+                        const int32_t *err, bool plain, int qgroup, hipStream_t st) {
+  if (q <= 0) return hipSuccess;
+  if (plain) {
+    hipLaunchKernelGGL(k_query_plain, dim3(grid_for(q, 256, 65536)), dim3(256), 0, st, ix, pairs,
+                       q, out, err);
+    return hipGetLastError();
+  }
+  switch (qgroup) {
+    case 16:
+      hipLaunchKernelGGL(k_query_group<16>, dim3(grid_for(q * 16, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_query_group<32>, dim3(grid_for(q * 32, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+    default:
+      hipLaunchKernelGGL(k_query_group<64>, dim3(grid_for(q * 64, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pll

@@ -1,0 +1,94 @@
+"""Host-only checks of the C ABI: the library loads, exports every entry
+point include/pll.h declares, and rejects bad arguments before touching a
+device (so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import graphs
+from paper_1304_4661_amd import binding, gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", f)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(pll_[a-z_]+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.library()
+    decl = declared_symbols()
+    assert "pll_build" in decl and "pll_query" in decl
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(binding.EXPORTED) <= set(decl)
+
+
+def test_strerror_and_tuning():
+    lib = binding.library()
+    assert lib.pll_strerror(0) == b"ok"
+    assert b"range" in lib.pll_strerror(-3) or b"8 bits" in lib.pll_strerror(-3)
+    old = binding.get_tuning("window")
+    binding.set_tuning("window", 64)
+    assert binding.get_tuning("window") == 64
+    binding.set_tuning("window", old)
+    with pytest.raises(binding.PllError):
+        binding.set_tuning("window", 0)
+    with pytest.raises(binding.PllError):
+        binding.set_tuning("group", 12)
+    with pytest.raises(binding.PllError):
+        binding.set_tuning("nope", 1)
+
+
+def _rc_build(rp, col, order, t, flags=0):
+    lib = binding.library()
+    h = C.c_void_p()
+    rp = np.ascontiguousarray(rp, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    order = np.ascontiguousarray(order, np.int32)
+    rc = lib.pll_build(len(order), rp.ctypes.data, col.ctypes.data if len(col) else None,
+                       order.ctypes.data, t, flags, None, C.byref(h))
+    return rc, h
+
+
+def test_build_rejects_bad_input_before_device_work():
+    g = graphs.cycle(6)
+    order = gen.degree_order(g)
+    bad_order = order.copy()
+    bad_order[1] = bad_order[0]
+    assert _rc_build(g.row_ptr, g.col, bad_order, 0)[0] == binding.E_INVAL
+    col = g.col.copy()
+    col[0] = 0  # self-loop
+    assert _rc_build(g.row_ptr, col, order, 0)[0] == binding.E_INVAL
+    col = g.col.copy()
+    col[3] = 99
+    assert _rc_build(g.row_ptr, col, order, 0)[0] == binding.E_INVAL
+    rp = g.row_ptr.copy()
+    rp[0] = 1
+    assert _rc_build(rp, g.col, order, 0)[0] == binding.E_INVAL
+    assert _rc_build(g.row_ptr, g.col, order, 65)[0] == binding.E_INVAL
+    assert _rc_build(g.row_ptr, g.col, order, -1)[0] == binding.E_INVAL
+    # asymmetric graph, only caught under PLL_VALIDATE
+    rp = np.array([0, 1, 1], np.int32)
+    col = np.array([1], np.int32)
+    assert _rc_build(rp, col, np.array([0, 1], np.int32), 0, binding.VALIDATE)[0] == binding.E_INVAL
+    rc, h = _rc_build(g.row_ptr, g.col, bad_order, 0)
+    assert rc == binding.E_INVAL and h.value is None  # *out stays NULL on error
+
+
+def test_query_rejects_null_index():
+    lib = binding.library()
+    pairs = np.zeros(2, np.int32)
+    out = np.zeros(1, np.uint8)
+    assert lib.pll_query(None, pairs.ctypes.data, 1, out.ctypes.data, 0, None) == binding.E_INVAL
+    assert lib.pll_stats(None, 0, None, 0) == binding.E_INVAL
+    lib.pll_free(None)

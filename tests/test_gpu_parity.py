@@ -1,0 +1,172 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every index array (labels, bit-parallel labels, ranks) and every query answer
+must equal the oracle's.  Runs only on an MI355X (``-m gpu``)."""
+import os
+
+import numpy as np
+import pytest
+
+import graphs
+import oracle
+from paper_1304_4661_amd import binding, gen
+
+pytestmark = pytest.mark.gpu
+
+
+def _require_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def assert_same_index(gx, ox, tag=""):
+    e = gx.export()
+    assert np.array_equal(e["rank"], ox.rank), tag
+    assert np.array_equal(e["off"], ox.off), f"{tag}: label sizes differ"
+    assert np.array_equal(e["hub"], ox.hub), f"{tag}: hubs differ"
+    assert np.array_equal(e["dist"], ox.dist), f"{tag}: distances differ"
+    assert np.array_equal(e["bp_d"], ox.bp_d), f"{tag}: bit-parallel distances differ"
+    assert np.array_equal(e["bp_m1"], ox.bp_m1), f"{tag}: S^-1 differ"
+    assert np.array_equal(e["bp_0"], ox.bp_0), f"{tag}: S^0 differ"
+
+
+def all_pairs(n):
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    return np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+
+
+class Tuned:
+    """Temporarily set library tuning knobs."""
+
+    def __init__(self, **kv):
+        self.kv = kv
+        self.old = {}
+
+    def __enter__(self):
+        for k, v in self.kv.items():
+            self.old[k] = binding.get_tuning(k)
+            binding.set_tuning(k, v)
+
+    def __exit__(self, *a):
+        for k, v in self.old.items():
+            binding.set_tuning(k, v)
+
+
+FAMILIES = graphs.families()
+
+
+@pytest.mark.parametrize("name,g", FAMILIES, ids=[f[0] for f in FAMILIES])
+@pytest.mark.parametrize("t_bp", [0, 2, 64])
+def test_small_families(name, g, t_bp):
+    _require_gpu()
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    gx = binding.build(g.row_ptr, g.col, order, t_bp, validate=True)
+    assert_same_index(gx, ox, name)
+    if g.n:
+        p = all_pairs(g.n)
+        want = oracle.query(ox, p)
+        assert np.array_equal(gx.query(p), want)
+        assert np.array_equal(gx.query(p, plain=True), want)
+
+
+@pytest.mark.parametrize("window,group", [(1, 16), (3, 4), (17, 8), (64, 64), (1024, 32)])
+def test_windows_and_groups(window, group):
+    # concurrent roots + cleaning must give the sequential labels exactly
+    _require_gpu()
+    g = gen.ba_graph(700, 3, 31)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, 4)
+    with Tuned(window=window, group=group, chunk=64):
+        gx = binding.build(g.row_ptr, g.col, order, 4)
+    assert_same_index(gx, ox, f"w{window} g{group}")
+
+
+def test_random_order_and_plain_build():
+    _require_gpu()
+    g = graphs.erdos_renyi(150, 0.04, 8)
+    order = gen.random_order(g.n, 5)
+    ox = oracle.build(g.row_ptr, g.col, order, 3)
+    assert_same_index(binding.build(g.row_ptr, g.col, order, 3, plain=True), ox, "plain")
+    assert_same_index(binding.build(g.row_ptr, g.col, order, 3), ox, "windowed")
+
+
+def test_ba2000_workload():
+    # the small named workload: BA n=2000, m=4, t_bp=16, 1e5 pairs
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    assert_same_index(gx, ox, "ba2000")
+    want = oracle.query(ox, pairs)
+    assert np.array_equal(gx.query(pairs), want)
+    assert np.array_equal(gx.query(pairs, plain=True), want)
+    st = gx.stats()
+    assert st["entries"] == ox.counters["entries"]
+    assert st["roots"] == ox.counters["roots"]
+
+
+def test_device_pointer_queries():
+    import torch
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    dp = torch.from_numpy(pairs).cuda()
+    out = torch.empty(len(pairs), dtype=torch.uint8, device="cuda")
+    gx.query_device(dp, out, sync=True)
+    assert np.array_equal(out.cpu().numpy(), oracle.query(ox, pairs))
+    out2 = torch.empty_like(out)
+    gx.query_device(dp, out2, plain=True)
+    gx.sync()
+    assert torch.equal(out, out2)
+    # an out-of-range id: nothing written, error reported
+    bad = dp.clone()
+    bad[5, 1] = g.n
+    out3 = torch.full_like(out, 7)
+    with pytest.raises(binding.PllError):
+        gx.query_device(bad, out3, sync=True)
+    assert int((out3 != 7).sum()) == 0
+    gx.query_device(bad, out3)
+    with pytest.raises(binding.PllError):
+        gx.sync()
+    gx.sync()  # cleared
+
+
+def test_range_error_and_clamped_answers():
+    _require_gpu()
+    g = graphs.path(256)
+    order = gen.degree_order(g)
+    gx = binding.build(g.row_ptr, g.col, order, 1)
+    ox = oracle.build(g.row_ptr, g.col, order, 1)
+    assert_same_index(gx, ox, "path256")
+    q = np.array([[1, 255], [0, 255], [0, 254]], np.int32)
+    assert gx.query(q).tolist() == [254, 255, 254]
+    g2 = graphs.path(257)
+    for t in (0, 1):
+        with pytest.raises(binding.PllError) as e:
+            binding.build(g2.row_ptr, g2.col, gen.degree_order(g2), t)
+        assert e.value.code == binding.E_RANGE
+
+
+def test_deterministic_rebuild():
+    _require_gpu()
+    g = gen.rmat_graph(12, seed=4)
+    order = gen.degree_order(g)
+    a = binding.build(g.row_ptr, g.col, order, 8).export()
+    b = binding.build(g.row_ptr, g.col, order, 8).export()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.slow
+def test_rmat14_and_tiny_windows():
+    _require_gpu()
+    g = gen.rmat_graph(14, seed=7)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, 16)
+    assert_same_index(binding.build(g.row_ptr, g.col, order, 16), ox, "rmat14")
+    with Tuned(window=5, chunk=64, group=4):
+        assert_same_index(binding.build(g.row_ptr, g.col, order, 16), ox, "rmat14 w5")
+    p = gen.random_pairs(g.n, 200_000, 9)
+    assert np.array_equal(binding.build(g.row_ptr, g.col, order, 16).query(p), oracle.query(ox, p))
