@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark: Pruned Landmark Labeling index build + batched queries on one
+MI355X.
+
+One step = the whole hot path on one synthetic workload with its inputs
+already in HBM: rank relabel, bit-parallel root choice, bit-parallel BFSs,
+windowed pruned BFSs with cleaning, final label CSR, then one batch of query
+pairs.  Default workload: R-MAT scale 18 (edge factor 16, a/b/c/d =
+.57/.19/.19/.05, symmetrized, de-duplicated, self-loops dropped, largest
+component kept), Degree order, t_bp = 50, 1e6 uniform random pairs.
+
+Prints ONE JSON line.  See DESIGN.md for the byte model behind "roofline".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PLL index build s & edges/s; queries/s + p99 latency, batched vs plain"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "win_level_traffic_rmat18.json")
+LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip")
+
+
+def describe(name, g, t_bp, q):
+    if name.startswith("rmat"):
+        m = g.meta
+        return (f"R-MAT scale {m['scale']}, edge factor {m['edge_factor']}, abcd="
+                f"{m['abcd']}, symmetrized+dedup+no self-loops+largest component "
+                f"(n'={g.n}, m'={g.m}); Degree order; t_bp={t_bp}; {q} uniform random pairs")
+    m = g.meta
+    return (f"Barabasi-Albert n={g.n}, m={m['m_attach']} (m'={g.m}); Degree order; "
+            f"t_bp={t_bp}; {q} uniform random pairs")
+
+
+def pctl(xs, p):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), p)) if len(xs) else None
+
+
+def file_sha(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def level_kernel_bytes(st, t_bp):
+    """Algorithmic bytes of the pruned-phase level kernel, summed over all its
+    launches in one build (per-unit figures of the byte model):
+      per visited (root, vertex): 16 B label offsets + 17*t_bp B bit-parallel
+        label of the vertex,
+      per label entry scanned by a normal-label test: 5 B (hub + distance),
+      per labeled vertex: 8 B row offsets + 5 B label append,
+      per adjacency entry expanded: 5 B (neighbour id + visited check)."""
+    return (st["visited"] * (16 + 17 * t_bp) + 5 * st["label_scanned"]
+            + 13 * st["candidates"] + 5 * st["edges"])
+
+
+def cpu_baseline(g, order, t_bp, pairs):
+    """The oracle as it stands: single thread on a host core, full workload."""
+    import oracle
+
+    t0 = time.perf_counter()
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.query(ox, pairs)
+    tq = time.perf_counter() - t0
+    return {
+        "value": g.m / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
+        "sample": (f"whole step on the same workload: oracle index build ({tb:.2f} s) + "
+                   f"{len(pairs)} queries ({tq:.2f} s), one thread"),
+        "build_s": tb, "queries_per_s": len(pairs) / tq,
+        "entries": ox.counters["entries"],
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="rmat18")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plain-form and latency measurements")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index "
+              "build and the queries here are single-GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1304_4661_amd import binding, gen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
+        return
+
+    g, order, t_bp, pairs = gen.config_graph(args.config)
+    q = len(pairs)
+    d_row = torch.from_numpy(g.row_ptr).to(dev)
+    d_col = torch.from_numpy(g.col).to(dev)
+    d_order = torch.from_numpy(order).to(dev)
+    d_pairs = torch.from_numpy(pairs).to(dev)
+    d_out = torch.empty(q, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    binding.set_tuning("profile", 1)
+
+    def step():
+        ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        ix.query_device(d_pairs, d_out, stream=stream)
+        ev1.record(stream)
+        return ix, ev0, ev1
+
+    for _ in range(args.warmup):
+        ix, _, _ = step()
+        ix.sync()
+        ix.close()
+    torch.cuda.synchronize()
+
+    build_s, query_ms, stats = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tb = time.perf_counter()
+        ix, ev0, ev1 = step()
+        build_s.append(time.perf_counter() - tb)  # pll_build synchronises
+        ix.sync()
+        query_ms.append(ev0.elapsed_time(ev1))
+        stats.append(ix.stats())
+        ix.close()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    ms_per_step = 1e3 * total / args.steps
+
+    st = stats[-1]
+    lvl_bytes = level_kernel_bytes(st, t_bp)
+    lvl_s = st["level_ns"] * 1e-9
+    launches = st["level_launches"]
+    achieved = lvl_bytes / lvl_s / 1e9 if lvl_s > 0 else None
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {
+        "kernel": "k_win_level (pruned-BFS level over all roots of a window)",
+        "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+        "achieved": achieved, "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+        "traffic": traffic,
+        "launches": launches, "avg_launch_us": (lvl_s / launches * 1e6) if launches else None,
+        "algorithmic_bytes_per_launch": lvl_bytes / launches if launches else None,
+        "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": g.m / (ms_per_step / 1e3),
+        "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": describe(args.config, g, t_bp, q), "name": args.config,
+                   "n": g.n, "m": g.m, "t_bp": t_bp, "queries": q},
+        "build_s": float(np.median(build_s)),
+        "build_edges_per_s": g.m / float(np.median(build_s)),
+        "queries_per_s": q / (float(np.median(query_ms)) / 1e3),
+        "query_batch_ms_p50": pctl(query_ms, 50), "query_batch_ms_p99": pctl(query_ms, 99),
+        "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}",
+                  "bytes": st["index_bytes"], "windows": st["windows"],
+                  "retries": st["retries"], "visited": st["visited"],
+                  "candidates": st["candidates"]},
+        "phases_s": {"bit_parallel": st["bp_ns"] * 1e-9, "pruned": st["pruned_ns"] * 1e-9},
+        "roofline": roofline,
+    }
+
+    if not args.no_extras:
+        ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        rates = {}
+        for plain in (False, True):
+            ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(5):
+                ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates["plain" if plain else "batched"] = 5 * q / (e0.elapsed_time(e1) / 1e3)
+        lat = {}
+        for bs in (1, 64, 4096):
+            sub = d_pairs[:bs].contiguous()
+            so = d_out[:bs]
+            xs = []
+            for i in range(200):
+                t1 = time.perf_counter()
+                ix.query_device(sub, so, stream=stream)
+                torch.cuda.synchronize()
+                xs.append((time.perf_counter() - t1) * 1e6)
+            lat[str(bs)] = {"p50_us": pctl(xs[20:], 50), "p99_us": pctl(xs[20:], 99)}
+        ix.close()
+        # plain (one root at a time) vs windowed build on the small BA workload
+        gb, ob, tb_, _ = gen.config_graph("ba2000")
+        bt = {}
+        for plain in (False, True):
+            binding.build(gb.row_ptr, gb.col, ob, tb_, plain=plain).close()
+            t1 = time.perf_counter()
+            binding.build(gb.row_ptr, gb.col, ob, tb_, plain=plain).close()
+            bt["plain" if plain else "batched"] = time.perf_counter() - t1
+        out["plain_vs_batched"] = {
+            "query_per_s": rates, "build_s_ba2000": bt,
+        }
+        out["query_latency_host_us"] = lat
+
+    binding.set_tuning("profile", 0)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+    print(json.dumps(out))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

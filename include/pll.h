@@ -49,7 +49,7 @@ enum {
 #define PLL_MAX_TBP 64 /* bit-parallel slots: one 64-bit word per set (b = 64) */
 
 /* flags */
-#define PLL_DEVICE_PTRS 1u /* pll_query*: pairs and out are device pointers */
+#define PLL_DEVICE_PTRS 1u /* array arguments are device pointers */
 #define PLL_VALIDATE 2u    /* pll_build*: also check that the graph is symmetric */
 #define PLL_SYNC 4u        /* block until the call's device work is complete */
 #define PLL_PLAIN 8u       /* plain forms: build one root at a time (no
@@ -59,18 +59,21 @@ enum {
  * Build the index of one graph (Algorithm 2 with the bit-parallel phase of
  * Section 5.4 in front).
  *   n        number of vertices (>= 0)
- *   row_ptr  host int32[n+1], CSR row offsets: row_ptr[0] = 0, non-decreasing
- *   col      host int32[row_ptr[n]], neighbour ids; the graph must be
+ *   row_ptr  int32[n+1], CSR row offsets: row_ptr[0] = 0, non-decreasing
+ *   col      int32[row_ptr[n]], neighbour ids; the graph must be
  *            symmetric (each edge in both rows) with no self-loops;
  *            repeated edges are allowed
- *   order    host int32[n], a permutation: order[i] is the vertex of rank i
+ *   order    int32[n], a permutation: order[i] is the vertex of rank i
  *            (Section 4.4; pruned BFSs run in this order)
  *   t_bp     number of bit-parallel roots, 0..PLL_MAX_TBP (Section 5.4: the
  *            root is the lowest-rank unused vertex, its up to 64 lowest-rank
  *            unused neighbours form S_r; an exhausted slot stays empty)
- *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC
+ *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC, PLL_DEVICE_PTRS
  *   out      receives the new index on success
- * The inputs are copied; the caller may free them when the call returns.
+ * row_ptr, col and order are host memory, or device memory under
+ * PLL_DEVICE_PTRS (then they are checked by a kernel before the build, and
+ * PLL_VALIDATE is PLL_E_UNSUPPORTED).  The inputs are copied or only read;
+ * the caller may free them when the call returns.
  * Errors: PLL_E_INVAL (bad CSR, self-loop, out-of-range id, order not a
  * permutation, t_bp outside 0..64, asymmetric graph under PLL_VALIDATE),
  * PLL_E_RANGE, PLL_E_NOMEM, PLL_E_DEVICE.  The build always synchronises
@@ -143,6 +146,13 @@ enum {
   PLL_STAT_BUILD_NS,     /* wall time of the build, ns */
   PLL_STAT_BP_NS,        /* bit-parallel phase, ns */
   PLL_STAT_PRUNED_NS,    /* pruned phase, ns */
+  PLL_STAT_NORMAL_TESTS, /* visits that reached the normal-label test */
+  PLL_STAT_LABEL_SCANNED,/* label entries read by normal-label tests */
+  PLL_STAT_EDGES,        /* adjacency entries expanded by the level kernel */
+  PLL_STAT_TASK_EDGES,   /* adjacency entries expanded as long-list tasks */
+  PLL_STAT_LEVEL_LAUNCHES, /* launches of the pruned-phase level kernel */
+  PLL_STAT_LEVEL_NS,     /* their summed duration from HIP events, ns; only
+                            with the "profile" knob set, else 0 */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
@@ -157,8 +167,10 @@ const char *pll_strerror(int code);
  * Tuning knobs (process-wide): "window" (max concurrent roots, 1..1024),
  * "group" (lanes per frontier vertex: 4,8,16,32,64), "chunk" (edges a
  * group expands inline before handing the rest to whole waves), "qgroup"
- * (lanes per query pair: 16, 32, 64).  Returns PLL_E_INVAL for an unknown
- * key or value.
+ * (lanes per query pair: 16, 32, 64), "levels_per_sync" (level kernels
+ * launched between host checks), "profile" (0/1: time every pruned-phase
+ * level kernel with HIP events on the build stream).  Returns PLL_E_INVAL
+ * for an unknown key or value.
  */
 int pll_set_tuning(const char *key, int64_t value);
 int64_t pll_get_tuning(const char *key);

@@ -23,6 +23,7 @@ DEVICE_PTRS, VALIDATE, SYNC, PLAIN = 1, 2, 4, 8
 STAT_NAMES = [
     "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
     "retries", "bp_visited", "levels", "index_bytes", "build_ns", "bp_ns", "pruned_ns",
+    "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
 ]
 
 EXPORTED = [
@@ -166,6 +167,26 @@ class Index:
         c = np.zeros(len(STAT_NAMES), np.int64)
         _check(_lib().pll_stats(self._h, 0, _ptr(c), len(c)), "stats")
         return {k: int(v) for k, v in zip(STAT_NAMES, c)}
+
+
+def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=None) -> Index:
+    """Build from device tensors (torch, int32, contiguous, on the GPU)."""
+    import torch
+
+    for a in (row_ptr, col, order):
+        assert a.dtype == torch.int32 and a.is_cuda and a.is_contiguous()
+    n = order.numel()
+    if row_ptr.numel() != n + 1:
+        raise PllError(E_INVAL, "build_device: row_ptr length")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    flags = DEVICE_PTRS | (PLAIN if plain else 0)
+    h = C.c_void_p()
+    rc = _lib().pll_build(n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()),
+                          C.c_void_p(order.data_ptr()), int(t_bp), flags,
+                          C.c_void_p(stream.cuda_stream), C.byref(h))
+    _check(rc, "build_device")
+    return Index(h)
 
 
 def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = False,

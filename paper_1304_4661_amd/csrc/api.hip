@@ -23,6 +23,7 @@ struct Tuning {
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
+  int profile = 0;
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -190,26 +191,35 @@ struct Builder {
   DBuf<int32_t> col;
   DBuf<uint8_t> used;
   int64_t stat_levels = 0, stat_bp_visited = 0, stat_visited = 0, stat_cand = 0,
-          stat_windows = 0, stat_retries = 0, stat_roots = 0;
+          stat_windows = 0, stat_retries = 0, stat_roots = 0, stat_tests = 0, stat_scanned = 0,
+          stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0;
 
   DGraph graph() const { return DGraph{n, nwords, row.p, col.p}; }
 
-  // a1: rank[order[i]] = i; rank-space CSR
-  void relabel(const int32_t *h_row, const int32_t *h_col, const int32_t *h_order,
-               pll_index *ix) {
-    DBuf<int32_t> in_row((size_t)n + 1), in_col((size_t)std::max<int64_t>(nnz, 1)),
-        order((size_t)n);
-    h2d(in_row.p, h_row, (size_t)n + 1, st);
-    h2d(in_col.p, h_col, (size_t)nnz, st);
-    h2d(order.p, h_order, (size_t)n, st);
+  // a1: rank[order[i]] = i; rank-space CSR.  Inputs are host arrays, or
+  // device arrays (already validated) when `device` is set.
+  void relabel(const int32_t *in_row_p, const int32_t *in_col_p, const int32_t *order_p,
+               bool device, pll_index *ix) {
+    DBuf<int32_t> in_row, in_col, order;
+    if (!device) {
+      in_row.alloc((size_t)n + 1);
+      in_col.alloc((size_t)std::max<int64_t>(nnz, 1));
+      order.alloc((size_t)n);
+      h2d(in_row.p, in_row_p, (size_t)n + 1, st);
+      h2d(in_col.p, in_col_p, (size_t)nnz, st);
+      h2d(order.p, order_p, (size_t)n, st);
+      in_row_p = in_row.p;
+      in_col_p = in_col.p;
+      order_p = order.p;
+    }
     ix->rank.alloc((size_t)n);
-    check(launch_iota_rank(order.p, ix->rank.p, n, st));
+    check(launch_iota_rank(order_p, ix->rank.p, n, st));
     DBuf<int64_t> deg((size_t)n), tmp((size_t)scan_tmp_elems(n));
     row.alloc((size_t)n + 1);
     col.alloc((size_t)std::max<int64_t>(nnz, 1));
-    check(launch_degrees(in_row.p, order.p, deg.p, n, st));
+    check(launch_degrees(in_row_p, order_p, deg.p, n, st));
     check(launch_exclusive_scan(deg.p, row.p, n, tmp.p, st));
-    check(launch_relabel_cols(in_row.p, in_col.p, order.p, ix->rank.p, row.p, col.p, n, st));
+    check(launch_relabel_cols(in_row_p, in_col_p, order_p, ix->rank.p, row.p, col.p, n, st));
     check(hipStreamSynchronize(st));
   }
 
@@ -336,6 +346,19 @@ struct Builder {
     int64_t entries_bound = 0;
     unsigned long long htop = 0;
 
+    // optional timing of each level kernel (events on the build stream)
+    std::vector<hipEvent_t> evs;
+    if (tu.profile) {
+      evs.resize(2 * (size_t)tu.levels_per_sync);
+      for (auto &e : evs) check(hipEventCreate(&e));
+    }
+    struct EvGuard {
+      std::vector<hipEvent_t> &v;
+      ~EvGuard() {
+        for (auto e : v) (void)hipEventDestroy(e);
+      }
+    } ev_guard{evs};
+
     int32_t s = 0;
     int W = wmax;
     while (s < n) {
@@ -349,14 +372,23 @@ struct Builder {
       int d = 0;
       bool done = false;
       while (!done) {
+        const int d0 = d;
         const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
         for (; d < upto; d++) {
-          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.chunk, st));
+          hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
+          hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
+          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.chunk, st, e0, e1));
           stat_levels++;
+          stat_level_launches++;
         }
         read_ctl(&h, ctl.p, st);
         check(hipMemcpyAsync(&htop, top.p, sizeof(htop), hipMemcpyDeviceToHost, st));
         check(hipStreamSynchronize(st));
+        for (int i = 0; !evs.empty() && i < d - d0; i++) {
+          float ms = 0.f;
+          check(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+          stat_level_ns += (int64_t)(ms * 1e6);
+        }
         if (h.flags || h.cnt[d] == 0 || d >= kMaxLevels - 1) done = true;
       }
       int64_t nvisited = 0;
@@ -394,6 +426,10 @@ struct Builder {
       check(launch_win_commit(w, sto, ncand, st));
       entries_bound += ncand;
       stat_visited += (int64_t)h.visited;
+      stat_tests += (int64_t)h.ntests;
+      stat_scanned += (int64_t)h.lscanned;
+      stat_edges += (int64_t)h.edges;
+      stat_hedges += (int64_t)h.hedges;
       stat_cand += ncand;
       stat_windows++;
       s = e;
@@ -425,7 +461,7 @@ struct Builder {
 };
 
 int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
-              int32_t t_bp, uint32_t flags, hipStream_t st, pll_index *ix) {
+              int64_t nnz, int32_t t_bp, uint32_t flags, hipStream_t st, pll_index *ix) {
   const auto t0 = Clock::now();
   Builder b;
   b.st = st;
@@ -434,10 +470,10 @@ int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   b.n = n;
   b.t = t_bp;
   b.nwords = (n + 31) / 32;
-  b.nnz = n > 0 ? row_ptr[n] : 0;
+  b.nnz = nnz;
   ix->n = n;
   ix->t = t_bp;
-  b.relabel(row_ptr, col, order, ix);
+  b.relabel(row_ptr, col, order, (flags & PLL_DEVICE_PTRS) != 0, ix);
   const auto t1 = Clock::now();
   b.bit_parallel(ix);
   const int64_t bp_ns = ns_since(t1);
@@ -465,6 +501,12 @@ int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
                                       ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes());
   S[PLL_STAT_BP_NS] = bp_ns;
   S[PLL_STAT_PRUNED_NS] = pr_ns;
+  S[PLL_STAT_NORMAL_TESTS] = b.stat_tests;
+  S[PLL_STAT_LABEL_SCANNED] = b.stat_scanned;
+  S[PLL_STAT_EDGES] = b.stat_edges;
+  S[PLL_STAT_TASK_EDGES] = b.stat_hedges;
+  S[PLL_STAT_LEVEL_LAUNCHES] = b.stat_level_launches;
+  S[PLL_STAT_LEVEL_NS] = b.stat_level_ns;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }
@@ -494,12 +536,40 @@ int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
               int32_t t_bp, uint32_t flags, void *stream, pll_index **out) {
   if (!out) return PLL_E_INVAL;
   *out = nullptr;
-  int rc = validate_graph(n, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
-  if (rc != PLL_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  int64_t nnz = 0;
+  if (!device) {
+    int rc = validate_graph(n, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
+    if (rc != PLL_OK) return rc;
+    nnz = n > 0 ? row_ptr[n] : 0;
+  } else {
+    if (n < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP) return PLL_E_INVAL;
+    if (flags & PLL_VALIDATE) return PLL_E_UNSUPPORTED;
+    if (n > 0 && (!row_ptr || !order)) return PLL_E_INVAL;
+    if (n > 0) {
+      int rc = guarded([&] {
+        int32_t hn = 0;
+        d2h(&hn, row_ptr + n, 1, st);
+        check(hipStreamSynchronize(st));
+        nnz = hn;
+        if (nnz < 0 || (nnz > 0 && !col)) return PLL_E_INVAL;
+        DBuf<uint32_t> seen((size_t)(n + 31) / 32);
+        DBuf<int32_t> err(1);
+        fill(seen, 0, st);
+        fill(err, 0, st);
+        check(launch_validate_graph(n, row_ptr, col, order, seen.p, err.p, st));
+        int32_t herr = 0;
+        d2h(&herr, err.p, 1, st);
+        check(hipStreamSynchronize(st));
+        return herr ? PLL_E_INVAL : PLL_OK;
+      });
+      if (rc != PLL_OK) return rc;
+    }
+  }
   pll_index *ix = new (std::nothrow) pll_index();
   if (!ix) return PLL_E_NOMEM;
-  hipStream_t st = (hipStream_t)stream;
-  rc = guarded([&] { return build_one(n, row_ptr, col, order, t_bp, flags, st, ix); });
+  int rc = guarded([&] { return build_one(n, row_ptr, col, order, nnz, t_bp, flags, st, ix); });
   if (rc != PLL_OK) {
     (void)hipStreamSynchronize(st);
     delete ix;
@@ -654,6 +724,9 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "levels_per_sync") {
     if (value < 1 || value > 64) return PLL_E_INVAL;
     g_tune.levels_per_sync = (int)value;
+  } else if (k == "profile") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.profile = (int)value;
   } else {
     return PLL_E_INVAL;
   }
@@ -669,6 +742,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;
+  if (k == "profile") return g_tune.profile;
   return PLL_E_INVAL;
 }
 

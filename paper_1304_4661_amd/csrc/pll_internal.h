@@ -59,6 +59,11 @@ struct Group {
     for (int o = 1; o < G; o <<= 1) v |= __shfl_xor(v, o, G);
     return v;
   }
+  __device__ __forceinline__ static unsigned long long sum_reduce(unsigned long long v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+    return v;
+  }
   __device__ __forceinline__ static int min_reduce(int v) {
 #pragma unroll
     for (int o = 1; o < G; o <<= 1) {
@@ -120,7 +125,12 @@ struct LevelCtl {
   unsigned long long hcnt[kMaxLevels + 2];  // heavy expansion tasks per level
   unsigned long long hcnt2[kMaxLevels + 2]; // second task list (bit-parallel E1)
   unsigned long long ccnt;                  // candidate labels of the window
-  unsigned long long visited;               // total visits (statistics)
+  unsigned long long visited;               // (root, vertex) entries tested
+  unsigned long long ntests;                // ... that reached the normal-label test
+  unsigned long long lscanned;              // label entries read by those tests
+  unsigned long long labeled;               // entries labeled (candidates)
+  unsigned long long edges;                 // adjacency entries expanded inline
+  unsigned long long hedges;                // adjacency entries expanded as tasks
   int32_t flags;
   int32_t pad;
 };
@@ -175,6 +185,9 @@ struct DWindow {
 // ---------------------------------------------------------------------------
 // Launchers (return hipError_t of the launch).
 
+hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
+                                 const int32_t *order, uint32_t *seen, int32_t *err,
+                                 hipStream_t st);
 hipError_t launch_iota_rank(const int32_t *order, int32_t *rank, int32_t n, hipStream_t st);
 hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *deg, int32_t n,
                           hipStream_t st);
@@ -202,8 +215,9 @@ hipError_t launch_bp_finish(int32_t n, int32_t t, const uint8_t *bd, const uint6
 hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
 hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                            hipStream_t st);
+// ev0/ev1 (may be null): recorded around the level kernel itself.
 hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int chunk, hipStream_t st);
+                            int chunk, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                             int64_t nvisited, hipStream_t st);
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);

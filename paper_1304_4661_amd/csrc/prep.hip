@@ -94,6 +94,34 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int64_t *in, 
   }
 }
 
+// Device-side argument checks for inputs given as device pointers: CSR
+// offsets non-decreasing from 0, neighbours in range and not the vertex
+// itself, order a permutation.  Any violation sets *err.
+__global__ void k_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
+                                 const int32_t *order, uint32_t *seen, int32_t *err) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t a = row[v], b = row[v + 1];
+    if ((v == 0 && a != 0) || b < a) {
+      atomicOr(err, 1);
+      continue;
+    }
+    for (int32_t j = a; j < b; j++) {
+      const int32_t w = col[j];
+      if (w < 0 || w >= n || w == (int32_t)v) {
+        atomicOr(err, 1);
+        break;
+      }
+    }
+    const int32_t o = order[v];
+    if (o < 0 || o >= n) {
+      atomicOr(err, 1);
+    } else if (atomicOr(&seen[o >> 5], 1u << (o & 31)) & (1u << (o & 31))) {
+      atomicOr(err, 1);
+    }
+  }
+}
+
 __global__ void k_iota_rank(const int32_t *order, int32_t *rank, int32_t n) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) rank[order[i]] = i;
@@ -256,6 +284,17 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int
   hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, tmp, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out, n,
                      tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
+                                 const int32_t *order, uint32_t *seen, int32_t *err,
+                                 hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  int64_t blocks = ((int64_t)n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_validate_graph, dim3((unsigned)blocks), dim3(256), 0, st, n, row, col,
+                     order, seen, err);
   return hipGetLastError();
 }
 

@@ -94,15 +94,13 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
   const int gr = Group<G>::rank();
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
+  // work counters, per lane (group leaders), summed once per wave at the end
+  unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0, c_edge = 0;
   for (int64_t p = gid; p < (int64_t)cnt; p += ngroups) {
     const int32_t j = f.slot[beg + p];
     const int32_t u = f.v[beg + p];
     const int32_t k = w.s + j;
-    {
-      const uint64_t m = __ballot(gr == 0);
-      if (lane_id() == __ffsll((unsigned long long)m) - 1)
-        atomicAdd(&ctl->visited, (unsigned long long)__popcll(m));
-    }
+    if (gr == 0) c_visit++;
     // bit-parallel labels first (Section 5.4)
     bool pr = false;
     for (int32_t i = gr; i < t; i += G) {
@@ -118,6 +116,10 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
       const uint8_t *Tj = w.T + (int64_t)j * n;
       const int64_t o = st.off[u];
       const int32_t len = st.len[u];
+      if (gr == 0) {
+        c_test++;
+        c_scan += (unsigned long long)len;
+      }
       for (int32_t e = gr; e < len; e += G) {
         const int th = Tj[st.hub[o + e]];
         if (th != kInf8 && st.dist[o + e] + th <= d) pr = true;
@@ -126,6 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
     }
     if (pr) continue;
     // label (k, d) for u, pending cleaning
+    if (gr == 0) c_lab++;
     const int64_t c = wave_append(gr == 0, &ctl->ccnt);
     if (c >= 0) {
       if (c < w.ccap) {
@@ -153,6 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
       continue;
     }
     const int64_t lim = deg < chunk ? deg : chunk;
+    if (gr == 0) c_edge += (unsigned long long)lim;
     for (int64_t e = gr; e < lim; e += G) {
       const int32_t x = g.col[e0 + e];
       const uint32_t bit = 1u << (x & 31);
@@ -184,6 +188,18 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
       }
     }
   }
+  c_visit = Group<kWave>::sum_reduce(c_visit);
+  c_test = Group<kWave>::sum_reduce(c_test);
+  c_scan = Group<kWave>::sum_reduce(c_scan);
+  c_lab = Group<kWave>::sum_reduce(c_lab);
+  c_edge = Group<kWave>::sum_reduce(c_edge);
+  if (lane_id() == 0 && c_visit) {
+    atomicAdd(&ctl->visited, c_visit);
+    atomicAdd(&ctl->ntests, c_test);
+    atomicAdd(&ctl->lscanned, c_scan);
+    atomicAdd(&ctl->labeled, c_lab);
+    atomicAdd(&ctl->edges, c_edge);
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFrontier f, int d,
@@ -201,6 +217,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFron
     const int64_t a = e0 + (int64_t)c * chunk;
     const int64_t b = a + chunk < e1 ? a + chunk : e1;
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
+    if (lane_id() == 0) atomicAdd(&ctl->hedges, (unsigned long long)(b - a));
     for (int64_t e = a + lane_id(); e < b; e += kWave) {
       const int32_t x = g.col[e];
       const uint32_t bit = 1u << (x & 31);
@@ -374,8 +391,10 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t 
 
 template <int G>
 void launch_level_g(DGraph g, DBp bp, DStore st, DWindow w, DFrontier f, int d, int chunk,
-                    hipStream_t s, int blocks) {
+                    hipStream_t s, int blocks, hipEvent_t ev0, hipEvent_t ev1) {
+  if (ev0) (void)hipEventRecord(ev0, s);
   hipLaunchKernelGGL(k_win_level<G>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d, chunk);
+  if (ev1) (void)hipEventRecord(ev1, s);
   hipLaunchKernelGGL(k_win_heavy, dim3(blocks), dim3(kBlock), 0, s, g, w, f, d, chunk);
 }
 
@@ -401,14 +420,14 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 }
 
 hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int chunk, hipStream_t st) {
+                            int chunk, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   const int blocks = 2048;
   switch (group) {
-    case 4: launch_level_g<4>(g, bp, s, w, f, d, chunk, st, blocks); break;
-    case 8: launch_level_g<8>(g, bp, s, w, f, d, chunk, st, blocks); break;
-    case 16: launch_level_g<16>(g, bp, s, w, f, d, chunk, st, blocks); break;
-    case 32: launch_level_g<32>(g, bp, s, w, f, d, chunk, st, blocks); break;
-    default: launch_level_g<64>(g, bp, s, w, f, d, chunk, st, blocks); break;
+    case 4: launch_level_g<4>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
+    case 8: launch_level_g<8>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
+    case 16: launch_level_g<16>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
+    case 32: launch_level_g<32>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
+    default: launch_level_g<64>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
   }
   return hipGetLastError();
 }
