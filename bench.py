@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PLL index build s & edges/s; queries/s + p99 latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "win_level_traffic_rmat18.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_test_traffic_rmat18.json")
 LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip")
 
 
@@ -52,15 +52,15 @@ def file_sha(path):
 
 
 def level_kernel_bytes(st, t_bp):
-    """Algorithmic bytes of the pruned-phase level kernel, summed over all its
-    launches in one build (per-unit figures of the byte model):
+    """Algorithmic bytes of the pruned-phase prune-test kernel (k_win_test),
+    summed over all its launches in one build (per-unit figures of the byte
+    model in DESIGN.md):
       per visited (root, vertex): 16 B label offsets + 17*t_bp B bit-parallel
         label of the vertex,
       per label entry scanned by a normal-label test: 5 B (hub + distance),
-      per labeled vertex: 8 B row offsets + 5 B label append,
-      per adjacency entry expanded: 5 B (neighbour id + visited check)."""
+      per labeled vertex: 5 B label append."""
     return (st["visited"] * (16 + 17 * t_bp) + 5 * st["label_scanned"]
-            + 13 * st["candidates"] + 5 * st["edges"])
+            + 5 * st["candidates"])
 
 
 def cpu_baseline(g, order, t_bp, pairs):
@@ -166,7 +166,7 @@ def main():
         if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
             traffic = tr.get("bytes_per_launch")
     roofline = {
-        "kernel": "k_win_level (pruned-BFS level over all roots of a window)",
+        "kernel": "k_win_test (pruned-BFS prune tests, all roots of a window, one level)",
         "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
         "achieved": achieved, "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": traffic,

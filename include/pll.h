@@ -153,6 +153,9 @@ enum {
   PLL_STAT_LEVEL_LAUNCHES, /* launches of the pruned-phase level kernel */
   PLL_STAT_LEVEL_NS,     /* their summed duration from HIP events, ns; only
                             with the "profile" knob set, else 0 */
+  PLL_STAT_BP_DIRECT,    /* visits pruned by bit-parallel distances alone */
+  PLL_STAT_BP_SETS,      /* visits whose bit-parallel test read slot sets */
+  PLL_STAT_BP_CHECKS,    /* slot set pairs read by those tests */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);

@@ -19,11 +19,12 @@ namespace {
 
 struct Tuning {
   int window = 1024;  // concurrent roots of the pruned phase
-  int group = 16;     // lanes per frontier entry
+  int group = 4;      // lanes per frontier entry
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
   int profile = 0;
+  int bp_chunk = 64;  // adjacency entries per bit-parallel work item
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -110,10 +111,10 @@ int64_t ns_since(Clock::time_point t0) {
 // ---------------------------------------------------------------------------
 
 struct pll_index {
-  int32_t n = 0, t = 0;
-  DBuf<int32_t> rank;  // id -> rank
-  DBuf<uint8_t> bpd;   // [n][t]
-  DBuf<uint64_t> bpm;  // [n][t][2]
+  int32_t n = 0, t = 0, tpad = 0;
+  DBuf<int32_t> rank;   // id -> rank
+  DBuf<uint8_t> bpd;    // [n][tpad], padding 255
+  DBuf<uint64_t> bpm;   // [n][t][2] (S^{-1}, S^{0}) pairs
   DBuf<int64_t> off;   // [n+1], sentinel-inclusive CSR
   DBuf<uint32_t> hub;
   DBuf<uint8_t> dist;
@@ -126,6 +127,7 @@ struct pll_index {
     DIndex v;
     v.n = n;
     v.t = t;
+    v.tpad = tpad;
     v.rank = rank.p;
     v.bpd = bpd.p;
     v.bpm = bpm.p;
@@ -192,7 +194,8 @@ struct Builder {
   DBuf<uint8_t> used;
   int64_t stat_levels = 0, stat_bp_visited = 0, stat_visited = 0, stat_cand = 0,
           stat_windows = 0, stat_retries = 0, stat_roots = 0, stat_tests = 0, stat_scanned = 0,
-          stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0;
+          stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0,
+          stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0;
 
   DGraph graph() const { return DGraph{n, nwords, row.p, col.p}; }
 
@@ -227,12 +230,16 @@ struct Builder {
   void bit_parallel(pll_index *ix) {
     used.alloc((size_t)n);
     fill(used, 0, st);
-    ix->bpd.alloc((size_t)n * t);
+    const int32_t tpad = bp_pad(t);
+    ix->tpad = tpad;
+    ix->bpd.alloc((size_t)n * tpad);
     ix->bpm.alloc((size_t)n * t * 2);
     ix->bp_root.assign((size_t)t, -1);
     ix->bp_nsel.assign((size_t)t, 0);
     ix->bp_sel.assign((size_t)t * 64, -1);
     if (t == 0) return;
+    fill(ix->bpd, 0xFF, st);
+    if (n == 0) return;
     DBuf<uint32_t> used_bits((size_t)nwords), tmp_bits((size_t)nwords);
     DBuf<int32_t> root((size_t)t), nsel((size_t)t), sel((size_t)t * 64);
     fill(used_bits, 0, st);
@@ -243,63 +250,54 @@ struct Builder {
     d2h(ix->bp_root.data(), root.p, (size_t)t, st);
     d2h(ix->bp_nsel.data(), nsel.p, (size_t)t, st);
     d2h(ix->bp_sel.data(), sel.p, (size_t)t * 64, st);
-    check(hipStreamSynchronize(st));
-
-    // slot-major working arrays
-    DBuf<uint8_t> bd((size_t)t * n);
-    DBuf<uint64_t> bs1((size_t)t * n), bs0((size_t)t * n);
-    DBuf<uint32_t> vis((size_t)t * nwords);
-    fill(bd, 0xFF, st);
-    fill(bs1, 0, st);
-    fill(bs0, 0, st);
-    fill(vis, 0, st);
-    // frontier: every (slot, vertex) is visited at most once
-    const int64_t fcap = std::max<int64_t>((int64_t)t * n, 1);
-    const int64_t hcap = std::max<int64_t>((int64_t)t * (nnz / tu.chunk + 1), 1);
-    DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap);
-    DBuf<int32_t> h1((size_t)hcap * 3), h2((size_t)hcap * 3);
-    DBuf<LevelCtl> ctl(1);
-    // levels 0 and 1 start with the roots and their chosen neighbours
-    std::vector<int32_t> s0, v0, s1, v1;
-    for (int32_t i = 0; i < t; i++) {
-      if (ix->bp_root[i] < 0) continue;
-      s0.push_back(i);
-      v0.push_back(ix->bp_root[i]);
-      for (int32_t j = 0; j < ix->bp_nsel[i]; j++) {
-        s1.push_back(i);
-        v1.push_back(ix->bp_sel[(size_t)i * 64 + j]);
-      }
+    // distances start at infinity, sets empty
+    fill(ix->bpd, 0xFF, st);
+    fill(ix->bpm, 0, st);
+    DBuf<uint64_t> found((size_t)n);
+    fill(found, 0, st);
+    // work items: (vertex, chunk of its adjacency list)
+    const int bchunk = tu.bp_chunk;
+    int64_t nitems = 0;
+    DBuf<int32_t> it_v, it_c;
+    {
+      DBuf<int64_t> icnt((size_t)n), ioff((size_t)n + 1), tmp((size_t)scan_tmp_elems(n));
+      check(launch_bpv_items_count(graph(), bchunk, icnt.p, ioff.p, tmp.p, st));
+      d2h(&nitems, ioff.p + n, 1, st);
+      check(hipStreamSynchronize(st));
+      it_v.alloc((size_t)std::max<int64_t>(nitems, 1));
+      it_c.alloc((size_t)std::max<int64_t>(nitems, 1));
+      check(launch_bpv_items_fill(graph(), ioff.p, it_v.p, it_c.p, st));
     }
-    std::vector<int32_t> fs(s0), fvv(v0);
-    fs.insert(fs.end(), s1.begin(), s1.end());
-    fvv.insert(fvv.end(), v1.begin(), v1.end());
-    h2d(fslot.p, fs.data(), fs.size(), st);
-    h2d(fv.p, fvv.data(), fvv.size(), st);
-    LevelCtl h{};
-    h.cnt[0] = s0.size();
-    h.cnt[1] = s1.size();
-    h.base[0] = 0;
-    h.base[1] = s0.size();
-    check(hipMemcpyAsync(ctl.p, &h, sizeof(LevelCtl), hipMemcpyHostToDevice, st));
-    DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
-                h2.p, h2.p + hcap, h2.p + 2 * hcap, ctl.p};
-    check(launch_bp_init(graph(), t, root.p, nsel.p, sel.p, nullptr, bd.p, bs1.p, vis.p, f, st));
+    DBpW b{t, tpad, ix->bpd.p, ix->bpm.p, found.p};
+    check(launch_bpv_init(t, b, root.p, nsel.p, sel.p, st));
+    // per-level counts of newly reached (slot, vertex) pairs, and flags
+    DBuf<unsigned long long> lcnt(kMaxLevels + 2);
+    DBuf<int32_t> flags(1);
+    fill(lcnt, 0, st);
+    fill(flags, 0, st);
+    std::vector<unsigned long long> hc(kMaxLevels + 2, 0);
     int L = 0;
-    bool done = s0.empty();
+    bool done = false;
     while (!done) {
       const int upto = std::min(L + tu.levels_per_sync, kMaxLevels - 1);
       for (; L < upto; L++) {
-        check(launch_bp_level(graph(), t, L, tu.group, tu.chunk, bd.p, bs1.p, bs0.p, vis.p, f,
-                              st));
+        check(launch_bpv_level(graph(), b, it_v.p, it_c.p, nitems, bchunk, L, lcnt.p + L, flags.p,
+                               st));
         stat_levels++;
       }
-      read_ctl(&h, ctl.p, st);
-      if (h.flags & kFlagRange) throw Fail{PLL_E_RANGE};
-      if (h.flags) throw Fail{PLL_E_NOMEM};
-      if (h.cnt[L] == 0 || L >= kMaxLevels - 1) done = true;
+      int32_t hf = 0;
+      d2h(hc.data(), lcnt.p, hc.size(), st);
+      d2h(&hf, flags.p, 1, st);
+      check(hipStreamSynchronize(st));
+      if (hf & kFlagRange) throw Fail{PLL_E_RANGE};
+      // level L-1 found nothing new: every slot's BFS is over
+      if (hc[L - 1] == 0 || L >= kMaxLevels - 1) done = true;
     }
-    for (int i = 0; i < kMaxLevels + 2; i++) stat_bp_visited += (int64_t)h.cnt[i];
-    check(launch_bp_finish(n, t, bd.p, bs1.p, bs0.p, ix->bpd.p, ix->bpm.p, st));
+    int64_t reached = 0;
+    for (int32_t i = 0; i < t; i++) reached += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
+    for (auto c : hc) reached += (int64_t)c;
+    stat_bp_visited = reached;
+    check(launch_bpv_finish((int64_t)n * t, ix->bpm.p, st));
     check(hipStreamSynchronize(st));
   }
 
@@ -341,7 +339,7 @@ struct Builder {
     DBuf<LevelCtl> ctl(1);
     DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
                 nullptr, nullptr, nullptr, ctl.p};
-    DBp bp{t, ix->bpd.p, ix->bpm.p};
+    DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p};
     LevelCtl h{};
     int64_t entries_bound = 0;
     unsigned long long htop = 0;
@@ -430,6 +428,9 @@ struct Builder {
       stat_scanned += (int64_t)h.lscanned;
       stat_edges += (int64_t)h.edges;
       stat_hedges += (int64_t)h.hedges;
+      stat_bp_direct += (int64_t)h.bp_direct;
+      stat_bp_sets += (int64_t)h.bp_sets;
+      stat_bp_checks += (int64_t)h.bp_checks;
       stat_cand += ncand;
       stat_windows++;
       s = e;
@@ -507,6 +508,9 @@ int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   S[PLL_STAT_TASK_EDGES] = b.stat_hedges;
   S[PLL_STAT_LEVEL_LAUNCHES] = b.stat_level_launches;
   S[PLL_STAT_LEVEL_NS] = b.stat_level_ns;
+  S[PLL_STAT_BP_DIRECT] = b.stat_bp_direct;
+  S[PLL_STAT_BP_SETS] = b.stat_bp_sets;
+  S[PLL_STAT_BP_CHECKS] = b.stat_bp_checks;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }
@@ -666,7 +670,13 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
     }
     if (off) off[n] = e;
     const size_t nb = (size_t)n * t;
-    if (bp_d && nb) d2h(bp_d, idx->bpd.p, nb, st);
+    if (bp_d && nb) {
+      std::vector<uint8_t> dpad((size_t)n * idx->tpad);
+      d2h(dpad.data(), idx->bpd.p, dpad.size(), st);
+      check(hipStreamSynchronize(st));
+      for (size_t v = 0; v < (size_t)n; v++)
+        std::memcpy(bp_d + v * t, dpad.data() + v * idx->tpad, (size_t)t);
+    }
     if ((bp_m1 || bp_0) && nb) {
       std::vector<uint64_t> m(nb * 2);
       d2h(m.data(), idx->bpm.p, nb * 2, st);
@@ -727,6 +737,9 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "profile") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.profile = (int)value;
+  } else if (k == "bp_chunk") {
+    if (value < 1 || value > (1 << 20)) return PLL_E_INVAL;
+    g_tune.bp_chunk = (int)value;
   } else {
     return PLL_E_INVAL;
   }
@@ -743,6 +756,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;
   if (k == "profile") return g_tune.profile;
+  if (k == "bp_chunk") return g_tune.bp_chunk;
   return PLL_E_INVAL;
 }
 

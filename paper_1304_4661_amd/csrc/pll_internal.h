@@ -41,6 +41,45 @@ __device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *ct
   return (int64_t)(base + (unsigned long long)__popcll(m & lanes_below_mask()));
 }
 
+// Wave-private staging of (a, b) pairs in LDS, written out to a global
+// list with one atomic reservation per flush.  Every method must be called
+// by all 64 lanes of the wave together (converged code): the fill count is
+// then the same in every lane.
+template <int CAP>
+struct WaveStage {
+  int32_t *a, *b;  // this wave's LDS arrays, CAP entries each
+  int n;           // entries staged (wave-uniform)
+  __device__ __forceinline__ void init(int32_t *aa, int32_t *bb) {
+    a = aa;
+    b = bb;
+    n = 0;
+  }
+  // stage (va, vb) from each lane with pred; flush first if it might not fit
+  template <typename F>
+  __device__ __forceinline__ void push(bool pred, int32_t va, int32_t vb, F &&flush) {
+    const uint64_t m = __ballot(pred);
+    if (!m) return;
+    if (n + kWave > CAP) {
+      flush(*this);
+      n = 0;
+    }
+    if (pred) {
+      const int pos = n + __popcll(m & lanes_below_mask());
+      a[pos] = va;
+      b[pos] = vb;
+    }
+    n += __popcll(m);
+  }
+  // reserve n slots at *ctr; returns the base (same in every lane) after
+  // making the staged entries visible to the whole wave
+  __device__ __forceinline__ unsigned long long reserve(unsigned long long *ctr) {
+    __threadfence_block();
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(ctr, (unsigned long long)n);
+    return __shfl(base, 0);
+  }
+};
+
 // Groups of G consecutive lanes inside a wave.
 template <int G>
 struct Group {
@@ -62,6 +101,14 @@ struct Group {
   __device__ __forceinline__ static unsigned long long sum_reduce(unsigned long long v) {
 #pragma unroll
     for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, G);
+    return v;
+  }
+  __device__ __forceinline__ static int64_t max_reduce64(int64_t v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      int64_t w = __shfl_xor(v, o, G);
+      v = w > v ? w : v;
+    }
     return v;
   }
   __device__ __forceinline__ static int min_reduce(int v) {
@@ -109,13 +156,24 @@ struct DGraph {
   const int32_t *col;  // [row[n]]
 };
 
-// Bit-parallel labels, vertex-major: for vertex v and slot i, d[v*t+i] and
-// m[2*(v*t+i)] = S^{-1}, m[2*(v*t+i)+1] = S^{0}.
+// Bit-parallel labels, vertex-major: for vertex v and slot i, the distance
+// d[v*tpad+i] (rows padded to a multiple of 16 bytes with 255, so a lane can
+// read 16 slots at once) and the two sets of the slot side by side in one
+// 16-byte pair: m[2*(v*t+i)] = S^{-1}, m[2*(v*t+i)+1] = S^{0}.
 struct DBp {
-  int32_t t;
+  int32_t t, tpad;
   const uint8_t *d;
   const uint64_t *m;
 };
+// The same, writable, plus per-vertex "found at the next level" slot bits
+// used while the bit-parallel BFS runs.
+struct DBpW {
+  int32_t t, tpad;
+  uint8_t *d;
+  uint64_t *m;
+  uint64_t *found;
+};
+__host__ __device__ inline int32_t bp_pad(int32_t t) { return (t + 15) & ~15; }
 
 // Per-level control block of a level-synchronous frontier whose levels are
 // stored one after another: level L occupies [base[L], base[L] + cnt[L]).
@@ -124,6 +182,7 @@ struct LevelCtl {
   unsigned long long base[kMaxLevels + 2];
   unsigned long long hcnt[kMaxLevels + 2];  // heavy expansion tasks per level
   unsigned long long hcnt2[kMaxLevels + 2]; // second task list (bit-parallel E1)
+  unsigned long long cmark[kMaxLevels + 2]; // first candidate found at each level
   unsigned long long ccnt;                  // candidate labels of the window
   unsigned long long visited;               // (root, vertex) entries tested
   unsigned long long ntests;                // ... that reached the normal-label test
@@ -131,6 +190,9 @@ struct LevelCtl {
   unsigned long long labeled;               // entries labeled (candidates)
   unsigned long long edges;                 // adjacency entries expanded inline
   unsigned long long hedges;                // adjacency entries expanded as tasks
+  unsigned long long bp_direct;             // entries pruned by distance bytes alone
+  unsigned long long bp_sets;               // entries that read slot sets
+  unsigned long long bp_checks;             // slot-set pairs read
   int32_t flags;
   int32_t pad;
 };
@@ -203,14 +265,17 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int
 hipError_t launch_bp_select(DGraph g, int32_t t, uint32_t *used_bits, uint32_t *tmp_bits,
                             uint8_t *used_bytes, int32_t *root, int32_t *nsel, int32_t *sel,
                             hipStream_t st);
-hipError_t launch_bp_init(DGraph g, int32_t t, const int32_t *root, const int32_t *nsel,
-                          const int32_t *sel, const int32_t *sel_pos, uint8_t *bd, uint64_t *bs1,
-                          uint32_t *vis, DFrontier f, hipStream_t st);
-hipError_t launch_bp_level(DGraph g, int32_t t, int L, int group, int chunk, uint8_t *bd,
-                           uint64_t *bs1, uint64_t *bs0, uint32_t *vis, DFrontier f,
-                           hipStream_t st);
-hipError_t launch_bp_finish(int32_t n, int32_t t, const uint8_t *bd, const uint64_t *bs1,
-                            const uint64_t *bs0, uint8_t *d, uint64_t *m, hipStream_t st);
+// bit-parallel BFS: work items = (vertex, chunk of its adjacency list)
+hipError_t launch_bpv_items_count(DGraph g, int chunk, int64_t *cnt, int64_t *ioff, int64_t *tmp,
+                                  hipStream_t st);
+hipError_t launch_bpv_items_fill(DGraph g, const int64_t *ioff, int32_t *it_v, int32_t *it_c,
+                                 hipStream_t st);
+hipError_t launch_bpv_init(int32_t t, DBpW b, const int32_t *root, const int32_t *nsel,
+                           const int32_t *sel, hipStream_t st);
+hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t *it_c,
+                            int64_t nitems, int chunk, int L, unsigned long long *cnt,
+                            int32_t *flags, hipStream_t st);
+hipError_t launch_bpv_finish(int64_t total, uint64_t *m, hipStream_t st);
 
 hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
 hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
@@ -230,10 +295,10 @@ hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint
 // Queries: ranks of ids, bit-parallel labels, final CSR labels with sentinel.
 struct DIndex {
   int32_t n;
-  int32_t t;
+  int32_t t, tpad;
   const int32_t *rank;
   const uint8_t *bpd;
-  const uint64_t *bpm;
+  const uint64_t *bpm;  // interleaved (S^{-1}, S^{0}) pairs
   const int64_t *off;
   const uint32_t *hub;
   const uint8_t *dist;

@@ -99,25 +99,29 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int64_t *in, 
 // itself, order a permutation.  Any violation sets *err.
 __global__ void k_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
                                  const int32_t *order, uint32_t *seen, int32_t *err) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-       v += (int64_t)gridDim.x * blockDim.x) {
+  // one wave per vertex: offsets and the order entry by lane 0, the row's
+  // neighbours by all lanes
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t v = wid; v < n; v += nw) {
     const int32_t a = row[v], b = row[v + 1];
     if ((v == 0 && a != 0) || b < a) {
-      atomicOr(err, 1);
+      if (lane_id() == 0) atomicOr(err, 1);
       continue;
     }
-    for (int32_t j = a; j < b; j++) {
+    bool bad = false;
+    for (int32_t j = a + lane_id(); j < b; j += kWave) {
       const int32_t w = col[j];
-      if (w < 0 || w >= n || w == (int32_t)v) {
-        atomicOr(err, 1);
-        break;
-      }
+      bad |= w < 0 || w >= n || w == (int32_t)v;
     }
-    const int32_t o = order[v];
-    if (o < 0 || o >= n) {
-      atomicOr(err, 1);
-    } else if (atomicOr(&seen[o >> 5], 1u << (o & 31)) & (1u << (o & 31))) {
-      atomicOr(err, 1);
+    if (bad) atomicOr(err, 1);
+    if (lane_id() == 0) {
+      const int32_t o = order[v];
+      if (o < 0 || o >= n) {
+        atomicOr(err, 1);
+      } else if (atomicOr(&seen[o >> 5], 1u << (o & 31)) & (1u << (o & 31))) {
+        atomicOr(err, 1);
+      }
     }
   }
 }
@@ -291,8 +295,8 @@ hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *c
                                  const int32_t *order, uint32_t *seen, int32_t *err,
                                  hipStream_t st) {
   if (n == 0) return hipSuccess;
-  int64_t blocks = ((int64_t)n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  int64_t blocks = ((int64_t)n * kWave + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_validate_graph, dim3((unsigned)blocks), dim3(256), 0, st, n, row, col,
                      order, seen, err);
   return hipGetLastError();

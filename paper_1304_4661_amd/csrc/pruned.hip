@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
 __device__ bool prune_test_serial(DBp bp, DStore st, const uint8_t *Tj, int32_t k, int32_t u,
                                   int d) {
   for (int32_t i = 0; i < bp.t; i++) {
-    const int dk = bp.d[(int64_t)k * bp.t + i], du = bp.d[(int64_t)u * bp.t + i];
+    const int dk = bp.d[(int64_t)k * bp.tpad + i], du = bp.d[(int64_t)u * bp.tpad + i];
     if (dk == kInf8 || du == kInf8) continue;
     const uint64_t *mk = bp.m + 2 * ((int64_t)k * bp.t + i);
     const uint64_t *mu = bp.m + 2 * ((int64_t)u * bp.t + i);
@@ -74,15 +74,129 @@ __device__ bool prune_test_serial(DBp bp, DStore st, const uint8_t *Tj, int32_t 
   return false;
 }
 
-// One BFS level of every root of the window.  A group of G lanes takes one
-// (root slot j, vertex u) entry at distance d: bit-parallel test over the
-// slots, then the normal-label test against T[j] (prune iff some hub gives
-// <= d), else record the candidate label (k, d) and push u's unvisited
-// neighbours to level d+1.  Long adjacency lists: the first `chunk` edges
-// here, the rest as tasks for whole waves.
+// Bit-parallel prune test of (root k, vertex u, distance d) by a group of G
+// lanes: does some slot give QUERY_BP(k, u) <= d (Section 5.3)?  A slot's
+// estimate is d_k + d_u minus 0, 1 or 2, so the distance bytes decide most
+// slots alone: d_k + d_u <= d prunes outright ("direct"), d_k + d_u - 2 > d
+// never does.  Only the slots in between read their (S^{-1}, S^{0}) pairs,
+// G slots per round, the slots that prune with -1 or -2 first (they succeed
+// more often than the -2-only ones), stopping at the first round that
+// prunes.  Distance rows are read 16 slots per lane.
+struct BpTally {
+  unsigned long long direct = 0, sets = 0, checks = 0;
+};
+
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore st, DWindow w,
-                                                      DFrontier f, int d, int chunk) {
+__device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, int d,
+                                          BpTally &tally) {
+  const int gr = Group<G>::rank();
+  const int nv = bp.tpad >> 4;
+  bool direct = false;
+  uint64_t need1 = 0, need2 = 0;  // slots where only -2 helps / where -1 or -2 helps
+  if (gr < nv) {
+    const uint4 a = reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad)[gr];
+    const uint4 b = reinterpret_cast<const uint4 *>(bp.d + (int64_t)u * bp.tpad)[gr];
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+#pragma unroll
+      for (int y = 0; y < 4; y++) {
+        const int dk = (aw[q] >> (8 * y)) & 0xff, du = (bw[q] >> (8 * y)) & 0xff;
+        if (dk == kInf8 || du == kInf8) continue;
+        const int sum = dk + du;
+        const uint64_t bit = 1ull << (gr * 16 + q * 4 + y);
+        if (sum <= d)
+          direct = true;
+        else if (sum - 1 == d)
+          need2 |= bit;
+        else if (sum - 2 == d)
+          need1 |= bit;
+      }
+    }
+  }
+  if (Group<G>::any(direct)) {
+    if (gr == 0) tally.direct++;
+    return true;
+  }
+  need1 = Group<G>::or_reduce(need1);
+  need2 = Group<G>::or_reduce(need2);
+  if (!(need1 | need2)) return false;
+  if (gr == 0) tally.sets++;
+  const ulonglong2 *pk = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)k * bp.t;
+  const ulonglong2 *pu = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)u * bp.t;
+  uint64_t rest2 = need2, rest1 = need1;
+  while (rest2 | rest1) {
+    // deal the next G slots of the queue (need2 first) to the lanes
+    int mine = -1;
+    bool mine2 = false;
+#pragma unroll
+    for (int r = 0; r < G; r++) {
+      int i = -1;
+      bool is2 = false;
+      if (rest2) {
+        i = __ffsll((unsigned long long)rest2) - 1;
+        rest2 &= rest2 - 1;
+        is2 = true;
+      } else if (rest1) {
+        i = __ffsll((unsigned long long)rest1) - 1;
+        rest1 &= rest1 - 1;
+      }
+      if (r == gr) {
+        mine = i;
+        mine2 = is2;
+      }
+    }
+    bool pr = false;
+    if (mine >= 0) {
+      if (gr == 0) tally.checks++;
+      const ulonglong2 mk = pk[mine], mu = pu[mine];
+      pr = (mk.x & mu.x) != 0 || (mine2 && ((mk.y & mu.x) | (mk.x & mu.y)) != 0);
+    }
+    if (Group<G>::any(pr)) return true;
+  }
+  return false;
+}
+
+// Normal-label test against the root's row of T (Section 4.5.1): is some
+// (h, delta) of L(u) with delta + T[h] <= d?  Stops at the first hit.
+template <int G>
+__device__ __forceinline__ bool label_prunes(const DStore &st, const uint8_t *Tj, int32_t u,
+                                             int d, int32_t *len_out) {
+  const int gr = Group<G>::rank();
+  const int64_t o = st.off[u];
+  const int32_t len = st.len[u];
+  *len_out = len;
+  for (int32_t base = 0; base < len; base += G) {
+    const int32_t e = base + gr;
+    bool hit = false;
+    if (e < len) {
+      const int th = Tj[st.hub[o + e]];
+      hit = th != kInf8 && st.dist[o + e] + th <= d;
+    }
+    if (Group<G>::any(hit)) return true;
+  }
+  return false;
+}
+
+// One BFS level of every root of the window, in two kernels.
+//
+// k_win_test: a group of G lanes takes one (root slot j, vertex u) entry at
+// distance d and runs the bit-parallel test, then the normal-label test
+// against T[j].  If neither prunes, u gets the candidate label (k, d).  The
+// work per entry is short and uniform, so many entries are in flight.
+//
+// k_win_expand: the candidates of this level push their unvisited
+// neighbours to level d+1, a group per candidate with lanes over the
+// adjacency list (long lists: the first `chunk` entries here, the rest as
+// tasks for whole waves in k_win_heavy).
+constexpr int kStage = 256;                 // staged entries per wave
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DWindow w,
+                                                     DFrontier f, int d) {
+  __shared__ int32_t s_a[kWavesPerBlock][kStage];
+  __shared__ int32_t s_b[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
   const unsigned long long nbase = beg + cnt;
@@ -90,90 +204,164 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
   // after an overflow the window is redone; never read past the buffer
   if (cnt == 0 || (ctl->flags & kOverflowFlags) || nbase > (unsigned long long)f.cap) return;
   const int64_t n = g.n;
-  const int32_t t = bp.t;
   const int gr = Group<G>::rank();
-  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
-  // work counters, per lane (group leaders), summed once per wave at the end
-  unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0, c_edge = 0;
-  for (int64_t p = gid; p < (int64_t)cnt; p += ngroups) {
-    const int32_t j = f.slot[beg + p];
-    const int32_t u = f.v[beg + p];
-    const int32_t k = w.s + j;
-    if (gr == 0) c_visit++;
-    // bit-parallel labels first (Section 5.4)
-    bool pr = false;
-    for (int32_t i = gr; i < t; i += G) {
-      const int dk = bp.d[(int64_t)k * t + i], du = bp.d[(int64_t)u * t + i];
-      if (dk != kInf8 && du != kInf8 && dk + du - 2 <= d) {
-        const uint64_t *mk = bp.m + 2 * ((int64_t)k * t + i);
-        const uint64_t *mu = bp.m + 2 * ((int64_t)u * t + i);
-        if (bp_pair_dist(dk, mk[0], mk[1], du, mu[0], mu[1]) <= d) pr = true;
-      }
-    }
-    pr = Group<G>::any(pr);
-    if (!pr) {
-      const uint8_t *Tj = w.T + (int64_t)j * n;
-      const int64_t o = st.off[u];
-      const int32_t len = st.len[u];
-      if (gr == 0) {
-        c_test++;
-        c_scan += (unsigned long long)len;
-      }
-      for (int32_t e = gr; e < len; e += G) {
-        const int th = Tj[st.hub[o + e]];
-        if (th != kInf8 && st.dist[o + e] + th <= d) pr = true;
-      }
-      pr = Group<G>::any(pr);
-    }
-    if (pr) continue;
-    // label (k, d) for u, pending cleaning
-    if (gr == 0) c_lab++;
-    const int64_t c = wave_append(gr == 0, &ctl->ccnt);
-    if (c >= 0) {
-      if (c < w.ccap) {
+  constexpr int kPerWave = kWave / G;
+  const int wv = threadIdx.x / kWave;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  WaveStage<kStage> stage;
+  stage.init(s_a[wv], s_b[wv]);
+  // candidates (u, j): reserve list slots, write them and their window rows
+  auto flush = [&](WaveStage<kStage> &sg) {
+    const unsigned long long c0 = sg.reserve(&ctl->ccnt);
+    for (int i = lane_id(); i < sg.n; i += kWave) {
+      const unsigned long long c = c0 + i;
+      if (c < (unsigned long long)w.ccap) {
+        const int32_t u = sg.a[i], j = sg.b[i];
         w.cu[c] = u;
         w.cj[c] = j;
         w.cd[c] = (uint8_t)d;
-        w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
-        atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
-                 1ull << (j & 63));
       } else {
         atomicOr(&ctl->flags, kFlagOvfCand);
       }
     }
-    const int64_t e0 = g.row[u];
-    const int64_t deg = g.row[u + 1] - e0;
-    uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-    if (d + 1 >= (int)kInf8) {
-      // neighbours would sit at distance 255: fine only if all are pruned
-      const uint8_t *Tj = w.T + (int64_t)j * n;
-      for (int64_t e = gr; e < deg; e += G) {
-        const int32_t x = g.col[e0 + e];
-        if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
-        if (!prune_test_serial(bp, st, Tj, k, x, d + 1)) atomicOr(&ctl->flags, kFlagRange);
-      }
-      continue;
-    }
-    const int64_t lim = deg < chunk ? deg : chunk;
-    if (gr == 0) c_edge += (unsigned long long)lim;
-    for (int64_t e = gr; e < lim; e += G) {
-      const int32_t x = g.col[e0 + e];
-      const uint32_t bit = 1u << (x & 31);
-      bool claimed = false;
-      if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vs[x >> 5], bit) & bit);
-      const int64_t pos = wave_append(claimed, &ctl->cnt[d + 1]);
-      if (pos >= 0) {
-        if ((int64_t)nbase + pos < f.cap) {
-          f.slot[nbase + pos] = j;
-          f.v[nbase + pos] = x;
-        } else {
-          atomicOr(&ctl->flags, kFlagOvfFrontier);
+  };
+  unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
+  BpTally tally;
+  // the wave steps through the frontier in lockstep, kPerWave entries at a time
+  for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
+    const int64_t p = base + lane_id() / G;
+    bool labeled = false;
+    int32_t u = 0, j = 0;
+    if (p < (int64_t)cnt) {
+      j = f.slot[beg + p];
+      u = f.v[beg + p];
+      const int32_t k = w.s + j;
+      if (gr == 0) c_visit++;
+      bool pr = bp_prunes<G>(bp, k, u, d, tally);  // bit-parallel first (Section 5.4)
+      if (!pr) {
+        int32_t len;
+        pr = label_prunes<G>(st, w.T + (int64_t)j * n, u, d, &len);
+        if (gr == 0) {
+          c_test++;
+          c_scan += (unsigned long long)len;
         }
       }
+      labeled = !pr && gr == 0;
+      if (labeled) {
+        c_lab++;
+        w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
+        atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
+                 1ull << (j & 63));
+      }
     }
-    if (deg > chunk) {
-      const int64_t extra = (deg + chunk - 1) / chunk - 1;
+    stage.push(labeled, u, j, flush);
+  }
+  if (stage.n) flush(stage);
+  c_visit = Group<kWave>::sum_reduce(c_visit);
+  c_test = Group<kWave>::sum_reduce(c_test);
+  c_scan = Group<kWave>::sum_reduce(c_scan);
+  c_lab = Group<kWave>::sum_reduce(c_lab);
+  tally.direct = Group<kWave>::sum_reduce(tally.direct);
+  tally.sets = Group<kWave>::sum_reduce(tally.sets);
+  tally.checks = Group<kWave>::sum_reduce(tally.checks);
+  if (lane_id() == 0 && c_visit) {
+    atomicAdd(&ctl->visited, c_visit);
+    atomicAdd(&ctl->ntests, c_test);
+    atomicAdd(&ctl->lscanned, c_scan);
+    atomicAdd(&ctl->labeled, c_lab);
+    atomicAdd(&ctl->bp_direct, tally.direct);
+    atomicAdd(&ctl->bp_sets, tally.sets);
+    atomicAdd(&ctl->bp_checks, tally.checks);
+  }
+}
+
+// Frontier entries (j, x) of level d+1: reserve slots and write them.
+struct FrontierFlush {
+  LevelCtl *ctl;
+  DFrontier f;
+  unsigned long long nbase;
+  int d;
+  __device__ void operator()(WaveStage<kStage> &sg) const {
+    const unsigned long long q0 = sg.reserve(&ctl->cnt[d + 1]);
+    for (int i = lane_id(); i < sg.n; i += kWave) {
+      const unsigned long long q = nbase + q0 + i;
+      if (q < (unsigned long long)f.cap) {
+        f.slot[q] = sg.a[i];
+        f.v[q] = sg.b[i];
+      } else {
+        atomicOr(&ctl->flags, kFlagOvfFrontier);
+      }
+    }
+  }
+};
+
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore st, DWindow w,
+                                                       DFrontier f, int d, int chunk) {
+  __shared__ int32_t s_a[kWavesPerBlock][kStage];
+  __shared__ int32_t s_b[kWavesPerBlock][kStage];
+  LevelCtl *ctl = f.ctl;
+  const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
+  const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
+  if (cend <= cbeg || (ctl->flags & kOverflowFlags)) return;
+  const unsigned long long nbase = ctl->base[d + 1];
+  const int64_t n = g.n;
+  const int gr = Group<G>::rank();
+  constexpr int kPerWave = kWave / G;
+  const int wv = threadIdx.x / kWave;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int64_t ncand = (int64_t)(cend - cbeg);
+  if (d + 1 >= (int)kInf8) {
+    // neighbours would sit at distance 255: fine only if all are pruned
+    for (int64_t c = (int64_t)cbeg + wid; c < (int64_t)cend; c += nw) {
+      const int32_t u = w.cu[c], j = w.cj[c];
+      const int64_t e0 = g.row[u], deg = g.row[u + 1] - e0;
+      const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
+      const uint8_t *Tj = w.T + (int64_t)j * n;
+      for (int64_t e = lane_id(); e < deg; e += kWave) {
+        const int32_t x = g.col[e0 + e];
+        if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
+        if (!prune_test_serial(bp, st, Tj, w.s + j, x, d + 1)) atomicOr(&ctl->flags, kFlagRange);
+      }
+    }
+    return;
+  }
+  WaveStage<kStage> stage;
+  stage.init(s_a[wv], s_b[wv]);
+  const FrontierFlush flush{ctl, f, nbase, d};
+  unsigned long long c_edge = 0;
+  for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
+    const int64_t c = (int64_t)cbeg + base + lane_id() / G;
+    const bool act = c < (int64_t)cend;
+    int32_t u = 0, j = 0;
+    int64_t e0 = 0, deg = 0, lim = 0;
+    if (act) {
+      u = w.cu[c];
+      j = w.cj[c];
+      e0 = g.row[u];
+      deg = g.row[u + 1] - e0;
+      lim = deg < chunk ? deg : chunk;
+      if (gr == 0) c_edge += (unsigned long long)lim;
+    }
+    const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
+    uint32_t *vsw = w.vis + (int64_t)j * g.nwords;
+    const int64_t wl = Group<kWave>::max_reduce64(lim);
+    for (int64_t e = 0; e < wl; e += G) {
+      const int64_t idx = e + gr;
+      bool claimed = false;
+      int32_t x = 0;
+      if (idx < lim) {
+        x = g.col[e0 + idx];
+        const uint32_t bit = 1u << (x & 31);
+        if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vsw[x >> 5], bit) & bit);
+      }
+      stage.push(claimed, j, x, flush);
+    }
+    if (act && deg > lim) {
+      const int64_t extra = (deg - lim + chunk - 1) / chunk;
       unsigned long long tb = 0;
       if (gr == 0) tb = atomicAdd(&ctl->hcnt[d], (unsigned long long)extra);
       tb = __shfl(tb, Group<G>::base());
@@ -181,59 +369,55 @@ __global__ void __launch_bounds__(kBlock) k_win_level(DGraph g, DBp bp, DStore s
         if ((int64_t)tb + q < f.hcap) {
           f.hslot[tb + q] = j;
           f.hv[tb + q] = u;
-          f.hchunk[tb + q] = (int32_t)(q + 1);
+          f.hchunk[tb + q] = (int32_t)q;
         } else {
           atomicOr(&ctl->flags, kFlagOvfHeavy);
         }
       }
     }
   }
-  c_visit = Group<kWave>::sum_reduce(c_visit);
-  c_test = Group<kWave>::sum_reduce(c_test);
-  c_scan = Group<kWave>::sum_reduce(c_scan);
-  c_lab = Group<kWave>::sum_reduce(c_lab);
+  if (stage.n) flush(stage);
   c_edge = Group<kWave>::sum_reduce(c_edge);
-  if (lane_id() == 0 && c_visit) {
-    atomicAdd(&ctl->visited, c_visit);
-    atomicAdd(&ctl->ntests, c_test);
-    atomicAdd(&ctl->lscanned, c_scan);
-    atomicAdd(&ctl->labeled, c_lab);
-    atomicAdd(&ctl->edges, c_edge);
-  }
+  if (lane_id() == 0 && c_edge) atomicAdd(&ctl->edges, c_edge);
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFrontier f, int d,
-                                                      int chunk) {
+                                                      int chunk, int lim_inline) {
+  __shared__ int32_t s_a[kWavesPerBlock][kStage];
+  __shared__ int32_t s_b[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long ntask = ctl->hcnt[d];
   if (ntask == 0 || (ctl->flags & kOverflowFlags)) return;
   const int64_t ntasks = (int64_t)ntask < f.hcap ? (int64_t)ntask : f.hcap;
   const unsigned long long nbase = ctl->base[d] + ctl->cnt[d];
+  const int wv = threadIdx.x / kWave;
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  WaveStage<kStage> stage;
+  stage.init(s_a[wv], s_b[wv]);
+  const FrontierFlush flush{ctl, f, nbase, d};
+  unsigned long long c_edge = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
     const int32_t j = f.hslot[tk], u = f.hv[tk], c = f.hchunk[tk];
     const int64_t e0 = g.row[u], e1 = g.row[u + 1];
-    const int64_t a = e0 + (int64_t)c * chunk;
+    const int64_t a = e0 + lim_inline + (int64_t)c * chunk;
     const int64_t b = a + chunk < e1 ? a + chunk : e1;
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-    if (lane_id() == 0) atomicAdd(&ctl->hedges, (unsigned long long)(b - a));
-    for (int64_t e = a + lane_id(); e < b; e += kWave) {
-      const int32_t x = g.col[e];
-      const uint32_t bit = 1u << (x & 31);
+    c_edge += (unsigned long long)(b - a);
+    for (int64_t e0b = a; e0b < b; e0b += kWave) {
+      const int64_t e = e0b + lane_id();
       bool claimed = false;
-      if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vs[x >> 5], bit) & bit);
-      const int64_t pos = wave_append(claimed, &ctl->cnt[d + 1]);
-      if (pos >= 0) {
-        if ((int64_t)nbase + pos < f.cap) {
-          f.slot[nbase + pos] = j;
-          f.v[nbase + pos] = x;
-        } else {
-          atomicOr(&ctl->flags, kFlagOvfFrontier);
-        }
+      int32_t x = 0;
+      if (e < b) {
+        x = g.col[e];
+        const uint32_t bit = 1u << (x & 31);
+        if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vs[x >> 5], bit) & bit);
       }
+      stage.push(claimed, j, x, flush);
     }
   }
+  if (stage.n) flush(stage);
+  if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
 }
 
 // Clear visited words of every (slot, vertex) ever put on the frontier, and
@@ -393,9 +577,10 @@ template <int G>
 void launch_level_g(DGraph g, DBp bp, DStore st, DWindow w, DFrontier f, int d, int chunk,
                     hipStream_t s, int blocks, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(k_win_level<G>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d, chunk);
+  hipLaunchKernelGGL(k_win_test<G>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d);
   if (ev1) (void)hipEventRecord(ev1, s);
-  hipLaunchKernelGGL(k_win_heavy, dim3(blocks), dim3(kBlock), 0, s, g, w, f, d, chunk);
+  hipLaunchKernelGGL(k_win_expand<16>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d, chunk);
+  hipLaunchKernelGGL(k_win_heavy, dim3(blocks), dim3(kBlock), 0, s, g, w, f, d, chunk, chunk);
 }
 
 unsigned grid_for(int64_t items, int per_block, int64_t cap) {

@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(256) k_query_plain(DIndex ix, const int32_t *p
     int best = kInf8;
     const int32_t t = ix.t;
     for (int32_t k = 0; k < t; k++) {
-      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
+      const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
       if (ds == kInf8 || dt == kInf8) continue;
       const uint64_t *ms = ix.bpm + 2 * ((int64_t)rs * t + k);
       const uint64_t *mt = ix.bpm + 2 * ((int64_t)rt * t + k);
@@ -72,40 +72,43 @@ __global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *p
   const int32_t t = ix.t;
   for (int64_t i = gid; i < q; i += ngroups) {
     const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
-    // (a) bit-parallel: lower bound first, sets only where they can matter
+    // (a) bit-parallel: lane k takes slot k (and k+G, ...).  The root alone
+    // gives d_s + d_t; the sets can only take 1 or 2 off it, so a slot's
+    // (S^{-1}, S^{0}) pairs are read only if d_s + d_t - 2 beats the best
+    // root estimate of the group.
     int ub = kInf8;
     for (int32_t k = gr; k < t; k += G) {
-      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
-      if (ds != kInf8 && dt != kInf8) ub = ds + dt < ub ? ds + dt : ub;
+      const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
+      if (ds != kInf8 && dt != kInf8 && ds + dt < ub) ub = ds + dt;
     }
     ub = Group<G>::min_reduce(ub);
     int best = ub;
     for (int32_t k = gr; k < t; k += G) {
-      const int ds = ix.bpd[(int64_t)rs * t + k], dt = ix.bpd[(int64_t)rt * t + k];
+      const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
       if (ds != kInf8 && dt != kInf8 && ds + dt - 2 < best) {
-        const uint64_t *ms = ix.bpm + 2 * ((int64_t)rs * t + k);
-        const uint64_t *mt = ix.bpm + 2 * ((int64_t)rt * t + k);
-        const int v = bp_pair_dist(ds, ms[0], ms[1], dt, mt[0], mt[1]);
+        const ulonglong2 ms = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rs * t + k];
+        const ulonglong2 mt = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rt * t + k];
+        const int v = bp_pair_dist(ds, ms.x, ms.y, dt, mt.x, mt.y);
         best = v < best ? v : best;
       }
     }
     // (b) merge join by chunks of G entries
     int64_t a = ix.off[rs], b = ix.off[rt];
+    const int64_t ea = ix.off[rs + 1], eb = ix.off[rt + 1];
     for (;;) {
-      const uint32_t ha = ix.hub[a + gr < ix.off[rs + 1] ? a + gr : ix.off[rs + 1] - 1];
-      const uint32_t hb = ix.hub[b + gr < ix.off[rt + 1] ? b + gr : ix.off[rt + 1] - 1];
-      // position of ha among this group's hb values (sorted): binary search
-      // (halving search: lo ends at the first index with hb >= ha, or G-1)
+      const uint32_t ha = ix.hub[a + gr < ea ? a + gr : ea - 1];
+      const uint32_t hb = ix.hub[b + gr < eb ? b + gr : eb - 1];
+      // position of ha among this group's hb values (sorted): halving search
+      // for the first index with hb >= ha (or G-1)
       int lo = 0;
 #pragma unroll
       for (int s = G / 2; s >= 1; s >>= 1) {
         const uint32_t hm = __shfl(hb, gb + lo + s - 1);
         if (hm < ha) lo += s;
       }
-      const int pos = lo;
-      const uint32_t hf = __shfl(hb, gb + pos);
+      const uint32_t hf = __shfl(hb, gb + lo);
       if (hf == ha && ha != kSentinel) {
-        const int v = (int)ix.dist[a + gr] + (int)ix.dist[b + pos];
+        const int v = (int)ix.dist[a + gr] + (int)ix.dist[b + lo];
         best = v < best ? v : best;
       }
       const uint32_t lastA = __shfl(ha, gb + G - 1), lastB = __shfl(hb, gb + G - 1);

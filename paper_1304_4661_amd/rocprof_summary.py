@@ -1,0 +1,80 @@
+"""Summarise rocprofv3 CSV output for the library's kernels.
+
+    python -m paper_1304_4661_amd.rocprof_summary stats DIR
+        per-kernel calls / total / average duration from a --kernel-trace
+        --stats run (DIR/*_kernel_stats.csv)
+    python -m paper_1304_4661_amd.rocprof_summary traffic KERNEL FETCH_DIR WRITE_DIR
+                                                   CFETCH_DIR CWRITE_DIR COPY_BYTES
+        average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of KERNEL, scaled by
+        what the same counters read for a device copy of COPY_BYTES bytes
+        (read COPY_BYTES, write COPY_BYTES), as HBM bytes per launch
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _rows(d, suffix):
+    fs = glob.glob(os.path.join(d, f"*{suffix}"))
+    if not fs:
+        raise FileNotFoundError(f"no *{suffix} in {d}")
+    with open(fs[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def stats(d):
+    out = []
+    for r in _rows(d, "_kernel_stats.csv"):
+        out.append((r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]),
+                    float(r["AverageNs"]), float(r["Percentage"])))
+    return out
+
+
+def counter_per_dispatch(d, kernel_substr, counter):
+    vals = [float(r["Counter_Value"]) for r in _rows(d, "_counter_collection.csv")
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def copy_kib(d, counter):
+    """The largest per-dispatch value of the counter in a copy-probe run (the
+    copy kernel dominates every other dispatch there)."""
+    vals = [float(r["Counter_Value"]) for r in _rows(d, "_counter_collection.csv")
+            if r["Counter_Name"] == counter]
+    return max(vals) if vals else None
+
+
+def traffic(kernel, fdir, wdir, cfdir, cwdir, copy_bytes):
+    f, nf = counter_per_dispatch(fdir, kernel, "FETCH_SIZE")
+    w, nw = counter_per_dispatch(wdir, kernel, "WRITE_SIZE")
+    cf, cw = copy_kib(cfdir, "FETCH_SIZE"), copy_kib(cwdir, "WRITE_SIZE")
+    kf = copy_bytes / (cf * 1024.0)  # true bytes per counted byte (reads)
+    kw = copy_bytes / (cw * 1024.0)  # (writes)
+    return {
+        "kernel": kernel, "dispatches": nf,
+        "fetch_kib_per_dispatch": f, "write_kib_per_dispatch": w,
+        "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_bytes": copy_bytes,
+        "fetch_scale": kf, "write_scale": kw,
+        "bytes_per_launch": f * 1024.0 * kf + w * 1024.0 * kw,
+    }
+
+
+def main(argv):
+    if argv[0] == "stats":
+        rows = stats(argv[1])
+        print(f"{'kernel':70s} {'calls':>7s} {'total ms':>10s} {'avg us':>10s} {'%':>6s}")
+        for name, calls, tot, avg, pct in rows:
+            print(f"{name[:70]:70s} {calls:7d} {tot / 1e6:10.3f} {avg / 1e3:10.2f} {pct:6.2f}")
+    elif argv[0] == "traffic":
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], argv[5], float(argv[6])),
+                         indent=1))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
