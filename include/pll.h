@@ -101,6 +101,39 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
               uint32_t flags, void *stream);
 
 /*
+ * Build the indexes of G independent graphs at once (each graph exactly as
+ * pll_build would index it alone: its own order, its own t_bp bit-parallel
+ * roots, labels over its own vertices).
+ *   G        number of graphs (>= 0)
+ *   vtx_off  host int64[G+1]: graph g owns global ids [vtx_off[g],
+ *            vtx_off[g+1]); vtx_off[0] = 0, non-decreasing, total < 2^31
+ *   row_ptr  int32[N+1], col int32[row_ptr[N]]: one CSR over global ids;
+ *            every edge stays inside its graph; symmetric, no self-loops
+ *   order    int32[N]: order[vtx_off[g] + i] is the LOCAL id (0-based
+ *            within graph g) of graph g's vertex of local rank i
+ *   t_bp, flags, stream, out: as pll_build (PLL_DEVICE_PTRS applies to
+ *            row_ptr, col and order; vtx_off is always host memory)
+ * All graphs share the launches: their roots are interleaved by local rank
+ * into one build over the disjoint union, which yields every graph's own
+ * labels.  Export and statistics take the graph index; pll_stats reports
+ * the whole batch.
+ * Errors: as pll_build, plus PLL_E_INVAL for a bad vtx_off, an edge leaving
+ * its graph, or an order entry outside its graph.
+ */
+int pll_build_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, const int32_t *col,
+                    const int32_t *order, int32_t t_bp, uint32_t flags, void *stream,
+                    pll_index **out);
+
+/*
+ * Queries on an index from pll_build_batch, by global ids: pairs inside one
+ * graph get that graph's distance, pairs across graphs get 255.  Same
+ * arguments, memory rules and errors as pll_query (which behaves the same
+ * on a batch index).
+ */
+int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+                    uint32_t flags, void *stream);
+
+/*
  * Wait for the index's work on stream and return (and clear) the error
  * recorded by earlier asynchronous pll_query calls with device pointers.
  */
@@ -109,19 +142,21 @@ int pll_sync(const pll_index *idx, void *stream);
 /*
  * Sizes of one graph of the index for pll_export: vertices, normal label
  * entries (no sentinels) and bit-parallel slots.  graph is 0 for an index
- * made by pll_build.  Any pointer may be NULL.
+ * made by pll_build, 0..G-1 for a batch.  Any pointer may be NULL.
  */
 int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *entries,
                      int32_t *t_bp);
 
 /*
  * Copy one graph's index to host memory in the canonical layout used for
- * bit-exact comparison: vertices in rank order; off int64[n+1] (off[0] = 0),
- * hub uint32[entries] (hub ranks, ascending within each vertex), dist
+ * bit-exact comparison: vertices in (local) rank order; off int64[n+1]
+ * (off[0] = 0), hub uint32[entries] (hub local ranks, ascending within each
+ * vertex), dist
  * uint8[entries], no sentinels (Section 4.5.2 keeps a sentinel in storage
  * only); bp_d uint8[n][t_bp], bp_m1 / bp_0 uint64[n][t_bp] (the S^{-1} and
  * S^{0} sets of Section 5.1, bit j = j-th chosen neighbour in ascending rank).
- * Any output pointer may be NULL to skip that array.  rank: int32[n] id->rank.
+ * Any output pointer may be NULL to skip that array.  rank: int32[n] local
+ * id -> local rank.
  */
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);

@@ -28,8 +28,9 @@ STAT_NAMES = [
 ]
 
 EXPORTED = [
-    "pll_build", "pll_query", "pll_sync", "pll_export_sizes", "pll_export", "pll_stats",
-    "pll_free", "pll_strerror", "pll_set_tuning", "pll_get_tuning",
+    "pll_build", "pll_build_batch", "pll_query", "pll_query_batch", "pll_sync",
+    "pll_export_sizes", "pll_export", "pll_stats", "pll_free", "pll_strerror",
+    "pll_set_tuning", "pll_get_tuning",
 ]
 
 
@@ -54,6 +55,11 @@ def _lib():
         lib.pll_build.restype = C.c_int
         lib.pll_query.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
         lib.pll_query.restype = C.c_int
+        lib.pll_build_batch.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_uint32, P,
+                                        C.POINTER(C.c_void_p)]
+        lib.pll_build_batch.restype = C.c_int
+        lib.pll_query_batch.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
+        lib.pll_query_batch.restype = C.c_int
         lib.pll_sync.argtypes = [P, P]
         lib.pll_sync.restype = C.c_int
         lib.pll_export_sizes.argtypes = [P, C.c_int32, P, P, P]
@@ -145,21 +151,23 @@ class Index:
         s = None if stream is None else C.c_void_p(stream.cuda_stream)
         _check(_lib().pll_sync(self._h, s), "sync")
 
-    def sizes(self):
+    def sizes(self, graph: int = 0):
         n, e, t = C.c_int64(), C.c_int64(), C.c_int32()
-        _check(_lib().pll_export_sizes(self._h, 0, C.byref(n), C.byref(e), C.byref(t)), "sizes")
+        _check(_lib().pll_export_sizes(self._h, graph, C.byref(n), C.byref(e), C.byref(t)),
+               "sizes")
         return n.value, e.value, t.value
 
-    def export(self) -> dict:
-        """Canonical host copy: rank order, no sentinels (see include/pll.h)."""
-        n, e, t = self.sizes()
+    def export(self, graph: int = 0) -> dict:
+        """Canonical host copy of one graph: local rank order, no sentinels
+        (see include/pll.h)."""
+        n, e, t = self.sizes(graph)
         out = {
             "off": np.zeros(n + 1, np.int64), "hub": np.zeros(e, np.uint32),
             "dist": np.zeros(e, np.uint8), "bp_d": np.zeros((n, t), np.uint8),
             "bp_m1": np.zeros((n, t), np.uint64), "bp_0": np.zeros((n, t), np.uint64),
             "rank": np.zeros(n, np.int32),
         }
-        _check(_lib().pll_export(self._h, 0, *(_ptr(out[k]) for k in
+        _check(_lib().pll_export(self._h, graph, *(_ptr(out[k]) for k in
                                                 ("off", "hub", "dist", "bp_d", "bp_m1", "bp_0",
                                                  "rank"))), "export")
         return out
@@ -187,6 +195,34 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
                           C.c_void_p(order.data_ptr()), int(t_bp), flags,
                           C.c_void_p(stream.cuda_stream), C.byref(h))
     _check(rc, "build_device")
+    return Index(h)
+
+
+def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
+                plain: bool = False, stream=None, device: bool = False) -> Index:
+    """Build the indexes of a batch of graphs (see include/pll.h).  With
+    device=True, row_ptr/col/order are torch device tensors."""
+    vtx_off = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    G = len(vtx_off) - 1
+    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0)
+    h = C.c_void_p()
+    if device:
+        import torch
+
+        for a in (row_ptr, col, order):
+            assert a.dtype == torch.int32 and a.is_cuda and a.is_contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        args = [C.c_void_p(a.data_ptr()) for a in (row_ptr, col, order)]
+        flags |= DEVICE_PTRS
+    else:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        args = [_ptr(row_ptr), _ptr(col), _ptr(order)]
+    s = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = _lib().pll_build_batch(G, _ptr(vtx_off), *args, int(t_bp), flags, s, C.byref(h))
+    _check(rc, "build_batch")
     return Index(h)
 
 

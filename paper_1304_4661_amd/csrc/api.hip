@@ -112,6 +112,16 @@ int64_t ns_since(Clock::time_point t0) {
 
 struct pll_index {
   int32_t n = 0, t = 0, tpad = 0;
+  // graphs of a batch (one for pll_build): graph g owns ids
+  // [vtx_off[g], vtx_off[g+1]); its vertex of local rank l has global rank
+  // lbase[l] + gpos[g]
+  int32_t G = 1;
+  std::vector<int64_t> vtx_off, lbase, g_entries;
+  std::vector<int32_t> gpos;
+  std::vector<int32_t> lrank_h;  // local rank of every global rank (host copy)
+  std::vector<int64_t> hoff;     // host copy of off
+  DBuf<int32_t> rgid;   // graph of every global rank (batches only)
+  DBuf<int32_t> lrank;  // local rank of every global rank
   DBuf<int32_t> rank;   // id -> rank
   DBuf<uint8_t> bpd;    // [n][tpad], padding 255
   DBuf<uint64_t> bpm;   // [n][t][2] (S^{-1}, S^{0}) pairs
@@ -121,7 +131,7 @@ struct pll_index {
   DBuf<int32_t> err;  // sticky error of asynchronous device-pointer queries
   int64_t entries = 0;
   int64_t stats[PLL_NSTATS] = {};
-  std::vector<int32_t> bp_root, bp_nsel, bp_sel;
+  std::vector<int32_t> bp_root, bp_nsel, bp_sel;  // per slot record (graph * t + slot)
 
   DIndex view() const {
     DIndex v;
@@ -129,6 +139,7 @@ struct pll_index {
     v.t = t;
     v.tpad = tpad;
     v.rank = rank.p;
+    v.rgid = G > 1 ? rgid.p : nullptr;
     v.bpd = bpd.p;
     v.bpm = bpm.p;
     v.off = off.p;
@@ -143,35 +154,75 @@ namespace {
 // ---------------------------------------------------------------------------
 // Validation (before any device work).
 
-int validate_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
-                   int32_t t_bp, bool symmetric) {
-  if (n < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP) return PLL_E_INVAL;
-  if (n == 0) return PLL_OK;
+// A batch of G graphs packed into one CSR with global ids: graph g owns ids
+// [vtx_off[g], vtx_off[g+1]) and its edges stay inside that range; order
+// holds each graph's local order (local ranks -> local ids) at the graph's
+// offsets.  A single graph is G = 1, vtx_off = {0, n}.
+int validate_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, const int32_t *col,
+                   const int32_t *order, int32_t t_bp, bool symmetric) {
+  if (G < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP || (G > 0 && !vtx_off)) return PLL_E_INVAL;
+  if (G == 0) return PLL_OK;
+  if (vtx_off[0] != 0) return PLL_E_INVAL;
+  for (int32_t g = 0; g < G; g++)
+    if (vtx_off[g + 1] < vtx_off[g]) return PLL_E_INVAL;
+  const int64_t N = vtx_off[G];
+  if (N > INT32_MAX - 1) return PLL_E_INVAL;
+  if (N == 0) return PLL_OK;
   if (!row_ptr || !order) return PLL_E_INVAL;
   if (row_ptr[0] != 0) return PLL_E_INVAL;
-  for (int32_t v = 0; v < n; v++)
+  for (int64_t v = 0; v < N; v++)
     if (row_ptr[v + 1] < row_ptr[v]) return PLL_E_INVAL;
-  const int64_t nnz = row_ptr[n];
+  const int64_t nnz = row_ptr[N];
   if (nnz > 0 && !col) return PLL_E_INVAL;
-  for (int32_t v = 0; v < n; v++)
-    for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++)
-      if (col[j] < 0 || col[j] >= n || col[j] == v) return PLL_E_INVAL;
-  std::vector<char> seen((size_t)n, 0);
-  for (int32_t i = 0; i < n; i++) {
-    if (order[i] < 0 || order[i] >= n || seen[order[i]]) return PLL_E_INVAL;
-    seen[order[i]] = 1;
+  std::vector<char> seen((size_t)N, 0);
+  for (int32_t g = 0; g < G; g++) {
+    const int64_t lo = vtx_off[g], hi = vtx_off[g + 1];
+    for (int64_t v = lo; v < hi; v++) {
+      for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++)
+        if (col[j] < lo || col[j] >= hi || col[j] == v) return PLL_E_INVAL;
+      const int32_t o = order[v];
+      if (o < 0 || o >= hi - lo || seen[lo + o]) return PLL_E_INVAL;
+      seen[lo + o] = 1;
+    }
   }
   if (symmetric) {
     std::vector<int32_t> sorted(col, col + nnz);
-    for (int32_t v = 0; v < n; v++) std::sort(sorted.begin() + row_ptr[v], sorted.begin() + row_ptr[v + 1]);
-    for (int32_t v = 0; v < n; v++)
+    for (int64_t v = 0; v < N; v++)
+      std::sort(sorted.begin() + row_ptr[v], sorted.begin() + row_ptr[v + 1]);
+    for (int64_t v = 0; v < N; v++)
       for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++) {
         const int32_t w = sorted[j];
-        if (!std::binary_search(sorted.begin() + row_ptr[w], sorted.begin() + row_ptr[w + 1], v))
+        if (!std::binary_search(sorted.begin() + row_ptr[w], sorted.begin() + row_ptr[w + 1],
+                                (int32_t)v))
           return PLL_E_INVAL;
       }
   }
   return PLL_OK;
+}
+
+// Interleaving of a batch's graphs by local rank: graphs sorted by
+// decreasing size (ties by index) get positions gpos; lbase[l] = number of
+// vertices of local rank < l over all graphs.  Then global rank
+// lbase[l] + gpos[g] is a bijection, and restricted to one graph it is that
+// graph's own order, so the union's labels are each graph's labels.  It also
+// puts every graph's early (heavy) roots in the same windows, where roots of
+// different graphs never interact.
+void interleave(int32_t G, const std::vector<int64_t> &vtx_off, std::vector<int32_t> &gpos,
+                std::vector<int64_t> &lbase) {
+  std::vector<int32_t> idx((size_t)G);
+  for (int32_t g = 0; g < G; g++) idx[g] = g;
+  auto size = [&](int32_t g) { return vtx_off[g + 1] - vtx_off[g]; };
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return size(a) > size(b); });
+  gpos.assign((size_t)G, 0);
+  for (int32_t i = 0; i < G; i++) gpos[idx[i]] = i;
+  const int64_t maxn = G ? size(idx[0]) : 0;
+  lbase.assign((size_t)maxn + 1, 0);
+  // graphs with size > l form the prefix idx[0 .. cnt) of the size order
+  int32_t cnt = G;
+  for (int64_t l = 0; l < maxn; l++) {
+    while (cnt > 0 && size(idx[cnt - 1]) <= l) cnt--;
+    lbase[l + 1] = lbase[l] + cnt;
+  }
 }
 
 // Reads a LevelCtl back to the host (synchronising the stream).
@@ -199,10 +250,16 @@ struct Builder {
 
   DGraph graph() const { return DGraph{n, nwords, row.p, col.p}; }
 
-  // a1: rank[order[i]] = i; rank-space CSR.  Inputs are host arrays, or
-  // device arrays (already validated) when `device` is set.
+  // a1: global ranks (interleaved graphs; for one graph rank[order[i]] = i)
+  // and the rank-space CSR.  Inputs are host arrays, or device arrays
+  // (already validated) when `device` is set.
+  int32_t G = 1;
+  std::vector<int64_t> vtx_off;
+  DBuf<int64_t> d_vtx_off, d_lbase;
+  DBuf<int32_t> d_gpos;
+
   void relabel(const int32_t *in_row_p, const int32_t *in_col_p, const int32_t *order_p,
-               bool device, pll_index *ix) {
+               bool device, pll_index *ix, DBuf<int32_t> *gid_in) {
     DBuf<int32_t> in_row, in_col, order;
     if (!device) {
       in_row.alloc((size_t)n + 1);
@@ -215,14 +272,38 @@ struct Builder {
       in_col_p = in_col.p;
       order_p = order.p;
     }
+    interleave(G, vtx_off, ix->gpos, ix->lbase);
+    ix->G = G;
+    ix->vtx_off = vtx_off;
+    if (!d_vtx_off.p) {
+      d_vtx_off.alloc((size_t)G + 1);
+      h2d(d_vtx_off.p, vtx_off.data(), (size_t)G + 1, st);
+    }
+    d_lbase.alloc(ix->lbase.size());
+    d_gpos.alloc((size_t)std::max(G, 1));
+    h2d(d_lbase.p, ix->lbase.data(), ix->lbase.size(), st);
+    h2d(d_gpos.p, ix->gpos.data(), (size_t)G, st);
+    DBuf<int32_t> gid_own;
+    DBuf<int32_t> *gid = gid_in;
+    if (!gid || !gid->p) {
+      gid_own.alloc((size_t)std::max(n, 1));
+      check(launch_fill_gid(d_vtx_off.p, G, gid_own.p, st));
+      gid = &gid_own;
+    }
     ix->rank.alloc((size_t)n);
-    check(launch_iota_rank(order_p, ix->rank.p, n, st));
+    ix->lrank.alloc((size_t)n);
+    ix->rgid.alloc((size_t)n);
+    DBuf<int32_t> gorder((size_t)n);
+    check(launch_batch_rank(n, gid->p, d_vtx_off.p, order_p, d_lbase.p, d_gpos.p, ix->rank.p,
+                            gorder.p, ix->lrank.p, ix->rgid.p, st));
     DBuf<int64_t> deg((size_t)n), tmp((size_t)scan_tmp_elems(n));
     row.alloc((size_t)n + 1);
     col.alloc((size_t)std::max<int64_t>(nnz, 1));
-    check(launch_degrees(in_row_p, order_p, deg.p, n, st));
+    check(launch_degrees(in_row_p, gorder.p, deg.p, n, st));
     check(launch_exclusive_scan(deg.p, row.p, n, tmp.p, st));
-    check(launch_relabel_cols(in_row_p, in_col_p, order_p, ix->rank.p, row.p, col.p, n, st));
+    check(launch_relabel_cols(in_row_p, in_col_p, gorder.p, ix->rank.p, row.p, col.p, n, st));
+    ix->lrank_h.resize((size_t)n);
+    d2h(ix->lrank_h.data(), ix->lrank.p, (size_t)n, st);
     check(hipStreamSynchronize(st));
   }
 
@@ -234,22 +315,23 @@ struct Builder {
     ix->tpad = tpad;
     ix->bpd.alloc((size_t)n * tpad);
     ix->bpm.alloc((size_t)n * t * 2);
-    ix->bp_root.assign((size_t)t, -1);
-    ix->bp_nsel.assign((size_t)t, 0);
-    ix->bp_sel.assign((size_t)t * 64, -1);
+    const size_t nrec = (size_t)G * t;  // slot records: graph * t + slot
+    ix->bp_root.assign(nrec, -1);
+    ix->bp_nsel.assign(nrec, 0);
+    ix->bp_sel.assign(nrec * 64, -1);
     if (t == 0) return;
     fill(ix->bpd, 0xFF, st);
     if (n == 0) return;
-    DBuf<uint32_t> used_bits((size_t)nwords), tmp_bits((size_t)nwords);
-    DBuf<int32_t> root((size_t)t), nsel((size_t)t), sel((size_t)t * 64);
+    DBuf<uint32_t> used_bits((size_t)nwords), tmp_bits((size_t)nwords + 1);
+    DBuf<int32_t> root(nrec), nsel(nrec), sel(nrec * 64);
     fill(used_bits, 0, st);
     fill(tmp_bits, 0, st);
     fill(sel, 0xFF, st);
-    check(launch_bp_select(graph(), t, used_bits.p, tmp_bits.p, used.p, root.p, nsel.p, sel.p,
-                           st));
-    d2h(ix->bp_root.data(), root.p, (size_t)t, st);
-    d2h(ix->bp_nsel.data(), nsel.p, (size_t)t, st);
-    d2h(ix->bp_sel.data(), sel.p, (size_t)t * 64, st);
+    check(launch_bp_select(graph(), G, t, d_vtx_off.p, d_lbase.p, d_gpos.p, ix->lrank.p,
+                           used_bits.p, tmp_bits.p, used.p, root.p, nsel.p, sel.p, st));
+    d2h(ix->bp_root.data(), root.p, nrec, st);
+    d2h(ix->bp_nsel.data(), nsel.p, nrec, st);
+    d2h(ix->bp_sel.data(), sel.p, nrec * 64, st);
     // distances start at infinity, sets empty
     fill(ix->bpd, 0xFF, st);
     fill(ix->bpm, 0, st);
@@ -269,7 +351,7 @@ struct Builder {
       check(launch_bpv_items_fill(graph(), ioff.p, it_v.p, it_c.p, st));
     }
     DBpW b{t, tpad, ix->bpd.p, ix->bpm.p, found.p};
-    check(launch_bpv_init(t, b, root.p, nsel.p, sel.p, st));
+    check(launch_bpv_init((int32_t)nrec, t, b, root.p, nsel.p, sel.p, st));
     // per-level counts of newly reached (slot, vertex) pairs, and flags
     DBuf<unsigned long long> lcnt(kMaxLevels + 2);
     DBuf<int32_t> flags(1);
@@ -294,7 +376,7 @@ struct Builder {
       if (hc[L - 1] == 0 || L >= kMaxLevels - 1) done = true;
     }
     int64_t reached = 0;
-    for (int32_t i = 0; i < t; i++) reached += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
+    for (size_t i = 0; i < nrec; i++) reached += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
     for (auto c : hc) reached += (int64_t)c;
     stat_bp_visited = reached;
     check(launch_bpv_finish((int64_t)n * t, ix->bpm.p, st));
@@ -461,20 +543,26 @@ struct Builder {
   }
 };
 
-int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
-              int64_t nnz, int32_t t_bp, uint32_t flags, hipStream_t st, pll_index *ix) {
+int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *row_ptr,
+                 const int32_t *col, const int32_t *order, int64_t nnz, int32_t t_bp,
+                 uint32_t flags, hipStream_t st, pll_index *ix, DBuf<int64_t> *d_vtx_off,
+                 DBuf<int32_t> *gid) {
   const auto t0 = Clock::now();
+  const int32_t n = (int32_t)vtx_off[G];
   Builder b;
   b.st = st;
   b.tu = tuning();
   b.plain = (flags & PLL_PLAIN) != 0;
+  b.G = G;
+  b.vtx_off = vtx_off;
+  if (d_vtx_off && d_vtx_off->p) b.d_vtx_off = std::move(*d_vtx_off);
   b.n = n;
   b.t = t_bp;
   b.nwords = (n + 31) / 32;
   b.nnz = nnz;
   ix->n = n;
   ix->t = t_bp;
-  b.relabel(row_ptr, col, order, (flags & PLL_DEVICE_PTRS) != 0, ix);
+  b.relabel(row_ptr, col, order, (flags & PLL_DEVICE_PTRS) != 0, ix, gid);
   const auto t1 = Clock::now();
   b.bit_parallel(ix);
   const int64_t bp_ns = ns_since(t1);
@@ -483,9 +571,25 @@ int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   const int64_t pr_ns = ns_since(t2);
   ix->err.alloc(1);
   check(hipMemsetAsync(ix->err.p, 0, sizeof(int32_t), st));
+  {
+    // entries per graph (for export sizes): label lengths by global rank
+    std::vector<int64_t> &hoff = ix->hoff;
+    hoff.assign((size_t)n + 1, 0);
+    if (n) d2h(hoff.data(), ix->off.p, (size_t)n + 1, st);
+    check(hipStreamSynchronize(st));
+    ix->g_entries.assign((size_t)G, 0);
+    for (int32_t g = 0; g < G; g++) {
+      const int64_t ng = vtx_off[g + 1] - vtx_off[g];
+      for (int64_t l = 0; l < ng; l++) {
+        const int64_t r = ix->lbase[l] + ix->gpos[g];
+        ix->g_entries[g] += hoff[r + 1] - hoff[r] - 1;
+      }
+    }
+  }
   check(hipStreamSynchronize(st));
   int64_t bp_used = 0;
-  for (int32_t i = 0; i < t_bp; i++) bp_used += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
+  for (size_t i = 0; i < ix->bp_root.size(); i++)
+    bp_used += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
   int64_t *S = ix->stats;
   S[PLL_STAT_N] = n;
   S[PLL_STAT_TBP] = t_bp;
@@ -498,7 +602,8 @@ int build_one(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   S[PLL_STAT_RETRIES] = b.stat_retries;
   S[PLL_STAT_BP_VISITED] = b.stat_bp_visited;
   S[PLL_STAT_LEVELS] = b.stat_levels;
-  S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->bpd.bytes() + ix->bpm.bytes() +
+  S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->rgid.bytes() + ix->bpd.bytes() +
+                                      ix->bpm.bytes() +
                                       ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes());
   S[PLL_STAT_BP_NS] = bp_ns;
   S[PLL_STAT_PRUNED_NS] = pr_ns;
@@ -536,33 +641,49 @@ int guarded(F &&fn) {
 
 extern "C" {
 
-int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
-              int32_t t_bp, uint32_t flags, void *stream, pll_index **out) {
+static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr,
+                       const int32_t *col, const int32_t *order, int32_t t_bp, uint32_t flags,
+                       void *stream, pll_index **out) {
   if (!out) return PLL_E_INVAL;
   *out = nullptr;
   hipStream_t st = (hipStream_t)stream;
   const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  if (G < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP || (G > 0 && !vtx_off)) return PLL_E_INVAL;
+  std::vector<int64_t> voff(vtx_off, vtx_off + (G > 0 ? G + 1 : 0));
+  if (G == 0) voff.assign(1, 0);
+  if (voff[0] != 0) return PLL_E_INVAL;
+  for (int32_t g = 0; g < G; g++)
+    if (voff[g + 1] < voff[g]) return PLL_E_INVAL;
+  const int64_t N = voff.back();
+  if (N > INT32_MAX - 1) return PLL_E_INVAL;
   int64_t nnz = 0;
+  DBuf<int64_t> d_voff;
+  DBuf<int32_t> gid;
   if (!device) {
-    int rc = validate_graph(n, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
+    int rc = validate_batch(G, vtx_off, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
     if (rc != PLL_OK) return rc;
-    nnz = n > 0 ? row_ptr[n] : 0;
+    nnz = N > 0 ? row_ptr[N] : 0;
   } else {
-    if (n < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP) return PLL_E_INVAL;
     if (flags & PLL_VALIDATE) return PLL_E_UNSUPPORTED;
-    if (n > 0 && (!row_ptr || !order)) return PLL_E_INVAL;
-    if (n > 0) {
+    if (N > 0 && (!row_ptr || !order)) return PLL_E_INVAL;
+    if (N > 0) {
       int rc = guarded([&] {
-        int32_t hn = 0;
-        d2h(&hn, row_ptr + n, 1, st);
+        int32_t hn = 0, h0 = 0;
+        d2h(&hn, row_ptr + N, 1, st);
+        d2h(&h0, row_ptr, 1, st);
         check(hipStreamSynchronize(st));
         nnz = hn;
-        if (nnz < 0 || (nnz > 0 && !col)) return PLL_E_INVAL;
-        DBuf<uint32_t> seen((size_t)(n + 31) / 32);
+        if (h0 != 0 || nnz < 0 || (nnz > 0 && !col)) return PLL_E_INVAL;
+        d_voff.alloc((size_t)std::max(G, 1) + 1);
+        h2d(d_voff.p, voff.data(), voff.size(), st);
+        gid.alloc((size_t)N);
+        check(launch_fill_gid(d_voff.p, G, gid.p, st));
+        DBuf<uint32_t> seen((size_t)(N + 31) / 32);
         DBuf<int32_t> err(1);
         fill(seen, 0, st);
         fill(err, 0, st);
-        check(launch_validate_graph(n, row_ptr, col, order, seen.p, err.p, st));
+        check(launch_validate_graph((int32_t)N, row_ptr, col, order, gid.p, d_voff.p, seen.p,
+                                    err.p, st));
         int32_t herr = 0;
         d2h(&herr, err.p, 1, st);
         check(hipStreamSynchronize(st));
@@ -573,7 +694,11 @@ int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   }
   pll_index *ix = new (std::nothrow) pll_index();
   if (!ix) return PLL_E_NOMEM;
-  int rc = guarded([&] { return build_one(n, row_ptr, col, order, nnz, t_bp, flags, st, ix); });
+  const int32_t Gb = G > 0 ? G : 1;
+  if (G == 0) voff.push_back(0);
+  int rc = guarded([&] {
+    return build_graphs(Gb, voff, row_ptr, col, order, nnz, t_bp, flags, st, ix, &d_voff, &gid);
+  });
   if (rc != PLL_OK) {
     (void)hipStreamSynchronize(st);
     delete ix;
@@ -581,6 +706,19 @@ int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32
   }
   *out = ix;
   return PLL_OK;
+}
+
+int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+              int32_t t_bp, uint32_t flags, void *stream, pll_index **out) {
+  if (n < 0) return PLL_E_INVAL;
+  const int64_t voff[2] = {0, n};
+  return build_entry(1, voff, row_ptr, col, order, t_bp, flags, stream, out);
+}
+
+int pll_build_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, const int32_t *col,
+                    const int32_t *order, int32_t t_bp, uint32_t flags, void *stream,
+                    pll_index **out) {
+  return build_entry(G, vtx_off, row_ptr, col, order, t_bp, flags, stream, out);
 }
 
 int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out, uint32_t flags,
@@ -624,6 +762,11 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
   });
 }
 
+int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+                    uint32_t flags, void *stream) {
+  return pll_query(idx, pairs, q, out, flags, stream);
+}
+
 int pll_sync(const pll_index *idx, void *stream) {
   if (!idx) return PLL_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -638,62 +781,65 @@ int pll_sync(const pll_index *idx, void *stream) {
 
 int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *entries,
                      int32_t *t_bp) {
-  if (!idx || graph != 0) return PLL_E_INVAL;
-  if (n) *n = idx->n;
-  if (entries) *entries = idx->entries;
+  if (!idx || graph < 0 || graph >= idx->G) return PLL_E_INVAL;
+  if (n) *n = idx->vtx_off[graph + 1] - idx->vtx_off[graph];
+  if (entries) *entries = idx->g_entries.empty() ? 0 : idx->g_entries[graph];
   if (t_bp) *t_bp = idx->t;
   return PLL_OK;
 }
 
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank) {
-  if (!idx || graph != 0) return PLL_E_INVAL;
+  if (!idx || graph < 0 || graph >= idx->G) return PLL_E_INVAL;
   return guarded([&] {
-    const int32_t n = idx->n, t = idx->t;
-    const int64_t tot = idx->entries + n;
-    std::vector<int64_t> hoff((size_t)n + 1);
-    std::vector<uint32_t> hh((size_t)std::max<int64_t>(tot, 1));
-    std::vector<uint8_t> hd((size_t)std::max<int64_t>(tot, 1));
+    const int32_t t = idx->t, tp = idx->tpad;
+    const int64_t g0 = idx->vtx_off[graph];
+    const int64_t ng = idx->vtx_off[graph + 1] - g0;
+    const int32_t gp = idx->gpos[graph];
     hipStream_t st = nullptr;
-    d2h(hoff.data(), idx->off.p, (size_t)n + 1, st);
-    if (hub) d2h(hh.data(), idx->hub.p, (size_t)tot, st);
-    if (dist) d2h(hd.data(), idx->dist.p, (size_t)tot, st);
-    check(hipStreamSynchronize(st));
-    int64_t e = 0;
-    for (int32_t r = 0; r < n; r++) {
-      const int64_t a = hoff[r], b = hoff[r + 1] - 1;  // drop the sentinel
-      if (off) off[r] = e;
-      for (int64_t x = a; x < b; x++, e++) {
-        if (hub) hub[e] = hh[x];
-        if (dist) dist[e] = hd[x];
-      }
+    // the graph's rows (global ranks) in local rank order, and output offsets
+    std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
+    for (int64_t l = 0; l < ng; l++) {
+      rows[l] = idx->lbase[l] + gp;
+      oo[l + 1] = oo[l] + idx->hoff[rows[l] + 1] - 1 - idx->hoff[rows[l]];
     }
-    if (off) off[n] = e;
-    const size_t nb = (size_t)n * t;
-    if (bp_d && nb) {
-      std::vector<uint8_t> dpad((size_t)n * idx->tpad);
-      d2h(dpad.data(), idx->bpd.p, dpad.size(), st);
+    const int64_t ne = oo[ng];
+    if (off) std::memcpy(off, oo.data(), oo.size() * sizeof(int64_t));
+    if (ng == 0) return PLL_OK;
+    DBuf<int64_t> drows((size_t)ng), doo((size_t)ng + 1);
+    h2d(drows.p, rows.data(), (size_t)ng, st);
+    h2d(doo.p, oo.data(), (size_t)ng + 1, st);
+    if ((hub || dist) && ne > 0) {
+      DBuf<uint32_t> oh((size_t)ne);
+      DBuf<uint8_t> od((size_t)ne);
+      check(launch_gather_labels(drows.p, ng, idx->off.p, idx->hub.p, idx->dist.p, idx->lrank.p,
+                                 doo.p, oh.p, od.p, st));
+      if (hub) d2h(hub, oh.p, (size_t)ne, st);
+      if (dist) d2h(dist, od.p, (size_t)ne, st);
       check(hipStreamSynchronize(st));
-      for (size_t v = 0; v < (size_t)n; v++)
-        std::memcpy(bp_d + v * t, dpad.data() + v * idx->tpad, (size_t)t);
     }
-    if ((bp_m1 || bp_0) && nb) {
-      std::vector<uint64_t> m(nb * 2);
-      d2h(m.data(), idx->bpm.p, nb * 2, st);
+    if (t > 0 && (bp_d || bp_m1 || bp_0)) {
+      const size_t nb = (size_t)ng * t;
+      DBuf<uint8_t> obd(nb);
+      DBuf<uint64_t> om1(nb), om0(nb);
+      check(launch_gather_bp(drows.p, ng, t, tp, idx->bpd.p, idx->bpm.p, obd.p, om1.p, om0.p, st));
+      if (bp_d) d2h(bp_d, obd.p, nb, st);
+      if (bp_m1) d2h(bp_m1, om1.p, nb, st);
+      if (bp_0) d2h(bp_0, om0.p, nb, st);
       check(hipStreamSynchronize(st));
-      for (size_t i = 0; i < nb; i++) {
-        if (bp_m1) bp_m1[i] = m[2 * i];
-        if (bp_0) bp_0[i] = m[2 * i + 1];
-      }
     }
-    if (rank && n) d2h(rank, idx->rank.p, (size_t)n, st);
-    check(hipStreamSynchronize(st));
+    if (rank) {
+      DBuf<int32_t> orank((size_t)ng);
+      check(launch_gather_rank(g0, ng, idx->rank.p, idx->lrank.p, orank.p, st));
+      d2h(rank, orank.p, (size_t)ng, st);
+      check(hipStreamSynchronize(st));
+    }
     return PLL_OK;
   });
 }
 
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters) {
-  if (!idx || graph != 0 || !counters || ncounters < 0) return PLL_E_INVAL;
+  if (!idx || graph < 0 || graph >= idx->G || !counters || ncounters < 0) return PLL_E_INVAL;
   for (int32_t i = 0; i < ncounters && i < PLL_NSTATS; i++) counters[i] = idx->stats[i];
   return PLL_OK;
 }

@@ -50,15 +50,20 @@ __global__ void k_bpv_fill_items(DGraph g, const int64_t *ioff, int32_t *it_v, i
 }
 
 // Roots at distance 0, chosen neighbours at distance 1 with S^{-1} = {self}
-// (the initial state of Algorithm 3).  Block s handles slot s.
-__global__ void k_bpv_init(DBpW b, const int32_t *root, const int32_t *nsel, const int32_t *sel) {
-  const int32_t s = blockIdx.x;
-  const int32_t r = root[s];
+// (the initial state of Algorithm 3).  Block x handles slot record x
+// (graph x / t, slot x % t): the graphs of a batch are disjoint, so one slot
+// is a BFS from every graph's root at once, each vertex reached only from
+// its own graph's root.
+__global__ void k_bpv_init(int32_t t, DBpW b, const int32_t *root, const int32_t *nsel,
+                           const int32_t *sel) {
+  const int32_t x = blockIdx.x;
+  const int32_t s = x % t;
+  const int32_t r = root[x];
   if (r < 0) return;
   const int32_t j = threadIdx.x;
   if (j == 0) b.d[(int64_t)r * b.tpad + s] = 0;
-  if (j < nsel[s]) {
-    const int32_t w = sel[s * 64 + j];
+  if (j < nsel[x]) {
+    const int32_t w = sel[(int64_t)x * 64 + j];
     b.d[(int64_t)w * b.tpad + s] = 1;
     b.m[2 * ((int64_t)w * b.t + s)] = 1ull << j;
   }
@@ -197,10 +202,10 @@ hipError_t launch_bpv_items_fill(DGraph g, const int64_t *ioff, int32_t *it_v, i
   return hipGetLastError();
 }
 
-hipError_t launch_bpv_init(int32_t t, DBpW b, const int32_t *root, const int32_t *nsel,
-                           const int32_t *sel, hipStream_t st) {
-  if (t == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bpv_init, dim3(t), dim3(64), 0, st, b, root, nsel, sel);
+hipError_t launch_bpv_init(int32_t nrec, int32_t t, DBpW b, const int32_t *root,
+                           const int32_t *nsel, const int32_t *sel, hipStream_t st) {
+  if (t == 0 || nrec == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bpv_init, dim3(nrec), dim3(64), 0, st, t, b, root, nsel, sel);
   return hipGetLastError();
 }
 

@@ -248,8 +248,14 @@ struct DWindow {
 // Launchers (return hipError_t of the launch).
 
 hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
-                                 const int32_t *order, uint32_t *seen, int32_t *err,
+                                 const int32_t *order, const int32_t *gid,
+                                 const int64_t *vtx_off, uint32_t *seen, int32_t *err,
                                  hipStream_t st);
+hipError_t launch_fill_gid(const int64_t *vtx_off, int32_t G, int32_t *gid, hipStream_t st);
+hipError_t launch_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
+                             const int32_t *order, const int64_t *lbase, const int32_t *gpos,
+                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid,
+                             hipStream_t st);
 hipError_t launch_iota_rank(const int32_t *order, int32_t *rank, int32_t n, hipStream_t st);
 hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *deg, int32_t n,
                           hipStream_t st);
@@ -262,16 +268,18 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
                                  hipStream_t st);
 
-hipError_t launch_bp_select(DGraph g, int32_t t, uint32_t *used_bits, uint32_t *tmp_bits,
-                            uint8_t *used_bytes, int32_t *root, int32_t *nsel, int32_t *sel,
-                            hipStream_t st);
+hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
+                            const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
+                            uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
+                            int32_t *root, int32_t *nsel, int32_t *sel, hipStream_t st);
 // bit-parallel BFS: work items = (vertex, chunk of its adjacency list)
 hipError_t launch_bpv_items_count(DGraph g, int chunk, int64_t *cnt, int64_t *ioff, int64_t *tmp,
                                   hipStream_t st);
 hipError_t launch_bpv_items_fill(DGraph g, const int64_t *ioff, int32_t *it_v, int32_t *it_c,
                                  hipStream_t st);
-hipError_t launch_bpv_init(int32_t t, DBpW b, const int32_t *root, const int32_t *nsel,
-                           const int32_t *sel, hipStream_t st);
+// slot records: root[s], nsel[s], sel[s*64..] for s = graph * t + slot
+hipError_t launch_bpv_init(int32_t nrec, int32_t t, DBpW b, const int32_t *root,
+                           const int32_t *nsel, const int32_t *sel, hipStream_t st);
 hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t *it_c,
                             int64_t nitems, int chunk, int L, unsigned long long *cnt,
                             int32_t *flags, hipStream_t st);
@@ -297,6 +305,7 @@ struct DIndex {
   int32_t n;
   int32_t t, tpad;
   const int32_t *rank;
+  const int32_t *rgid;  // graph of each rank (batches), or null for one graph
   const uint8_t *bpd;
   const uint64_t *bpm;  // interleaved (S^{-1}, S^{0}) pairs
   const int64_t *off;
@@ -308,5 +317,16 @@ hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int
 hipError_t launch_or_flag(const int32_t *src, int32_t *dst, hipStream_t st);
 hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
                         const int32_t *err, bool plain, int qgroup, hipStream_t st);
+
+// export of one graph (rows = its global ranks in local rank order)
+hipError_t launch_gather_labels(const int64_t *rows, int64_t m, const int64_t *src_off,
+                                const uint32_t *hub, const uint8_t *dist, const int32_t *lrank,
+                                const int64_t *out_off, uint32_t *out_hub, uint8_t *out_dist,
+                                hipStream_t st);
+hipError_t launch_gather_bp(const int64_t *rows, int64_t m, int32_t t, int32_t tpad,
+                            const uint8_t *bpd, const uint64_t *bpm, uint8_t *out_d,
+                            uint64_t *out_m1, uint64_t *out_m0, hipStream_t st);
+hipError_t launch_gather_rank(int64_t g0, int64_t ng, const int32_t *rank, const int32_t *lrank,
+                              int32_t *out, hipStream_t st);
 
 }  // namespace pll

@@ -95,12 +95,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int64_t *in, 
 }
 
 // Device-side argument checks for inputs given as device pointers: CSR
-// offsets non-decreasing from 0, neighbours in range and not the vertex
-// itself, order a permutation.  Any violation sets *err.
+// offsets non-decreasing from 0, neighbours inside the vertex's own graph
+// and not the vertex itself, and each graph's order a permutation of its
+// local ids.  Any violation sets *err.  One wave per vertex.
 __global__ void k_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
-                                 const int32_t *order, uint32_t *seen, int32_t *err) {
-  // one wave per vertex: offsets and the order entry by lane 0, the row's
-  // neighbours by all lanes
+                                 const int32_t *order, const int32_t *gid,
+                                 const int64_t *vtx_off, uint32_t *seen, int32_t *err) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t v = wid; v < n; v += nw) {
@@ -109,20 +109,49 @@ __global__ void k_validate_graph(int32_t n, const int32_t *row, const int32_t *c
       if (lane_id() == 0) atomicOr(err, 1);
       continue;
     }
+    const int32_t g = gid[v];
+    const int64_t lo = vtx_off[g], hi = vtx_off[g + 1];
     bool bad = false;
     for (int32_t j = a + lane_id(); j < b; j += kWave) {
       const int32_t w = col[j];
-      bad |= w < 0 || w >= n || w == (int32_t)v;
+      bad |= w < lo || w >= hi || w == (int32_t)v;
     }
     if (bad) atomicOr(err, 1);
     if (lane_id() == 0) {
       const int32_t o = order[v];
-      if (o < 0 || o >= n) {
+      if (o < 0 || o >= hi - lo) {
         atomicOr(err, 1);
-      } else if (atomicOr(&seen[o >> 5], 1u << (o & 31)) & (1u << (o & 31))) {
-        atomicOr(err, 1);
+      } else {
+        const int64_t x = lo + o;
+        if (atomicOr(&seen[x >> 5], 1u << (x & 31)) & (1u << (x & 31))) atomicOr(err, 1);
       }
     }
+  }
+}
+
+// Graph id of every vertex: block g fills its graph's range.
+__global__ void k_fill_gid(const int64_t *vtx_off, int32_t *gid) {
+  const int32_t g = blockIdx.x;
+  for (int64_t v = vtx_off[g] + threadIdx.x; v < vtx_off[g + 1]; v += blockDim.x) gid[v] = g;
+}
+
+// Ranks of a batch of independent graphs.  Graph g's vertex of local rank l
+// gets global rank lbase[l] + gpos[g] (graphs interleaved by local rank; see
+// the batch notes in api.hip).  Also the inverse order, the local rank of
+// every global rank and the graph of every global rank.
+__global__ void k_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
+                             const int32_t *order, const int64_t *lbase, const int32_t *gpos,
+                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t g = gid[p];
+    const int64_t l = p - vtx_off[g];
+    const int32_t v = (int32_t)(vtx_off[g] + order[p]);
+    const int32_t r = (int32_t)(lbase[l] + gpos[g]);
+    rank[v] = r;
+    gorder[r] = v;
+    lrank[r] = (int32_t)l;
+    rgid[r] = g;
   }
 }
 
@@ -181,94 +210,115 @@ __device__ int32_t block_min_i32(int32_t v) {
 __device__ int32_t block_max_i32(int32_t v) { return -block_min_i32(-v); }
 
 __global__ void __launch_bounds__(kSelThreads) k_bp_select(DGraph g, int32_t t,
+                                                           const int64_t *vtx_off,
+                                                           const int64_t *lbase,
+                                                           const int32_t *gpos,
+                                                           const int32_t *lrank,
                                                            uint32_t *used_bits,
                                                            uint32_t *tmp_bits,
                                                            uint8_t *used_bytes, int32_t *root,
                                                            int32_t *nsel, int32_t *sel) {
+  // block gi handles graph gi; its vertex of local rank l has global rank
+  // lbase[l] + gpos[gi]; temporary bits are kept per local rank at
+  // vtx_off[gi] + l (boundary words are shared with the next graph, hence
+  // atomics for setting and clearing)
   const int tid = threadIdx.x;
-  const int32_t n = g.n, nwords = g.nwords;
-  int32_t cursor = 0;  // every rank below cursor is used
+  const int32_t gi = blockIdx.x;
+  const int64_t g0 = vtx_off[gi];
+  const int32_t ng = (int32_t)(vtx_off[gi + 1] - g0);
+  const int32_t gp = gpos[gi];
+  auto grank = [&](int32_t l) { return (int32_t)(lbase[l] + gp); };
+  int32_t cursor = 0;  // every local rank below cursor is used
   for (int32_t i = 0; i < t; i++) {
-    // lowest unused rank >= cursor
-    int32_t r = -1;
-    while (cursor < n) {
-      int32_t w0 = cursor >> 5;
-      int32_t w = w0 + tid;
+    const int64_t si = (int64_t)gi * t + i;
+    // lowest unused local rank >= cursor
+    int32_t lr = -1;
+    while (cursor < ng) {
+      const int32_t l = cursor + tid;
       int32_t cand = INT32_MAX;
-      if (w < nwords) {
-        uint32_t free_bits = ~ld_acquire_agent(&used_bits[w]);
-        if (w == w0) free_bits &= ~((1u << (cursor & 31)) - 1u);
-        if (w == nwords - 1 && (n & 31)) free_bits &= (1u << (n & 31)) - 1u;
-        if (free_bits) cand = w * 32 + __ffs(free_bits) - 1;
+      if (l < ng) {
+        const int32_t r = grank(l);
+        if (!((ld_acquire_agent(&used_bits[r >> 5]) >> (r & 31)) & 1u)) cand = l;
       }
       cand = block_min_i32(cand);
       if (cand != INT32_MAX) {
-        r = cand;
+        lr = cand;
         break;
       }
-      int64_t next = ((int64_t)w0 + kSelThreads) * 32;
-      cursor = next < (int64_t)n ? (int32_t)next : n;
+      const int64_t next = (int64_t)cursor + kSelThreads;
+      cursor = next < (int64_t)ng ? (int32_t)next : ng;
     }
-    if (r < 0) {
+    if (lr < 0) {
       if (tid == 0) {
-        root[i] = -1;
-        nsel[i] = 0;
+        root[si] = -1;
+        nsel[si] = 0;
       }
       continue;
     }
-    cursor = r + 1;
+    cursor = lr + 1;
+    const int32_t r = grank(lr);
     if (tid == 0) {
       atomicOr(&used_bits[r >> 5], 1u << (r & 31));
       used_bytes[r] = 1;
-      root[i] = r;
+      root[si] = r;
     }
     __threadfence();
     __syncthreads();
-    // unused neighbours of r into tmp_bits
+    // unused neighbours of r, by local rank, into tmp_bits
     const int64_t e0 = g.row[r], e1 = g.row[r + 1];
     int32_t lo = INT32_MAX, hi = -1;
     for (int64_t e = e0 + tid; e < e1; e += kSelThreads) {
-      int32_t w = g.col[e];
+      const int32_t w = g.col[e];
       if (!((ld_acquire_agent(&used_bits[w >> 5]) >> (w & 31)) & 1u)) {
-        atomicOr(&tmp_bits[w >> 5], 1u << (w & 31));
-        lo = w < lo ? w : lo;
-        hi = w > hi ? w : hi;
+        const int32_t lw = lrank[w];
+        const int64_t x = g0 + lw;
+        atomicOr(&tmp_bits[x >> 5], 1u << (x & 31));
+        lo = lw < lo ? lw : lo;
+        hi = lw > hi ? lw : hi;
       }
     }
     lo = block_min_i32(lo);
     hi = block_max_i32(hi);
     __threadfence();
     __syncthreads();
-    // the first 64 set bits of tmp_bits, ascending
+    // the first 64 set bits in [g0+lo, g0+hi], ascending
     int32_t taken = 0;
     if (hi >= 0) {
-      for (int32_t wb = lo >> 5; wb <= (hi >> 5) && taken < 64; wb += kSelThreads) {
-        int32_t w = wb + tid;
-        uint32_t bits = w <= (hi >> 5) ? ld_acquire_agent(&tmp_bits[w]) : 0u;
+      const int64_t xlo = g0 + lo, xhi = g0 + hi;
+      for (int64_t wb = xlo >> 5; wb <= (xhi >> 5) && taken < 64; wb += kSelThreads) {
+        const int64_t w = wb + tid;
+        uint32_t bits = 0;
+        if (w <= (xhi >> 5)) {
+          bits = ld_acquire_agent(&tmp_bits[w]);
+          // keep only this graph's bits inside [xlo, xhi]
+          const int64_t b0 = w * 32;
+          if (b0 < xlo) bits &= ~0u << (xlo - b0);
+          if (b0 + 31 > xhi) bits &= ~0u >> (b0 + 31 - xhi);
+        }
         int64_t tot;
         int32_t pos = taken + (int32_t)block_excl_scan<kSelThreads>(__popc(bits), &tot);
         while (bits && pos < 64) {
-          int b = __ffs(bits) - 1;
+          const int b = __ffs(bits) - 1;
           bits &= bits - 1;
-          sel[i * 64 + pos] = w * 32 + b;
+          sel[si * 64 + pos] = grank((int32_t)(w * 32 + b - g0));
           pos++;
         }
         taken += (int32_t)tot;
       }
     }
-    int32_t ns = taken < 64 ? taken : 64;
+    const int32_t ns = taken < 64 ? taken : 64;
     __threadfence();
     __syncthreads();
     for (int32_t k = tid; k < ns; k += kSelThreads) {
-      int32_t v = sel[i * 64 + k];
+      const int32_t v = sel[si * 64 + k];
       atomicOr(&used_bits[v >> 5], 1u << (v & 31));
       used_bytes[v] = 1;
     }
     for (int64_t e = e0 + tid; e < e1; e += kSelThreads) {
-      int32_t w = g.col[e];
-      st_relaxed_agent(&tmp_bits[w >> 5], 0u);
+      const int64_t x = g0 + lrank[g.col[e]];
+      atomicAnd(&tmp_bits[x >> 5], ~(1u << (x & 31)));
     }
-    if (tid == 0) nsel[i] = ns;
+    if (tid == 0) nsel[si] = ns;
     __threadfence();
     __syncthreads();
   }
@@ -292,13 +342,32 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int
 }
 
 hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
-                                 const int32_t *order, uint32_t *seen, int32_t *err,
+                                 const int32_t *order, const int32_t *gid,
+                                 const int64_t *vtx_off, uint32_t *seen, int32_t *err,
                                  hipStream_t st) {
   if (n == 0) return hipSuccess;
   int64_t blocks = ((int64_t)n * kWave + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_validate_graph, dim3((unsigned)blocks), dim3(256), 0, st, n, row, col,
-                     order, seen, err);
+                     order, gid, vtx_off, seen, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_gid(const int64_t *vtx_off, int32_t G, int32_t *gid, hipStream_t st) {
+  if (G == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_gid, dim3(G), dim3(256), 0, st, vtx_off, gid);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
+                             const int32_t *order, const int64_t *lbase, const int32_t *gpos,
+                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid,
+                             hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  int64_t blocks = ((int64_t)N + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_batch_rank, dim3((unsigned)blocks), dim3(256), 0, st, N, gid, vtx_off,
+                     order, lbase, gpos, rank, gorder, lrank, rgid);
   return hipGetLastError();
 }
 
@@ -326,12 +395,13 @@ hipError_t launch_relabel_cols(const int32_t *in_row, const int32_t *in_col, con
   return hipGetLastError();
 }
 
-hipError_t launch_bp_select(DGraph g, int32_t t, uint32_t *used_bits, uint32_t *tmp_bits,
-                            uint8_t *used_bytes, int32_t *root, int32_t *nsel, int32_t *sel,
-                            hipStream_t st) {
-  if (t == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_bp_select, dim3(1), dim3(kSelThreads), 0, st, g, t, used_bits, tmp_bits,
-                     used_bytes, root, nsel, sel);
+hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
+                            const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
+                            uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
+                            int32_t *root, int32_t *nsel, int32_t *sel, hipStream_t st) {
+  if (t == 0 || G == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bp_select, dim3(G), dim3(kSelThreads), 0, st, g, t, vtx_off, lbase, gpos,
+                     lrank, used_bits, tmp_bits, used_bytes, root, nsel, sel);
   return hipGetLastError();
 }
 

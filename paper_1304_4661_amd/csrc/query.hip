@@ -32,6 +32,10 @@ __global__ void __launch_bounds__(256) k_query_plain(DIndex ix, const int32_t *p
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    if (ix.rgid && ix.rgid[rs] != ix.rgid[rt]) {  // different graphs of a batch
+      out[i] = kInf8;
+      continue;
+    }
     int best = kInf8;
     const int32_t t = ix.t;
     for (int32_t k = 0; k < t; k++) {
@@ -72,6 +76,10 @@ __global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *p
   const int32_t t = ix.t;
   for (int64_t i = gid; i < q; i += ngroups) {
     const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    if (ix.rgid && ix.rgid[rs] != ix.rgid[rt]) {  // different graphs of a batch
+      if (gr == 0) out[i] = kInf8;
+      continue;
+    }
     // (a) bit-parallel: lane k takes slot k (and k+G, ...).  The root alone
     // gives d_s + d_t; the sets can only take 1 or 2 off it, so a slot's
     // (S^{-1}, S^{0}) pairs are read only if d_s + d_t - 2 beats the best

@@ -92,3 +92,32 @@ def test_query_rejects_null_index():
     assert lib.pll_query(None, pairs.ctypes.data, 1, out.ctypes.data, 0, None) == binding.E_INVAL
     assert lib.pll_stats(None, 0, None, 0) == binding.E_INVAL
     lib.pll_free(None)
+
+
+def test_build_batch_rejects_bad_input_before_device_work():
+    lib = binding.library()
+    g1, g2 = graphs.cycle(4), graphs.path(3)
+    vtx_off, rp, col, order = gen.pack_batch([g1, g2])
+
+    def rc(vo, rp_, col_, order_, t=0, G=None):
+        h = C.c_void_p()
+        vo = np.ascontiguousarray(vo, np.int64)
+        rp_ = np.ascontiguousarray(rp_, np.int32)
+        col_ = np.ascontiguousarray(col_, np.int32)
+        order_ = np.ascontiguousarray(order_, np.int32)
+        G = len(vo) - 1 if G is None else G
+        r = lib.pll_build_batch(G, vo.ctypes.data, rp_.ctypes.data, col_.ctypes.data,
+                                order_.ctypes.data, t, 0, None, C.byref(h))
+        assert h.value is None or r == 0
+        return r
+
+    bad = col.copy()
+    bad[0] = 5  # vertex 0 (graph 0) linked into graph 1
+    assert rc(vtx_off, rp, bad, order) == binding.E_INVAL
+    bo = order.copy()
+    bo[4] = 3  # graph 1 has 3 vertices: local id 3 is out of range
+    assert rc(vtx_off, rp, col, bo) == binding.E_INVAL
+    assert rc(np.array([1, 4, 7]), rp, col, order) == binding.E_INVAL  # vtx_off[0] != 0
+    assert rc(np.array([0, 5, 4]), rp, col, order) == binding.E_INVAL  # decreasing
+    assert rc(vtx_off, rp, col, order, t=65) == binding.E_INVAL
+    assert rc(vtx_off, rp, col, order, G=-1) == binding.E_INVAL

@@ -170,3 +170,19 @@ def test_rmat14_and_tiny_windows():
         assert_same_index(binding.build(g.row_ptr, g.col, order, 16), ox, "rmat14 w5")
     p = gen.random_pairs(g.n, 200_000, 9)
     assert np.array_equal(binding.build(g.row_ptr, g.col, order, 16).query(p), oracle.query(ox, p))
+
+
+def test_rmat18_benchmark_workload():
+    # the benchmark's workload itself: R-MAT 18, t_bp = 50, 1e6 pairs, built
+    # from device pointers in the launch configuration bench.py times
+    import torch
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("rmat18")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    d = [torch.from_numpy(a).cuda() for a in (g.row_ptr, g.col, order)]
+    gx = binding.build_device(*d, t_bp)
+    assert_same_index(gx, ox, "rmat18")
+    dp = torch.from_numpy(pairs).cuda()
+    out = torch.empty(len(pairs), dtype=torch.uint8, device="cuda")
+    gx.query_device(dp, out, sync=True)
+    assert np.array_equal(out.cpu().numpy(), oracle.query(ox, pairs))
