@@ -32,6 +32,10 @@ LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip
 
 
 def describe(name, g, t_bp, q):
+    if name == "ba256":
+        return (f"{g.meta['graphs']} Barabasi-Albert graphs, n log-uniform in [1e3, 2e5], "
+                f"m uniform in 2..8, seeded per graph (total n={g.n}, m={g.m}), one packed CSR, "
+                f"Degree order per graph; t_bp={t_bp} per graph; {q} pairs inside the graphs")
     if name.startswith("rmat"):
         m = g.meta
         return (f"R-MAT scale {m['scale']}, edge factor {m['edge_factor']}, abcd="
@@ -82,6 +86,31 @@ def cpu_baseline(g, order, t_bp, pairs):
     }
 
 
+def cpu_baseline_batch(gs, vtx_off, t_bp, pairs, budget_s=20.0):
+    """The oracle on a bounded sample of the batch: whole graphs in batch
+    order (index build + their own pairs) until about budget_s of CPU time."""
+    import oracle
+
+    from paper_1304_4661_amd import gen
+
+    m_done, t_done, q_done, k = 0, 0.0, 0, 0
+    per = len(pairs) // len(gs)
+    for i, g in enumerate(gs):
+        if t_done > budget_s:
+            break
+        t0 = time.perf_counter()
+        ox = oracle.build(g.row_ptr, g.col, gen.degree_order(g), t_bp)
+        loc = pairs[i * per:(i + 1) * per] - np.int32(vtx_off[i])
+        oracle.query(ox, loc)
+        t_done += time.perf_counter() - t0
+        m_done += g.m
+        q_done += len(loc)
+        k += 1
+    return {"value": m_done / t_done, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {k} of {len(gs)} graphs ({m_done} edges, {q_done} pairs): "
+                       f"oracle index builds + their queries, one thread, {t_done:.1f} s")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,7 +143,13 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
         return
 
-    g, order, t_bp, pairs = gen.config_graph(args.config)
+    batch = args.config == "ba256"
+    if batch:
+        gs, vtx_off, row_ptr, col, order, t_bp, pairs = gen.batch_workload()
+        g = gen.Graph(int(vtx_off[-1]), row_ptr, col, {"kind": "batch", "graphs": len(gs)})
+    else:
+        g, order, t_bp, pairs = gen.config_graph(args.config)
+        gs, vtx_off = [g], np.array([0, g.n], np.int64)
     q = len(pairs)
     d_row = torch.from_numpy(g.row_ptr).to(dev)
     d_col = torch.from_numpy(g.col).to(dev)
@@ -124,8 +159,14 @@ def main():
     stream = torch.cuda.current_stream()
     binding.set_tuning("profile", 1)
 
+    def build():
+        if batch:
+            return binding.build_batch(vtx_off, d_row, d_col, d_order, t_bp, stream=stream,
+                                       device=True)
+        return binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+
     def step():
-        ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        ix = build()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
@@ -197,7 +238,7 @@ def main():
     }
 
     if not args.no_extras:
-        ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        ix = build()
         rates = {}
         for plain in (False, True):
             ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
@@ -237,7 +278,10 @@ def main():
 
     binding.set_tuning("profile", 0)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
+        if batch:
+            out["cpu_baseline"] = cpu_baseline_batch(gs, vtx_off, t_bp, pairs)
+        else:
+            out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(out))
 

@@ -162,8 +162,59 @@ def ba_edges(n: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return us, vs
 
 
+_NATIVE = None
+
+
+def _native():
+    """ctypes handle of gen_native.c (compiled with gcc on first use), or None."""
+    global _NATIVE
+    if _NATIVE is None:
+        import ctypes as C
+        import os
+        import subprocess
+
+        here = os.path.dirname(os.path.abspath(__file__))
+        src = os.path.join(here, "gen_native.c")
+        lib = os.path.join(here, "libgen_native.so")
+        try:
+            if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+                tmp = f"{lib}.tmp{os.getpid()}"
+                subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src])
+                os.replace(tmp, lib)
+            h = C.CDLL(lib)
+            P = C.c_void_p
+            h.ba_edges.argtypes = [C.c_int64, C.c_int32, P, C.c_int64, P, P, P]
+            h.ba_edges.restype = C.c_int64
+            _NATIVE = h
+        except (OSError, subprocess.CalledProcessError):
+            _NATIVE = False
+    return _NATIVE or None
+
+
+def ba_edges_fast(n: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Same edges as :func:`ba_edges` (same draws in the same order), with the
+    attachment loop in C."""
+    lib = _native()
+    if lib is None or m > 64:
+        return ba_edges(n, m, seed)
+    if m < 1 or n <= m:
+        raise ValueError("need 1 <= m < n")
+    rng = _rng(seed)
+    ne = m * (n - m)
+    us = np.empty(ne, dtype=np.int64)
+    vs = np.empty(ne, dtype=np.int64)
+    ends = np.empty(2 * ne, dtype=np.int64)
+    u = rng.random(int(ne * 1.25) + 4096)
+    while True:
+        used = lib.ba_edges(n, m, u.ctypes.data, len(u), us.ctypes.data, vs.ctypes.data,
+                            ends.ctypes.data)
+        if used >= 0:
+            return us, vs
+        u = np.concatenate([u, rng.random(len(u) // 2 + 4096)])
+
+
 def ba_graph(n: int, m: int, seed: int) -> Graph:
-    u, v = ba_edges(n, m, seed)
+    u, v = ba_edges_fast(n, m, seed)
     g = csr_from_edges(n, u, v)
     g.meta = {"kind": "ba", "n": n, "m_attach": m, "seed": seed}
     return g
@@ -295,6 +346,21 @@ CONFIGS = {
     "rmat20": ({"kind": "rmat", "scale": 20, "seed": 3}, 64, 10_000_000, 103),
     "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 0, 105),
 }
+
+
+def batch_workload(count: int = 256, t_bp: int = 16, pairs_per_graph: int = 10_000,
+                   seed_base: int = 4000, pair_seed_base: int = 14000):
+    """The multi-graph workload: ``count`` Barabasi-Albert graphs from
+    :func:`batch_spec`, packed by :func:`pack_batch`, with ``pairs_per_graph``
+    uniform pairs inside each graph (PCG64 seeded ``pair_seed_base + i``), as
+    global ids.  Returns (graphs, vtx_off, row_ptr, col, order, t_bp, pairs)."""
+    spec = batch_spec(count, seed_base=seed_base)
+    graphs = [ba_graph(n, m, s) for n, m, s in spec]
+    vtx_off, row_ptr, col, order = pack_batch(graphs)
+    pairs = np.concatenate([
+        random_pairs(g.n, pairs_per_graph, pair_seed_base + i) + np.int32(vtx_off[i])
+        for i, g in enumerate(graphs)]).astype(np.int32)
+    return graphs, vtx_off, row_ptr, col, order, t_bp, pairs
 
 
 def config_graph(name: str) -> tuple[Graph, np.ndarray, int, np.ndarray]:

@@ -69,3 +69,10 @@ def test_batch_spec_and_pack():
         assert np.array_equal(rp[a:b + 1] - rp[a], g.row_ptr)
         assert np.array_equal(col[rp[a]:rp[b]] - a, g.col)
         assert np.array_equal(order[a:b], gen.degree_order(g))
+
+
+def test_native_ba_matches_python_loop():
+    for n, m, s in [(2000, 4, 1), (1500, 8, 7), (64, 2, 3)]:
+        a = gen.ba_edges(n, m, s)
+        b = gen.ba_edges_fast(n, m, s)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
