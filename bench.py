@@ -111,6 +111,51 @@ def cpu_baseline_batch(gs, vtx_off, t_bp, pairs, budget_s=20.0):
                        f"oracle index builds + their queries, one thread, {t_done:.1f} s")}
 
 
+def serve(args):
+    """Serving: index resident on the GPU, requests of log-uniform size in
+    [1, 4096] pairs arriving as a Poisson process; X_sat = saturated
+    requests/s (all requests at once), then offered loads of 0.25, 0.5 and
+    0.85 X_sat.  Batched = continuous batching over 4 slots; plain = one
+    launch per request."""
+    import torch
+
+    from paper_1304_4661_amd import binding, gen
+
+    name = args.config if args.config != "rmat18" else "rmat22"
+    g, order, t_bp, _ = gen.config_graph(name)
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, order)]
+    t0 = time.perf_counter()
+    ix = binding.build_device(*d, t_bp)
+    build_s = time.perf_counter() - t0
+    st = ix.stats()
+    nreq = args.serve_requests
+    res = {}
+    for mode, co in (("batched", 1), ("plain", 0)):
+        binding.set_tuning("serve_coalesce", co)
+        binding.serve_bench(ix, 0.0, min(nreq, 2000), seed=104)  # warm-up
+        sat = binding.serve_bench(ix, 0.0, nreq, seed=105)
+        loads = {}
+        for f in (0.25, 0.5, 0.85):
+            r = binding.serve_bench(ix, f * sat["requests_per_s"], nreq, seed=106)
+            loads[str(f)] = {k: r[k] for k in ("p50_us", "p99_us", "mean_us", "pairs_per_s",
+                                                "requests_per_s", "pairs_per_launch")}
+        res[mode] = {"x_sat_requests_per_s": sat["requests_per_s"],
+                     "x_sat_pairs_per_s": sat["pairs_per_s"], "loads": loads}
+    binding.set_tuning("serve_coalesce", 1)
+    print(json.dumps({
+        "metric": "PLL serving: queries/s and p50/p99 request latency at offered loads",
+        "value": res["batched"]["x_sat_pairs_per_s"], "unit": "queries/s",
+        "higher_is_better": True, "n_gpus": 1, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": describe(name, g, t_bp, nreq) + "; requests log-uniform in "
+                   "[1, 4096] pairs, Poisson arrivals", "name": name, "n": g.n, "m": g.m,
+                   "t_bp": t_bp, "requests_per_load": nreq},
+        "build_s": build_s, "index": {"entries": st["entries"], "bytes": st["index_bytes"],
+                                      "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}"},
+        "serving": res,
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +165,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain-form and latency measurements")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving run instead: saturated rate, then Poisson loads")
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -143,6 +191,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel() * 4, "copies": 3}))
         return
 
+    if args.serve:
+        serve(args)
+        return
     batch = args.config == "ba256"
     if batch:
         gs, vtx_off, row_ptr, col, order, t_bp, pairs = gen.batch_workload()

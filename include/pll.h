@@ -202,13 +202,50 @@ void pll_free(pll_index *idx);
 const char *pll_strerror(int code);
 
 /*
+ * Serving: continuous batching of query requests over a device-resident
+ * index (the index must outlive the server).
+ *
+ * pll_server_start: a worker thread with nslots (1..32) slots, each a HIP
+ *   stream with pinned staging for slot_pairs pairs.  Requests queue FIFO;
+ *   each free slot takes the oldest requests that fit, so requests arriving
+ *   while others run on the GPU are admitted as slots free up and run
+ *   concurrently with them.  Every request gets exactly the answers
+ *   pll_query would give it alone.
+ * pll_server_submit: queue q (1..slot_pairs) pairs from host memory; the
+ *   answers go to out[q] (host).  The caller keeps pairs and out alive until
+ *   the request is done.  *ticket identifies the request.  Ids are checked
+ *   on submission (PLL_E_INVAL).
+ * pll_server_done: 1 if the request is answered (optionally waiting), 0 if
+ *   not yet; *latency_us = answer time - submission time.
+ * pll_server_stop: answer everything queued, stop the worker, free the
+ *   server.  stats (optional): launches, pairs launched, max queue length.
+ * pll_serve_bench: open-loop load test in native code: nreq requests of
+ *   log-uniform size in [1, max_batch] with uniform random pairs, Poisson
+ *   arrivals at `rate` requests/s (rate <= 0: all at once = saturation),
+ *   SplitMix64 randomness from seed.  stats[9]: p50 / p99 / mean latency in
+ *   us (from the scheduled arrival, so queueing counts), pairs/s,
+ *   requests/s, seconds, launches, mean pairs per launch, max queue length.
+ */
+typedef struct pll_server pll_server;
+int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, pll_server **out);
+int pll_server_submit(pll_server *srv, const int32_t *pairs, int64_t q, uint8_t *out,
+                      int64_t *ticket);
+int pll_server_done(pll_server *srv, int64_t ticket, int32_t wait, double *latency_us);
+int pll_server_stop(pll_server *srv, int64_t *stats, int32_t nstats);
+int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max_batch,
+                    uint64_t seed, int32_t nslots, int64_t slot_pairs, double *stats,
+                    int32_t nstats);
+
+/*
  * Tuning knobs (process-wide): "window" (max concurrent roots, 1..1024),
  * "group" (lanes per frontier vertex: 4,8,16,32,64), "chunk" (edges a
  * group expands inline before handing the rest to whole waves), "qgroup"
  * (lanes per query pair: 16, 32, 64), "levels_per_sync" (level kernels
  * launched between host checks), "profile" (0/1: time every pruned-phase
- * level kernel with HIP events on the build stream).  Returns PLL_E_INVAL
- * for an unknown key or value.
+ * level kernel with HIP events on the build stream), "bp_chunk" (adjacency
+ * entries per bit-parallel work item), "serve_coalesce" (0/1: servers
+ * started afterwards launch one request at a time / pack several).  Returns
+ * PLL_E_INVAL for an unknown key or value.
  */
 int pll_set_tuning(const char *key, int64_t value);
 int64_t pll_get_tuning(const char *key);

@@ -30,8 +30,12 @@ STAT_NAMES = [
 EXPORTED = [
     "pll_build", "pll_build_batch", "pll_query", "pll_query_batch", "pll_sync",
     "pll_export_sizes", "pll_export", "pll_stats", "pll_free", "pll_strerror",
-    "pll_set_tuning", "pll_get_tuning",
+    "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
+    "pll_server_done", "pll_server_stop", "pll_serve_bench",
 ]
+
+SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
+               "launches", "pairs_per_launch", "max_queue"]
 
 
 class PllError(RuntimeError):
@@ -76,6 +80,17 @@ def _lib():
         lib.pll_set_tuning.restype = C.c_int
         lib.pll_get_tuning.argtypes = [C.c_char_p]
         lib.pll_get_tuning.restype = C.c_int64
+        lib.pll_server_start.argtypes = [P, C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]
+        lib.pll_server_start.restype = C.c_int
+        lib.pll_server_submit.argtypes = [P, P, C.c_int64, P, C.POINTER(C.c_int64)]
+        lib.pll_server_submit.restype = C.c_int
+        lib.pll_server_done.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
+        lib.pll_server_done.restype = C.c_int
+        lib.pll_server_stop.argtypes = [P, P, C.c_int32]
+        lib.pll_server_stop.restype = C.c_int
+        lib.pll_serve_bench.argtypes = [P, C.c_double, C.c_int64, C.c_int64, C.c_uint64,
+                                        C.c_int32, C.c_int64, P, C.c_int32]
+        lib.pll_serve_bench.restype = C.c_int
         _LIB = lib
     return _LIB
 
@@ -242,3 +257,57 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
                           C.byref(h))
     _check(rc, "build")
     return Index(h)
+
+
+class Server:
+    """Continuous-batching query server over an index (see include/pll.h).
+    Submitted arrays are kept referenced until the request is answered."""
+
+    def __init__(self, index: Index, nslots: int = 4, slot_pairs: int = 1 << 16):
+        self.index = index
+        h = C.c_void_p()
+        _check(_lib().pll_server_start(index.handle, nslots, slot_pairs, C.byref(h)),
+               "server_start")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, pairs) -> int:
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros(len(pairs), np.uint8)
+        t = C.c_int64()
+        _check(_lib().pll_server_submit(self._h, _ptr(pairs), len(pairs), _ptr(out), C.byref(t)),
+               "server_submit")
+        self._keep[t.value] = (pairs, out)
+        return t.value
+
+    def result(self, ticket: int, wait: bool = True):
+        """(answers or None, latency_us or None)."""
+        lat = C.c_double()
+        r = _lib().pll_server_done(self._h, ticket, 1 if wait else 0, C.byref(lat))
+        if r < 0:
+            raise PllError(r, "server_done")
+        if r == 0:
+            return None, None
+        return self._keep[ticket][1], lat.value
+
+    def stop(self) -> dict:
+        st = np.zeros(3, np.int64)
+        h, self._h = self._h, None
+        if h is not None:
+            _check(_lib().pll_server_stop(h, _ptr(st), 3), "server_stop")
+        return {"launches": int(st[0]), "pairs": int(st[1]), "max_queue": int(st[2])}
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
+
+
+def serve_bench(index: Index, rate: float, nreq: int, max_batch: int = 4096, seed: int = 105,
+                nslots: int = 4, slot_pairs: int = 1 << 16) -> dict:
+    st = np.zeros(len(SERVE_STATS), np.float64)
+    _check(_lib().pll_serve_bench(index.handle, float(rate), int(nreq), int(max_batch),
+                                  int(seed), int(nslots), int(slot_pairs), _ptr(st), len(st)),
+           "serve_bench")
+    return {k: float(v) for k, v in zip(SERVE_STATS, st)}

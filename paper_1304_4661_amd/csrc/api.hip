@@ -25,6 +25,7 @@ struct Tuning {
   int levels_per_sync = 4;
   int profile = 0;
   int bp_chunk = 64;  // adjacency entries per bit-parallel work item
+  int serve_coalesce = 1;  // servers pack several requests per launch
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -636,6 +637,14 @@ int guarded(F &&fn) {
 
 }  // namespace
 
+// accessors for the serving loop (serve.hip)
+namespace pll {
+DIndex index_view(const pll_index *idx) { return idx->view(); }
+int32_t index_n(const pll_index *idx) { return idx->n; }
+int64_t query_group_size() { return tuning().qgroup; }
+int64_t serve_coalesce() { return tuning().serve_coalesce; }
+}  // namespace pll
+
 // ---------------------------------------------------------------------------
 // ABI
 
@@ -883,6 +892,9 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "profile") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.profile = (int)value;
+  } else if (k == "serve_coalesce") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.serve_coalesce = (int)value;
   } else if (k == "bp_chunk") {
     if (value < 1 || value > (1 << 20)) return PLL_E_INVAL;
     g_tune.bp_chunk = (int)value;
@@ -903,6 +915,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "levels_per_sync") return g_tune.levels_per_sync;
   if (k == "profile") return g_tune.profile;
   if (k == "bp_chunk") return g_tune.bp_chunk;
+  if (k == "serve_coalesce") return g_tune.serve_coalesce;
   return PLL_E_INVAL;
 }
 

@@ -121,3 +121,14 @@ def test_build_batch_rejects_bad_input_before_device_work():
     assert rc(np.array([0, 5, 4]), rp, col, order) == binding.E_INVAL  # decreasing
     assert rc(vtx_off, rp, col, order, t=65) == binding.E_INVAL
     assert rc(vtx_off, rp, col, order, G=-1) == binding.E_INVAL
+
+
+def test_server_rejects_bad_arguments_without_device_work():
+    lib = binding.library()
+    h = C.c_void_p()
+    assert lib.pll_server_start(None, 2, 1024, C.byref(h)) == binding.E_INVAL
+    assert h.value is None
+    assert lib.pll_server_stop(None, None, 0) == binding.E_INVAL
+    assert lib.pll_server_done(None, 0, 0, None) == binding.E_INVAL
+    st = np.zeros(9)
+    assert lib.pll_serve_bench(None, 1.0, 10, 16, 1, 2, 1024, st.ctypes.data, 9) == binding.E_INVAL
