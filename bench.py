@@ -284,6 +284,7 @@ def main():
                   "bytes": st["index_bytes"], "windows": st["windows"],
                   "retries": st["retries"], "visited": st["visited"],
                   "candidates": st["candidates"]},
+        "counters": {k: int(v) for k, v in st.items()},
         "phases_s": {"bit_parallel": st["bp_ns"] * 1e-9, "pruned": st["pruned_ns"] * 1e-9},
         "roofline": roofline,
     }

@@ -171,7 +171,8 @@ enum {
   PLL_STAT_ENTRIES,      /* normal label entries, no sentinels */
   PLL_STAT_BP_USED,      /* vertices used as bit-parallel roots or neighbours */
   PLL_STAT_ROOTS,        /* pruned BFSs run */
-  PLL_STAT_VISITED,      /* (root, vertex) visits of the pruned phase */
+  PLL_STAT_VISITED,      /* (root, vertex) visits of the pruned phase (entries
+                            of the BFS levels, each tested once) */
   PLL_STAT_CANDIDATES,   /* labels appended before cleaning */
   PLL_STAT_WINDOWS,      /* root windows */
   PLL_STAT_RETRIES,      /* windows re-run smaller after overflow */
@@ -188,12 +189,26 @@ enum {
   PLL_STAT_LEVEL_LAUNCHES, /* launches of the pruned-phase level kernel */
   PLL_STAT_LEVEL_NS,     /* their summed duration from HIP events, ns; only
                             with the "profile" knob set, else 0 */
-  PLL_STAT_BP_DIRECT,    /* visits pruned by bit-parallel distances alone */
+  PLL_STAT_BP_DIRECT,    /* reached neighbours that bit-parallel distances alone
+                            prune; they are not visited (counted per edge) */
   PLL_STAT_BP_SETS,      /* visits whose bit-parallel test read slot sets */
   PLL_STAT_BP_CHECKS,    /* slot set pairs read by those tests */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
+
+/*
+ * Per-level profile of the pruned phase, recorded only when the "profile"
+ * tuning knob was set during the build (else there are no rows).  Each row
+ * has PLL_TRACE_COLS values: window index, first root rank of the window,
+ * roots in the window, BFS level d, (root, vertex) entries at level d,
+ * candidate labels made at level d, and the duration in ns of the level's
+ * kernels (HIP events on the build stream).  Copies up to max_rows rows
+ * into rows (row-major) and returns the total number of rows, or
+ * PLL_E_INVAL.
+ */
+#define PLL_TRACE_COLS 7
+int64_t pll_level_trace(const pll_index *idx, int64_t *rows, int64_t max_rows);
 
 /* Release the index and all its device memory.  NULL is ignored. */
 void pll_free(pll_index *idx);
@@ -237,15 +252,20 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
                     int32_t nstats);
 
 /*
- * Tuning knobs (process-wide): "window" (max concurrent roots, 1..1024),
- * "group" (lanes per frontier vertex: 4,8,16,32,64), "chunk" (edges a
- * group expands inline before handing the rest to whole waves), "qgroup"
- * (lanes per query pair: 16, 32, 64), "levels_per_sync" (level kernels
- * launched between host checks), "profile" (0/1: time every pruned-phase
- * level kernel with HIP events on the build stream), "bp_chunk" (adjacency
- * entries per bit-parallel work item), "serve_coalesce" (0/1: servers
- * started afterwards launch one request at a time / pack several).  Returns
- * PLL_E_INVAL for an unknown key or value.
+ * Tuning knobs (process-wide), each a power of two where it is a lane
+ * count.  Pruned phase: "window" (most concurrent roots, 1..16384),
+ * "window_work" (visits aimed at per window: the window grows or shrinks
+ * toward it after each window; 0 keeps every window at the maximum),
+ * "window_mem_mb" (device memory the per-root window state may take; caps
+ * the window at about this / (2.4 n) roots), "group" (lanes per frontier
+ * entry in the prune tests: 4..64), "xgroup" (lanes per candidate expanding
+ * its adjacency list: 4..64), "chunk" (edges a group expands inline before
+ * handing the rest to whole waves), "levels_per_sync" (levels launched
+ * between host checks), "profile" (0/1: time every level with HIP events on
+ * the build stream).  Bit-parallel phase: "bp_chunk" (adjacency entries per
+ * work item).  Queries: "qgroup" (lanes per pair: 16, 32, 64),
+ * "serve_coalesce" (0/1: servers started afterwards launch one request at a
+ * time / pack several).  Returns PLL_E_INVAL for an unknown key or value.
  */
 int pll_set_tuning(const char *key, int64_t value);
 int64_t pll_get_tuning(const char *key);

@@ -29,7 +29,7 @@ STAT_NAMES = [
 
 EXPORTED = [
     "pll_build", "pll_build_batch", "pll_query", "pll_query_batch", "pll_sync",
-    "pll_export_sizes", "pll_export", "pll_stats", "pll_free", "pll_strerror",
+    "pll_export_sizes", "pll_export", "pll_stats", "pll_level_trace", "pll_free", "pll_strerror",
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench",
 ]
@@ -72,6 +72,8 @@ def _lib():
         lib.pll_export.restype = C.c_int
         lib.pll_stats.argtypes = [P, C.c_int32, P, C.c_int32]
         lib.pll_stats.restype = C.c_int
+        lib.pll_level_trace.argtypes = [P, P, C.c_int64]
+        lib.pll_level_trace.restype = C.c_int64
         lib.pll_free.argtypes = [P]
         lib.pll_free.restype = None
         lib.pll_strerror.argtypes = [C.c_int]
@@ -185,6 +187,20 @@ class Index:
         _check(_lib().pll_export(self._h, graph, *(_ptr(out[k]) for k in
                                                 ("off", "hub", "dist", "bp_d", "bp_m1", "bp_0",
                                                  "rank"))), "export")
+        return out
+
+    TRACE_COLS = ["window", "first_root", "roots", "level", "entries", "candidates", "ns"]
+
+    def level_trace(self) -> np.ndarray:
+        """Per-level profile of the pruned phase (rows of TRACE_COLS); empty
+        unless the "profile" knob was set during the build."""
+        k = len(self.TRACE_COLS)
+        nrows = int(_lib().pll_level_trace(self._h, None, 0))
+        if nrows < 0:
+            _check(nrows, "level_trace")
+        out = np.zeros((nrows, k), np.int64)
+        if nrows:
+            _lib().pll_level_trace(self._h, _ptr(out), nrows)
         return out
 
     def stats(self) -> dict:

@@ -18,8 +18,11 @@ using namespace pll;
 namespace {
 
 struct Tuning {
-  int window = 1024;  // concurrent roots of the pruned phase
-  int group = 4;      // lanes per frontier entry
+  int window = 16384;  // most concurrent roots of the pruned phase
+  int64_t window_work = 32000000;  // visits aimed at per window (0: fixed size)
+  int64_t window_mem_mb = 16384;  // device memory allowed for per-root state
+  int group = 4;      // lanes per frontier entry (prune tests)
+  int xgroup = 16;    // lanes per candidate expanding its adjacency list
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
@@ -132,6 +135,7 @@ struct pll_index {
   DBuf<int32_t> err;  // sticky error of asynchronous device-pointer queries
   int64_t entries = 0;
   int64_t stats[PLL_NSTATS] = {};
+  std::vector<int64_t> level_trace;  // pruned-phase levels, PLL_TRACE_COLS per row
   std::vector<int32_t> bp_root, bp_nsel, bp_sel;  // per slot record (graph * t + slot)
 
   DIndex view() const {
@@ -227,10 +231,28 @@ void interleave(int32_t G, const std::vector<int64_t> &vtx_off, std::vector<int3
 }
 
 // Reads a LevelCtl back to the host (synchronising the stream).
-void read_ctl(LevelCtl *h, const LevelCtl *d, hipStream_t st) {
-  check(hipMemcpyAsync(h, d, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
-  check(hipStreamSynchronize(st));
-}
+// Pinned host mirror of the level control block and the pool top, read back
+// together with one synchronisation per batch of levels.
+struct CtlMirror {
+  LevelCtl ctl;
+  unsigned long long top;
+};
+struct PinnedMirror {
+  CtlMirror *p = nullptr;
+  PinnedMirror() {
+    if (hipHostMalloc((void **)&p, sizeof(CtlMirror), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      throw Fail{PLL_E_NOMEM};
+    }
+  }
+  ~PinnedMirror() {
+    if (p) (void)hipHostFree(p);
+  }
+  PinnedMirror(const PinnedMirror &) = delete;
+  PinnedMirror &operator=(const PinnedMirror &) = delete;
+};
+
+constexpr size_t kTraceCols = PLL_TRACE_COLS;
 
 // ---------------------------------------------------------------------------
 // The build of one graph, in rank space, into `ix`.
@@ -248,6 +270,9 @@ struct Builder {
           stat_windows = 0, stat_retries = 0, stat_roots = 0, stat_tests = 0, stat_scanned = 0,
           stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0,
           stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0;
+  // with the "profile" knob: one row per level, kTraceCols values each
+  std::vector<int64_t> level_trace;
+  size_t trace_mark = 0;
 
   DGraph graph() const { return DGraph{n, nwords, row.p, col.p}; }
 
@@ -386,7 +411,12 @@ struct Builder {
 
   // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR
   void pruned(pll_index *ix) {
-    const int wmax = plain ? 1 : std::max(1, std::min(tu.window, kMaxWindow));
+    // per-root window state: T row (n B), distance column of wd (n B),
+    // visited bits (n/8 B) and two mask bits per vertex (n/4 B)
+    const int64_t per_root = 2 * (int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1;
+    const int64_t wmem = std::max<int64_t>(64, (tu.window_mem_mb << 20) / per_root);
+    const int wmax =
+        plain ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>({tu.window, kMaxWindow, wmem}));
     const int words = (wmax + 63) / 64;
     const int64_t wstride = (int64_t)words * 64;
     // growing label store
@@ -402,8 +432,8 @@ struct Builder {
     fill(top, 0, st);
     // window state
     DBuf<uint32_t> vis((size_t)wmax * nwords);
-    DBuf<uint8_t> T((size_t)wmax * n), wd((size_t)n * wstride);
-    DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words);
+    DBuf<uint8_t> T((size_t)n * wstride), wd((size_t)n * wstride);
+    DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words), sig((size_t)wmax * 4);
     fill(vis, 0, st);
     fill(T, 0xFF, st);
     fill(wd, 0xFF, st);
@@ -423,9 +453,12 @@ struct Builder {
     DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
                 nullptr, nullptr, nullptr, ctl.p};
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p};
-    LevelCtl h{};
+    PinnedMirror mirror;
+    LevelCtl &h = mirror.p->ctl;
+    unsigned long long &htop = mirror.p->top;
+    h = LevelCtl{};
+    htop = 0;
     int64_t entries_bound = 0;
-    unsigned long long htop = 0;
 
     // optional timing of each level kernel (events on the build stream)
     std::vector<hipEvent_t> evs;
@@ -440,14 +473,18 @@ struct Builder {
       }
     } ev_guard{evs};
 
+    // Window size: fixed at wmax, or adapted so that each window does about
+    // window_work visits (early roots have large pruned BFSs, late ones
+    // tiny; one launch per level must still fill the device).
     int32_t s = 0;
-    int W = wmax;
+    const bool adaptive = tu.window_work > 0 && wmax > 1;
+    int W = adaptive ? std::min(wmax, 256) : wmax;
     while (s < n) {
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
       DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
-      DWindow w{s, nr, words, vis.p, T.p, wd.p, cmask.p, kmask.p, cu.p, cj.p, cd.p, cdes.p, ccap,
-                used.p};
+      DWindow w{s,    nr,   words, vis.p,  T.p,  sig.p, wd.p,
+                cmask.p, kmask.p, cu.p, cj.p, cd.p, cdes.p, ccap, used.p};
       check(launch_win_reset_ctl(ctl.p, st));
       check(launch_win_init(graph(), w, sto, f, nr, st));
       int d = 0;
@@ -458,22 +495,31 @@ struct Builder {
         for (; d < upto; d++) {
           hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
           hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
-          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.chunk, st, e0, e1));
+          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.xgroup, tu.chunk, st, e0,
+                                 e1));
           stat_levels++;
           stat_level_launches++;
         }
-        read_ctl(&h, ctl.p, st);
+        check(hipMemcpyAsync(&h, ctl.p, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
         check(hipMemcpyAsync(&htop, top.p, sizeof(htop), hipMemcpyDeviceToHost, st));
         check(hipStreamSynchronize(st));
         for (int i = 0; !evs.empty() && i < d - d0; i++) {
           float ms = 0.f;
           check(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
           stat_level_ns += (int64_t)(ms * 1e6);
+          const int lv = d0 + i;
+          level_trace.insert(level_trace.end(), {stat_windows, (int64_t)s, (int64_t)nr, (int64_t)lv,
+                                                 (int64_t)h.cnt[lv], 0, (int64_t)(ms * 1e6)});
         }
         if (h.flags || h.cnt[d] == 0 || d >= kMaxLevels - 1) done = true;
       }
       int64_t nvisited = 0;
       for (int i = 0; i <= d; i++) nvisited += (int64_t)h.cnt[i];
+      for (size_t r = trace_mark; r < level_trace.size(); r += kTraceCols) {
+        const int lv = (int)level_trace[r + 3];
+        const unsigned long long c1 = lv + 1 < d ? h.cmark[lv + 1] : h.ccnt;
+        level_trace[r + 5] = (int64_t)(c1 - h.cmark[lv]);
+      }
       const int64_t ncand = std::min<int64_t>((int64_t)h.ccnt, ccap);
       if (h.flags) {
         // undo the window and run it again with fewer roots
@@ -484,6 +530,7 @@ struct Builder {
         if (W == 1) throw Fail{(h.flags & kFlagRange) ? PLL_E_RANGE : PLL_E_NOMEM};
         W = std::max(1, W / 4);
         stat_retries++;
+        level_trace.resize(trace_mark);
         continue;
       }
       // make sure the commit can grow every touched label without running
@@ -516,8 +563,16 @@ struct Builder {
       stat_bp_checks += (int64_t)h.bp_checks;
       stat_cand += ncand;
       stat_windows++;
+      trace_mark = level_trace.size();
       s = e;
-      if (W < wmax) W = std::min(wmax, W * 2);
+      if (adaptive) {
+        const double work = (double)h.visited + (double)h.bp_direct;
+        double f = (double)tu.window_work / std::max(work, 1.0);
+        f = std::min(4.0, std::max(0.25, f));
+        W = (int)std::min<double>(wmax, std::max(1.0, W * f));
+      } else if (W < wmax) {
+        W = std::min(wmax, W * 2);
+      }
     }
     check(hipStreamSynchronize(st));
     {
@@ -592,6 +647,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   for (size_t i = 0; i < ix->bp_root.size(); i++)
     bp_used += (ix->bp_root[i] >= 0 ? 1 : 0) + ix->bp_nsel[i];
   int64_t *S = ix->stats;
+  ix->level_trace = std::move(b.level_trace);
   S[PLL_STAT_N] = n;
   S[PLL_STAT_TBP] = t_bp;
   S[PLL_STAT_ENTRIES] = ix->entries;
@@ -853,6 +909,14 @@ int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t nc
   return PLL_OK;
 }
 
+int64_t pll_level_trace(const pll_index *idx, int64_t *rows, int64_t max_rows) {
+  if (!idx || max_rows < 0 || (max_rows > 0 && !rows)) return PLL_E_INVAL;
+  const int64_t nrows = (int64_t)(idx->level_trace.size() / kTraceCols);
+  const int64_t k = std::min(nrows, max_rows);
+  if (k > 0) std::memcpy(rows, idx->level_trace.data(), (size_t)k * kTraceCols * sizeof(int64_t));
+  return nrows;
+}
+
 void pll_free(pll_index *idx) { delete idx; }
 
 const char *pll_strerror(int code) {
@@ -877,9 +941,18 @@ int pll_set_tuning(const char *key, int64_t value) {
   if (k == "window") {
     if (value < 1 || value > kMaxWindow) return PLL_E_INVAL;
     g_tune.window = (int)value;
+  } else if (k == "window_work") {
+    if (value < 0 || value > (1ll << 40)) return PLL_E_INVAL;
+    g_tune.window_work = value;
+  } else if (k == "window_mem_mb") {
+    if (value < 1 || value > (1ll << 22)) return PLL_E_INVAL;
+    g_tune.window_mem_mb = value;
   } else if (k == "group") {
     if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
     g_tune.group = (int)value;
+  } else if (k == "xgroup") {
+    if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
+    g_tune.xgroup = (int)value;
   } else if (k == "chunk") {
     if (value < 64 || value > (1 << 20)) return PLL_E_INVAL;
     g_tune.chunk = (int)value;
@@ -909,7 +982,10 @@ int64_t pll_get_tuning(const char *key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const std::string k(key);
   if (k == "window") return g_tune.window;
+  if (k == "window_work") return g_tune.window_work;
+  if (k == "window_mem_mb") return g_tune.window_mem_mb;
   if (k == "group") return g_tune.group;
+  if (k == "xgroup") return g_tune.xgroup;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

@@ -15,7 +15,7 @@ constexpr uint8_t kInf8 = 255;           // "infinity" in 8-bit distances
 constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // hub of the storage-only sentinel
 constexpr int kWave = 64;                // CDNA wavefront width
 constexpr int kMaxLevels = 256;          // BFS levels 0..254 are storable
-constexpr int kMaxWindow = 1024;         // concurrent roots (bits per vertex mask)
+constexpr int kMaxWindow = 16384;        // concurrent roots (bits per vertex mask)
 
 // ---------------------------------------------------------------------------
 // Wave helpers (64-wide wavefronts).
@@ -190,8 +190,8 @@ struct LevelCtl {
   unsigned long long labeled;               // entries labeled (candidates)
   unsigned long long edges;                 // adjacency entries expanded inline
   unsigned long long hedges;                // adjacency entries expanded as tasks
-  unsigned long long bp_direct;             // entries pruned by distance bytes alone
-  unsigned long long bp_sets;               // entries that read slot sets
+  unsigned long long bp_direct;             // reached neighbours pruned by distances alone
+  unsigned long long bp_sets;               // entries whose test read slot sets
   unsigned long long bp_checks;             // slot-set pairs read
   int32_t flags;
   int32_t pad;
@@ -230,9 +230,12 @@ struct DFrontier {
 
 // State of one window of concurrently processed roots [s, s + W).
 struct DWindow {
-  int32_t s, W, words;  // words: mask words per vertex (row stride of wd is words*64)
+  int32_t s, W, words;  // W roots; words: mask row stride (wd row stride words*64);
+                        // only the first (W+63)/64 words are in use
   uint32_t *vis;        // [W][nwords] visited bits per root slot
-  uint8_t *T;           // [W][n] root labels scattered by hub (Section 4.5.1)
+  uint8_t *T;           // [n][words*64] root j's label distance to hub h at
+                        // T[h][j], else 255 (Section 4.5.1)
+  uint64_t *sig;        // [W][4] 256-bit hub signature of each root's label
   uint8_t *wd;          // [n][words*64] distance from window root j, or 255
   uint64_t *cmask;      // [n][words] window roots that labeled the vertex
   uint64_t *kmask;      // [n][words] ... and whose label survived cleaning
@@ -290,7 +293,8 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
                            hipStream_t st);
 // ev0/ev1 (may be null): recorded around the level kernel itself.
 hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int chunk, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1);
+                            int xgroup, int chunk, hipStream_t st, hipEvent_t ev0,
+                            hipEvent_t ev1);
 hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                             int64_t nvisited, hipStream_t st);
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);

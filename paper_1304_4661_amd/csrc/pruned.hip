@@ -29,23 +29,52 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Column j of the window's T array.  T is stored hub-major, T[h][j]: the
+// roots of a window probe the same popular hubs, whose rows then stay in
+// cache, where a root-major layout would touch one line per (root, hub).
+struct TCol {
+  uint8_t *p;
+  int64_t stride;
+  __device__ __forceinline__ uint8_t &at(int64_t h) const { return p[h * stride]; }
+};
+__device__ __forceinline__ TCol t_col(const DWindow &w, int32_t j) {
+  return TCol{w.T + j, (int64_t)w.words * 64};
+}
+
 __global__ void k_win_reset_ctl(LevelCtl *ctl) {
   unsigned long long *p = reinterpret_cast<unsigned long long *>(ctl);
   const int words = (int)(sizeof(LevelCtl) / sizeof(unsigned long long));
   for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
 }
 
-// Block j: root k = s + j.  Scatter L(k) into T[j][.], mark k visited and
-// put (j, k) on level 0.  Bit-parallel roots and neighbours run no pruned
-// BFS (they would prune themselves at distance 0).
+// Hub signature bit (0..255) of a root's label: multiplicative hashing.
+__device__ __forceinline__ uint32_t sig_bit(uint32_t h) { return (h * 2654435761u) >> 24; }
+
+// Block j: root k = s + j.  Scatter L(k) into column j of T, build the
+// 256-bit signature of L(k)'s hubs, mark k visited and put (j, k) on
+// level 0.  Bit-parallel roots and neighbours run no pruned BFS (they would
+// prune themselves at distance 0).
 __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore st, DFrontier f) {
+  __shared__ unsigned long long s_sig[4];
   const int32_t j = blockIdx.x;
   const int32_t k = w.s + j;
-  if (w.used[k]) return;
-  uint8_t *Tj = w.T + (int64_t)j * g.n;
+  if (w.used[k]) {
+    if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = 0ull;
+    return;
+  }
+  if (threadIdx.x < 4) s_sig[threadIdx.x] = 0ull;
+  __syncthreads();
+  const TCol Tj = t_col(w, j);
   const int64_t o = st.off[k];
   const int32_t len = st.len[k];
-  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) Tj[st.hub[o + e]] = st.dist[o + e];
+  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) {
+    const uint32_t h = st.hub[o + e];
+    Tj.at(h) = st.dist[o + e];
+    const uint32_t b = sig_bit(h);
+    atomicOr(&s_sig[b >> 6], 1ull << (b & 63));
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = s_sig[threadIdx.x];
   if (threadIdx.x == 0) {
     atomicOr(&w.vis[(int64_t)j * g.nwords + (k >> 5)], 1u << (k & 31));
     const unsigned long long p = atomicAdd(&f.ctl->cnt[0], 1ull);
@@ -56,7 +85,7 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
 
 // Full prune test of one vertex by one lane (used only for the rare vertex
 // at distance 255, to decide whether the build must fail).
-__device__ bool prune_test_serial(DBp bp, DStore st, const uint8_t *Tj, int32_t k, int32_t u,
+__device__ bool prune_test_serial(DBp bp, DStore st, TCol Tj, int32_t k, int32_t u,
                                   int d) {
   for (int32_t i = 0; i < bp.t; i++) {
     const int dk = bp.d[(int64_t)k * bp.tpad + i], du = bp.d[(int64_t)u * bp.tpad + i];
@@ -68,7 +97,7 @@ __device__ bool prune_test_serial(DBp bp, DStore st, const uint8_t *Tj, int32_t 
   const int64_t o = st.off[u];
   const int32_t len = st.len[u];
   for (int32_t e = 0; e < len; e++) {
-    const int th = Tj[st.hub[o + e]];
+    const int th = Tj.at(st.hub[o + e]);
     if (th != kInf8 && st.dist[o + e] + th <= d) return true;
   }
   return false;
@@ -157,40 +186,89 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
   return false;
 }
 
-// Normal-label test against the root's row of T (Section 4.5.1): is some
-// (h, delta) of L(u) with delta + T[h] <= d?  Stops at the first hit.
+// Normal-label test against column j of T (Section 4.5.1): is some
+// (h, delta) of L(u) with delta + T[h][j] <= d?  Stops at the first hit.
+// T is large and its cells are read at random, so a hub is looked up only
+// when its bit is set in the 256-bit signature of the root's label (held
+// in registers): most hubs of L(u) are not in L(k) and cost no T read.
 template <int G>
-__device__ __forceinline__ bool label_prunes(const DStore &st, const uint8_t *Tj, int32_t u,
-                                             int d, int32_t *len_out) {
+__device__ __forceinline__ bool label_prunes(const DStore &st, TCol Tj, const uint64_t *sig,
+                                             int32_t u, int d, int32_t *len_out) {
   const int gr = Group<G>::rank();
   const int64_t o = st.off[u];
   const int32_t len = st.len[u];
   *len_out = len;
+  if (len == 0) return false;
+  const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
+  const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
   for (int32_t base = 0; base < len; base += G) {
     const int32_t e = base + gr;
     bool hit = false;
     if (e < len) {
-      const int th = Tj[st.hub[o + e]];
-      hit = th != kInf8 && st.dist[o + e] + th <= d;
+      const uint32_t h = st.hub[o + e];
+      const uint32_t b = sig_bit(h);
+      const uint64_t wd = (b & 128) ? ((b & 64) ? s23.y : s23.x) : ((b & 64) ? s01.y : s01.x);
+      if ((wd >> (b & 63)) & 1ull) {
+        const int th = Tj.at(h);
+        hit = th != kInf8 && st.dist[o + e] + th <= d;
+      }
     }
     if (Group<G>::any(hit)) return true;
   }
   return false;
 }
 
-// One BFS level of every root of the window, in two kernels.
+// One BFS level of every root of the window, in two kernels (plus one for
+// long adjacency lists).
 //
 // k_win_test: a group of G lanes takes one (root slot j, vertex u) entry at
 // distance d and runs the bit-parallel test, then the normal-label test
-// against T[j].  If neither prunes, u gets the candidate label (k, d).  The
-// work per entry is short and uniform, so many entries are in flight.
+// against column j of T.  If neither prunes, u gets the candidate label
+// (k, d).  The work per entry is short, so many entries are in flight.
 //
-// k_win_expand: the candidates of this level push their unvisited
-// neighbours to level d+1, a group per candidate with lanes over the
-// adjacency list (long lists: the first `chunk` entries here, the rest as
-// tasks for whole waves in k_win_heavy).
+// k_win_expand: the candidates of this level reach their neighbours at
+// d+1, a group per candidate with lanes over the adjacency list (long
+// lists: the first `chunk` entries here, the rest as tasks for whole waves
+// in k_win_heavy).  A neighbour not yet visited by the root whose distance
+// row already prunes it at d+1 (some bit-parallel root on a shortest path)
+// is left unvisited: it would be pruned at any later level too, and other
+// parents test it again.  The others are claimed and go to level d+1.
 constexpr int kStage = 256;                 // staged entries per wave
 constexpr int kWavesPerBlock = kBlock / kWave;
+
+// The root's distance row (up to 64 slots) held in registers.
+struct RootRow {
+  uint4 v[4];
+  int nv;
+  __device__ __forceinline__ void load(const DBp &bp, int32_t k) {
+    nv = bp.tpad >> 4;
+    const uint4 *p = reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad);
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = q < nv ? p[q] : make_uint4(~0u, ~0u, ~0u, ~0u);
+  }
+  // Is d_k + d_x <= D for some slot?  Byte sums are formed two at a time in
+  // 16-bit fields (at most 510) and compared with D+1 by one subtraction per
+  // field; 255 (unreachable, padding) never counts: 255 + anything > 254 >= D.
+  __device__ __forceinline__ bool direct(const DBp &bp, int32_t x, int D) const {
+    const uint32_t K = (uint32_t)(D + 1) * 0x00010001u;
+    const uint4 *p = reinterpret_cast<const uint4 *>(bp.d + (int64_t)x * bp.tpad);
+    uint32_t hit = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      if (q >= nv) break;
+      const uint4 b = p[q];
+      const uint32_t aw[4] = {v[q].x, v[q].y, v[q].z, v[q].w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int y = 0; y < 4; y++) {
+        const uint32_t se = (aw[y] & 0x00FF00FFu) + (bw[y] & 0x00FF00FFu);
+        const uint32_t so = ((aw[y] >> 8) & 0x00FF00FFu) + ((bw[y] >> 8) & 0x00FF00FFu);
+        hit |= ~((se | 0x80008000u) - K) & 0x80008000u;
+        hit |= ~((so | 0x80008000u) - K) & 0x80008000u;
+      }
+    }
+    return hit != 0;
+  }
+};
 
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DWindow w,
@@ -203,7 +281,6 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->base[d + 1] = nbase;
   // after an overflow the window is redone; never read past the buffer
   if (cnt == 0 || (ctl->flags & kOverflowFlags) || nbase > (unsigned long long)f.cap) return;
-  const int64_t n = g.n;
   const int gr = Group<G>::rank();
   constexpr int kPerWave = kWave / G;
   const int wv = threadIdx.x / kWave;
@@ -211,15 +288,14 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv]);
-  // candidates (u, j): reserve list slots, write them and their window rows
+  // candidates (u, j): reserve list slots and write them
   auto flush = [&](WaveStage<kStage> &sg) {
     const unsigned long long c0 = sg.reserve(&ctl->ccnt);
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long c = c0 + i;
       if (c < (unsigned long long)w.ccap) {
-        const int32_t u = sg.a[i], j = sg.b[i];
-        w.cu[c] = u;
-        w.cj[c] = j;
+        w.cu[c] = sg.a[i];
+        w.cj[c] = sg.b[i];
         w.cd[c] = (uint8_t)d;
       } else {
         atomicOr(&ctl->flags, kFlagOvfCand);
@@ -228,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   };
   unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
   BpTally tally;
-  // the wave steps through the frontier in lockstep, kPerWave entries at a time
+  // the wave steps through the level in lockstep, kPerWave entries at a time
   for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
     const int64_t p = base + lane_id() / G;
     bool labeled = false;
@@ -236,12 +312,12 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
     if (p < (int64_t)cnt) {
       j = f.slot[beg + p];
       u = f.v[beg + p];
-      const int32_t k = w.s + j;
       if (gr == 0) c_visit++;
-      bool pr = bp_prunes<G>(bp, k, u, d, tally);  // bit-parallel first (Section 5.4)
+      // bit-parallel labels first (Section 5.4)
+      bool pr = bp_prunes<G>(bp, w.s + j, u, d, tally);
       if (!pr) {
         int32_t len;
-        pr = label_prunes<G>(st, w.T + (int64_t)j * n, u, d, &len);
+        pr = label_prunes<G>(st, t_col(w, j), w.sig + 4 * (int64_t)j, u, d, &len);
         if (gr == 0) {
           c_test++;
           c_scan += (unsigned long long)len;
@@ -262,7 +338,6 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   c_test = Group<kWave>::sum_reduce(c_test);
   c_scan = Group<kWave>::sum_reduce(c_scan);
   c_lab = Group<kWave>::sum_reduce(c_lab);
-  tally.direct = Group<kWave>::sum_reduce(tally.direct);
   tally.sets = Group<kWave>::sum_reduce(tally.sets);
   tally.checks = Group<kWave>::sum_reduce(tally.checks);
   if (lane_id() == 0 && c_visit) {
@@ -270,13 +345,12 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
     atomicAdd(&ctl->ntests, c_test);
     atomicAdd(&ctl->lscanned, c_scan);
     atomicAdd(&ctl->labeled, c_lab);
-    atomicAdd(&ctl->bp_direct, tally.direct);
     atomicAdd(&ctl->bp_sets, tally.sets);
     atomicAdd(&ctl->bp_checks, tally.checks);
   }
 }
 
-// Frontier entries (j, x) of level d+1: reserve slots and write them.
+// Entries (j, x) of level d+1: reserve slots and write them.
 struct FrontierFlush {
   LevelCtl *ctl;
   DFrontier f;
@@ -296,6 +370,20 @@ struct FrontierFlush {
   }
 };
 
+// One adjacency entry x of a candidate of root k (slot j) at level d: true
+// if x is claimed for level d+1, false if it was visited already or its
+// distance row prunes it (counted in `direct`).
+__device__ __forceinline__ bool reach(const DBp &bp, const RootRow &rr, uint32_t *vs, int32_t x,
+                                      int d, unsigned long long &direct) {
+  const uint32_t bit = 1u << (x & 31);
+  if (vs[x >> 5] & bit) return false;
+  if (rr.direct(bp, x, d + 1)) {
+    direct++;
+    return false;
+  }
+  return !(atomicOr(&vs[x >> 5], bit) & bit);
+}
+
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore st, DWindow w,
                                                        DFrontier f, int d, int chunk) {
@@ -307,7 +395,6 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
   const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
   if (cend <= cbeg || (ctl->flags & kOverflowFlags)) return;
   const unsigned long long nbase = ctl->base[d + 1];
-  const int64_t n = g.n;
   const int gr = Group<G>::rank();
   constexpr int kPerWave = kWave / G;
   const int wv = threadIdx.x / kWave;
@@ -320,7 +407,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       const int32_t u = w.cu[c], j = w.cj[c];
       const int64_t e0 = g.row[u], deg = g.row[u + 1] - e0;
       const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-      const uint8_t *Tj = w.T + (int64_t)j * n;
+      const TCol Tj = t_col(w, j);
       for (int64_t e = lane_id(); e < deg; e += kWave) {
         const int32_t x = g.col[e0 + e];
         if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
@@ -332,12 +419,14 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv]);
   const FrontierFlush flush{ctl, f, nbase, d};
-  unsigned long long c_edge = 0;
+  unsigned long long c_edge = 0, c_direct = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
     const bool act = c < (int64_t)cend;
     int32_t u = 0, j = 0;
     int64_t e0 = 0, deg = 0, lim = 0;
+    RootRow rr;
+    rr.nv = 0;
     if (act) {
       u = w.cu[c];
       j = w.cj[c];
@@ -345,9 +434,9 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       deg = g.row[u + 1] - e0;
       lim = deg < chunk ? deg : chunk;
       if (gr == 0) c_edge += (unsigned long long)lim;
+      rr.load(bp, w.s + j);
     }
-    const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-    uint32_t *vsw = w.vis + (int64_t)j * g.nwords;
+    uint32_t *vs = w.vis + (int64_t)j * g.nwords;
     const int64_t wl = Group<kWave>::max_reduce64(lim);
     for (int64_t e = 0; e < wl; e += G) {
       const int64_t idx = e + gr;
@@ -355,8 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       int32_t x = 0;
       if (idx < lim) {
         x = g.col[e0 + idx];
-        const uint32_t bit = 1u << (x & 31);
-        if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vsw[x >> 5], bit) & bit);
+        claimed = reach(bp, rr, vs, x, d, c_direct);
       }
       stage.push(claimed, j, x, flush);
     }
@@ -378,11 +466,13 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
   }
   if (stage.n) flush(stage);
   c_edge = Group<kWave>::sum_reduce(c_edge);
+  c_direct = Group<kWave>::sum_reduce(c_direct);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->edges, c_edge);
+  if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
 }
 
-__global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFrontier f, int d,
-                                                      int chunk, int lim_inline) {
+__global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow w, DFrontier f,
+                                                      int d, int chunk, int lim_inline) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
@@ -396,13 +486,15 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFron
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv]);
   const FrontierFlush flush{ctl, f, nbase, d};
-  unsigned long long c_edge = 0;
+  unsigned long long c_edge = 0, c_direct = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
     const int32_t j = f.hslot[tk], u = f.hv[tk], c = f.hchunk[tk];
     const int64_t e0 = g.row[u], e1 = g.row[u + 1];
     const int64_t a = e0 + lim_inline + (int64_t)c * chunk;
     const int64_t b = a + chunk < e1 ? a + chunk : e1;
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
+    RootRow rr;
+    rr.load(bp, w.s + j);
     c_edge += (unsigned long long)(b - a);
     for (int64_t e0b = a; e0b < b; e0b += kWave) {
       const int64_t e = e0b + lane_id();
@@ -410,18 +502,18 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DWindow w, DFron
       int32_t x = 0;
       if (e < b) {
         x = g.col[e];
-        const uint32_t bit = 1u << (x & 31);
-        if (!(vs[x >> 5] & bit)) claimed = !(atomicOr(&vs[x >> 5], bit) & bit);
+        claimed = reach(bp, rr, vs, x, d, c_direct);
       }
       stage.push(claimed, j, x, flush);
     }
   }
   if (stage.n) flush(stage);
+  c_direct = Group<kWave>::sum_reduce(c_direct);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
+  if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
 }
 
-// Clear visited words of every (slot, vertex) ever put on the frontier, and
-// each root's row of T.
+// Clear visited words of every (slot, vertex) ever put on a level.
 __global__ void __launch_bounds__(kBlock) k_win_reset_vis(DGraph g, DWindow w, DFrontier f,
                                                           int64_t nvisited) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nvisited;
@@ -435,10 +527,10 @@ __global__ void __launch_bounds__(kBlock) k_win_reset_T(DGraph g, DWindow w, DSt
   const int32_t j = blockIdx.x;
   const int32_t k = w.s + j;
   if (w.used[k]) return;
-  uint8_t *Tj = w.T + (int64_t)j * g.n;
+  const TCol Tj = t_col(w, j);
   const int64_t o = st.off[k];
   const int32_t len = st.len[k];
-  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) Tj[st.hub[o + e]] = kInf8;
+  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) Tj.at(st.hub[o + e]) = kInf8;
 }
 
 // Drop the window's candidates (a window is re-run smaller after an overflow).
@@ -447,7 +539,7 @@ __global__ void __launch_bounds__(kBlock) k_win_abort(DWindow w, int64_t ncand) 
        c += (int64_t)gridDim.x * blockDim.x) {
     const int32_t u = w.cu[c];
     w.wd[(int64_t)u * (w.words * 64) + w.cj[c]] = kInf8;
-    for (int i = 0; i < w.words; i++) w.cmask[(int64_t)u * w.words + i] = 0ull;
+    for (int i = 0; i < ((w.W + 63) >> 6); i++) w.cmask[(int64_t)u * w.words + i] = 0ull;
   }
 }
 
@@ -482,7 +574,7 @@ __global__ void __launch_bounds__(kBlock) k_win_clean(DWindow w, int64_t ncand) 
     if (!drop)
       atomicOr((unsigned long long *)&w.kmask[(int64_t)u * w.words + jw], 1ull << jb);
     int low = -1;
-    for (int i = 0; i < w.words; i++) {
+    for (int i = 0; i < ((w.W + 63) >> 6); i++) {
       if (cu_row[i]) {
         low = i * 64 + __ffsll((unsigned long long)cu_row[i]) - 1;
         break;
@@ -492,59 +584,90 @@ __global__ void __launch_bounds__(kBlock) k_win_clean(DWindow w, int64_t ncand) 
   }
 }
 
-// Commit: one thread per touched vertex appends its surviving labels in
-// root order (labels stay sorted by hub rank, Section 4.5.1), growing its
-// slot in the pool when full, and clears the vertex's window rows.
-__global__ void __launch_bounds__(kBlock) k_win_commit(DWindow w, DStore st, int64_t ncand) {
-  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    if (!w.cdes[c]) continue;
-    const int32_t u = w.cu[c];
-    uint64_t *crow = w.cmask + (int64_t)u * w.words;
-    uint64_t *krow = w.kmask + (int64_t)u * w.words;
-    uint8_t *wu = w.wd + (int64_t)u * (w.words * 64);
-    int32_t total = 0;
-    for (int i = 0; i < w.words; i++) total += __popcll(krow[i]);
-    if (total > 0) {
-      const int32_t len = st.len[u];
+// Commit, in three passes so that no thread walks a whole row serially.
+// Pass 1, one lane per touched vertex (its designated candidate): count the
+// surviving labels, grow the vertex's pool slot when full (the copy of the
+// old entries is done by the whole wave), publish the new length and clear
+// the vertex's candidate mask.
+__global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore st,
+                                                             int64_t ncand) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nloop = (ncand + stride - 1) / stride;
+  for (int64_t it = 0; it < nloop; it++) {
+    const int64_t c = t0 + it * stride;
+    bool reloc = false;
+    int32_t u = 0, len = 0;
+    int64_t oo = 0, no = 0, nc = 0;
+    if (c < ncand && w.cdes[c]) {
+      u = w.cu[c];
+      const uint64_t *krow = w.kmask + (int64_t)u * w.words;
+      uint64_t *crow = w.cmask + (int64_t)u * w.words;
+      int32_t total = 0;
+      for (int i = 0; i < ((w.W + 63) >> 6); i++) {
+        total += __popcll(krow[i]);
+        crow[i] = 0ull;
+      }
+      len = st.len[u];
       const int32_t need = len + total;
-      if (need > st.cap[u]) {
-        int64_t nc = 2 * (int64_t)need;
+      if (total > 0 && need > st.cap[u]) {
+        nc = 2 * (int64_t)need;
         if (nc < 16) nc = 16;
         nc = (nc + 15) & ~(int64_t)15;
-        const int64_t no = (int64_t)atomicAdd(st.top, (unsigned long long)nc);
-        const int64_t oo = st.off[u];
-        for (int32_t e = 0; e < len; e++) {
-          st.hub[no + e] = st.hub[oo + e];
-          st.dist[no + e] = st.dist[oo + e];
-        }
-        st.off[u] = no;
-        st.cap[u] = (int32_t)nc;
-      }
-      int64_t o = st.off[u] + len;
-      for (int i = 0; i < w.words; i++) {
-        uint64_t m = krow[i];
-        while (m) {
-          const int b = __ffsll((unsigned long long)m) - 1;
-          m &= m - 1;
-          const int jj = i * 64 + b;
-          st.hub[o] = (uint32_t)(w.s + jj);
-          st.dist[o] = wu[jj];
-          o++;
-        }
+        no = (int64_t)atomicAdd(st.top, (unsigned long long)nc);
+        oo = st.off[u];
+        reloc = true;
       }
       st.len[u] = need;
     }
-    for (int i = 0; i < w.words; i++) {
-      uint64_t m = crow[i];
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        wu[i * 64 + b] = kInf8;
+    uint64_t m = __ballot(reloc);
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int32_t ln = __shfl(len, l);
+      const int64_t so = __shfl(oo, l), dn = __shfl(no, l);
+      for (int32_t e = lane_id(); e < ln; e += kWave) {
+        st.hub[dn + e] = st.hub[so + e];
+        st.dist[dn + e] = st.dist[so + e];
       }
-      crow[i] = 0ull;
-      krow[i] = 0ull;
     }
+    if (reloc) {
+      st.off[u] = no;
+      st.cap[u] = (int32_t)nc;
+    }
+  }
+}
+
+// Pass 2, one thread per candidate: a survivor writes (root rank, distance)
+// at its place among the vertex's new labels, in root order, so labels stay
+// sorted by hub rank (Section 4.5.1); every candidate clears its distance
+// cell of the window.
+__global__ void __launch_bounds__(kBlock) k_win_commit_write(DWindow w, DStore st,
+                                                             int64_t ncand) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = w.cu[c], j = w.cj[c];
+    const int jw = j >> 6, jb = j & 63;
+    const uint64_t *krow = w.kmask + (int64_t)u * w.words;
+    const uint64_t kw = krow[jw];
+    if ((kw >> jb) & 1ull) {
+      int32_t above = __popcll(jb == 63 ? 0ull : (kw >> (jb + 1)));
+      for (int i = jw + 1; i < ((w.W + 63) >> 6); i++) above += __popcll(krow[i]);
+      const int64_t o = st.off[u] + st.len[u] - 1 - above;
+      st.hub[o] = (uint32_t)(w.s + j);
+      st.dist[o] = w.cd[c];
+    }
+    w.wd[(int64_t)u * (w.words * 64) + j] = kInf8;
+  }
+}
+
+// Pass 3, one thread per touched vertex: clear its survivor mask.
+__global__ void __launch_bounds__(kBlock) k_win_commit_clear(DWindow w, int64_t ncand) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (!w.cdes[c]) continue;
+    uint64_t *krow = w.kmask + (int64_t)w.cu[c] * w.words;
+    for (int i = 0; i < ((w.W + 63) >> 6); i++) krow[i] = 0ull;
   }
 }
 
@@ -573,16 +696,6 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t 
   }
 }
 
-template <int G>
-void launch_level_g(DGraph g, DBp bp, DStore st, DWindow w, DFrontier f, int d, int chunk,
-                    hipStream_t s, int blocks, hipEvent_t ev0, hipEvent_t ev1) {
-  if (ev0) (void)hipEventRecord(ev0, s);
-  hipLaunchKernelGGL(k_win_test<G>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d);
-  if (ev1) (void)hipEventRecord(ev1, s);
-  hipLaunchKernelGGL(k_win_expand<16>, dim3(blocks), dim3(kBlock), 0, s, g, bp, st, w, f, d, chunk);
-  hipLaunchKernelGGL(k_win_heavy, dim3(blocks), dim3(kBlock), 0, s, g, w, f, d, chunk, chunk);
-}
-
 unsigned grid_for(int64_t items, int per_block, int64_t cap) {
   int64_t b = (items + per_block - 1) / per_block;
   if (b < 1) b = 1;
@@ -605,15 +718,27 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 }
 
 hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int chunk, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                            int xgroup, int chunk, hipStream_t st, hipEvent_t ev0,
+                            hipEvent_t ev1) {
   const int blocks = 2048;
+  const dim3 gd(blocks), bd(kBlock);
+  if (ev0) (void)hipEventRecord(ev0, st);
   switch (group) {
-    case 4: launch_level_g<4>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
-    case 8: launch_level_g<8>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
-    case 16: launch_level_g<16>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
-    case 32: launch_level_g<32>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
-    default: launch_level_g<64>(g, bp, s, w, f, d, chunk, st, blocks, ev0, ev1); break;
+    case 4: hipLaunchKernelGGL(k_win_test<4>, gd, bd, 0, st, g, bp, s, w, f, d); break;
+    case 8: hipLaunchKernelGGL(k_win_test<8>, gd, bd, 0, st, g, bp, s, w, f, d); break;
+    case 16: hipLaunchKernelGGL(k_win_test<16>, gd, bd, 0, st, g, bp, s, w, f, d); break;
+    case 32: hipLaunchKernelGGL(k_win_test<32>, gd, bd, 0, st, g, bp, s, w, f, d); break;
+    default: hipLaunchKernelGGL(k_win_test<64>, gd, bd, 0, st, g, bp, s, w, f, d); break;
   }
+  if (ev1) (void)hipEventRecord(ev1, st);
+  switch (xgroup) {
+    case 4: hipLaunchKernelGGL(k_win_expand<4>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+    case 8: hipLaunchKernelGGL(k_win_expand<8>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+    case 16: hipLaunchKernelGGL(k_win_expand<16>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+    case 32: hipLaunchKernelGGL(k_win_expand<32>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+    default: hipLaunchKernelGGL(k_win_expand<64>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+  }
+  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, bp, w, f, d, chunk, chunk);
   return hipGetLastError();
 }
 
@@ -641,9 +766,11 @@ hipError_t launch_win_clean(DWindow w, int64_t ncand, hipStream_t st) {
 }
 
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st) {
-  if (ncand > 0)
-    hipLaunchKernelGGL(k_win_commit, dim3(grid_for(ncand, kBlock, 8192)), dim3(kBlock), 0, st, w,
-                       s, ncand);
+  if (ncand <= 0) return hipSuccess;
+  const unsigned blocks = grid_for(ncand, kBlock, 8192);
+  hipLaunchKernelGGL(k_win_commit_alloc, dim3(blocks), dim3(kBlock), 0, st, w, s, ncand);
+  hipLaunchKernelGGL(k_win_commit_write, dim3(blocks), dim3(kBlock), 0, st, w, s, ncand);
+  hipLaunchKernelGGL(k_win_commit_clear, dim3(blocks), dim3(kBlock), 0, st, w, ncand);
   return hipGetLastError();
 }
 
