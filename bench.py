@@ -59,12 +59,15 @@ def level_kernel_bytes(st, t_bp):
     """Algorithmic bytes of the pruned-phase prune-test kernel (k_win_test),
     summed over all its launches in one build (per-unit figures of the byte
     model in DESIGN.md):
-      per visited (root, vertex): 16 B label offsets + 17*t_bp B bit-parallel
-        label of the vertex,
-      per label entry scanned by a normal-label test: 5 B (hub + distance),
-      per labeled vertex: 5 B label append."""
-    return (st["visited"] * (16 + 17 * t_bp) + 5 * st["label_scanned"]
-            + 5 * st["candidates"])
+      per level entry (root slot, vertex): 8 B entry + t_bp B distance row,
+      per (S^{-1}, S^{0}) slot pair read by a set check: 32 B (root's and
+        vertex's pair),
+      per normal-label test: 12 B label offset and length, plus 5 B (hub +
+        distance) per label entry scanned,
+      per candidate label: 18 B (list entry 9 B, window distance 1 B, mask
+        word 8 B)."""
+    return (st["visited"] * (8 + t_bp) + 32 * st["bp_checks"] + 12 * st["normal_tests"]
+            + 5 * st["label_scanned"] + 18 * st["candidates"])
 
 
 def cpu_baseline(g, order, t_bp, pairs):

@@ -177,7 +177,7 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
     }
     bool pr = false;
     if (mine >= 0) {
-      if (gr == 0) tally.checks++;
+      tally.checks++;  // one slot pair per lane
       const ulonglong2 mk = pk[mine], mu = pu[mine];
       pr = (mk.x & mu.x) != 0 || (mine2 && ((mk.y & mu.x) | (mk.x & mu.y)) != 0);
     }

@@ -47,6 +47,20 @@ def test_strerror_and_tuning():
         binding.set_tuning("group", 12)
     with pytest.raises(binding.PllError):
         binding.set_tuning("nope", 1)
+    for key, good, bad in [("xgroup", 32, 24), ("window_work", 0, -1), ("window_mem_mb", 64, 0),
+                           ("window", 16384, 16385), ("group", 64, 128)]:
+        old = binding.get_tuning(key)
+        binding.set_tuning(key, good)
+        assert binding.get_tuning(key) == good
+        with pytest.raises(binding.PllError):
+            binding.set_tuning(key, bad)
+        assert binding.get_tuning(key) == good
+        binding.set_tuning(key, old)
+
+
+def test_level_trace_rejects_null():
+    lib = binding.library()
+    assert lib.pll_level_trace(None, None, 0) == binding.E_INVAL
 
 
 def _rc_build(rp, col, order, t, flags=0):

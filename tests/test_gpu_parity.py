@@ -70,16 +70,41 @@ def test_small_families(name, g, t_bp):
         assert np.array_equal(gx.query(p, plain=True), want)
 
 
-@pytest.mark.parametrize("window,group", [(1, 16), (3, 4), (17, 8), (64, 64), (1024, 32)])
-def test_windows_and_groups(window, group):
-    # concurrent roots + cleaning must give the sequential labels exactly
+@pytest.mark.parametrize("window,group,xgroup,work", [
+    (1, 16, 16, 0), (3, 4, 4, 0), (17, 8, 64, 0), (64, 64, 8, 0), (1024, 32, 16, 0),
+    (16384, 4, 16, 300), (4096, 4, 32, 5000), (700, 8, 4, 0)])
+def test_windows_and_groups(window, group, xgroup, work):
+    # concurrent roots + cleaning must give the sequential labels exactly,
+    # for fixed windows (work 0) and windows resized after every window
     _require_gpu()
     g = gen.ba_graph(700, 3, 31)
     order = gen.degree_order(g)
     ox = oracle.build(g.row_ptr, g.col, order, 4)
-    with Tuned(window=window, group=group, chunk=64):
+    with Tuned(window=window, group=group, xgroup=xgroup, window_work=work, chunk=64):
         gx = binding.build(g.row_ptr, g.col, order, 4)
-    assert_same_index(gx, ox, f"w{window} g{group}")
+    assert_same_index(gx, ox, f"w{window} g{group} x{xgroup} work{work}")
+
+
+def test_level_trace():
+    # the per-level profile accounts for every visit and candidate
+    _require_gpu()
+    g, order, t_bp, _ = gen.config_graph("ba2000")
+    with Tuned(profile=0):
+        gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    assert gx.level_trace().shape == (0, 7)
+    with Tuned(profile=1, window_work=2000):
+        gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    tr, st = gx.level_trace(), gx.stats()
+    assert tr.shape[1] == len(binding.Index.TRACE_COLS) and len(tr) == st["level_launches"]
+    assert tr[:, 4].sum() == st["visited"] and tr[:, 5].sum() == st["candidates"]
+    assert len(np.unique(tr[:, 0])) == st["windows"] and np.all(tr[:, 6] >= 0)
+    for wi in np.unique(tr[:, 0]):
+        rows = tr[tr[:, 0] == wi]
+        assert np.array_equal(rows[:, 3], np.arange(len(rows)))  # levels 0, 1, ...
+        assert len(np.unique(rows[:, 1])) == 1 and len(np.unique(rows[:, 2])) == 1
+    firsts = tr[tr[:, 3] == 0][:, 1:3]
+    assert firsts[0, 0] == 0 and np.array_equal(firsts[1:, 0], firsts[:-1].sum(1))
+    assert firsts[-1].sum() == g.n
 
 
 def test_random_order_and_plain_build():
