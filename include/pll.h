@@ -56,6 +56,21 @@ enum {
                               concurrent roots); query one thread per pair */
 
 /*
+ * Device allocator for builds and indexes (process-wide; the default is
+ * hipMalloc/hipFree).  alloc(bytes, stream, ctx) returns device memory or
+ * NULL (then the call fails with PLL_E_NOMEM); `stream` is the stream of the
+ * build that asked, so a stream-ordered allocator (for example a caching
+ * allocator's raw alloc/delete) may reuse memory in stream order.
+ * free_(ptr, stream, ctx) gets the same stream.  Index memory is released
+ * by pll_free, which the caller issues only when no work on the index is
+ * pending.  Both NULL restores the default; exactly one NULL is
+ * PLL_E_INVAL.  Memory keeps the allocator it came from: changing the hook
+ * does not affect existing indexes.
+ */
+int pll_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
+                      void (*free_)(void *ptr, void *stream, void *ctx), void *ctx);
+
+/*
  * Build the index of one graph (Algorithm 2 with the bit-parallel phase of
  * Section 5.4 in front).
  *   n        number of vertices (>= 0)

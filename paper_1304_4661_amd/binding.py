@@ -31,7 +31,7 @@ EXPORTED = [
     "pll_build", "pll_build_batch", "pll_query", "pll_query_batch", "pll_sync",
     "pll_export_sizes", "pll_export", "pll_stats", "pll_level_trace", "pll_free", "pll_strerror",
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
-    "pll_server_done", "pll_server_stop", "pll_serve_bench",
+    "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -78,6 +78,8 @@ def _lib():
         lib.pll_free.restype = None
         lib.pll_strerror.argtypes = [C.c_int]
         lib.pll_strerror.restype = C.c_char_p
+        lib.pll_set_allocator.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.pll_set_allocator.restype = C.c_int
         lib.pll_set_tuning.argtypes = [C.c_char_p, C.c_int64]
         lib.pll_set_tuning.restype = C.c_int
         lib.pll_get_tuning.argtypes = [C.c_char_p]
@@ -117,6 +119,39 @@ def set_tuning(key: str, value: int):
 
 def get_tuning(key: str) -> int:
     return int(_lib().pll_get_tuning(key.encode()))
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_allocator_refs = []  # keeps the installed callbacks alive
+
+
+def use_torch_allocator(enable: bool = True):
+    """Route the library's device allocations through torch's caching
+    allocator (memory then shows in torch.cuda.memory_allocated and is
+    reused by torch after pll_free), or back to hipMalloc."""
+    lib = _lib()
+    if not enable:
+        _check(lib.pll_set_allocator(None, None, None), "set_allocator")
+        _allocator_refs.clear()
+        return
+    import torch
+
+    dev = torch.cuda.current_device()
+
+    def _alloc(nbytes, stream, _ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+        except Exception:  # out of memory: the library reports PLL_E_NOMEM
+            return None
+
+    def _free(ptr, _stream, _ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = ALLOC_FN(_alloc), FREE_FN(_free)
+    _check(lib.pll_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None),
+           "set_allocator")
+    _allocator_refs[:] = [a, f]
 
 
 class Index:

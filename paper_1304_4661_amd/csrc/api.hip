@@ -49,15 +49,41 @@ void check(hipError_t e) {
 }
 
 // Owning device buffer.
+// Device memory of builds and indexes: hipMalloc, or a caller's allocator
+// (pll_set_allocator), which receives the stream of the build so that a
+// stream-ordered allocator can reuse memory safely.
+struct AllocHook {
+  void *(*alloc)(size_t, void *, void *) = nullptr;
+  void (*free_)(void *, void *, void *) = nullptr;
+  void *ctx = nullptr;
+};
+AllocHook g_alloc_hook;
+std::mutex g_alloc_mu;
+thread_local hipStream_t t_alloc_stream = nullptr;
+
+AllocHook alloc_hook() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc_hook;
+}
+
+// Sets the stream passed to the allocator for this thread's allocations.
+struct AllocStream {
+  hipStream_t old;
+  explicit AllocStream(hipStream_t s) : old(t_alloc_stream) { t_alloc_stream = s; }
+  ~AllocStream() { t_alloc_stream = old; }
+};
+
 template <typename T>
 struct DBuf {
   T *p = nullptr;
   size_t count = 0;
+  AllocHook hook;                // allocator the memory came from
+  hipStream_t stream = nullptr;  // stream it was allocated for
   DBuf() = default;
   explicit DBuf(size_t c) { alloc(c); }
   DBuf(const DBuf &) = delete;
   DBuf &operator=(const DBuf &) = delete;
-  DBuf(DBuf &&o) noexcept : p(o.p), count(o.count) {
+  DBuf(DBuf &&o) noexcept : p(o.p), count(o.count), hook(o.hook), stream(o.stream) {
     o.p = nullptr;
     o.count = 0;
   }
@@ -66,6 +92,8 @@ struct DBuf {
       reset();
       p = o.p;
       count = o.count;
+      hook = o.hook;
+      stream = o.stream;
       o.p = nullptr;
       o.count = 0;
     }
@@ -73,18 +101,29 @@ struct DBuf {
   }
   void alloc(size_t c) {
     reset();
-    count = c;
-    size_t bytes = std::max<size_t>(c * sizeof(T), 1);
-    hipError_t e = hipMalloc((void **)&p, bytes);
-    if (e != hipSuccess) {
-      p = nullptr;
-      count = 0;
-      (void)hipGetLastError();
-      throw Fail{e == hipErrorOutOfMemory ? PLL_E_NOMEM : PLL_E_DEVICE};
+    const size_t bytes = std::max<size_t>(c * sizeof(T), 1);
+    hook = alloc_hook();
+    stream = t_alloc_stream;
+    if (hook.alloc) {
+      p = static_cast<T *>(hook.alloc(bytes, (void *)stream, hook.ctx));
+      if (!p) throw Fail{PLL_E_NOMEM};
+    } else {
+      hipError_t e = hipMalloc((void **)&p, bytes);
+      if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        throw Fail{e == hipErrorOutOfMemory ? PLL_E_NOMEM : PLL_E_DEVICE};
+      }
     }
+    count = c;
   }
   void reset() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (hook.alloc)
+        hook.free_(p, (void *)stream, hook.ctx);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     count = 0;
   }
@@ -712,6 +751,7 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   if (!out) return PLL_E_INVAL;
   *out = nullptr;
   hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
   const bool device = (flags & PLL_DEVICE_PTRS) != 0;
   if (G < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP || (G > 0 && !vtx_off)) return PLL_E_INVAL;
   std::vector<int64_t> voff(vtx_off, vtx_off + (G > 0 ? G + 1 : 0));
@@ -773,6 +813,14 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   return PLL_OK;
 }
 
+int pll_set_allocator(void *(*alloc)(size_t, void *, void *), void (*free_)(void *, void *, void *),
+                      void *ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return PLL_E_INVAL;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc_hook = AllocHook{alloc, free_, alloc ? ctx : nullptr};
+  return PLL_OK;
+}
+
 int pll_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
               int32_t t_bp, uint32_t flags, void *stream, pll_index **out) {
   if (n < 0) return PLL_E_INVAL;
@@ -792,6 +840,7 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
   if (q == 0) return PLL_OK;
   if (!pairs || !out) return PLL_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
   const Tuning tu = tuning();
   const bool plain = (flags & PLL_PLAIN) != 0;
   if (!(flags & PLL_DEVICE_PTRS)) {

@@ -58,6 +58,13 @@ def test_strerror_and_tuning():
         binding.set_tuning(key, old)
 
 
+def test_set_allocator_arguments():
+    lib = binding.library()
+    f = binding.FREE_FN(lambda p, s, c: None)
+    assert lib.pll_set_allocator(None, C.cast(f, C.c_void_p), None) == binding.E_INVAL
+    assert lib.pll_set_allocator(None, None, None) == binding.OK
+
+
 def test_level_trace_rejects_null():
     lib = binding.library()
     assert lib.pll_level_trace(None, None, 0) == binding.E_INVAL

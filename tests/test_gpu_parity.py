@@ -85,6 +85,30 @@ def test_windows_and_groups(window, group, xgroup, work):
     assert_same_index(gx, ox, f"w{window} g{group} x{xgroup} work{work}")
 
 
+def test_torch_allocator_hook():
+    # builds through torch's caching allocator: same index, memory visible
+    # to torch while the index lives and handed back by pll_free
+    import torch
+
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    binding.use_torch_allocator(True)
+    try:
+        gx = binding.build(g.row_ptr, g.col, order, t_bp)
+        held = torch.cuda.memory_allocated() - base
+        assert held >= gx.stats()["index_bytes"] > 0
+        assert_same_index(gx, ox, "torch allocator")
+        assert np.array_equal(gx.query(pairs), oracle.query(ox, pairs))
+        gx.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        binding.use_torch_allocator(False)
+
+
 def test_level_trace():
     # the per-level profile accounts for every visit and candidate
     _require_gpu()
