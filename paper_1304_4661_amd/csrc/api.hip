@@ -450,9 +450,9 @@ struct Builder {
 
   // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR
   void pruned(pll_index *ix) {
-    // per-root window state: T row (n B), distance column of wd (n B),
-    // visited bits (n/8 B) and two mask bits per vertex (n/4 B)
-    const int64_t per_root = 2 * (int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1;
+    // per-root window state: distance column of wd (n B), visited bits
+    // (n/8 B) and two mask bits per vertex (n/4 B)
+    const int64_t per_root = (int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1;
     const int64_t wmem = std::max<int64_t>(64, (tu.window_mem_mb << 20) / per_root);
     const int wmax =
         plain ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>({tu.window, kMaxWindow, wmem}));
@@ -471,10 +471,14 @@ struct Builder {
     fill(top, 0, st);
     // window state
     DBuf<uint32_t> vis((size_t)wmax * nwords);
-    DBuf<uint8_t> T((size_t)n * wstride), wd((size_t)n * wstride);
+    DBuf<uint8_t> wd((size_t)n * wstride);
+    // the roots' label tables: grown when a window needs more
+    int64_t htcap = std::max<int64_t>(1 << 20, 32 * (int64_t)wmax);
+    DBuf<uint64_t> ht((size_t)htcap);
+    DBuf<int64_t> htoff((size_t)wmax + 1), hsize((size_t)wmax + 1),
+        htmp((size_t)scan_tmp_elems((int64_t)wmax + 1));
     DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words), sig((size_t)wmax * 4);
     fill(vis, 0, st);
-    fill(T, 0xFF, st);
     fill(wd, 0xFF, st);
     fill(cmask, 0, st);
     fill(kmask, 0, st);
@@ -522,10 +526,10 @@ struct Builder {
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
       DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
-      DWindow w{s,    nr,   words, vis.p,  T.p,  sig.p, wd.p,
-                cmask.p, kmask.p, cu.p, cj.p, cd.p, cdes.p, ccap, used.p};
+      DWindow w{s,     nr,    words,   vis.p, ht.p, htoff.p, htcap, sig.p, wd.p,
+                cmask.p, kmask.p, cu.p, cj.p,  cd.p, cdes.p,  ccap,  used.p};
       check(launch_win_reset_ctl(ctl.p, st));
-      check(launch_win_init(graph(), w, sto, f, nr, st));
+      check(launch_win_init(graph(), w, sto, f, nr, hsize.p, htmp.p, st));
       int d = 0;
       bool done = false;
       while (!done) {
@@ -566,10 +570,16 @@ struct Builder {
         check(launch_win_abort(graph(), w, ncand, st));
         if (h.flags & kFlagOvfFrontier) fill(vis, 0, st);
         check(hipStreamSynchronize(st));
+        level_trace.resize(trace_mark);
+        if (h.flags == kFlagOvfHash) {
+          // same window again with room for its root tables
+          htcap = std::max<int64_t>(2 * htcap, (int64_t)h.httotal + (int64_t)h.httotal / 4);
+          ht.alloc((size_t)htcap);
+          continue;
+        }
         if (W == 1) throw Fail{(h.flags & kFlagRange) ? PLL_E_RANGE : PLL_E_NOMEM};
         W = std::max(1, W / 4);
         stat_retries++;
-        level_trace.resize(trace_mark);
         continue;
       }
       // make sure the commit can grow every touched label without running

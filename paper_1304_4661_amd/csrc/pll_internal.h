@@ -184,6 +184,7 @@ struct LevelCtl {
   unsigned long long hcnt2[kMaxLevels + 2]; // second task list (bit-parallel E1)
   unsigned long long cmark[kMaxLevels + 2]; // first candidate found at each level
   unsigned long long ccnt;                  // candidate labels of the window
+  unsigned long long httotal;               // entries of the window's root tables
   unsigned long long visited;               // (root, vertex) entries tested
   unsigned long long ntests;                // ... that reached the normal-label test
   unsigned long long lscanned;              // label entries read by those tests
@@ -202,7 +203,8 @@ enum : int32_t {
   kFlagOvfHeavy = 2,
   kFlagOvfCand = 4,
   kFlagRange = 8,  // a vertex at distance 255 would be labeled (or reached, BP)
-  kOverflowFlags = kFlagOvfFrontier | kFlagOvfHeavy | kFlagOvfCand,
+  kFlagOvfHash = 16,  // the root tables need more room than allocated
+  kOverflowFlags = kFlagOvfFrontier | kFlagOvfHeavy | kFlagOvfCand | kFlagOvfHash,
 };
 
 // Growing label store used during the build: label of rank r lives at
@@ -233,8 +235,9 @@ struct DWindow {
   int32_t s, W, words;  // W roots; words: mask row stride (wd row stride words*64);
                         // only the first (W+63)/64 words are in use
   uint32_t *vis;        // [W][nwords] visited bits per root slot
-  uint8_t *T;           // [n][words*64] root j's label distance to hub h at
-                        // T[h][j], else 255 (Section 4.5.1)
+  uint64_t *ht;         // hash tables of the roots' labels (hub, distance)
+  int64_t *htoff;       // [W+1] table j at [htoff[j], htoff[j+1]), size 2^x or 0
+  int64_t htcap;        // entries available at ht
   uint64_t *sig;        // [W][4] 256-bit hub signature of each root's label
   uint8_t *wd;          // [n][words*64] distance from window root j, or 255
   uint64_t *cmask;      // [n][words] window roots that labeled the vertex
@@ -289,8 +292,9 @@ hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t
 hipError_t launch_bpv_finish(int64_t total, uint64_t *m, hipStream_t st);
 
 hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
+// sizes: int64[nroots + 1]; scan_tmp: scan_tmp_elems(nroots + 1) int64
 hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
-                           hipStream_t st);
+                           int64_t *sizes, int64_t *scan_tmp, hipStream_t st);
 // ev0/ev1 (may be null): recorded around the level kernel itself.
 hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
                             int xgroup, int chunk, hipStream_t st, hipEvent_t ev0,

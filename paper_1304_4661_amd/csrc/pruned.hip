@@ -29,16 +29,39 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Column j of the window's T array.  T is stored hub-major, T[h][j]: the
-// roots of a window probe the same popular hubs, whose rows then stay in
-// cache, where a root-major layout would touch one line per (root, hub).
-struct TCol {
-  uint8_t *p;
-  int64_t stride;
-  __device__ __forceinline__ uint8_t &at(int64_t h) const { return p[h * stride]; }
+// The root's label for the normal-label test (the role of the paper's
+// array T, Section 4.5.1 "Querying"): an open-addressing table per window
+// root mapping hub -> distance, sized to a power of two >= 4 |L(k)|, so a
+// lookup costs about one probe.  All tables of a window take a few MB and
+// stay in cache, where a dense T would take n bytes per root and every
+// lookup would be a random HBM read.  An entry packs hub (low 32 bits) and
+// distance (next 8); kEmpty marks a free slot (no hub is 0xFFFFFFFF).
+constexpr uint64_t kEmpty = ~0ull;
+
+__device__ __forceinline__ uint32_t ht_hash(uint32_t h) {
+  uint32_t x = h * 0x85EBCA6Bu;
+  return x ^ (x >> 16);
+}
+
+struct RootTable {
+  const uint64_t *p;
+  uint32_t mask;  // size - 1; size 0 means an empty label
+  bool empty;
+  // distance from the root to hub h, or 255 if h is not in L(k)
+  __device__ __forceinline__ int get(uint32_t h) const {
+    if (empty) return kInf8;
+    uint32_t slot = ht_hash(h) & mask;
+    for (;;) {
+      const uint64_t e = p[slot];
+      if ((uint32_t)e == h) return (int)((e >> 32) & 0xFFu);
+      if (e == kEmpty) return kInf8;
+      slot = (slot + 1) & mask;
+    }
+  }
 };
-__device__ __forceinline__ TCol t_col(const DWindow &w, int32_t j) {
-  return TCol{w.T + j, (int64_t)w.words * 64};
+__device__ __forceinline__ RootTable root_table(const DWindow &w, int32_t j) {
+  const int64_t a = w.htoff[j], b = w.htoff[j + 1];
+  return RootTable{w.ht + a, (uint32_t)(b - a - 1), b == a};
 }
 
 __global__ void k_win_reset_ctl(LevelCtl *ctl) {
@@ -50,28 +73,59 @@ __global__ void k_win_reset_ctl(LevelCtl *ctl) {
 // Hub signature bit (0..255) of a root's label: multiplicative hashing.
 __device__ __forceinline__ uint32_t sig_bit(uint32_t h) { return (h * 2654435761u) >> 24; }
 
-// Block j: root k = s + j.  Scatter L(k) into column j of T, build the
-// 256-bit signature of L(k)'s hubs, mark k visited and put (j, k) on
-// level 0.  Bit-parallel roots and neighbours run no pruned BFS (they would
-// prune themselves at distance 0).
+// Table size of each window root (0 for an empty label or a root that runs
+// no BFS), for the exclusive scan that places the tables; sizes[W] = 0.
+__global__ void k_win_ht_size(DWindow w, DStore st, int64_t *sizes) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > w.W) return;
+  int64_t sz = 0;
+  if (j < w.W && !w.used[w.s + j]) {
+    const int32_t len = st.len[w.s + j];
+    if (len > 0) {
+      sz = 8;
+      while (sz < 4 * (int64_t)len) sz <<= 1;
+    }
+  }
+  sizes[j] = sz;
+}
+
+// Block j: root k = s + j.  Build the root's table of L(k) and the 256-bit
+// signature of its hubs, mark k visited and put (j, k) on level 0.
+// Bit-parallel roots and neighbours run no pruned BFS (they would prune
+// themselves at distance 0).  Block 0 publishes the tables' total size and
+// flags a window whose tables do not fit (it is then run again after the
+// host grows the table area).
 __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore st, DFrontier f) {
   __shared__ unsigned long long s_sig[4];
   const int32_t j = blockIdx.x;
   const int32_t k = w.s + j;
+  const int64_t total = w.htoff[w.W];
+  if (j == 0 && threadIdx.x == 0) {
+    f.ctl->httotal = (unsigned long long)total;
+    if (total > w.htcap) atomicOr(&f.ctl->flags, kFlagOvfHash);
+  }
   if (w.used[k]) {
     if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = 0ull;
     return;
   }
   if (threadIdx.x < 4) s_sig[threadIdx.x] = 0ull;
+  const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
+  const bool fits = total <= w.htcap;
+  if (fits)
+    for (int64_t e = threadIdx.x; e < sz; e += blockDim.x) w.ht[a + e] = kEmpty;
   __syncthreads();
-  const TCol Tj = t_col(w, j);
   const int64_t o = st.off[k];
   const int32_t len = st.len[k];
   for (int32_t e = threadIdx.x; e < len; e += blockDim.x) {
     const uint32_t h = st.hub[o + e];
-    Tj.at(h) = st.dist[o + e];
     const uint32_t b = sig_bit(h);
     atomicOr(&s_sig[b >> 6], 1ull << (b & 63));
+    if (!fits) continue;
+    const unsigned long long ent = ((unsigned long long)st.dist[o + e] << 32) | h;
+    uint32_t slot = ht_hash(h) & (uint32_t)(sz - 1);
+    while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmpty, ent) !=
+           (unsigned long long)kEmpty)
+      slot = (slot + 1) & (uint32_t)(sz - 1);
   }
   __syncthreads();
   if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = s_sig[threadIdx.x];
@@ -85,7 +139,7 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
 
 // Full prune test of one vertex by one lane (used only for the rare vertex
 // at distance 255, to decide whether the build must fail).
-__device__ bool prune_test_serial(DBp bp, DStore st, TCol Tj, int32_t k, int32_t u,
+__device__ bool prune_test_serial(DBp bp, DStore st, RootTable Tj, int32_t k, int32_t u,
                                   int d) {
   for (int32_t i = 0; i < bp.t; i++) {
     const int dk = bp.d[(int64_t)k * bp.tpad + i], du = bp.d[(int64_t)u * bp.tpad + i];
@@ -97,7 +151,7 @@ __device__ bool prune_test_serial(DBp bp, DStore st, TCol Tj, int32_t k, int32_t
   const int64_t o = st.off[u];
   const int32_t len = st.len[u];
   for (int32_t e = 0; e < len; e++) {
-    const int th = Tj.at(st.hub[o + e]);
+    const int th = Tj.get(st.hub[o + e]);
     if (th != kInf8 && st.dist[o + e] + th <= d) return true;
   }
   return false;
@@ -111,6 +165,30 @@ __device__ bool prune_test_serial(DBp bp, DStore st, TCol Tj, int32_t k, int32_t
 // G slots per round, the slots that prune with -1 or -2 first (they succeed
 // more often than the -2-only ones), stopping at the first round that
 // prunes.  Distance rows are read 16 slots per lane.
+// Byte-wise sums of two distance-row words, two bytes at a time in 16-bit
+// fields: `hit` gets a bit where a + c <= D (K1 = (D+1) * 0x00010001; 255
+// never counts there since 255 + c > 254 >= D), n2 / n1 the 4-bit masks (bit
+// = byte) of the bytes with a + c == D + 1 / D + 2 (K2 = (D+2) * 0x00010001),
+// both distances finite.
+__device__ __forceinline__ void swar_word(uint32_t aw, uint32_t bw, uint32_t K1, uint32_t K2,
+                                          uint32_t &hit, uint32_t &n1, uint32_t &n2) {
+  uint32_t z1[2], z2[2];
+#pragma unroll
+  for (int h = 0; h < 2; h++) {  // h = 0: bytes 0 and 2, h = 1: bytes 1 and 3
+    const uint32_t a = (aw >> (8 * h)) & 0x00FF00FFu;
+    const uint32_t c = (bw >> (8 * h)) & 0x00FF00FFu;
+    uint32_t sum = a + c;
+    hit |= ~((sum | 0x80008000u) - K1) & 0x80008000u;
+    const uint32_t inf = (((a + 0x00010001u) | (c + 0x00010001u)) >> 8) & 0x00010001u;
+    sum |= inf * 0x1FFu;  // 255 in either byte: the field is >= 511
+    const uint32_t x1 = sum ^ K1, x2 = sum ^ K2;
+    z1[h] = ~((x1 | 0x80008000u) - 0x00010001u) & 0x80008000u;
+    z2[h] = ~((x2 | 0x80008000u) - 0x00010001u) & 0x80008000u;
+  }
+  n2 = ((z1[0] >> 15) & 1u) | ((z1[1] >> 14) & 2u) | ((z1[0] >> 29) & 4u) | ((z1[1] >> 28) & 8u);
+  n1 = ((z2[0] >> 15) & 1u) | ((z2[1] >> 14) & 2u) | ((z2[0] >> 29) & 4u) | ((z2[1] >> 28) & 8u);
+}
+
 struct BpTally {
   unsigned long long direct = 0, sets = 0, checks = 0;
 };
@@ -126,22 +204,16 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
     const uint4 a = reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad)[gr];
     const uint4 b = reinterpret_cast<const uint4 *>(bp.d + (int64_t)u * bp.tpad)[gr];
     const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+    const uint32_t K1 = (uint32_t)(d + 1) * 0x00010001u, K2 = (uint32_t)(d + 2) * 0x00010001u;
+    uint32_t hit = 0;
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-#pragma unroll
-      for (int y = 0; y < 4; y++) {
-        const int dk = (aw[q] >> (8 * y)) & 0xff, du = (bw[q] >> (8 * y)) & 0xff;
-        if (dk == kInf8 || du == kInf8) continue;
-        const int sum = dk + du;
-        const uint64_t bit = 1ull << (gr * 16 + q * 4 + y);
-        if (sum <= d)
-          direct = true;
-        else if (sum - 1 == d)
-          need2 |= bit;
-        else if (sum - 2 == d)
-          need1 |= bit;
-      }
+      uint32_t n1, n2;
+      swar_word(aw[q], bw[q], K1, K2, hit, n1, n2);
+      need1 |= (uint64_t)n1 << (gr * 16 + q * 4);
+      need2 |= (uint64_t)n2 << (gr * 16 + q * 4);
     }
+    direct = hit != 0;
   }
   if (Group<G>::any(direct)) {
     if (gr == 0) tally.direct++;
@@ -186,31 +258,60 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
   return false;
 }
 
-// Normal-label test against column j of T (Section 4.5.1): is some
-// (h, delta) of L(u) with delta + T[h][j] <= d?  Stops at the first hit.
-// T is large and its cells are read at random, so a hub is looked up only
-// when its bit is set in the 256-bit signature of the root's label (held
-// in registers): most hubs of L(u) are not in L(k) and cost no T read.
+// Normal-label test against the root's table (Section 4.5.1): is some
+// (h, delta) of L(u) with delta + d(k, h) <= d?  Stops at the first step
+// that finds one.  Each lane takes U entries per step (G*U per group), so
+// their hub loads, and then their table probes, are in flight together.  A
+// hub is probed only when its bit is set in the 256-bit signature of the
+// root's label (held in registers): with short root labels most hubs of
+// L(u) cost no probe.  An empty root label prunes nothing.
 template <int G>
-__device__ __forceinline__ bool label_prunes(const DStore &st, TCol Tj, const uint64_t *sig,
+__device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, const uint64_t *sig,
                                              int32_t u, int d, int32_t *len_out) {
+  constexpr int U = 4;
+  constexpr uint32_t kNoHub = 0xFFFFFFFFu;
   const int gr = Group<G>::rank();
   const int64_t o = st.off[u];
   const int32_t len = st.len[u];
   *len_out = len;
-  if (len == 0) return false;
+  if (len == 0 || Tj.empty) return false;
+  const uint32_t *hp = st.hub + o;
+  const uint8_t *dp = st.dist + o;
   const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
   const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
-  for (int32_t base = 0; base < len; base += G) {
-    const int32_t e = base + gr;
-    bool hit = false;
-    if (e < len) {
-      const uint32_t h = st.hub[o + e];
-      const uint32_t b = sig_bit(h);
+  for (int32_t base = 0; base < len; base += G * U) {
+    uint32_t hh[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      const int32_t e = base + i * G + gr;
+      hh[i] = e < len ? hp[e] : kNoHub;
+    }
+    uint32_t slot[U];
+    bool want[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      const uint32_t b = sig_bit(hh[i]);
       const uint64_t wd = (b & 128) ? ((b & 64) ? s23.y : s23.x) : ((b & 64) ? s01.y : s01.x);
-      if ((wd >> (b & 63)) & 1ull) {
-        const int th = Tj.at(h);
-        hit = th != kInf8 && st.dist[o + e] + th <= d;
+      want[i] = hh[i] != kNoHub && ((wd >> (b & 63)) & 1ull);
+      slot[i] = ht_hash(hh[i]) & Tj.mask;
+    }
+    uint64_t ent[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) ent[i] = want[i] ? Tj.p[slot[i]] : kEmpty;
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      if (!want[i]) continue;
+      // finish the probe sequence (rarely more than one slot at load <= 1/4)
+      uint64_t e = ent[i];
+      uint32_t sl = slot[i];
+      while ((uint32_t)e != hh[i] && e != kEmpty) {
+        sl = (sl + 1) & Tj.mask;
+        e = Tj.p[sl];
+      }
+      if (e != kEmpty) {
+        const int32_t idx = base + i * G + gr;
+        hit |= (int)dp[idx] + (int)((e >> 32) & 0xFFu) <= d;
       }
     }
     if (Group<G>::any(hit)) return true;
@@ -317,7 +418,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       bool pr = bp_prunes<G>(bp, w.s + j, u, d, tally);
       if (!pr) {
         int32_t len;
-        pr = label_prunes<G>(st, t_col(w, j), w.sig + 4 * (int64_t)j, u, d, &len);
+        pr = label_prunes<G>(st, root_table(w, j), w.sig + 4 * (int64_t)j, u, d, &len);
         if (gr == 0) {
           c_test++;
           c_scan += (unsigned long long)len;
@@ -407,7 +508,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       const int32_t u = w.cu[c], j = w.cj[c];
       const int64_t e0 = g.row[u], deg = g.row[u + 1] - e0;
       const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-      const TCol Tj = t_col(w, j);
+      const RootTable Tj = root_table(w, j);
       for (int64_t e = lane_id(); e < deg; e += kWave) {
         const int32_t x = g.col[e0 + e];
         if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
@@ -523,15 +624,6 @@ __global__ void __launch_bounds__(kBlock) k_win_reset_vis(DGraph g, DWindow w, D
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_win_reset_T(DGraph g, DWindow w, DStore st) {
-  const int32_t j = blockIdx.x;
-  const int32_t k = w.s + j;
-  if (w.used[k]) return;
-  const TCol Tj = t_col(w, j);
-  const int64_t o = st.off[k];
-  const int32_t len = st.len[k];
-  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) Tj.at(st.hub[o + e]) = kInf8;
-}
 
 // Drop the window's candidates (a window is re-run smaller after an overflow).
 __global__ void __launch_bounds__(kBlock) k_win_abort(DWindow w, int64_t ncand) {
@@ -711,8 +803,11 @@ hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st) {
 }
 
 hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
-                           hipStream_t st) {
+                           int64_t *sizes, int64_t *scan_tmp, hipStream_t st) {
   if (nroots <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_win_ht_size, dim3((nroots + 1 + 255) / 256), dim3(256), 0, st, w, s, sizes);
+  hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)nroots + 1, scan_tmp, st);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_win_init, dim3(nroots), dim3(kBlock), 0, st, g, w, s, f);
   return hipGetLastError();
 }
@@ -747,7 +842,6 @@ hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t 
   if (nvisited > 0)
     hipLaunchKernelGGL(k_win_reset_vis, dim3(grid_for(nvisited, kBlock, 8192)), dim3(kBlock), 0,
                        st, g, w, f, nvisited);
-  if (nroots > 0) hipLaunchKernelGGL(k_win_reset_T, dim3(nroots), dim3(kBlock), 0, st, g, w, s);
   return hipGetLastError();
 }
 
