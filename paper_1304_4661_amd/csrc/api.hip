@@ -19,7 +19,7 @@ namespace {
 
 struct Tuning {
   int window = 16384;  // most concurrent roots of the pruned phase
-  int64_t window_work = 32000000;  // visits aimed at per window (0: fixed size)
+  int64_t window_work = 64000000;  // visits aimed at per window (0: fixed size)
   int64_t window_mem_mb = 16384;  // device memory allowed for per-root state
   int group = 4;      // lanes per frontier entry (prune tests)
   int xgroup = 16;    // lanes per candidate expanding its adjacency list
@@ -464,7 +464,7 @@ struct Builder {
     fill(soff, 0, st);
     fill(slen, 0, st);
     fill(scap, 0, st);
-    int64_t pool_cap = std::max<int64_t>(16 * (int64_t)n, 1 << 16);
+    int64_t pool_cap = std::max<int64_t>(32 * (int64_t)n, 1 << 20);
     DBuf<uint32_t> phub((size_t)pool_cap);
     DBuf<uint8_t> pdist((size_t)pool_cap);
     DBuf<unsigned long long> top(1);
@@ -478,10 +478,11 @@ struct Builder {
     DBuf<int64_t> htoff((size_t)wmax + 1), hsize((size_t)wmax + 1),
         htmp((size_t)scan_tmp_elems((int64_t)wmax + 1));
     DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words), sig((size_t)wmax * 4);
+    DBuf<uint64_t> csum((size_t)n * 4);
     fill(vis, 0, st);
-    fill(wd, 0xFF, st);
     fill(cmask, 0, st);
     fill(kmask, 0, st);
+    fill(csum, 0, st);
     const int64_t fcap = std::max<int64_t>(2 * (int64_t)n + 64,
                                            std::min<int64_t>((int64_t)wmax * n, 96ll << 20));
     const int64_t hcap = std::max<int64_t>((int64_t)n + nnz / tu.chunk + 64,
@@ -526,8 +527,8 @@ struct Builder {
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
       DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
-      DWindow w{s,     nr,    words,   vis.p, ht.p, htoff.p, htcap, sig.p, wd.p,
-                cmask.p, kmask.p, cu.p, cj.p,  cd.p, cdes.p,  ccap,  used.p};
+      DWindow w{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
+                cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, used.p};
       check(launch_win_reset_ctl(ctl.p, st));
       check(launch_win_init(graph(), w, sto, f, nr, hsize.p, htmp.p, st));
       int d = 0;
@@ -569,6 +570,11 @@ struct Builder {
         check(launch_win_reset(graph(), w, sto, f, nr, std::min(nvisited, fcap), st));
         check(launch_win_abort(graph(), w, ncand, st));
         if (h.flags & kFlagOvfFrontier) fill(vis, 0, st);
+        // candidates past the list's end set mask bits the list cannot undo
+        if (h.flags & kFlagOvfCand) {
+          fill(cmask, 0, st);
+          fill(csum, 0, st);
+        }
         check(hipStreamSynchronize(st));
         level_trace.resize(trace_mark);
         if (h.flags == kFlagOvfHash) {
@@ -586,7 +592,7 @@ struct Builder {
       // out of pool: each vertex takes at most 2*(len+new)+32 slots
       const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
       if (pool_cap - (int64_t)htop < need) {
-        const int64_t ncap = std::max<int64_t>(2 * pool_cap, (int64_t)htop + 2 * need);
+        const int64_t ncap = std::max<int64_t>(3 * pool_cap, (int64_t)htop + 2 * need);
         DBuf<uint32_t> nh((size_t)ncap);
         DBuf<uint8_t> nd((size_t)ncap);
         check(hipMemcpyAsync(nh.p, phub.p, (size_t)htop * sizeof(uint32_t),

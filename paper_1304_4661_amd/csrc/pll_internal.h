@@ -239,9 +239,11 @@ struct DWindow {
   int64_t *htoff;       // [W+1] table j at [htoff[j], htoff[j+1]), size 2^x or 0
   int64_t htcap;        // entries available at ht
   uint64_t *sig;        // [W][4] 256-bit hub signature of each root's label
-  uint8_t *wd;          // [n][words*64] distance from window root j, or 255
+  uint8_t *wd;          // [n][words*64] distance from window root j (valid
+                        // where the vertex's cmask bit j is set)
   uint64_t *cmask;      // [n][words] window roots that labeled the vertex
   uint64_t *kmask;      // [n][words] ... and whose label survived cleaning
+  uint64_t *csum;       // [n][4] bit i: word i of the vertex's cmask row is non-zero
   int32_t *cu;          // candidate vertex
   int32_t *cj;          // candidate root slot
   uint8_t *cd;          // candidate distance

@@ -430,6 +430,8 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
         w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
         atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
                  1ull << (j & 63));
+        atomicOr((unsigned long long *)&w.csum[4 * (int64_t)u + (j >> 12)],
+                 1ull << ((j >> 6) & 63));
       }
     }
     stage.push(labeled, u, j, flush);
@@ -625,13 +627,34 @@ __global__ void __launch_bounds__(kBlock) k_win_reset_vis(DGraph g, DWindow w, D
 }
 
 
-// Drop the window's candidates (a window is re-run smaller after an overflow).
+// Mask rows of a vertex hold one bit per window root; csum (4 words per
+// vertex) marks which 64-bit words of the row are non-zero, so the passes
+// below visit only those words (a vertex is labeled by few roots of a
+// window, and rows are up to 256 words long).
+__device__ __forceinline__ void csum_load(const DWindow &w, int32_t u, uint64_t sm[4]) {
+  const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(w.csum + 4 * (int64_t)u);
+  const ulonglong2 a = p[0], b = p[1];
+  sm[0] = a.x;
+  sm[1] = a.y;
+  sm[2] = b.x;
+  sm[3] = b.y;
+}
+
+// Drop the window's candidates (a window is re-run smaller after an
+// overflow), in two passes: every candidate clears its own mask word, then
+// (all words cleared) the summaries.
 __global__ void __launch_bounds__(kBlock) k_win_abort(DWindow w, int64_t ncand) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
+       c += (int64_t)gridDim.x * blockDim.x)
+    w.cmask[(int64_t)w.cu[c] * w.words + (w.cj[c] >> 6)] = 0ull;
+}
+
+__global__ void __launch_bounds__(kBlock) k_win_abort_sum(DWindow w, int64_t ncand) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
        c += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t u = w.cu[c];
-    w.wd[(int64_t)u * (w.words * 64) + w.cj[c]] = kInf8;
-    for (int i = 0; i < ((w.W + 63) >> 6); i++) w.cmask[(int64_t)u * w.words + i] = 0ull;
+    ulonglong2 *p = reinterpret_cast<ulonglong2 *>(w.csum + 4 * (int64_t)w.cu[c]);
+    p[0] = make_ulonglong2(0ull, 0ull);
+    p[1] = make_ulonglong2(0ull, 0ull);
   }
 }
 
@@ -649,27 +672,36 @@ __global__ void __launch_bounds__(kBlock) k_win_clean(DWindow w, int64_t ncand) 
     const uint8_t *wu = w.wd + (int64_t)u * (w.words * 64);
     const uint8_t *wk = w.wd + (int64_t)k * (w.words * 64);
     const int jw = j >> 6, jb = j & 63;
+    uint64_t su[4], sk[4];
+    csum_load(w, u, su);
+    csum_load(w, k, sk);
     bool drop = false;
-    for (int i = 0; i <= jw && !drop; i++) {
-      uint64_t m = cu_row[i] & ck_row[i];
-      if (i == jw) m &= jb ? (~0ull >> (64 - jb)) : 0ull;
-      while (m) {
-        const int b = __ffsll((unsigned long long)m) - 1;
-        m &= m - 1;
-        const int jj = i * 64 + b;
-        if ((int)wu[jj] + (int)wk[jj] <= d) {
-          drop = true;
-          break;
+    for (int q = 0; q <= (jw >> 6) && !drop; q++) {
+      uint64_t sm = su[q] & sk[q];
+      if (q == (jw >> 6)) sm &= (jw & 63) == 63 ? ~0ull : ((2ull << (jw & 63)) - 1);
+      while (sm && !drop) {
+        const int i = q * 64 + __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        uint64_t m = cu_row[i] & ck_row[i];
+        if (i == jw) m &= jb ? (~0ull >> (64 - jb)) : 0ull;
+        while (m) {
+          const int b = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int jj = i * 64 + b;
+          if ((int)wu[jj] + (int)wk[jj] <= d) {
+            drop = true;
+            break;
+          }
         }
       }
     }
     if (!drop)
       atomicOr((unsigned long long *)&w.kmask[(int64_t)u * w.words + jw], 1ull << jb);
     int low = -1;
-    for (int i = 0; i < ((w.W + 63) >> 6); i++) {
-      if (cu_row[i]) {
+    for (int q = 0; q < 4 && low < 0; q++) {
+      if (su[q]) {
+        const int i = q * 64 + __ffsll((unsigned long long)su[q]) - 1;
         low = i * 64 + __ffsll((unsigned long long)cu_row[i]) - 1;
-        break;
       }
     }
     w.cdes[c] = (low == j) ? 1 : 0;
@@ -695,10 +727,17 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
       u = w.cu[c];
       const uint64_t *krow = w.kmask + (int64_t)u * w.words;
       uint64_t *crow = w.cmask + (int64_t)u * w.words;
+      uint64_t su[4];
+      csum_load(w, u, su);
       int32_t total = 0;
-      for (int i = 0; i < ((w.W + 63) >> 6); i++) {
-        total += __popcll(krow[i]);
-        crow[i] = 0ull;
+      for (int q = 0; q < 4; q++) {
+        uint64_t sm = su[q];
+        while (sm) {
+          const int i = q * 64 + __ffsll((unsigned long long)sm) - 1;
+          sm &= sm - 1;
+          total += __popcll(krow[i]);
+          crow[i] = 0ull;
+        }
       }
       len = st.len[u];
       const int32_t need = len + total;
@@ -732,8 +771,7 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
 
 // Pass 2, one thread per candidate: a survivor writes (root rank, distance)
 // at its place among the vertex's new labels, in root order, so labels stay
-// sorted by hub rank (Section 4.5.1); every candidate clears its distance
-// cell of the window.
+// sorted by hub rank (Section 4.5.1).
 __global__ void __launch_bounds__(kBlock) k_win_commit_write(DWindow w, DStore st,
                                                              int64_t ncand) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
@@ -744,22 +782,45 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_write(DWindow w, DStore s
     const uint64_t kw = krow[jw];
     if ((kw >> jb) & 1ull) {
       int32_t above = __popcll(jb == 63 ? 0ull : (kw >> (jb + 1)));
-      for (int i = jw + 1; i < ((w.W + 63) >> 6); i++) above += __popcll(krow[i]);
+      uint64_t su[4];
+      csum_load(w, u, su);
+      for (int q = jw >> 6; q < 4; q++) {
+        uint64_t sm = su[q];
+        if (q == (jw >> 6)) sm &= (jw & 63) == 63 ? 0ull : (~0ull << ((jw & 63) + 1));
+        while (sm) {
+          const int i = q * 64 + __ffsll((unsigned long long)sm) - 1;
+          sm &= sm - 1;
+          above += __popcll(krow[i]);
+        }
+      }
       const int64_t o = st.off[u] + st.len[u] - 1 - above;
       st.hub[o] = (uint32_t)(w.s + j);
       st.dist[o] = w.cd[c];
     }
-    w.wd[(int64_t)u * (w.words * 64) + j] = kInf8;
   }
 }
 
-// Pass 3, one thread per touched vertex: clear its survivor mask.
+// Pass 3, one thread per touched vertex: clear its survivor mask and the
+// summary.
 __global__ void __launch_bounds__(kBlock) k_win_commit_clear(DWindow w, int64_t ncand) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
        c += (int64_t)gridDim.x * blockDim.x) {
     if (!w.cdes[c]) continue;
-    uint64_t *krow = w.kmask + (int64_t)w.cu[c] * w.words;
-    for (int i = 0; i < ((w.W + 63) >> 6); i++) krow[i] = 0ull;
+    const int32_t u = w.cu[c];
+    uint64_t *krow = w.kmask + (int64_t)u * w.words;
+    uint64_t su[4];
+    csum_load(w, u, su);
+    for (int q = 0; q < 4; q++) {
+      uint64_t sm = su[q];
+      while (sm) {
+        const int i = q * 64 + __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        krow[i] = 0ull;
+      }
+    }
+    ulonglong2 *p = reinterpret_cast<ulonglong2 *>(w.csum + 4 * (int64_t)u);
+    p[0] = make_ulonglong2(0ull, 0ull);
+    p[1] = make_ulonglong2(0ull, 0ull);
   }
 }
 
@@ -846,9 +907,11 @@ hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t 
 }
 
 hipError_t launch_win_abort(DGraph /*g*/, DWindow w, int64_t ncand, hipStream_t st) {
-  if (ncand > 0)
-    hipLaunchKernelGGL(k_win_abort, dim3(grid_for(ncand, kBlock, 8192)), dim3(kBlock), 0, st, w,
-                       ncand);
+  if (ncand > 0) {
+    const unsigned blocks = grid_for(ncand, kBlock, 8192);
+    hipLaunchKernelGGL(k_win_abort, dim3(blocks), dim3(kBlock), 0, st, w, ncand);
+    hipLaunchKernelGGL(k_win_abort_sum, dim3(blocks), dim3(kBlock), 0, st, w, ncand);
+  }
   return hipGetLastError();
 }
 
