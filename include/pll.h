@@ -274,7 +274,12 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * "window_mem_mb" (device memory the per-root window state may take; caps
  * the window at about this / (2.4 n) roots), "group" (lanes per frontier
  * entry in the prune tests: 4..64), "xgroup" (lanes per candidate expanding
- * its adjacency list: 4..64), "chunk" (edges a group expands inline before
+ * its adjacency list: 4..64), "list_cap" (upper bound on the entries of
+ * the frontier, candidate and task lists, never below what one root needs;
+ * 0 = sized from the window; a window that overflows is re-run with a
+ * quarter of the roots), "table_cap" (first size of the root-table area in
+ * entries; 0 = sized from the window; it grows when a window needs more),
+ * "chunk" (edges a group expands inline before
  * handing the rest to whole waves), "levels_per_sync" (levels launched
  * between host checks), "profile" (0/1: time every level with HIP events on
  * the build stream).  Bit-parallel phase: "bp_chunk" (adjacency entries per

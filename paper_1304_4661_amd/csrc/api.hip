@@ -21,6 +21,8 @@ struct Tuning {
   int window = 16384;  // most concurrent roots of the pruned phase
   int64_t window_work = 64000000;  // visits aimed at per window (0: fixed size)
   int64_t window_mem_mb = 16384;  // device memory allowed for per-root state
+  int64_t list_cap = 0;   // cap on frontier / candidate / task lists (0: sized from W)
+  int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
   int group = 4;      // lanes per frontier entry (prune tests)
   int xgroup = 16;    // lanes per candidate expanding its adjacency list
   int chunk = 256;    // edges expanded inline before splitting into tasks
@@ -473,7 +475,7 @@ struct Builder {
     DBuf<uint32_t> vis((size_t)wmax * nwords);
     DBuf<uint8_t> wd((size_t)n * wstride);
     // the roots' label tables: grown when a window needs more
-    int64_t htcap = std::max<int64_t>(1 << 20, 32 * (int64_t)wmax);
+    int64_t htcap = tu.table_cap > 0 ? tu.table_cap : std::max<int64_t>(1 << 20, 32 * (int64_t)wmax);
     DBuf<uint64_t> ht((size_t)htcap);
     DBuf<int64_t> htoff((size_t)wmax + 1), hsize((size_t)wmax + 1),
         htmp((size_t)scan_tmp_elems((int64_t)wmax + 1));
@@ -483,13 +485,16 @@ struct Builder {
     fill(cmask, 0, st);
     fill(kmask, 0, st);
     fill(csum, 0, st);
-    const int64_t fcap = std::max<int64_t>(2 * (int64_t)n + 64,
-                                           std::min<int64_t>((int64_t)wmax * n, 96ll << 20));
-    const int64_t hcap = std::max<int64_t>((int64_t)n + nnz / tu.chunk + 64,
-                                           std::min<int64_t>((int64_t)wmax * (nnz / tu.chunk + 1),
-                                                             16ll << 20));
+    // list capacities: sized from the window, never below what one root
+    // needs (a window of one root always fits); `list_cap` lowers them
+    const int64_t lcap = tu.list_cap > 0 ? tu.list_cap : INT64_MAX;
+    const int64_t fcap = std::max<int64_t>(
+        2 * (int64_t)n + 64, std::min<int64_t>({(int64_t)wmax * n, 96ll << 20, lcap}));
+    const int64_t hcap = std::max<int64_t>(
+        (int64_t)n + nnz / tu.chunk + 64,
+        std::min<int64_t>({(int64_t)wmax * (nnz / tu.chunk + 1), 16ll << 20, lcap}));
     const int64_t ccap = std::max<int64_t>((int64_t)n + 64,
-                                           std::min<int64_t>((int64_t)wmax * n, 32ll << 20));
+                                           std::min<int64_t>({(int64_t)wmax * n, 32ll << 20, lcap}));
     DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap), h1((size_t)hcap * 3);
     DBuf<int32_t> cu((size_t)ccap), cj((size_t)ccap);
     DBuf<uint8_t> cd((size_t)ccap), cdes((size_t)ccap);
@@ -1009,6 +1014,12 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "window_work") {
     if (value < 0 || value > (1ll << 40)) return PLL_E_INVAL;
     g_tune.window_work = value;
+  } else if (k == "list_cap") {
+    if (value < 0) return PLL_E_INVAL;
+    g_tune.list_cap = value;
+  } else if (k == "table_cap") {
+    if (value < 0) return PLL_E_INVAL;
+    g_tune.table_cap = value;
   } else if (k == "window_mem_mb") {
     if (value < 1 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.window_mem_mb = value;
@@ -1049,6 +1060,8 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "window") return g_tune.window;
   if (k == "window_work") return g_tune.window_work;
   if (k == "window_mem_mb") return g_tune.window_mem_mb;
+  if (k == "list_cap") return g_tune.list_cap;
+  if (k == "table_cap") return g_tune.table_cap;
   if (k == "group") return g_tune.group;
   if (k == "xgroup") return g_tune.xgroup;
   if (k == "chunk") return g_tune.chunk;

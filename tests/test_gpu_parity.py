@@ -85,6 +85,24 @@ def test_windows_and_groups(window, group, xgroup, work):
     assert_same_index(gx, ox, f"w{window} g{group} x{xgroup} work{work}")
 
 
+@pytest.mark.parametrize("knobs", [dict(list_cap=1, window=256, window_work=0),
+                                   dict(list_cap=1, window=16384, window_work=100000),
+                                   dict(table_cap=8, window=64, window_work=0)],
+                         ids=["lists-fixed", "lists-adaptive", "tables"])
+def test_overflow_retries(knobs):
+    # lists and root tables far too small: windows overflow and are re-run
+    # (fewer roots, or a grown table area) and the labels stay exact
+    _require_gpu()
+    g = gen.ba_graph(900, 3, 77)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, 2)
+    with Tuned(**knobs):
+        gx = binding.build(g.row_ptr, g.col, order, 2)
+    assert_same_index(gx, ox, str(knobs))
+    if "list_cap" in knobs:
+        assert gx.stats()["retries"] > 0
+
+
 def test_torch_allocator_hook():
     # builds through torch's caching allocator: same index, memory visible
     # to torch while the index lives and handed back by pll_free
