@@ -19,7 +19,7 @@ namespace {
 
 struct Tuning {
   int window = 16384;  // most concurrent roots of the pruned phase
-  int64_t window_work = 64000000;  // visits aimed at per window (0: fixed size)
+  int64_t window_work = 128000000;  // visits aimed at per window (0: fixed size)
   int64_t window_mem_mb = 16384;  // device memory allowed for per-root state
   int64_t list_cap = 0;   // cap on frontier / candidate / task lists (0: sized from W)
   int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
@@ -501,7 +501,9 @@ struct Builder {
     DBuf<LevelCtl> ctl(1);
     DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
                 nullptr, nullptr, nullptr, ctl.p};
-    DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p};
+    DBuf<uint64_t> bpz((size_t)std::max<int32_t>(n, 1));
+    check(launch_bpv_nonempty(n, t, ix->bpm.p, bpz.p, st));
+    DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
     PinnedMirror mirror;
     LevelCtl &h = mirror.p->ctl;
     unsigned long long &htop = mirror.p->top;

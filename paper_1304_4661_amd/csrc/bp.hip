@@ -178,6 +178,18 @@ __global__ void k_bpv_finish(int64_t total, uint64_t *m) {
     m[2 * x + 1] &= ~m[2 * x];
 }
 
+// Per vertex, the slots whose S^{-1} is non-empty (bit i = slot i): a set
+// check that needs S^{-1} of a vertex where it is empty cannot succeed.
+__global__ void k_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t *z) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t b = 0;
+    for (int32_t i = 0; i < t; i++)
+      if (m[2 * (v * t + i)] != 0) b |= 1ull << i;
+    z[v] = b;
+  }
+}
+
 unsigned grid_for(int64_t items, int per_block, int64_t cap) {
   int64_t bl = (items + per_block - 1) / per_block;
   if (bl < 1) bl = 1;
@@ -219,6 +231,13 @@ hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t
                      L);
   hipLaunchKernelGGL(k_bpv_commit, dim3(grid_for(g.n, kBlock, 4096)), dim3(kBlock), 0, st, g.n, b,
                      L, cnt, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t *z,
+                               hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bpv_nonempty, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, t, m, z);
   return hipGetLastError();
 }
 

@@ -164,6 +164,7 @@ struct DBp {
   int32_t t, tpad;
   const uint8_t *d;
   const uint64_t *m;
+  const uint64_t *z;  // [n] slots whose S^{-1} is non-empty (bit per slot)
 };
 // The same, writable, plus per-vertex "found at the next level" slot bits
 // used while the bit-parallel BFS runs.
@@ -292,6 +293,8 @@ hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t
                             int64_t nitems, int chunk, int L, unsigned long long *cnt,
                             int32_t *flags, hipStream_t st);
 hipError_t launch_bpv_finish(int64_t total, uint64_t *m, hipStream_t st);
+hipError_t launch_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t *z,
+                               hipStream_t st);
 
 hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
 // sizes: int64[nroots + 1]; scan_tmp: scan_tmp_elems(nroots + 1) int64

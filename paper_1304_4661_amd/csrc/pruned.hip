@@ -222,6 +222,14 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
   need1 = Group<G>::or_reduce(need1);
   need2 = Group<G>::or_reduce(need2);
   if (!(need1 | need2)) return false;
+  // -2 needs S^{-1} non-empty on both sides; -1 (with S^0 on one side)
+  // needs it on at least one
+  {
+    const uint64_t zk = bp.z[k], zu = bp.z[u];
+    need1 &= zk & zu;
+    need2 &= zk | zu;
+    if (!(need1 | need2)) return false;
+  }
   if (gr == 0) tally.sets++;
   const ulonglong2 *pk = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)k * bp.t;
   const ulonglong2 *pu = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)u * bp.t;
