@@ -204,8 +204,9 @@ enum {
   PLL_STAT_LEVEL_LAUNCHES, /* launches of the pruned-phase level kernel */
   PLL_STAT_LEVEL_NS,     /* their summed duration from HIP events, ns; only
                             with the "profile" knob set, else 0 */
-  PLL_STAT_BP_DIRECT,    /* reached neighbours that bit-parallel distances alone
-                            prune; they are not visited (counted per edge) */
+  PLL_STAT_BP_DIRECT,    /* adjacency entries whose neighbour bit-parallel
+                            distances alone prune at the next level; it is not
+                            visited through them (counted per edge) */
   PLL_STAT_BP_SETS,      /* visits whose bit-parallel test read slot sets */
   PLL_STAT_BP_CHECKS,    /* slot set pairs read by those tests */
   PLL_NSTATS

@@ -89,37 +89,39 @@ __global__ void k_win_ht_size(DWindow w, DStore st, int64_t *sizes) {
   sizes[j] = sz;
 }
 
-// Block j: root k = s + j.  Build the root's table of L(k) and the 256-bit
-// signature of its hubs, mark k visited and put (j, k) on level 0.
-// Bit-parallel roots and neighbours run no pruned BFS (they would prune
-// themselves at distance 0).  Block 0 publishes the tables' total size and
-// flags a window whose tables do not fit (it is then run again after the
-// host grows the table area).
+// Wave j (of the grid): root k = s + j.  Build the root's table of L(k)
+// and the 256-bit signature of its hubs, mark k visited and put (j, k) on
+// level 0.  Bit-parallel roots and neighbours run no pruned BFS (they would
+// prune themselves at distance 0).  The first wave publishes the tables'
+// total size and flags a window whose tables do not fit (it is then run
+// again after the host grows the table area).
 __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore st, DFrontier f) {
-  __shared__ unsigned long long s_sig[4];
-  const int32_t j = blockIdx.x;
+  const int32_t j = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (j >= w.W) return;
+  const int lane = lane_id();
   const int32_t k = w.s + j;
   const int64_t total = w.htoff[w.W];
-  if (j == 0 && threadIdx.x == 0) {
+  if (j == 0 && lane == 0) {
     f.ctl->httotal = (unsigned long long)total;
     if (total > w.htcap) atomicOr(&f.ctl->flags, kFlagOvfHash);
   }
   if (w.used[k]) {
-    if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = 0ull;
+    if (lane < 4) w.sig[4 * (int64_t)j + lane] = 0ull;
     return;
   }
-  if (threadIdx.x < 4) s_sig[threadIdx.x] = 0ull;
   const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
   const bool fits = total <= w.htcap;
   if (fits)
-    for (int64_t e = threadIdx.x; e < sz; e += blockDim.x) w.ht[a + e] = kEmpty;
-  __syncthreads();
+    for (int64_t e = lane; e < sz; e += kWave) w.ht[a + e] = kEmpty;
+  __threadfence_block();  // the wave's clears land before its inserts
   const int64_t o = st.off[k];
   const int32_t len = st.len[k];
-  for (int32_t e = threadIdx.x; e < len; e += blockDim.x) {
+  uint64_t sg[4] = {0ull, 0ull, 0ull, 0ull};
+  for (int32_t e = lane; e < len; e += kWave) {
     const uint32_t h = st.hub[o + e];
     const uint32_t b = sig_bit(h);
-    atomicOr(&s_sig[b >> 6], 1ull << (b & 63));
+#pragma unroll
+    for (int q = 0; q < 4; q++) sg[q] |= (uint32_t)q == (b >> 6) ? 1ull << (b & 63) : 0ull;
     if (!fits) continue;
     const unsigned long long ent = ((unsigned long long)st.dist[o + e] << 32) | h;
     uint32_t slot = ht_hash(h) & (uint32_t)(sz - 1);
@@ -127,9 +129,10 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
            (unsigned long long)kEmpty)
       slot = (slot + 1) & (uint32_t)(sz - 1);
   }
-  __syncthreads();
-  if (threadIdx.x < 4) w.sig[4 * (int64_t)j + threadIdx.x] = s_sig[threadIdx.x];
-  if (threadIdx.x == 0) {
+#pragma unroll
+  for (int q = 0; q < 4; q++) sg[q] = Group<kWave>::or_reduce(sg[q]);
+  if (lane < 4) w.sig[4 * (int64_t)j + lane] = lane == 0 ? sg[0] : lane == 1 ? sg[1] : lane == 2 ? sg[2] : sg[3];
+  if (lane == 0) {
     atomicOr(&w.vis[(int64_t)j * g.nwords + (k >> 5)], 1u << (k & 31));
     const unsigned long long p = atomicAdd(&f.ctl->cnt[0], 1ull);
     f.slot[p] = j;
@@ -482,16 +485,19 @@ struct FrontierFlush {
 };
 
 // One adjacency entry x of a candidate of root k (slot j) at level d: true
-// if x is claimed for level d+1, false if it was visited already or its
-// distance row prunes it (counted in `direct`).
+// if x is claimed for level d+1, false if its distance row prunes it
+// (counted in `direct`) or it was visited already.  The distance rows (t
+// bytes per vertex) mostly stay in cache while a root's visited bits are
+// spread over W·n/8 bytes, so the row test goes first and most edges never
+// touch the visited bits.
 __device__ __forceinline__ bool reach(const DBp &bp, const RootRow &rr, uint32_t *vs, int32_t x,
                                       int d, unsigned long long &direct) {
-  const uint32_t bit = 1u << (x & 31);
-  if (vs[x >> 5] & bit) return false;
   if (rr.direct(bp, x, d + 1)) {
     direct++;
     return false;
   }
+  const uint32_t bit = 1u << (x & 31);
+  if (vs[x >> 5] & bit) return false;
   return !(atomicOr(&vs[x >> 5], bit) & bit);
 }
 
@@ -877,7 +883,8 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
   hipLaunchKernelGGL(k_win_ht_size, dim3((nroots + 1 + 255) / 256), dim3(256), 0, st, w, s, sizes);
   hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)nroots + 1, scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_win_init, dim3(nroots), dim3(kBlock), 0, st, g, w, s, f);
+  hipLaunchKernelGGL(k_win_init, dim3((nroots + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
+                     0, st, g, w, s, f);
   return hipGetLastError();
 }
 
