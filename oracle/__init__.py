@@ -14,6 +14,7 @@ from .oracle import (  # noqa: F401
     build_library,
     load_variant,
     source_text,
+    paths,
     query,
     query_parts,
 )

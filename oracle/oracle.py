@@ -63,6 +63,10 @@ def _configure(lib):
         lib.orc_query_parts.restype = C.c_int
         lib.orc_root_counts.argtypes = [C.c_void_p, P, P]
         lib.orc_root_counts.restype = C.c_int
+        lib.orc_paths.argtypes = [C.c_void_p, P, C.c_int64, C.c_int32, P, P]
+        lib.orc_paths.restype = C.c_int
+        lib.orc_export_parents.argtypes = [C.c_void_p, P]
+        lib.orc_export_parents.restype = C.c_int
     return lib
 
 
@@ -110,6 +114,7 @@ class OracleIndex:
     bp_root: np.ndarray  # int32[t_bp]: rank of root, -1 if empty
     bp_nsel: np.ndarray  # int32[t_bp]
     bp_sel: np.ndarray   # int32[t_bp, 64]: ranks of chosen neighbours
+    par: np.ndarray | None = None  # uint32[entries]: parent (rank) of each entry's vertex
     counters: dict = field(default_factory=dict)
     root_visited: np.ndarray | None = None  # int32[n] per rank (pruned phase)
     root_labeled: np.ndarray | None = None  # int32[n] per rank
@@ -157,6 +162,9 @@ def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None
         bp_root=np.zeros(tb, np.int32), bp_nsel=np.zeros(tb, np.int32),
         bp_sel=np.zeros((tb, 64), np.int32), _handle=h)
     idx._lib = lib
+    idx.par = np.zeros(ne, np.uint32)
+    if ne:
+        lib.orc_export_parents(h, _ptr(idx.par))
     lib.orc_export(h, _ptr(idx.off), _ptr(idx.hub), _ptr(idx.dist), _ptr(idx.bp_d),
                    _ptr(idx.bp_m1), _ptr(idx.bp_0), _ptr(idx.rank), _ptr(idx.bp_root),
                    _ptr(idx.bp_nsel), _ptr(idx.bp_sel))
@@ -188,3 +196,16 @@ def query_parts(idx: OracleIndex, pairs) -> tuple[np.ndarray, np.ndarray]:
     if rc != 0:
         raise OracleError(rc)
     return a, b
+
+
+def paths(idx: OracleIndex, pairs, maxlen: int) -> tuple[np.ndarray, np.ndarray]:
+    """Shortest paths (input ids) of each pair: (paths[q, maxlen], lens[q]);
+    lens = D+1, 0 if unreachable, -(D+1) if maxlen is too small."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.full((len(pairs), max(maxlen, 0)), -1, np.int32)
+    lens = np.zeros(len(pairs), np.int32)
+    rc = (idx._lib or _load()).orc_paths(idx._handle, _ptr(pairs), len(pairs), int(maxlen),
+                                        _ptr(out), _ptr(lens))
+    if rc != 0:
+        raise OracleError(rc)
+    return out, lens

@@ -23,6 +23,9 @@
  *   O4  labels stored with a sentinel after the last entry (Section 4.5.2).
  *   O5  queries: bit-parallel part (Section 5.3) plus the merge join over
  *       sorted labels (Section 3.3).
+ *   O6  shortest paths (Section 7, "Shortest-Path Queries"): every label
+ *       entry (h, d) of v also keeps the parent of v in the pruned BFS tree
+ *       of h, and a path is restored by ascending those trees.
  *
  * Readings of points the paper leaves open (each one also fixed on the GPU
  * side, so both compute the same bytes):
@@ -44,6 +47,15 @@
  *   - S^0 is stored as Section 5.1 defines it (disjoint from S^{-1}); the
  *     printed Algorithm 3 alone can leave S^{-1} members in it.
  *   - Query answers are min(QUERY, 255); 255 means unreachable.
+ *   - The parent kept with (h, d) in L(v) is the vertex that first enqueued
+ *     v in the BFS from h (the root itself for its own entry; Section 7
+ *     names it the parent in the pruned BFS tree, and the printed text says
+ *     "of u" where the tree is rooted at u: the parent of v is meant).
+ *   - Bit-parallel labels keep no tree (Section 7 treats normal labels only).
+ *     When a bit-parallel slot gives the distance, the path is walked by
+ *     scanning neighbours in ascending rank: towards the root r with the
+ *     distances of the slot, towards a chosen neighbour w with w in S^{-1}
+ *     (one step closer to w per level) or S^{0} (same distance as to r).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -80,6 +92,7 @@ enum {
 typedef struct {
   uint32_t *hub; /* hub ranks, ascending, then ORC_SENTINEL */
   uint8_t *dist;
+  uint32_t *par; /* parent (rank) of this vertex in the BFS tree of the hub */
   int64_t len;   /* entries, not counting the sentinel */
   int64_t cap;
 } orc_label;
@@ -96,6 +109,9 @@ typedef struct orc_index {
   int32_t *bp_sel;    /* [t_bp][64]: ranks of S_r in bit order */
   int32_t *root_visited; /* [n]: vertices dequeued by the pruned BFS of rank k */
   int32_t *root_labeled; /* [n]: vertices it labeled (Figure 4 quantities) */
+  int32_t *ord;          /* [n]: input id of rank r */
+  int64_t *off;          /* [n+1] rank-space adjacency (kept for paths) */
+  int32_t *adj;
   int64_t cnt[ORC_NCOUNTERS];
 } orc_index;
 
@@ -106,6 +122,7 @@ static void label_free_all(orc_label *lab, int32_t n) {
   for (int32_t i = 0; i < n; i++) {
     free(lab[i].hub);
     free(lab[i].dist);
+    free(lab[i].par);
   }
   free(lab);
 }
@@ -122,11 +139,14 @@ void orc_free(orc_index *x) {
   free(x->bp_sel);
   free(x->root_visited);
   free(x->root_labeled);
+  free(x->ord);
+  free(x->off);
+  free(x->adj);
   free(x);
 }
 
-/* append (h, d) and keep the sentinel after the last entry */
-static int label_push(orc_label *L, uint32_t h, uint8_t d) {
+/* append (h, d, parent) and keep the sentinel after the last entry */
+static int label_push(orc_label *L, uint32_t h, uint8_t d, uint32_t par) {
   if (L->len + 2 > L->cap) {
     int64_t nc = L->cap ? 2 * L->cap : 4;
     uint32_t *nh = (uint32_t *)realloc(L->hub, (size_t)nc * sizeof(uint32_t));
@@ -135,13 +155,18 @@ static int label_push(orc_label *L, uint32_t h, uint8_t d) {
     uint8_t *nd = (uint8_t *)realloc(L->dist, (size_t)nc);
     if (!nd) return ORC_E_NOMEM;
     L->dist = nd;
+    uint32_t *np = (uint32_t *)realloc(L->par, (size_t)nc * sizeof(uint32_t));
+    if (!np) return ORC_E_NOMEM;
+    L->par = np;
     L->cap = nc;
   }
   L->hub[L->len] = h;
   L->dist[L->len] = d;
+  L->par[L->len] = par;
   L->len++;
   L->hub[L->len] = ORC_SENTINEL;
   L->dist[L->len] = (uint8_t)ORC_INF;
+  L->par[L->len] = ORC_SENTINEL;
   return ORC_OK;
 }
 
@@ -352,8 +377,9 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
   uint8_t *P = (uint8_t *)malloc((size_t)n);
   uint8_t *T = (uint8_t *)malloc((size_t)n);
   int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+  int32_t *PP = (int32_t *)malloc((size_t)n * sizeof(int32_t)); /* enqueuing parent */
   int rc = ORC_OK;
-  if (!P || !T || !queue) {
+  if (!P || !T || !queue || !PP) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -369,12 +395,13 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
     int64_t qh = 0, qt = 0;
     queue[qt++] = k;
     P[k] = 0;
+    PP[k] = k;
     while (qh < qt) {
       int32_t u = queue[qh++];
       int d = P[u];
       x->cnt[C_VISITED]++;
       if (pruned_at(x, k, u, d, T)) continue;
-      rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d);
+      rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);
       if (rc != ORC_OK) break;
       x->cnt[C_LABELED]++;
       if (d > x->cnt[C_MAX_DIST]) x->cnt[C_MAX_DIST] = d;
@@ -391,6 +418,7 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
           continue;
         }
         P[w] = (uint8_t)(d + 1);
+        PP[w] = u;
         queue[qt++] = w;
       }
       if (rc != ORC_OK) break;
@@ -405,6 +433,7 @@ done:
   free(P);
   free(T);
   free(queue);
+  free(PP);
   return rc;
 }
 
@@ -484,19 +513,33 @@ int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
     if (x->lab[v].cap == 0) {
       x->lab[v].hub = (uint32_t *)malloc(sizeof(uint32_t));
       x->lab[v].dist = (uint8_t *)malloc(1);
-      if (!x->lab[v].hub || !x->lab[v].dist) {
+      x->lab[v].par = (uint32_t *)malloc(sizeof(uint32_t));
+      if (!x->lab[v].hub || !x->lab[v].dist || !x->lab[v].par) {
         rc = ORC_E_NOMEM;
         goto fail;
       }
       x->lab[v].cap = 1;
       x->lab[v].hub[0] = ORC_SENTINEL;
       x->lab[v].dist[0] = (uint8_t)ORC_INF;
+      x->lab[v].par[0] = ORC_SENTINEL;
     }
   }
   x->cnt[C_N] = n;
   x->cnt[C_TBP] = t_bp;
 
-  free(off); free(adj); free(used); free(P); free(s1); free(s0);
+  /* keep the rank-space graph and the rank -> id map for path queries */
+  x->ord = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  if (!x->ord) {
+    rc = ORC_E_NOMEM;
+    goto fail;
+  }
+  for (int32_t i = 0; i < n; i++) x->ord[i] = order[i];
+  x->off = off;
+  x->adj = adj;
+  off = NULL;
+  adj = NULL;
+
+  free(used); free(P); free(s1); free(s0);
   free(q0); free(q1); free(e0); free(e1);
   *out = x;
   return ORC_OK;
@@ -615,5 +658,208 @@ int orc_root_counts(const orc_index *x, int32_t *visited, int32_t *labeled) {
   if (!x) return ORC_E_INVAL;
   if (visited && x->n) memcpy(visited, x->root_visited, (size_t)x->n * sizeof(int32_t));
   if (labeled && x->n) memcpy(labeled, x->root_labeled, (size_t)x->n * sizeof(int32_t));
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O6: shortest paths (Section 7)                                            */
+
+/* entry of hub h in L(v) (labels are sorted by hub rank), or -1 */
+static int64_t find_hub(const orc_label *L, uint32_t h) {
+  int64_t lo = 0, hi = L->len;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (L->hub[mid] < h) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < L->len && L->hub[lo] == h) ? lo : -1;
+}
+
+/* One step of a walk on bit-parallel slot i from c: the first neighbour x
+ * (ascending rank) with d(x) == dc + ddx and, when bit != 0, that bit in
+ * S^{-1}(x) (sel = 1) or S^{0}(x) (sel = 0).  -1 if there is none. */
+static int32_t bp_step(const orc_index *x, int32_t c, int32_t i, int ddx, uint64_t bit, int sel) {
+  int32_t tb = x->t_bp;
+  int dc = x->bp_d[(int64_t)c * tb + i];
+  for (int64_t j = x->off[c]; j < x->off[c + 1]; j++) {
+    int32_t y = x->adj[j];
+    if ((int)x->bp_d[(int64_t)y * tb + i] != dc + ddx) continue;
+    if (!bit) return y;
+    uint64_t m = sel ? x->bp_m1[(int64_t)y * tb + i] : x->bp_0[(int64_t)y * tb + i];
+    if (m & bit) return y;
+  }
+  return -1;
+}
+
+/* Walk from c on slot i and write the visited ranks at out[pos], out[pos +
+ * dir], ...  mode 0: towards the root (d decreases to 0); mode 1: towards
+ * neighbour w (bit) with w in S^{-1}(c) (d decreases to 1, ends at w);
+ * mode 2: towards w with w in S^{0}(c) (a step to a vertex one level closer
+ * keeps w in S^{0}; a step within the level puts w in S^{-1}, mode 1 from
+ * there).  Returns the number of vertices written, or -1. */
+static int bp_walk(const orc_index *x, int32_t c, int32_t i, uint64_t bit, int mode,
+                   int32_t *out, int pos, int dir) {
+  int32_t tb = x->t_bp;
+  int nw = 0;
+  for (;;) {
+    out[pos] = c;
+    pos += dir;
+    nw++;
+    int dc = x->bp_d[(int64_t)c * tb + i];
+    if (mode == 0) {
+      if (dc == 0) return nw;
+      c = bp_step(x, c, i, -1, 0, 0);
+    } else if (mode == 1) {
+      if (dc == 1) return nw; /* c is w: S^{-1}(w) = {w} at level 1 */
+      c = bp_step(x, c, i, -1, bit, 1);
+    } else {
+      int32_t y = bp_step(x, c, i, -1, bit, 0);
+      if (y < 0) {
+        y = bp_step(x, c, i, 0, bit, 1);
+        if (y >= 0) mode = 1;
+      }
+      c = y;
+    }
+    if (c < 0) return -1;
+  }
+}
+
+/* Shortest path from s to t (input ids) into out[0..D] as input ids.
+ * *len = D+1, 0 if t is unreachable (or 255 or more away), -(D+1) if
+ * maxlen < D+1 (nothing written).  Returns ORC_OK, or ORC_E_RANGE if a walk
+ * fails (it cannot on a correct index). */
+static int path_one(const orc_index *x, int32_t s, int32_t t, int32_t maxlen, int32_t *out,
+                    int32_t *len) {
+  int32_t rs = x->rank[s], rt = x->rank[t], tb = x->t_bp;
+  if (rs == rt) {
+    if (maxlen < 1) {
+      *len = -1;
+      return ORC_OK;
+    }
+    out[0] = s;
+    *len = 1;
+    return ORC_OK;
+  }
+  /* normal part: best hub by the merge join (first one on ties) */
+  const orc_label *A = &x->lab[rs], *B = &x->lab[rt];
+  int best_n = 1 << 20, ia = -1, ib = -1;
+  for (int64_t i = 0, j = 0;;) {
+    uint32_t ha = A->hub[i], hb = B->hub[j];
+    if (ha == hb) {
+      if (ha == ORC_SENTINEL) break;
+      int v = (int)A->dist[i] + (int)B->dist[j];
+      if (v < best_n) {
+        best_n = v;
+        ia = (int)i;
+        ib = (int)j;
+      }
+      i++;
+      j++;
+    } else if (ha < hb) {
+      i++;
+    } else {
+      j++;
+    }
+  }
+  /* bit-parallel part: best slot (lowest on ties) and its witness */
+  int best_b = 1 << 20, bi = -1, kind = 0;
+  uint64_t wbit = 0;
+  for (int32_t i = 0; i < tb; i++) {
+    uint8_t ds = x->bp_d[(int64_t)rs * tb + i], dt = x->bp_d[(int64_t)rt * tb + i];
+    if (ds == ORC_INF || dt == ORC_INF) continue;
+    uint64_t m1s = x->bp_m1[(int64_t)rs * tb + i], m0s = x->bp_0[(int64_t)rs * tb + i];
+    uint64_t m1t = x->bp_m1[(int64_t)rt * tb + i], m0t = x->bp_0[(int64_t)rt * tb + i];
+    int v = bp_slot_dist(ds, m1s, m0s, dt, m1t, m0t);
+    if (v < best_b) {
+      best_b = v;
+      bi = i;
+      kind = (int)ds + (int)dt - v;
+      uint64_t m = kind == 2 ? (m1s & m1t) : kind == 1 ? ((m1s & m0t) ? (m1s & m0t) : (m0s & m1t)) : 0;
+      wbit = m & (~m + 1); /* lowest set bit */
+    }
+  }
+  int D = best_n <= best_b ? best_n : best_b;
+  *len = 0;
+  if (D >= (int)ORC_INF) return ORC_OK;
+  if (maxlen < D + 1) {
+    *len = -(D + 1);
+    return ORC_OK;
+  }
+  int32_t *tmp = out; /* ranks first, mapped to ids at the end */
+  if (best_n <= best_b) {
+    uint32_t h = A->hub[ia];
+    int ds = A->dist[ia], dt = B->dist[ib];
+    int32_t c = rs;
+    for (int k = 0; k <= ds; k++) {
+      tmp[k] = c;
+      if (k < ds) {
+        int64_t e = find_hub(&x->lab[c], h);
+        if (e < 0) return ORC_E_RANGE;
+        c = (int32_t)x->lab[c].par[e];
+      }
+    }
+    c = rt;
+    for (int k = 0; k < dt; k++) {
+      tmp[D - k] = c;
+      int64_t e = find_hub(&x->lab[c], h);
+      if (e < 0) return ORC_E_RANGE;
+      c = (int32_t)x->lab[c].par[e];
+    }
+    if (c != (int32_t)h) return ORC_E_RANGE;
+  } else {
+    int ds = x->bp_d[(int64_t)rs * tb + bi], dt = x->bp_d[(int64_t)rt * tb + bi];
+    uint64_t m1s = x->bp_m1[(int64_t)rs * tb + bi];
+    int ms, mt; /* walk modes of the two halves */
+    if (kind == 0) {
+      ms = 0;
+      mt = 0;
+    } else if (kind == 2) {
+      ms = 1;
+      mt = 1;
+    } else if (m1s & wbit) {
+      ms = 1;
+      mt = 2;
+    } else {
+      ms = 2;
+      mt = 1;
+    }
+    /* the s half ends at the meeting vertex (r or w), written at position ls-1 */
+    int ls = ms == 1 ? ds : ds + 1;
+    int a = bp_walk(x, rs, bi, wbit, ms, tmp, 0, 1);
+    if (a != ls) return ORC_E_RANGE;
+    int lt = mt == 1 ? dt : dt + 1;
+    /* the t half, written backwards from D; its last vertex is the meeting one */
+    int b = bp_walk(x, rt, bi, wbit, mt, tmp, D, -1);
+    if (b != lt || ls + lt - 1 != D + 1) return ORC_E_RANGE;
+  }
+  for (int k = 0; k <= D; k++) out[k] = x->ord[tmp[k]];
+  *len = D + 1;
+  return ORC_OK;
+}
+
+/* Paths of q pairs: row i of paths (maxlen ids) and lens[i] as path_one. */
+int orc_paths(const orc_index *x, const int32_t *pairs, int64_t q, int32_t maxlen,
+              int32_t *paths, int32_t *lens) {
+  if (!x || q < 0 || maxlen < 0 || (q > 0 && (!pairs || !lens || (maxlen > 0 && !paths))))
+    return ORC_E_INVAL;
+  for (int64_t i = 0; i < 2 * q; i++)
+    if (pairs[i] < 0 || pairs[i] >= x->n) return ORC_E_INVAL;
+  for (int64_t i = 0; i < q; i++) {
+    int rc = path_one(x, pairs[2 * i], pairs[2 * i + 1], maxlen, paths + i * (int64_t)maxlen,
+                      &lens[i]);
+    if (rc != ORC_OK) return rc;
+  }
+  return ORC_OK;
+}
+
+/* Parents of the exported label entries (ranks), same order as orc_export. */
+int orc_export_parents(const orc_index *x, uint32_t *par) {
+  if (!x || !par) return ORC_E_INVAL;
+  int64_t e = 0;
+  for (int32_t v = 0; v < x->n; v++) {
+    const orc_label *L = &x->lab[v];
+    if (L->len) memcpy(par + e, L->par, (size_t)L->len * sizeof(uint32_t));
+    e += L->len;
+  }
   return ORC_OK;
 }

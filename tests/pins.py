@@ -185,8 +185,67 @@ def check_visited_counter(ix, g, order) -> list[str]:
     return fails
 
 
+def check_parents(ix, g, order, D) -> list[str]:
+    """Section 7: the parent kept with (h, d) in L(v) is v's predecessor in
+    the BFS tree of h -- v itself for d = 0, else a neighbour of v whose
+    plain-BFS distance to h is d - 1."""
+    fails = []
+    for r in range(ix.n):
+        a, b = int(ix.off[r]), int(ix.off[r + 1])
+        v = int(order[r])
+        nb = set(int(w) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]])
+        for h, d, p in zip(ix.hub[a:b], ix.dist[a:b], ix.par[a:b]):
+            h, d, p = int(h), int(d), int(p)
+            if d == 0:
+                if p != r:
+                    fails.append(f"rank {r}: self entry has parent {p}")
+            elif not (0 <= p < ix.n) or int(order[p]) not in nb or D[order[h], order[p]] != d - 1:
+                fails.append(f"rank {r}: entry ({h},{d}) has parent {p}")
+            if len(fails) >= 5:
+                return fails
+    return fails
+
+
+def check_paths(ix, g, order, D) -> list[str]:
+    """Paths restored from the labels (Section 7) are shortest paths: from s
+    to t along edges with d(s,t) edges; none for unreachable pairs; a row
+    too short reports -(d+1) and s = t gives [s]."""
+    n = g.n
+    if n == 0:
+        return []
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    P, L = oracle.paths(ix, pairs, n + 1)
+    fails = []
+    for i, (a, b) in enumerate(pairs):
+        d = int(D[a, b])
+        if d >= INF:
+            if L[i] != 0:
+                fails.append(f"path({a},{b}) of an unreachable pair: {L[i]}")
+        elif L[i] != d + 1:
+            fails.append(f"path({a},{b}) has {L[i]} vertices, d = {d}")
+        else:
+            p = [int(x) for x in P[i, :d + 1]]
+            if p[0] != a or p[-1] != b:
+                fails.append(f"path({a},{b}) = {p} has wrong ends")
+            for x, y in zip(p[:-1], p[1:]):
+                if y not in g.col[g.row_ptr[x]:g.row_ptr[x + 1]]:
+                    fails.append(f"path({a},{b}) = {p} uses non-edge ({x},{y})")
+                    break
+        if len(fails) >= 5:
+            return fails
+    far = np.argwhere((D >= 1) & (D < INF))
+    if len(far):
+        a, b = far[0]
+        _, L1 = oracle.paths(ix, np.array([[a, b]], np.int32), 1)
+        if L1[0] != -(int(D[a, b]) + 1):
+            fails.append(f"short row for ({a},{b}) gave {L1[0]}")
+    return fails
+
+
 ALL = (check_queries_vs_apsp, check_bp_selection, check_bp_closed_form,
-       check_canonical_labels, check_query_parts, check_visited_counter)
+       check_canonical_labels, check_query_parts, check_visited_counter,
+       check_parents, check_paths)
 
 
 def run_all(g, order, t_bp, lib=None, checks=ALL) -> list[str]:
@@ -198,7 +257,7 @@ def run_all(g, order, t_bp, lib=None, checks=ALL) -> list[str]:
             fails += c(ix, g, D)
         elif c is check_bp_selection:
             fails += c(ix, g, order)
-        elif c in (check_bp_closed_form, check_query_parts):
+        elif c in (check_bp_closed_form, check_query_parts, check_parents, check_paths):
             fails += c(ix, g, order, D)
         else:
             fails += c(ix, g, order)

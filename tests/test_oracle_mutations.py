@@ -33,8 +33,8 @@ MUTATIONS = [
     ("bit-parallel prune test strict",
      "m0u[i]) <= d) {", "m0u[i]) < d) {"),
     ("literal Algorithm 1 append: distance of the root",
-     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d);",
-     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)0);"),
+     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);",
+     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)0, (uint32_t)PP[u]);"),
     ("literal Algorithm 1 expansion: neighbours of the root",
      "      for (int64_t j = off[u]; j < off[u + 1]; j++) {\n        int32_t w = adj[j];\n        x->cnt[C_EDGES]++;",
      "      for (int64_t j = off[k]; j < off[k + 1]; j++) {\n        int32_t w = adj[j];\n        x->cnt[C_EDGES]++;"),
@@ -54,6 +54,12 @@ MUTATIONS = [
     ("S^0 left as the raw dynamic programme",
      "x->bp_0[(int64_t)v * t + slot] = s0[v] & ~s1[v];",
      "x->bp_0[(int64_t)v * t + slot] = s0[v];"),
+    ("path parent recorded as the BFS root",
+     "        PP[w] = u;\n", "        PP[w] = k;\n"),
+    ("walk towards a neighbour follows S^0 instead of S^-1",
+     "      c = bp_step(x, c, i, -1, bit, 1);\n", "      c = bp_step(x, c, i, -1, bit, 0);\n"),
+    ("bit-parallel path ignores the -1/-2 witnesses",
+     "      kind = (int)ds + (int)dt - v;\n", "      kind = 0;\n"),
     ("pruned BFS also run from bit-parallel vertices",
      "    if (used[k]) continue;\n    x->cnt[C_ROOTS]++;", "    x->cnt[C_ROOTS]++;"),
 ]

@@ -257,3 +257,57 @@ def test_ba2000_all_pairs_and_canonical():
     assert not pins.check_bp_closed_form(ix, g, order, D)
     assert not pins.check_canonical_labels(ix, g, order)
     assert not pins.check_visited_counter(ix, g, order)
+
+
+def test_ba2000_parents_and_sampled_paths():
+    # parents of every entry; paths of the benchmark pairs of the small
+    # named workload against BFS distances and edges
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ix = oracle.build(g.row_ptr, g.col, order, t_bp)
+    D = brute.apsp(g.row_ptr, g.col)
+    assert not pins.check_parents(ix, g, order, D)
+    sample = pairs[:20000]
+    P, L = oracle.paths(ix, sample, 32)
+    d = D[sample[:, 0], sample[:, 1]]
+    assert np.array_equal(L, d + 1)
+    for i in range(len(sample)):
+        p = P[i, :L[i]]
+        assert p[0] == sample[i, 0] and p[-1] == sample[i, 1]
+        for x, y in zip(p[:-1], p[1:]):
+            assert y in g.col[g.row_ptr[x]:g.row_ptr[x + 1]]
+
+
+def _bp_path_kinds(ix, pairs):
+    """Which bit-parallel case (0: via r, 1: -1, 2: -2) restores each pair
+    whose distance only a bit-parallel slot gives (normal wins ties)."""
+    a, b = oracle.query_parts(ix, pairs)
+    kinds = set()
+    for (s, t), bp, nm in zip(pairs, a, b):
+        if not bp < nm:
+            continue
+        rs, rt = ix.rank[s], ix.rank[t]
+        for i in range(ix.t_bp):
+            ds, dt = int(ix.bp_d[rs, i]), int(ix.bp_d[rt, i])
+            if ds == INF or dt == INF:
+                continue
+            m1s, m0s, m1t, m0t = (int(ix.bp_m1[rs, i]), int(ix.bp_0[rs, i]),
+                                  int(ix.bp_m1[rt, i]), int(ix.bp_0[rt, i]))
+            v = ds + dt - (2 if m1s & m1t else 1 if (m1s & m0t) | (m0s & m1t) else 0)
+            if v == bp:
+                kinds.add(ds + dt - v)
+                break
+    return kinds
+
+
+def test_paths_cover_every_bit_parallel_case():
+    # the pins above see paths restored through the root and through a
+    # chosen neighbour with both -1 and -2 (the walks of each case)
+    kinds = set()
+    for g, t in [(gen.ba_graph(300, 2, 9), 2), (graphs.grid(6, 7), 1),
+                 (graphs.erdos_renyi(120, 0.04, 5), 3), (gen.ba_graph(400, 3, 2), 1)]:
+        ix = oracle.build(g.row_ptr, g.col, gen.degree_order(g), t)
+        D = brute.apsp(g.row_ptr, g.col)
+        assert not pins.check_paths(ix, g, gen.degree_order(g), D)
+        s, u = np.meshgrid(np.arange(g.n), np.arange(g.n), indexing="ij")
+        kinds |= _bp_path_kinds(ix, np.stack([s.ravel(), u.ravel()], 1).astype(np.int32))
+    assert kinds == {0, 1, 2}
