@@ -330,6 +330,8 @@ def main():
             "query_per_s": rates, "build_s_ba2000": bt,
         }
         out["query_latency_host_us"] = lat
+        if not batch:
+            out["shortest_paths"] = path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream)
 
     binding.set_tuning("profile", 0)
     if not args.no_cpu_baseline:
@@ -339,6 +341,36 @@ def main():
             out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(out))
+
+
+def path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream, nq=100_000, max_len=32):
+    """Build with parents (Section 7) and restore nq shortest paths on the
+    device; inputs and outputs in HBM, timed with events on the stream."""
+    import torch
+
+    from paper_1304_4661_amd import binding
+
+    binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True).close()
+    t1 = time.perf_counter()
+    ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True)
+    bs = time.perf_counter() - t1
+    pairs = d_pairs[:nq].contiguous()
+    paths = torch.empty((len(pairs), max_len), dtype=torch.int32, device=pairs.device)
+    lens = torch.empty(len(pairs), dtype=torch.int32, device=pairs.device)
+    ix.query_path_device(pairs, paths, lens, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(3):
+        ix.query_path_device(pairs, paths, lens, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ix.sync()
+    ln = lens.cpu().numpy()
+    ix.close()
+    return {"build_s_with_parents": bs, "paths_per_s": 3 * len(pairs) / (e0.elapsed_time(e1) / 1e3),
+            "pairs": len(pairs), "mean_vertices": float(ln[ln > 0].mean()) if (ln > 0).any() else 0.0}
 
 
 def cpu_model():

@@ -54,6 +54,9 @@ enum {
 #define PLL_SYNC 4u        /* block until the call's device work is complete */
 #define PLL_PLAIN 8u       /* plain forms: build one root at a time (no
                               concurrent roots); query one thread per pair */
+#define PLL_PARENTS 16u    /* pll_build*: keep, with every label entry (h, d) of
+                              v, the parent of v in the pruned BFS tree of h
+                              (Section 7), plus the graph, for pll_query_path */
 
 /*
  * Device allocator for builds and indexes (process-wide; the default is
@@ -83,7 +86,7 @@ int pll_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
  *   t_bp     number of bit-parallel roots, 0..PLL_MAX_TBP (Section 5.4: the
  *            root is the lowest-rank unused vertex, its up to 64 lowest-rank
  *            unused neighbours form S_r; an exhausted slot stays empty)
- *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC, PLL_DEVICE_PTRS
+ *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC, PLL_DEVICE_PTRS, PLL_PARENTS
  *   out      receives the new index on success
  * row_ptr, col and order are host memory, or device memory under
  * PLL_DEVICE_PTRS (then they are checked by a kernel before the build, and
@@ -173,6 +176,37 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
  * Any output pointer may be NULL to skip that array.  rank: int32[n] local
  * id -> local rank.
  */
+/*
+ * Shortest paths (Section 7, "Shortest-Path Queries") of q pairs, for an
+ * index built with PLL_PARENTS (else PLL_E_UNSUPPORTED).
+ *   pairs    int32[2q] ids, as pll_query
+ *   max_len  vertices room per path (>= 0)
+ *   paths    int32[q][max_len]: row i gets the ids of a shortest path from
+ *            pairs[2i] to pairs[2i+1], both ends included
+ *   lens     int32[q]: d+1 (vertices written); 0 if unreachable or 255 or
+ *            more away (the distance query's 255); -(d+1) if max_len < d+1
+ *            (row not written); INT32_MIN only for an inconsistent index
+ * When the best common hub h of the normal labels gives the distance (ties
+ * go to it, then to the lowest hub), the path ascends the BFS trees of h
+ * from both ends.  When only a bit-parallel slot gives it (lowest slot on
+ * ties), the path is walked through neighbours in ascending rank: to the
+ * slot's root, or to its chosen neighbour w in S^{-1} / S^{0} (Section 5.1
+ * sets) of both ends.  Paths over normal labels depend on which parent a
+ * concurrent build recorded: any shortest path may come back, its length
+ * is always d+1.  Memory kinds, validation, errors and PLL_SYNC as
+ * pll_query.
+ */
+int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_t max_len,
+                   int32_t *paths, int32_t *lens, uint32_t flags, void *stream);
+
+/*
+ * Parents of one graph's label entries (index built with PLL_PARENTS, else
+ * PLL_E_UNSUPPORTED), in pll_export's entry order, as local ranks: the
+ * parent of vertex v for entry (h, d) is a neighbour of v at distance d-1
+ * from h, and v itself for d = 0.  par: host uint32[entries].
+ */
+int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par);
+
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);
 

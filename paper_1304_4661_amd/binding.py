@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpll.so")
 OK, E_INVAL, E_NOMEM, E_RANGE, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 INF = 255
 MAX_TBP = 64
-DEVICE_PTRS, VALIDATE, SYNC, PLAIN = 1, 2, 4, 8
+DEVICE_PTRS, VALIDATE, SYNC, PLAIN, PARENTS = 1, 2, 4, 8, 16
 
 STAT_NAMES = [
     "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
@@ -32,6 +32,7 @@ EXPORTED = [
     "pll_export_sizes", "pll_export", "pll_stats", "pll_level_trace", "pll_free", "pll_strerror",
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
+    "pll_query_path", "pll_export_parents",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -72,6 +73,10 @@ def _lib():
         lib.pll_export.restype = C.c_int
         lib.pll_stats.argtypes = [P, C.c_int32, P, C.c_int32]
         lib.pll_stats.restype = C.c_int
+        lib.pll_query_path.argtypes = [P, P, C.c_int64, C.c_int32, P, P, C.c_uint32, P]
+        lib.pll_query_path.restype = C.c_int
+        lib.pll_export_parents.argtypes = [P, C.c_int32, P]
+        lib.pll_export_parents.restype = C.c_int
         lib.pll_level_trace.argtypes = [P, P, C.c_int64]
         lib.pll_level_trace.restype = C.c_int64
         lib.pll_free.argtypes = [P]
@@ -209,6 +214,42 @@ class Index:
                "sizes")
         return n.value, e.value, t.value
 
+    def query_path(self, pairs, max_len: int = 64):
+        """Shortest paths (index built with parents=True): ``pairs``
+        int32[q, 2] ids -> (paths int32[q, max_len] ids, lens int32[q]);
+        lens = d+1, 0 if unreachable, -(d+1) if max_len is too small.
+        Unwritten cells are -1."""
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        paths = np.full((len(pairs), max_len), -1, np.int32)
+        lens = np.zeros(len(pairs), np.int32)
+        _check(_lib().pll_query_path(self._h, _ptr(pairs), len(pairs), int(max_len), _ptr(paths),
+                                     _ptr(lens), 0, None), "query_path")
+        return paths, lens
+
+    def query_path_device(self, pairs, paths, lens, stream=None, sync: bool = False):
+        """Device tensors (torch): ``pairs`` int32 [q, 2], ``paths`` int32
+        [q, max_len], ``lens`` int32 [q]; runs on ``stream``."""
+        import torch
+
+        assert pairs.dtype == torch.int32 and paths.dtype == torch.int32 and lens.dtype == torch.int32
+        assert pairs.is_cuda and paths.is_cuda and lens.is_cuda
+        assert pairs.is_contiguous() and paths.is_contiguous() and lens.is_contiguous()
+        q = lens.numel()
+        assert pairs.numel() == 2 * q and paths.dim() == 2 and paths.shape[0] == q
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        flags = DEVICE_PTRS | (SYNC if sync else 0)
+        _check(_lib().pll_query_path(self._h, C.c_void_p(pairs.data_ptr()), q, int(paths.shape[1]),
+                                     C.c_void_p(paths.data_ptr()), C.c_void_p(lens.data_ptr()),
+                                     flags, C.c_void_p(stream.cuda_stream)), "query_path_device")
+
+    def export_parents(self, graph: int = 0) -> np.ndarray:
+        """Parents of the exported entries of one graph, as local ranks."""
+        _, e, _ = self.sizes(graph)
+        par = np.zeros(e, np.uint32)
+        _check(_lib().pll_export_parents(self._h, int(graph), _ptr(par)), "export_parents")
+        return par
+
     def export(self, graph: int = 0) -> dict:
         """Canonical host copy of one graph: local rank order, no sentinels
         (see include/pll.h)."""
@@ -244,7 +285,8 @@ class Index:
         return {k: int(v) for k, v in zip(STAT_NAMES, c)}
 
 
-def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=None) -> Index:
+def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=None,
+                 parents: bool = False) -> Index:
     """Build from device tensors (torch, int32, contiguous, on the GPU)."""
     import torch
 
@@ -255,7 +297,7 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
         raise PllError(E_INVAL, "build_device: row_ptr length")
     if stream is None:
         stream = torch.cuda.current_stream()
-    flags = DEVICE_PTRS | (PLAIN if plain else 0)
+    flags = DEVICE_PTRS | (PLAIN if plain else 0) | (PARENTS if parents else 0)
     h = C.c_void_p()
     rc = _lib().pll_build(n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()),
                           C.c_void_p(order.data_ptr()), int(t_bp), flags,
@@ -265,12 +307,13 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
 
 
 def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
-                plain: bool = False, stream=None, device: bool = False) -> Index:
+                plain: bool = False, stream=None, device: bool = False,
+                parents: bool = False) -> Index:
     """Build the indexes of a batch of graphs (see include/pll.h).  With
     device=True, row_ptr/col/order are torch device tensors."""
     vtx_off = np.ascontiguousarray(vtx_off, dtype=np.int64)
     G = len(vtx_off) - 1
-    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0)
+    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
     h = C.c_void_p()
     if device:
         import torch
@@ -293,7 +336,7 @@ def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
 
 
 def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = False,
-          stream=None) -> Index:
+          stream=None, parents: bool = False) -> Index:
     """Build the index of one graph (host CSR and order, see include/pll.h)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -301,7 +344,7 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
     n = len(order)
     if len(row_ptr) != n + 1:
         raise PllError(E_INVAL, "build: row_ptr length")
-    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0)
+    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
     h = C.c_void_p()
     s = None if stream is None else C.c_void_p(stream.cuda_stream)
     rc = _lib().pll_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp), flags, s,

@@ -174,6 +174,13 @@ struct pll_index {
   DBuf<uint32_t> hub;
   DBuf<uint8_t> dist;
   DBuf<int32_t> err;  // sticky error of asynchronous device-pointer queries
+  // kept by builds with PLL_PARENTS: parents (layout of hub), the
+  // rank-space graph and rank -> id, for path queries
+  bool parents = false;
+  DBuf<uint32_t> par;
+  DBuf<int64_t> grow;
+  DBuf<int32_t> gcol;
+  DBuf<int32_t> ord;
   int64_t entries = 0;
   int64_t stats[PLL_NSTATS] = {};
   std::vector<int64_t> level_trace;  // pruned-phase levels, PLL_TRACE_COLS per row
@@ -191,6 +198,10 @@ struct pll_index {
     v.off = off.p;
     v.hub = hub.p;
     v.dist = dist.p;
+    v.par = par.p;
+    v.grow = grow.p;
+    v.gcol = gcol.p;
+    v.ord = ord.p;
     return v;
   }
 };
@@ -302,6 +313,7 @@ struct Builder {
   hipStream_t st;
   Tuning tu;
   bool plain;
+  bool parents = false;  // keep the BFS-tree parent of every label entry
   int32_t n, t, nwords;
   int64_t nnz;
   DBuf<int64_t> row;
@@ -467,7 +479,9 @@ struct Builder {
     fill(slen, 0, st);
     fill(scap, 0, st);
     int64_t pool_cap = std::max<int64_t>(32 * (int64_t)n, 1 << 20);
-    DBuf<uint32_t> phub((size_t)pool_cap);
+    // (buffers for parents stay unallocated, null, when they are not kept)
+    DBuf<uint32_t> phub((size_t)pool_cap), ppar;
+    if (parents) ppar.alloc((size_t)pool_cap);
     DBuf<uint8_t> pdist((size_t)pool_cap);
     DBuf<unsigned long long> top(1);
     fill(top, 0, st);
@@ -496,11 +510,15 @@ struct Builder {
     const int64_t ccap = std::max<int64_t>((int64_t)n + 64,
                                            std::min<int64_t>({(int64_t)wmax * n, 32ll << 20, lcap}));
     DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap), h1((size_t)hcap * 3);
-    DBuf<int32_t> cu((size_t)ccap), cj((size_t)ccap);
+    DBuf<int32_t> cu((size_t)ccap), cj((size_t)ccap), cpar, fpar;
+    if (parents) {
+      cpar.alloc((size_t)ccap);
+      fpar.alloc((size_t)fcap);
+    }
     DBuf<uint8_t> cd((size_t)ccap), cdes((size_t)ccap);
     DBuf<LevelCtl> ctl(1);
-    DFrontier f{fslot.p, fv.p, fcap, h1.p, h1.p + hcap, h1.p + 2 * hcap, hcap,
-                nullptr, nullptr, nullptr, ctl.p};
+    DFrontier f{fslot.p, fv.p,    fcap,    h1.p,  h1.p + hcap, h1.p + 2 * hcap, hcap,
+                nullptr, nullptr, nullptr, ctl.p, fpar.p};
     DBuf<uint64_t> bpz((size_t)std::max<int32_t>(n, 1));
     check(launch_bpv_nonempty(n, t, ix->bpm.p, bpz.p, st));
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
@@ -533,9 +551,10 @@ struct Builder {
     while (s < n) {
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
-      DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
+      DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
       DWindow w{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
-                cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, used.p};
+                cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, cpar.p,
+                used.p};
       check(launch_win_reset_ctl(ctl.p, st));
       check(launch_win_init(graph(), w, sto, f, nr, hsize.p, htmp.p, st));
       int d = 0;
@@ -600,16 +619,21 @@ struct Builder {
       const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
       if (pool_cap - (int64_t)htop < need) {
         const int64_t ncap = std::max<int64_t>(3 * pool_cap, (int64_t)htop + 2 * need);
-        DBuf<uint32_t> nh((size_t)ncap);
+        DBuf<uint32_t> nh((size_t)ncap), np;
+        if (parents) np.alloc((size_t)ncap);
         DBuf<uint8_t> nd((size_t)ncap);
         check(hipMemcpyAsync(nh.p, phub.p, (size_t)htop * sizeof(uint32_t),
                              hipMemcpyDeviceToDevice, st));
         check(hipMemcpyAsync(nd.p, pdist.p, (size_t)htop, hipMemcpyDeviceToDevice, st));
+        if (parents)
+          check(hipMemcpyAsync(np.p, ppar.p, (size_t)htop * sizeof(uint32_t),
+                               hipMemcpyDeviceToDevice, st));
         check(hipStreamSynchronize(st));
         phub = std::move(nh);
         pdist = std::move(nd);
+        ppar = std::move(np);
         pool_cap = ncap;
-        sto = DStore{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
+        sto = DStore{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
       }
       check(launch_win_reset(graph(), w, sto, f, nr, nvisited, st));
       check(launch_win_clean(w, ncand, st));
@@ -654,8 +678,9 @@ struct Builder {
     check(hipStreamSynchronize(st));
     ix->hub.alloc((size_t)std::max<int64_t>(total, 1));
     ix->dist.alloc((size_t)std::max<int64_t>(total, 1));
-    DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap};
-    check(launch_final_copy(sto, ix->off.p, ix->hub.p, ix->dist.p, n, st));
+    if (parents) ix->par.alloc((size_t)std::max<int64_t>(total, 1));
+    DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
+    check(launch_final_copy(sto, ix->off.p, ix->hub.p, ix->dist.p, ix->par.p, n, st));
     check(hipStreamSynchronize(st));
     ix->entries = total - n;
   }
@@ -671,6 +696,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   b.st = st;
   b.tu = tuning();
   b.plain = (flags & PLL_PLAIN) != 0;
+  b.parents = (flags & PLL_PARENTS) != 0;
   b.G = G;
   b.vtx_off = vtx_off;
   if (d_vtx_off && d_vtx_off->p) b.d_vtx_off = std::move(*d_vtx_off);
@@ -687,6 +713,13 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   const auto t2 = Clock::now();
   b.pruned(ix);
   const int64_t pr_ns = ns_since(t2);
+  if (b.parents) {
+    ix->parents = true;
+    ix->grow = std::move(b.row);
+    ix->gcol = std::move(b.col);
+    ix->ord.alloc((size_t)std::max<int32_t>(n, 1));
+    check(launch_invert_rank(ix->rank.p, ix->ord.p, n, st));
+  }
   ix->err.alloc(1);
   check(hipMemsetAsync(ix->err.p, 0, sizeof(int32_t), st));
   {
@@ -723,7 +756,9 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   S[PLL_STAT_LEVELS] = b.stat_levels;
   S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->rgid.bytes() + ix->bpd.bytes() +
                                       ix->bpm.bytes() +
-                                      ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes());
+                                      ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes() +
+                                      ix->par.bytes() + ix->grow.bytes() + ix->gcol.bytes() +
+                                      ix->ord.bytes());
   S[PLL_STAT_BP_NS] = bp_ns;
   S[PLL_STAT_PRUNED_NS] = pr_ns;
   S[PLL_STAT_NORMAL_TESTS] = b.stat_tests;
@@ -923,6 +958,78 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
   if (entries) *entries = idx->g_entries.empty() ? 0 : idx->g_entries[graph];
   if (t_bp) *t_bp = idx->t;
   return PLL_OK;
+}
+
+int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_t max_len,
+                   int32_t *paths, int32_t *lens, uint32_t flags, void *stream) {
+  if (!idx || q < 0 || max_len < 0) return PLL_E_INVAL;
+  if (!idx->parents) return PLL_E_UNSUPPORTED;
+  if (q == 0) return PLL_OK;
+  if (!pairs || !lens || (max_len > 0 && !paths)) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
+  if (!(flags & PLL_DEVICE_PTRS)) {
+    for (int64_t i = 0; i < 2 * q; i++)
+      if (pairs[i] < 0 || pairs[i] >= idx->n) return PLL_E_INVAL;
+    return guarded([&] {
+      const size_t cells = (size_t)q * (size_t)max_len;
+      DBuf<int32_t> dp((size_t)(2 * q)), dpath(std::max<size_t>(cells, 1)), dlen((size_t)q);
+      h2d(dp.p, pairs, (size_t)(2 * q), st);
+      // rows the kernel leaves alone come back unchanged
+      if (cells) h2d(dpath.p, paths, cells, st);
+      check(launch_query_path(idx->view(), dp.p, q, max_len, dpath.p, dlen.p, nullptr, st));
+      d2h(lens, dlen.p, (size_t)q, st);
+      if (cells) d2h(paths, dpath.p, cells, st);
+      check(hipStreamSynchronize(st));
+      return PLL_OK;
+    });
+  }
+  return guarded([&] {
+    int32_t *err = nullptr;
+    check(hipMallocAsync((void **)&err, sizeof(int32_t), st));
+    check(hipMemsetAsync(err, 0, sizeof(int32_t), st));
+    check(launch_validate_pairs(pairs, q, idx->n, err, st));
+    check(launch_query_path(idx->view(), pairs, q, max_len, paths, lens, err, st));
+    int32_t herr = 0;
+    if (flags & PLL_SYNC) {
+      check(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      check(hipFreeAsync(err, st));
+      check(hipStreamSynchronize(st));
+      return herr ? PLL_E_INVAL : PLL_OK;
+    }
+    check(launch_or_flag(err, idx->err.p, st));
+    check(hipFreeAsync(err, st));
+    return PLL_OK;
+  });
+}
+
+int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
+  if (!idx || graph < 0 || graph >= idx->G || !par) return PLL_E_INVAL;
+  if (!idx->parents) return PLL_E_UNSUPPORTED;
+  return guarded([&] {
+    const int64_t g0 = idx->vtx_off[graph];
+    const int64_t ng = idx->vtx_off[graph + 1] - g0;
+    const int32_t gp = idx->gpos[graph];
+    hipStream_t st = nullptr;
+    std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
+    for (int64_t l = 0; l < ng; l++) {
+      rows[l] = idx->lbase[l] + gp;
+      oo[l + 1] = oo[l] + idx->hoff[rows[l] + 1] - 1 - idx->hoff[rows[l]];
+    }
+    const int64_t ne = oo[ng];
+    if (ne == 0) return PLL_OK;
+    DBuf<int64_t> drows((size_t)ng), doo((size_t)ng + 1);
+    h2d(drows.p, rows.data(), (size_t)ng, st);
+    h2d(doo.p, oo.data(), (size_t)ng + 1, st);
+    DBuf<uint32_t> op((size_t)ne);
+    DBuf<uint8_t> od((size_t)ne);
+    // same gather as the hubs: parents are global ranks too
+    check(launch_gather_labels(drows.p, ng, idx->off.p, idx->par.p, idx->dist.p, idx->lrank.p,
+                               doo.p, op.p, od.p, st));
+    d2h(par, op.p, (size_t)ne, st);
+    check(hipStreamSynchronize(st));
+    return PLL_OK;
+  });
 }
 
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,

@@ -1,0 +1,259 @@
+// Shortest-path queries (Section 7, "Shortest-Path Queries"): every label
+// entry (h, d) of v keeps the parent of v in the pruned BFS tree of h, so a
+// path through the best common hub h is restored by ascending both trees.
+// Bit-parallel labels keep no tree; when a bit-parallel slot gives the
+// distance, the path is walked through neighbours in ascending rank with
+// the slot's distances and sets, always to the lowest-rank neighbour that
+// fits: towards the root r (distance one less per step), towards a chosen
+// neighbour w in S^{-1} (w stays in S^{-1} one level closer), or towards w
+// in S^{0} (w in S^{0} one level closer, or in S^{-1} within the same level,
+// then on as before).
+//
+// One wave per pair: the label merge and the tree ascent run on one lane,
+// the neighbour scans of the bit-parallel walks on all 64.
+#include <climits>
+
+#include "pll_internal.h"
+
+namespace pll {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_invert_rank(const int32_t *rank, int32_t *ord, int32_t n) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x)
+    ord[rank[v]] = (int32_t)v;
+}
+
+// entry of hub h in the label of rank c (sorted by hub rank), or -1
+__device__ int64_t find_hub(const DIndex &ix, int32_t c, uint32_t h) {
+  int64_t lo = ix.off[c], hi = ix.off[c + 1] - 1;  // sentinel excluded
+  const int64_t end = hi;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (ix.hub[mid] < h)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < end && ix.hub[lo] == h) ? lo : -1;
+}
+
+// Lowest-rank neighbour y of c with bit-parallel distance `want` in slot i
+// and, when bit != 0, that bit in S^{-1}(y) (sel = 0) or S^{0}(y) (sel = 1);
+// -1 if none.  The rank-space rows keep the input's neighbour order, so the
+// whole row is scanned.  Called by the whole wave.
+__device__ int32_t bp_scan(const DIndex &ix, int32_t c, int32_t i, int want, uint64_t bit,
+                           int sel) {
+  const int64_t a = ix.grow[c], b = ix.grow[c + 1];
+  int best = INT_MAX;
+  for (int64_t e0 = a; e0 < b; e0 += kWave) {
+    const int64_t e = e0 + lane_id();
+    int y = INT_MAX;
+    if (e < b) {
+      const int32_t x = ix.gcol[e];
+      bool ok = (int)ix.bpd[(int64_t)x * ix.tpad + i] == want;
+      if (ok && bit) ok = (ix.bpm[2 * ((int64_t)x * ix.t + i) + sel] & bit) != 0;
+      if (ok) y = x;
+    }
+    y = Group<kWave>::min_reduce(y);
+    best = y < best ? y : best;
+  }
+  return best == INT_MAX ? -1 : best;
+}
+
+// Walk from c on slot i (modes above: 0 to r, 1 to w in S^{-1}, 2 to w in
+// S^{0}), writing ids at out[pos], out[pos + dir], ...  Returns the
+// vertices written or -1.  Called by the whole wave.
+__device__ int bp_walk(const DIndex &ix, int32_t c, int32_t i, uint64_t bit, int mode,
+                       int32_t *out, int pos, int dir) {
+  int nw = 0;
+  for (int guard = 0; guard < 2 * (int)kInf8 + 4; guard++) {
+    if (lane_id() == 0) out[pos] = ix.ord[c];
+    pos += dir;
+    nw++;
+    const int dc = ix.bpd[(int64_t)c * ix.tpad + i];
+    int32_t y;
+    if (mode == 0) {
+      if (dc == 0) return nw;
+      y = bp_scan(ix, c, i, dc - 1, 0, 0);
+    } else if (mode == 1) {
+      if (dc == 1) return nw;  // c is w: S^{-1}(w) = {w} at level 1
+      y = bp_scan(ix, c, i, dc - 1, bit, 0);
+    } else {
+      y = bp_scan(ix, c, i, dc - 1, bit, 1);
+      if (y < 0) {
+        y = bp_scan(ix, c, i, dc, bit, 0);
+        if (y >= 0) mode = 1;
+      }
+    }
+    if (y < 0) return -1;
+    c = y;
+  }
+  return -1;
+}
+
+__global__ void __launch_bounds__(kBlock) k_query_path(DIndex ix, const int32_t *pairs, int64_t q,
+                                                       int32_t maxlen, int32_t *paths,
+                                                       int32_t *lens, const int32_t *err) {
+  if (err && *err) return;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  for (int64_t pi = wid; pi < q; pi += nw) {
+    const int32_t s = pairs[2 * pi], t = pairs[2 * pi + 1];
+    const int32_t rs = ix.rank[s], rt = ix.rank[t];
+    int32_t *out = paths + pi * (int64_t)maxlen;
+    if (ix.rgid && ix.rgid[rs] != ix.rgid[rt]) {
+      if (lane == 0) lens[pi] = 0;
+      continue;
+    }
+    if (rs == rt) {
+      if (lane == 0) {
+        if (maxlen >= 1) out[0] = s;
+        lens[pi] = maxlen >= 1 ? 1 : -1;
+      }
+      continue;
+    }
+    // normal part: best common hub, first on ties (one lane)
+    int bn = 1 << 20;
+    int64_t ia = -1, ib = -1;
+    if (lane == 0) {
+      int64_t i = ix.off[rs], j = ix.off[rt];
+      for (;;) {
+        const uint32_t ha = ix.hub[i], hb = ix.hub[j];
+        if (ha == hb) {
+          if (ha == kSentinel) break;
+          const int v = (int)ix.dist[i] + (int)ix.dist[j];
+          if (v < bn) {
+            bn = v;
+            ia = i;
+            ib = j;
+          }
+          i++;
+          j++;
+        } else if (ha < hb) {
+          i++;
+        } else {
+          j++;
+        }
+      }
+    }
+    bn = __shfl(bn, 0);
+    ia = __shfl(ia, 0);
+    ib = __shfl(ib, 0);
+    // bit-parallel part: lane = slot; lowest slot on ties
+    int key = INT_MAX, kind = 0;
+    uint64_t wb = 0;
+    if (lane < ix.t) {
+      const int ds = ix.bpd[(int64_t)rs * ix.tpad + lane], dt = ix.bpd[(int64_t)rt * ix.tpad + lane];
+      if (ds != kInf8 && dt != kInf8) {
+        const uint64_t m1s = ix.bpm[2 * ((int64_t)rs * ix.t + lane)];
+        const uint64_t m0s = ix.bpm[2 * ((int64_t)rs * ix.t + lane) + 1];
+        const uint64_t m1t = ix.bpm[2 * ((int64_t)rt * ix.t + lane)];
+        const uint64_t m0t = ix.bpm[2 * ((int64_t)rt * ix.t + lane) + 1];
+        uint64_t m = 0;
+        if (m1s & m1t) {
+          kind = 2;
+          m = m1s & m1t;
+        } else if ((m1s & m0t) | (m0s & m1t)) {
+          kind = 1;
+          m = (m1s & m0t) ? (m1s & m0t) : (m0s & m1t);
+        }
+        wb = m & (~m + 1);
+        key = (ds + dt - kind) * 64 + lane;
+      }
+    }
+    const int best = Group<kWave>::min_reduce(key);
+    const int bi = best == INT_MAX ? -1 : (best & 63);
+    const int bb = best == INT_MAX ? (1 << 20) : (best >> 6);
+    kind = __shfl(kind, bi < 0 ? 0 : bi);
+    wb = __shfl(wb, bi < 0 ? 0 : bi);
+    const int D = bn <= bb ? bn : bb;
+    if (D >= (int)kInf8) {
+      if (lane == 0) lens[pi] = 0;
+      continue;
+    }
+    if (maxlen < D + 1) {
+      if (lane == 0) lens[pi] = -(D + 1);
+      continue;
+    }
+    bool ok = true;
+    if (bn <= bb) {
+      // ascend the BFS tree of h from s (positions 0..ds) and from t
+      // (positions D down to ds+1)
+      if (lane == 0) {
+        const uint32_t h = ix.hub[ia];
+        const int ds = ix.dist[ia], dt = ix.dist[ib];
+        int32_t c = rs;
+        for (int k = 0; k <= ds && ok; k++) {
+          out[k] = ix.ord[c];
+          if (k < ds) {
+            const int64_t e = find_hub(ix, c, h);
+            if (e < 0) ok = false;
+            else c = (int32_t)ix.par[e];
+          }
+        }
+        c = rt;
+        for (int k = 0; k < dt && ok; k++) {
+          out[D - k] = ix.ord[c];
+          const int64_t e = find_hub(ix, c, h);
+          if (e < 0) ok = false;
+          else c = (int32_t)ix.par[e];
+        }
+        if (c != (int32_t)h) ok = false;
+      }
+      ok = __shfl(ok ? 1 : 0, 0) != 0;
+    } else {
+      const int ds = ix.bpd[(int64_t)rs * ix.tpad + bi], dt = ix.bpd[(int64_t)rt * ix.tpad + bi];
+      const uint64_t m1s = ix.bpm[2 * ((int64_t)rs * ix.t + bi)];
+      int ms, mt;
+      if (kind == 0) {
+        ms = 0;
+        mt = 0;
+      } else if (kind == 2) {
+        ms = 1;
+        mt = 1;
+      } else if (m1s & wb) {
+        ms = 1;
+        mt = 2;
+      } else {
+        ms = 2;
+        mt = 1;
+      }
+      const int ls = ms == 1 ? ds : ds + 1, lt = mt == 1 ? dt : dt + 1;
+      const int a = bp_walk(ix, rs, bi, wb, ms, out, 0, 1);
+      const int b = bp_walk(ix, rt, bi, wb, mt, out, D, -1);
+      ok = a == ls && b == lt && ls + lt - 1 == D + 1;
+    }
+    if (lane == 0) lens[pi] = ok ? D + 1 : INT_MIN;
+  }
+}
+
+unsigned grid_for(int64_t items, int per_block, int64_t cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_invert_rank(const int32_t *rank, int32_t *ord, int32_t n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_invert_rank, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, rank, ord,
+                       n);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_path(DIndex ix, const int32_t *pairs, int64_t q, int32_t maxlen,
+                             int32_t *paths, int32_t *lens, const int32_t *err, hipStream_t st) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query_path, dim3(grid_for(q * kWave, kBlock, 4096)), dim3(kBlock), 0, st,
+                     ix, pairs, q, maxlen, paths, lens, err);
+  return hipGetLastError();
+}
+
+}  // namespace pll

@@ -48,15 +48,19 @@ __device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *ct
 template <int CAP>
 struct WaveStage {
   int32_t *a, *b;  // this wave's LDS arrays, CAP entries each
+  int32_t *c;      // optional third array (null: not staged)
   int n;           // entries staged (wave-uniform)
-  __device__ __forceinline__ void init(int32_t *aa, int32_t *bb) {
+  __device__ __forceinline__ void init(int32_t *aa, int32_t *bb, int32_t *cc = nullptr) {
     a = aa;
     b = bb;
+    c = cc;
     n = 0;
   }
-  // stage (va, vb) from each lane with pred; flush first if it might not fit
+  // stage (va, vb[, vc]) from each lane with pred; flush first if it might
+  // not fit
   template <typename F>
-  __device__ __forceinline__ void push(bool pred, int32_t va, int32_t vb, F &&flush) {
+  __device__ __forceinline__ void push(bool pred, int32_t va, int32_t vb, F &&flush,
+                                       int32_t vc = 0) {
     const uint64_t m = __ballot(pred);
     if (!m) return;
     if (n + kWave > CAP) {
@@ -67,6 +71,7 @@ struct WaveStage {
       const int pos = n + __popcll(m & lanes_below_mask());
       a[pos] = va;
       b[pos] = vb;
+      if (c) c[pos] = vc;
     }
     n += __popcll(m);
   }
@@ -218,6 +223,7 @@ struct DStore {
   uint8_t *dist;
   unsigned long long *top;  // pool bump pointer (device)
   int64_t pool_cap;
+  uint32_t *par;  // parent of the vertex in the hub's BFS tree (null: not kept)
 };
 
 // Frontier and task buffers shared by both BFS phases.
@@ -229,6 +235,7 @@ struct DFrontier {
   int64_t hcap;
   int32_t *h2slot, *h2v, *h2chunk;
   LevelCtl *ctl;
+  int32_t *par;  // [cap] vertex that reached each entry (null: not kept)
 };
 
 // State of one window of concurrently processed roots [s, s + W).
@@ -250,6 +257,7 @@ struct DWindow {
   uint8_t *cd;          // candidate distance
   uint8_t *cdes;        // 1 if this candidate commits its vertex's row
   int64_t ccap;
+  int32_t *cp;          // candidate's parent in the root's BFS tree (null: not kept)
   const uint8_t *used;  // [n] 1 for bit-parallel roots and neighbours
 };
 
@@ -311,7 +319,7 @@ hipError_t launch_win_clean(DWindow w, int64_t ncand, hipStream_t st);
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
-                             int32_t n, hipStream_t st);
+                             uint32_t *fpar, int32_t n, hipStream_t st);
 
 // Queries: ranks of ids, bit-parallel labels, final CSR labels with sentinel.
 struct DIndex {
@@ -324,6 +332,12 @@ struct DIndex {
   const int64_t *off;
   const uint32_t *hub;
   const uint8_t *dist;
+  // kept by builds with PLL_PARENTS (else null): parent of each entry's
+  // vertex in the hub's BFS tree, the rank-space graph, rank -> id
+  const uint32_t *par;
+  const int64_t *grow;
+  const int32_t *gcol;
+  const int32_t *ord;
 };
 hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err,
                                  hipStream_t st);
@@ -332,6 +346,12 @@ hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out
                         const int32_t *err, bool plain, int qgroup, hipStream_t st);
 
 // export of one graph (rows = its global ranks in local rank order)
+hipError_t launch_invert_rank(const int32_t *rank, int32_t *ord, int32_t n, hipStream_t st);
+// Shortest paths of q pairs (ids): row i of paths (maxlen ids) and lens[i]
+// (D+1; 0 unreachable; -(D+1) if maxlen is too small; INT32_MIN if the
+// index is inconsistent).  err as launch_query.
+hipError_t launch_query_path(DIndex ix, const int32_t *pairs, int64_t q, int32_t maxlen,
+                             int32_t *paths, int32_t *lens, const int32_t *err, hipStream_t st);
 hipError_t launch_gather_labels(const int64_t *rows, int64_t m, const int64_t *src_off,
                                 const uint32_t *hub, const uint8_t *dist, const int32_t *lrank,
                                 const int64_t *out_off, uint32_t *out_hub, uint8_t *out_dist,

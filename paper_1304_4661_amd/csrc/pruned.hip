@@ -137,6 +137,7 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
     const unsigned long long p = atomicAdd(&f.ctl->cnt[0], 1ull);
     f.slot[p] = j;
     f.v[p] = k;
+    if (f.par) f.par[p] = k;
   }
 }
 
@@ -387,6 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
                                                      DFrontier f, int d) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
+  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
   const unsigned long long nbase = beg + cnt;
@@ -399,8 +401,8 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv]);
-  // candidates (u, j): reserve list slots and write them
+  stage.init(s_a[wv], s_b[wv], w.cp ? s_c[wv] : nullptr);
+  // candidates (u, j[, parent]): reserve list slots and write them
   auto flush = [&](WaveStage<kStage> &sg) {
     const unsigned long long c0 = sg.reserve(&ctl->ccnt);
     for (int i = lane_id(); i < sg.n; i += kWave) {
@@ -409,6 +411,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
         w.cu[c] = sg.a[i];
         w.cj[c] = sg.b[i];
         w.cd[c] = (uint8_t)d;
+        if (sg.c) w.cp[c] = sg.c[i];
       } else {
         atomicOr(&ctl->flags, kFlagOvfCand);
       }
@@ -420,10 +423,11 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
     const int64_t p = base + lane_id() / G;
     bool labeled = false;
-    int32_t u = 0, j = 0;
+    int32_t u = 0, j = 0, par = 0;
     if (p < (int64_t)cnt) {
       j = f.slot[beg + p];
       u = f.v[beg + p];
+      if (f.par) par = f.par[beg + p];
       if (gr == 0) c_visit++;
       // bit-parallel labels first (Section 5.4)
       bool pr = bp_prunes<G>(bp, w.s + j, u, d, tally);
@@ -445,7 +449,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
                  1ull << ((j >> 6) & 63));
       }
     }
-    stage.push(labeled, u, j, flush);
+    stage.push(labeled, u, j, flush, par);
   }
   if (stage.n) flush(stage);
   c_visit = Group<kWave>::sum_reduce(c_visit);
@@ -477,6 +481,7 @@ struct FrontierFlush {
       if (q < (unsigned long long)f.cap) {
         f.slot[q] = sg.a[i];
         f.v[q] = sg.b[i];
+        if (sg.c) f.par[q] = sg.c[i];
       } else {
         atomicOr(&ctl->flags, kFlagOvfFrontier);
       }
@@ -506,6 +511,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
                                                        DFrontier f, int d, int chunk) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
+  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
@@ -534,7 +540,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
     return;
   }
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv]);
+  stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
   unsigned long long c_edge = 0, c_direct = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
@@ -563,7 +569,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
         x = g.col[e0 + idx];
         claimed = reach(bp, rr, vs, x, d, c_direct);
       }
-      stage.push(claimed, j, x, flush);
+      stage.push(claimed, j, x, flush, u);
     }
     if (act && deg > lim) {
       const int64_t extra = (deg - lim + chunk - 1) / chunk;
@@ -592,6 +598,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
                                                       int d, int chunk, int lim_inline) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
+  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long ntask = ctl->hcnt[d];
   if (ntask == 0 || (ctl->flags & kOverflowFlags)) return;
@@ -601,7 +608,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv]);
+  stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
   unsigned long long c_edge = 0, c_direct = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
@@ -621,7 +628,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
         x = g.col[e];
         claimed = reach(bp, rr, vs, x, d, c_direct);
       }
-      stage.push(claimed, j, x, flush);
+      stage.push(claimed, j, x, flush, u);
     }
   }
   if (stage.n) flush(stage);
@@ -774,6 +781,7 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
       for (int32_t e = lane_id(); e < ln; e += kWave) {
         st.hub[dn + e] = st.hub[so + e];
         st.dist[dn + e] = st.dist[so + e];
+        if (st.par) st.par[dn + e] = st.par[so + e];
       }
     }
     if (reloc) {
@@ -810,6 +818,7 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_write(DWindow w, DStore s
       const int64_t o = st.off[u] + st.len[u] - 1 - above;
       st.hub[o] = (uint32_t)(w.s + j);
       st.dist[o] = w.cd[c];
+      if (st.par) st.par[o] = (uint32_t)w.cp[c];
     }
   }
 }
@@ -846,7 +855,8 @@ __global__ void k_final_count(const int32_t *len, int64_t *cnt, int32_t n) {
 // One wave per vertex: copy its label into the final CSR and close it with
 // the storage-only sentinel (Section 4.5.2).
 __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t *foff,
-                                                       uint32_t *fhub, uint8_t *fdist, int32_t n) {
+                                                       uint32_t *fhub, uint8_t *fdist,
+                                                       uint32_t *fpar, int32_t n) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t r = wid; r < n; r += nw) {
@@ -855,10 +865,12 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t 
     for (int32_t e = lane_id(); e < len; e += kWave) {
       fhub[fo + e] = st.hub[o + e];
       fdist[fo + e] = st.dist[o + e];
+      if (fpar) fpar[fo + e] = st.par[o + e];
     }
     if (lane_id() == 0) {
       fhub[fo + len] = kSentinel;
       fdist[fo + len] = kInf8;
+      if (fpar) fpar[fo + len] = kSentinel;
     }
   }
 }
@@ -952,10 +964,10 @@ hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipSt
 }
 
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
-                             int32_t n, hipStream_t st) {
+                             uint32_t *fpar, int32_t n, hipStream_t st) {
   if (n > 0)
     hipLaunchKernelGGL(k_final_copy, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
-                       dim3(kBlock), 0, st, s, foff, fhub, fdist, n);
+                       dim3(kBlock), 0, st, s, foff, fhub, fdist, fpar, n);
   return hipGetLastError();
 }
 

@@ -66,6 +66,15 @@ def test_set_allocator_arguments():
     assert lib.pll_set_allocator(None, None, None) == binding.OK
 
 
+def test_path_queries_reject_bad_arguments():
+    lib = binding.library()
+    lens = np.zeros(1, np.int32)
+    pairs = np.zeros(2, np.int32)
+    assert lib.pll_query_path(None, pairs.ctypes.data, 1, 4, None, lens.ctypes.data, 0,
+                              None) == binding.E_INVAL
+    assert lib.pll_export_parents(None, 0, lens.ctypes.data) == binding.E_INVAL
+
+
 def test_level_trace_rejects_null():
     lib = binding.library()
     assert lib.pll_level_trace(None, None, 0) == binding.E_INVAL
