@@ -8,13 +8,16 @@ GPU library.
 """
 from .oracle import (  # noqa: F401
     COUNTER_NAMES,
+    DirectedIndex,
     OracleError,
     OracleIndex,
     build,
+    build_directed,
     build_library,
     load_variant,
     source_text,
     paths,
     query,
+    query_directed,
     query_parts,
 )

@@ -67,6 +67,10 @@ def _configure(lib):
         lib.orc_paths.restype = C.c_int
         lib.orc_export_parents.argtypes = [C.c_void_p, P]
         lib.orc_export_parents.restype = C.c_int
+        lib.orc_build_directed.argtypes = [C.c_int32, P, P, P, C.POINTER(C.c_void_p)]
+        lib.orc_build_directed.restype = C.c_int
+        lib.orc_export_in.argtypes = [C.c_void_p, P, P, P, P]
+        lib.orc_export_in.restype = C.c_int
     return lib
 
 
@@ -209,3 +213,75 @@ def paths(idx: OracleIndex, pairs, maxlen: int) -> tuple[np.ndarray, np.ndarray]
     if rc != 0:
         raise OracleError(rc)
     return out, lens
+
+
+@dataclass
+class DirectedIndex:
+    """Exported oracle index of a directed graph (Section 7): L_OUT and L_IN
+    in rank order, no sentinels."""
+    n: int
+    rank: np.ndarray
+    out_off: np.ndarray
+    out_hub: np.ndarray
+    out_dist: np.ndarray
+    in_off: np.ndarray
+    in_hub: np.ndarray
+    in_dist: np.ndarray
+    counters: dict = field(default_factory=dict)
+    _handle: C.c_void_p | None = None
+    _lib: object = None
+
+    def close(self):
+        if self._handle is not None:
+            (self._lib or _load()).orc_free(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_directed(row_ptr, col, order, lib=None) -> DirectedIndex:
+    """Labels of a directed graph given by its out-edges."""
+    lib = lib or _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n = len(order)
+    if len(row_ptr) != n + 1:
+        raise OracleError(-1)
+    h = C.c_void_p()
+    rc = lib.orc_build_directed(n, _ptr(row_ptr), _ptr(col), _ptr(order), C.byref(h))
+    if rc != 0:
+        raise OracleError(rc)
+    out_off = np.zeros(n + 1, np.int64)
+    lib.orc_export(h, _ptr(out_off), None, None, None, None, None, None, None, None, None)
+    ne_out = int(out_off[-1])
+    ix = DirectedIndex(n=n, rank=np.zeros(n, np.int32), out_off=out_off,
+                       out_hub=np.zeros(ne_out, np.uint32), out_dist=np.zeros(ne_out, np.uint8),
+                       in_off=np.zeros(n + 1, np.int64), in_hub=None, in_dist=None, _handle=h)
+    ix._lib = lib
+    lib.orc_export(h, None, _ptr(ix.out_hub), _ptr(ix.out_dist), None, None, None,
+                   _ptr(ix.rank), None, None, None)
+    ne_in = C.c_int64()
+    lib.orc_export_in(h, C.byref(ne_in), _ptr(ix.in_off), None, None)
+    ix.in_hub = np.zeros(ne_in.value, np.uint32)
+    ix.in_dist = np.zeros(ne_in.value, np.uint8)
+    lib.orc_export_in(h, None, None, _ptr(ix.in_hub), _ptr(ix.in_dist))
+    nc = lib.orc_ncounters()
+    cnt = np.zeros(nc, np.int64)
+    lib.orc_counters(h, _ptr(cnt), nc)
+    ix.counters = {k: int(v) for k, v in zip(COUNTER_NAMES, cnt)}
+    return ix
+
+
+def query_directed(ix: DirectedIndex, pairs) -> np.ndarray:
+    """d(s, t) along edge directions, min(., 255)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(len(pairs), np.uint8)
+    rc = (ix._lib or _load()).orc_query(ix._handle, _ptr(pairs), len(pairs), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return out

@@ -26,6 +26,12 @@
  *   O6  shortest paths (Section 7, "Shortest-Path Queries"): every label
  *       entry (h, d) of v also keeps the parent of v in the pruned BFS tree
  *       of h, and a path is restored by ascending those trees.
+ *   O7  directed graphs (Section 7, "Directed Graphs"): labels L_OUT(v) =
+ *       {(u, d(v,u))} and L_IN(v) = {(u, d(u,v))}; from every vertex in rank
+ *       order one pruned BFS along the edges (it labels L_IN of what it
+ *       reaches, pruning with L_OUT(root) and L_IN(u)) and one against them
+ *       (labels L_OUT, pruning with L_OUT(u) and L_IN(root)); d(s,t) is the
+ *       merge of L_OUT(s) and L_IN(t).
  *
  * Readings of points the paper leaves open (each one also fixed on the GPU
  * side, so both compute the same bytes):
@@ -100,7 +106,8 @@ typedef struct {
 typedef struct orc_index {
   int32_t n, t_bp;
   int32_t *rank;      /* rank[v] for input id v */
-  orc_label *lab;     /* indexed by rank */
+  orc_label *lab;     /* indexed by rank (L_OUT for a directed graph) */
+  orc_label *lab_in;  /* L_IN of a directed graph, else NULL */
   uint8_t *bp_d;      /* [n][t_bp], indexed by rank */
   uint64_t *bp_m1;    /* S^{-1} sets */
   uint64_t *bp_0;     /* S^{0} sets */
@@ -131,6 +138,7 @@ void orc_free(orc_index *x) {
   if (!x) return;
   free(x->rank);
   label_free_all(x->lab, x->n);
+  label_free_all(x->lab_in, x->n);
   free(x->bp_d);
   free(x->bp_m1);
   free(x->bp_0);
@@ -567,7 +575,7 @@ static void query_parts(const orc_index *x, int32_t s, int32_t t, int *bp_part,
   }
   *bp_part = best;
   best = (int)ORC_INF;
-  const orc_label *A = &x->lab[rs], *B = &x->lab[rt];
+  const orc_label *A = &x->lab[rs], *B = x->lab_in ? &x->lab_in[rt] : &x->lab[rt];
   int64_t i = 0, j = 0;
   for (;;) {
     uint32_t ha = A->hub[i], hb = B->hub[j];
@@ -840,7 +848,8 @@ static int path_one(const orc_index *x, int32_t s, int32_t t, int32_t maxlen, in
 /* Paths of q pairs: row i of paths (maxlen ids) and lens[i] as path_one. */
 int orc_paths(const orc_index *x, const int32_t *pairs, int64_t q, int32_t maxlen,
               int32_t *paths, int32_t *lens) {
-  if (!x || q < 0 || maxlen < 0 || (q > 0 && (!pairs || !lens || (maxlen > 0 && !paths))))
+  if (!x || x->lab_in || q < 0 || maxlen < 0 ||
+      (q > 0 && (!pairs || !lens || (maxlen > 0 && !paths))))
     return ORC_E_INVAL;
   for (int64_t i = 0; i < 2 * q; i++)
     if (pairs[i] < 0 || pairs[i] >= x->n) return ORC_E_INVAL;
@@ -861,5 +870,164 @@ int orc_export_parents(const orc_index *x, uint32_t *par) {
     if (L->len) memcpy(par + e, L->par, (size_t)L->len * sizeof(uint32_t));
     e += L->len;
   }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7: directed graphs (Section 7)                                           */
+
+/* min over (h, delta) of L with T[h] finite of delta + T[h] */
+static int t_query(const orc_label *L, const uint8_t *T) {
+  int best = 1 << 20;
+  for (int64_t i = 0; i < L->len; i++) {
+    uint8_t th = T[L->hub[i]];
+    if (th == ORC_INF) continue;
+    int v = (int)L->dist[i] + (int)th;
+    if (v < best) best = v;
+  }
+  return best;
+}
+
+/* One pruned BFS from root k over adj (out-edges for the forward search,
+ * in-edges for the reverse one).  T holds the root's label on the other
+ * side; `own` receives (k, d) at every vertex it does not prune. */
+static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32_t *adj,
+                        orc_label *own, const orc_label *root_side, uint8_t *P, uint8_t *T,
+                        int32_t *queue) {
+  const orc_label *Lk = &root_side[k];
+  for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
+  x->cnt[C_ROOT_STAGED] += Lk->len;
+  int rc = ORC_OK;
+  int64_t qh = 0, qt = 0;
+  queue[qt++] = k;
+  P[k] = 0;
+  while (qh < qt && rc == ORC_OK) {
+    int32_t u = queue[qh++];
+    int d = P[u];
+    x->cnt[C_VISITED]++;
+    x->cnt[C_NORMAL_TESTS]++;
+    x->cnt[C_LABEL_SCANNED] += own[u].len;
+    if (t_query(&own[u], T) <= d) continue;
+    rc = label_push(&own[u], (uint32_t)k, (uint8_t)d, ORC_SENTINEL);
+    if (rc != ORC_OK) break;
+    x->cnt[C_LABELED]++;
+    if (d > x->cnt[C_MAX_DIST]) x->cnt[C_MAX_DIST] = d;
+    for (int64_t j = off[u]; j < off[u + 1]; j++) {
+      int32_t w = adj[j];
+      x->cnt[C_EDGES]++;
+      if (P[w] != ORC_INF) continue;
+      if (d + 1 >= (int)ORC_INF) {
+        /* w sits at distance 255: fine only if it would be pruned */
+        if (t_query(&own[w], T) > d + 1) {
+          rc = ORC_E_RANGE;
+          break;
+        }
+        continue;
+      }
+      P[w] = (uint8_t)(d + 1);
+      queue[qt++] = w;
+    }
+  }
+  for (int64_t i = 0; i < qt; i++) P[queue[i]] = (uint8_t)ORC_INF;
+  for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = (uint8_t)ORC_INF;
+  return rc;
+}
+
+/* Build the two labels of a directed graph (row_ptr/col: out-edges), in
+ * rank order, forward search before reverse search for each root.  No
+ * bit-parallel labels (Section 5 is written for undirected graphs). */
+int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                       const int32_t *order, orc_index **out) {
+  if (!out) return ORC_E_INVAL;
+  *out = NULL;
+  int rc = validate(n, row_ptr, col, order, 0);
+  if (rc != ORC_OK) return rc;
+  orc_index *x = (orc_index *)calloc(1, sizeof(orc_index));
+  if (!x) return ORC_E_NOMEM;
+  x->n = n;
+  x->t_bp = 0;
+  int64_t nn = n > 0 ? n : 1;
+  int64_t nnz = n > 0 ? row_ptr[n] : 0, mm = nnz > 0 ? nnz : 1;
+  x->rank = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  x->lab = (orc_label *)calloc((size_t)nn, sizeof(orc_label));
+  x->lab_in = (orc_label *)calloc((size_t)nn, sizeof(orc_label));
+  x->bp_d = (uint8_t *)malloc(1);
+  x->bp_m1 = (uint64_t *)malloc(sizeof(uint64_t));
+  x->bp_0 = (uint64_t *)malloc(sizeof(uint64_t));
+  x->bp_root = (int32_t *)malloc(sizeof(int32_t));
+  x->bp_nsel = (int32_t *)malloc(sizeof(int32_t));
+  x->bp_sel = (int32_t *)malloc(sizeof(int32_t));
+  x->root_visited = (int32_t *)calloc((size_t)nn, sizeof(int32_t));
+  x->root_labeled = (int32_t *)calloc((size_t)nn, sizeof(int32_t));
+  x->ord = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  int64_t *off = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+  int32_t *adj = (int32_t *)malloc((size_t)mm * sizeof(int32_t));
+  int64_t *ioff = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+  int32_t *iadj = (int32_t *)malloc((size_t)mm * sizeof(int32_t));
+  int64_t *fill = (int64_t *)calloc((size_t)nn, sizeof(int64_t));
+  uint8_t *P = (uint8_t *)malloc((size_t)nn);
+  uint8_t *T = (uint8_t *)malloc((size_t)nn);
+  int32_t *queue = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  if (!x->rank || !x->lab || !x->lab_in || !x->bp_d || !x->bp_m1 || !x->bp_0 || !x->bp_root ||
+      !x->bp_nsel || !x->bp_sel || !x->root_visited || !x->root_labeled || !x->ord || !off ||
+      !adj || !ioff || !iadj || !fill || !P || !T || !queue) {
+    rc = ORC_E_NOMEM;
+    goto done;
+  }
+  /* ranks; out-adjacency and its transpose (in-adjacency), rows sorted */
+  for (int32_t i = 0; i < n; i++) {
+    x->rank[order[i]] = i;
+    x->ord[i] = order[i];
+  }
+  for (int32_t r = 0; r < n; r++) {
+    int32_t v = order[r];
+    int64_t deg = row_ptr[v + 1] - row_ptr[v];
+    for (int64_t j = 0; j < deg; j++) adj[off[r] + j] = x->rank[col[row_ptr[v] + j]];
+    qsort(adj + off[r], (size_t)deg, sizeof(int32_t), cmp_i32);
+    off[r + 1] = off[r] + deg;
+  }
+  for (int64_t j = 0; j < nnz; j++) ioff[adj[j] + 1]++;
+  for (int32_t r = 0; r < n; r++) ioff[r + 1] += ioff[r];
+  for (int32_t r = 0; r < n; r++) /* sources in ascending rank: rows come out sorted */
+    for (int64_t j = off[r]; j < off[r + 1]; j++) iadj[ioff[adj[j]] + fill[adj[j]]++] = r;
+  memset(P, (int)ORC_INF, (size_t)nn);
+  memset(T, (int)ORC_INF, (size_t)nn);
+  for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
+    x->cnt[C_ROOTS]++;
+    int64_t vis0 = x->cnt[C_VISITED], lab0 = x->cnt[C_LABELED];
+    rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue);
+    if (rc == ORC_OK) rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue);
+    x->root_visited[k] = (int32_t)(x->cnt[C_VISITED] - vis0);
+    x->root_labeled[k] = (int32_t)(x->cnt[C_LABELED] - lab0);
+  }
+  if (rc != ORC_OK) goto done;
+  for (int32_t v = 0; v < n; v++) x->cnt[C_ENTRIES] += x->lab[v].len + x->lab_in[v].len;
+  x->cnt[C_N] = n;
+  x->off = off;
+  x->adj = adj;
+  off = NULL;
+  adj = NULL;
+  *out = x;
+  x = NULL;
+done:
+  free(off); free(adj); free(ioff); free(iadj); free(fill); free(P); free(T); free(queue);
+  if (x) orc_free(x);
+  return rc;
+}
+
+/* The in-labels of a directed index, in rank order, without sentinels. */
+int orc_export_in(const orc_index *x, int64_t *entries, int64_t *off, uint32_t *hub,
+                  uint8_t *dist) {
+  if (!x || !x->lab_in) return ORC_E_INVAL;
+  int64_t e = 0;
+  for (int32_t v = 0; v < x->n; v++) {
+    if (off) off[v] = e;
+    const orc_label *L = &x->lab_in[v];
+    if (hub && L->len) memcpy(hub + e, L->hub, (size_t)L->len * sizeof(uint32_t));
+    if (dist && L->len) memcpy(dist + e, L->dist, (size_t)L->len);
+    e += L->len;
+  }
+  if (off) off[x->n] = e;
+  if (entries) *entries = e;
   return ORC_OK;
 }

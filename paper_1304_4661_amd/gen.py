@@ -264,6 +264,75 @@ def rmat_graph(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.
 
 
 # --------------------------------------------------------------------------
+# Directed graphs (Section 7, "Directed Graphs")
+# --------------------------------------------------------------------------
+
+def digraph_from_edges(n: int, u: np.ndarray, v: np.ndarray) -> Graph:
+    """Directed edges u -> v: drop self-loops, de-duplicate, CSR of
+    out-edges with sorted rows.  meta["directed"] is set; ``nnz`` is the
+    number of arcs."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    keep = u != v
+    key = np.unique(u[keep] * np.int64(n) + v[keep])
+    src = key // n
+    dst = key - src * n
+    counts = np.bincount(src, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("graph too large for int32 CSR")
+    return Graph(n, row_ptr.astype(np.int32), dst.astype(np.int32), {"directed": True})
+
+
+def weakly_connected_part(g: Graph) -> Graph:
+    """Keep the largest weakly connected component of a digraph (ids
+    compacted in their original order)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    if g.n == 0:
+        return g
+    a = csr_matrix((np.ones(len(g.col), dtype=np.int8), g.col, g.row_ptr), shape=(g.n, g.n))
+    ncomp, lab = connected_components(a, directed=True, connection="weak")
+    keep = lab == int(np.argmax(np.bincount(lab, minlength=ncomp)))
+    newid = np.cumsum(keep) - 1
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    emask = keep[src] & keep[g.col]
+    out = digraph_from_edges(int(keep.sum()), newid[src[emask]], newid[g.col[emask]])
+    out.meta = dict(g.meta)
+    return out
+
+
+def rmat_digraph(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+                 c: float = 0.19, seed: int = 0) -> Graph:
+    """R-MAT samples as arcs (not symmetrized), self-loops dropped,
+    de-duplicated, largest weakly connected component kept."""
+    u, v = rmat_edges(scale, edge_factor, a, b, c, seed)
+    g = weakly_connected_part(digraph_from_edges(1 << scale, u, v))
+    g.meta = {"kind": "rmat", "directed": True, "scale": scale, "edge_factor": edge_factor,
+              "abcd": [a, b, c, round(1 - a - b - c, 6)], "seed": seed}
+    return g
+
+
+def er_digraph(n: int, p: float, seed: int) -> Graph:
+    """Each of the n(n-1) arcs independently with probability p."""
+    rng = _rng(seed)
+    m = rng.random((n, n)) < p
+    np.fill_diagonal(m, False)
+    u, v = np.nonzero(m)
+    return digraph_from_edges(n, u, v)
+
+
+def degree_order_directed(g: Graph) -> np.ndarray:
+    """Degree strategy for a digraph: in-degree plus out-degree descending,
+    ties by ascending id."""
+    deg = np.diff(g.row_ptr).astype(np.int64) + np.bincount(g.col, minlength=g.n)
+    ids = np.arange(g.n, dtype=np.int64)
+    return np.lexsort((ids, -deg)).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
 # Orders, pairs, digests, batches
 # --------------------------------------------------------------------------
 

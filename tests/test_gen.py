@@ -76,3 +76,18 @@ def test_native_ba_matches_python_loop():
         a = gen.ba_edges(n, m, s)
         b = gen.ba_edges_fast(n, m, s)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_digraph_generators():
+    g = gen.digraph_from_edges(5, np.array([0, 0, 1, 2, 3, 3]), np.array([1, 1, 1, 0, 4, 2]))
+    assert g.row_ptr.tolist() == [0, 1, 1, 2, 4, 4] and g.col.tolist() == [1, 0, 2, 4]
+    assert g.meta["directed"]
+    d = gen.rmat_digraph(10, 8, seed=3)
+    a = csr_matrix((np.ones(len(d.col)), d.col, d.row_ptr), shape=(d.n, d.n))
+    assert connected_components(a, directed=True, connection="weak")[0] == 1
+    src = np.repeat(np.arange(d.n), np.diff(d.row_ptr))
+    assert np.all(src != d.col)
+    assert gen.csr_sha256(d) == gen.csr_sha256(gen.rmat_digraph(10, 8, seed=3))
+    # in+out degree descending, ties by id
+    g2 = gen.digraph_from_edges(4, np.array([0, 1, 2]), np.array([1, 2, 3]))
+    assert gen.degree_order_directed(g2).tolist() == [1, 2, 0, 3]
