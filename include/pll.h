@@ -57,6 +57,11 @@ enum {
 #define PLL_PARENTS 16u    /* pll_build*: keep, with every label entry (h, d) of
                               v, the parent of v in the pruned BFS tree of h
                               (Section 7), plus the graph, for pll_query_path */
+#define PLL_DIRECTED 32u   /* pll_build*: the CSR lists out-arcs of a directed
+                              graph (Section 7): labels L_OUT and L_IN, queries
+                              give the distance from s to t along the arcs;
+                              needs t_bp = 0 and no PLL_PARENTS (else
+                              PLL_E_UNSUPPORTED); no symmetry is required */
 
 /*
  * Device allocator for builds and indexes (process-wide; the default is
@@ -86,7 +91,8 @@ int pll_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx),
  *   t_bp     number of bit-parallel roots, 0..PLL_MAX_TBP (Section 5.4: the
  *            root is the lowest-rank unused vertex, its up to 64 lowest-rank
  *            unused neighbours form S_r; an exhausted slot stays empty)
- *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC, PLL_DEVICE_PTRS, PLL_PARENTS
+ *   flags    PLL_VALIDATE, PLL_PLAIN, PLL_SYNC, PLL_DEVICE_PTRS, PLL_PARENTS,
+ *            PLL_DIRECTED
  *   out      receives the new index on success
  * row_ptr, col and order are host memory, or device memory under
  * PLL_DEVICE_PTRS (then they are checked by a kernel before the build, and
@@ -206,6 +212,17 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
  * from h, and v itself for d = 0.  par: host uint32[entries].
  */
 int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par);
+
+/*
+ * L_IN of one graph of a directed index (built with PLL_DIRECTED, else
+ * PLL_E_UNSUPPORTED), in pll_export's layout: vertices in local rank order,
+ * off int64[n+1], hub uint32[entries] (local ranks), dist uint8[entries],
+ * no sentinels; (h, d) in L_IN(v) means d(h, v) = d.  *entries gets the
+ * entry count; pass NULL arrays to ask for it first.  pll_export gives
+ * L_OUT of a directed index ((h, d) in L_OUT(v): d(v, h) = d).
+ */
+int pll_export_in(const pll_index *idx, int32_t graph, int64_t *entries, int64_t *off,
+                  uint32_t *hub, uint8_t *dist);
 
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);

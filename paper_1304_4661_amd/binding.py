@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpll.so")
 OK, E_INVAL, E_NOMEM, E_RANGE, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 INF = 255
 MAX_TBP = 64
-DEVICE_PTRS, VALIDATE, SYNC, PLAIN, PARENTS = 1, 2, 4, 8, 16
+DEVICE_PTRS, VALIDATE, SYNC, PLAIN, PARENTS, DIRECTED = 1, 2, 4, 8, 16, 32
 
 STAT_NAMES = [
     "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
@@ -32,7 +32,7 @@ EXPORTED = [
     "pll_export_sizes", "pll_export", "pll_stats", "pll_level_trace", "pll_free", "pll_strerror",
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
-    "pll_query_path", "pll_export_parents",
+    "pll_query_path", "pll_export_parents", "pll_export_in",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -77,6 +77,8 @@ def _lib():
         lib.pll_query_path.restype = C.c_int
         lib.pll_export_parents.argtypes = [P, C.c_int32, P]
         lib.pll_export_parents.restype = C.c_int
+        lib.pll_export_in.argtypes = [P, C.c_int32, P, P, P, P]
+        lib.pll_export_in.restype = C.c_int
         lib.pll_level_trace.argtypes = [P, P, C.c_int64]
         lib.pll_level_trace.restype = C.c_int64
         lib.pll_free.argtypes = [P]
@@ -243,6 +245,19 @@ class Index:
                                      C.c_void_p(paths.data_ptr()), C.c_void_p(lens.data_ptr()),
                                      flags, C.c_void_p(stream.cuda_stream)), "query_path_device")
 
+    def export_in(self, graph: int = 0) -> dict:
+        """L_IN of a directed index (off, hub, dist; local ranks, no
+        sentinels); ``export`` gives L_OUT."""
+        n, _, _ = self.sizes(graph)
+        ne = C.c_int64()
+        _check(_lib().pll_export_in(self._h, int(graph), C.byref(ne), None, None, None), "export_in")
+        off = np.zeros(n + 1, np.int64)
+        hub = np.zeros(ne.value, np.uint32)
+        dist = np.zeros(ne.value, np.uint8)
+        _check(_lib().pll_export_in(self._h, int(graph), None, _ptr(off), _ptr(hub), _ptr(dist)),
+               "export_in")
+        return {"off": off, "hub": hub, "dist": dist}
+
     def export_parents(self, graph: int = 0) -> np.ndarray:
         """Parents of the exported entries of one graph, as local ranks."""
         _, e, _ = self.sizes(graph)
@@ -286,7 +301,7 @@ class Index:
 
 
 def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=None,
-                 parents: bool = False) -> Index:
+                 parents: bool = False, directed: bool = False) -> Index:
     """Build from device tensors (torch, int32, contiguous, on the GPU)."""
     import torch
 
@@ -297,7 +312,8 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
         raise PllError(E_INVAL, "build_device: row_ptr length")
     if stream is None:
         stream = torch.cuda.current_stream()
-    flags = DEVICE_PTRS | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+    flags = (DEVICE_PTRS | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+             | (DIRECTED if directed else 0))
     h = C.c_void_p()
     rc = _lib().pll_build(n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()),
                           C.c_void_p(order.data_ptr()), int(t_bp), flags,
@@ -308,12 +324,13 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
 
 def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
                 plain: bool = False, stream=None, device: bool = False,
-                parents: bool = False) -> Index:
+                parents: bool = False, directed: bool = False) -> Index:
     """Build the indexes of a batch of graphs (see include/pll.h).  With
     device=True, row_ptr/col/order are torch device tensors."""
     vtx_off = np.ascontiguousarray(vtx_off, dtype=np.int64)
     G = len(vtx_off) - 1
-    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+    flags = ((VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+             | (DIRECTED if directed else 0))
     h = C.c_void_p()
     if device:
         import torch
@@ -336,7 +353,7 @@ def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
 
 
 def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = False,
-          stream=None, parents: bool = False) -> Index:
+          stream=None, parents: bool = False, directed: bool = False) -> Index:
     """Build the index of one graph (host CSR and order, see include/pll.h)."""
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -344,7 +361,8 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
     n = len(order)
     if len(row_ptr) != n + 1:
         raise PllError(E_INVAL, "build: row_ptr length")
-    flags = (VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+    flags = ((VALIDATE if validate else 0) | (PLAIN if plain else 0) | (PARENTS if parents else 0)
+             | (DIRECTED if directed else 0))
     h = C.c_void_p()
     s = None if stream is None else C.c_void_p(stream.cuda_stream)
     rc = _lib().pll_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp), flags, s,

@@ -178,6 +178,11 @@ struct pll_index {
   // rank-space graph and rank -> id, for path queries
   bool parents = false;
   DBuf<uint32_t> par;
+  // a directed graph (PLL_DIRECTED): off/hub/dist hold L_OUT, these L_IN
+  bool directed = false;
+  DBuf<int64_t> ioff;
+  DBuf<uint32_t> ihub;
+  DBuf<uint8_t> idist;
   DBuf<int64_t> grow;
   DBuf<int32_t> gcol;
   DBuf<int32_t> ord;
@@ -198,6 +203,9 @@ struct pll_index {
     v.off = off.p;
     v.hub = hub.p;
     v.dist = dist.p;
+    v.toff = directed ? ioff.p : off.p;
+    v.thub = directed ? ihub.p : hub.p;
+    v.tdist = directed ? idist.p : dist.p;
     v.par = par.p;
     v.grow = grow.p;
     v.gcol = gcol.p;
@@ -462,72 +470,213 @@ struct Builder {
     check(hipStreamSynchronize(st));
   }
 
-  // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR
+  // Growing label store of one side (the labels of an undirected graph, or
+  // L_IN / L_OUT of a directed one): per-vertex slots in a pool.
+  struct Store {
+    DBuf<int64_t> off;
+    DBuf<int32_t> len, cap;
+    DBuf<uint32_t> hub, par;  // par stays null unless parents are kept
+    DBuf<uint8_t> dist;
+    DBuf<unsigned long long> top;
+    int64_t pool_cap = 0;
+    DStore view() const {
+      return DStore{off.p, len.p, cap.p, hub.p, dist.p, top.p, pool_cap, par.p};
+    }
+  };
+
+  // One search direction of the pruned phase: the graph its BFSs follow,
+  // the store it labels, the store the roots' tables come from, and its
+  // window state.
+  struct Side {
+    DGraph g;
+    Store *own = nullptr, *roots = nullptr;
+    int64_t htcap = 0, fcap = 0, hcap = 0, ccap = 0;
+    DBuf<uint32_t> vis;
+    DBuf<uint8_t> wd, cd, cdes;
+    DBuf<uint64_t> ht, cmask, kmask, sig, csum;
+    DBuf<int64_t> htoff, hsize, htmp;
+    DBuf<int32_t> fslot, fv, h1, cu, cj, cpar, fpar;
+    DBuf<LevelCtl> ctl;
+    PinnedMirror mirror;  // level counters and the own store's pool top
+    DFrontier f;
+    DWindow window(int32_t s, int32_t nr, int words, const uint8_t *used) const {
+      return DWindow{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
+                     cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, cpar.p,
+                     used};
+    }
+  };
+
+  void store_init(Store &S, int64_t pool_cap) {
+    S.off.alloc((size_t)n);
+    S.len.alloc((size_t)n);
+    S.cap.alloc((size_t)n);
+    fill(S.off, 0, st);
+    fill(S.len, 0, st);
+    fill(S.cap, 0, st);
+    S.pool_cap = pool_cap;
+    S.hub.alloc((size_t)pool_cap);
+    S.dist.alloc((size_t)pool_cap);
+    if (parents) S.par.alloc((size_t)pool_cap);
+    S.top.alloc(1);
+    fill(S.top, 0, st);
+  }
+
+  // Grow the pool so that a commit of ncand candidates cannot run out
+  // (each touched vertex takes at most 2*(len+new)+32 slots).
+  void store_reserve(Store &S, int64_t entries_bound, int64_t ncand, unsigned long long htop) {
+    const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
+    if (S.pool_cap - (int64_t)htop >= need) return;
+    const int64_t ncap = std::max<int64_t>(3 * S.pool_cap, (int64_t)htop + 2 * need);
+    DBuf<uint32_t> nh((size_t)ncap), np;
+    if (parents) np.alloc((size_t)ncap);
+    DBuf<uint8_t> nd((size_t)ncap);
+    check(hipMemcpyAsync(nh.p, S.hub.p, (size_t)htop * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                         st));
+    check(hipMemcpyAsync(nd.p, S.dist.p, (size_t)htop, hipMemcpyDeviceToDevice, st));
+    if (parents)
+      check(hipMemcpyAsync(np.p, S.par.p, (size_t)htop * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, st));
+    check(hipStreamSynchronize(st));
+    S.hub = std::move(nh);
+    S.dist = std::move(nd);
+    S.par = std::move(np);
+    S.pool_cap = ncap;
+  }
+
+  void side_init(Side &D, DGraph g, Store *own, Store *roots, int wmax, int words) {
+    D.g = g;
+    D.own = own;
+    D.roots = roots;
+    const int64_t wstride = (int64_t)words * 64;
+    D.vis.alloc((size_t)wmax * nwords);
+    D.wd.alloc((size_t)n * wstride);
+    D.htcap = tu.table_cap > 0 ? tu.table_cap : std::max<int64_t>(1 << 20, 32 * (int64_t)wmax);
+    D.ht.alloc((size_t)D.htcap);
+    D.htoff.alloc((size_t)wmax + 1);
+    D.hsize.alloc((size_t)wmax + 1);
+    D.htmp.alloc((size_t)scan_tmp_elems((int64_t)wmax + 1));
+    D.cmask.alloc((size_t)n * words);
+    D.kmask.alloc((size_t)n * words);
+    D.sig.alloc((size_t)wmax * 4);
+    D.csum.alloc((size_t)n * 4);
+    fill(D.vis, 0, st);
+    fill(D.cmask, 0, st);
+    fill(D.kmask, 0, st);
+    fill(D.csum, 0, st);
+    // list capacities: sized from the window, never below what one root
+    // needs (a window of one root always fits); `list_cap` lowers them
+    const int64_t lcap = tu.list_cap > 0 ? tu.list_cap : INT64_MAX;
+    const int64_t m = g.row ? nnz : 0;
+    D.fcap = std::max<int64_t>(2 * (int64_t)n + 64,
+                               std::min<int64_t>({(int64_t)wmax * n, 96ll << 20, lcap}));
+    D.hcap = std::max<int64_t>((int64_t)n + m / tu.chunk + 64,
+                               std::min<int64_t>({(int64_t)wmax * (m / tu.chunk + 1), 16ll << 20,
+                                                  lcap}));
+    D.ccap = std::max<int64_t>((int64_t)n + 64,
+                               std::min<int64_t>({(int64_t)wmax * n, 32ll << 20, lcap}));
+    D.fslot.alloc((size_t)D.fcap);
+    D.fv.alloc((size_t)D.fcap);
+    D.h1.alloc((size_t)D.hcap * 3);
+    D.cu.alloc((size_t)D.ccap);
+    D.cj.alloc((size_t)D.ccap);
+    if (parents) {
+      D.cpar.alloc((size_t)D.ccap);
+      D.fpar.alloc((size_t)D.fcap);
+    }
+    D.cd.alloc((size_t)D.ccap);
+    D.cdes.alloc((size_t)D.ccap);
+    D.ctl.alloc(1);
+    D.f = DFrontier{D.fslot.p, D.fv.p,  D.fcap,  D.h1.p, D.h1.p + D.hcap, D.h1.p + 2 * D.hcap,
+                    D.hcap,    nullptr, nullptr, nullptr, D.ctl.p,         D.fpar.p};
+    D.mirror.p->ctl = LevelCtl{};
+    D.mirror.p->top = 0;
+  }
+
+  // One window's BFS levels in one direction, until every root's search has
+  // ended or a list overflowed.  Returns the last level index.
+  int side_levels(Side &D, const DBp &bp, const DWindow &w, int64_t window_index,
+                  std::vector<hipEvent_t> &evs) {
+    LevelCtl &h = D.mirror.p->ctl;
+    const DStore sto = D.own->view();
+    const size_t mark0 = level_trace.size();
+    check(launch_win_reset_ctl(D.ctl.p, st));
+    check(launch_win_init(D.g, w, D.roots->view(), D.f, w.W, D.hsize.p, D.htmp.p, st));
+    int d = 0;
+    for (bool done = false; !done;) {
+      const int d0 = d;
+      const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
+      for (; d < upto; d++) {
+        hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
+        hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
+        check(launch_win_level(D.g, bp, sto, w, D.f, d, tu.group, tu.xgroup, tu.chunk, st, e0, e1));
+        stat_levels++;
+        stat_level_launches++;
+      }
+      check(hipMemcpyAsync(&h, D.ctl.p, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
+      check(hipMemcpyAsync(&D.mirror.p->top, D.own->top.p, sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, st));
+      check(hipStreamSynchronize(st));
+      for (int i = 0; !evs.empty() && i < d - d0; i++) {
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+        stat_level_ns += (int64_t)(ms * 1e6);
+        const int lv = d0 + i;
+        level_trace.insert(level_trace.end(), {window_index, (int64_t)w.s, (int64_t)w.W,
+                                               (int64_t)lv, (int64_t)h.cnt[lv], 0,
+                                               (int64_t)(ms * 1e6)});
+      }
+      if (h.flags || h.cnt[d] == 0 || d >= kMaxLevels - 1) done = true;
+    }
+    // candidates made at each traced level
+    for (size_t r = mark0; r < level_trace.size(); r += kTraceCols) {
+      const int lv = (int)level_trace[r + 3];
+      const unsigned long long c1 = lv + 1 < d ? h.cmark[lv + 1] : h.ccnt;
+      level_trace[r + 5] = (int64_t)(c1 - h.cmark[lv]);
+    }
+    return d;
+  }
+
+  // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR.
+  // An undirected graph has one side; a directed one (Section 7) a forward
+  // side (follows the arcs, labels L_IN, root tables from L_OUT) and a
+  // reverse side (in-edges, labels L_OUT, root tables from L_IN).
+  bool directed = false;
+  DBuf<int64_t> irow;  // in-edges of a directed graph (rank space)
+  DBuf<int32_t> icol;
+
   void pruned(pll_index *ix) {
-    // per-root window state: distance column of wd (n B), visited bits
-    // (n/8 B) and two mask bits per vertex (n/4 B)
-    const int64_t per_root = (int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1;
+    const int nsides = directed ? 2 : 1;
+    // per-root window state per side: distance column of wd (n B), visited
+    // bits (n/8 B) and two mask bits per vertex (n/4 B)
+    const int64_t per_root = nsides * ((int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1);
     const int64_t wmem = std::max<int64_t>(64, (tu.window_mem_mb << 20) / per_root);
     const int wmax =
         plain ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>({tu.window, kMaxWindow, wmem}));
     const int words = (wmax + 63) / 64;
-    const int64_t wstride = (int64_t)words * 64;
-    // growing label store
-    DBuf<int64_t> soff((size_t)n);
-    DBuf<int32_t> slen((size_t)n), scap((size_t)n);
-    fill(soff, 0, st);
-    fill(slen, 0, st);
-    fill(scap, 0, st);
-    int64_t pool_cap = std::max<int64_t>(32 * (int64_t)n, 1 << 20);
-    // (buffers for parents stay unallocated, null, when they are not kept)
-    DBuf<uint32_t> phub((size_t)pool_cap), ppar;
-    if (parents) ppar.alloc((size_t)pool_cap);
-    DBuf<uint8_t> pdist((size_t)pool_cap);
-    DBuf<unsigned long long> top(1);
-    fill(top, 0, st);
-    // window state
-    DBuf<uint32_t> vis((size_t)wmax * nwords);
-    DBuf<uint8_t> wd((size_t)n * wstride);
-    // the roots' label tables: grown when a window needs more
-    int64_t htcap = tu.table_cap > 0 ? tu.table_cap : std::max<int64_t>(1 << 20, 32 * (int64_t)wmax);
-    DBuf<uint64_t> ht((size_t)htcap);
-    DBuf<int64_t> htoff((size_t)wmax + 1), hsize((size_t)wmax + 1),
-        htmp((size_t)scan_tmp_elems((int64_t)wmax + 1));
-    DBuf<uint64_t> cmask((size_t)n * words), kmask((size_t)n * words), sig((size_t)wmax * 4);
-    DBuf<uint64_t> csum((size_t)n * 4);
-    fill(vis, 0, st);
-    fill(cmask, 0, st);
-    fill(kmask, 0, st);
-    fill(csum, 0, st);
-    // list capacities: sized from the window, never below what one root
-    // needs (a window of one root always fits); `list_cap` lowers them
-    const int64_t lcap = tu.list_cap > 0 ? tu.list_cap : INT64_MAX;
-    const int64_t fcap = std::max<int64_t>(
-        2 * (int64_t)n + 64, std::min<int64_t>({(int64_t)wmax * n, 96ll << 20, lcap}));
-    const int64_t hcap = std::max<int64_t>(
-        (int64_t)n + nnz / tu.chunk + 64,
-        std::min<int64_t>({(int64_t)wmax * (nnz / tu.chunk + 1), 16ll << 20, lcap}));
-    const int64_t ccap = std::max<int64_t>((int64_t)n + 64,
-                                           std::min<int64_t>({(int64_t)wmax * n, 32ll << 20, lcap}));
-    DBuf<int32_t> fslot((size_t)fcap), fv((size_t)fcap), h1((size_t)hcap * 3);
-    DBuf<int32_t> cu((size_t)ccap), cj((size_t)ccap), cpar, fpar;
-    if (parents) {
-      cpar.alloc((size_t)ccap);
-      fpar.alloc((size_t)fcap);
+    const int64_t pool0 = std::max<int64_t>(32 * (int64_t)n, 1 << 20);
+    Store stores[2];
+    Side sides[2];
+    if (!directed) {
+      store_init(stores[0], pool0);
+      side_init(sides[0], graph(), &stores[0], &stores[0], wmax, words);
+    } else {
+      irow.alloc((size_t)n + 1);
+      icol.alloc((size_t)std::max<int64_t>(nnz, 1));
+      {
+        DBuf<int64_t> work((size_t)n + 1), tmp((size_t)scan_tmp_elems((int64_t)n + 1));
+        check(launch_transpose(row.p, col.p, n, irow.p, icol.p, work.p, tmp.p, st));
+        check(hipStreamSynchronize(st));
+      }
+      // stores[0] = L_IN (forward side), stores[1] = L_OUT (reverse side)
+      store_init(stores[0], pool0);
+      store_init(stores[1], pool0);
+      side_init(sides[0], graph(), &stores[0], &stores[1], wmax, words);
+      side_init(sides[1], DGraph{n, nwords, irow.p, icol.p}, &stores[1], &stores[0], wmax, words);
     }
-    DBuf<uint8_t> cd((size_t)ccap), cdes((size_t)ccap);
-    DBuf<LevelCtl> ctl(1);
-    DFrontier f{fslot.p, fv.p,    fcap,    h1.p,  h1.p + hcap, h1.p + 2 * hcap, hcap,
-                nullptr, nullptr, nullptr, ctl.p, fpar.p};
     DBuf<uint64_t> bpz((size_t)std::max<int32_t>(n, 1));
     check(launch_bpv_nonempty(n, t, ix->bpm.p, bpz.p, st));
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
-    PinnedMirror mirror;
-    LevelCtl &h = mirror.p->ctl;
-    unsigned long long &htop = mirror.p->top;
-    h = LevelCtl{};
-    htop = 0;
-    int64_t entries_bound = 0;
+    int64_t entries_bound[2] = {0, 0};
 
     // optional timing of each level kernel (events on the build stream)
     std::vector<hipEvent_t> evs;
@@ -551,108 +700,89 @@ struct Builder {
     while (s < n) {
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
-      DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
-      DWindow w{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
-                cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, cpar.p,
-                used.p};
-      check(launch_win_reset_ctl(ctl.p, st));
-      check(launch_win_init(graph(), w, sto, f, nr, hsize.p, htmp.p, st));
-      int d = 0;
-      bool done = false;
-      while (!done) {
-        const int d0 = d;
-        const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
-        for (; d < upto; d++) {
-          hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
-          hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
-          check(launch_win_level(graph(), bp, sto, w, f, d, tu.group, tu.xgroup, tu.chunk, st, e0,
-                                 e1));
-          stat_levels++;
-          stat_level_launches++;
-        }
-        check(hipMemcpyAsync(&h, ctl.p, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
-        check(hipMemcpyAsync(&htop, top.p, sizeof(htop), hipMemcpyDeviceToHost, st));
-        check(hipStreamSynchronize(st));
-        for (int i = 0; !evs.empty() && i < d - d0; i++) {
-          float ms = 0.f;
-          check(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
-          stat_level_ns += (int64_t)(ms * 1e6);
-          const int lv = d0 + i;
-          level_trace.insert(level_trace.end(), {stat_windows, (int64_t)s, (int64_t)nr, (int64_t)lv,
-                                                 (int64_t)h.cnt[lv], 0, (int64_t)(ms * 1e6)});
-        }
-        if (h.flags || h.cnt[d] == 0 || d >= kMaxLevels - 1) done = true;
+      DWindow w[2];
+      int last[2] = {0, 0};
+      bool ran[2] = {false, false};
+      int flags = 0;
+      for (int k = 0; k < nsides && !flags; k++) {  // after an overflow the window is redone
+        w[k] = sides[k].window(s, nr, words, used.p);
+        last[k] = side_levels(sides[k], bp, w[k], stat_windows, evs);
+        ran[k] = true;
+        flags |= sides[k].mirror.p->ctl.flags;
       }
-      int64_t nvisited = 0;
-      for (int i = 0; i <= d; i++) nvisited += (int64_t)h.cnt[i];
-      for (size_t r = trace_mark; r < level_trace.size(); r += kTraceCols) {
-        const int lv = (int)level_trace[r + 3];
-        const unsigned long long c1 = lv + 1 < d ? h.cmark[lv + 1] : h.ccnt;
-        level_trace[r + 5] = (int64_t)(c1 - h.cmark[lv]);
+      int64_t nvisited[2] = {0, 0}, ncand[2] = {0, 0};
+      for (int k = 0; k < nsides; k++) {
+        if (!ran[k]) continue;
+        const LevelCtl &h = sides[k].mirror.p->ctl;
+        for (int i = 0; i <= last[k]; i++) nvisited[k] += (int64_t)h.cnt[i];
+        ncand[k] = std::min<int64_t>((int64_t)h.ccnt, sides[k].ccap);
       }
-      const int64_t ncand = std::min<int64_t>((int64_t)h.ccnt, ccap);
-      if (h.flags) {
-        // undo the window and run it again with fewer roots
-        check(launch_win_reset(graph(), w, sto, f, nr, std::min(nvisited, fcap), st));
-        check(launch_win_abort(graph(), w, ncand, st));
-        if (h.flags & kFlagOvfFrontier) fill(vis, 0, st);
-        // candidates past the list's end set mask bits the list cannot undo
-        if (h.flags & kFlagOvfCand) {
-          fill(cmask, 0, st);
-          fill(csum, 0, st);
+      if (flags) {
+        // undo the window (both sides) and run it again
+        int reset_flags = 0;
+        for (int k = 0; k < nsides; k++) {
+          if (!ran[k]) continue;
+          Side &D = sides[k];
+          const LevelCtl &h = D.mirror.p->ctl;
+          reset_flags |= h.flags;
+          check(launch_win_reset(D.g, w[k], D.own->view(), D.f, nr,
+                                 std::min(nvisited[k], D.fcap), st));
+          check(launch_win_abort(D.g, w[k], ncand[k], st));
+          if (h.flags & kFlagOvfFrontier) fill(D.vis, 0, st);
+          // candidates past the list's end set mask bits the list cannot undo
+          if (h.flags & kFlagOvfCand) {
+            fill(D.cmask, 0, st);
+            fill(D.csum, 0, st);
+          }
         }
         check(hipStreamSynchronize(st));
         level_trace.resize(trace_mark);
-        if (h.flags == kFlagOvfHash) {
+        if (reset_flags == kFlagOvfHash) {
           // same window again with room for its root tables
-          htcap = std::max<int64_t>(2 * htcap, (int64_t)h.httotal + (int64_t)h.httotal / 4);
-          ht.alloc((size_t)htcap);
+          for (int k = 0; k < nsides; k++) {
+            if (!ran[k]) continue;
+            Side &D = sides[k];
+            const unsigned long long tot = D.mirror.p->ctl.httotal;
+            if ((int64_t)tot > D.htcap) {
+              D.htcap = std::max<int64_t>(2 * D.htcap, (int64_t)tot + (int64_t)tot / 4);
+              D.ht.alloc((size_t)D.htcap);
+            }
+          }
           continue;
         }
-        if (W == 1) throw Fail{(h.flags & kFlagRange) ? PLL_E_RANGE : PLL_E_NOMEM};
+        if (W == 1) throw Fail{(reset_flags & kFlagRange) ? PLL_E_RANGE : PLL_E_NOMEM};
         W = std::max(1, W / 4);
         stat_retries++;
         continue;
       }
-      // make sure the commit can grow every touched label without running
-      // out of pool: each vertex takes at most 2*(len+new)+32 slots
-      const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
-      if (pool_cap - (int64_t)htop < need) {
-        const int64_t ncap = std::max<int64_t>(3 * pool_cap, (int64_t)htop + 2 * need);
-        DBuf<uint32_t> nh((size_t)ncap), np;
-        if (parents) np.alloc((size_t)ncap);
-        DBuf<uint8_t> nd((size_t)ncap);
-        check(hipMemcpyAsync(nh.p, phub.p, (size_t)htop * sizeof(uint32_t),
-                             hipMemcpyDeviceToDevice, st));
-        check(hipMemcpyAsync(nd.p, pdist.p, (size_t)htop, hipMemcpyDeviceToDevice, st));
-        if (parents)
-          check(hipMemcpyAsync(np.p, ppar.p, (size_t)htop * sizeof(uint32_t),
-                               hipMemcpyDeviceToDevice, st));
-        check(hipStreamSynchronize(st));
-        phub = std::move(nh);
-        pdist = std::move(nd);
-        ppar = std::move(np);
-        pool_cap = ncap;
-        sto = DStore{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
+      for (int k = 0; k < nsides; k++) {
+        store_reserve(*sides[k].own, entries_bound[k], ncand[k], sides[k].mirror.p->top);
+        check(launch_win_reset(sides[k].g, w[k], sides[k].own->view(), sides[k].f, nr,
+                               nvisited[k], st));
       }
-      check(launch_win_reset(graph(), w, sto, f, nr, nvisited, st));
-      check(launch_win_clean(w, ncand, st));
-      check(launch_win_commit(w, sto, ncand, st));
-      entries_bound += ncand;
-      stat_visited += (int64_t)h.visited;
-      stat_tests += (int64_t)h.ntests;
-      stat_scanned += (int64_t)h.lscanned;
-      stat_edges += (int64_t)h.edges;
-      stat_hedges += (int64_t)h.hedges;
-      stat_bp_direct += (int64_t)h.bp_direct;
-      stat_bp_sets += (int64_t)h.bp_sets;
-      stat_bp_checks += (int64_t)h.bp_checks;
-      stat_cand += ncand;
+      // cleaning reads both sides' masks; then each side commits its store
+      for (int k = 0; k < nsides; k++)
+        check(launch_win_clean(w[k], w[nsides - 1 - k], ncand[k], st));
+      double work = 0;
+      for (int k = 0; k < nsides; k++) {
+        check(launch_win_commit(w[k], sides[k].own->view(), ncand[k], st));
+        const LevelCtl &h = sides[k].mirror.p->ctl;
+        entries_bound[k] += ncand[k];
+        stat_visited += (int64_t)h.visited;
+        stat_tests += (int64_t)h.ntests;
+        stat_scanned += (int64_t)h.lscanned;
+        stat_edges += (int64_t)h.edges;
+        stat_hedges += (int64_t)h.hedges;
+        stat_bp_direct += (int64_t)h.bp_direct;
+        stat_bp_sets += (int64_t)h.bp_sets;
+        stat_bp_checks += (int64_t)h.bp_checks;
+        stat_cand += ncand[k];
+        work += (double)h.visited + (double)h.bp_direct;
+      }
       stat_windows++;
       trace_mark = level_trace.size();
       s = e;
       if (adaptive) {
-        const double work = (double)h.visited + (double)h.bp_direct;
         double f = (double)tu.window_work / std::max(work, 1.0);
         f = std::min(4.0, std::max(0.25, f));
         W = (int)std::min<double>(wmax, std::max(1.0, W * f));
@@ -668,21 +798,29 @@ struct Builder {
       for (uint8_t x : hused) stat_roots += x ? 0 : 1;
     }
 
-    // a5: final CSR with sentinels
-    DBuf<int64_t> cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
-    ix->off.alloc((size_t)n + 1);
-    check(launch_final_count(slen.p, cnt.p, n, st));
-    check(launch_exclusive_scan(cnt.p, ix->off.p, n, tmp.p, st));
-    int64_t total = 0;
-    if (n > 0) d2h(&total, ix->off.p + n, 1, st);
-    check(hipStreamSynchronize(st));
-    ix->hub.alloc((size_t)std::max<int64_t>(total, 1));
-    ix->dist.alloc((size_t)std::max<int64_t>(total, 1));
-    if (parents) ix->par.alloc((size_t)std::max<int64_t>(total, 1));
-    DStore sto{soff.p, slen.p, scap.p, phub.p, pdist.p, top.p, pool_cap, ppar.p};
-    check(launch_final_copy(sto, ix->off.p, ix->hub.p, ix->dist.p, ix->par.p, n, st));
-    check(hipStreamSynchronize(st));
-    ix->entries = total - n;
+    // a5: final CSR with sentinels (L_OUT in off/hub/dist, L_IN apart)
+    ix->entries = 0;
+    for (int k = nsides - 1; k >= 0; k--) {
+      Store &S = stores[k];
+      const bool in_side = directed && k == 0;
+      DBuf<int64_t> &foff = in_side ? ix->ioff : ix->off;
+      DBuf<uint32_t> &fhub = in_side ? ix->ihub : ix->hub;
+      DBuf<uint8_t> &fdist = in_side ? ix->idist : ix->dist;
+      DBuf<int64_t> cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
+      foff.alloc((size_t)n + 1);
+      check(launch_final_count(S.len.p, cnt.p, n, st));
+      check(launch_exclusive_scan(cnt.p, foff.p, n, tmp.p, st));
+      int64_t total = 0;
+      if (n > 0) d2h(&total, foff.p + n, 1, st);
+      check(hipStreamSynchronize(st));
+      fhub.alloc((size_t)std::max<int64_t>(total, 1));
+      fdist.alloc((size_t)std::max<int64_t>(total, 1));
+      if (parents && !in_side) ix->par.alloc((size_t)std::max<int64_t>(total, 1));
+      check(launch_final_copy(S.view(), foff.p, fhub.p, fdist.p,
+                              in_side ? nullptr : ix->par.p, n, st));
+      check(hipStreamSynchronize(st));
+      ix->entries += total - n;
+    }
   }
 };
 
@@ -697,6 +835,8 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   b.tu = tuning();
   b.plain = (flags & PLL_PLAIN) != 0;
   b.parents = (flags & PLL_PARENTS) != 0;
+  b.directed = (flags & PLL_DIRECTED) != 0;
+  ix->directed = b.directed;
   b.G = G;
   b.vtx_off = vtx_off;
   if (d_vtx_off && d_vtx_off->p) b.d_vtx_off = std::move(*d_vtx_off);
@@ -758,7 +898,8 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
                                       ix->bpm.bytes() +
                                       ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes() +
                                       ix->par.bytes() + ix->grow.bytes() + ix->gcol.bytes() +
-                                      ix->ord.bytes());
+                                      ix->ord.bytes() + ix->ioff.bytes() + ix->ihub.bytes() +
+                                      ix->idist.bytes());
   S[PLL_STAT_BP_NS] = bp_ns;
   S[PLL_STAT_PRUNED_NS] = pr_ns;
   S[PLL_STAT_NORMAL_TESTS] = b.stat_tests;
@@ -812,6 +953,8 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   const AllocStream alloc_stream(st);
   const bool device = (flags & PLL_DEVICE_PTRS) != 0;
   if (G < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP || (G > 0 && !vtx_off)) return PLL_E_INVAL;
+  // directed graphs: no bit-parallel labels and no parents
+  if ((flags & PLL_DIRECTED) && (t_bp > 0 || (flags & PLL_PARENTS))) return PLL_E_UNSUPPORTED;
   std::vector<int64_t> voff(vtx_off, vtx_off + (G > 0 ? G + 1 : 0));
   if (G == 0) voff.assign(1, 0);
   if (voff[0] != 0) return PLL_E_INVAL;
@@ -823,7 +966,9 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   DBuf<int64_t> d_voff;
   DBuf<int32_t> gid;
   if (!device) {
-    int rc = validate_batch(G, vtx_off, row_ptr, col, order, t_bp, (flags & PLL_VALIDATE) != 0);
+    // symmetry is the undirected precondition; a directed graph has none
+    int rc = validate_batch(G, vtx_off, row_ptr, col, order, t_bp,
+                            (flags & PLL_VALIDATE) != 0 && !(flags & PLL_DIRECTED));
     if (rc != PLL_OK) return rc;
     nnz = N > 0 ? row_ptr[N] : 0;
   } else {
@@ -999,6 +1144,41 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
     }
     check(launch_or_flag(err, idx->err.p, st));
     check(hipFreeAsync(err, st));
+    return PLL_OK;
+  });
+}
+
+int pll_export_in(const pll_index *idx, int32_t graph, int64_t *entries, int64_t *off,
+                  uint32_t *hub, uint8_t *dist) {
+  if (!idx || graph < 0 || graph >= idx->G) return PLL_E_INVAL;
+  if (!idx->directed) return PLL_E_UNSUPPORTED;
+  return guarded([&] {
+    const int64_t g0 = idx->vtx_off[graph];
+    const int64_t ng = idx->vtx_off[graph + 1] - g0;
+    const int32_t gp = idx->gpos[graph];
+    hipStream_t st = nullptr;
+    std::vector<int64_t> hio((size_t)idx->n + 1);
+    if (idx->n) d2h(hio.data(), idx->ioff.p, (size_t)idx->n + 1, st);
+    check(hipStreamSynchronize(st));
+    std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
+    for (int64_t l = 0; l < ng; l++) {
+      rows[l] = idx->lbase[l] + gp;
+      oo[l + 1] = oo[l] + hio[rows[l] + 1] - 1 - hio[rows[l]];
+    }
+    const int64_t ne = oo[ng];
+    if (entries) *entries = ne;
+    if (off) std::memcpy(off, oo.data(), oo.size() * sizeof(int64_t));
+    if (ne == 0 || (!hub && !dist)) return PLL_OK;
+    DBuf<int64_t> drows((size_t)ng), doo((size_t)ng + 1);
+    h2d(drows.p, rows.data(), (size_t)ng, st);
+    h2d(doo.p, oo.data(), (size_t)ng + 1, st);
+    DBuf<uint32_t> oh((size_t)ne);
+    DBuf<uint8_t> od((size_t)ne);
+    check(launch_gather_labels(drows.p, ng, idx->ioff.p, idx->ihub.p, idx->idist.p, idx->lrank.p,
+                               doo.p, oh.p, od.p, st));
+    if (hub) d2h(hub, oh.p, (size_t)ne, st);
+    if (dist) d2h(dist, od.p, (size_t)ne, st);
+    check(hipStreamSynchronize(st));
     return PLL_OK;
   });
 }

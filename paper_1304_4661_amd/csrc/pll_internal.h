@@ -285,6 +285,10 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp,
                                  hipStream_t st);
 
+// In-edges of the rank-space graph: irow int64[n+1], icol int32[row[n]];
+// work int64[n+1], tmp scan_tmp_elems(n+1) int64.
+hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, int64_t *irow,
+                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st);
 hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
                             const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
                             uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
@@ -315,7 +319,7 @@ hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, 
 hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                             int64_t nvisited, hipStream_t st);
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);
-hipError_t launch_win_clean(DWindow w, int64_t ncand, hipStream_t st);
+hipError_t launch_win_clean(DWindow w, DWindow o, int64_t ncand, hipStream_t st);
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
@@ -332,6 +336,11 @@ struct DIndex {
   const int64_t *off;
   const uint32_t *hub;
   const uint8_t *dist;
+  // labels of the target side of a query: the same arrays for an
+  // undirected graph, L_IN for a directed one (off/hub/dist are L_OUT)
+  const int64_t *toff;
+  const uint32_t *thub;
+  const uint8_t *tdist;
   // kept by builds with PLL_PARENTS (else null): parent of each entry's
   // vertex in the hub's BFS tree, the rank-space graph, rank -> id
   const uint32_t *par;

@@ -324,6 +324,30 @@ __global__ void __launch_bounds__(kSelThreads) k_bp_select(DGraph g, int32_t t,
   }
 }
 
+// Transpose of the rank-space graph (in-edges of a directed graph): count
+// the arcs into each vertex, then place each arc r -> c into c's row.  Row
+// order follows the atomics (the searches do not depend on it).
+__global__ void __launch_bounds__(256) k_in_count(const int64_t *row, const int32_t *col,
+                                                  int32_t n, unsigned long long *cnt) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wave; r < n; r += nwaves)
+    for (int64_t e = row[r] + lane_id(); e < row[r + 1]; e += kWave)
+      atomicAdd(&cnt[col[e]], 1ull);
+}
+
+__global__ void __launch_bounds__(256) k_in_fill(const int64_t *row, const int32_t *col, int32_t n,
+                                                 const int64_t *irow, unsigned long long *cursor,
+                                                 int32_t *icol) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wave; r < n; r += nwaves)
+    for (int64_t e = row[r] + lane_id(); e < row[r + 1]; e += kWave) {
+      const int32_t c = col[e];
+      icol[irow[c] + (int64_t)atomicAdd(&cursor[c], 1ull)] = (int32_t)r;
+    }
+}
+
 }  // namespace
 
 int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -381,6 +405,24 @@ hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *
                           hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_degrees, dim3((n + 255) / 256), dim3(256), 0, st, in_row, order, deg, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, int64_t *irow,
+                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(work, 0, ((size_t)n + 1) * sizeof(int64_t), st);
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipMemsetAsync(irow, 0, sizeof(int64_t), st);
+  int64_t blocks = ((int64_t)n * kWave + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  unsigned long long *cnt = reinterpret_cast<unsigned long long *>(work);
+  hipLaunchKernelGGL(k_in_count, dim3((unsigned)blocks), dim3(256), 0, st, row, col, n, cnt);
+  e = launch_exclusive_scan(work, irow, (int64_t)n + 1, tmp, st);
+  if (e != hipSuccess) return e;
+  e = hipMemsetAsync(work, 0, ((size_t)n + 1) * sizeof(int64_t), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_in_fill, dim3((unsigned)blocks), dim3(256), 0, st, row, col, n, irow, cnt,
+                     icol);
   return hipGetLastError();
 }
 

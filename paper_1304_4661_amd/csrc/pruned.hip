@@ -681,21 +681,25 @@ __global__ void __launch_bounds__(kBlock) k_win_abort_sum(DWindow w, int64_t nca
 
 // Cleaning: candidate (k = s+j, d) of u survives iff no window root j' < j
 // labeled both u and v_k with d(j',u) + d(j',v_k) <= d.  Also marks one
-// candidate per vertex (the lowest j) to commit the vertex's row.
-__global__ void __launch_bounds__(kBlock) k_win_clean(DWindow w, int64_t ncand) {
+// candidate per vertex (the lowest j) to commit the vertex's row.  `o` is
+// the window whose candidates give the v_k side: the same window for an
+// undirected graph; for a directed one the search in the other direction
+// (a forward candidate (k, d(k,u)) is dropped by j' with d(k,j') from the
+// reverse search and d(j',u) from the forward one, and vice versa).
+__global__ void __launch_bounds__(kBlock) k_win_clean(DWindow w, DWindow o, int64_t ncand) {
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncand;
        c += (int64_t)gridDim.x * blockDim.x) {
     const int32_t u = w.cu[c], j = w.cj[c];
     const int d = w.cd[c];
     const int32_t k = w.s + j;
     const uint64_t *cu_row = w.cmask + (int64_t)u * w.words;
-    const uint64_t *ck_row = w.cmask + (int64_t)k * w.words;
+    const uint64_t *ck_row = o.cmask + (int64_t)k * o.words;
     const uint8_t *wu = w.wd + (int64_t)u * (w.words * 64);
-    const uint8_t *wk = w.wd + (int64_t)k * (w.words * 64);
+    const uint8_t *wk = o.wd + (int64_t)k * (o.words * 64);
     const int jw = j >> 6, jb = j & 63;
     uint64_t su[4], sk[4];
     csum_load(w, u, su);
-    csum_load(w, k, sk);
+    csum_load(o, k, sk);
     bool drop = false;
     for (int q = 0; q <= (jw >> 6) && !drop; q++) {
       uint64_t sm = su[q] & sk[q];
@@ -942,9 +946,9 @@ hipError_t launch_win_abort(DGraph /*g*/, DWindow w, int64_t ncand, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_win_clean(DWindow w, int64_t ncand, hipStream_t st) {
+hipError_t launch_win_clean(DWindow w, DWindow o, int64_t ncand, hipStream_t st) {
   if (ncand > 0)
-    hipLaunchKernelGGL(k_win_clean, dim3(grid_for(ncand, kBlock, 8192)), dim3(kBlock), 0, st, w,
+    hipLaunchKernelGGL(k_win_clean, dim3(grid_for(ncand, kBlock, 8192)), dim3(kBlock), 0, st, w, o,
                        ncand);
   return hipGetLastError();
 }

@@ -46,12 +46,12 @@ __global__ void __launch_bounds__(256) k_query_plain(DIndex ix, const int32_t *p
       const int v = bp_pair_dist(ds, ms[0], ms[1], dt, mt[0], mt[1]);
       best = v < best ? v : best;
     }
-    int64_t a = ix.off[rs], b = ix.off[rt];
+    int64_t a = ix.off[rs], b = ix.toff[rt];
     for (;;) {
-      const uint32_t ha = ix.hub[a], hb = ix.hub[b];
+      const uint32_t ha = ix.hub[a], hb = ix.thub[b];
       if (ha == hb) {
         if (ha == kSentinel) break;
-        const int v = (int)ix.dist[a] + (int)ix.dist[b];
+        const int v = (int)ix.dist[a] + (int)ix.tdist[b];
         best = v < best ? v : best;
         a++;
         b++;
@@ -101,11 +101,11 @@ __global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *p
       }
     }
     // (b) merge join by chunks of G entries
-    int64_t a = ix.off[rs], b = ix.off[rt];
-    const int64_t ea = ix.off[rs + 1], eb = ix.off[rt + 1];
+    int64_t a = ix.off[rs], b = ix.toff[rt];
+    const int64_t ea = ix.off[rs + 1], eb = ix.toff[rt + 1];
     for (;;) {
       const uint32_t ha = ix.hub[a + gr < ea ? a + gr : ea - 1];
-      const uint32_t hb = ix.hub[b + gr < eb ? b + gr : eb - 1];
+      const uint32_t hb = ix.thub[b + gr < eb ? b + gr : eb - 1];
       // position of ha among this group's hb values (sorted): halving search
       // for the first index with hb >= ha (or G-1)
       int lo = 0;
@@ -116,7 +116,7 @@ __global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *p
       }
       const uint32_t hf = __shfl(hb, gb + lo);
       if (hf == ha && ha != kSentinel) {
-        const int v = (int)ix.dist[a + gr] + (int)ix.dist[b + lo];
+        const int v = (int)ix.dist[a + gr] + (int)ix.tdist[b + lo];
         best = v < best ? v : best;
       }
       const uint32_t lastA = __shfl(ha, gb + G - 1), lastB = __shfl(hb, gb + G - 1);

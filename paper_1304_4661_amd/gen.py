@@ -378,12 +378,14 @@ def batch_spec(count: int, seed_base: int = 4000, n_lo: float = 1e3, n_hi: float
     return out
 
 
-def pack_batch(graphs: list[Graph]):
+def pack_batch(graphs: list[Graph], order_fn=None):
     """Concatenate graphs into one CSR with global ids.
 
     Returns ``(vtx_off int64[G+1], row_ptr int32[N+1], col int32[nnz],
-    order int32[N])`` where ``order`` holds, for graph ``g``, its local Degree
-    order in ``order[vtx_off[g]:vtx_off[g+1]]`` (local ranks -> local ids)."""
+    order int32[N])`` where ``order`` holds, for graph ``g``, its local order
+    (``order_fn``, default Degree) in ``order[vtx_off[g]:vtx_off[g+1]]``
+    (local ranks -> local ids)."""
+    order_fn = order_fn or degree_order
     G = len(graphs)
     vtx_off = np.zeros(G + 1, dtype=np.int64)
     vtx_off[1:] = np.cumsum([g.n for g in graphs])
@@ -399,7 +401,7 @@ def pack_batch(graphs: list[Graph]):
         v0 = int(vtx_off[gi])
         row_ptr[v0 + 1:v0 + g.n + 1] = g.row_ptr[1:] + e
         col[e:e + len(g.col)] = g.col + v0
-        order[v0:v0 + g.n] = degree_order(g)
+        order[v0:v0 + g.n] = order_fn(g)
         e += len(g.col)
     return vtx_off, row_ptr, col, order
 

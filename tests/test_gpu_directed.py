@@ -1,0 +1,94 @@
+"""GPU directed builds (Section 7) against the oracle, array for array:
+L_OUT (pll_export), L_IN (pll_export_in) and every query answer.  Runs only
+on an MI355X (``-m gpu``)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1304_4661_amd import binding, gen
+from test_gpu_parity import Tuned, all_pairs
+from test_oracle_directed import digraphs
+
+pytestmark = pytest.mark.gpu
+
+
+def _require_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+
+
+def assert_same_directed(gx, ox, tag=""):
+    o = gx.export()
+    i = gx.export_in()
+    assert np.array_equal(o["rank"], ox.rank), tag
+    assert np.array_equal(o["off"], ox.out_off), f"{tag}: L_OUT sizes"
+    assert np.array_equal(o["hub"], ox.out_hub) and np.array_equal(o["dist"], ox.out_dist), tag
+    assert np.array_equal(i["off"], ox.in_off), f"{tag}: L_IN sizes"
+    assert np.array_equal(i["hub"], ox.in_hub) and np.array_equal(i["dist"], ox.in_dist), tag
+
+
+DG = digraphs()
+
+
+@pytest.mark.parametrize("name,g", DG, ids=[x[0] for x in DG])
+@pytest.mark.parametrize("knobs", [{}, dict(window=3, window_work=0), dict(window=1, window_work=0)],
+                         ids=["adaptive", "w3", "w1"])
+def test_directed_families(name, g, knobs):
+    _require_gpu()
+    order = gen.degree_order_directed(g)
+    ox = oracle.build_directed(g.row_ptr, g.col, order)
+    with Tuned(**knobs):
+        gx = binding.build(g.row_ptr, g.col, order, 0, directed=True)
+    assert_same_directed(gx, ox, name)
+    if g.n:
+        p = all_pairs(g.n)
+        want = oracle.query_directed(ox, p)
+        assert np.array_equal(gx.query(p), want)
+        assert np.array_equal(gx.query(p, plain=True), want)
+
+
+def test_directed_rmat_and_overflow():
+    _require_gpu()
+    g = gen.rmat_digraph(12, 8, seed=6)
+    order = gen.degree_order_directed(g)
+    ox = oracle.build_directed(g.row_ptr, g.col, order)
+    pairs = gen.random_pairs(g.n, 50000, 3)
+    want = oracle.query_directed(ox, pairs)
+    for knobs in ({}, dict(window=256, window_work=0), dict(list_cap=1, window=128, window_work=0),
+                  dict(table_cap=8)):
+        with Tuned(**knobs):
+            gx = binding.build(g.row_ptr, g.col, order, 0, directed=True)
+        assert_same_directed(gx, ox, str(knobs))
+        assert np.array_equal(gx.query(pairs), want)
+
+
+def test_symmetric_directed_equals_undirected():
+    _require_gpu()
+    g = gen.ba_graph(500, 3, 21)
+    order = gen.degree_order(g)
+    u = binding.build(g.row_ptr, g.col, order, 0).export()
+    dx = binding.build(g.row_ptr, g.col, order, 0, directed=True)
+    for e in (dx.export(), dx.export_in()):
+        assert np.array_equal(e["off"], u["off"]) and np.array_equal(e["hub"], u["hub"])
+        assert np.array_equal(e["dist"], u["dist"])
+
+
+def test_directed_batch_and_errors():
+    _require_gpu()
+    gs = [gen.er_digraph(50, 0.05, 1), gen.rmat_digraph(9, 8, seed=2), gen.er_digraph(70, 0.03, 4)]
+    vtx_off, rp, col, order = gen.pack_batch(gs, order_fn=gen.degree_order_directed)
+    gx = binding.build_batch(vtx_off, rp, col, order, 0, directed=True)
+    for i, g in enumerate(gs):
+        ox = oracle.build_directed(g.row_ptr, g.col, gen.degree_order_directed(g))
+        e, ei = gx.export(i), gx.export_in(i)
+        assert np.array_equal(e["hub"], ox.out_hub) and np.array_equal(ei["hub"], ox.in_hub)
+        p = all_pairs(g.n)
+        assert np.array_equal(gx.query(p + np.int32(vtx_off[i])), oracle.query_directed(ox, p))
+    assert gx.query(np.array([[0, int(vtx_off[1])]], np.int32))[0] == 255
+    g = gs[0]
+    with pytest.raises(binding.PllError):
+        binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 2, directed=True)
+    with pytest.raises(binding.PllError):
+        binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0, directed=True, parents=True)
+    with pytest.raises(binding.PllError):
+        binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0).export_in()
