@@ -36,6 +36,12 @@ def describe(name, g, t_bp, q):
         return (f"{g.meta['graphs']} Barabasi-Albert graphs, n log-uniform in [1e3, 2e5], "
                 f"m uniform in 2..8, seeded per graph (total n={g.n}, m={g.m}), one packed CSR, "
                 f"Degree order per graph; t_bp={t_bp} per graph; {q} pairs inside the graphs")
+    if g.meta.get("directed"):
+        m = g.meta
+        return (f"directed R-MAT scale {m['scale']}, edge factor {m['edge_factor']}, abcd="
+                f"{m['abcd']}, arcs de-duplicated, no self-loops, largest weakly connected part "
+                f"(n'={g.n}, arcs={len(g.col)}); in+out Degree order; t_bp=0; {q} uniform "
+                f"random pairs")
     if name.startswith("rmat"):
         m = g.meta
         return (f"R-MAT scale {m['scale']}, edge factor {m['edge_factor']}, abcd="
@@ -70,22 +76,30 @@ def level_kernel_bytes(st, t_bp):
             + 5 * st["label_scanned"] + 18 * st["candidates"])
 
 
+def edges_of(g):
+    """Input edges: undirected edges, or arcs of a directed graph."""
+    return len(g.col) if g.meta.get("directed") else g.m
+
+
 def cpu_baseline(g, order, t_bp, pairs):
     """The oracle as it stands: single thread on a host core, full workload."""
     import oracle
 
+    directed = bool(g.meta.get("directed"))
     t0 = time.perf_counter()
-    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    ox = (oracle.build_directed(g.row_ptr, g.col, order) if directed
+          else oracle.build(g.row_ptr, g.col, order, t_bp))
     tb = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.query(ox, pairs)
+    (oracle.query_directed if directed else oracle.query)(ox, pairs)
     tq = time.perf_counter() - t0
+    entries = (len(ox.out_hub) + len(ox.in_hub)) if directed else ox.counters["entries"]
     return {
-        "value": g.m / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
+        "value": edges_of(g) / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
         "sample": (f"whole step on the same workload: oracle index build ({tb:.2f} s) + "
                    f"{len(pairs)} queries ({tq:.2f} s), one thread"),
         "build_s": tb, "queries_per_s": len(pairs) / tq,
-        "entries": ox.counters["entries"],
+        "entries": entries,
     }
 
 
@@ -198,6 +212,7 @@ def main():
         serve(args)
         return
     batch = args.config == "ba256"
+    directed = args.config.endswith("d")
     if batch:
         gs, vtx_off, row_ptr, col, order, t_bp, pairs = gen.batch_workload()
         g = gen.Graph(int(vtx_off[-1]), row_ptr, col, {"kind": "batch", "graphs": len(gs)})
@@ -217,7 +232,7 @@ def main():
         if batch:
             return binding.build_batch(vtx_off, d_row, d_col, d_order, t_bp, stream=stream,
                                        device=True)
-        return binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        return binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, directed=directed)
 
     def step():
         ix = build()
@@ -272,15 +287,15 @@ def main():
 
     out = {
         "metric": METRIC,
-        "value": g.m / (ms_per_step / 1e3),
+        "value": edges_of(g) / (ms_per_step / 1e3),
         "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": describe(args.config, g, t_bp, q), "name": args.config,
-                   "n": g.n, "m": g.m, "t_bp": t_bp, "queries": q},
+                   "n": g.n, "m": edges_of(g), "t_bp": t_bp, "queries": q},
         "build_s": float(np.median(build_s)),
-        "build_edges_per_s": g.m / float(np.median(build_s)),
+        "build_edges_per_s": edges_of(g) / float(np.median(build_s)),
         "queries_per_s": q / (float(np.median(query_ms)) / 1e3),
         "query_batch_ms_p50": pctl(query_ms, 50), "query_batch_ms_p99": pctl(query_ms, 99),
         "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}",
@@ -330,7 +345,7 @@ def main():
             "query_per_s": rates, "build_s_ba2000": bt,
         }
         out["query_latency_host_us"] = lat
-        if not batch:
+        if not batch and not directed:
             out["shortest_paths"] = path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream)
 
     binding.set_tuning("profile", 0)

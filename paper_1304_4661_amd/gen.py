@@ -416,6 +416,8 @@ CONFIGS = {
     "rmat18": ({"kind": "rmat", "scale": 18, "seed": 2}, 50, 1_000_000, 102),
     "rmat20": ({"kind": "rmat", "scale": 20, "seed": 3}, 64, 10_000_000, 103),
     "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 0, 105),
+    # directed (Section 7): R-MAT arcs, no bit-parallel labels
+    "rmat18d": ({"kind": "rmat", "directed": True, "scale": 18, "seed": 2}, 0, 1_000_000, 102),
 }
 
 
@@ -439,6 +441,9 @@ def config_graph(name: str) -> tuple[Graph, np.ndarray, int, np.ndarray]:
     recipe, t_bp, q, pseed = CONFIGS[name]
     if recipe["kind"] == "ba":
         g = ba_graph(recipe["n"], recipe["m"], recipe["seed"])
+    elif recipe.get("directed"):
+        g = rmat_digraph(recipe["scale"], seed=recipe["seed"])
+        return g, degree_order_directed(g), t_bp, random_pairs(g.n, q, pseed)
     else:
         g = rmat_graph(recipe["scale"], seed=recipe["seed"])
     order = degree_order(g)
