@@ -187,6 +187,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--sweep", choices=["tbp", "orders"],
+                    help="analysis instead of the step: t_bp sweep (Fig. 6) or vertex "
+                         "orders (Table 5); one JSON line per point plus a table")
+    ap.add_argument("--sweep-out", default=None, help="markdown table of the sweep")
+    ap.add_argument("--max-random-scale", type=int, default=14,
+                    help="largest R-MAT scale the Random order is built on")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the index "
@@ -210,6 +216,9 @@ def main():
 
     if args.serve:
         serve(args)
+        return
+    if args.sweep:
+        sweep(args)
         return
     batch = args.config == "ba256"
     directed = args.config.endswith("d")
@@ -356,6 +365,91 @@ def main():
             out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(out))
+
+
+def sweep_point(g, order, t_bp, reps, nq=1_000_000):
+    """Build the index reps times from device-resident inputs (median time)
+    and time nq uniform random queries (batched and plain kernels, events on
+    the stream); label sizes and index bytes from the build's counters."""
+    import torch
+
+    from paper_1304_4661_amd import binding, gen
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    d_row = torch.from_numpy(g.row_ptr).to(dev)
+    d_col = torch.from_numpy(g.col).to(dev)
+    d_order = torch.from_numpy(np.ascontiguousarray(order, np.int32)).to(dev)
+    d_pairs = torch.from_numpy(gen.random_pairs(g.n, nq, 11)).to(dev)
+    d_out = torch.empty(nq, dtype=torch.uint8, device=dev)
+    binding.build_device(d_row, d_col, d_order, t_bp, stream=stream).close()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream)
+        ts.append(time.perf_counter() - t1)
+        st = ix.stats()
+        if len(ts) < reps:
+            ix.close()
+    qns = {}
+    for plain in (False, True):
+        ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        qns["plain" if plain else "batched"] = e0.elapsed_time(e1) * 1e6 / (3 * nq)
+    ix.sync()
+    ix.close()
+    return {"n": g.n, "m": g.m, "t_bp": t_bp, "build_s": float(np.median(ts)),
+            "ln_normal": st["entries"] / max(g.n, 1), "ln_bp": t_bp, "bp_vertices": st["bp_used"],
+            "index_bytes": st["index_bytes"], "query_ns_batched": qns["batched"],
+            "query_ns_plain": qns["plain"], "visited": st["visited"]}
+
+
+def sweep(args):
+    """The paper's two parameter studies on synthetic graphs: the number of
+    bit-parallel roots (Fig. 6: build time, query time, normal label size,
+    index size) and the vertex order (Table 5: average label size with no
+    bit-parallel roots, Random / Degree / Closeness)."""
+    from paper_1304_4661_amd import gen
+
+    rows = []
+    if args.sweep == "tbp":
+        graphs_ = [("rmat18", gen.rmat_graph(18, seed=1)), ("ba200k_m4", gen.ba_graph(200_000, 4, 3))]
+        for gname, g in graphs_:
+            order = gen.degree_order(g)
+            for t in (0, 1, 2, 4, 8, 16, 32, 50, 64):
+                r = {"graph": gname, "order": "degree", **sweep_point(g, order, t, args.steps)}
+                rows.append(r)
+                print(json.dumps(r), flush=True)
+        cols = ["graph", "t_bp", "build_s", "query_ns_batched", "query_ns_plain", "ln_normal",
+                "ln_bp", "index_bytes"]
+    else:
+        graphs_ = [(f"rmat{s}", gen.rmat_graph(s, seed=1)) for s in (12, 14, 16, 18)]
+        graphs_.append(("ba200k_m4", gen.ba_graph(200_000, 4, 3)))
+        for gname, g in graphs_:
+            orders = [("degree", gen.degree_order(g)), ("closeness", gen.closeness_order(g, 16, 0))]
+            scale = int(gname[4:]) if gname.startswith("rmat") else 99
+            if scale <= args.max_random_scale:
+                orders.append(("random", gen.random_order(g.n, 0)))
+            for oname, order in orders:
+                r = {"graph": gname, "order": oname, **sweep_point(g, order, 0, args.steps)}
+                rows.append(r)
+                print(json.dumps(r), flush=True)
+        cols = ["graph", "n", "m", "order", "ln_normal", "build_s", "query_ns_batched",
+                "index_bytes"]
+    if args.sweep_out:
+        def fmt(v):
+            return f"{v:.4g}" if isinstance(v, float) else str(v)
+        with open(args.sweep_out, "w") as f:
+            f.write("| " + " | ".join(cols) + " |\n|" + "---|" * len(cols) + "\n")
+            for r in rows:
+                f.write("| " + " | ".join(fmt(r[c]) for c in cols) + " |\n")
 
 
 def path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream, nq=100_000, max_len=32):

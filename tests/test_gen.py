@@ -91,3 +91,17 @@ def test_digraph_generators():
     # in+out degree descending, ties by id
     g2 = gen.digraph_from_edges(4, np.array([0, 1, 2]), np.array([1, 2, 3]))
     assert gen.degree_order_directed(g2).tolist() == [1, 2, 0, 3]
+
+
+def test_closeness_order():
+    from graphs import from_edges
+    # path 0-1-2-3-4: the middle is most central, then its neighbours (ties by id)
+    p = from_edges(5, [(0, 1), (1, 2), (2, 3), (3, 4)])
+    assert gen.closeness_order(p, samples=5).tolist() == [2, 1, 3, 0, 4]
+    # star: the centre first whatever the sample
+    st = from_edges(6, [(0, i) for i in range(1, 6)])
+    assert gen.closeness_order(st, samples=2, seed=3)[0] == 0
+    g = gen.ba_graph(300, 3, 5)
+    o = gen.closeness_order(g, samples=16, seed=1)
+    assert sorted(o.tolist()) == list(range(g.n))
+    assert np.array_equal(o, gen.closeness_order(g, samples=16, seed=1))
