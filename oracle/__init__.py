@@ -11,13 +11,17 @@ from .oracle import (  # noqa: F401
     DirectedIndex,
     OracleError,
     OracleIndex,
+    WINF,
+    WeightedIndex,
     build,
     build_directed,
     build_library,
+    build_weighted,
     load_variant,
     source_text,
     paths,
     query,
     query_directed,
     query_parts,
+    query_weighted,
 )

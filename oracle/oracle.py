@@ -71,6 +71,19 @@ def _configure(lib):
         lib.orc_build_directed.restype = C.c_int
         lib.orc_export_in.argtypes = [C.c_void_p, P, P, P, P]
         lib.orc_export_in.restype = C.c_int
+        lib.orc_build_weighted.argtypes = [C.c_int32, P, P, P, P, C.c_uint32,
+                                           C.POINTER(C.c_void_p)]
+        lib.orc_build_weighted.restype = C.c_int
+        lib.orc_wquery.argtypes = [C.c_void_p, P, C.c_int64, P]
+        lib.orc_wquery.restype = C.c_int
+        lib.orc_wfree.argtypes = [C.c_void_p]
+        lib.orc_wfree.restype = None
+        lib.orc_wncounters.argtypes = []
+        lib.orc_wncounters.restype = C.c_int32
+        lib.orc_wcounters.argtypes = [C.c_void_p, P, C.c_int32]
+        lib.orc_wcounters.restype = C.c_int
+        lib.orc_wexport.argtypes = [C.c_void_p, C.c_int32, P, P, P, P, P]
+        lib.orc_wexport.restype = C.c_int
     return lib
 
 
@@ -282,6 +295,92 @@ def query_directed(ix: DirectedIndex, pairs) -> np.ndarray:
     pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
     out = np.zeros(len(pairs), np.uint8)
     rc = (ix._lib or _load()).orc_query(ix._handle, _ptr(pairs), len(pairs), _ptr(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return out
+
+
+WCOUNTER_NAMES = ["n", "entries", "roots", "settled", "labeled", "edges", "pushes",
+                  "label_scanned", "max_dist"]
+WINF = 0xFFFFFFFF
+
+
+@dataclass
+class WeightedIndex:
+    """Exported oracle index of a weighted graph (Section 7): labels in rank
+    order, no sentinels, uint32 distances; ``in_*`` only for a digraph."""
+    n: int
+    directed: bool
+    rank: np.ndarray
+    off: np.ndarray
+    hub: np.ndarray
+    dist: np.ndarray
+    in_off: np.ndarray | None = None
+    in_hub: np.ndarray | None = None
+    in_dist: np.ndarray | None = None
+    counters: dict = field(default_factory=dict)
+    _handle: C.c_void_p | None = None
+    _lib: object = None
+
+    def close(self):
+        if self._handle is not None:
+            (self._lib or _load()).orc_wfree(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_weighted(row_ptr, col, wgt, order, directed: bool = False,
+                   check_symmetric: bool = True, lib=None) -> WeightedIndex:
+    """Pruned Dijkstra labels (weights uint32 >= 1, one per CSR entry)."""
+    lib = lib or _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    wgt = np.ascontiguousarray(wgt, dtype=np.uint32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    n = len(order)
+    if len(row_ptr) != n + 1 or len(wgt) != len(col):
+        raise OracleError(-1)
+    flags = (2 if directed else 0) | (1 if check_symmetric and not directed else 0)
+    h = C.c_void_p()
+    rc = lib.orc_build_weighted(n, _ptr(row_ptr), _ptr(col), _ptr(wgt), _ptr(order), flags,
+                                C.byref(h))
+    if rc != 0:
+        raise OracleError(rc)
+
+    def side(s):
+        ne = C.c_int64()
+        off = np.zeros(n + 1, np.int64)
+        lib.orc_wexport(h, s, C.byref(ne), _ptr(off), None, None, None)
+        hub = np.zeros(ne.value, np.uint32)
+        dist = np.zeros(ne.value, np.uint32)
+        lib.orc_wexport(h, s, None, None, _ptr(hub), _ptr(dist), None)
+        return off, hub, dist
+
+    rank = np.zeros(n, np.int32)
+    lib.orc_wexport(h, 0, None, None, None, None, _ptr(rank))
+    off, hub, dist = side(0)
+    ix = WeightedIndex(n=n, directed=directed, rank=rank, off=off, hub=hub, dist=dist, _handle=h)
+    ix._lib = lib
+    if directed:
+        ix.in_off, ix.in_hub, ix.in_dist = side(1)
+    nc = lib.orc_wncounters()
+    cnt = np.zeros(nc, np.int64)
+    lib.orc_wcounters(h, _ptr(cnt), nc)
+    ix.counters = {k: int(v) for k, v in zip(WCOUNTER_NAMES, cnt)}
+    return ix
+
+
+def query_weighted(ix: WeightedIndex, pairs) -> np.ndarray:
+    """d(s, t) (along the arcs for a digraph) as uint32; WINF = unreachable
+    or 2^32 - 1 or more away."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(len(pairs), np.uint32)
+    rc = (ix._lib or _load()).orc_wquery(ix._handle, _ptr(pairs), len(pairs), _ptr(out))
     if rc != 0:
         raise OracleError(rc)
     return out

@@ -32,6 +32,11 @@
  *       reaches, pruning with L_OUT(root) and L_IN(u)) and one against them
  *       (labels L_OUT, pruning with L_OUT(u) and L_IN(root)); d(s,t) is the
  *       merge of L_OUT(s) and L_IN(t).
+ *   O8  weighted graphs (Section 7, "Weighted Graphs"): the pruned BFS of
+ *       Algorithm 1 becomes a pruned Dijkstra search (a binary heap, a vertex
+ *       is tested and, if not pruned, labeled and relaxed when it is settled);
+ *       no bit-parallel labels; distances are 32-bit.  Also for digraphs,
+ *       with the two searches of O7.
  *
  * Readings of points the paper leaves open (each one also fixed on the GPU
  * side, so both compute the same bytes):
@@ -1029,5 +1034,385 @@ int orc_export_in(const orc_index *x, int64_t *entries, int64_t *off, uint32_t *
   }
   if (off) off[x->n] = e;
   if (entries) *entries = e;
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O8: weighted graphs (Section 7, "Weighted Graphs")                        */
+/*
+ * Readings:
+ *   - Edge weights are integers >= 1 (a weight of 0 is rejected); distances
+ *     are uint32.  ORC_WINF = 2^32 - 1 means unreachable.
+ *   - A relaxation whose distance would reach ORC_WINF is dropped, so a
+ *     vertex at distance >= ORC_WINF from a root is treated as unreachable
+ *     from it: the labels are exactly the unbounded ones with distance below
+ *     ORC_WINF, and a query answer of ORC_WINF means unreachable or that far.
+ *   - Sums of two distances are formed in 64 bits.
+ */
+
+#define ORC_WINF 0xFFFFFFFFu
+
+typedef struct {
+  uint32_t *hub; /* hub ranks, ascending, then ORC_SENTINEL */
+  uint32_t *dist;
+  int64_t len, cap;
+} orc_wlabel;
+
+enum {
+  W_N = 0,         /* vertices */
+  W_ENTRIES,       /* label entries (both directions of a digraph) */
+  W_ROOTS,         /* pruned searches run (two per root for a digraph) */
+  W_SETTLED,       /* vertices settled (each tested once per search) */
+  W_LABELED,       /* vertices labeled */
+  W_EDGES,         /* adjacency entries relaxed from labeled vertices */
+  W_PUSHES,        /* heap insertions (improvements of a tentative distance) */
+  W_LABEL_SCANNED, /* label entries read by prune tests */
+  W_MAX_DIST,      /* largest stored distance */
+  ORC_WNCOUNTERS
+};
+
+typedef struct orc_windex {
+  int32_t n, directed;
+  int32_t *rank;
+  orc_wlabel *out; /* L of an undirected graph; L_OUT of a digraph */
+  orc_wlabel *in;  /* L_IN of a digraph, else NULL */
+  int64_t cnt[ORC_WNCOUNTERS];
+} orc_windex;
+
+static void wlabel_free_all(orc_wlabel *lab, int32_t n) {
+  if (!lab) return;
+  for (int32_t v = 0; v < n; v++) {
+    free(lab[v].hub);
+    free(lab[v].dist);
+  }
+  free(lab);
+}
+
+void orc_wfree(orc_windex *x) {
+  if (!x) return;
+  wlabel_free_all(x->out, x->n);
+  wlabel_free_all(x->in, x->n);
+  free(x->rank);
+  free(x);
+}
+
+/* Append (h, d) and keep the sentinel after the last entry. */
+static int wlabel_push(orc_wlabel *L, uint32_t h, uint32_t d) {
+  if (L->len + 2 > L->cap) {
+    int64_t nc = L->cap ? 2 * L->cap : 4;
+    uint32_t *nh = (uint32_t *)realloc(L->hub, (size_t)nc * sizeof(uint32_t));
+    if (!nh) return ORC_E_NOMEM;
+    L->hub = nh;
+    uint32_t *nd = (uint32_t *)realloc(L->dist, (size_t)nc * sizeof(uint32_t));
+    if (!nd) return ORC_E_NOMEM;
+    L->dist = nd;
+    L->cap = nc;
+  }
+  L->hub[L->len] = h;
+  L->dist[L->len] = d;
+  L->len++;
+  L->hub[L->len] = ORC_SENTINEL;
+  L->dist[L->len] = ORC_WINF;
+  return ORC_OK;
+}
+
+/* Binary min-heap of (distance, vertex) keys packed as d << 32 | v. */
+typedef struct {
+  uint64_t *a;
+  int64_t len, cap;
+} wheap;
+
+static int wheap_push(wheap *h, uint64_t key) {
+  if (h->len == h->cap) {
+    int64_t nc = h->cap ? 2 * h->cap : 64;
+    uint64_t *na = (uint64_t *)realloc(h->a, (size_t)nc * sizeof(uint64_t));
+    if (!na) return ORC_E_NOMEM;
+    h->a = na;
+    h->cap = nc;
+  }
+  int64_t i = h->len++;
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (h->a[p] <= key) break;
+    h->a[i] = h->a[p];
+    i = p;
+  }
+  h->a[i] = key;
+  return ORC_OK;
+}
+
+static uint64_t wheap_pop(wheap *h) {
+  uint64_t top = h->a[0], last = h->a[--h->len];
+  int64_t i = 0;
+  for (;;) {
+    int64_t c = 2 * i + 1;
+    if (c >= h->len) break;
+    if (c + 1 < h->len && h->a[c + 1] < h->a[c]) c++;
+    if (h->a[c] >= last) break;
+    h->a[i] = h->a[c];
+    i = c;
+  }
+  if (h->len) h->a[i] = last;
+  return top;
+}
+
+/* One pruned Dijkstra search from root k over (off, adj, wgt): settled
+ * vertices are tested against T (the root's labels from tlab, indexed by
+ * hub) and their own labels in `lab`; a vertex that is not pruned gets
+ * (k, d) in `lab` and relaxes its edges.  D, T and settled are all-INF /
+ * zero on entry and on exit. */
+static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const int32_t *adj,
+                           const uint32_t *wgt, orc_wlabel *lab, const orc_wlabel *tlab,
+                           uint32_t *D, uint32_t *T, char *settled, int32_t *touched,
+                           wheap *heap) {
+  int rc = ORC_OK;
+  const orc_wlabel *Lk = &tlab[k];
+  for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
+  int64_t nt = 0;
+  heap->len = 0;
+  D[k] = 0;
+  touched[nt++] = k;
+  rc = wheap_push(heap, (uint64_t)k);
+  x->cnt[W_PUSHES]++;
+  while (rc == ORC_OK && heap->len) {
+    uint64_t key = wheap_pop(heap);
+    int32_t u = (int32_t)(key & 0xFFFFFFFFu);
+    uint32_t d = (uint32_t)(key >> 32);
+    if (settled[u] || d != D[u]) continue; /* stale heap entry */
+    settled[u] = 1;
+    x->cnt[W_SETTLED]++;
+    /* prune test: QUERY(v_k, u) over the labels so far (Section 4.5.1 T) */
+    const orc_wlabel *L = &lab[u];
+    x->cnt[W_LABEL_SCANNED] += L->len;
+    int pruned = 0;
+    for (int64_t i = 0; i < L->len && !pruned; i++) {
+      uint32_t th = T[L->hub[i]];
+      if (th != ORC_WINF && (uint64_t)L->dist[i] + th <= d) pruned = 1;
+    }
+    if (pruned) continue;
+    rc = wlabel_push(&lab[u], (uint32_t)k, d);
+    if (rc != ORC_OK) break;
+    x->cnt[W_LABELED]++;
+    if ((int64_t)d > x->cnt[W_MAX_DIST]) x->cnt[W_MAX_DIST] = d;
+    for (int64_t j = off[u]; j < off[u + 1] && rc == ORC_OK; j++) {
+      int32_t w = adj[j];
+      x->cnt[W_EDGES]++;
+      uint64_t nd = (uint64_t)d + wgt[j];
+      if (nd >= ORC_WINF || settled[w] || nd >= D[w]) continue;
+      if (D[w] == ORC_WINF) touched[nt++] = w;
+      D[w] = (uint32_t)nd;
+      rc = wheap_push(heap, nd << 32 | (uint64_t)w);
+      x->cnt[W_PUSHES]++;
+    }
+  }
+  for (int64_t i = 0; i < nt; i++) {
+    D[touched[i]] = ORC_WINF;
+    settled[touched[i]] = 0;
+  }
+  for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = ORC_WINF;
+  return rc;
+}
+
+typedef struct {
+  int32_t v;
+  uint32_t w;
+} wnbr;
+
+static int cmp_wnbr(const void *a, const void *b) {
+  const wnbr *x = (const wnbr *)a, *y = (const wnbr *)b;
+  if (x->v != y->v) return x->v < y->v ? -1 : 1;
+  return (x->w > y->w) - (x->w < y->w);
+}
+
+/* Rank-space adjacency with weights, each row sorted by (rank, weight). */
+static void weighted_adjacency(const orc_windex *x, const int32_t *row_ptr, const int32_t *col,
+                               const uint32_t *wgt, const int32_t *order, int64_t *off,
+                               int32_t *adj, uint32_t *aw, wnbr *tmp) {
+  int32_t n = x->n;
+  off[0] = 0;
+  for (int32_t r = 0; r < n; r++) {
+    int32_t v = order[r];
+    int64_t deg = row_ptr[v + 1] - row_ptr[v];
+    for (int64_t j = 0; j < deg; j++) {
+      tmp[j].v = x->rank[col[row_ptr[v] + j]];
+      tmp[j].w = wgt[row_ptr[v] + j];
+    }
+    qsort(tmp, (size_t)deg, sizeof(wnbr), cmp_wnbr);
+    for (int64_t j = 0; j < deg; j++) {
+      adj[off[r] + j] = tmp[j].v;
+      aw[off[r] + j] = tmp[j].w;
+    }
+    off[r + 1] = off[r] + deg;
+  }
+}
+
+/* Weighted build.  flags bit 0: check that every edge (u, v, w) has its
+ * reverse (v, u, w) (undirected only); bit 1: the CSR lists out-arcs of a
+ * digraph (labels L_OUT and L_IN, Section 7). */
+int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                       const uint32_t *wgt, const int32_t *order, uint32_t flags,
+                       orc_windex **out) {
+  if (!out) return ORC_E_INVAL;
+  *out = NULL;
+  int rc = validate(n, row_ptr, col, order, 0);
+  if (rc != ORC_OK) return rc;
+  int64_t nnz = n > 0 ? row_ptr[n] : 0;
+  if (nnz > 0 && !wgt) return ORC_E_INVAL;
+  for (int64_t j = 0; j < nnz; j++)
+    if (wgt[j] == 0) return ORC_E_INVAL;
+  int directed = (flags & 2u) != 0;
+  orc_windex *x = (orc_windex *)calloc(1, sizeof(orc_windex));
+  if (!x) return ORC_E_NOMEM;
+  x->n = n;
+  x->directed = directed;
+  int64_t nn = n > 0 ? n : 1, mm = nnz > 0 ? nnz : 1, maxdeg = 1;
+  for (int32_t v = 0; v < n; v++)
+    if (row_ptr[v + 1] - row_ptr[v] > maxdeg) maxdeg = row_ptr[v + 1] - row_ptr[v];
+  x->rank = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  x->out = (orc_wlabel *)calloc((size_t)nn, sizeof(orc_wlabel));
+  if (directed) x->in = (orc_wlabel *)calloc((size_t)nn, sizeof(orc_wlabel));
+  int64_t *off = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+  int32_t *adj = (int32_t *)malloc((size_t)mm * sizeof(int32_t));
+  uint32_t *aw = (uint32_t *)malloc((size_t)mm * sizeof(uint32_t));
+  int64_t *ioff = NULL;
+  int32_t *iadj = NULL;
+  uint32_t *iaw = NULL;
+  wnbr *tmp = (wnbr *)malloc((size_t)maxdeg * sizeof(wnbr));
+  uint32_t *D = (uint32_t *)malloc((size_t)nn * sizeof(uint32_t));
+  uint32_t *T = (uint32_t *)malloc((size_t)nn * sizeof(uint32_t));
+  char *settled = (char *)calloc((size_t)nn, 1);
+  int32_t *touched = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  wheap heap = {NULL, 0, 0};
+  if (!x->rank || !x->out || (directed && !x->in) || !off || !adj || !aw || !tmp || !D || !T ||
+      !settled || !touched) {
+    rc = ORC_E_NOMEM;
+    goto done;
+  }
+  for (int32_t i = 0; i < n; i++) x->rank[order[i]] = i;
+  weighted_adjacency(x, row_ptr, col, wgt, order, off, adj, aw, tmp);
+  if (!directed && (flags & 1u)) {
+    /* every (r, s, w) has (s, r, w): rows are sorted by (rank, weight) */
+    for (int32_t r = 0; r < n && rc == ORC_OK; r++)
+      for (int64_t j = off[r]; j < off[r + 1]; j++) {
+        int32_t s2 = adj[j];
+        int found = 0;
+        for (int64_t i = off[s2]; i < off[s2 + 1] && !found; i++)
+          if (adj[i] == r && aw[i] == aw[j]) found = 1;
+        if (!found) {
+          rc = ORC_E_INVAL;
+          break;
+        }
+      }
+    if (rc != ORC_OK) goto done;
+  }
+  if (directed) {
+    /* transpose: in-arcs of every vertex, sources in ascending rank */
+    ioff = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
+    iadj = (int32_t *)malloc((size_t)mm * sizeof(int32_t));
+    iaw = (uint32_t *)malloc((size_t)mm * sizeof(uint32_t));
+    int64_t *fill = (int64_t *)calloc((size_t)nn, sizeof(int64_t));
+    if (!ioff || !iadj || !iaw || !fill) {
+      free(fill);
+      rc = ORC_E_NOMEM;
+      goto done;
+    }
+    for (int64_t j = 0; j < nnz; j++) ioff[adj[j] + 1]++;
+    for (int32_t r = 0; r < n; r++) ioff[r + 1] += ioff[r];
+    for (int32_t r = 0; r < n; r++)
+      for (int64_t j = off[r]; j < off[r + 1]; j++) {
+        int64_t p = ioff[adj[j]] + fill[adj[j]]++;
+        iadj[p] = r;
+        iaw[p] = aw[j];
+      }
+    free(fill);
+  }
+  for (int32_t r = 0; r < n; r++) {
+    D[r] = ORC_WINF;
+    T[r] = ORC_WINF;
+  }
+  for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
+    if (!directed) {
+      x->cnt[W_ROOTS]++;
+      rc = weighted_search(x, k, off, adj, aw, x->out, x->out, D, T, settled, touched, &heap);
+    } else {
+      /* along the arcs: labels L_IN, root distances from L_OUT(k); then
+       * against them: labels L_OUT, root distances from L_IN(k) */
+      x->cnt[W_ROOTS] += 2;
+      rc = weighted_search(x, k, off, adj, aw, x->in, x->out, D, T, settled, touched, &heap);
+      if (rc == ORC_OK)
+        rc = weighted_search(x, k, ioff, iadj, iaw, x->out, x->in, D, T, settled, touched,
+                             &heap);
+    }
+  }
+  if (rc != ORC_OK) goto done;
+  for (int32_t v = 0; v < n; v++)
+    x->cnt[W_ENTRIES] += x->out[v].len + (directed ? x->in[v].len : 0);
+  x->cnt[W_N] = n;
+  *out = x;
+  x = NULL;
+done:
+  free(off); free(adj); free(aw); free(ioff); free(iadj); free(iaw); free(tmp);
+  free(D); free(T); free(settled); free(touched); free(heap.a);
+  if (x) orc_wfree(x);
+  return rc;
+}
+
+/* QUERY over sorted labels (Section 3.3 merge join), 64-bit sums. */
+static uint32_t wquery_one(const orc_windex *x, int32_t s, int32_t t) {
+  const orc_wlabel *A = &x->out[x->rank[s]];
+  const orc_wlabel *B = x->directed ? &x->in[x->rank[t]] : &x->out[x->rank[t]];
+  uint64_t best = ORC_WINF;
+  if (!A->hub || !B->hub) return ORC_WINF;
+  int64_t i = 0, j = 0;
+  for (;;) {
+    uint32_t ha = A->hub[i], hb = B->hub[j];
+    if (ha == hb) {
+      if (ha == ORC_SENTINEL) break;
+      uint64_t v = (uint64_t)A->dist[i] + B->dist[j];
+      if (v < best) best = v;
+      i++;
+      j++;
+    } else if (ha < hb) {
+      i++;
+    } else {
+      j++;
+    }
+  }
+  return (uint32_t)best;
+}
+
+int orc_wquery(const orc_windex *x, const int32_t *pairs, int64_t q, uint32_t *out) {
+  if (!x || q < 0 || (q > 0 && (!pairs || !out))) return ORC_E_INVAL;
+  for (int64_t i = 0; i < 2 * q; i++)
+    if (pairs[i] < 0 || pairs[i] >= x->n) return ORC_E_INVAL;
+  for (int64_t i = 0; i < q; i++) out[i] = wquery_one(x, pairs[2 * i], pairs[2 * i + 1]);
+  return ORC_OK;
+}
+
+int32_t orc_wncounters(void) { return ORC_WNCOUNTERS; }
+
+int orc_wcounters(const orc_windex *x, int64_t *c, int32_t nc) {
+  if (!x || !c) return ORC_E_INVAL;
+  for (int32_t i = 0; i < nc && i < ORC_WNCOUNTERS; i++) c[i] = x->cnt[i];
+  return ORC_OK;
+}
+
+/* Labels in rank order without sentinels: side 0 = L (L_OUT of a digraph),
+ * side 1 = L_IN.  *entries gets the count; NULL arrays skip the copy. */
+int orc_wexport(const orc_windex *x, int32_t side, int64_t *entries, int64_t *off,
+                uint32_t *hub, uint32_t *dist, int32_t *rank) {
+  if (!x || (side == 1 && !x->in) || side < 0 || side > 1) return ORC_E_INVAL;
+  const orc_wlabel *lab = side ? x->in : x->out;
+  int64_t e = 0;
+  for (int32_t v = 0; v < x->n; v++) {
+    if (off) off[v] = e;
+    const orc_wlabel *L = &lab[v];
+    if (hub && L->len) memcpy(hub + e, L->hub, (size_t)L->len * sizeof(uint32_t));
+    if (dist && L->len) memcpy(dist + e, L->dist, (size_t)L->len * sizeof(uint32_t));
+    e += L->len;
+  }
+  if (off) off[x->n] = e;
+  if (entries) *entries = e;
+  if (rank && x->n) memcpy(rank, x->rank, (size_t)x->n * sizeof(int32_t));
   return ORC_OK;
 }

@@ -40,6 +40,7 @@ __all__ = [
     "degree_order",
     "closeness_order",
     "random_order",
+    "uniform_weights",
     "random_pairs",
     "csr_sha256",
     "pack_batch",
@@ -55,6 +56,7 @@ class Graph:
     row_ptr: np.ndarray  # int32[n+1]
     col: np.ndarray      # int32[nnz]
     meta: dict = field(default_factory=dict)
+    w: np.ndarray | None = None  # uint32[nnz] edge weights of a weighted graph
 
     @property
     def m(self) -> int:
@@ -370,6 +372,24 @@ def random_order(n: int, seed: int) -> np.ndarray:
     return _rng(seed).permutation(n).astype(np.int32)
 
 
+def uniform_weights(g: Graph, lo: int, hi: int, seed: int) -> Graph:
+    """The same graph with integer edge weights drawn i.i.d. uniform in
+    ``[lo, hi]`` (PCG64 ``seed``): one draw per undirected edge, stored on
+    both of its CSR entries, in the order of the edges' (smaller id, larger
+    id) keys; one draw per arc of a digraph, in CSR order."""
+    rows = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    col = g.col.astype(np.int64)
+    r = _rng(seed)
+    if g.meta.get("directed"):
+        w = r.integers(lo, hi + 1, size=len(col), dtype=np.int64)
+    else:
+        key = np.minimum(rows, col) * g.n + np.maximum(rows, col)
+        uniq, inv = np.unique(key, return_inverse=True)
+        w = r.integers(lo, hi + 1, size=len(uniq), dtype=np.int64)[inv]
+    meta = dict(g.meta, weights=(lo, hi, seed))
+    return Graph(g.n, g.row_ptr, g.col, meta, w.astype(np.uint32))
+
+
 def random_pairs(n: int, q: int, seed: int) -> np.ndarray:
     """``q`` pairs, both ends i.i.d. uniform over ``[0, n)`` with replacement
     (``s == t`` allowed), returned as ``int32[q, 2]``."""
@@ -440,6 +460,11 @@ CONFIGS = {
     "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 0, 105),
     # directed (Section 7): R-MAT arcs, no bit-parallel labels
     "rmat18d": ({"kind": "rmat", "directed": True, "scale": 18, "seed": 2}, 0, 1_000_000, 102),
+    # weighted (Section 7): integer weights uniform in [1, 100], no bit-parallel labels
+    "ba2000w": ({"kind": "ba", "n": 2000, "m": 4, "seed": 1, "weights": (1, 100, 7)}, 0,
+                100_000, 101),
+    "rmat18w": ({"kind": "rmat", "scale": 18, "seed": 2, "weights": (1, 100, 8)}, 0,
+                1_000_000, 102),
 }
 
 
@@ -465,9 +490,10 @@ def config_graph(name: str) -> tuple[Graph, np.ndarray, int, np.ndarray]:
         g = ba_graph(recipe["n"], recipe["m"], recipe["seed"])
     elif recipe.get("directed"):
         g = rmat_digraph(recipe["scale"], seed=recipe["seed"])
-        return g, degree_order_directed(g), t_bp, random_pairs(g.n, q, pseed)
     else:
         g = rmat_graph(recipe["scale"], seed=recipe["seed"])
-    order = degree_order(g)
+    order = degree_order_directed(g) if recipe.get("directed") else degree_order(g)
+    if "weights" in recipe:
+        g = uniform_weights(g, *recipe["weights"])
     pairs = random_pairs(g.n, q, pseed)
     return g, order, t_bp, pairs
