@@ -1369,7 +1369,7 @@ static uint32_t wquery_one(const orc_windex *x, int32_t s, int32_t t) {
     if (ha == hb) {
       if (ha == ORC_SENTINEL) break;
       uint64_t v = (uint64_t)A->dist[i] + B->dist[j];
-      if (v < best) best = v;
+      best = v < best ? v : best;
       i++;
       j++;
     } else if (ha < hb) {
