@@ -228,6 +228,51 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);
 
 /*
+ * Weighted graphs (Section 7, "Weighted Graphs"): every vertex, in rank
+ * order, runs a pruned Dijkstra search in place of the pruned BFS; there are
+ * no bit-parallel labels and distances are uint32.
+ *   n, row_ptr, col, order, stream, out: as pll_build (one graph)
+ *   wgt      uint32[row_ptr[n]]: weight of edge col[e], >= 1 (0 is
+ *            PLL_E_INVAL); an undirected graph lists every edge in both
+ *            rows with the same weight (checked under PLL_VALIDATE)
+ *   flags    PLL_DEVICE_PTRS (row_ptr, col, wgt and order on the device),
+ *            PLL_VALIDATE (host pointers only), PLL_PLAIN (one root at a
+ *            time), PLL_DIRECTED (the CSR lists out-arcs; labels L_OUT and
+ *            L_IN as for pll_build); PLL_PARENTS is PLL_E_UNSUPPORTED
+ * A relaxation whose distance would reach 2^32 - 1 is dropped: a vertex that
+ * far from a root counts as unreachable from it, so the labels are the
+ * exact ones with distance below 2^32 - 1 and queries read 2^32 - 1
+ * (PLL_WINF) for pairs that are unreachable or at least that far apart.
+ * Errors: as pll_build.  The index answers only pll_query_weighted,
+ * pll_export_weighted, pll_export_sizes, pll_stats, pll_sync and pll_free
+ * (other calls return PLL_E_UNSUPPORTED).  Always synchronises the stream.
+ */
+#define PLL_WINF 0xFFFFFFFFu
+int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,
+                       const int32_t *order, uint32_t flags, void *stream, pll_index **out);
+
+/*
+ * Distance queries on a weighted index: out[i] = min(d(s_i, t_i), PLL_WINF)
+ * as uint32 (along the arcs for a digraph), merge join of Section 3.3 with
+ * 64-bit sums.  pairs, out: host memory, or device memory under
+ * PLL_DEVICE_PTRS; validation, PLL_SYNC, PLL_PLAIN and errors as
+ * pll_query.  PLL_E_UNSUPPORTED on an unweighted index.
+ */
+int pll_query_weighted(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t *out,
+                       uint32_t flags, void *stream);
+
+/*
+ * Labels of a weighted index in rank order without sentinels: side 0 is L
+ * (L_OUT of a digraph: (h, d) means d(v, h) = d), side 1 is L_IN of a
+ * digraph ((h, d): d(h, v) = d).  entries gets the entry count; off
+ * int64[n+1], hub uint32[entries] (ranks, ascending per vertex), dist
+ * uint32[entries], rank int32[n] (id -> rank); any pointer may be NULL.
+ * PLL_E_UNSUPPORTED on an unweighted index or side 1 of an undirected one.
+ */
+int pll_export_weighted(const pll_index *idx, int32_t side, int64_t *entries, int64_t *off,
+                        uint32_t *hub, uint32_t *dist, int32_t *rank);
+
+/*
  * Work counters of the build (PLL_STAT_* below), for reporting and for the
  * algorithmic-byte model.  Copies min(ncounters, PLL_NSTATS) values.
  */
@@ -260,6 +305,8 @@ enum {
                             visited through them (counted per edge) */
   PLL_STAT_BP_SETS,      /* visits whose bit-parallel test read slot sets */
   PLL_STAT_BP_CHECKS,    /* slot set pairs read by those tests */
+  PLL_STAT_IMPROVED,     /* weighted builds: tentative distances lowered */
+  PLL_STAT_TOUCHED,      /* weighted builds: (root, vertex) entries reached */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);

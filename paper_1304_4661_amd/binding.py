@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpll.so")
 
 OK, E_INVAL, E_NOMEM, E_RANGE, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 INF = 255
+WINF = 0xFFFFFFFF  # weighted distances: unreachable or 2^32 - 1 and more
 MAX_TBP = 64
 DEVICE_PTRS, VALIDATE, SYNC, PLAIN, PARENTS, DIRECTED = 1, 2, 4, 8, 16, 32
 
@@ -24,7 +25,7 @@ STAT_NAMES = [
     "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
     "retries", "bp_visited", "levels", "index_bytes", "build_ns", "bp_ns", "pruned_ns",
     "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
-    "bp_direct", "bp_sets", "bp_checks",
+    "bp_direct", "bp_sets", "bp_checks", "improved", "touched",
 ]
 
 EXPORTED = [
@@ -32,7 +33,8 @@ EXPORTED = [
     "pll_export_sizes", "pll_export", "pll_stats", "pll_level_trace", "pll_free", "pll_strerror",
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
-    "pll_query_path", "pll_export_parents", "pll_export_in",
+    "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
+    "pll_query_weighted", "pll_export_weighted",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -79,6 +81,13 @@ def _lib():
         lib.pll_export_parents.restype = C.c_int
         lib.pll_export_in.argtypes = [P, C.c_int32, P, P, P, P]
         lib.pll_export_in.restype = C.c_int
+        lib.pll_build_weighted.argtypes = [C.c_int32, P, P, P, P, C.c_uint32, P,
+                                           C.POINTER(C.c_void_p)]
+        lib.pll_build_weighted.restype = C.c_int
+        lib.pll_query_weighted.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
+        lib.pll_query_weighted.restype = C.c_int
+        lib.pll_export_weighted.argtypes = [P, C.c_int32, P, P, P, P, P]
+        lib.pll_export_weighted.restype = C.c_int
         lib.pll_level_trace.argtypes = [P, P, C.c_int64]
         lib.pll_level_trace.restype = C.c_int64
         lib.pll_free.argtypes = [P]
@@ -280,6 +289,47 @@ class Index:
                                                  "rank"))), "export")
         return out
 
+    def query_weighted(self, pairs, plain: bool = False) -> np.ndarray:
+        """Weighted index, host arrays: ``pairs`` int32[q, 2] ids ->
+        uint32[q] (WINF: unreachable or too far)."""
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        out = np.zeros(len(pairs), np.uint32)
+        flags = PLAIN if plain else 0
+        _check(_lib().pll_query_weighted(self._h, _ptr(pairs), len(pairs), _ptr(out), flags, None),
+               "query_weighted")
+        return out
+
+    def query_weighted_device(self, pairs, out, stream=None, plain: bool = False,
+                              sync: bool = False):
+        """Weighted index, device tensors: ``pairs`` int32 [q, 2], ``out``
+        int32 [q] (read as uint32) on the GPU; runs on ``stream``."""
+        import torch
+
+        assert pairs.dtype == torch.int32 and out.dtype == torch.int32
+        assert pairs.is_cuda and out.is_cuda and pairs.is_contiguous() and out.is_contiguous()
+        q = out.numel()
+        assert pairs.numel() == 2 * q
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        flags = DEVICE_PTRS | (PLAIN if plain else 0) | (SYNC if sync else 0)
+        _check(_lib().pll_query_weighted(self._h, C.c_void_p(pairs.data_ptr()), q,
+                                         C.c_void_p(out.data_ptr()), flags,
+                                         C.c_void_p(stream.cuda_stream)), "query_weighted_device")
+
+    def export_weighted(self, side: int = 0) -> dict:
+        """Labels of a weighted index in rank order, no sentinels: side 0 is
+        L (L_OUT of a digraph), side 1 L_IN."""
+        n, _, _ = self.sizes(0)
+        ne = C.c_int64()
+        _check(_lib().pll_export_weighted(self._h, int(side), C.byref(ne), None, None, None, None),
+               "export_weighted")
+        out = {"off": np.zeros(n + 1, np.int64), "hub": np.zeros(ne.value, np.uint32),
+               "dist": np.zeros(ne.value, np.uint32), "rank": np.zeros(n, np.int32)}
+        _check(_lib().pll_export_weighted(self._h, int(side), None, _ptr(out["off"]),
+                                          _ptr(out["hub"]), _ptr(out["dist"]), _ptr(out["rank"])),
+               "export_weighted")
+        return out
+
     TRACE_COLS = ["window", "first_root", "roots", "level", "entries", "candidates", "ns"]
 
     def level_trace(self) -> np.ndarray:
@@ -368,6 +418,40 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
     rc = _lib().pll_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp), flags, s,
                           C.byref(h))
     _check(rc, "build")
+    return Index(h)
+
+
+def build_weighted(row_ptr, col, wgt, order, directed: bool = False, plain: bool = False,
+                   validate: bool = False, stream=None, device: bool = False) -> Index:
+    """Pruned Dijkstra index of a weighted graph (Section 7; see
+    include/pll.h).  Host arrays, or torch device tensors with device=True
+    (wgt as int32 or uint32-valued int32 tensor)."""
+    flags = ((VALIDATE if validate else 0) | (PLAIN if plain else 0)
+             | (DIRECTED if directed else 0))
+    h = C.c_void_p()
+    if device:
+        import torch
+
+        for a in (row_ptr, col, order, wgt):
+            assert a.dtype == torch.int32 and a.is_cuda and a.is_contiguous()
+        n = order.numel()
+        if row_ptr.numel() != n + 1 or wgt.numel() != col.numel():
+            raise PllError(E_INVAL, "build_weighted: array lengths")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        args = [C.c_void_p(a.data_ptr()) for a in (row_ptr, col, wgt, order)]
+        flags |= DEVICE_PTRS
+    else:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        wgt = np.ascontiguousarray(wgt, dtype=np.uint32)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        n = len(order)
+        if len(row_ptr) != n + 1 or len(wgt) != len(col):
+            raise PllError(E_INVAL, "build_weighted: array lengths")
+        args = [_ptr(row_ptr), _ptr(col), _ptr(wgt), _ptr(order)]
+    s = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(_lib().pll_build_weighted(n, *args, flags, s, C.byref(h)), "build_weighted")
     return Index(h)
 
 

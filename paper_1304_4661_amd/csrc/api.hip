@@ -186,6 +186,10 @@ struct pll_index {
   DBuf<int64_t> grow;
   DBuf<int32_t> gcol;
   DBuf<int32_t> ord;
+  // a weighted graph (pll_build_weighted): labels as packed entries
+  // hub << 32 | distance at off (L, or L_OUT of a digraph) and ioff (L_IN)
+  bool weighted = false;
+  DBuf<uint64_t> went, iwent;
   int64_t entries = 0;
   int64_t stats[PLL_NSTATS] = {};
   std::vector<int64_t> level_trace;  // pruned-phase levels, PLL_TRACE_COLS per row
@@ -210,6 +214,8 @@ struct pll_index {
     v.grow = grow.p;
     v.gcol = gcol.p;
     v.ord = ord.p;
+    v.went = went.p;
+    v.twent = directed ? iwent.p : went.p;
     return v;
   }
 };
@@ -824,6 +830,470 @@ struct Builder {
   }
 };
 
+// ---------------------------------------------------------------------------
+// Weighted graphs (Section 7): pruned Dijkstra searches in root windows
+// (weighted.hip), 32-bit distances, no bit-parallel labels.
+
+// Pinned host copy of a weighted window's control block and its store's
+// pool top, read back with one synchronisation.
+struct WMirrorData {
+  WCtl ctl;
+  unsigned long long top;
+};
+struct WMirror {
+  WMirrorData *p = nullptr;
+  WMirror() {
+    if (hipHostMalloc((void **)&p, sizeof(WMirrorData), hipHostMallocDefault) != hipSuccess) {
+      p = nullptr;
+      throw Fail{PLL_E_NOMEM};
+    }
+  }
+  ~WMirror() {
+    if (p) (void)hipHostFree(p);
+  }
+  WMirror(const WMirror &) = delete;
+  WMirror &operator=(const WMirror &) = delete;
+};
+
+constexpr int32_t kMaxWWindow = 4096;  // roots per weighted window (64 mask words)
+
+struct WBuilder {
+  hipStream_t st;
+  Tuning tu;
+  bool plain = false, directed = false;
+  int32_t n = 0;
+  int64_t nnz = 0;
+  DBuf<int64_t> row, irow;
+  DBuf<int32_t> col, icol;
+  DBuf<uint32_t> wt, iwt;
+  int64_t stat_windows = 0, stat_retries = 0, stat_steps = 0, stat_proc = 0, stat_tests = 0,
+          stat_scanned = 0, stat_edges = 0, stat_improved = 0, stat_cand = 0, stat_touched = 0,
+          stat_level_ns = 0;
+
+  struct WStore {
+    DBuf<int64_t> off;
+    DBuf<int32_t> len, cap;
+    DBuf<uint64_t> ent;
+    DBuf<unsigned long long> top;
+    int64_t pool_cap = 0;
+    int64_t entries = 0;  // committed so far (host count)
+    DWStore view() const { return DWStore{off.p, len.p, cap.p, ent.p, top.p, pool_cap}; }
+  };
+
+  // One search direction: the graph it follows, the store it labels, the
+  // store its root tables come from, and its window state.
+  struct WSide {
+    DWGraph g;
+    WStore *own = nullptr, *roots = nullptr;
+    int64_t htcap = 0, fcap = 0, tcap = 0, ccap = 0;
+    int32_t wmax = 0;
+    DBuf<uint32_t> td, cd;
+    DBuf<uint8_t> fl, cdes;
+    DBuf<uint64_t> ht, lm, km, lsum;
+    DBuf<int64_t> htoff, hsize, htmp;
+    DBuf<int32_t> fj0, fu0, fj1, fu1, tj, tu, cj, cu;
+    DBuf<WCtl> ctl;
+    WMirror mirror;
+    DWWindow window(int32_t s, int32_t W, int32_t nn) const {
+      DWWindow w;
+      w.s = s;
+      w.W = W;
+      w.n = nn;
+      w.words = (W + 63) / 64;
+      w.td = td.p;
+      w.fl = fl.p;
+      w.ht = ht.p;
+      w.htoff = htoff.p;
+      w.htcap = htcap;
+      w.lm = lm.p;
+      w.km = km.p;
+      w.lsum = lsum.p;
+      w.fj0 = fj0.p;
+      w.fu0 = fu0.p;
+      w.fj1 = fj1.p;
+      w.fu1 = fu1.p;
+      w.fcap = fcap;
+      w.tj = tj.p;
+      w.tu = tu.p;
+      w.tcap = tcap;
+      w.cj = cj.p;
+      w.cu = cu.p;
+      w.cd = cd.p;
+      w.cdes = cdes.p;
+      w.ccap = ccap;
+      w.ctl = ctl.p;
+      return w;
+    }
+  };
+
+  void store_init(WStore &S, int64_t pool_cap) {
+    S.off.alloc((size_t)n);
+    S.len.alloc((size_t)n);
+    S.cap.alloc((size_t)n);
+    fill(S.off, 0, st);
+    fill(S.len, 0, st);
+    fill(S.cap, 0, st);
+    S.pool_cap = pool_cap;
+    S.ent.alloc((size_t)pool_cap);
+    S.top.alloc(1);
+    fill(S.top, 0, st);
+  }
+
+  // Grow the pool so that committing ncand candidates cannot run out (a
+  // vertex that grows takes at most 2*(len+new)+16 slots).
+  void store_reserve(WStore &S, int64_t ncand, unsigned long long htop) {
+    const int64_t need = 2 * (S.entries + ncand) + 16 * ncand + 64;
+    if (S.pool_cap - (int64_t)htop >= need) return;
+    const int64_t ncap = std::max<int64_t>(2 * S.pool_cap, (int64_t)htop + 2 * need);
+    DBuf<uint64_t> ne((size_t)ncap);
+    check(hipMemcpyAsync(ne.p, S.ent.p, (size_t)htop * sizeof(uint64_t), hipMemcpyDeviceToDevice,
+                         st));
+    check(hipStreamSynchronize(st));
+    S.ent = std::move(ne);
+    S.pool_cap = ncap;
+  }
+
+  void side_init(WSide &D, DWGraph g, WStore *own, WStore *roots, int32_t wmax) {
+    D.g = g;
+    D.own = own;
+    D.roots = roots;
+    D.wmax = wmax;
+    const int64_t cells = (int64_t)wmax * n;
+    D.td.alloc((size_t)cells);
+    fill(D.td, 0xFF, st);
+    D.fl.alloc((size_t)((cells + 3) & ~(int64_t)3));
+    fill(D.fl, 0, st);
+    const int64_t words = (wmax + 63) / 64;
+    D.lm.alloc((size_t)n * words);
+    D.km.alloc((size_t)n * words);
+    D.lsum.alloc((size_t)n);
+    fill(D.lm, 0, st);
+    fill(D.km, 0, st);
+    fill(D.lsum, 0, st);
+    D.htcap = tu.table_cap > 0 ? tu.table_cap : std::max<int64_t>(1 << 20, 64 * (int64_t)wmax);
+    D.ht.alloc((size_t)D.htcap);
+    D.htoff.alloc((size_t)wmax + 1);
+    D.hsize.alloc((size_t)wmax + 1);
+    D.htmp.alloc((size_t)scan_tmp_elems((int64_t)wmax + 1));
+    // every list holds at least one root's worth (n entries), so one root
+    // always fits
+    const int64_t budget = tu.list_cap > 0 ? tu.list_cap : (int64_t)1 << 25;
+    const int64_t cap = std::max<int64_t>(std::max<int64_t>(n, 1), std::min<int64_t>(cells, budget));
+    D.fcap = D.tcap = D.ccap = cap;
+    D.fj0.alloc((size_t)cap);
+    D.fu0.alloc((size_t)cap);
+    D.fj1.alloc((size_t)cap);
+    D.fu1.alloc((size_t)cap);
+    D.tj.alloc((size_t)cap);
+    D.tu.alloc((size_t)cap);
+    D.cj.alloc((size_t)cap);
+    D.cu.alloc((size_t)cap);
+    D.cd.alloc((size_t)cap);
+    D.cdes.alloc((size_t)cap);
+    D.ctl.alloc(1);
+  }
+
+  // Back to the all-clear state after an aborted window (lists may have
+  // overflowed, so no reset list can be trusted).
+  void side_clear(WSide &D, int32_t W) {
+    const int64_t cells = (int64_t)W * n;
+    check(hipMemsetAsync(D.td.p, 0xFF, (size_t)cells * sizeof(uint32_t), st));
+    check(hipMemsetAsync(D.fl.p, 0, (size_t)((cells + 3) & ~(int64_t)3), st));
+    fill(D.lm, 0, st);
+    fill(D.km, 0, st);
+    fill(D.lsum, 0, st);
+  }
+
+  void pruned(pll_index *ix) {
+    const int nsides = directed ? 2 : 1;
+    WStore stores[2];
+    const int64_t pool0 = std::max<int64_t>(1 << 16, 8 * (int64_t)n);
+    for (int k = 0; k < nsides; k++) store_init(stores[k], pool0);
+    // memory: td and fl take 5 bytes per (root, vertex) cell per side
+    const int64_t mem = std::max<int64_t>(1, tu.window_mem_mb) << 20;
+    const int64_t per_root = 5 * (int64_t)std::max(n, 1) * nsides;
+    int32_t wmax = (int32_t)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)tu.window, (int64_t)kMaxWWindow, mem / per_root,
+                              (int64_t)std::max(n, 1)}));
+    if (plain) wmax = 1;
+    WSide sides[2];
+    // an undirected graph: one side labeling L with tables from L.  A
+    // digraph: side 0 follows the arcs (labels L_IN of what it reaches,
+    // tables from L_OUT(root)), side 1 follows them backwards (labels L_OUT,
+    // tables from L_IN(root)).
+    const DWGraph gf{n, row.p, col.p, wt.p};
+    if (!directed) {
+      side_init(sides[0], gf, &stores[0], &stores[0], wmax);
+    } else {
+      const DWGraph gr{n, irow.p, icol.p, iwt.p};
+      side_init(sides[0], gf, &stores[1], &stores[0], wmax);
+      side_init(sides[1], gr, &stores[0], &stores[1], wmax);
+    }
+    check(hipStreamSynchronize(st));
+    const int64_t target = std::max<int64_t>(1, tu.window_work / 8);
+    int32_t W = plain ? 1 : std::min<int32_t>(wmax, 64);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (tu.profile) {
+      check(hipEventCreate(&ev0));
+      check(hipEventCreate(&ev1));
+    }
+    struct EvGuard {
+      hipEvent_t a, b;
+      ~EvGuard() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+      }
+    } evg{ev0, ev1};
+    int32_t s = 0;
+    while (s < n) {
+      const int32_t nr = std::min<int32_t>(W, n - s);
+      DWWindow win[2];
+      for (int k = 0; k < nsides; k++) {
+        win[k] = sides[k].window(s, nr, n);
+        check(launch_ww_reset_ctl(sides[k].ctl.p, st));
+        check(launch_ww_init(sides[k].roots->view(), win[k], sides[k].hsize.p, sides[k].htmp.p,
+                             st));
+      }
+      // steps until every side's frontier is empty
+      int cur = 0;
+      int32_t flags = 0;
+      int64_t wsteps = 0;
+      if (ev0) check(hipEventRecord(ev0, st));
+      for (;;) {
+        // step i settles every entry whose search path has at most i edges,
+        // so n + 1 steps always suffice
+        if (wsteps > (int64_t)n + 1 + tu.levels_per_sync) throw Fail{PLL_E_DEVICE};
+        wsteps += tu.levels_per_sync;
+        for (int b = 0; b < tu.levels_per_sync; b++) {
+          for (int k = 0; k < nsides; k++) {
+            check(launch_ww_zero_list(sides[k].ctl.p, cur ^ 1, st));
+            check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.xgroup, st));
+          }
+          cur ^= 1;
+          stat_steps++;
+        }
+        for (int k = 0; k < nsides; k++)
+          check(hipMemcpyAsync(&sides[k].mirror.p->ctl, sides[k].ctl.p, sizeof(WCtl),
+                               hipMemcpyDeviceToHost, st));
+        check(hipStreamSynchronize(st));
+        bool more = false;
+        for (int k = 0; k < nsides; k++) {
+          flags |= sides[k].mirror.p->ctl.flags;
+          more |= sides[k].mirror.p->ctl.fcnt[cur] != 0;
+        }
+        if (flags || !more) break;
+      }
+      if (ev1) {
+        check(hipEventRecord(ev1, st));
+        check(hipEventSynchronize(ev1));
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, ev0, ev1));
+        stat_level_ns += (int64_t)(ms * 1e6);
+      }
+      if (!flags) {
+        for (int k = 0; k < nsides; k++) check(launch_ww_collect(win[k], st));
+        for (int k = 0; k < nsides; k++) check(launch_ww_clean(win[k], win[nsides - 1 - k], st));
+        for (int k = 0; k < nsides; k++) {
+          check(hipMemcpyAsync(&sides[k].mirror.p->ctl, sides[k].ctl.p, sizeof(WCtl),
+                               hipMemcpyDeviceToHost, st));
+          check(hipMemcpyAsync(&sides[k].mirror.p->top, sides[k].own->top.p,
+                               sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+        }
+        check(hipStreamSynchronize(st));
+        for (int k = 0; k < nsides; k++) flags |= sides[k].mirror.p->ctl.flags;
+      }
+      if (flags) {
+        // run the window again: bigger tables, or fewer roots
+        stat_retries++;
+        for (int k = 0; k < nsides; k++) side_clear(sides[k], nr);
+        if (flags & kWOvfHash) {
+          for (int k = 0; k < nsides; k++) {
+            WSide &D = sides[k];
+            const int64_t want = (int64_t)D.mirror.p->ctl.httotal;
+            if (want > D.htcap) {
+              D.htcap = std::max<int64_t>(2 * D.htcap, want + want / 2);
+              D.ht.alloc((size_t)D.htcap);
+            }
+          }
+        } else if (W > 1) {
+          W = std::max<int32_t>(1, W / 4);
+        } else {
+          throw Fail{PLL_E_NOMEM};  // one root's lists cannot overflow
+        }
+        check(hipStreamSynchronize(st));
+        continue;
+      }
+      for (int k = 0; k < nsides; k++)
+        store_reserve(*sides[k].own, (int64_t)sides[k].mirror.p->ctl.ccnt,
+                      sides[k].mirror.p->top);
+      for (int k = 0; k < nsides; k++) check(launch_ww_commit(win[k], sides[k].own->view(), st));
+      for (int k = 0; k < nsides; k++) check(launch_ww_reset(win[k], st));
+      int64_t touched = 0;
+      for (int k = 0; k < nsides; k++) {
+        const WCtl &c = sides[k].mirror.p->ctl;
+        sides[k].own->entries += (int64_t)c.survivors;
+        stat_proc += (int64_t)c.processed;
+        stat_tests += (int64_t)c.tests;
+        stat_scanned += (int64_t)c.scanned;
+        stat_edges += (int64_t)c.edges;
+        stat_improved += (int64_t)c.improved;
+        stat_cand += (int64_t)c.ccnt;
+        touched += (int64_t)c.tcnt;
+      }
+      stat_touched += touched;
+      stat_windows++;
+      s += nr;
+      if (!plain) {
+        // aim the next window at `target` touched entries
+        int64_t nw = touched > 0 ? (int64_t)((double)W * target / (double)touched) : 4 * (int64_t)W;
+        nw = std::max<int64_t>(nw, std::max<int64_t>(1, W / 4));
+        nw = std::min<int64_t>(nw, 4 * (int64_t)W);
+        W = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nw, wmax));
+      }
+    }
+    check(hipStreamSynchronize(st));
+    // final CSR with sentinels: L (or L_OUT) at off/went, L_IN at ioff/iwent
+    ix->entries = 0;
+    for (int k = 0; k < nsides; k++) {
+      WStore &S = stores[k];
+      const bool in_side = directed && k == 1;
+      DBuf<int64_t> &foff = in_side ? ix->ioff : ix->off;
+      DBuf<uint64_t> &fent = in_side ? ix->iwent : ix->went;
+      DBuf<int64_t> cnt((size_t)std::max(n, 1)), tmp((size_t)scan_tmp_elems(n));
+      foff.alloc((size_t)n + 1);
+      check(launch_wfinal_count(S.len.p, cnt.p, n, st));
+      check(launch_exclusive_scan(cnt.p, foff.p, n, tmp.p, st));
+      int64_t total = 0;
+      if (n > 0) d2h(&total, foff.p + n, 1, st);
+      check(hipStreamSynchronize(st));
+      fent.alloc((size_t)std::max<int64_t>(total, 1));
+      check(launch_wfinal_copy(S.view(), foff.p, fent.p, n, st));
+      check(hipStreamSynchronize(st));
+      ix->entries += total - n;
+    }
+  }
+};
+
+// Host-side checks of a weighted graph: weights >= 1 and, for an undirected
+// graph under PLL_VALIDATE, every (u, v, w) matched by (v, u, w).
+int validate_weights(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,
+                     bool symmetric) {
+  const int64_t nnz = n > 0 ? row_ptr[n] : 0;
+  if (nnz > 0 && !wgt) return PLL_E_INVAL;
+  for (int64_t j = 0; j < nnz; j++)
+    if (wgt[j] == 0) return PLL_E_INVAL;
+  if (!symmetric) return PLL_OK;
+  std::vector<std::pair<int32_t, uint32_t>> e((size_t)nnz);
+  for (int64_t j = 0; j < nnz; j++) e[j] = {col[j], wgt[j]};
+  for (int32_t v = 0; v < n; v++) std::sort(e.begin() + row_ptr[v], e.begin() + row_ptr[v + 1]);
+  for (int32_t v = 0; v < n; v++)
+    for (int32_t j = row_ptr[v]; j < row_ptr[v + 1]; j++) {
+      const int32_t u = e[j].first;
+      if (!std::binary_search(e.begin() + row_ptr[u], e.begin() + row_ptr[u + 1],
+                              std::make_pair(v, e[j].second)))
+        return PLL_E_INVAL;
+    }
+  return PLL_OK;
+}
+
+int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,
+                   const int32_t *order, int64_t nnz, uint32_t flags, hipStream_t st,
+                   pll_index *ix) {
+  const auto t0 = Clock::now();
+  const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  WBuilder wb;
+  wb.st = st;
+  wb.tu = tuning();
+  wb.plain = (flags & PLL_PLAIN) != 0;
+  wb.directed = (flags & PLL_DIRECTED) != 0;
+  wb.n = n;
+  wb.nnz = nnz;
+  ix->weighted = true;
+  ix->directed = wb.directed;
+  ix->n = n;
+  ix->t = 0;
+  // inputs on the device (copies of host arrays)
+  DBuf<int32_t> h_row, h_col, h_order;
+  DBuf<uint32_t> h_w;
+  const int32_t *d_row = row_ptr, *d_col = col, *d_order = order;
+  const uint32_t *d_w = wgt;
+  if (!device) {
+    h_row.alloc((size_t)n + 1);
+    h_col.alloc((size_t)std::max<int64_t>(nnz, 1));
+    h_order.alloc((size_t)std::max(n, 1));
+    h_w.alloc((size_t)std::max<int64_t>(nnz, 1));
+    h2d(h_row.p, row_ptr, (size_t)n + 1, st);
+    h2d(h_col.p, col, (size_t)nnz, st);
+    h2d(h_order.p, order, (size_t)n, st);
+    h2d(h_w.p, wgt, (size_t)nnz, st);
+    d_row = h_row.p;
+    d_col = h_col.p;
+    d_order = h_order.p;
+    d_w = h_w.p;
+  }
+  // a1: ranks and the rank-space CSR (the unweighted relabel), weights
+  // moved along with their edges
+  {
+    Builder b;
+    b.st = st;
+    b.tu = wb.tu;
+    b.G = 1;
+    b.vtx_off = {0, (int64_t)n};
+    b.n = n;
+    b.t = 0;
+    b.nwords = (n + 31) / 32;
+    b.nnz = nnz;
+    b.relabel(d_row, d_col, d_order, true, ix, nullptr);
+    wb.row = std::move(b.row);
+    wb.col = std::move(b.col);
+  }
+  wb.wt.alloc((size_t)std::max<int64_t>(nnz, 1));
+  check(launch_relabel_weights(d_row, d_w, d_order, wb.row.p, wb.wt.p, n, st));
+  if (wb.directed) {
+    wb.irow.alloc((size_t)n + 1);
+    wb.icol.alloc((size_t)std::max<int64_t>(nnz, 1));
+    wb.iwt.alloc((size_t)std::max<int64_t>(nnz, 1));
+    DBuf<int64_t> work((size_t)n + 1), tmp((size_t)scan_tmp_elems((int64_t)n + 1));
+    check(launch_transpose(wb.row.p, wb.col.p, n, wb.irow.p, wb.icol.p, work.p, tmp.p, st, wb.wt.p,
+                           wb.iwt.p));
+  }
+  check(hipStreamSynchronize(st));
+  h_row.reset();
+  h_col.reset();
+  h_order.reset();
+  h_w.reset();
+  const auto t2 = Clock::now();
+  wb.pruned(ix);
+  const int64_t pr_ns = ns_since(t2);
+  ix->err.alloc(1);
+  check(hipMemsetAsync(ix->err.p, 0, sizeof(int32_t), st));
+  ix->g_entries.assign(1, ix->entries);
+  ix->hoff.clear();
+  check(hipStreamSynchronize(st));
+  int64_t *S = ix->stats;
+  S[PLL_STAT_N] = n;
+  S[PLL_STAT_TBP] = 0;
+  S[PLL_STAT_ENTRIES] = ix->entries;
+  S[PLL_STAT_ROOTS] = (int64_t)n * (wb.directed ? 2 : 1);
+  S[PLL_STAT_VISITED] = wb.stat_proc;
+  S[PLL_STAT_CANDIDATES] = wb.stat_cand;
+  S[PLL_STAT_WINDOWS] = wb.stat_windows;
+  S[PLL_STAT_RETRIES] = wb.stat_retries;
+  S[PLL_STAT_LEVELS] = wb.stat_steps;
+  S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->off.bytes() + ix->went.bytes() +
+                                      ix->ioff.bytes() + ix->iwent.bytes());
+  S[PLL_STAT_PRUNED_NS] = pr_ns;
+  S[PLL_STAT_NORMAL_TESTS] = wb.stat_tests;
+  S[PLL_STAT_LABEL_SCANNED] = wb.stat_scanned;
+  S[PLL_STAT_EDGES] = wb.stat_edges;
+  S[PLL_STAT_LEVEL_LAUNCHES] = wb.stat_steps;
+  S[PLL_STAT_LEVEL_NS] = wb.stat_level_ns;
+  S[PLL_STAT_IMPROVED] = wb.stat_improved;
+  S[PLL_STAT_TOUCHED] = wb.stat_touched;
+  S[PLL_STAT_BUILD_NS] = ns_since(t0);
+  return PLL_OK;
+}
+
 int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *row_ptr,
                  const int32_t *col, const int32_t *order, int64_t nnz, int32_t t_bp,
                  uint32_t flags, hipStream_t st, pll_index *ix, DBuf<int64_t> *d_vtx_off,
@@ -935,6 +1405,7 @@ int guarded(F &&fn) {
 namespace pll {
 DIndex index_view(const pll_index *idx) { return idx->view(); }
 int32_t index_n(const pll_index *idx) { return idx->n; }
+bool index_weighted(const pll_index *idx) { return idx->weighted; }
 int64_t query_group_size() { return tuning().qgroup; }
 int64_t serve_coalesce() { return tuning().serve_coalesce; }
 }  // namespace pll
@@ -1037,9 +1508,148 @@ int pll_build_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, c
   return build_entry(G, vtx_off, row_ptr, col, order, t_bp, flags, stream, out);
 }
 
+int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,
+                       const int32_t *order, uint32_t flags, void *stream, pll_index **out) {
+  if (!out) return PLL_E_INVAL;
+  *out = nullptr;
+  if (n < 0) return PLL_E_INVAL;
+  if (flags & PLL_PARENTS) return PLL_E_UNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
+  const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  const bool directed = (flags & PLL_DIRECTED) != 0;
+  int64_t nnz = 0;
+  if (!device) {
+    const int64_t voff[2] = {0, n};
+    int rc = validate_batch(1, voff, row_ptr, col, order, 0, false);
+    if (rc != PLL_OK) return rc;
+    nnz = n > 0 ? row_ptr[n] : 0;
+    rc = validate_weights(n, row_ptr, col, wgt, (flags & PLL_VALIDATE) != 0 && !directed);
+    if (rc != PLL_OK) return rc;
+  } else {
+    if (flags & PLL_VALIDATE) return PLL_E_UNSUPPORTED;
+    if (n > 0 && (!row_ptr || !order)) return PLL_E_INVAL;
+    if (n > 0) {
+      int rc = guarded([&] {
+        int32_t hn = 0, h0 = 0;
+        d2h(&hn, row_ptr + n, 1, st);
+        d2h(&h0, row_ptr, 1, st);
+        check(hipStreamSynchronize(st));
+        nnz = hn;
+        if (h0 != 0 || nnz < 0 || (nnz > 0 && (!col || !wgt))) return PLL_E_INVAL;
+        const std::vector<int64_t> voff = {0, (int64_t)n};
+        DBuf<int64_t> d_voff(2);
+        h2d(d_voff.p, voff.data(), 2, st);
+        DBuf<int32_t> gid((size_t)n);
+        check(launch_fill_gid(d_voff.p, 1, gid.p, st));
+        DBuf<uint32_t> seen((size_t)(n + 31) / 32);
+        DBuf<int32_t> err(1);
+        fill(seen, 0, st);
+        fill(err, 0, st);
+        check(launch_validate_graph(n, row_ptr, col, order, gid.p, d_voff.p, seen.p, err.p, st));
+        check(launch_validate_weights(wgt, nnz, err.p, st));
+        int32_t herr = 0;
+        d2h(&herr, err.p, 1, st);
+        check(hipStreamSynchronize(st));
+        return herr ? PLL_E_INVAL : PLL_OK;
+      });
+      if (rc != PLL_OK) return rc;
+    }
+  }
+  pll_index *ix = new (std::nothrow) pll_index();
+  if (!ix) return PLL_E_NOMEM;
+  int rc = guarded([&] { return build_weighted(n, row_ptr, col, wgt, order, nnz, flags, st, ix); });
+  if (rc != PLL_OK) {
+    (void)hipStreamSynchronize(st);
+    delete ix;
+    return rc;
+  }
+  *out = ix;
+  return PLL_OK;
+}
+
+int pll_query_weighted(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t *out,
+                       uint32_t flags, void *stream) {
+  if (!idx || q < 0) return PLL_E_INVAL;
+  if (!idx->weighted) return PLL_E_UNSUPPORTED;
+  if (q == 0) return PLL_OK;
+  if (!pairs || !out) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
+  const Tuning tu = tuning();
+  const bool plain = (flags & PLL_PLAIN) != 0;
+  if (!(flags & PLL_DEVICE_PTRS)) {
+    for (int64_t i = 0; i < 2 * q; i++)
+      if (pairs[i] < 0 || pairs[i] >= idx->n) return PLL_E_INVAL;
+    return guarded([&] {
+      DBuf<int32_t> dp((size_t)(2 * q));
+      DBuf<uint32_t> dout((size_t)q);
+      h2d(dp.p, pairs, (size_t)(2 * q), st);
+      check(launch_wquery(idx->view(), dp.p, q, dout.p, nullptr, plain, tu.qgroup, st));
+      d2h(out, dout.p, (size_t)q, st);
+      check(hipStreamSynchronize(st));
+      return PLL_OK;
+    });
+  }
+  return guarded([&] {
+    int32_t *err = nullptr;
+    check(hipMallocAsync((void **)&err, sizeof(int32_t), st));
+    check(hipMemsetAsync(err, 0, sizeof(int32_t), st));
+    check(launch_validate_pairs(pairs, q, idx->n, err, st));
+    check(launch_wquery(idx->view(), pairs, q, out, err, plain, tu.qgroup, st));
+    int32_t herr = 0;
+    if (flags & PLL_SYNC) {
+      check(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+      check(hipFreeAsync(err, st));
+      check(hipStreamSynchronize(st));
+      return herr ? PLL_E_INVAL : PLL_OK;
+    }
+    check(launch_or_flag(err, idx->err.p, st));
+    check(hipFreeAsync(err, st));
+    return PLL_OK;
+  });
+}
+
+int pll_export_weighted(const pll_index *idx, int32_t side, int64_t *entries, int64_t *off,
+                        uint32_t *hub, uint32_t *dist, int32_t *rank) {
+  if (!idx || side < 0 || side > 1) return PLL_E_INVAL;
+  if (!idx->weighted || (side == 1 && !idx->directed)) return PLL_E_UNSUPPORTED;
+  return guarded([&] {
+    hipStream_t st = nullptr;
+    const int32_t n = idx->n;
+    const DBuf<int64_t> &doff = side ? idx->ioff : idx->off;
+    const DBuf<uint64_t> &dent = side ? idx->iwent : idx->went;
+    std::vector<int64_t> ho((size_t)n + 1, 0);
+    if (n) d2h(ho.data(), doff.p, (size_t)n + 1, st);
+    check(hipStreamSynchronize(st));
+    const int64_t total = n ? ho[n] : 0;
+    if (entries) *entries = total - n;
+    if (off) {
+      for (int32_t r = 0; r <= n; r++) off[r] = ho[r] - r;  // without sentinels
+    }
+    if ((hub || dist) && total > n) {
+      std::vector<uint64_t> he((size_t)total);
+      d2h(he.data(), dent.p, (size_t)total, st);
+      check(hipStreamSynchronize(st));
+      int64_t o = 0;
+      for (int32_t r = 0; r < n; r++)
+        for (int64_t e = ho[r]; e < ho[r + 1] - 1; e++, o++) {
+          if (hub) hub[o] = (uint32_t)(he[e] >> 32);
+          if (dist) dist[o] = (uint32_t)he[e];
+        }
+    }
+    if (rank && n) {
+      d2h(rank, idx->rank.p, (size_t)n, st);
+      check(hipStreamSynchronize(st));
+    }
+    return PLL_OK;
+  });
+}
+
 int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out, uint32_t flags,
               void *stream) {
   if (!idx || q < 0) return PLL_E_INVAL;
+  if (idx->weighted) return PLL_E_UNSUPPORTED;
   if (q == 0) return PLL_OK;
   if (!pairs || !out) return PLL_E_INVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -1151,7 +1761,7 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
 int pll_export_in(const pll_index *idx, int32_t graph, int64_t *entries, int64_t *off,
                   uint32_t *hub, uint8_t *dist) {
   if (!idx || graph < 0 || graph >= idx->G) return PLL_E_INVAL;
-  if (!idx->directed) return PLL_E_UNSUPPORTED;
+  if (!idx->directed || idx->weighted) return PLL_E_UNSUPPORTED;
   return guarded([&] {
     const int64_t g0 = idx->vtx_off[graph];
     const int64_t ng = idx->vtx_off[graph + 1] - g0;
@@ -1215,6 +1825,7 @@ int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
 int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub, uint8_t *dist,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank) {
   if (!idx || graph < 0 || graph >= idx->G) return PLL_E_INVAL;
+  if (idx->weighted) return PLL_E_UNSUPPORTED;
   return guarded([&] {
     const int32_t t = idx->t, tp = idx->tpad;
     const int64_t g0 = idx->vtx_off[graph];

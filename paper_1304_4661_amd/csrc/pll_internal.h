@@ -262,6 +262,77 @@ struct DWindow {
 };
 
 // ---------------------------------------------------------------------------
+// Weighted graphs (pruned Dijkstra searches, Section 7).
+
+constexpr uint32_t kWInf = 0xFFFFFFFFu;  // "infinity" in 32-bit distances
+
+// Weighted graph in rank space: weight wt[e] belongs to edge col[e].
+struct DWGraph {
+  int32_t n;
+  const int64_t *row;
+  const int32_t *col;
+  const uint32_t *wt;
+};
+
+// Growing weighted label store: label of rank r at ent[off[r] ..
+// off[r]+len[r]), each entry hub << 32 | distance (so entries sort by hub).
+struct DWStore {
+  int64_t *off;
+  int32_t *len;
+  int32_t *cap;
+  uint64_t *ent;
+  unsigned long long *top;  // pool bump pointer (device)
+  int64_t pool_cap;
+};
+
+// Control block of one weighted window (device).
+struct WCtl {
+  unsigned long long fcnt[2];  // entries of the two frontier lists
+  unsigned long long tcnt;     // touched (root slot, vertex) entries
+  unsigned long long ccnt;     // candidate labels
+  unsigned long long httotal;  // entries of the window's root tables
+  unsigned long long survivors;
+  unsigned long long tests;    // entries that ran the prune test
+  unsigned long long scanned;  // label entries read by prune tests
+  unsigned long long edges;    // edges relaxed
+  unsigned long long improved; // tentative distances lowered
+  unsigned long long processed;  // frontier entries processed
+  int32_t flags;
+  int32_t pad;
+};
+enum : int32_t {
+  kWOvfFrontier = 1,
+  kWOvfTouched = 2,
+  kWOvfCand = 4,
+  kWOvfHash = 16,
+};
+
+// Per-window state of the weighted searches of roots [s, s+W) on one side
+// (an undirected graph has one side; a digraph a forward and a reverse one).
+// Entry (j, u) stands for vertex u in the search of root s+j; td and fl are
+// dense [W][n].
+struct DWWindow {
+  int32_t s, W, n, words;  // words: 64-bit mask words per vertex, (W+63)/64
+  uint32_t *td;            // tentative distance, kWInf if not reached
+  uint8_t *fl;             // flag bits (weighted.hip), padded to 4 bytes
+  uint64_t *ht;            // root tables: hub -> distance of L(s+j)
+  int64_t *htoff;          // [W+1]
+  int64_t htcap;
+  uint64_t *lm;            // [n][words]: roots whose search labeled the vertex
+  uint64_t *km;            // [n][words]: ... whose label survived cleaning
+  uint64_t *lsum;          // [n]: bit q set if word q of the lm row is non-zero
+  int32_t *fj0, *fu0, *fj1, *fu1;  // the two frontier lists
+  int64_t fcap;
+  int32_t *tj, *tu;        // touched entries
+  int64_t tcap;
+  int32_t *cj, *cu;        // candidates: root slot, vertex, distance
+  uint32_t *cd;
+  uint8_t *cdes;           // 1 if the candidate commits its vertex's row
+  int64_t ccap;
+  WCtl *ctl;
+};
+
+// ---------------------------------------------------------------------------
 // Launchers (return hipError_t of the launch).
 
 hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *col,
@@ -286,9 +357,11 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int
                                  hipStream_t st);
 
 // In-edges of the rank-space graph: irow int64[n+1], icol int32[row[n]];
-// work int64[n+1], tmp scan_tmp_elems(n+1) int64.
+// work int64[n+1], tmp scan_tmp_elems(n+1) int64; with wt, iwt[row[n]] gets
+// the weight of each in-edge.
 hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, int64_t *irow,
-                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st);
+                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st,
+                            const uint32_t *wt = nullptr, uint32_t *iwt = nullptr);
 hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
                             const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
                             uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
@@ -347,6 +420,10 @@ struct DIndex {
   const int64_t *grow;
   const int32_t *gcol;
   const int32_t *ord;
+  // weighted index: packed entries hub << 32 | distance at off (source
+  // side) and toff (target side), each label closed by ~0
+  const uint64_t *went;
+  const uint64_t *twent;
 };
 hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err,
                                  hipStream_t st);
@@ -370,5 +447,26 @@ hipError_t launch_gather_bp(const int64_t *rows, int64_t m, int32_t t, int32_t t
                             uint64_t *out_m1, uint64_t *out_m0, hipStream_t st);
 hipError_t launch_gather_rank(int64_t g0, int64_t ng, const int32_t *rank, const int32_t *lrank,
                               int32_t *out, hipStream_t st);
+
+// Weighted graphs (weighted.hip).
+hipError_t launch_validate_weights(const uint32_t *w, int64_t nnz, int32_t *err, hipStream_t st);
+hipError_t launch_relabel_weights(const int32_t *in_row, const uint32_t *in_w, const int32_t *order,
+                                  const int64_t *row, uint32_t *wt, int32_t n, hipStream_t st);
+hipError_t launch_ww_reset_ctl(WCtl *ctl, hipStream_t st);
+hipError_t launch_ww_zero_list(WCtl *ctl, int list, hipStream_t st);
+// sizes: int64[W + 1]; scan_tmp: scan_tmp_elems(W + 1) int64
+hipError_t launch_ww_init(DWStore tabsrc, DWWindow w, int64_t *sizes, int64_t *scan_tmp,
+                          hipStream_t st);
+hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st);
+hipError_t launch_ww_collect(DWWindow w, hipStream_t st);
+hipError_t launch_ww_clean(DWWindow w, DWWindow o, hipStream_t st);
+hipError_t launch_ww_commit(DWWindow w, DWStore s, hipStream_t st);
+hipError_t launch_ww_reset(DWWindow w, hipStream_t st);
+hipError_t launch_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
+hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, int32_t n,
+                              hipStream_t st);
+// out[i] = min(d(s, t), kWInf) over the packed weighted labels of ix
+hipError_t launch_wquery(DIndex ix, const int32_t *pairs, int64_t q, uint32_t *out,
+                         const int32_t *err, bool plain, int qgroup, hipStream_t st);
 
 }  // namespace pll

@@ -338,13 +338,16 @@ __global__ void __launch_bounds__(256) k_in_count(const int64_t *row, const int3
 
 __global__ void __launch_bounds__(256) k_in_fill(const int64_t *row, const int32_t *col, int32_t n,
                                                  const int64_t *irow, unsigned long long *cursor,
-                                                 int32_t *icol) {
+                                                 int32_t *icol, const uint32_t *wt,
+                                                 uint32_t *iwt) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t r = wave; r < n; r += nwaves)
     for (int64_t e = row[r] + lane_id(); e < row[r + 1]; e += kWave) {
       const int32_t c = col[e];
-      icol[irow[c] + (int64_t)atomicAdd(&cursor[c], 1ull)] = (int32_t)r;
+      const int64_t p = irow[c] + (int64_t)atomicAdd(&cursor[c], 1ull);
+      icol[p] = (int32_t)r;
+      if (wt) iwt[p] = wt[e];  // an arc keeps its weight
     }
 }
 
@@ -409,7 +412,8 @@ hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *
 }
 
 hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, int64_t *irow,
-                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st) {
+                            int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st,
+                            const uint32_t *wt, uint32_t *iwt) {
   hipError_t e = hipMemsetAsync(work, 0, ((size_t)n + 1) * sizeof(int64_t), st);
   if (e != hipSuccess) return e;
   if (n == 0) return hipMemsetAsync(irow, 0, sizeof(int64_t), st);
@@ -417,12 +421,12 @@ hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, i
   if (blocks > 65536) blocks = 65536;
   unsigned long long *cnt = reinterpret_cast<unsigned long long *>(work);
   hipLaunchKernelGGL(k_in_count, dim3((unsigned)blocks), dim3(256), 0, st, row, col, n, cnt);
-  e = launch_exclusive_scan(work, irow, (int64_t)n + 1, tmp, st);
+  e = launch_exclusive_scan(work, irow, (int64_t)n, tmp, st);  // irow[n] = total
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(work, 0, ((size_t)n + 1) * sizeof(int64_t), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_in_fill, dim3((unsigned)blocks), dim3(256), 0, st, row, col, n, irow, cnt,
-                     icol);
+                     icol, wt, iwt);
   return hipGetLastError();
 }
 

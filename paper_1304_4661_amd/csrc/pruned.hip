@@ -897,7 +897,7 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
                            int64_t *sizes, int64_t *scan_tmp, hipStream_t st) {
   if (nroots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_win_ht_size, dim3((nroots + 1 + 255) / 256), dim3(256), 0, st, w, s, sizes);
-  hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)nroots + 1, scan_tmp, st);
+  hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)nroots, scan_tmp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_win_init, dim3((nroots + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
                      0, st, g, w, s, f);

@@ -29,6 +29,7 @@ namespace pll {
 // defined in api.hip
 DIndex index_view(const pll_index *idx);
 int32_t index_n(const pll_index *idx);
+bool index_weighted(const pll_index *idx);
 int64_t query_group_size();
 int64_t serve_coalesce();
 }  // namespace pll
@@ -181,6 +182,7 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
   *out = nullptr;
   if (!idx || nslots < 1 || nslots > 32 || slot_pairs < 1 || slot_pairs > (1ll << 30))
     return PLL_E_INVAL;
+  if (index_weighted(idx)) return PLL_E_UNSUPPORTED;  // 8-bit answers only
   pll_server *sv = new (std::nothrow) pll_server();
   if (!sv) return PLL_E_NOMEM;
   sv->idx = idx;

@@ -1,0 +1,707 @@
+// Weighted graphs (Section 7, "Weighted Graphs"): every root runs a pruned
+// Dijkstra search instead of a pruned BFS; there are no bit-parallel labels
+// and distances are 32-bit.
+//
+// A window of roots [s, s+W) runs concurrently, each search pruning with the
+// labels of roots before s, exactly as the unweighted windows do; the
+// cleaning argument there only uses shortest-path distances, so it carries
+// over unchanged (a candidate (k, d) of u is dropped iff a window root j < k
+// labeled both u and v_k with d(j,u) + d(j,v_k) <= d).
+//
+// One search on the GPU is label-correcting instead of settling vertices in
+// distance order: steps over a frontier of (root slot, vertex) entries whose
+// tentative distance dropped.  An entry is tested against the root's table
+// with its current distance; if it is not pruned it is marked labeled and
+// relaxes its edges (atomicMin on the tentative distances), and every entry
+// whose distance drops joins the next frontier.  The distances only fall and
+// the test only gets easier to pass as they fall, so "labeled" never has to
+// be undone, and at the fixpoint the labeled entries and their distances are
+// those of the pruned Dijkstra search: a vertex pruned at its final
+// distance relaxed nothing after it was reached at that distance, and every
+// vertex not pruned at its final distance was tested at it.
+//
+// Entry flags (one byte per entry, updated through 32-bit atomics): Q0/Q1
+// "in frontier list 0/1", TOUCHED "on the touched list" (for the reset and
+// the candidates), LABELED.  A step reading list c clears Q_c of what it
+// reads and sets Q_{1-c} of what it queues, so an entry is on each list at
+// most once and no improvement is lost: one made during a step is always
+// seen by a later step (the entry is queued for the next one, or already
+// is).
+#include "pll_internal.h"
+
+namespace pll {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr unsigned kGrid = 2048;
+constexpr uint64_t kEmptyW = ~0ull;
+
+constexpr uint32_t kQ0 = 1, kQ1 = 2, kTouched = 4, kLabeled = 8;
+
+__device__ __forceinline__ uint32_t qbit(int list) { return list ? kQ1 : kQ0; }
+
+// Byte flags through the aligned 32-bit word that holds them; return the
+// byte's old value.
+__device__ __forceinline__ uint32_t fl_or(uint8_t *fl, int64_t idx, uint32_t bits) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(fl + (idx & ~(int64_t)3));
+  const int sh = (int)(idx & 3) * 8;
+  return (atomicOr(w, bits << sh) >> sh) & 0xFFu;
+}
+__device__ __forceinline__ uint32_t fl_clear(uint8_t *fl, int64_t idx, uint32_t bits) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(fl + (idx & ~(int64_t)3));
+  const int sh = (int)(idx & 3) * 8;
+  return (atomicAnd(w, ~(bits << sh)) >> sh) & 0xFFu;
+}
+
+// The root's label as an open-addressing table hub -> distance (the role of
+// the array T of Section 4.5.1): entry = distance << 32 | hub, kEmptyW free,
+// size a power of two >= 4 |L(root)|.
+__device__ __forceinline__ uint32_t wt_hash(uint32_t h) {
+  const uint32_t x = h * 0x9E3779B1u;
+  return x ^ (x >> 15);
+}
+
+struct WRootTable {
+  const uint64_t *p;
+  uint32_t mask;
+  bool empty;
+  __device__ __forceinline__ uint32_t get(uint32_t h) const {
+    if (empty) return kWInf;
+    uint32_t slot = wt_hash(h) & mask;
+    for (;;) {
+      const uint64_t e = p[slot];
+      if ((uint32_t)e == h) return (uint32_t)(e >> 32);
+      if (e == kEmptyW) return kWInf;
+      slot = (slot + 1) & mask;
+    }
+  }
+};
+
+__device__ __forceinline__ WRootTable wroot_table(const DWWindow &w, int32_t j) {
+  const int64_t a = w.htoff[j], b = w.htoff[j + 1];
+  return WRootTable{w.ht + a, (uint32_t)(b - a - 1), b == a};
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  return Group<kWave>::sum_reduce(v);
+}
+
+__global__ void k_validate_weights(const uint32_t *w, int64_t nnz, int32_t *err) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
+       i += (int64_t)gridDim.x * blockDim.x)
+    if (w[i] == 0) atomicOr(err, 1);
+}
+
+// One wave per rank-space row: the weights of vertex order[r]'s row, in the
+// row's order (the column copy maps the neighbours the same way).
+__global__ void __launch_bounds__(kBlock) k_relabel_weights(const int32_t *in_row,
+                                                            const uint32_t *in_w,
+                                                            const int32_t *order,
+                                                            const int64_t *row, uint32_t *wt,
+                                                            int32_t n) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wave; r < n; r += nwaves) {
+    const int32_t v = order[r];
+    const int64_t a = in_row[v], b = in_row[v + 1], o = row[r];
+    for (int64_t e = a + lane_id(); e < b; e += kWave) wt[o + (e - a)] = in_w[e];
+  }
+}
+
+__global__ void k_ww_reset_ctl(WCtl *ctl) {
+  unsigned long long *p = reinterpret_cast<unsigned long long *>(ctl);
+  const int words = (int)(sizeof(WCtl) / sizeof(unsigned long long));
+  for (int i = threadIdx.x; i < words; i += blockDim.x) p[i] = 0;
+}
+
+__global__ void k_ww_zero_list(WCtl *ctl, int list) {
+  if (threadIdx.x == 0) ctl->fcnt[list] = 0;
+}
+
+__global__ void k_ww_ht_size(DWStore src, DWWindow w, int64_t *sizes) {
+  const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > w.W) return;
+  int64_t sz = 0;
+  if (j < w.W) {
+    const int32_t len = src.len[w.s + j];
+    if (len > 0) {
+      sz = 8;
+      while (sz < 4 * (int64_t)len) sz <<= 1;
+    }
+  }
+  sizes[j] = sz;
+}
+
+// Wave j: root r = s + j.  Its table from L(r) in `src` (the root's own
+// labels; for a digraph the opposite direction's), distance 0 at r, (j, r)
+// on frontier list 0 and on the touched list.  Wave 0 publishes the list
+// counts and flags tables that do not fit (the window is then re-run after
+// the host grows the table area; the steps do nothing while a flag is set).
+__global__ void __launch_bounds__(kBlock) k_ww_init(DWStore src, DWWindow w) {
+  const int32_t j = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (j >= w.W) return;
+  const int lane = lane_id();
+  const int32_t r = w.s + j;
+  const int64_t total = w.htoff[w.W];
+  const bool fits = total <= w.htcap;
+  if (j == 0 && lane == 0) {
+    w.ctl->httotal = (unsigned long long)total;
+    if (!fits) atomicOr(&w.ctl->flags, kWOvfHash);
+    w.ctl->fcnt[0] = (unsigned long long)w.W;
+    w.ctl->tcnt = (unsigned long long)w.W;
+  }
+  if (fits) {
+    const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
+    for (int64_t e = lane; e < sz; e += kWave) w.ht[a + e] = kEmptyW;
+    __threadfence_block();  // the wave's clears land before its inserts
+    const int64_t o = src.off[r];
+    const int32_t len = src.len[r];
+    for (int32_t e = lane; e < len; e += kWave) {
+      const uint64_t ent = src.ent[o + e];
+      const uint32_t h = (uint32_t)(ent >> 32);
+      const unsigned long long te = ((ent & 0xFFFFFFFFull) << 32) | h;
+      uint32_t slot = wt_hash(h) & (uint32_t)(sz - 1);
+      while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmptyW, te) !=
+             (unsigned long long)kEmptyW)
+        slot = (slot + 1) & (uint32_t)(sz - 1);
+    }
+  }
+  if (lane == 0) {
+    const int64_t idx = (int64_t)j * w.n + r;
+    w.td[idx] = 0;
+    fl_or(w.fl, idx, kTouched | kQ0);
+    w.fj0[j] = j;
+    w.fu0[j] = r;
+    w.tj[j] = j;
+    w.tu[j] = r;
+  }
+}
+
+// One step over frontier list `cur`, G lanes per entry: the prune test
+// (QUERY(root, u) over the labels committed before the window, with the
+// root's table) while the entry is not labeled yet, then the relaxation of
+// u's edges.  Improved entries go to list 1-cur (once) and, the first time
+// they are reached, to the touched list.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWindow w, int cur) {
+  if (w.ctl->flags) return;
+  unsigned long long cnt = w.ctl->fcnt[cur];
+  if (cnt > (unsigned long long)w.fcap) cnt = (unsigned long long)w.fcap;
+  const int32_t *inj = cur ? w.fj1 : w.fj0;
+  const int32_t *inu = cur ? w.fu1 : w.fu0;
+  int32_t *outj = cur ? w.fj0 : w.fj1;
+  int32_t *outu = cur ? w.fu0 : w.fu1;
+  unsigned long long *outc = &w.ctl->fcnt[cur ^ 1];
+  const uint32_t qc = qbit(cur), qn = qbit(cur ^ 1);
+  const int gr = Group<G>::rank(), gb = Group<G>::base();
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int32_t n = w.n;
+  unsigned long long c_tests = 0, c_scanned = 0, c_edges = 0, c_improved = 0, c_proc = 0;
+  for (int64_t i = gid; i < (int64_t)cnt; i += ngroups) {
+    const int32_t j = inj[i], u = inu[i];
+    const int64_t idx = (int64_t)j * n + u;
+    uint32_t f = 0, d = 0;
+    if (gr == 0) {
+      f = fl_clear(w.fl, idx, qc);
+      d = ld_acquire_agent(&w.td[idx]);
+      c_proc++;
+    }
+    f = (uint32_t)__shfl((int)f, gb);
+    d = (uint32_t)__shfl((int)d, gb);
+    if (!(f & kLabeled)) {
+      const WRootTable T = wroot_table(w, j);
+      const int64_t o = s.off[u];
+      const int32_t len = s.len[u];
+      if (gr == 0) {
+        c_tests++;
+        c_scanned += (unsigned long long)len;
+      }
+      bool pr = false;
+      for (int32_t b = 0; b < len; b += G) {
+        const int32_t e = b + gr;
+        if (e < len) {
+          const uint64_t ent = s.ent[o + e];
+          const uint32_t th = T.get((uint32_t)(ent >> 32));
+          if (th != kWInf && (ent & 0xFFFFFFFFull) + th <= (uint64_t)d) pr = true;
+        }
+        if (Group<G>::any(pr)) {
+          pr = true;
+          break;
+        }
+      }
+      if (pr) continue;
+      if (gr == 0) fl_or(w.fl, idx, kLabeled);
+    }
+    const int64_t a = g.row[u], b = g.row[u + 1];
+    for (int64_t e = a + gr; e < b; e += G) {
+      const int32_t v = g.col[e];
+      const uint64_t nd = (uint64_t)d + g.wt[e];
+      bool push_n = false, push_t = false;
+      c_edges++;
+      if (nd < (uint64_t)kWInf) {
+        const int64_t vi = (int64_t)j * n + v;
+        if ((uint32_t)nd < w.td[vi]) {
+          const uint32_t old = atomicMin(&w.td[vi], (uint32_t)nd);
+          if ((uint32_t)nd < old) {
+            c_improved++;
+            const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
+            push_t = !(of & kTouched);
+            push_n = !(of & qn);
+          }
+        }
+      }
+      const int64_t pn = wave_append(push_n, outc);
+      if (push_n) {
+        if (pn < w.fcap) {
+          outj[pn] = j;
+          outu[pn] = v;
+        } else {
+          atomicOr(&w.ctl->flags, kWOvfFrontier);
+        }
+      }
+      const int64_t pt = wave_append(push_t, &w.ctl->tcnt);
+      if (push_t) {
+        if (pt < w.tcap) {
+          w.tj[pt] = j;
+          w.tu[pt] = v;
+        } else {
+          atomicOr(&w.ctl->flags, kWOvfTouched);
+        }
+      }
+    }
+  }
+  c_tests = wave_sum(c_tests);
+  c_scanned = wave_sum(c_scanned);
+  c_edges = wave_sum(c_edges);
+  c_improved = wave_sum(c_improved);
+  c_proc = wave_sum(c_proc);
+  if (lane_id() == 0) {
+    if (c_tests) atomicAdd(&w.ctl->tests, c_tests);
+    if (c_scanned) atomicAdd(&w.ctl->scanned, c_scanned);
+    if (c_edges) atomicAdd(&w.ctl->edges, c_edges);
+    if (c_improved) atomicAdd(&w.ctl->improved, c_improved);
+    if (c_proc) atomicAdd(&w.ctl->processed, c_proc);
+  }
+}
+
+// Labeled touched entries become candidates (root slot, vertex, final
+// distance); the vertex's mask row and summary get the root's bit.
+__global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
+  unsigned long long tc = w.ctl->tcnt;
+  if (tc > (unsigned long long)w.tcap) tc = (unsigned long long)w.tcap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nloop = ((int64_t)tc + stride - 1) / stride;
+  for (int64_t it = 0; it < nloop; it++) {  // wave-uniform trip count
+    const int64_t i = t0 + it * stride;
+    bool lab = false;
+    int32_t j = 0, u = 0;
+    uint32_t d = 0;
+    if (i < (int64_t)tc) {
+      j = w.tj[i];
+      u = w.tu[i];
+      const int64_t idx = (int64_t)j * w.n + u;
+      lab = (w.fl[idx] & kLabeled) != 0;
+      d = w.td[idx];
+    }
+    const int64_t p = wave_append(lab, &w.ctl->ccnt);
+    if (lab) {
+      if (p < w.ccap) {
+        w.cj[p] = j;
+        w.cu[p] = u;
+        w.cd[p] = d;
+        atomicOr((unsigned long long *)&w.lm[(int64_t)u * w.words + (j >> 6)],
+                 1ull << (j & 63));
+        atomicOr((unsigned long long *)&w.lsum[u], 1ull << (j >> 6));
+      } else {
+        atomicOr(&w.ctl->flags, kWOvfCand);
+      }
+    }
+  }
+}
+
+// Cleaning: candidate (k, d) of u is dropped iff a window root j < k labeled
+// both u (in this side's searches) and v_k (in side o's: the same side for
+// an undirected graph, the opposite direction for a digraph) with
+// d(j, u) + d(j, v_k) <= d.  Survivors set their bit in the km row; the
+// candidate of u's lowest window root is u's designated committer.
+__global__ void __launch_bounds__(kBlock) k_ww_clean(DWWindow w, DWWindow o) {
+  unsigned long long cc = w.ctl->ccnt;
+  if (cc > (unsigned long long)w.ccap) cc = (unsigned long long)w.ccap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nloop = ((int64_t)cc + stride - 1) / stride;
+  const int32_t n = w.n;
+  for (int64_t it = 0; it < nloop; it++) {
+    const int64_t c = t0 + it * stride;
+    bool keep = false;
+    if (c < (int64_t)cc) {
+      const int32_t k = w.cj[c], u = w.cu[c];
+      const uint64_t d = w.cd[c];
+      const int32_t rk = w.s + k;
+      const int kw = k >> 6;
+      const uint64_t *lu = w.lm + (int64_t)u * w.words;
+      const uint64_t *lk = o.lm + (int64_t)rk * o.words;
+      uint64_t sm = w.lsum[u] & o.lsum[rk];
+      sm &= kw == 63 ? ~0ull : ((2ull << kw) - 1);
+      bool drop = false;
+      while (sm && !drop) {
+        const int q = __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        uint64_t m = lu[q] & lk[q];
+        if (q == kw) m &= (1ull << (k & 63)) - 1;
+        while (m) {
+          const int bb = __ffsll((unsigned long long)m) - 1;
+          m &= m - 1;
+          const int64_t jj = (int64_t)q * 64 + bb;
+          if ((uint64_t)w.td[jj * n + u] + o.td[jj * n + rk] <= d) {
+            drop = true;
+            break;
+          }
+        }
+      }
+      if (!drop) {
+        keep = true;
+        atomicOr((unsigned long long *)&w.km[(int64_t)u * w.words + kw], 1ull << (k & 63));
+      }
+      const int q0 = __ffsll((unsigned long long)w.lsum[u]) - 1;
+      const int low = q0 * 64 + __ffsll((unsigned long long)lu[q0]) - 1;
+      w.cdes[c] = low == k ? 1 : 0;
+    }
+    const unsigned long long ks = wave_sum(keep ? 1ull : 0ull);
+    if (lane_id() == 0 && ks) atomicAdd(&w.ctl->survivors, ks);
+  }
+}
+
+// Commit pass 1, one lane per designated candidate: count the vertex's
+// survivors, grow its slot when full (the whole wave copies the old
+// entries), publish the new length, clear the lm row.
+__global__ void __launch_bounds__(kBlock) k_ww_commit_alloc(DWWindow w, DWStore st) {
+  unsigned long long cc = w.ctl->ccnt;
+  if (cc > (unsigned long long)w.ccap) cc = (unsigned long long)w.ccap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nloop = ((int64_t)cc + stride - 1) / stride;
+  for (int64_t it = 0; it < nloop; it++) {
+    const int64_t c = t0 + it * stride;
+    bool reloc = false;
+    int32_t u = 0, len = 0;
+    int64_t oo = 0, no = 0, nc = 0;
+    if (c < (int64_t)cc && w.cdes[c]) {
+      u = w.cu[c];
+      uint64_t *lrow = w.lm + (int64_t)u * w.words;
+      const uint64_t *krow = w.km + (int64_t)u * w.words;
+      uint64_t sm = w.lsum[u];
+      int32_t total = 0;
+      while (sm) {
+        const int q = __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        total += __popcll(krow[q]);
+        lrow[q] = 0ull;
+      }
+      len = st.len[u];
+      const int32_t need = len + total;
+      if (total > 0 && need > st.cap[u]) {
+        nc = 2 * (int64_t)need;
+        if (nc < 16) nc = 16;
+        nc = (nc + 15) & ~(int64_t)15;
+        no = (int64_t)atomicAdd(st.top, (unsigned long long)nc);
+        oo = st.off[u];
+        reloc = true;
+      }
+      st.len[u] = need;
+    }
+    uint64_t m = __ballot(reloc);
+    while (m) {
+      const int l = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      const int32_t ln = __shfl(len, l);
+      const int64_t so = __shfl(oo, l), dn = __shfl(no, l);
+      for (int32_t e = lane_id(); e < ln; e += kWave) st.ent[dn + e] = st.ent[so + e];
+    }
+    if (reloc) {
+      st.off[u] = no;
+      st.cap[u] = (int32_t)nc;
+    }
+  }
+}
+
+// Commit pass 2, one thread per candidate: a survivor writes (root rank,
+// distance) at its place among the vertex's new entries, in root order, so
+// labels stay sorted by hub rank.
+__global__ void __launch_bounds__(kBlock) k_ww_commit_write(DWWindow w, DWStore st) {
+  unsigned long long cc = w.ctl->ccnt;
+  if (cc > (unsigned long long)w.ccap) cc = (unsigned long long)w.ccap;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < (int64_t)cc;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = w.cu[c], k = w.cj[c];
+    const int kw = k >> 6, kb = k & 63;
+    const uint64_t *krow = w.km + (int64_t)u * w.words;
+    const uint64_t kword = krow[kw];
+    if (!((kword >> kb) & 1ull)) continue;
+    int32_t above = __popcll(kb == 63 ? 0ull : (kword >> (kb + 1)));
+    uint64_t sm = w.lsum[u] & (kw == 63 ? 0ull : (~0ull << (kw + 1)));
+    while (sm) {
+      const int q = __ffsll((unsigned long long)sm) - 1;
+      sm &= sm - 1;
+      above += __popcll(krow[q]);
+    }
+    const int64_t o = st.off[u] + st.len[u] - 1 - above;
+    st.ent[o] = ((uint64_t)(uint32_t)(w.s + k) << 32) | w.cd[c];
+  }
+}
+
+// Commit pass 3, one thread per designated candidate: clear the km row and
+// the summary.
+__global__ void __launch_bounds__(kBlock) k_ww_commit_clear(DWWindow w) {
+  unsigned long long cc = w.ctl->ccnt;
+  if (cc > (unsigned long long)w.ccap) cc = (unsigned long long)w.ccap;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < (int64_t)cc;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    if (!w.cdes[c]) continue;
+    const int32_t u = w.cu[c];
+    uint64_t *krow = w.km + (int64_t)u * w.words;
+    uint64_t sm = w.lsum[u];
+    while (sm) {
+      const int q = __ffsll((unsigned long long)sm) - 1;
+      sm &= sm - 1;
+      krow[q] = 0ull;
+    }
+    w.lsum[u] = 0ull;
+  }
+}
+
+// Touched entries back to "not reached" (never a full sweep).
+__global__ void __launch_bounds__(kBlock) k_ww_reset(DWWindow w) {
+  unsigned long long tc = w.ctl->tcnt;
+  if (tc > (unsigned long long)w.tcap) tc = (unsigned long long)w.tcap;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)tc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = (int64_t)w.tj[i] * w.n + w.tu[i];
+    w.td[idx] = kWInf;
+    w.fl[idx] = 0;
+  }
+}
+
+__global__ void k_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n) {
+  const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) cnt[r] = (int64_t)len[r] + 1;  // + sentinel
+}
+
+__global__ void __launch_bounds__(kBlock) k_wfinal_copy(DWStore st, const int64_t *foff,
+                                                        uint64_t *fent, int32_t n) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wid; r < n; r += nw) {
+    const int64_t o = st.off[r], fo = foff[r];
+    const int32_t len = st.len[r];
+    for (int32_t e = lane_id(); e < len; e += kWave) fent[fo + e] = st.ent[o + e];
+    if (lane_id() == 0) fent[fo + len] = kEmptyW;
+  }
+}
+
+// Queries: merge join (Section 3.3) over the packed labels, 64-bit sums.
+__global__ void __launch_bounds__(kBlock) k_wquery_plain(DIndex ix, const int32_t *pairs, int64_t q,
+                                                         uint32_t *out, const int32_t *err) {
+  if (err && *err) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    uint64_t best = kWInf;
+    int64_t a = ix.off[rs], b = ix.toff[rt];
+    for (;;) {
+      const uint64_t ea = ix.went[a], eb = ix.twent[b];
+      const uint32_t ha = (uint32_t)(ea >> 32), hb = (uint32_t)(eb >> 32);
+      if (ha == hb) {
+        if (ha == kSentinel) break;
+        const uint64_t v = (ea & 0xFFFFFFFFull) + (eb & 0xFFFFFFFFull);
+        best = v < best ? v : best;
+        a++;
+        b++;
+      } else if (ha < hb) {
+        a++;
+      } else {
+        b++;
+      }
+    }
+    out[i] = (uint32_t)best;
+  }
+}
+
+// G lanes per pair: chunks of G entries of both labels; each lane finds its
+// source hub among the target chunk held in lanes by a halving search.
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_wquery_group(DIndex ix, const int32_t *pairs, int64_t q,
+                                                         uint32_t *out, const int32_t *err) {
+  if (err && *err) return;
+  const int gr = Group<G>::rank();
+  const int gb = Group<G>::base();
+  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+  const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
+  for (int64_t i = gid; i < q; i += ngroups) {
+    const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+    uint64_t best = kWInf;
+    int64_t a = ix.off[rs], b = ix.toff[rt];
+    const int64_t ea = ix.off[rs + 1], eb = ix.toff[rt + 1];
+    for (;;) {
+      const uint64_t xa = ix.went[a + gr < ea ? a + gr : ea - 1];
+      const uint64_t xb = ix.twent[b + gr < eb ? b + gr : eb - 1];
+      const uint32_t ha = (uint32_t)(xa >> 32), hb = (uint32_t)(xb >> 32);
+      int lo = 0;
+#pragma unroll
+      for (int s = G / 2; s >= 1; s >>= 1) {
+        const uint32_t hm = (uint32_t)__shfl((int)hb, gb + lo + s - 1);
+        if (hm < ha) lo += s;
+      }
+      const uint32_t hf = (uint32_t)__shfl((int)hb, gb + lo);
+      const uint32_t df = (uint32_t)__shfl((int)(uint32_t)xb, gb + lo);
+      if (hf == ha && ha != kSentinel) {
+        const uint64_t v = (xa & 0xFFFFFFFFull) + df;
+        best = v < best ? v : best;
+      }
+      const uint32_t lastA = (uint32_t)__shfl((int)ha, gb + G - 1);
+      const uint32_t lastB = (uint32_t)__shfl((int)hb, gb + G - 1);
+      if (lastA == kSentinel && lastB == kSentinel) break;
+      if (lastA <= lastB) a += G;
+      if (lastB <= lastA) b += G;
+    }
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const uint64_t v = __shfl_xor(best, o, G);
+      best = v < best ? v : best;
+    }
+    if (gr == 0) out[i] = (uint32_t)best;
+  }
+}
+
+unsigned grid_for(int64_t items, int per_block, int64_t cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t launch_validate_weights(const uint32_t *w, int64_t nnz, int32_t *err, hipStream_t st) {
+  if (nnz <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_validate_weights, dim3(grid_for(nnz, 256, 4096)), dim3(256), 0, st, w, nnz,
+                     err);
+  return hipGetLastError();
+}
+
+hipError_t launch_relabel_weights(const int32_t *in_row, const uint32_t *in_w, const int32_t *order,
+                                  const int64_t *row, uint32_t *wt, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_relabel_weights, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
+                     dim3(kBlock), 0, st, in_row, in_w, order, row, wt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_reset_ctl(WCtl *ctl, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_reset_ctl, dim3(1), dim3(64), 0, st, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_zero_list(WCtl *ctl, int list, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_zero_list, dim3(1), dim3(64), 0, st, ctl, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_init(DWStore tabsrc, DWWindow w, int64_t *sizes, int64_t *scan_tmp,
+                          hipStream_t st) {
+  if (w.W <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ww_ht_size, dim3((w.W + 1 + 255) / 256), dim3(256), 0, st, tabsrc, w,
+                     sizes);
+  hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)w.W, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_ww_init, dim3(grid_for((int64_t)w.W * kWave, kBlock, 1 << 20)),
+                     dim3(kBlock), 0, st, tabsrc, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st) {
+  switch (group) {
+    case 4:
+      hipLaunchKernelGGL(k_ww_step<4>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_ww_step<8>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_ww_step<32>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      break;
+    case 64:
+      hipLaunchKernelGGL(k_ww_step<64>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      break;
+    default:
+      hipLaunchKernelGGL(k_ww_step<16>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_collect(DWWindow w, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_collect, dim3(kGrid), dim3(kBlock), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_clean(DWWindow w, DWWindow o, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_clean, dim3(kGrid), dim3(kBlock), 0, st, w, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_commit(DWWindow w, DWStore s, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_commit_alloc, dim3(kGrid), dim3(kBlock), 0, st, w, s);
+  hipLaunchKernelGGL(k_ww_commit_write, dim3(kGrid), dim3(kBlock), 0, st, w, s);
+  hipLaunchKernelGGL(k_ww_commit_clear, dim3(kGrid), dim3(kBlock), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_reset(DWWindow w, hipStream_t st) {
+  hipLaunchKernelGGL(k_ww_reset, dim3(kGrid), dim3(kBlock), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wfinal_count, dim3((n + 255) / 256), dim3(256), 0, st, len, cnt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, int32_t n,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wfinal_copy, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
+                     dim3(kBlock), 0, st, s, foff, fent, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_wquery(DIndex ix, const int32_t *pairs, int64_t q, uint32_t *out,
+                         const int32_t *err, bool plain, int qgroup, hipStream_t st) {
+  if (q <= 0) return hipSuccess;
+  if (plain) {
+    hipLaunchKernelGGL(k_wquery_plain, dim3(grid_for(q, 256, 65536)), dim3(256), 0, st, ix, pairs,
+                       q, out, err);
+    return hipGetLastError();
+  }
+  switch (qgroup) {
+    case 16:
+      hipLaunchKernelGGL(k_wquery_group<16>, dim3(grid_for(q * 16, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_wquery_group<32>, dim3(grid_for(q * 32, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+    default:
+      hipLaunchKernelGGL(k_wquery_group<64>, dim3(grid_for(q * 64, 256, 16384)), dim3(256), 0, st,
+                         ix, pairs, q, out, err);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pll

@@ -163,3 +163,35 @@ def test_server_rejects_bad_arguments_without_device_work():
     assert lib.pll_server_done(None, 0, 0, None) == binding.E_INVAL
     st = np.zeros(9)
     assert lib.pll_serve_bench(None, 1.0, 10, 16, 1, 2, 1024, st.ctypes.data, 9) == binding.E_INVAL
+
+
+def test_weighted_entry_points_reject_bad_arguments():
+    # all of these fail in host-side validation, before any device work
+    lib = binding.library()
+    g = gen.uniform_weights(graphs.cycle(6), 1, 9, 1)
+    order = gen.degree_order(g)
+    h = C.c_void_p()
+    ptr = lambda a: a.ctypes.data  # noqa: E731
+    w0 = g.w.copy()
+    w0[3] = 0
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(w0), ptr(order), 0, None,
+                                  C.byref(h)) == binding.E_INVAL
+    w1 = g.w.copy()
+    w1[0] += 1  # (0,1) and (1,0) disagree
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(w1), ptr(order),
+                                  binding.VALIDATE, None, C.byref(h)) == binding.E_INVAL
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), None, ptr(order), 0, None,
+                                  C.byref(h)) == binding.E_INVAL
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(g.w), ptr(order),
+                                  binding.PARENTS, None, C.byref(h)) == binding.E_UNSUPPORTED
+    assert lib.pll_build_weighted(-1, None, None, None, None, 0, None, C.byref(h)) == binding.E_INVAL
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(g.w), ptr(order), 0, None,
+                                  None) == binding.E_INVAL
+    bad = order.copy()
+    bad[0] = bad[1]
+    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(g.w), ptr(bad), 0, None,
+                                  C.byref(h)) == binding.E_INVAL
+    out = np.zeros(1, np.uint32)
+    pairs = np.zeros(2, np.int32)
+    assert lib.pll_query_weighted(None, ptr(pairs), 1, ptr(out), 0, None) == binding.E_INVAL
+    assert lib.pll_export_weighted(None, 0, None, None, None, None, None) == binding.E_INVAL
