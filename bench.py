@@ -29,9 +29,19 @@ METRIC = "PLL index build s & edges/s; queries/s + p99 latency, batched vs plain
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_test_traffic_rmat18.json")
 LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip")
+WTRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ww_step_traffic_rmat18w.json")
+WSTEP_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "weighted.hip")
 
 
 def describe(name, g, t_bp, q):
+    if g.meta.get("weights"):
+        lo, hi, ws = g.meta["weights"]
+        base = (f"R-MAT scale {g.meta['scale']}, edge factor {g.meta['edge_factor']}, abcd="
+                f"{g.meta['abcd']}, symmetrized+dedup+no self-loops+largest component"
+                if "scale" in g.meta else f"Barabasi-Albert n={g.n}, m={g.meta.get('m_attach')}")
+        return (f"{base} (n'={g.n}, m'={g.m}), integer edge weights uniform in [{lo}, {hi}] "
+                f"(seed {ws}); Degree order; pruned Dijkstra, no bit-parallel labels; {q} uniform "
+                f"random pairs")
     if name == "ba256":
         return (f"{g.meta['graphs']} Barabasi-Albert graphs, n log-uniform in [1e3, 2e5], "
                 f"m uniform in 2..8, seeded per graph (total n={g.n}, m={g.m}), one packed CSR, "
@@ -74,6 +84,20 @@ def level_kernel_bytes(st, t_bp):
         word 8 B)."""
     return (st["visited"] * (8 + t_bp) + 32 * st["bp_checks"] + 12 * st["normal_tests"]
             + 5 * st["label_scanned"] + 18 * st["candidates"])
+
+
+def weighted_step_bytes(st):
+    """Algorithmic bytes of the weighted search step kernel (k_ww_step),
+    summed over its launches in one build:
+      per frontier entry processed: 8 B list entry + 4 B flag word + 4 B
+        tentative distance,
+      per prune test: 12 B label offset and length, plus 8 B per label entry
+        scanned (packed hub and distance),
+      per edge relaxed: 4 B neighbour + 4 B weight + 4 B tentative distance,
+      per distance lowered: 4 B atomic minimum + 4 B flag word + 8 B list
+        entry."""
+    return (16 * st["visited"] + 12 * st["normal_tests"] + 8 * st["label_scanned"]
+            + 12 * st["edges"] + 16 * st["improved"])
 
 
 def edges_of(g):
@@ -220,6 +244,9 @@ def main():
     if args.sweep:
         sweep(args)
         return
+    if args.config.endswith("w"):
+        bench_weighted(args)
+        return
     batch = args.config == "ba256"
     directed = args.config.endswith("d")
     if batch:
@@ -365,6 +392,115 @@ def main():
             out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
     print(json.dumps(out))
+
+
+def bench_weighted(args):
+    """The weighted step (Section 7): pruned Dijkstra index build from
+    device-resident inputs + one batch of queries, timed like the default
+    step; roofline of the search step kernel; the oracle as CPU baseline."""
+    import torch
+
+    from paper_1304_4661_amd import binding, gen
+
+    dev = torch.device("cuda:0")
+    g, order, _, pairs = gen.config_graph(args.config)
+    q = len(pairs)
+    as_i32 = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)  # noqa: E731
+    d_row, d_col, d_w, d_order = as_i32(g.row_ptr), as_i32(g.col), as_i32(g.w), as_i32(order)
+    d_pairs = torch.from_numpy(pairs).to(dev)
+    d_out = torch.empty(q, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    binding.set_tuning("profile", 1)
+
+    def step():
+        ix = binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ix.query_weighted_device(d_pairs, d_out, stream=stream)
+        e1.record(stream)
+        return ix, e0, e1
+
+    for _ in range(args.warmup):
+        ix, _, _ = step()
+        ix.sync()
+        ix.close()
+    torch.cuda.synchronize()
+    build_s, query_ms, stats = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tb = time.perf_counter()
+        ix, e0, e1 = step()
+        build_s.append(time.perf_counter() - tb)
+        ix.sync()
+        query_ms.append(e0.elapsed_time(e1))
+        stats.append(ix.stats())
+        ix.close()
+    torch.cuda.synchronize()
+    ms_per_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    binding.set_tuning("profile", 0)
+    st = stats[-1]
+    step_bytes = weighted_step_bytes(st)
+    lvl_s = st["level_ns"] * 1e-9
+    launches = st["level_launches"]
+    achieved = step_bytes / lvl_s / 1e9 if lvl_s > 0 else None
+    traffic = None
+    if os.path.exists(WTRAFFIC_FILE):
+        with open(WTRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == file_sha(WSTEP_KERNEL_SRC) and tr.get("config") == args.config:
+            traffic = tr.get("bytes_per_launch")
+    out = {
+        "metric": METRIC, "value": g.m / (ms_per_step / 1e3), "unit": "edges/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": describe(args.config, g, 0, q), "name": args.config, "n": g.n,
+                   "m": g.m, "t_bp": 0, "queries": q},
+        "build_s": float(np.median(build_s)),
+        "build_edges_per_s": g.m / float(np.median(build_s)),
+        "queries_per_s": q / (float(np.median(query_ms)) / 1e3),
+        "query_batch_ms_p50": pctl(query_ms, 50), "query_batch_ms_p99": pctl(query_ms, 99),
+        "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}",
+                  "bytes": st["index_bytes"], "windows": st["windows"], "retries": st["retries"],
+                  "steps": st["levels"], "touched": st["touched"], "processed": st["visited"],
+                  "candidates": st["candidates"]},
+        "counters": {k: int(v) for k, v in st.items()},
+        "roofline": {
+            "kernel": "k_ww_step (weighted search step, all roots of a window, one step)",
+            "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": achieved,
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "launches": launches, "avg_launch_us": (lvl_s / launches * 1e6) if launches else None,
+            "algorithmic_bytes_per_launch": step_bytes / launches if launches else None,
+            "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_weighted(g, order, pairs)
+        out["cpu_baseline"]["cpu_model"] = cpu_model()
+    print(json.dumps(out))
+
+
+def cpu_baseline_weighted(g, order, pairs, budget_q=200_000):
+    """The weighted oracle as it stands, one thread: the whole index build
+    of the same graph plus the first budget_q of the pairs."""
+    import oracle
+
+    t0 = time.perf_counter()
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
+    tb = time.perf_counter() - t0
+    sub = pairs[:budget_q]
+    t0 = time.perf_counter()
+    oracle.query_weighted(ox, sub)
+    tq = time.perf_counter() - t0 if len(sub) else 0.0
+    tq_all = tq * len(pairs) / max(len(sub), 1)
+    return {
+        "value": g.m / (tb + tq_all), "unit": "edges/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle index build of the whole graph ({tb:.2f} s) + {len(sub)} of the "
+                   f"{len(pairs)} queries ({tq:.2f} s, scaled to all), one thread"),
+        "build_s": tb, "queries_per_s": len(sub) / tq if tq > 0 else None,
+        "entries": ox.counters["entries"],
+    }
 
 
 def sweep_point(g, order, t_bp, reps, nq=1_000_000):

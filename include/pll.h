@@ -7,7 +7,9 @@
  * The library builds a 2-hop distance-labeling index of an undirected,
  * unweighted graph (bit-parallel labels, Section 5, plus pruned-BFS labels,
  * Section 4) on one GPU and answers exact distance queries from it
- * (Sections 3.3 and 5.3).  Every step of the build and of the query runs in
+ * (Sections 3.3 and 5.3); Section 7's extensions are here too: shortest
+ * paths (PLL_PARENTS), directed graphs (PLL_DIRECTED) and weighted graphs
+ * (pll_build_weighted).  Every step of the build and of the query runs in
  * the library's own HIP kernels; the index stays in device memory.
  *
  * Conventions shared by all entry points
@@ -274,7 +276,12 @@ int pll_export_weighted(const pll_index *idx, int32_t side, int64_t *entries, in
 
 /*
  * Work counters of the build (PLL_STAT_* below), for reporting and for the
- * algorithmic-byte model.  Copies min(ncounters, PLL_NSTATS) values.
+ * algorithmic-byte model.  Copies min(ncounters, PLL_NSTATS) values.  For a
+ * weighted build: VISITED counts frontier entries processed by the search
+ * steps (an entry is processed again each time its distance drops), LEVELS
+ * the steps, EDGES the edges relaxed, NORMAL_TESTS / LABEL_SCANNED the prune
+ * tests, LEVEL_LAUNCHES / LEVEL_NS the step kernels; the bit-parallel and
+ * task counters stay 0.
  */
 enum {
   PLL_STAT_N = 0,        /* vertices */

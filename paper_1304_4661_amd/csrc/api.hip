@@ -868,7 +868,7 @@ struct WBuilder {
   DBuf<uint32_t> wt, iwt;
   int64_t stat_windows = 0, stat_retries = 0, stat_steps = 0, stat_proc = 0, stat_tests = 0,
           stat_scanned = 0, stat_edges = 0, stat_improved = 0, stat_cand = 0, stat_touched = 0,
-          stat_level_ns = 0;
+          stat_level_ns = 0, stat_step_launches = 0;
 
   struct WStore {
     DBuf<int64_t> off;
@@ -1032,18 +1032,18 @@ struct WBuilder {
     check(hipStreamSynchronize(st));
     const int64_t target = std::max<int64_t>(1, tu.window_work / 8);
     int32_t W = plain ? 1 : std::min<int32_t>(wmax, 64);
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (tu.profile) {
-      check(hipEventCreate(&ev0));
-      check(hipEventCreate(&ev1));
-    }
-    struct EvGuard {
-      hipEvent_t a, b;
-      ~EvGuard() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
+    // with the "profile" knob: an event pair around every step kernel of a
+    // batch, read after the batch's synchronisation
+    struct EvPool {
+      std::vector<hipEvent_t> ev;
+      ~EvPool() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
       }
-    } evg{ev0, ev1};
+    } evp;
+    if (tu.profile) {
+      evp.ev.resize((size_t)2 * tu.levels_per_sync * nsides, nullptr);
+      for (auto &e : evp.ev) check(hipEventCreate(&e));
+    }
     int32_t s = 0;
     while (s < n) {
       const int32_t nr = std::min<int32_t>(W, n - s);
@@ -1058,16 +1058,20 @@ struct WBuilder {
       int cur = 0;
       int32_t flags = 0;
       int64_t wsteps = 0;
-      if (ev0) check(hipEventRecord(ev0, st));
       for (;;) {
         // step i settles every entry whose search path has at most i edges,
         // so n + 1 steps always suffice
         if (wsteps > (int64_t)n + 1 + tu.levels_per_sync) throw Fail{PLL_E_DEVICE};
         wsteps += tu.levels_per_sync;
+        size_t ne = 0;
         for (int b = 0; b < tu.levels_per_sync; b++) {
           for (int k = 0; k < nsides; k++) {
             check(launch_ww_zero_list(sides[k].ctl.p, cur ^ 1, st));
+            if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne], st));
             check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.xgroup, st));
+            if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne + 1], st));
+            ne += 2;
+            stat_step_launches++;
           }
           cur ^= 1;
           stat_steps++;
@@ -1076,19 +1080,17 @@ struct WBuilder {
           check(hipMemcpyAsync(&sides[k].mirror.p->ctl, sides[k].ctl.p, sizeof(WCtl),
                                hipMemcpyDeviceToHost, st));
         check(hipStreamSynchronize(st));
+        for (size_t e = 0; e < evp.ev.size(); e += 2) {
+          float ms = 0.f;
+          check(hipEventElapsedTime(&ms, evp.ev[e], evp.ev[e + 1]));
+          stat_level_ns += (int64_t)((double)ms * 1e6);
+        }
         bool more = false;
         for (int k = 0; k < nsides; k++) {
           flags |= sides[k].mirror.p->ctl.flags;
           more |= sides[k].mirror.p->ctl.fcnt[cur] != 0;
         }
         if (flags || !more) break;
-      }
-      if (ev1) {
-        check(hipEventRecord(ev1, st));
-        check(hipEventSynchronize(ev1));
-        float ms = 0.f;
-        check(hipEventElapsedTime(&ms, ev0, ev1));
-        stat_level_ns += (int64_t)(ms * 1e6);
       }
       if (!flags) {
         for (int k = 0; k < nsides; k++) check(launch_ww_collect(win[k], st));
@@ -1286,7 +1288,7 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   S[PLL_STAT_NORMAL_TESTS] = wb.stat_tests;
   S[PLL_STAT_LABEL_SCANNED] = wb.stat_scanned;
   S[PLL_STAT_EDGES] = wb.stat_edges;
-  S[PLL_STAT_LEVEL_LAUNCHES] = wb.stat_steps;
+  S[PLL_STAT_LEVEL_LAUNCHES] = wb.stat_step_launches;
   S[PLL_STAT_LEVEL_NS] = wb.stat_level_ns;
   S[PLL_STAT_IMPROVED] = wb.stat_improved;
   S[PLL_STAT_TOUCHED] = wb.stat_touched;
