@@ -94,10 +94,14 @@ def weighted_step_bytes(st):
       per prune test: 12 B label offset and length, plus 8 B per label entry
         scanned (packed hub and distance),
       per edge relaxed: 4 B neighbour + 4 B weight + 4 B tentative distance,
+      per landmark check of a relaxation: 32 B (16 16-bit landmark distances
+        of the reached vertex; a filtered edge then skips its tentative
+        distance),
       per distance lowered: 4 B atomic minimum + 4 B flag word + 8 B list
         entry."""
     return (16 * st["visited"] + 12 * st["normal_tests"] + 8 * st["label_scanned"]
-            + 12 * st["edges"] + 16 * st["improved"])
+            + 12 * st["edges"] + 32 * st["land_checks"] - 4 * st["filtered"]
+            + 16 * st["improved"])
 
 
 def edges_of(g):
@@ -464,6 +468,7 @@ def bench_weighted(args):
         "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}",
                   "bytes": st["index_bytes"], "windows": st["windows"], "retries": st["retries"],
                   "steps": st["levels"], "touched": st["touched"], "processed": st["visited"],
+                  "filtered_relaxations": st["filtered"],
                   "candidates": st["candidates"]},
         "counters": {k: int(v) for k, v in st.items()},
         "roofline": {

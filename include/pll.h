@@ -314,6 +314,10 @@ enum {
   PLL_STAT_BP_CHECKS,    /* slot set pairs read by those tests */
   PLL_STAT_IMPROVED,     /* weighted builds: tentative distances lowered */
   PLL_STAT_TOUCHED,      /* weighted builds: (root, vertex) entries reached */
+  PLL_STAT_FILTERED,     /* weighted builds: relaxations skipped because
+                            distances through 16 exact landmark hubs already
+                            prune the vertex at the new distance */
+  PLL_STAT_LAND_CHECKS,  /* weighted builds: relaxations checked that way */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
@@ -388,7 +392,12 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * "chunk" (edges a group expands inline before
  * handing the rest to whole waves), "levels_per_sync" (levels launched
  * between host checks), "profile" (0/1: time every level with HIP events on
- * the build stream).  Bit-parallel phase: "bp_chunk" (adjacency entries per
+ * the build stream).  Weighted builds: "wgroup" (lanes per frontier entry
+ * of a search step: 4..64), "wwork" ((root, vertex) entries a window aims
+ * to reach: the window grows or shrinks toward it; 0 keeps every window
+ * after the first at the maximum), and "window", "window_mem_mb", "list_cap",
+ * "table_cap", "levels_per_sync" (steps between host checks) and "profile"
+ * as above.  Bit-parallel phase: "bp_chunk" (adjacency entries per
  * work item).  Queries: "qgroup" (lanes per pair: 16, 32, 64),
  * "serve_coalesce" (0/1: servers started afterwards launch one request at a
  * time / pack several).  Returns PLL_E_INVAL for an unknown key or value.

@@ -25,7 +25,7 @@ STAT_NAMES = [
     "n", "t_bp", "entries", "bp_used", "roots", "visited", "candidates", "windows",
     "retries", "bp_visited", "levels", "index_bytes", "build_ns", "bp_ns", "pruned_ns",
     "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
-    "bp_direct", "bp_sets", "bp_checks", "improved", "touched",
+    "bp_direct", "bp_sets", "bp_checks", "improved", "touched", "filtered", "land_checks",
 ]
 
 EXPORTED = [

@@ -25,6 +25,8 @@ struct Tuning {
   int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
   int group = 4;      // lanes per frontier entry (prune tests)
   int xgroup = 16;    // lanes per candidate expanding its adjacency list
+  int wgroup = 64;    // lanes per frontier entry of a weighted search step
+  int64_t wwork = 2000000;  // touched entries aimed at per weighted window
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
@@ -868,7 +870,8 @@ struct WBuilder {
   DBuf<uint32_t> wt, iwt;
   int64_t stat_windows = 0, stat_retries = 0, stat_steps = 0, stat_proc = 0, stat_tests = 0,
           stat_scanned = 0, stat_edges = 0, stat_improved = 0, stat_cand = 0, stat_touched = 0,
-          stat_level_ns = 0, stat_step_launches = 0;
+          stat_level_ns = 0, stat_step_launches = 0, stat_filtered = 0,
+          stat_checked = 0;
 
   struct WStore {
     DBuf<int64_t> off;
@@ -889,13 +892,17 @@ struct WBuilder {
     int32_t wmax = 0;
     DBuf<uint32_t> td, cd;
     DBuf<uint8_t> fl, cdes;
-    DBuf<uint64_t> ht, lm, km, lsum;
+    DBuf<uint64_t> ht, lm, km, lsum, sig;
     DBuf<int64_t> htoff, hsize, htmp;
     DBuf<int32_t> fj0, fu0, fj1, fu1, tj, tu, cj, cu;
     DBuf<WCtl> ctl;
     WMirror mirror;
-    DWWindow window(int32_t s, int32_t W, int32_t nn) const {
+    DWWindow window(int32_t s, int32_t W, int32_t nn, const uint16_t *lroot,
+                    const uint16_t *lvert, const uint8_t *lskip) const {
       DWWindow w;
+      w.lroot = lroot;
+      w.lvert = lvert;
+      w.lskip = lskip;
       w.s = s;
       w.W = W;
       w.n = nn;
@@ -905,6 +912,7 @@ struct WBuilder {
       w.ht = ht.p;
       w.htoff = htoff.p;
       w.htcap = htcap;
+      w.sig = sig.p;
       w.lm = lm.p;
       w.km = km.p;
       w.lsum = lsum.p;
@@ -975,6 +983,7 @@ struct WBuilder {
     D.htoff.alloc((size_t)wmax + 1);
     D.hsize.alloc((size_t)wmax + 1);
     D.htmp.alloc((size_t)scan_tmp_elems((int64_t)wmax + 1));
+    D.sig.alloc((size_t)wmax * 4);
     // every list holds at least one root's worth (n entries), so one root
     // always fits
     const int64_t budget = tu.list_cap > 0 ? tu.list_cap : (int64_t)1 << 25;
@@ -1030,8 +1039,9 @@ struct WBuilder {
       side_init(sides[1], gr, &stores[0], &stores[1], wmax);
     }
     check(hipStreamSynchronize(st));
-    const int64_t target = std::max<int64_t>(1, tu.window_work / 8);
-    int32_t W = plain ? 1 : std::min<int32_t>(wmax, 64);
+    const int64_t target = std::max<int64_t>(1, tu.wwork);
+    // the first window: the kWLand landmark searches, unpruned and exact
+    int32_t W = plain ? 1 : std::min<int32_t>(wmax, kWLand);
     // with the "profile" knob: an event pair around every step kernel of a
     // batch, read after the batch's synchronisation
     struct EvPool {
@@ -1044,12 +1054,19 @@ struct WBuilder {
       evp.ev.resize((size_t)2 * tu.levels_per_sync * nsides, nullptr);
       for (auto &e : evp.ev) check(hipEventCreate(&e));
     }
+    // landmark rows for the relaxation filter (weighted.hip): land[k] from
+    // side k's first window, vertex-major
+    DBuf<uint16_t> land[2];
+    DBuf<uint8_t> lskip[2];
+    bool have_land = false;
     int32_t s = 0;
     while (s < n) {
       const int32_t nr = std::min<int32_t>(W, n - s);
       DWWindow win[2];
       for (int k = 0; k < nsides; k++) {
-        win[k] = sides[k].window(s, nr, n);
+        const bool filt = have_land && s >= kWLand;
+        win[k] = sides[k].window(s, nr, n, filt ? land[nsides - 1 - k].p : nullptr,
+                                 filt ? land[k].p : nullptr, filt ? lskip[k].p : nullptr);
         check(launch_ww_reset_ctl(sides[k].ctl.p, st));
         check(launch_ww_init(sides[k].roots->view(), win[k], sides[k].hsize.p, sides[k].htmp.p,
                              st));
@@ -1068,7 +1085,7 @@ struct WBuilder {
           for (int k = 0; k < nsides; k++) {
             check(launch_ww_zero_list(sides[k].ctl.p, cur ^ 1, st));
             if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne], st));
-            check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.xgroup, st));
+            check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.wgroup, st));
             if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne + 1], st));
             ne += 2;
             stat_step_launches++;
@@ -1125,10 +1142,27 @@ struct WBuilder {
         check(hipStreamSynchronize(st));
         continue;
       }
+      const bool make_land = s == 0 && nr >= kWLand && !have_land && !plain;
+      if (make_land) {
+        // the first window's searches had no labels to prune with: its
+        // first kWLand distance rows are exact
+        for (int k = 0; k < nsides; k++) {
+          land[k].alloc((size_t)n * kWLand);
+          check(launch_ww_landmarks(win[k], land[k].p, st));
+        }
+      }
       for (int k = 0; k < nsides; k++)
         store_reserve(*sides[k].own, (int64_t)sides[k].mirror.p->ctl.ccnt,
                       sides[k].mirror.p->top);
       for (int k = 0; k < nsides; k++) check(launch_ww_commit(win[k], sides[k].own->view(), st));
+      if (make_land) {
+        // landmark hubs at the head of every label, once they are committed
+        for (int k = 0; k < nsides; k++) {
+          lskip[k].alloc((size_t)n);
+          check(launch_ww_lskip(sides[k].own->view(), n, lskip[k].p, st));
+        }
+        have_land = true;
+      }
       for (int k = 0; k < nsides; k++) check(launch_ww_reset(win[k], st));
       int64_t touched = 0;
       for (int k = 0; k < nsides; k++) {
@@ -1139,13 +1173,17 @@ struct WBuilder {
         stat_scanned += (int64_t)c.scanned;
         stat_edges += (int64_t)c.edges;
         stat_improved += (int64_t)c.improved;
+        stat_filtered += (int64_t)c.filtered;
+        stat_checked += (int64_t)c.checked;
         stat_cand += (int64_t)c.ccnt;
         touched += (int64_t)c.tcnt;
       }
       stat_touched += touched;
       stat_windows++;
       s += nr;
-      if (!plain) {
+      if (!plain && tu.wwork == 0) {
+        W = wmax;  // fixed windows
+      } else if (!plain) {
         // aim the next window at `target` touched entries
         int64_t nw = touched > 0 ? (int64_t)((double)W * target / (double)touched) : 4 * (int64_t)W;
         nw = std::max<int64_t>(nw, std::max<int64_t>(1, W / 4));
@@ -1292,6 +1330,8 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   S[PLL_STAT_LEVEL_NS] = wb.stat_level_ns;
   S[PLL_STAT_IMPROVED] = wb.stat_improved;
   S[PLL_STAT_TOUCHED] = wb.stat_touched;
+  S[PLL_STAT_FILTERED] = wb.stat_filtered;
+  S[PLL_STAT_LAND_CHECKS] = wb.stat_checked;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }
@@ -1931,6 +1971,12 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "xgroup") {
     if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
     g_tune.xgroup = (int)value;
+  } else if (k == "wgroup") {
+    if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
+    g_tune.wgroup = (int)value;
+  } else if (k == "wwork") {
+    if (value < 0 || value > (1ll << 40)) return PLL_E_INVAL;
+    g_tune.wwork = value;
   } else if (k == "chunk") {
     if (value < 64 || value > (1 << 20)) return PLL_E_INVAL;
     g_tune.chunk = (int)value;
@@ -1966,6 +2012,8 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "table_cap") return g_tune.table_cap;
   if (k == "group") return g_tune.group;
   if (k == "xgroup") return g_tune.xgroup;
+  if (k == "wgroup") return g_tune.wgroup;
+  if (k == "wwork") return g_tune.wwork;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

@@ -265,6 +265,7 @@ struct DWindow {
 // Weighted graphs (pruned Dijkstra searches, Section 7).
 
 constexpr uint32_t kWInf = 0xFFFFFFFFu;  // "infinity" in 32-bit distances
+constexpr int kWLand = 16;               // landmark hubs of the relaxation filter
 
 // Weighted graph in rank space: weight wt[e] belongs to edge col[e].
 struct DWGraph {
@@ -297,6 +298,8 @@ struct WCtl {
   unsigned long long edges;    // edges relaxed
   unsigned long long improved; // tentative distances lowered
   unsigned long long processed;  // frontier entries processed
+  unsigned long long filtered;   // relaxations skipped by the landmark bound
+  unsigned long long checked;    // relaxations checked against it
   int32_t flags;
   int32_t pad;
 };
@@ -318,6 +321,7 @@ struct DWWindow {
   uint64_t *ht;            // root tables: hub -> distance of L(s+j)
   int64_t *htoff;          // [W+1]
   int64_t htcap;
+  uint64_t *sig;           // [W][4]: 256-bit hub signature of each root's label
   uint64_t *lm;            // [n][words]: roots whose search labeled the vertex
   uint64_t *km;            // [n][words]: ... whose label survived cleaning
   uint64_t *lsum;          // [n]: bit q set if word q of the lm row is non-zero
@@ -330,6 +334,14 @@ struct DWWindow {
   uint8_t *cdes;           // 1 if the candidate commits its vertex's row
   int64_t ccap;
   WCtl *ctl;
+  // relaxation filter (null: off): 16-bit distances (65535 = that far or
+  // unreachable) between the kWLand landmark hubs and every vertex,
+  // vertex-major, [n][kWLand]: lroot gives the root's side of a hub path,
+  // lvert the reached vertex's side; lskip[u] = entries of landmark hubs at
+  // the head of u's label in this side's store
+  const uint16_t *lroot;
+  const uint16_t *lvert;
+  const uint8_t *lskip;
 };
 
 // ---------------------------------------------------------------------------
@@ -462,6 +474,10 @@ hipError_t launch_ww_collect(DWWindow w, hipStream_t st);
 hipError_t launch_ww_clean(DWWindow w, DWWindow o, hipStream_t st);
 hipError_t launch_ww_commit(DWWindow w, DWStore s, hipStream_t st);
 hipError_t launch_ww_reset(DWWindow w, hipStream_t st);
+// out uint16[n][kWLand] <- the first kWLand distance rows of w (W >= kWLand),
+// saturated at 65535; skip[v] <- label entries of v with a hub < kWLand
+hipError_t launch_ww_landmarks(DWWindow w, uint16_t *out, hipStream_t st);
+hipError_t launch_ww_lskip(DWStore s, int32_t n, uint8_t *skip, hipStream_t st);
 hipError_t launch_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, int32_t n,
                               hipStream_t st);

@@ -27,6 +27,24 @@
 // most once and no improvement is lost: one made during a step is always
 // seen by a later step (the entry is queued for the next one, or already
 // is).
+//
+// Relaxation filter.  The first window's searches run with no committed
+// labels, so for its first kWLand roots h they are complete Dijkstra
+// searches and their distance rows are exact: d(h, v) for every v.  For any
+// later window, QUERY(root, v) over the committed labels equals the minimum
+// of d(root, h) + d(h, v) over all committed hubs h (the property behind
+// Theorem 4.1), so it is at most lb = min over those kWLand hubs.  An edge
+// that would give v a distance nd >= lb can only make v pruned at nd, and
+// a pruned vertex does nothing, so the relaxation is skipped before its
+// random read of td: the rows are kept vertex-major as 16-bit distances
+// (kWLand of them = 32 bytes per vertex, cache resident), a distance of
+// 65535 or more stored as 65535 and then left out of the minimum (the bound
+// only gets weaker, so it stays safe).  For a digraph the forward search
+// uses d(root -> h) from the reverse rows and d(h -> v) from the forward
+// rows, and the reverse search the other way round.  The same bound makes
+// the landmark hubs useless in the prune test of a later window (an entry
+// is only reached below it), so a test at a distance below 65535 skips the
+// label entries of hubs below kWLand.
 #include "pll_internal.h"
 
 namespace pll {
@@ -81,6 +99,65 @@ struct WRootTable {
 __device__ __forceinline__ WRootTable wroot_table(const DWWindow &w, int32_t j) {
   const int64_t a = w.htoff[j], b = w.htoff[j + 1];
   return WRootTable{w.ht + a, (uint32_t)(b - a - 1), b == a};
+}
+
+// Hub signature bit (0..255) of a root's label: a label entry whose hub's
+// bit is clear in the root's 256-bit signature cannot be in the root's
+// table, so it is not probed.
+__device__ __forceinline__ uint32_t wsig_bit(uint32_t h) { return (h * 2654435761u) >> 24; }
+
+// The prune test of entry (root table T, vertex u) at distance d: does some
+// hub of L(u) (from entry b0 on) give T[h] + d(h, u) <= d?  G lanes, U
+// entries per lane per round, signature check before each probe; adds the
+// entries read to *scanned (lane 0).
+template <int G>
+__device__ __forceinline__ bool wlabel_prunes(const DWStore &s, const WRootTable &T,
+                                              const uint64_t *sig, int32_t u, uint32_t d,
+                                              int32_t b0, unsigned long long *scanned) {
+  constexpr int U = 2;
+  const int gr = Group<G>::rank();
+  const int64_t o = s.off[u];
+  const int32_t len = s.len[u];
+  if (T.empty || len <= b0) return false;
+  const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
+  const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
+  for (int32_t base = b0; base < len; base += G * U) {
+    if (gr == 0) *scanned += (unsigned long long)(len - base < G * U ? len - base : G * U);
+    uint64_t ent[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      const int32_t e = base + i * G + gr;
+      ent[i] = e < len ? s.ent[o + e] : kEmptyW;
+    }
+    uint32_t hh[U], slot[U];
+    bool want[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      hh[i] = (uint32_t)(ent[i] >> 32);
+      const uint32_t b = wsig_bit(hh[i]);
+      const uint64_t wd = (b & 128) ? ((b & 64) ? s23.y : s23.x) : ((b & 64) ? s01.y : s01.x);
+      want[i] = ent[i] != kEmptyW && ((wd >> (b & 63)) & 1ull);
+      slot[i] = wt_hash(hh[i]) & T.mask;
+    }
+    uint64_t te[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) te[i] = want[i] ? T.p[slot[i]] : kEmptyW;
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      if (!want[i]) continue;
+      // finish the probe sequence (rarely more than one slot at load <= 1/4)
+      uint64_t e = te[i];
+      uint32_t sl = slot[i];
+      while ((uint32_t)e != hh[i] && e != kEmptyW) {
+        sl = (sl + 1) & T.mask;
+        e = T.p[sl];
+      }
+      if (e != kEmptyW) hit |= (ent[i] & 0xFFFFFFFFull) + (e >> 32) <= (uint64_t)d;
+    }
+    if (Group<G>::any(hit)) return true;
+  }
+  return false;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -151,22 +228,30 @@ __global__ void __launch_bounds__(kBlock) k_ww_init(DWStore src, DWWindow w) {
     w.ctl->fcnt[0] = (unsigned long long)w.W;
     w.ctl->tcnt = (unsigned long long)w.W;
   }
-  if (fits) {
-    const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
+  const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
+  if (fits)
     for (int64_t e = lane; e < sz; e += kWave) w.ht[a + e] = kEmptyW;
-    __threadfence_block();  // the wave's clears land before its inserts
-    const int64_t o = src.off[r];
-    const int32_t len = src.len[r];
-    for (int32_t e = lane; e < len; e += kWave) {
-      const uint64_t ent = src.ent[o + e];
-      const uint32_t h = (uint32_t)(ent >> 32);
-      const unsigned long long te = ((ent & 0xFFFFFFFFull) << 32) | h;
-      uint32_t slot = wt_hash(h) & (uint32_t)(sz - 1);
-      while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmptyW, te) !=
-             (unsigned long long)kEmptyW)
-        slot = (slot + 1) & (uint32_t)(sz - 1);
-    }
+  __threadfence_block();  // the wave's clears land before its inserts
+  const int64_t o = src.off[r];
+  const int32_t len = src.len[r];
+  uint64_t sg[4] = {0ull, 0ull, 0ull, 0ull};
+  for (int32_t e = lane; e < len; e += kWave) {
+    const uint64_t ent = src.ent[o + e];
+    const uint32_t h = (uint32_t)(ent >> 32);
+    const uint32_t bit = wsig_bit(h);
+#pragma unroll
+    for (int q = 0; q < 4; q++) sg[q] |= (uint32_t)q == (bit >> 6) ? 1ull << (bit & 63) : 0ull;
+    if (!fits) continue;
+    const unsigned long long te = ((ent & 0xFFFFFFFFull) << 32) | h;
+    uint32_t slot = wt_hash(h) & (uint32_t)(sz - 1);
+    while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmptyW, te) !=
+           (unsigned long long)kEmptyW)
+      slot = (slot + 1) & (uint32_t)(sz - 1);
   }
+#pragma unroll
+  for (int q = 0; q < 4; q++) sg[q] = Group<kWave>::or_reduce(sg[q]);
+  if (lane < 4)
+    w.sig[4 * (int64_t)j + lane] = lane == 0 ? sg[0] : lane == 1 ? sg[1] : lane == 2 ? sg[2] : sg[3];
   if (lane == 0) {
     const int64_t idx = (int64_t)j * w.n + r;
     w.td[idx] = 0;
@@ -198,7 +283,8 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
   const int32_t n = w.n;
-  unsigned long long c_tests = 0, c_scanned = 0, c_edges = 0, c_improved = 0, c_proc = 0;
+  unsigned long long c_tests = 0, c_scanned = 0, c_edges = 0, c_improved = 0, c_proc = 0,
+                     c_filtered = 0, c_checked = 0;
   for (int64_t i = gid; i < (int64_t)cnt; i += ngroups) {
     const int32_t j = inj[i], u = inu[i];
     const int64_t idx = (int64_t)j * n + u;
@@ -211,28 +297,28 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
     f = (uint32_t)__shfl((int)f, gb);
     d = (uint32_t)__shfl((int)d, gb);
     if (!(f & kLabeled)) {
-      const WRootTable T = wroot_table(w, j);
-      const int64_t o = s.off[u];
-      const int32_t len = s.len[u];
-      if (gr == 0) {
-        c_tests++;
-        c_scanned += (unsigned long long)len;
-      }
-      bool pr = false;
-      for (int32_t b = 0; b < len; b += G) {
-        const int32_t e = b + gr;
-        if (e < len) {
-          const uint64_t ent = s.ent[o + e];
-          const uint32_t th = T.get((uint32_t)(ent >> 32));
-          if (th != kWInf && (ent & 0xFFFFFFFFull) + th <= (uint64_t)d) pr = true;
-        }
-        if (Group<G>::any(pr)) {
-          pr = true;
-          break;
-        }
-      }
+      if (gr == 0) c_tests++;
+      // entries of landmark hubs cannot prune here (see above): the entry
+      // was reached below the 16-bit bound, and a hub left out of that
+      // bound is at least 65535 away, so below 65535 none of them can
+      const int32_t b0 = (w.lroot && d < 0xFFFFu) ? (int32_t)w.lskip[u] : 0;
+      const bool pr = wlabel_prunes<G>(s, wroot_table(w, j), w.sig + 4 * (int64_t)j, u, d, b0,
+                                       &c_scanned);
       if (pr) continue;
       if (gr == 0) fl_or(w.fl, idx, kLabeled);
+    }
+    // the root's distances to the landmark hubs (see the filter above)
+    uint32_t rl[kWLand / 2];  // pairs of 16-bit distances
+    if (w.lroot) {
+      const uint4 *p = reinterpret_cast<const uint4 *>(w.lroot + (int64_t)(w.s + j) * kWLand);
+#pragma unroll
+      for (int q = 0; q < kWLand / 8; q++) {
+        const uint4 x = p[q];
+        rl[4 * q] = x.x;
+        rl[4 * q + 1] = x.y;
+        rl[4 * q + 2] = x.z;
+        rl[4 * q + 3] = x.w;
+      }
     }
     const int64_t a = g.row[u], b = g.row[u + 1];
     for (int64_t e = a + gr; e < b; e += G) {
@@ -240,7 +326,32 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
       const uint64_t nd = (uint64_t)d + g.wt[e];
       bool push_n = false, push_t = false;
       c_edges++;
-      if (nd < (uint64_t)kWInf) {
+      bool useful = nd < (uint64_t)kWInf;
+      if (useful && w.lroot) {
+        c_checked++;
+        const uint4 *p = reinterpret_cast<const uint4 *>(w.lvert + (int64_t)v * kWLand);
+        uint32_t lb = kWInf;
+#pragma unroll
+        for (int q = 0; q < kWLand / 8; q++) {
+          const uint4 x = p[q];
+          const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+          for (int i = 0; i < 4; i++) {
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+              const uint32_t a16 = (rl[4 * q + i] >> (16 * half)) & 0xFFFFu;
+              const uint32_t b16 = (xv[i] >> (16 * half)) & 0xFFFFu;
+              const uint32_t t = (a16 == 0xFFFFu || b16 == 0xFFFFu) ? kWInf : a16 + b16;
+              lb = t < lb ? t : lb;
+            }
+          }
+        }
+        if ((uint64_t)lb <= nd) {
+          useful = false;
+          c_filtered++;
+        }
+      }
+      if (useful) {
         const int64_t vi = (int64_t)j * n + v;
         if ((uint32_t)nd < w.td[vi]) {
           const uint32_t old = atomicMin(&w.td[vi], (uint32_t)nd);
@@ -277,7 +388,11 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
   c_edges = wave_sum(c_edges);
   c_improved = wave_sum(c_improved);
   c_proc = wave_sum(c_proc);
+  c_filtered = wave_sum(c_filtered);
+  c_checked = wave_sum(c_checked);
   if (lane_id() == 0) {
+    if (c_checked) atomicAdd(&w.ctl->checked, c_checked);
+    if (c_filtered) atomicAdd(&w.ctl->filtered, c_filtered);
     if (c_tests) atomicAdd(&w.ctl->tests, c_tests);
     if (c_scanned) atomicAdd(&w.ctl->scanned, c_scanned);
     if (c_edges) atomicAdd(&w.ctl->edges, c_edges);
@@ -485,6 +600,30 @@ __global__ void __launch_bounds__(kBlock) k_ww_reset(DWWindow w) {
   }
 }
 
+// Vertex-major 16-bit copy of the first kWLand distance rows of a window:
+// out[v * kWLand + h] = min(td[h][v], 65535).
+__global__ void __launch_bounds__(kBlock) k_ww_landmarks(DWWindow w, uint16_t *out) {
+  const int64_t total = (int64_t)w.n * kWLand;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / kWLand, h = i % kWLand;
+    const uint32_t d = w.td[h * w.n + v];
+    out[i] = (uint16_t)(d < 0xFFFFu ? d : 0xFFFFu);
+  }
+}
+
+// Per vertex: how many of its first label entries have a landmark hub.
+__global__ void __launch_bounds__(kBlock) k_ww_lskip(DWStore st, int32_t n, uint8_t *skip) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o = st.off[v];
+    const int32_t len = st.len[v];
+    int32_t c = 0;
+    while (c < len && c < kWLand && (uint32_t)(st.ent[o + c] >> 32) < (uint32_t)kWLand) c++;
+    skip[v] = (uint8_t)c;
+  }
+}
+
 __global__ void k_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n) {
   const int32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < n) cnt[r] = (int64_t)len[r] + 1;  // + sentinel
@@ -662,6 +801,20 @@ hipError_t launch_ww_commit(DWWindow w, DWStore s, hipStream_t st) {
 
 hipError_t launch_ww_reset(DWWindow w, hipStream_t st) {
   hipLaunchKernelGGL(k_ww_reset, dim3(kGrid), dim3(kBlock), 0, st, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_landmarks(DWWindow w, uint16_t *out, hipStream_t st) {
+  if (w.n <= 0 || w.W < kWLand) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ww_landmarks, dim3(grid_for((int64_t)w.n * kWLand, kBlock, 8192)),
+                     dim3(kBlock), 0, st, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ww_lskip(DWStore s, int32_t n, uint8_t *skip, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ww_lskip, dim3(grid_for(n, kBlock, 8192)), dim3(kBlock), 0, st, s, n,
+                     skip);
   return hipGetLastError();
 }
 

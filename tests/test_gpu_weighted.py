@@ -60,17 +60,32 @@ def test_weighted_families(name, g):
         assert np.array_equal(gx.query_weighted(pairs, plain=True), want)
 
 
-@pytest.mark.parametrize("window,xgroup,work", [
+@pytest.mark.parametrize("window,wgroup,work", [
     (1, 16, 0), (3, 4, 0), (64, 64, 0), (700, 16, 0), (4096, 8, 0), (4096, 16, 1000),
-    (4096, 32, 200000)])
-def test_weighted_windows_and_groups(window, xgroup, work):
+    (4096, 32, 200000), (4096, 64, 30000)])
+def test_weighted_windows_and_groups(window, wgroup, work):
     _require_gpu()
     g = gen.uniform_weights(gen.rmat_graph(11, seed=4), 1, 100, 6)
     order = gen.degree_order(g)
     ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
-    with Tuned(window=window, xgroup=xgroup, window_work=work):
+    with Tuned(window=window, wgroup=wgroup, wwork=work):
         gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
-    assert_same_weighted(gx, ox, f"window={window} xgroup={xgroup} work={work}")
+    assert_same_weighted(gx, ox, f"window={window} wgroup={wgroup} work={work}")
+
+
+@pytest.mark.parametrize("lo,hi", [(1, 100000), (20000, 60000), (60000, 70000), (1, 3)])
+def test_weighted_landmark_saturation(lo, hi):
+    # distances beyond 16 bits weaken the landmark bound of later windows
+    # (saturated landmark distances are left out); labels must not change
+    _require_gpu()
+    g = gen.uniform_weights(gen.rmat_graph(11, seed=8), lo, hi, 10)
+    order = gen.degree_order(g)
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
+    with Tuned(window=4096, wwork=4000):
+        gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
+    assert_same_weighted(gx, ox, f"weights [{lo}, {hi}]")
+    pairs = gen.random_pairs(g.n, 50_000, 2)
+    assert np.array_equal(gx.query_weighted(pairs), oracle.query_weighted(ox, pairs))
 
 
 def test_weighted_plain_build():
@@ -82,9 +97,9 @@ def test_weighted_plain_build():
                          "plain")
 
 
-@pytest.mark.parametrize("knobs", [dict(list_cap=1, window=256, window_work=0),
-                                   dict(table_cap=1, window=128, window_work=0),
-                                   dict(list_cap=5000, table_cap=64, window=1024, window_work=0)])
+@pytest.mark.parametrize("knobs", [dict(list_cap=1, window=256, wwork=0),
+                                   dict(table_cap=1, window=128, wwork=0),
+                                   dict(list_cap=5000, table_cap=64, window=1024, wwork=0)])
 def test_weighted_overflow_retries(knobs):
     # lists or root tables too small: windows are re-run (fewer roots, or
     # bigger tables) until they fit; the result must not change
@@ -150,7 +165,7 @@ def test_weighted_digraphs(name, g, window):
     g = gen.uniform_weights(g, 1, 30, 9)
     order = gen.degree_order_directed(g)
     ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order, directed=True)
-    with Tuned(window=window, window_work=0):
+    with Tuned(window=window, wwork=0):
         gx = binding.build_weighted(g.row_ptr, g.col, g.w, order, directed=True)
     assert_same_weighted(gx, ox, f"{name} window={window}")
     pairs = all_pairs(g.n) if g.n <= 400 else gen.random_pairs(g.n, 200_000, 3)
