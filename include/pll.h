@@ -160,6 +160,19 @@ int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8
                     uint32_t flags, void *stream);
 
 /*
+ * Autotuner of the batched query kernels: times every lane group size
+ * (16, 32 and 64 lanes per pair) on q sample pairs of this index (3 timed
+ * launches each after a warm-up, HIP events on stream), sets the
+ * process-wide "qgroup" knob to the fastest and writes it to *best (may be
+ * NULL).  Works for unweighted and weighted indexes.  pairs: int32[2q] ids,
+ * host memory or device memory under PLL_DEVICE_PTRS (validated first).
+ * Synchronises the stream.  Errors: PLL_E_INVAL (null index or pairs,
+ * q <= 0, id out of range), PLL_E_NOMEM, PLL_E_DEVICE.
+ */
+int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t flags,
+                       void *stream, int32_t *best);
+
+/*
  * Wait for the index's work on stream and return (and clear) the error
  * recorded by earlier asynchronous pll_query calls with device pointers.
  */

@@ -34,7 +34,7 @@ EXPORTED = [
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
-    "pll_query_weighted", "pll_export_weighted",
+    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -88,6 +88,8 @@ def _lib():
         lib.pll_query_weighted.restype = C.c_int
         lib.pll_export_weighted.argtypes = [P, C.c_int32, P, P, P, P, P]
         lib.pll_export_weighted.restype = C.c_int
+        lib.pll_autotune_query.argtypes = [P, P, C.c_int64, C.c_uint32, P, P]
+        lib.pll_autotune_query.restype = C.c_int
         lib.pll_level_trace.argtypes = [P, P, C.c_int64]
         lib.pll_level_trace.restype = C.c_int64
         lib.pll_free.argtypes = [P]
@@ -329,6 +331,27 @@ class Index:
                                           _ptr(out["hub"]), _ptr(out["dist"]), _ptr(out["rank"])),
                "export_weighted")
         return out
+
+    def autotune_query(self, pairs, stream=None) -> int:
+        """Time the batched query kernel at 16/32/64 lanes per pair on these
+        sample pairs (numpy int32[q, 2], or a torch device tensor) and keep
+        the fastest as the "qgroup" knob; returns it."""
+        best = C.c_int32()
+        if isinstance(pairs, np.ndarray):
+            pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+            _check(_lib().pll_autotune_query(self._h, _ptr(pairs), len(pairs), 0, None,
+                                             C.byref(best)), "autotune_query")
+        else:
+            import torch
+
+            assert pairs.dtype == torch.int32 and pairs.is_cuda and pairs.is_contiguous()
+            if stream is None:
+                stream = torch.cuda.current_stream()
+            _check(_lib().pll_autotune_query(self._h, C.c_void_p(pairs.data_ptr()),
+                                             pairs.numel() // 2, DEVICE_PTRS,
+                                             C.c_void_p(stream.cuda_stream), C.byref(best)),
+                   "autotune_query")
+        return best.value
 
     TRACE_COLS = ["window", "first_root", "roots", "level", "entries", "candidates", "ns"]
 

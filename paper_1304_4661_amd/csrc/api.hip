@@ -1736,6 +1736,74 @@ int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8
   return pll_query(idx, pairs, q, out, flags, stream);
 }
 
+int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t flags,
+                       void *stream, int32_t *best) {
+  if (!idx || q <= 0 || !pairs) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
+  const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  if (!device)
+    for (int64_t i = 0; i < 2 * q; i++)
+      if (pairs[i] < 0 || pairs[i] >= idx->n) return PLL_E_INVAL;
+  return guarded([&] {
+    DBuf<int32_t> dp;
+    const int32_t *pp = pairs;
+    if (!device) {
+      dp.alloc((size_t)(2 * q));
+      h2d(dp.p, pairs, (size_t)(2 * q), st);
+      pp = dp.p;
+    } else {
+      // device ids are validated first, as in pll_query
+      DBuf<int32_t> err(1);
+      fill(err, 0, st);
+      check(launch_validate_pairs(pairs, q, idx->n, err.p, st));
+      int32_t herr = 0;
+      d2h(&herr, err.p, 1, st);
+      check(hipStreamSynchronize(st));
+      if (herr) return PLL_E_INVAL;
+    }
+    DBuf<uint32_t> out((size_t)q);  // room for 8- or 32-bit answers
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    check(hipEventCreate(&e0));
+    check(hipEventCreate(&e1));
+    struct EvGuard {
+      hipEvent_t a, b;
+      ~EvGuard() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } evg{e0, e1};
+    const DIndex v = idx->view();
+    auto launch = [&](int g) {
+      if (idx->weighted)
+        check(launch_wquery(v, pp, q, out.p, nullptr, false, g, st));
+      else
+        check(launch_query(v, pp, q, reinterpret_cast<uint8_t *>(out.p), nullptr, false, g, st));
+    };
+    int32_t choice = 64;
+    float best_ms = 0.f;
+    for (int g : {16, 32, 64}) {
+      launch(g);  // warm
+      check(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; r++) launch(g);
+      check(hipEventRecord(e1, st));
+      check(hipEventSynchronize(e1));
+      float ms = 0.f;
+      check(hipEventElapsedTime(&ms, e0, e1));
+      if (g == 16 || ms < best_ms) {
+        best_ms = ms;
+        choice = g;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune.qgroup = choice;
+    }
+    if (best) *best = choice;
+    return PLL_OK;
+  });
+}
+
 int pll_sync(const pll_index *idx, void *stream) {
   if (!idx) return PLL_E_INVAL;
   hipStream_t st = (hipStream_t)stream;

@@ -196,3 +196,10 @@ def test_weighted_entry_points_reject_bad_arguments():
     pairs = np.zeros(2, np.int32)
     assert lib.pll_query_weighted(None, ptr(pairs), 1, ptr(out), 0, None) == binding.E_INVAL
     assert lib.pll_export_weighted(None, 0, None, None, None, None, None) == binding.E_INVAL
+
+
+def test_autotune_rejects_bad_arguments():
+    lib = binding.library()
+    pairs = np.zeros(2, np.int32)
+    best = C.c_int32()
+    assert lib.pll_autotune_query(None, pairs.ctypes.data, 1, 0, None, C.byref(best)) == binding.E_INVAL

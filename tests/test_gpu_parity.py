@@ -253,3 +253,26 @@ def test_rmat18_benchmark_workload():
     out = torch.empty(len(pairs), dtype=torch.uint8, device="cuda")
     gx.query_device(dp, out, sync=True)
     assert np.array_equal(out.cpu().numpy(), oracle.query(ox, pairs))
+
+
+def test_query_autotune():
+    # the autotuner picks one of the group sizes and answers do not change
+    import torch
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    want = oracle.query(ox, pairs)
+    with Tuned(qgroup=64):
+        best = gx.autotune_query(pairs[:20000])
+        assert best in (16, 32, 64) and binding.get_tuning("qgroup") == best
+        assert np.array_equal(gx.query(pairs), want)
+        best2 = gx.autotune_query(torch.from_numpy(pairs[:20000]).cuda())
+        assert best2 in (16, 32, 64)
+        assert np.array_equal(gx.query(pairs), want)
+        bad = pairs[:10].copy()
+        bad[2, 1] = g.n
+        with pytest.raises(binding.PllError):
+            gx.autotune_query(bad)
+        with pytest.raises(binding.PllError):
+            gx.autotune_query(torch.from_numpy(bad).cuda())

@@ -253,3 +253,13 @@ def test_weighted_rmat18_workload_sampled():
         hits = np.flatnonzero(e["hub"] == srank[i])
         owners = np.searchsorted(e["off"], hits, side="right") - 1
         assert np.array_equal(e["dist"][hits].astype(np.uint64), want[i][inv[owners]])
+
+
+def test_weighted_query_autotune():
+    _require_gpu()
+    g, order, _, pairs = gen.config_graph("ba2000w")
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
+    gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
+    with Tuned(qgroup=64):
+        assert gx.autotune_query(pairs[:20000]) in (16, 32, 64)
+        assert np.array_equal(gx.query_weighted(pairs), oracle.query_weighted(ox, pairs))
