@@ -20,7 +20,7 @@ namespace {
 struct Tuning {
   int window = 16384;  // most concurrent roots of the pruned phase
   int64_t window_work = 128000000;  // visits aimed at per window (0: fixed size)
-  int64_t window_mem_mb = 16384;  // device memory allowed for per-root state
+  int64_t window_mem_mb = 65536;  // device memory allowed for per-root state
   int64_t list_cap = 0;   // cap on frontier / candidate / task lists (0: sized from W)
   int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
   int group = 4;      // lanes per frontier entry (prune tests)
