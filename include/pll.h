@@ -67,10 +67,11 @@ enum {
 
 /*
  * Device allocator for builds and indexes (process-wide; the default is
- * hipMalloc/hipFree).  alloc(bytes, stream, ctx) returns device memory or
- * NULL (then the call fails with PLL_E_NOMEM); `stream` is the stream of the
- * build that asked, so a stream-ordered allocator (for example a caching
- * allocator's raw alloc/delete) may reuse memory in stream order.
+ * hipMalloc/hipFree behind a cache of freed blocks, see "pool_keep_mb").  alloc(bytes, stream, ctx)
+ * returns device memory or NULL (then the call fails with PLL_E_NOMEM);
+ * `stream` is the stream of the build that asked, so a stream-ordered
+ * allocator (for example a caching allocator's raw alloc/delete) may reuse
+ * memory in stream order.
  * free_(ptr, stream, ctx) gets the same stream.  Index memory is released
  * by pll_free, which the caller issues only when no work on the index is
  * pending.  Both NULL restores the default; exactly one NULL is
@@ -411,7 +412,10 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * after the first at the maximum), and "window", "window_mem_mb", "list_cap",
  * "table_cap", "levels_per_sync" (steps between host checks) and "profile"
  * as above.  Bit-parallel phase: "bp_chunk" (adjacency entries per
- * work item).  Queries: "qgroup" (lanes per pair: 16, 32, 64),
+ * work item).  Memory: "pool_keep_mb" (device memory of freed build
+ * scratch and indexes kept for reuse by later builds, MB; reuse on another
+ * stream waits for the stream that freed it; lowering the value releases
+ * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64),
  * "serve_coalesce" (0/1: servers started afterwards launch one request at a
  * time / pack several).  Returns PLL_E_INVAL for an unknown key or value.
  */

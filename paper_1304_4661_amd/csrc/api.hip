@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -27,6 +28,7 @@ struct Tuning {
   int xgroup = 16;    // lanes per candidate expanding its adjacency list
   int wgroup = 64;    // lanes per frontier entry of a weighted search step
   int64_t wwork = 2000000;  // touched entries aimed at per weighted window
+  int64_t pool_keep_mb = 16384;  // freed device memory kept for reuse by later builds
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
@@ -77,6 +79,114 @@ struct AllocStream {
   ~AllocStream() { t_alloc_stream = old; }
 };
 
+// Default device allocations go through a small cache of freed blocks: a
+// build allocates and frees the same multi-GB scratch every time, and
+// hipMalloc/hipFree (or the stream-ordered pool's free) cost milliseconds
+// per build.  A freed block is kept (up to "pool_keep_mb" in total) with an
+// event recorded on the stream it was released on; a later allocation of
+// the same rounded size takes it and, on another stream, waits for that
+// event first, so reuse is stream-ordered.
+struct CachedBlock {
+  void *p;
+  int dev;
+  hipEvent_t ev;
+  hipStream_t stream;
+};
+struct BlockCache {
+  std::mutex mu;
+  std::multimap<size_t, CachedBlock> blocks;  // by rounded size
+  size_t total = 0;
+};
+BlockCache g_blocks;
+
+size_t round_bytes(size_t b) {
+  const size_t mb = (size_t)1 << 20;
+  return b <= mb ? ((b + 255) & ~(size_t)255) : ((b + mb - 1) & ~(mb - 1));
+}
+
+// Free every cached block (all devices) beyond `keep` bytes.
+void cache_trim(size_t keep) {
+  std::vector<CachedBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_blocks.mu);
+    while (g_blocks.total > keep && !g_blocks.blocks.empty()) {
+      auto it = std::prev(g_blocks.blocks.end());  // largest first
+      g_blocks.total -= it->first;
+      drop.push_back(it->second);
+      g_blocks.blocks.erase(it);
+    }
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (auto &b : drop) {
+    (void)hipSetDevice(b.dev);
+    (void)hipEventSynchronize(b.ev);
+    (void)hipEventDestroy(b.ev);
+    (void)hipFree(b.p);
+  }
+  (void)hipSetDevice(cur);
+}
+
+hipError_t cache_alloc(void **p, size_t bytes, hipStream_t st) {
+  const size_t rb = round_bytes(bytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_blocks.mu);
+    auto range = g_blocks.blocks.equal_range(rb);
+    for (auto it = range.first; it != range.second; ++it) {
+      if (it->second.dev != dev) continue;
+      CachedBlock b = it->second;
+      g_blocks.blocks.erase(it);
+      g_blocks.total -= rb;
+      if (b.stream != st) e = hipStreamWaitEvent(st, b.ev, 0);
+      (void)hipEventDestroy(b.ev);
+      if (e != hipSuccess) {
+        (void)hipFree(b.p);
+        return e;
+      }
+      *p = b.p;
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, rb);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    cache_trim(0);  // give the cached blocks back and try once more
+    e = hipMalloc(p, rb);
+  }
+  return e;
+}
+
+void cache_free(void *p, size_t bytes, hipStream_t st) {
+  const size_t rb = round_bytes(bytes);
+  const size_t keep = (size_t)tuning().pool_keep_mb << 20;
+  int dev = 0;
+  hipEvent_t ev = nullptr;
+  if (rb <= keep && hipGetDevice(&dev) == hipSuccess &&
+      hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
+    if (hipEventRecord(ev, st) == hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_blocks.mu);
+      g_blocks.blocks.emplace(rb, CachedBlock{p, dev, ev, st});
+      g_blocks.total += rb;
+      if (g_blocks.total <= keep) return;
+    } else {
+      (void)hipEventDestroy(ev);
+      ev = nullptr;
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(p);
+      return;
+    }
+    cache_trim(keep);  // over the limit: drop the largest blocks
+    return;
+  }
+  (void)hipGetLastError();
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(p);
+}
+
 template <typename T>
 struct DBuf {
   T *p = nullptr;
@@ -112,7 +222,7 @@ struct DBuf {
       p = static_cast<T *>(hook.alloc(bytes, (void *)stream, hook.ctx));
       if (!p) throw Fail{PLL_E_NOMEM};
     } else {
-      hipError_t e = hipMalloc((void **)&p, bytes);
+      hipError_t e = cache_alloc((void **)&p, bytes, stream);
       if (e != hipSuccess) {
         p = nullptr;
         (void)hipGetLastError();
@@ -126,7 +236,7 @@ struct DBuf {
       if (hook.alloc)
         hook.free_(p, (void *)stream, hook.ctx);
       else
-        (void)hipFree(p);
+        cache_free(p, std::max<size_t>(count * sizeof(T), 1), stream);
     }
     p = nullptr;
     count = 0;
@@ -196,6 +306,21 @@ struct pll_index {
   int64_t stats[PLL_NSTATS] = {};
   std::vector<int64_t> level_trace;  // pruned-phase levels, PLL_TRACE_COLS per row
   std::vector<int32_t> bp_root, bp_nsel, bp_sel;  // per slot record (graph * t + slot)
+
+  // The index outlives the stream it was built on: its memory is released
+  // in order on the null stream (pll_free requires no pending work on it).
+  void detach_streams() {
+    for (auto *b : {&rgid, &lrank, &rank, &err, &gcol, &ord})
+      if (!b->hook.alloc) b->stream = nullptr;
+    for (auto *b : {&bpd, &dist, &idist})
+      if (!b->hook.alloc) b->stream = nullptr;
+    for (auto *b : {&bpm, &went, &iwent})
+      if (!b->hook.alloc) b->stream = nullptr;
+    for (auto *b : {&off, &ioff, &grow})
+      if (!b->hook.alloc) b->stream = nullptr;
+    for (auto *b : {&hub, &par, &ihub})
+      if (!b->hook.alloc) b->stream = nullptr;
+  }
 
   DIndex view() const {
     DIndex v;
@@ -305,16 +430,40 @@ struct CtlMirror {
   LevelCtl ctl;
   unsigned long long top;
 };
-struct PinnedMirror {
-  CtlMirror *p = nullptr;
-  PinnedMirror() {
-    if (hipHostMalloc((void **)&p, sizeof(CtlMirror), hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
+// Pinned host blocks are recycled across builds: hipHostMalloc/hipHostFree
+// cost milliseconds each, a build needs only a few small ones.
+template <typename T>
+struct PinnedPool {
+  std::mutex mu;
+  std::vector<T *> free_list;
+  T *get() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!free_list.empty()) {
+        T *p = free_list.back();
+        free_list.pop_back();
+        return p;
+      }
+    }
+    T *p = nullptr;
+    if (hipHostMalloc((void **)&p, sizeof(T), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
       throw Fail{PLL_E_NOMEM};
     }
+    return p;
   }
+  void put(T *p) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_list.push_back(p);
+  }
+};
+PinnedPool<CtlMirror> g_ctl_pinned;
+
+struct PinnedMirror {
+  CtlMirror *p = nullptr;
+  PinnedMirror() { p = g_ctl_pinned.get(); }
   ~PinnedMirror() {
-    if (p) (void)hipHostFree(p);
+    if (p) g_ctl_pinned.put(p);
   }
   PinnedMirror(const PinnedMirror &) = delete;
   PinnedMirror &operator=(const PinnedMirror &) = delete;
@@ -842,16 +991,12 @@ struct WMirrorData {
   WCtl ctl;
   unsigned long long top;
 };
+PinnedPool<WMirrorData> g_wctl_pinned;
 struct WMirror {
   WMirrorData *p = nullptr;
-  WMirror() {
-    if (hipHostMalloc((void **)&p, sizeof(WMirrorData), hipHostMallocDefault) != hipSuccess) {
-      p = nullptr;
-      throw Fail{PLL_E_NOMEM};
-    }
-  }
+  WMirror() { p = g_wctl_pinned.get(); }
   ~WMirror() {
-    if (p) (void)hipHostFree(p);
+    if (p) g_wctl_pinned.put(p);
   }
   WMirror(const WMirror &) = delete;
   WMirror &operator=(const WMirror &) = delete;
@@ -1997,7 +2142,11 @@ int64_t pll_level_trace(const pll_index *idx, int64_t *rows, int64_t max_rows) {
   return nrows;
 }
 
-void pll_free(pll_index *idx) { delete idx; }
+void pll_free(pll_index *idx) {
+  if (!idx) return;
+  idx->detach_streams();
+  delete idx;
+}
 
 const char *pll_strerror(int code) {
   switch (code) {
@@ -2011,10 +2160,21 @@ const char *pll_strerror(int code) {
   }
 }
 
+static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_to);
+
 int pll_set_tuning(const char *key, int64_t value) {
   if (!key) return PLL_E_INVAL;
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  const std::string k(key);
+  int64_t trim_to = -1;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    rc = set_tuning_locked(std::string(key), value, trim_to);
+  }
+  if (rc == PLL_OK && trim_to >= 0) cache_trim((size_t)trim_to << 20);
+  return rc;
+}
+
+static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_to) {
   auto pow2_in = [](int64_t v, int64_t lo, int64_t hi) {
     return v >= lo && v <= hi && (v & (v - 1)) == 0;
   };
@@ -2042,6 +2202,10 @@ int pll_set_tuning(const char *key, int64_t value) {
   } else if (k == "wgroup") {
     if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
     g_tune.wgroup = (int)value;
+  } else if (k == "pool_keep_mb") {
+    if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
+    g_tune.pool_keep_mb = value;
+    trim_to = value;
   } else if (k == "wwork") {
     if (value < 0 || value > (1ll << 40)) return PLL_E_INVAL;
     g_tune.wwork = value;
@@ -2082,6 +2246,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "xgroup") return g_tune.xgroup;
   if (k == "wgroup") return g_tune.wgroup;
   if (k == "wwork") return g_tune.wwork;
+  if (k == "pool_keep_mb") return g_tune.pool_keep_mb;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;
