@@ -276,3 +276,28 @@ def test_query_autotune():
             gx.autotune_query(bad)
         with pytest.raises(binding.PllError):
             gx.autotune_query(torch.from_numpy(bad).cuda())
+
+
+def test_block_cache_across_streams():
+    # freed build memory is reused by later builds, also on other streams
+    # (event-ordered); with the cache off every block is freed; results equal
+    import torch
+    _require_gpu()
+    g, order, t_bp, pairs = gen.config_graph("ba2000")
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    want = oracle.query(ox, pairs)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dev = torch.device("cuda:0")
+    d = [torch.from_numpy(a).to(dev) for a in (g.row_ptr, g.col, order)]
+    dp = torch.from_numpy(pairs).to(dev)
+    torch.cuda.synchronize()
+    for keep in (16384, 0, 16384):
+        with Tuned(pool_keep_mb=keep):
+            for s in (s1, s2, s1):
+                with torch.cuda.stream(s):
+                    gx = binding.build_device(*d, t_bp, stream=s)
+                    out = torch.empty(len(pairs), dtype=torch.uint8, device=dev)
+                    gx.query_device(dp, out, stream=s, sync=True)
+                assert np.array_equal(out.cpu().numpy(), want), (keep, s)
+                assert_same_index(gx, ox, f"keep={keep}")
+                gx.close()
