@@ -571,14 +571,22 @@ def sweep(args):
     rows = []
     if args.sweep == "tbp":
         graphs_ = [("rmat18", gen.rmat_graph(18, seed=1)), ("ba200k_m4", gen.ba_graph(200_000, 4, 3))]
+        from paper_1304_4661_amd import binding
+
         for gname, g in graphs_:
             order = gen.degree_order(g)
-            for t in (0, 1, 2, 4, 8, 16, 32, 50, 64):
-                r = {"graph": gname, "order": "degree", **sweep_point(g, order, t, args.steps)}
+            # t_bp = 0 as the paper runs it (plain pruned BFSs) and with the
+            # library's landmark rows (same labels, less work)
+            for t, land in ((0, 0), (0, 1), (1, 1), (2, 1), (4, 1), (8, 1), (16, 1), (32, 1),
+                            (50, 1), (64, 1)):
+                binding.set_tuning("landmarks", land)
+                r = {"graph": gname, "order": "degree", "landmarks": land if t == 0 else "-",
+                     **sweep_point(g, order, t, args.steps)}
                 rows.append(r)
                 print(json.dumps(r), flush=True)
-        cols = ["graph", "t_bp", "build_s", "query_ns_batched", "query_ns_plain", "ln_normal",
-                "ln_bp", "index_bytes"]
+            binding.set_tuning("landmarks", 1)
+        cols = ["graph", "t_bp", "landmarks", "build_s", "query_ns_batched", "query_ns_plain",
+                "ln_normal", "ln_bp", "index_bytes"]
     else:
         graphs_ = [(f"rmat{s}", gen.rmat_graph(s, seed=1)) for s in (12, 14, 16, 18)]
         graphs_.append(("ba200k_m4", gen.ba_graph(200_000, 4, 3)))

@@ -412,7 +412,10 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * after the first at the maximum), and "window", "window_mem_mb", "list_cap",
  * "table_cap", "levels_per_sync" (steps between host checks) and "profile"
  * as above.  Bit-parallel phase: "bp_chunk" (adjacency entries per
- * work item).  Memory: "pool_keep_mb" (device memory of freed build
+ * work item).  "landmarks" (0/1: builds without bit-parallel labels --
+ * t_bp = 0, directed, weighted -- keep exact distances from their first 16
+ * roots and skip expansions those already prune; the labels do not
+ * change).  Memory: "pool_keep_mb" (device memory of freed build
  * scratch and indexes kept for reuse by later builds, MB; reuse on another
  * stream waits for the stream that freed it; lowering the value releases
  * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64),

@@ -29,6 +29,7 @@ struct Tuning {
   int wgroup = 64;    // lanes per frontier entry of a weighted search step
   int64_t wwork = 2000000;  // touched entries aimed at per weighted window
   int64_t pool_keep_mb = 16384;  // freed device memory kept for reuse by later builds
+  int landmarks = 1;  // landmark rows for builds without bit-parallel labels
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
@@ -751,8 +752,8 @@ struct Builder {
 
   // One window's BFS levels in one direction, until every root's search has
   // ended or a list overflowed.  Returns the last level index.
-  int side_levels(Side &D, const DBp &bp, const DWindow &w, int64_t window_index,
-                  std::vector<hipEvent_t> &evs) {
+  int side_levels(Side &D, const DBp &bp, const DBp &rb, const DBp &vb, const DWindow &w,
+                  int64_t window_index, std::vector<hipEvent_t> &evs) {
     LevelCtl &h = D.mirror.p->ctl;
     const DStore sto = D.own->view();
     const size_t mark0 = level_trace.size();
@@ -765,7 +766,8 @@ struct Builder {
       for (; d < upto; d++) {
         hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
         hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
-        check(launch_win_level(D.g, bp, sto, w, D.f, d, tu.group, tu.xgroup, tu.chunk, st, e0, e1));
+        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, tu.group, tu.xgroup, tu.chunk, st,
+                               e0, e1));
         stat_levels++;
         stat_level_launches++;
       }
@@ -834,6 +836,17 @@ struct Builder {
     check(launch_bpv_nonempty(n, t, ix->bpm.p, bpz.p, st));
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
     int64_t entries_bound[2] = {0, 0};
+    // Expansion-time prune rows.  With bit-parallel labels they are the
+    // bit-parallel distance rows (Section 5.4).  Without them (t = 0, and
+    // every directed build) the first window's first kLandmarks roots prune
+    // nothing, so its window distances are exact BFS distances from them;
+    // kept as rows, they bound QUERY(root, x) over the committed labels for
+    // every later window (the minimum of d(root, h) + d(h, x) over committed
+    // hubs h), so a neighbour at or below the bound is left unvisited as a
+    // bit-parallel row would leave it.  land[k] comes from side k.
+    DBuf<uint8_t> land[2];
+    bool have_land = false;
+    const DBp no_rows{0, 0, nullptr, nullptr, nullptr};
 
     // optional timing of each level kernel (events on the build stream)
     std::vector<hipEvent_t> evs;
@@ -863,7 +876,12 @@ struct Builder {
       int flags = 0;
       for (int k = 0; k < nsides && !flags; k++) {  // after an overflow the window is redone
         w[k] = sides[k].window(s, nr, words, used.p);
-        last[k] = side_levels(sides[k], bp, w[k], stat_windows, evs);
+        DBp rb = t > 0 ? bp : no_rows, vb = t > 0 ? bp : no_rows;
+        if (t == 0 && have_land && s >= kLandmarks) {
+          rb = DBp{kLandmarks, kLandmarks, land[nsides - 1 - k].p, nullptr, nullptr};
+          vb = DBp{kLandmarks, kLandmarks, land[k].p, nullptr, nullptr};
+        }
+        last[k] = side_levels(sides[k], bp, rb, vb, w[k], stat_windows, evs);
         ran[k] = true;
         flags |= sides[k].mirror.p->ctl.flags;
       }
@@ -911,6 +929,13 @@ struct Builder {
         W = std::max(1, W / 4);
         stat_retries++;
         continue;
+      }
+      if (t == 0 && s == 0 && nr >= kLandmarks && !have_land && !plain && tu.landmarks) {
+        for (int k = 0; k < nsides; k++) {
+          land[k].alloc((size_t)n * kLandmarks);
+          check(launch_win_landmarks(w[k], n, land[k].p, st));
+        }
+        have_land = true;
       }
       for (int k = 0; k < nsides; k++) {
         store_reserve(*sides[k].own, entries_bound[k], ncand[k], sides[k].mirror.p->top);
@@ -1287,7 +1312,7 @@ struct WBuilder {
         check(hipStreamSynchronize(st));
         continue;
       }
-      const bool make_land = s == 0 && nr >= kWLand && !have_land && !plain;
+      const bool make_land = s == 0 && nr >= kWLand && !have_land && !plain && tu.landmarks;
       if (make_land) {
         // the first window's searches had no labels to prune with: its
         // first kWLand distance rows are exact
@@ -2202,6 +2227,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "wgroup") {
     if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
     g_tune.wgroup = (int)value;
+  } else if (k == "landmarks") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.landmarks = (int)value;
   } else if (k == "pool_keep_mb") {
     if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.pool_keep_mb = value;
@@ -2247,6 +2275,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "wgroup") return g_tune.wgroup;
   if (k == "wwork") return g_tune.wwork;
   if (k == "pool_keep_mb") return g_tune.pool_keep_mb;
+  if (k == "landmarks") return g_tune.landmarks;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

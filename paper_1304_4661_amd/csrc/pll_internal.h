@@ -16,6 +16,7 @@ constexpr uint32_t kSentinel = 0xFFFFFFFFu;  // hub of the storage-only sentinel
 constexpr int kWave = 64;                // CDNA wavefront width
 constexpr int kMaxLevels = 256;          // BFS levels 0..254 are storable
 constexpr int kMaxWindow = 16384;        // concurrent roots (bits per vertex mask)
+constexpr int kLandmarks = 16;           // landmark rows of builds without bit-parallel labels
 
 // ---------------------------------------------------------------------------
 // Wave helpers (64-wide wavefronts).
@@ -397,10 +398,18 @@ hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
 // sizes: int64[nroots + 1]; scan_tmp: scan_tmp_elems(nroots + 1) int64
 hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                            int64_t *sizes, int64_t *scan_tmp, hipStream_t st);
-// ev0/ev1 (may be null): recorded around the level kernel itself.
-hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int xgroup, int chunk, hipStream_t st, hipEvent_t ev0,
-                            hipEvent_t ev1);
+// ev0/ev1 (may be null): recorded around the level kernel itself.  bp: the
+// bit-parallel labels of the prune test; rb / vb: distance rows of the
+// expansion-time prune, root side and reached-vertex side (the bit-parallel
+// rows for an undirected graph with t > 0; landmark rows otherwise, or
+// tpad = 0 for none).
+hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
+                            int d, int group, int xgroup, int chunk, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1);
+// Landmark rows out uint8[n][kLandmarks] of a window whose searches pruned
+// nothing (W >= kLandmarks): distance from its j-th root to every vertex,
+// 255 if not reached.  Run before the window's commit clears its masks.
+hipError_t launch_win_landmarks(DWindow w, int32_t n, uint8_t *out, hipStream_t st);
 hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                             int64_t nvisited, hipStream_t st);
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);

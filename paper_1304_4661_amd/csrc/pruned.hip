@@ -495,9 +495,9 @@ struct FrontierFlush {
 // bytes per vertex) mostly stay in cache while a root's visited bits are
 // spread over W·n/8 bytes, so the row test goes first and most edges never
 // touch the visited bits.
-__device__ __forceinline__ bool reach(const DBp &bp, const RootRow &rr, uint32_t *vs, int32_t x,
+__device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t *vs, int32_t x,
                                       int d, unsigned long long &direct) {
-  if (rr.direct(bp, x, d + 1)) {
+  if (rr.direct(vb, x, d + 1)) {
     direct++;
     return false;
   }
@@ -507,8 +507,9 @@ __device__ __forceinline__ bool reach(const DBp &bp, const RootRow &rr, uint32_t
 }
 
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore st, DWindow w,
-                                                       DFrontier f, int d, int chunk) {
+__global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb, DBp vb,
+                                                       DStore st, DWindow w, DFrontier f, int d,
+                                                       int chunk) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
@@ -557,7 +558,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       deg = g.row[u + 1] - e0;
       lim = deg < chunk ? deg : chunk;
       if (gr == 0) c_edge += (unsigned long long)lim;
-      rr.load(bp, w.s + j);
+      rr.load(rb, w.s + j);
     }
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
     const int64_t wl = Group<kWave>::max_reduce64(lim);
@@ -567,7 +568,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
       int32_t x = 0;
       if (idx < lim) {
         x = g.col[e0 + idx];
-        claimed = reach(bp, rr, vs, x, d, c_direct);
+        claimed = reach(vb, rr, vs, x, d, c_direct);
       }
       stage.push(claimed, j, x, flush, u);
     }
@@ -594,8 +595,9 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DStore 
   if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
 }
 
-__global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow w, DFrontier f,
-                                                      int d, int chunk, int lim_inline) {
+__global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
+                                                      DFrontier f, int d, int chunk,
+                                                      int lim_inline) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
@@ -618,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
     const int64_t b = a + chunk < e1 ? a + chunk : e1;
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
     RootRow rr;
-    rr.load(bp, w.s + j);
+    rr.load(rb, w.s + j);
     c_edge += (unsigned long long)(b - a);
     for (int64_t e0b = a; e0b < b; e0b += kWave) {
       const int64_t e = e0b + lane_id();
@@ -626,7 +628,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
       int32_t x = 0;
       if (e < b) {
         x = g.col[e];
-        claimed = reach(bp, rr, vs, x, d, c_direct);
+        claimed = reach(vb, rr, vs, x, d, c_direct);
       }
       stage.push(claimed, j, x, flush, u);
     }
@@ -635,6 +637,20 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp bp, DWindow 
   c_direct = Group<kWave>::sum_reduce(c_direct);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
   if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
+}
+
+// Landmark rows (see launch_win_landmarks): out[u * 16 + j] = d(root j, u)
+// for the first 16 roots of a window that pruned nothing, 255 if the root
+// did not reach u.
+__global__ void __launch_bounds__(kBlock) k_win_landmarks(DWindow w, int32_t n, uint8_t *out) {
+  const int64_t total = (int64_t)n * kLandmarks;
+  const int64_t stride = (int64_t)w.words * 64;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t u = i / kLandmarks, j = i % kLandmarks;
+    const bool hit = (w.cmask[u * w.words] >> j) & 1ull;
+    out[i] = hit ? w.wd[u * stride + j] : kInf8;
+  }
 }
 
 // Clear visited words of every (slot, vertex) ever put on a level.
@@ -904,9 +920,9 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
   return hipGetLastError();
 }
 
-hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, int d, int group,
-                            int xgroup, int chunk, hipStream_t st, hipEvent_t ev0,
-                            hipEvent_t ev1) {
+hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
+                            int d, int group, int xgroup, int chunk, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
   if (ev0) (void)hipEventRecord(ev0, st);
@@ -919,13 +935,20 @@ hipError_t launch_win_level(DGraph g, DBp bp, DStore s, DWindow w, DFrontier f, 
   }
   if (ev1) (void)hipEventRecord(ev1, st);
   switch (xgroup) {
-    case 4: hipLaunchKernelGGL(k_win_expand<4>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
-    case 8: hipLaunchKernelGGL(k_win_expand<8>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
-    case 16: hipLaunchKernelGGL(k_win_expand<16>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
-    case 32: hipLaunchKernelGGL(k_win_expand<32>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
-    default: hipLaunchKernelGGL(k_win_expand<64>, gd, bd, 0, st, g, bp, s, w, f, d, chunk); break;
+    case 4: hipLaunchKernelGGL(k_win_expand<4>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
+    case 8: hipLaunchKernelGGL(k_win_expand<8>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
+    case 16: hipLaunchKernelGGL(k_win_expand<16>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
+    case 32: hipLaunchKernelGGL(k_win_expand<32>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
+    default: hipLaunchKernelGGL(k_win_expand<64>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
   }
-  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, bp, w, f, d, chunk, chunk);
+  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_win_landmarks(DWindow w, int32_t n, uint8_t *out, hipStream_t st) {
+  if (n <= 0 || w.W < kLandmarks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_win_landmarks, dim3(grid_for((int64_t)n * kLandmarks, kBlock, 8192)),
+                     dim3(kBlock), 0, st, w, n, out);
   return hipGetLastError();
 }
 

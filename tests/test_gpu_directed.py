@@ -92,3 +92,21 @@ def test_directed_batch_and_errors():
         binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0, directed=True, parents=True)
     with pytest.raises(binding.PllError):
         binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0).export_in()
+
+
+@pytest.mark.parametrize("landmarks", [0, 1])
+@pytest.mark.parametrize("window", [64, 4096])
+def test_directed_landmark_rows(landmarks, window):
+    # the landmark rows of the first window only skip work: labels equal
+    _require_gpu()
+    g = gen.rmat_digraph(12, 8, seed=11)
+    order = gen.degree_order_directed(g)
+    ox = oracle.build_directed(g.row_ptr, g.col, order)
+    with Tuned(landmarks=landmarks, window=window, window_work=0):
+        gx = binding.build(g.row_ptr, g.col, order, 0, directed=True)
+    assert_same_directed(gx, ox, f"landmarks={landmarks} window={window}")
+    st = gx.stats()
+    if not landmarks:
+        assert st["bp_direct"] == 0
+    elif window < g.n:  # rows are used from the second window on
+        assert st["bp_direct"] > 0

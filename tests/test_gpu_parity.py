@@ -301,3 +301,22 @@ def test_block_cache_across_streams():
                 assert np.array_equal(out.cpu().numpy(), want), (keep, s)
                 assert_same_index(gx, ox, f"keep={keep}")
                 gx.close()
+
+
+@pytest.mark.parametrize("landmarks", [0, 1])
+@pytest.mark.parametrize("name,order_fn", [("degree", gen.degree_order),
+                                           ("random", lambda g: gen.random_order(g.n, 3))])
+def test_landmark_rows_without_bit_parallel(landmarks, name, order_fn):
+    # t_bp = 0: the first window's 16 exact BFS rows prune expansions; the
+    # labels must be the oracle's either way
+    _require_gpu()
+    g = gen.rmat_graph(11 if name == "random" else 13, seed=9)
+    order = order_fn(g)
+    ox = oracle.build(g.row_ptr, g.col, order, 0)
+    with Tuned(landmarks=landmarks, window_work=200000):
+        gx = binding.build(g.row_ptr, g.col, order, 0)
+    assert_same_index(gx, ox, f"{name} landmarks={landmarks}")
+    if not landmarks:
+        assert gx.stats()["bp_direct"] == 0
+    elif name == "degree":
+        assert gx.stats()["bp_direct"] > 0

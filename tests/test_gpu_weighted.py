@@ -263,3 +263,14 @@ def test_weighted_query_autotune():
     with Tuned(qgroup=64):
         assert gx.autotune_query(pairs[:20000]) in (16, 32, 64)
         assert np.array_equal(gx.query_weighted(pairs), oracle.query_weighted(ox, pairs))
+
+
+def test_weighted_without_landmarks():
+    _require_gpu()
+    g = gen.uniform_weights(gen.rmat_graph(11, seed=12), 1, 50, 13)
+    order = gen.degree_order(g)
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
+    with Tuned(landmarks=0, wwork=20000):
+        gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
+    assert_same_weighted(gx, ox, "no landmarks")
+    assert gx.stats()["land_checks"] == 0
