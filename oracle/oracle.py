@@ -67,6 +67,8 @@ def _configure(lib):
         lib.orc_paths.restype = C.c_int
         lib.orc_export_parents.argtypes = [C.c_void_p, P]
         lib.orc_export_parents.restype = C.c_int
+        lib.orc_export_in_parents.argtypes = [C.c_void_p, P]
+        lib.orc_export_in_parents.restype = C.c_int
         lib.orc_build_directed.argtypes = [C.c_int32, P, P, P, C.POINTER(C.c_void_p)]
         lib.orc_build_directed.restype = C.c_int
         lib.orc_export_in.argtypes = [C.c_void_p, P, P, P, P]
@@ -240,6 +242,8 @@ class DirectedIndex:
     in_off: np.ndarray
     in_hub: np.ndarray
     in_dist: np.ndarray
+    out_par: np.ndarray | None = None  # uint32 parents (ranks) of the L_OUT entries
+    in_par: np.ndarray | None = None   # ... of the L_IN entries
     counters: dict = field(default_factory=dict)
     _handle: C.c_void_p | None = None
     _lib: object = None
@@ -283,6 +287,12 @@ def build_directed(row_ptr, col, order, lib=None) -> DirectedIndex:
     ix.in_hub = np.zeros(ne_in.value, np.uint32)
     ix.in_dist = np.zeros(ne_in.value, np.uint8)
     lib.orc_export_in(h, None, None, _ptr(ix.in_hub), _ptr(ix.in_dist))
+    ix.out_par = np.zeros(ne_out, np.uint32)
+    ix.in_par = np.zeros(ne_in.value, np.uint32)
+    if ne_out:
+        lib.orc_export_parents(h, _ptr(ix.out_par))
+    if ne_in.value:
+        lib.orc_export_in_parents(h, _ptr(ix.in_par))
     nc = lib.orc_ncounters()
     cnt = np.zeros(nc, np.int64)
     lib.orc_counters(h, _ptr(cnt), nc)

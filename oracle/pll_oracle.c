@@ -31,7 +31,8 @@
  *       order one pruned BFS along the edges (it labels L_IN of what it
  *       reaches, pruning with L_OUT(root) and L_IN(u)) and one against them
  *       (labels L_OUT, pruning with L_OUT(u) and L_IN(root)); d(s,t) is the
- *       merge of L_OUT(s) and L_IN(t).
+ *       merge of L_OUT(s) and L_IN(t).  Entries keep parents as in O6, so
+ *       paths s -> t are restored through the best hub of that merge.
  *   O8  weighted graphs (Section 7, "Weighted Graphs"): the pruned BFS of
  *       Algorithm 1 becomes a pruned Dijkstra search (a binary heap, a vertex
  *       is tested and, if not pruned, labeled and relaxed when it is settled);
@@ -850,17 +851,87 @@ static int path_one(const orc_index *x, int32_t s, int32_t t, int32_t maxlen, in
   return ORC_OK;
 }
 
-/* Paths of q pairs: row i of paths (maxlen ids) and lens[i] as path_one. */
+/* Shortest path s -> t of a directed index, as path_one: the best hub h of
+ * the merge of L_OUT(s) and L_IN(t) (first on ties); the parents kept with
+ * (h, .) in L_OUT lead from s along the arcs to h, those in L_IN lead from t
+ * against the arcs back to h. */
+static int path_one_directed(const orc_index *x, int32_t s, int32_t t, int32_t maxlen,
+                             int32_t *out, int32_t *len) {
+  int32_t rs = x->rank[s], rt = x->rank[t];
+  if (rs == rt) {
+    if (maxlen < 1) {
+      *len = -1;
+      return ORC_OK;
+    }
+    out[0] = s;
+    *len = 1;
+    return ORC_OK;
+  }
+  const orc_label *A = &x->lab[rs], *B = &x->lab_in[rt];
+  int best = 1 << 20, ia = -1, ib = -1;
+  for (int64_t i = 0, j = 0;;) {
+    uint32_t ha = A->hub[i], hb = B->hub[j];
+    if (ha == hb) {
+      if (ha == ORC_SENTINEL) break;
+      int v = (int)A->dist[i] + (int)B->dist[j];
+      if (v < best) {
+        best = v;
+        ia = (int)i;
+        ib = (int)j;
+      }
+      i++;
+      j++;
+    } else if (ha < hb) {
+      i++;
+    } else {
+      j++;
+    }
+  }
+  *len = 0;
+  if (best >= (int)ORC_INF) return ORC_OK;
+  int D = best;
+  if (maxlen < D + 1) {
+    *len = -(D + 1);
+    return ORC_OK;
+  }
+  uint32_t h = A->hub[ia];
+  int ds = A->dist[ia], dt = B->dist[ib];
+  int32_t c = rs;
+  for (int k = 0; k <= ds; k++) {
+    out[k] = c;
+    if (k < ds) {
+      int64_t e = find_hub(&x->lab[c], h);
+      if (e < 0) return ORC_E_RANGE;
+      c = (int32_t)x->lab[c].par[e];
+    }
+  }
+  c = rt;
+  for (int k = 0; k < dt; k++) {
+    out[D - k] = c;
+    int64_t e = find_hub(&x->lab_in[c], h);
+    if (e < 0) return ORC_E_RANGE;
+    c = (int32_t)x->lab_in[c].par[e];
+  }
+  if (c != (int32_t)h) return ORC_E_RANGE;
+  for (int k = 0; k <= D; k++) out[k] = x->ord[out[k]];
+  *len = D + 1;
+  return ORC_OK;
+}
+
+/* Paths of q pairs: row i of paths (maxlen ids) and lens[i] as path_one
+ * (path_one_directed for a directed index). */
 int orc_paths(const orc_index *x, const int32_t *pairs, int64_t q, int32_t maxlen,
               int32_t *paths, int32_t *lens) {
-  if (!x || x->lab_in || q < 0 || maxlen < 0 ||
+  if (!x || q < 0 || maxlen < 0 ||
       (q > 0 && (!pairs || !lens || (maxlen > 0 && !paths))))
     return ORC_E_INVAL;
   for (int64_t i = 0; i < 2 * q; i++)
     if (pairs[i] < 0 || pairs[i] >= x->n) return ORC_E_INVAL;
   for (int64_t i = 0; i < q; i++) {
-    int rc = path_one(x, pairs[2 * i], pairs[2 * i + 1], maxlen, paths + i * (int64_t)maxlen,
-                      &lens[i]);
+    int rc = x->lab_in ? path_one_directed(x, pairs[2 * i], pairs[2 * i + 1], maxlen,
+                                           paths + i * (int64_t)maxlen, &lens[i])
+                       : path_one(x, pairs[2 * i], pairs[2 * i + 1], maxlen,
+                                  paths + i * (int64_t)maxlen, &lens[i]);
     if (rc != ORC_OK) return rc;
   }
   return ORC_OK;
@@ -898,7 +969,7 @@ static int t_query(const orc_label *L, const uint8_t *T) {
  * side; `own` receives (k, d) at every vertex it does not prune. */
 static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32_t *adj,
                         orc_label *own, const orc_label *root_side, uint8_t *P, uint8_t *T,
-                        int32_t *queue) {
+                        int32_t *queue, int32_t *PP) {
   const orc_label *Lk = &root_side[k];
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
   x->cnt[C_ROOT_STAGED] += Lk->len;
@@ -906,6 +977,7 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
   int64_t qh = 0, qt = 0;
   queue[qt++] = k;
   P[k] = 0;
+  PP[k] = k;
   while (qh < qt && rc == ORC_OK) {
     int32_t u = queue[qh++];
     int d = P[u];
@@ -913,7 +985,10 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
     x->cnt[C_NORMAL_TESTS]++;
     x->cnt[C_LABEL_SCANNED] += own[u].len;
     if (t_query(&own[u], T) <= d) continue;
-    rc = label_push(&own[u], (uint32_t)k, (uint8_t)d, ORC_SENTINEL);
+    /* the parent is the vertex that enqueued u: its predecessor on the
+     * path from k for the search along the arcs, its successor on the path
+     * to k for the search against them */
+    rc = label_push(&own[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);
     if (rc != ORC_OK) break;
     x->cnt[C_LABELED]++;
     if (d > x->cnt[C_MAX_DIST]) x->cnt[C_MAX_DIST] = d;
@@ -930,6 +1005,7 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
         continue;
       }
       P[w] = (uint8_t)(d + 1);
+      PP[w] = u;
       queue[qt++] = w;
     }
   }
@@ -973,9 +1049,10 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   uint8_t *P = (uint8_t *)malloc((size_t)nn);
   uint8_t *T = (uint8_t *)malloc((size_t)nn);
   int32_t *queue = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  int32_t *PP = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   if (!x->rank || !x->lab || !x->lab_in || !x->bp_d || !x->bp_m1 || !x->bp_0 || !x->bp_root ||
       !x->bp_nsel || !x->bp_sel || !x->root_visited || !x->root_labeled || !x->ord || !off ||
-      !adj || !ioff || !iadj || !fill || !P || !T || !queue) {
+      !adj || !ioff || !iadj || !fill || !P || !T || !queue || !PP) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -1000,8 +1077,8 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
     x->cnt[C_ROOTS]++;
     int64_t vis0 = x->cnt[C_VISITED], lab0 = x->cnt[C_LABELED];
-    rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue);
-    if (rc == ORC_OK) rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue);
+    rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue, PP);
+    if (rc == ORC_OK) rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue, PP);
     x->root_visited[k] = (int32_t)(x->cnt[C_VISITED] - vis0);
     x->root_labeled[k] = (int32_t)(x->cnt[C_LABELED] - lab0);
   }
@@ -1016,8 +1093,22 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   x = NULL;
 done:
   free(off); free(adj); free(ioff); free(iadj); free(fill); free(P); free(T); free(queue);
+  free(PP);
   if (x) orc_free(x);
   return rc;
+}
+
+/* Parents of the L_IN entries of a directed index (ranks), in the order of
+ * orc_export_in. */
+int orc_export_in_parents(const orc_index *x, uint32_t *par) {
+  if (!x || !x->lab_in || !par) return ORC_E_INVAL;
+  int64_t e = 0;
+  for (int32_t v = 0; v < x->n; v++) {
+    const orc_label *L = &x->lab_in[v];
+    if (L->len) memcpy(par + e, L->par, (size_t)L->len * sizeof(uint32_t));
+    e += L->len;
+  }
+  return ORC_OK;
 }
 
 /* The in-labels of a directed index, in rank order, without sentinels. */

@@ -85,6 +85,66 @@ def check_directed(g, order, lib=None):
             if np.any(np.diff(h.astype(np.int64)) <= 0):
                 fails.append(f"label of rank {r} not sorted")
                 break
+    fails += check_directed_parents(g, order, ix, D)
+    fails += check_directed_paths(g, ix, D, lib)
+    return fails
+
+
+def arcs_of(g):
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    return set(zip(rows.tolist(), g.col.tolist()))
+
+
+def check_directed_parents(g, order, ix, D):
+    """Parent of v for (h, d) in L_IN(v): an in-neighbour p of v with
+    d(h, p) = d - 1 (v itself at d = 0); in L_OUT(v): an out-neighbour p
+    with d(p, h) = d - 1.  Parents and hubs are ranks."""
+    fails = []
+    arcs = arcs_of(g)
+    for side, (off, hub, dist, par) in (("L_IN", (ix.in_off, ix.in_hub, ix.in_dist, ix.in_par)),
+                                        ("L_OUT", (ix.out_off, ix.out_hub, ix.out_dist,
+                                                   ix.out_par))):
+        for r in range(g.n):
+            v = int(order[r])
+            for e in range(int(off[r]), int(off[r + 1])):
+                h, d, p = int(order[hub[e]]), int(dist[e]), int(order[par[e]])
+                if d == 0:
+                    ok = p == v
+                elif side == "L_IN":
+                    ok = (p, v) in arcs and D[h, p] == d - 1
+                else:
+                    ok = (v, p) in arcs and D[p, h] == d - 1
+                if not ok:
+                    fails.append(f"{side} parent of rank {r} for hub {h}: {p}")
+                    return fails
+    return fails
+
+
+def check_directed_paths(g, ix, D, lib=None):
+    """Every restored path follows arcs from s to t with d(s, t) + 1
+    vertices; unreachable pairs give 0."""
+    fails = []
+    n = g.n
+    if n == 0:
+        return fails
+    arcs = arcs_of(g)
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    paths, lens = oracle.paths(ix, pairs, 64)
+    for i, (a, b) in enumerate(pairs.tolist()):
+        d = D[a, b]
+        if d >= INF:
+            if lens[i] != 0:
+                fails.append(f"path({a},{b}) unreachable but len {lens[i]}")
+            continue
+        if lens[i] != d + 1:
+            fails.append(f"path({a},{b}) len {lens[i]} != {d + 1}")
+            continue
+        pth = paths[i, :d + 1].tolist()
+        if pth[0] != a or pth[-1] != b or any((x, y) not in arcs for x, y in zip(pth, pth[1:])):
+            fails.append(f"path({a},{b}) = {pth} is not a path along the arcs")
+        if len(fails) > 3:
+            break
     return fails
 
 
@@ -112,11 +172,16 @@ def test_symmetric_input_reduces_to_undirected():
 
 MUTATIONS = [
     ("reverse search follows the arcs",
-     "rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue);",
-     "rc = directed_bfs(x, k, off, adj, x->lab, x->lab_in, P, T, queue);"),
+     "rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue, PP);",
+     "rc = directed_bfs(x, k, off, adj, x->lab, x->lab_in, P, T, queue, PP);"),
     ("forward search prunes with the root's in-label",
-     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue);",
-     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab_in, P, T, queue);"),
+     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue, PP);",
+     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab_in, P, T, queue, PP);"),
+    ("directed parent recorded as the search root",
+     "      PP[w] = u;\n      queue[qt++] = w;", "      PP[w] = k;\n      queue[qt++] = w;"),
+    ("directed path ascends L_OUT from the target",
+     "    int64_t e = find_hub(&x->lab_in[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab_in[c].par[e];",
+     "    int64_t e = find_hub(&x->lab[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab[c].par[e];"),
     ("query merges L_OUT(s) with L_OUT(t)",
      "*B = x->lab_in ? &x->lab_in[rt] : &x->lab[rt];", "*B = &x->lab[rt];"),
     ("transpose keeps the arcs' direction",
