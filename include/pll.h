@@ -62,8 +62,9 @@ enum {
 #define PLL_DIRECTED 32u   /* pll_build*: the CSR lists out-arcs of a directed
                               graph (Section 7): labels L_OUT and L_IN, queries
                               give the distance from s to t along the arcs;
-                              needs t_bp = 0 and no PLL_PARENTS (else
-                              PLL_E_UNSUPPORTED); no symmetry is required */
+                              needs t_bp = 0 (else PLL_E_UNSUPPORTED); no
+                              symmetry is required; with PLL_PARENTS both
+                              labels keep parents and paths follow the arcs */
 
 /*
  * Device allocator for builds and indexes (process-wide; the default is
@@ -210,7 +211,8 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
  *            (row not written); INT32_MIN only for an inconsistent index
  * When the best common hub h of the normal labels gives the distance (ties
  * go to it, then to the lowest hub), the path ascends the BFS trees of h
- * from both ends.  When only a bit-parallel slot gives it (lowest slot on
+ * from both ends (for a digraph: h is the best hub of L_OUT(s) and L_IN(t),
+ * and the path follows the arcs).  When only a bit-parallel slot gives it (lowest slot on
  * ties), the path is walked through neighbours in ascending rank: to the
  * slot's root, or to its chosen neighbour w in S^{-1} / S^{0} (Section 5.1
  * sets) of both ends.  Paths over normal labels depend on which parent a
@@ -225,9 +227,18 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
  * Parents of one graph's label entries (index built with PLL_PARENTS, else
  * PLL_E_UNSUPPORTED), in pll_export's entry order, as local ranks: the
  * parent of vertex v for entry (h, d) is a neighbour of v at distance d-1
- * from h, and v itself for d = 0.  par: host uint32[entries].
+ * from h, and v itself for d = 0 (for L_OUT of a digraph: an out-neighbour
+ * p of v with d(p, h) = d-1).  par: host uint32[entries].
  */
 int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par);
+
+/*
+ * Parents of the L_IN entries of a directed index built with PLL_PARENTS
+ * (else PLL_E_UNSUPPORTED), in pll_export_in's entry order, as local ranks:
+ * for (h, d) in L_IN(v), an in-neighbour p of v with d(h, p) = d-1, and v
+ * itself for d = 0.  par: host uint32[entries of pll_export_in].
+ */
+int pll_export_in_parents(const pll_index *idx, int32_t graph, uint32_t *par);
 
 /*
  * L_IN of one graph of a directed index (built with PLL_DIRECTED, else

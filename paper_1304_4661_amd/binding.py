@@ -34,7 +34,7 @@ EXPORTED = [
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
-    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query",
+    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -79,6 +79,8 @@ def _lib():
         lib.pll_query_path.restype = C.c_int
         lib.pll_export_parents.argtypes = [P, C.c_int32, P]
         lib.pll_export_parents.restype = C.c_int
+        lib.pll_export_in_parents.argtypes = [P, C.c_int32, P]
+        lib.pll_export_in_parents.restype = C.c_int
         lib.pll_export_in.argtypes = [P, C.c_int32, P, P, P, P]
         lib.pll_export_in.restype = C.c_int
         lib.pll_build_weighted.argtypes = [C.c_int32, P, P, P, P, C.c_uint32, P,
@@ -274,6 +276,18 @@ class Index:
         _, e, _ = self.sizes(graph)
         par = np.zeros(e, np.uint32)
         _check(_lib().pll_export_parents(self._h, int(graph), _ptr(par)), "export_parents")
+        return par
+
+    def export_in_parents(self, graph: int = 0) -> np.ndarray:
+        """Parents of the L_IN entries of a directed index built with
+        parents, in export_in's order, as local ranks."""
+        ne = C.c_int64()
+        _check(_lib().pll_export_in(self._h, int(graph), C.byref(ne), None, None, None),
+               "export_in")
+        par = np.zeros(ne.value, np.uint32)
+        if ne.value:
+            _check(_lib().pll_export_in_parents(self._h, int(graph), _ptr(par)),
+                   "export_in_parents")
         return par
 
     def export(self, graph: int = 0) -> dict:

@@ -292,9 +292,10 @@ struct pll_index {
   bool parents = false;
   DBuf<uint32_t> par;
   // a directed graph (PLL_DIRECTED): off/hub/dist hold L_OUT, these L_IN
+  // (ipar: parents of the L_IN entries)
   bool directed = false;
   DBuf<int64_t> ioff;
-  DBuf<uint32_t> ihub;
+  DBuf<uint32_t> ihub, ipar;
   DBuf<uint8_t> idist;
   DBuf<int64_t> grow;
   DBuf<int32_t> gcol;
@@ -319,7 +320,7 @@ struct pll_index {
       if (!b->hook.alloc) b->stream = nullptr;
     for (auto *b : {&off, &ioff, &grow})
       if (!b->hook.alloc) b->stream = nullptr;
-    for (auto *b : {&hub, &par, &ihub})
+    for (auto *b : {&hub, &par, &ihub, &ipar})
       if (!b->hook.alloc) b->stream = nullptr;
   }
 
@@ -339,6 +340,7 @@ struct pll_index {
     v.thub = directed ? ihub.p : hub.p;
     v.tdist = directed ? idist.p : dist.p;
     v.par = par.p;
+    v.tpar = directed ? ipar.p : par.p;
     v.grow = grow.p;
     v.gcol = gcol.p;
     v.ord = ord.p;
@@ -997,9 +999,10 @@ struct Builder {
       check(hipStreamSynchronize(st));
       fhub.alloc((size_t)std::max<int64_t>(total, 1));
       fdist.alloc((size_t)std::max<int64_t>(total, 1));
-      if (parents && !in_side) ix->par.alloc((size_t)std::max<int64_t>(total, 1));
-      check(launch_final_copy(S.view(), foff.p, fhub.p, fdist.p,
-                              in_side ? nullptr : ix->par.p, n, st));
+      DBuf<uint32_t> &fpar = in_side ? ix->ipar : ix->par;
+      if (parents) fpar.alloc((size_t)std::max<int64_t>(total, 1));
+      check(launch_final_copy(S.view(), foff.p, fhub.p, fdist.p, parents ? fpar.p : nullptr, n,
+                              st));
       check(hipStreamSynchronize(st));
       ix->entries += total - n;
     }
@@ -1580,7 +1583,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
                                       ix->bpm.bytes() +
                                       ix->off.bytes() + ix->hub.bytes() + ix->dist.bytes() +
                                       ix->par.bytes() + ix->grow.bytes() + ix->gcol.bytes() +
-                                      ix->ord.bytes() + ix->ioff.bytes() + ix->ihub.bytes() +
+                                      ix->ord.bytes() + ix->ioff.bytes() + ix->ihub.bytes() + ix->ipar.bytes() +
                                       ix->idist.bytes());
   S[PLL_STAT_BP_NS] = bp_ns;
   S[PLL_STAT_PRUNED_NS] = pr_ns;
@@ -1636,8 +1639,8 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   const AllocStream alloc_stream(st);
   const bool device = (flags & PLL_DEVICE_PTRS) != 0;
   if (G < 0 || t_bp < 0 || t_bp > PLL_MAX_TBP || (G > 0 && !vtx_off)) return PLL_E_INVAL;
-  // directed graphs: no bit-parallel labels and no parents
-  if ((flags & PLL_DIRECTED) && (t_bp > 0 || (flags & PLL_PARENTS))) return PLL_E_UNSUPPORTED;
+  // directed graphs: no bit-parallel labels
+  if ((flags & PLL_DIRECTED) && t_bp > 0) return PLL_E_UNSUPPORTED;
   std::vector<int64_t> voff(vtx_off, vtx_off + (G > 0 ? G + 1 : 0));
   if (G == 0) voff.assign(1, 0);
   if (voff[0] != 0) return PLL_E_INVAL;
@@ -2095,6 +2098,37 @@ int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
     DBuf<uint8_t> od((size_t)ne);
     // same gather as the hubs: parents are global ranks too
     check(launch_gather_labels(drows.p, ng, idx->off.p, idx->par.p, idx->dist.p, idx->lrank.p,
+                               doo.p, op.p, od.p, st));
+    d2h(par, op.p, (size_t)ne, st);
+    check(hipStreamSynchronize(st));
+    return PLL_OK;
+  });
+}
+
+int pll_export_in_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
+  if (!idx || graph < 0 || graph >= idx->G || !par) return PLL_E_INVAL;
+  if (!idx->parents || !idx->directed || idx->weighted) return PLL_E_UNSUPPORTED;
+  return guarded([&] {
+    const int64_t ng = idx->vtx_off[graph + 1] - idx->vtx_off[graph];
+    const int32_t gp = idx->gpos[graph];
+    hipStream_t st = nullptr;
+    std::vector<int64_t> hio((size_t)idx->n + 1);
+    if (idx->n) d2h(hio.data(), idx->ioff.p, (size_t)idx->n + 1, st);
+    check(hipStreamSynchronize(st));
+    std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
+    for (int64_t l = 0; l < ng; l++) {
+      rows[l] = idx->lbase[l] + gp;
+      oo[l + 1] = oo[l] + hio[rows[l] + 1] - 1 - hio[rows[l]];
+    }
+    const int64_t ne = oo[ng];
+    if (ne == 0) return PLL_OK;
+    DBuf<int64_t> drows((size_t)ng), doo((size_t)ng + 1);
+    h2d(drows.p, rows.data(), (size_t)ng, st);
+    h2d(doo.p, oo.data(), (size_t)ng + 1, st);
+    DBuf<uint32_t> op((size_t)ne);
+    DBuf<uint8_t> od((size_t)ne);
+    // same gather as the hubs: parents are global ranks too
+    check(launch_gather_labels(drows.p, ng, idx->ioff.p, idx->ipar.p, idx->idist.p, idx->lrank.p,
                                doo.p, op.p, od.p, st));
     d2h(par, op.p, (size_t)ne, st);
     check(hipStreamSynchronize(st));

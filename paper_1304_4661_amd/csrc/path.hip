@@ -10,7 +10,8 @@
 // then on as before).
 //
 // One wave per pair: the label merge and the tree ascent run on one lane,
-// the neighbour scans of the bit-parallel walks on all 64.
+// the neighbour scans of the bit-parallel walks on all 64.  For a digraph
+// (no bit-parallel labels) the merge is of L_OUT(s) and L_IN(t).
 #include <climits>
 
 #include "pll_internal.h"
@@ -28,17 +29,17 @@ __global__ void k_invert_rank(const int32_t *rank, int32_t *ord, int32_t n) {
 }
 
 // entry of hub h in the label of rank c (sorted by hub rank), or -1
-__device__ int64_t find_hub(const DIndex &ix, int32_t c, uint32_t h) {
-  int64_t lo = ix.off[c], hi = ix.off[c + 1] - 1;  // sentinel excluded
+__device__ int64_t find_hub(const int64_t *off, const uint32_t *hub, int32_t c, uint32_t h) {
+  int64_t lo = off[c], hi = off[c + 1] - 1;  // sentinel excluded
   const int64_t end = hi;
   while (lo < hi) {
     const int64_t mid = lo + (hi - lo) / 2;
-    if (ix.hub[mid] < h)
+    if (hub[mid] < h)
       lo = mid + 1;
     else
       hi = mid;
   }
-  return (lo < end && ix.hub[lo] == h) ? lo : -1;
+  return (lo < end && hub[lo] == h) ? lo : -1;
 }
 
 // Lowest-rank neighbour y of c with bit-parallel distance `want` in slot i
@@ -121,12 +122,12 @@ __global__ void __launch_bounds__(kBlock) k_query_path(DIndex ix, const int32_t 
     int bn = 1 << 20;
     int64_t ia = -1, ib = -1;
     if (lane == 0) {
-      int64_t i = ix.off[rs], j = ix.off[rt];
+      int64_t i = ix.off[rs], j = ix.toff[rt];
       for (;;) {
-        const uint32_t ha = ix.hub[i], hb = ix.hub[j];
+        const uint32_t ha = ix.hub[i], hb = ix.thub[j];
         if (ha == hb) {
           if (ha == kSentinel) break;
-          const int v = (int)ix.dist[i] + (int)ix.dist[j];
+          const int v = (int)ix.dist[i] + (int)ix.tdist[j];
           if (v < bn) {
             bn = v;
             ia = i;
@@ -183,15 +184,17 @@ __global__ void __launch_bounds__(kBlock) k_query_path(DIndex ix, const int32_t 
     bool ok = true;
     if (bn <= bb) {
       // ascend the BFS tree of h from s (positions 0..ds) and from t
-      // (positions D down to ds+1)
+      // (positions D down to ds+1); for a digraph the source side is L_OUT
+      // (parents lead along the arcs to h), the target side L_IN (parents
+      // lead back against the arcs to h)
       if (lane == 0) {
         const uint32_t h = ix.hub[ia];
-        const int ds = ix.dist[ia], dt = ix.dist[ib];
+        const int ds = ix.dist[ia], dt = ix.tdist[ib];
         int32_t c = rs;
         for (int k = 0; k <= ds && ok; k++) {
           out[k] = ix.ord[c];
           if (k < ds) {
-            const int64_t e = find_hub(ix, c, h);
+            const int64_t e = find_hub(ix.off, ix.hub, c, h);
             if (e < 0) ok = false;
             else c = (int32_t)ix.par[e];
           }
@@ -199,9 +202,9 @@ __global__ void __launch_bounds__(kBlock) k_query_path(DIndex ix, const int32_t 
         c = rt;
         for (int k = 0; k < dt && ok; k++) {
           out[D - k] = ix.ord[c];
-          const int64_t e = find_hub(ix, c, h);
+          const int64_t e = find_hub(ix.toff, ix.thub, c, h);
           if (e < 0) ok = false;
-          else c = (int32_t)ix.par[e];
+          else c = (int32_t)ix.tpar[e];
         }
         if (c != (int32_t)h) ok = false;
       }

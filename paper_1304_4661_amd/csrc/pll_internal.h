@@ -438,6 +438,7 @@ struct DIndex {
   // kept by builds with PLL_PARENTS (else null): parent of each entry's
   // vertex in the hub's BFS tree, the rank-space graph, rank -> id
   const uint32_t *par;
+  const uint32_t *tpar;  // parents of the target-side labels (L_IN of a digraph)
   const int64_t *grow;
   const int32_t *gcol;
   const int32_t *ord;

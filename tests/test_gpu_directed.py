@@ -89,9 +89,11 @@ def test_directed_batch_and_errors():
     with pytest.raises(binding.PllError):
         binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 2, directed=True)
     with pytest.raises(binding.PllError):
-        binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0, directed=True, parents=True)
-    with pytest.raises(binding.PllError):
         binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0).export_in()
+    # L_IN parents need a directed index built with parents
+    with pytest.raises(binding.PllError):
+        binding.build(g.row_ptr, g.col, gen.degree_order_directed(g), 0,
+                      directed=True).export_in_parents()
 
 
 @pytest.mark.parametrize("landmarks", [0, 1])
@@ -110,3 +112,60 @@ def test_directed_landmark_rows(landmarks, window):
         assert st["bp_direct"] == 0
     elif window < g.n:  # rows are used from the second window on
         assert st["bp_direct"] > 0
+
+
+DPATH = [("er60", gen.er_digraph(60, 0.05, 2)), ("rmat9", gen.rmat_digraph(9, 8, seed=4)),
+         ("rmat12", gen.rmat_digraph(12, 8, seed=5))]
+
+
+@pytest.mark.parametrize("name,g", DPATH, ids=[d[0] for d in DPATH])
+@pytest.mark.parametrize("window", [1, 64, 4096])
+def test_directed_paths(name, g, window):
+    # Section 7 paths on a digraph: labels as without parents, every path
+    # follows the arcs with d(s, t) + 1 vertices, parents of both labels are
+    # valid BFS-tree parents
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    _require_gpu()
+    order = gen.degree_order_directed(g)
+    ox = oracle.build_directed(g.row_ptr, g.col, order)
+    with Tuned(window=window, window_work=0):
+        gx = binding.build(g.row_ptr, g.col, order, 0, directed=True, parents=True)
+    assert_same_directed(gx, ox, f"{name} window={window}")
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    arcs = set(zip(rows.tolist(), g.col.tolist()))
+    pairs = all_pairs(g.n) if g.n <= 600 else gen.random_pairs(g.n, 100_000, 4)
+    want = oracle.query_directed(ox, pairs).astype(np.int64)
+    paths, lens = gx.query_path(pairs, max_len=64)
+    _, olens = oracle.paths(ox, pairs, 64)
+    assert np.array_equal(lens, olens)
+    reach = want < 255
+    assert np.array_equal(lens[reach], want[reach] + 1) and np.all(lens[~reach] == 0)
+    for i in np.flatnonzero(reach)[:20000]:
+        p = paths[i, :lens[i]].tolist()
+        assert p[0] == pairs[i, 0] and p[-1] == pairs[i, 1]
+        assert all((a, b) in arcs for a, b in zip(p, p[1:])), (pairs[i], p)
+    # parents: ranks; L_OUT parent is an out-neighbour one step closer to h,
+    # L_IN parent an in-neighbour one step further from h
+    a = csr_matrix((np.ones(len(g.col)), g.col, g.row_ptr), shape=(g.n, g.n))
+    D = shortest_path(a, unweighted=True, directed=True)
+    e = gx.export()
+    po = gx.export_parents()
+    ei = gx.export_in()
+    pi = gx.export_in_parents()
+    for (off, hub, dist, par, side) in ((e["off"], e["hub"], e["dist"], po, "out"),
+                                        (ei["off"], ei["hub"], ei["dist"], pi, "in")):
+        owner = np.repeat(np.arange(g.n), np.diff(off))
+        v = order[owner]
+        h = order[hub]
+        p = order[par]
+        d = dist.astype(np.int64)
+        z = d == 0
+        assert np.all(p[z] == v[z])
+        nz = ~z
+        if side == "out":
+            assert all((x, y) in arcs for x, y in zip(v[nz].tolist(), p[nz].tolist()))
+            assert np.array_equal(D[p[nz], h[nz]], d[nz] - 1)
+        else:
+            assert all((y, x) in arcs for x, y in zip(v[nz].tolist(), p[nz].tolist()))
+            assert np.array_equal(D[h[nz], p[nz]], d[nz] - 1)
