@@ -20,6 +20,7 @@ from .oracle import (  # noqa: F401
     load_variant,
     source_text,
     paths,
+    paths_weighted,
     query,
     query_directed,
     query_parts,

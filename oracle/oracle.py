@@ -86,6 +86,10 @@ def _configure(lib):
         lib.orc_wcounters.restype = C.c_int
         lib.orc_wexport.argtypes = [C.c_void_p, C.c_int32, P, P, P, P, P]
         lib.orc_wexport.restype = C.c_int
+        lib.orc_wpaths.argtypes = [C.c_void_p, P, C.c_int64, C.c_int32, P, P]
+        lib.orc_wpaths.restype = C.c_int
+        lib.orc_wexport_parents.argtypes = [C.c_void_p, C.c_int32, P]
+        lib.orc_wexport_parents.restype = C.c_int
     return lib
 
 
@@ -328,6 +332,8 @@ class WeightedIndex:
     in_off: np.ndarray | None = None
     in_hub: np.ndarray | None = None
     in_dist: np.ndarray | None = None
+    par: np.ndarray | None = None     # uint32 parents (ranks) of the side-0 entries
+    in_par: np.ndarray | None = None  # ... of the L_IN entries
     counters: dict = field(default_factory=dict)
     _handle: C.c_void_p | None = None
     _lib: object = None
@@ -371,13 +377,21 @@ def build_weighted(row_ptr, col, wgt, order, directed: bool = False,
         lib.orc_wexport(h, s, None, None, _ptr(hub), _ptr(dist), None)
         return off, hub, dist
 
+    def parents(s, ne):
+        par = np.zeros(ne, np.uint32)
+        if ne:
+            lib.orc_wexport_parents(h, s, _ptr(par))
+        return par
+
     rank = np.zeros(n, np.int32)
     lib.orc_wexport(h, 0, None, None, None, None, _ptr(rank))
     off, hub, dist = side(0)
     ix = WeightedIndex(n=n, directed=directed, rank=rank, off=off, hub=hub, dist=dist, _handle=h)
     ix._lib = lib
+    ix.par = parents(0, len(hub))
     if directed:
         ix.in_off, ix.in_hub, ix.in_dist = side(1)
+        ix.in_par = parents(1, len(ix.in_hub))
     nc = lib.orc_wncounters()
     cnt = np.zeros(nc, np.int64)
     lib.orc_wcounters(h, _ptr(cnt), nc)
@@ -394,3 +408,17 @@ def query_weighted(ix: WeightedIndex, pairs) -> np.ndarray:
     if rc != 0:
         raise OracleError(rc)
     return out
+
+
+def paths_weighted(ix: WeightedIndex, pairs, maxlen: int) -> tuple[np.ndarray, np.ndarray]:
+    """Shortest paths (input ids) of a weighted index: (paths[q, maxlen],
+    lens[q]); lens = vertices on the path, 0 if unreachable, -(vertices) if
+    maxlen is too small."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.full((len(pairs), max(maxlen, 0)), -1, np.int32)
+    lens = np.zeros(len(pairs), np.int32)
+    rc = (ix._lib or _load()).orc_wpaths(ix._handle, _ptr(pairs), len(pairs), int(maxlen),
+                                        _ptr(out), _ptr(lens))
+    if rc != 0:
+        raise OracleError(rc)
+    return out, lens

@@ -37,7 +37,9 @@
  *       Algorithm 1 becomes a pruned Dijkstra search (a binary heap, a vertex
  *       is tested and, if not pruned, labeled and relaxed when it is settled);
  *       no bit-parallel labels; distances are 32-bit.  Also for digraphs,
- *       with the two searches of O7.
+ *       with the two searches of O7.  Entries keep the parent in the search
+ *       tree of the hub (the last vertex that lowered the distance), so
+ *       shortest paths come back as in O6.
  *
  * Readings of points the paper leaves open (each one also fixed on the GPU
  * side, so both compute the same bytes):
@@ -1146,6 +1148,7 @@ int orc_export_in(const orc_index *x, int64_t *entries, int64_t *off, uint32_t *
 typedef struct {
   uint32_t *hub; /* hub ranks, ascending, then ORC_SENTINEL */
   uint32_t *dist;
+  uint32_t *par; /* parent (rank) of this vertex in the search tree of the hub */
   int64_t len, cap;
 } orc_wlabel;
 
@@ -1165,6 +1168,7 @@ enum {
 typedef struct orc_windex {
   int32_t n, directed;
   int32_t *rank;
+  int32_t *ord; /* input id of rank r */
   orc_wlabel *out; /* L of an undirected graph; L_OUT of a digraph */
   orc_wlabel *in;  /* L_IN of a digraph, else NULL */
   int64_t cnt[ORC_WNCOUNTERS];
@@ -1175,6 +1179,7 @@ static void wlabel_free_all(orc_wlabel *lab, int32_t n) {
   for (int32_t v = 0; v < n; v++) {
     free(lab[v].hub);
     free(lab[v].dist);
+    free(lab[v].par);
   }
   free(lab);
 }
@@ -1184,11 +1189,12 @@ void orc_wfree(orc_windex *x) {
   wlabel_free_all(x->out, x->n);
   wlabel_free_all(x->in, x->n);
   free(x->rank);
+  free(x->ord);
   free(x);
 }
 
 /* Append (h, d) and keep the sentinel after the last entry. */
-static int wlabel_push(orc_wlabel *L, uint32_t h, uint32_t d) {
+static int wlabel_push(orc_wlabel *L, uint32_t h, uint32_t d, uint32_t par) {
   if (L->len + 2 > L->cap) {
     int64_t nc = L->cap ? 2 * L->cap : 4;
     uint32_t *nh = (uint32_t *)realloc(L->hub, (size_t)nc * sizeof(uint32_t));
@@ -1197,13 +1203,18 @@ static int wlabel_push(orc_wlabel *L, uint32_t h, uint32_t d) {
     uint32_t *nd = (uint32_t *)realloc(L->dist, (size_t)nc * sizeof(uint32_t));
     if (!nd) return ORC_E_NOMEM;
     L->dist = nd;
+    uint32_t *np = (uint32_t *)realloc(L->par, (size_t)nc * sizeof(uint32_t));
+    if (!np) return ORC_E_NOMEM;
+    L->par = np;
     L->cap = nc;
   }
   L->hub[L->len] = h;
   L->dist[L->len] = d;
+  L->par[L->len] = par;
   L->len++;
   L->hub[L->len] = ORC_SENTINEL;
   L->dist[L->len] = ORC_WINF;
+  L->par[L->len] = ORC_SENTINEL;
   return ORC_OK;
 }
 
@@ -1255,13 +1266,14 @@ static uint64_t wheap_pop(wheap *h) {
 static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const int32_t *adj,
                            const uint32_t *wgt, orc_wlabel *lab, const orc_wlabel *tlab,
                            uint32_t *D, uint32_t *T, char *settled, int32_t *touched,
-                           wheap *heap) {
+                           wheap *heap, int32_t *PP) {
   int rc = ORC_OK;
   const orc_wlabel *Lk = &tlab[k];
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
   int64_t nt = 0;
   heap->len = 0;
   D[k] = 0;
+  PP[k] = k;
   touched[nt++] = k;
   rc = wheap_push(heap, (uint64_t)k);
   x->cnt[W_PUSHES]++;
@@ -1281,7 +1293,8 @@ static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const i
       if (th != ORC_WINF && (uint64_t)L->dist[i] + th <= d) pruned = 1;
     }
     if (pruned) continue;
-    rc = wlabel_push(&lab[u], (uint32_t)k, d);
+    /* the parent is the vertex whose relaxation last lowered D[u] */
+    rc = wlabel_push(&lab[u], (uint32_t)k, d, (uint32_t)PP[u]);
     if (rc != ORC_OK) break;
     x->cnt[W_LABELED]++;
     if ((int64_t)d > x->cnt[W_MAX_DIST]) x->cnt[W_MAX_DIST] = d;
@@ -1292,6 +1305,7 @@ static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const i
       if (nd >= ORC_WINF || settled[w] || nd >= D[w]) continue;
       if (D[w] == ORC_WINF) touched[nt++] = w;
       D[w] = (uint32_t)nd;
+      PP[w] = u;
       rc = wheap_push(heap, nd << 32 | (uint64_t)w);
       x->cnt[W_PUSHES]++;
     }
@@ -1373,13 +1387,18 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   uint32_t *T = (uint32_t *)malloc((size_t)nn * sizeof(uint32_t));
   char *settled = (char *)calloc((size_t)nn, 1);
   int32_t *touched = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  int32_t *PP = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
+  x->ord = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   wheap heap = {NULL, 0, 0};
   if (!x->rank || !x->out || (directed && !x->in) || !off || !adj || !aw || !tmp || !D || !T ||
-      !settled || !touched) {
+      !settled || !touched || !PP || !x->ord) {
     rc = ORC_E_NOMEM;
     goto done;
   }
-  for (int32_t i = 0; i < n; i++) x->rank[order[i]] = i;
+  for (int32_t i = 0; i < n; i++) {
+    x->rank[order[i]] = i;
+    x->ord[i] = order[i];
+  }
   weighted_adjacency(x, row_ptr, col, wgt, order, off, adj, aw, tmp);
   if (!directed && (flags & 1u)) {
     /* every (r, s, w) has (s, r, w): rows are sorted by (rank, weight) */
@@ -1424,15 +1443,17 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
     if (!directed) {
       x->cnt[W_ROOTS]++;
-      rc = weighted_search(x, k, off, adj, aw, x->out, x->out, D, T, settled, touched, &heap);
+      rc = weighted_search(x, k, off, adj, aw, x->out, x->out, D, T, settled, touched, &heap,
+                           PP);
     } else {
       /* along the arcs: labels L_IN, root distances from L_OUT(k); then
        * against them: labels L_OUT, root distances from L_IN(k) */
       x->cnt[W_ROOTS] += 2;
-      rc = weighted_search(x, k, off, adj, aw, x->in, x->out, D, T, settled, touched, &heap);
+      rc = weighted_search(x, k, off, adj, aw, x->in, x->out, D, T, settled, touched, &heap,
+                           PP);
       if (rc == ORC_OK)
         rc = weighted_search(x, k, ioff, iadj, iaw, x->out, x->in, D, T, settled, touched,
-                             &heap);
+                             &heap, PP);
     }
   }
   if (rc != ORC_OK) goto done;
@@ -1443,7 +1464,7 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   x = NULL;
 done:
   free(off); free(adj); free(aw); free(ioff); free(iadj); free(iaw); free(tmp);
-  free(D); free(T); free(settled); free(touched); free(heap.a);
+  free(D); free(T); free(settled); free(touched); free(heap.a); free(PP);
   if (x) orc_wfree(x);
   return rc;
 }
@@ -1505,5 +1526,109 @@ int orc_wexport(const orc_windex *x, int32_t side, int64_t *entries, int64_t *of
   if (off) off[x->n] = e;
   if (entries) *entries = e;
   if (rank && x->n) memcpy(rank, x->rank, (size_t)x->n * sizeof(int32_t));
+  return ORC_OK;
+}
+
+/* entry of hub h in a weighted label (sorted by hub rank), or -1 */
+static int64_t wfind_hub(const orc_wlabel *L, uint32_t h) {
+  int64_t lo = 0, hi = L->len;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (L->hub[mid] < h) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < L->len && L->hub[lo] == h) ? lo : -1;
+}
+
+/* Vertices from rank c up the search tree of hub h (c first, h last) into
+ * out[pos], out[pos + dir], ... (out may be NULL: count only).  Returns the
+ * count, or -1 if a label lacks h (a broken index). */
+static int64_t wascend(const orc_windex *x, const orc_wlabel *lab, int32_t c, uint32_t h,
+                       int32_t *out, int64_t pos, int64_t dir, int64_t room) {
+  int64_t cnt = 0;
+  for (;;) {
+    if (out && cnt < room) out[pos + dir * cnt] = x->ord[c];
+    cnt++;
+    if ((uint32_t)c == h) return cnt;
+    if (cnt > x->n) return -1;
+    int64_t e = wfind_hub(&lab[c], h);
+    if (e < 0) return -1;
+    c = (int32_t)lab[c].par[e];
+  }
+}
+
+/* Shortest path s -> t of a weighted index: the best hub h of the merge of
+ * L(s) (L_OUT) and L(t) (L_IN), first on ties, then both search trees of h
+ * ascended.  *len = vertices on the path, 0 if unreachable (or 2^32 - 1 or
+ * more away), -(vertices) if maxlen is too small (nothing written). */
+static int wpath_one(const orc_windex *x, int32_t s, int32_t t, int32_t maxlen, int32_t *out,
+                     int32_t *len) {
+  int32_t rs = x->rank[s], rt = x->rank[t];
+  const orc_wlabel *A = &x->out[rs], *B = x->directed ? &x->in[rt] : &x->out[rt];
+  const orc_wlabel *tl = x->directed ? x->in : x->out;
+  *len = 0;
+  if (rs == rt) {
+    if (maxlen >= 1) out[0] = s;
+    *len = maxlen >= 1 ? 1 : -1;
+    return ORC_OK;
+  }
+  uint64_t best = ORC_WINF;
+  uint32_t h = ORC_SENTINEL;
+  for (int64_t i = 0, j = 0;;) {
+    uint32_t ha = A->hub[i], hb = B->hub[j];
+    if (ha == hb) {
+      if (ha == ORC_SENTINEL) break;
+      uint64_t v = (uint64_t)B->dist[j] + A->dist[i];
+      if (v < best) {
+        best = v;
+        h = ha;
+      }
+      i++;
+      j++;
+    } else if (ha < hb) {
+      i++;
+    } else {
+      j++;
+    }
+  }
+  if (best >= ORC_WINF) return ORC_OK;
+  int64_t cs = wascend(x, x->out, rs, h, NULL, 0, 1, 0);
+  int64_t ct = wascend(x, tl, rt, h, NULL, 0, 1, 0);
+  if (cs < 0 || ct < 0) return ORC_E_RANGE;
+  int64_t total = cs + ct - 1; /* h counted once */
+  if (total > maxlen) {
+    *len = (int32_t)-total;
+    return ORC_OK;
+  }
+  wascend(x, x->out, rs, h, out, 0, 1, total);
+  wascend(x, tl, rt, h, out, total - 1, -1, total);
+  *len = (int32_t)total;
+  return ORC_OK;
+}
+
+int orc_wpaths(const orc_windex *x, const int32_t *pairs, int64_t q, int32_t maxlen,
+               int32_t *paths, int32_t *lens) {
+  if (!x || q < 0 || maxlen < 0 || (q > 0 && (!pairs || !lens || (maxlen > 0 && !paths))))
+    return ORC_E_INVAL;
+  for (int64_t i = 0; i < 2 * q; i++)
+    if (pairs[i] < 0 || pairs[i] >= x->n) return ORC_E_INVAL;
+  for (int64_t i = 0; i < q; i++) {
+    int rc = wpath_one(x, pairs[2 * i], pairs[2 * i + 1], maxlen, paths + i * (int64_t)maxlen,
+                       &lens[i]);
+    if (rc != ORC_OK) return rc;
+  }
+  return ORC_OK;
+}
+
+/* Parents (ranks) of the exported entries of one side, as orc_wexport. */
+int orc_wexport_parents(const orc_windex *x, int32_t side, uint32_t *par) {
+  if (!x || !par || (side == 1 && !x->in) || side < 0 || side > 1) return ORC_E_INVAL;
+  const orc_wlabel *lab = side ? x->in : x->out;
+  int64_t e = 0;
+  for (int32_t v = 0; v < x->n; v++) {
+    const orc_wlabel *L = &lab[v];
+    if (L->len) memcpy(par + e, L->par, (size_t)L->len * sizeof(uint32_t));
+    e += L->len;
+  }
   return ORC_OK;
 }

@@ -82,6 +82,73 @@ def check_weighted(g, order, directed=False, lib=None):
         fails.append("labels differ from their canonical form")
     if ix.counters["entries"] != len(ix.hub) + (len(ix.in_hub) if directed else 0):
         fails.append("entry counter")
+    fails += check_weighted_parents(g, order, ix, D, directed)
+    fails += check_weighted_paths(g, ix, D, directed)
+    return fails
+
+
+def edge_weights(g):
+    """Smallest weight of each arc (u, v) of the CSR."""
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    w = {}
+    for u, v, x in zip(rows.tolist(), g.col.tolist(), g.w.tolist()):
+        w[(u, v)] = min(x, w.get((u, v), x))
+    return w
+
+
+def check_weighted_parents(g, order, ix, D, directed):
+    """Parent p of v for (h, d): v itself at d = 0; else an edge p -> v
+    (undirected: p - v) with d(h, p) + w(p, v) = d for L (L_IN), and an arc
+    v -> p with w(v, p) + d(p, h) = d for L_OUT of a digraph."""
+    fails = []
+    ew = edge_weights(g)
+    sides = [("L" if not directed else "L_OUT", ix.off, ix.hub, ix.dist, ix.par)]
+    if directed:
+        sides.append(("L_IN", ix.in_off, ix.in_hub, ix.in_dist, ix.in_par))
+    for side, off, hub, dist, par in sides:
+        for r in range(g.n):
+            v = int(order[r])
+            for e in range(int(off[r]), int(off[r + 1])):
+                h, d, p = int(order[hub[e]]), int(dist[e]), int(order[par[e]])
+                if d == 0:
+                    ok = p == v
+                elif side == "L_OUT":
+                    ok = (v, p) in ew and ew[(v, p)] + D[p, h] == d
+                else:
+                    ok = (p, v) in ew and D[h, p] + ew[(p, v)] == d
+                if not ok:
+                    fails.append(f"{side} parent of rank {r} for hub {h}: {p}")
+                    return fails
+    return fails
+
+
+def check_weighted_paths(g, ix, D, directed):
+    """Every restored path follows edges (arcs) from s to t and its weights
+    sum to d(s, t); unreachable pairs give 0."""
+    fails = []
+    n = g.n
+    if n == 0:
+        return fails
+    ew = edge_weights(g)
+    s, t = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    paths, lens = oracle.paths_weighted(ix, pairs, n + 1)
+    for i, (a, b) in enumerate(pairs.tolist()):
+        d = D[a, b]
+        if d >= WINF:
+            if lens[i] != 0:
+                fails.append(f"path({a},{b}) unreachable but len {lens[i]}")
+            continue
+        if lens[i] <= 0:
+            fails.append(f"path({a},{b}) missing (len {lens[i]})")
+            continue
+        pth = paths[i, :lens[i]].tolist()
+        hops = list(zip(pth, pth[1:]))
+        if pth[0] != a or pth[-1] != b or any(x not in ew for x in hops) or \
+                sum(ew[x] for x in hops) != d:
+            fails.append(f"path({a},{b}) = {pth} is not a shortest path")
+        if len(fails) > 3:
+            break
     return fails
 
 
@@ -186,6 +253,11 @@ def test_weighted_generator_is_symmetric():
 
 
 MUTATIONS = [
+    ("parent recorded as the search root", "      D[w] = (uint32_t)nd;\n      PP[w] = u;\n",
+     "      D[w] = (uint32_t)nd;\n      PP[w] = k;\n"),
+    ("path ascends the source side from the target",
+     "  int64_t ct = wascend(x, tl, rt, h, NULL, 0, 1, 0);",
+     "  int64_t ct = wascend(x, x->in ? x->in : x->out, rs, h, NULL, 0, 1, 0);"),
     ("prune test strict", "if (th != ORC_WINF && (uint64_t)L->dist[i] + th <= d) pruned = 1;",
      "if (th != ORC_WINF && (uint64_t)L->dist[i] + th < d) pruned = 1;"),
     ("relaxation ignores the weight", "uint64_t nd = (uint64_t)d + wgt[j];",
