@@ -489,6 +489,34 @@ def bench_weighted(args):
             "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
         },
     }
+    if not args.no_extras:
+        # Section 7 paths on the weighted index: build with parents, restore
+        # 1e5 paths on the device (events on the stream)
+        binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True,
+                               parents=True).close()
+        t1 = time.perf_counter()
+        ix = binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True,
+                                    parents=True)
+        bs = time.perf_counter() - t1
+        sub = d_pairs[:100_000].contiguous()
+        paths = torch.empty((len(sub), 64), dtype=torch.int32, device=dev)
+        lens = torch.empty(len(sub), dtype=torch.int32, device=dev)
+        ix.query_path_device(sub, paths, lens, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            ix.query_path_device(sub, paths, lens, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ix.sync()
+        ln = lens.cpu().numpy()
+        ix.close()
+        out["shortest_paths"] = {
+            "build_s_with_parents": bs,
+            "paths_per_s": 3 * len(sub) / (e0.elapsed_time(e1) / 1e3), "pairs": len(sub),
+            "mean_vertices": float(ln[ln > 0].mean()) if (ln > 0).any() else 0.0}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_weighted(g, order, pairs)
         out["cpu_baseline"]["cpu_model"] = cpu_model()

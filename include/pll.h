@@ -201,7 +201,9 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
  */
 /*
  * Shortest paths (Section 7, "Shortest-Path Queries") of q pairs, for an
- * index built with PLL_PARENTS (else PLL_E_UNSUPPORTED).
+ * index built with PLL_PARENTS (else PLL_E_UNSUPPORTED).  On a weighted
+ * index lens[i] counts the vertices of the path (it is not d+1 there): 0
+ * if unreachable, -(vertices) if max_len is too small.
  *   pairs    int32[2q] ids, as pll_query
  *   max_len  vertices room per path (>= 0)
  *   paths    int32[q][max_len]: row i gets the ids of a shortest path from
@@ -265,14 +267,18 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
  *   flags    PLL_DEVICE_PTRS (row_ptr, col, wgt and order on the device),
  *            PLL_VALIDATE (host pointers only), PLL_PLAIN (one root at a
  *            time), PLL_DIRECTED (the CSR lists out-arcs; labels L_OUT and
- *            L_IN as for pll_build); PLL_PARENTS is PLL_E_UNSUPPORTED
+ *            L_IN as for pll_build), PLL_PARENTS (every entry keeps the
+ *            parent of its vertex in the hub's search tree: among the
+ *            labeled vertices p with d(h, p) + w(p, v) = d, the lowest
+ *            ranked; pll_query_path then restores paths)
  * A relaxation whose distance would reach 2^32 - 1 is dropped: a vertex that
  * far from a root counts as unreachable from it, so the labels are the
  * exact ones with distance below 2^32 - 1 and queries read 2^32 - 1
  * (PLL_WINF) for pairs that are unreachable or at least that far apart.
  * Errors: as pll_build.  The index answers only pll_query_weighted,
- * pll_export_weighted, pll_export_sizes, pll_stats, pll_sync and pll_free
- * (other calls return PLL_E_UNSUPPORTED).  Always synchronises the stream.
+ * pll_export_weighted, pll_export_weighted_parents, pll_query_path (with
+ * PLL_PARENTS), pll_export_sizes, pll_stats, pll_sync and pll_free (other
+ * calls return PLL_E_UNSUPPORTED).  Always synchronises the stream.
  */
 #define PLL_WINF 0xFFFFFFFFu
 int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,
@@ -298,6 +304,15 @@ int pll_query_weighted(const pll_index *idx, const int32_t *pairs, int64_t q, ui
  */
 int pll_export_weighted(const pll_index *idx, int32_t side, int64_t *entries, int64_t *off,
                         uint32_t *hub, uint32_t *dist, int32_t *rank);
+
+/*
+ * Parents (ranks) of the entries pll_export_weighted gives for `side`, in
+ * the same order, for a weighted index built with PLL_PARENTS (else
+ * PLL_E_UNSUPPORTED): for (h, d) in L(v) (L_IN(v)) an edge p -> v with
+ * d(h, p) + w(p, v) = d, for L_OUT(v) an arc v -> p with w(v, p) + d(p, h)
+ * = d; v itself for d = 0.  par: host uint32[entries].
+ */
+int pll_export_weighted_parents(const pll_index *idx, int32_t side, uint32_t *par);
 
 /*
  * Work counters of the build (PLL_STAT_* below), for reporting and for the

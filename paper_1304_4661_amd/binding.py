@@ -34,7 +34,7 @@ EXPORTED = [
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
-    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents",
+    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents", "pll_export_weighted_parents",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -90,6 +90,8 @@ def _lib():
         lib.pll_query_weighted.restype = C.c_int
         lib.pll_export_weighted.argtypes = [P, C.c_int32, P, P, P, P, P]
         lib.pll_export_weighted.restype = C.c_int
+        lib.pll_export_weighted_parents.argtypes = [P, C.c_int32, P]
+        lib.pll_export_weighted_parents.restype = C.c_int
         lib.pll_autotune_query.argtypes = [P, P, C.c_int64, C.c_uint32, P, P]
         lib.pll_autotune_query.restype = C.c_int
         lib.pll_level_trace.argtypes = [P, P, C.c_int64]
@@ -367,6 +369,18 @@ class Index:
                    "autotune_query")
         return best.value
 
+    def export_weighted_parents(self, side: int = 0) -> np.ndarray:
+        """Parents (ranks) of export_weighted(side)'s entries (weighted
+        index built with parents)."""
+        ne = C.c_int64()
+        _check(_lib().pll_export_weighted(self._h, int(side), C.byref(ne), None, None, None, None),
+               "export_weighted")
+        par = np.zeros(ne.value, np.uint32)
+        if ne.value:
+            _check(_lib().pll_export_weighted_parents(self._h, int(side), _ptr(par)),
+                   "export_weighted_parents")
+        return par
+
     TRACE_COLS = ["window", "first_root", "roots", "level", "entries", "candidates", "ns"]
 
     def level_trace(self) -> np.ndarray:
@@ -459,12 +473,13 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
 
 
 def build_weighted(row_ptr, col, wgt, order, directed: bool = False, plain: bool = False,
-                   validate: bool = False, stream=None, device: bool = False) -> Index:
+                   validate: bool = False, stream=None, device: bool = False,
+                   parents: bool = False) -> Index:
     """Pruned Dijkstra index of a weighted graph (Section 7; see
     include/pll.h).  Host arrays, or torch device tensors with device=True
     (wgt as int32 or uint32-valued int32 tensor)."""
     flags = ((VALIDATE if validate else 0) | (PLAIN if plain else 0)
-             | (DIRECTED if directed else 0))
+             | (DIRECTED if directed else 0) | (PARENTS if parents else 0))
     h = C.c_void_p()
     if device:
         import torch

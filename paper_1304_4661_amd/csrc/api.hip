@@ -1035,7 +1035,7 @@ constexpr int32_t kMaxWWindow = 4096;  // roots per weighted window (64 mask wor
 struct WBuilder {
   hipStream_t st;
   Tuning tu;
-  bool plain = false, directed = false;
+  bool plain = false, directed = false, parents = false;
   int32_t n = 0;
   int64_t nnz = 0;
   DBuf<int64_t> row, irow;
@@ -1050,10 +1050,11 @@ struct WBuilder {
     DBuf<int64_t> off;
     DBuf<int32_t> len, cap;
     DBuf<uint64_t> ent;
+    DBuf<uint32_t> par;  // null unless parents are kept
     DBuf<unsigned long long> top;
     int64_t pool_cap = 0;
     int64_t entries = 0;  // committed so far (host count)
-    DWStore view() const { return DWStore{off.p, len.p, cap.p, ent.p, top.p, pool_cap}; }
+    DWStore view() const { return DWStore{off.p, len.p, cap.p, ent.p, top.p, pool_cap, par.p}; }
   };
 
   // One search direction: the graph it follows, the store it labels, the
@@ -1063,7 +1064,8 @@ struct WBuilder {
     WStore *own = nullptr, *roots = nullptr;
     int64_t htcap = 0, fcap = 0, tcap = 0, ccap = 0;
     int32_t wmax = 0;
-    DBuf<uint32_t> td, cd;
+    DBuf<uint32_t> td, cd, cp;
+    DBuf<uint64_t> tdp;
     DBuf<uint8_t> fl, cdes;
     DBuf<uint64_t> ht, lm, km, lsum, sig;
     DBuf<int64_t> htoff, hsize, htmp;
@@ -1081,6 +1083,8 @@ struct WBuilder {
       w.n = nn;
       w.words = (W + 63) / 64;
       w.td = td.p;
+      w.tdp = tdp.p;
+      w.cp = cp.p;
       w.fl = fl.p;
       w.ht = ht.p;
       w.htoff = htoff.p;
@@ -1116,6 +1120,7 @@ struct WBuilder {
     fill(S.cap, 0, st);
     S.pool_cap = pool_cap;
     S.ent.alloc((size_t)pool_cap);
+    if (parents) S.par.alloc((size_t)pool_cap);
     S.top.alloc(1);
     fill(S.top, 0, st);
   }
@@ -1127,10 +1132,17 @@ struct WBuilder {
     if (S.pool_cap - (int64_t)htop >= need) return;
     const int64_t ncap = std::max<int64_t>(2 * S.pool_cap, (int64_t)htop + 2 * need);
     DBuf<uint64_t> ne((size_t)ncap);
+    DBuf<uint32_t> np;
     check(hipMemcpyAsync(ne.p, S.ent.p, (size_t)htop * sizeof(uint64_t), hipMemcpyDeviceToDevice,
                          st));
+    if (parents) {
+      np.alloc((size_t)ncap);
+      check(hipMemcpyAsync(np.p, S.par.p, (size_t)htop * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, st));
+    }
     check(hipStreamSynchronize(st));
     S.ent = std::move(ne);
+    if (parents) S.par = std::move(np);
     S.pool_cap = ncap;
   }
 
@@ -1140,8 +1152,13 @@ struct WBuilder {
     D.roots = roots;
     D.wmax = wmax;
     const int64_t cells = (int64_t)wmax * n;
-    D.td.alloc((size_t)cells);
-    fill(D.td, 0xFF, st);
+    if (parents) {
+      D.tdp.alloc((size_t)cells);
+      fill(D.tdp, 0xFF, st);
+    } else {
+      D.td.alloc((size_t)cells);
+      fill(D.td, 0xFF, st);
+    }
     D.fl.alloc((size_t)((cells + 3) & ~(int64_t)3));
     fill(D.fl, 0, st);
     const int64_t words = (wmax + 63) / 64;
@@ -1172,6 +1189,7 @@ struct WBuilder {
     D.cu.alloc((size_t)cap);
     D.cd.alloc((size_t)cap);
     D.cdes.alloc((size_t)cap);
+    if (parents) D.cp.alloc((size_t)cap);
     D.ctl.alloc(1);
   }
 
@@ -1179,7 +1197,10 @@ struct WBuilder {
   // overflowed, so no reset list can be trusted).
   void side_clear(WSide &D, int32_t W) {
     const int64_t cells = (int64_t)W * n;
-    check(hipMemsetAsync(D.td.p, 0xFF, (size_t)cells * sizeof(uint32_t), st));
+    if (parents)
+      check(hipMemsetAsync(D.tdp.p, 0xFF, (size_t)cells * sizeof(uint64_t), st));
+    else
+      check(hipMemsetAsync(D.td.p, 0xFF, (size_t)cells * sizeof(uint32_t), st));
     check(hipMemsetAsync(D.fl.p, 0, (size_t)((cells + 3) & ~(int64_t)3), st));
     fill(D.lm, 0, st);
     fill(D.km, 0, st);
@@ -1191,9 +1212,10 @@ struct WBuilder {
     WStore stores[2];
     const int64_t pool0 = std::max<int64_t>(1 << 16, 8 * (int64_t)n);
     for (int k = 0; k < nsides; k++) store_init(stores[k], pool0);
-    // memory: td and fl take 5 bytes per (root, vertex) cell per side
+    // memory: td and fl take 5 bytes per (root, vertex) cell per side (9
+    // with parents)
     const int64_t mem = std::max<int64_t>(1, tu.window_mem_mb) << 20;
-    const int64_t per_root = 5 * (int64_t)std::max(n, 1) * nsides;
+    const int64_t per_root = (parents ? 9 : 5) * (int64_t)std::max(n, 1) * nsides;
     int32_t wmax = (int32_t)std::max<int64_t>(
         1, std::min<int64_t>({(int64_t)tu.window, (int64_t)kMaxWWindow, mem / per_root,
                               (int64_t)std::max(n, 1)}));
@@ -1372,6 +1394,7 @@ struct WBuilder {
       const bool in_side = directed && k == 1;
       DBuf<int64_t> &foff = in_side ? ix->ioff : ix->off;
       DBuf<uint64_t> &fent = in_side ? ix->iwent : ix->went;
+      DBuf<uint32_t> &fpar = in_side ? ix->ipar : ix->par;
       DBuf<int64_t> cnt((size_t)std::max(n, 1)), tmp((size_t)scan_tmp_elems(n));
       foff.alloc((size_t)n + 1);
       check(launch_wfinal_count(S.len.p, cnt.p, n, st));
@@ -1380,7 +1403,8 @@ struct WBuilder {
       if (n > 0) d2h(&total, foff.p + n, 1, st);
       check(hipStreamSynchronize(st));
       fent.alloc((size_t)std::max<int64_t>(total, 1));
-      check(launch_wfinal_copy(S.view(), foff.p, fent.p, n, st));
+      if (parents) fpar.alloc((size_t)std::max<int64_t>(total, 1));
+      check(launch_wfinal_copy(S.view(), foff.p, fent.p, parents ? fpar.p : nullptr, n, st));
       check(hipStreamSynchronize(st));
       ix->entries += total - n;
     }
@@ -1419,6 +1443,7 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   wb.tu = tuning();
   wb.plain = (flags & PLL_PLAIN) != 0;
   wb.directed = (flags & PLL_DIRECTED) != 0;
+  wb.parents = (flags & PLL_PARENTS) != 0;
   wb.n = n;
   wb.nnz = nnz;
   ix->weighted = true;
@@ -1478,6 +1503,11 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   const auto t2 = Clock::now();
   wb.pruned(ix);
   const int64_t pr_ns = ns_since(t2);
+  if (wb.parents) {
+    ix->parents = true;
+    ix->ord.alloc((size_t)std::max<int32_t>(n, 1));
+    check(launch_invert_rank(ix->rank.p, ix->ord.p, n, st));
+  }
   ix->err.alloc(1);
   check(hipMemsetAsync(ix->err.p, 0, sizeof(int32_t), st));
   ix->g_entries.assign(1, ix->entries);
@@ -1494,7 +1524,8 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   S[PLL_STAT_RETRIES] = wb.stat_retries;
   S[PLL_STAT_LEVELS] = wb.stat_steps;
   S[PLL_STAT_INDEX_BYTES] = (int64_t)(ix->rank.bytes() + ix->off.bytes() + ix->went.bytes() +
-                                      ix->ioff.bytes() + ix->iwent.bytes());
+                                      ix->ioff.bytes() + ix->iwent.bytes() + ix->par.bytes() +
+                                      ix->ipar.bytes() + ix->ord.bytes());
   S[PLL_STAT_PRUNED_NS] = pr_ns;
   S[PLL_STAT_NORMAL_TESTS] = wb.stat_tests;
   S[PLL_STAT_LABEL_SCANNED] = wb.stat_scanned;
@@ -1728,7 +1759,6 @@ int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, co
   if (!out) return PLL_E_INVAL;
   *out = nullptr;
   if (n < 0) return PLL_E_INVAL;
-  if (flags & PLL_PARENTS) return PLL_E_UNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   const AllocStream alloc_stream(st);
   const bool device = (flags & PLL_DEVICE_PTRS) != 0;
@@ -1781,6 +1811,29 @@ int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, co
   }
   *out = ix;
   return PLL_OK;
+}
+
+int pll_export_weighted_parents(const pll_index *idx, int32_t side, uint32_t *par) {
+  if (!idx || side < 0 || side > 1 || !par) return PLL_E_INVAL;
+  if (!idx->weighted || !idx->parents || (side == 1 && !idx->directed)) return PLL_E_UNSUPPORTED;
+  return guarded([&] {
+    hipStream_t st = nullptr;
+    const int32_t n = idx->n;
+    const DBuf<int64_t> &doff = side ? idx->ioff : idx->off;
+    const DBuf<uint32_t> &dpar = side ? idx->ipar : idx->par;
+    std::vector<int64_t> ho((size_t)n + 1, 0);
+    if (n) d2h(ho.data(), doff.p, (size_t)n + 1, st);
+    check(hipStreamSynchronize(st));
+    const int64_t total = n ? ho[n] : 0;
+    if (total <= n) return PLL_OK;
+    std::vector<uint32_t> hp((size_t)total);
+    d2h(hp.data(), dpar.p, (size_t)total, st);
+    check(hipStreamSynchronize(st));
+    int64_t o = 0;
+    for (int32_t r = 0; r < n; r++)
+      for (int64_t e = ho[r]; e < ho[r + 1] - 1; e++) par[o++] = hp[e];
+    return PLL_OK;
+  });
 }
 
 int pll_query_weighted(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t *out,
@@ -2015,7 +2068,10 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
       h2d(dp.p, pairs, (size_t)(2 * q), st);
       // rows the kernel leaves alone come back unchanged
       if (cells) h2d(dpath.p, paths, cells, st);
-      check(launch_query_path(idx->view(), dp.p, q, max_len, dpath.p, dlen.p, nullptr, st));
+      if (idx->weighted)
+        check(launch_wquery_path(idx->view(), dp.p, q, max_len, dpath.p, dlen.p, nullptr, st));
+      else
+        check(launch_query_path(idx->view(), dp.p, q, max_len, dpath.p, dlen.p, nullptr, st));
       d2h(lens, dlen.p, (size_t)q, st);
       if (cells) d2h(paths, dpath.p, cells, st);
       check(hipStreamSynchronize(st));
@@ -2027,7 +2083,10 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
     check(hipMallocAsync((void **)&err, sizeof(int32_t), st));
     check(hipMemsetAsync(err, 0, sizeof(int32_t), st));
     check(launch_validate_pairs(pairs, q, idx->n, err, st));
-    check(launch_query_path(idx->view(), pairs, q, max_len, paths, lens, err, st));
+    if (idx->weighted)
+      check(launch_wquery_path(idx->view(), pairs, q, max_len, paths, lens, err, st));
+    else
+      check(launch_query_path(idx->view(), pairs, q, max_len, paths, lens, err, st));
     int32_t herr = 0;
     if (flags & PLL_SYNC) {
       check(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -285,6 +285,7 @@ struct DWStore {
   uint64_t *ent;
   unsigned long long *top;  // pool bump pointer (device)
   int64_t pool_cap;
+  uint32_t *par;  // parent of each entry's vertex in the hub's search tree (null: not kept)
 };
 
 // Control block of one weighted window (device).
@@ -317,7 +318,10 @@ enum : int32_t {
 // dense [W][n].
 struct DWWindow {
   int32_t s, W, n, words;  // words: 64-bit mask words per vertex, (W+63)/64
-  uint32_t *td;            // tentative distance, kWInf if not reached
+  uint32_t *td;            // tentative distance, kWInf if not reached (no parents)
+  uint64_t *tdp;           // with parents: distance << 32 | parent rank, ~0 if not
+                           // reached (then td is not used)
+  uint32_t *cp;            // candidate parents (with parents, else null)
   uint8_t *fl;             // flag bits (weighted.hip), padded to 4 bytes
   uint64_t *ht;            // root tables: hub -> distance of L(s+j)
   int64_t *htoff;          // [W+1]
@@ -489,8 +493,12 @@ hipError_t launch_ww_reset(DWWindow w, hipStream_t st);
 hipError_t launch_ww_landmarks(DWWindow w, uint16_t *out, hipStream_t st);
 hipError_t launch_ww_lskip(DWStore s, int32_t n, uint8_t *skip, hipStream_t st);
 hipError_t launch_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
-hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, int32_t n,
-                              hipStream_t st);
+hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, uint32_t *fpar,
+                              int32_t n, hipStream_t st);
+// Shortest paths of a weighted index built with parents (lens = vertices on
+// the path; 0 unreachable; -(vertices) if maxlen is too small).
+hipError_t launch_wquery_path(DIndex ix, const int32_t *pairs, int64_t q, int32_t maxlen,
+                              int32_t *paths, int32_t *lens, const int32_t *err, hipStream_t st);
 // out[i] = min(d(s, t), kWInf) over the packed weighted labels of ix
 hipError_t launch_wquery(DIndex ix, const int32_t *pairs, int64_t q, uint32_t *out,
                          const int32_t *err, bool plain, int qgroup, hipStream_t st);

@@ -45,6 +45,8 @@
 // the landmark hubs useless in the prune test of a later window (an entry
 // is only reached below it), so a test at a distance below 65535 skips the
 // label entries of hubs below kWLand.
+#include <climits>
+
 #include "pll_internal.h"
 
 namespace pll {
@@ -164,6 +166,14 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
   return Group<kWave>::sum_reduce(v);
 }
 
+// Tentative distance of entry idx: td, or the high half of tdp when parents
+// are kept (tdp = distance << 32 | parent, so one 64-bit atomic minimum
+// keeps distance and parent consistent: the smallest distance wins and,
+// among equal distances, the lowest-ranked parent).
+__device__ __forceinline__ uint32_t wdist(const DWWindow &w, int64_t idx) {
+  return w.tdp ? (uint32_t)(w.tdp[idx] >> 32) : w.td[idx];
+}
+
 __global__ void k_validate_weights(const uint32_t *w, int64_t nnz, int32_t *err) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -254,7 +264,10 @@ __global__ void __launch_bounds__(kBlock) k_ww_init(DWStore src, DWWindow w) {
     w.sig[4 * (int64_t)j + lane] = lane == 0 ? sg[0] : lane == 1 ? sg[1] : lane == 2 ? sg[2] : sg[3];
   if (lane == 0) {
     const int64_t idx = (int64_t)j * w.n + r;
-    w.td[idx] = 0;
+    if (w.tdp)
+      w.tdp[idx] = (uint64_t)(uint32_t)r;  // distance 0, its own parent
+    else
+      w.td[idx] = 0;
     fl_or(w.fl, idx, kTouched | kQ0);
     w.fj0[j] = j;
     w.fu0[j] = r;
@@ -291,7 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
     uint32_t f = 0, d = 0;
     if (gr == 0) {
       f = fl_clear(w.fl, idx, qc);
-      d = ld_acquire_agent(&w.td[idx]);
+      d = w.tdp ? (uint32_t)(ld_acquire_agent(&w.tdp[idx]) >> 32) : ld_acquire_agent(&w.td[idx]);
       c_proc++;
     }
     f = (uint32_t)__shfl((int)f, gb);
@@ -353,14 +366,24 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
       }
       if (useful) {
         const int64_t vi = (int64_t)j * n + v;
-        if ((uint32_t)nd < w.td[vi]) {
-          const uint32_t old = atomicMin(&w.td[vi], (uint32_t)nd);
-          if ((uint32_t)nd < old) {
-            c_improved++;
-            const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
-            push_t = !(of & kTouched);
-            push_n = !(of & qn);
+        bool lowered = false;
+        if (w.tdp) {
+          // distance and parent in one atomic; an equal distance with a
+          // lower-ranked parent only updates the parent
+          const unsigned long long key = (nd << 32) | (uint32_t)u;
+          if (key < w.tdp[vi]) {
+            const unsigned long long old =
+                atomicMin((unsigned long long *)&w.tdp[vi], key);
+            lowered = key < old && (uint32_t)(old >> 32) > (uint32_t)nd;
           }
+        } else if ((uint32_t)nd < w.td[vi]) {
+          lowered = (uint32_t)nd < atomicMin(&w.td[vi], (uint32_t)nd);
+        }
+        if (lowered) {
+          c_improved++;
+          const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
+          push_t = !(of & kTouched);
+          push_n = !(of & qn);
         }
       }
       const int64_t pn = wave_append(push_n, outc);
@@ -413,13 +436,14 @@ __global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
     const int64_t i = t0 + it * stride;
     bool lab = false;
     int32_t j = 0, u = 0;
-    uint32_t d = 0;
+    uint32_t d = 0, par = 0;
     if (i < (int64_t)tc) {
       j = w.tj[i];
       u = w.tu[i];
       const int64_t idx = (int64_t)j * w.n + u;
       lab = (w.fl[idx] & kLabeled) != 0;
-      d = w.td[idx];
+      d = wdist(w, idx);
+      if (w.cp) par = w.tdp ? (uint32_t)w.tdp[idx] : 0u;
     }
     const int64_t p = wave_append(lab, &w.ctl->ccnt);
     if (lab) {
@@ -427,6 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
         w.cj[p] = j;
         w.cu[p] = u;
         w.cd[p] = d;
+        if (w.cp) w.cp[p] = par;
         atomicOr((unsigned long long *)&w.lm[(int64_t)u * w.words + (j >> 6)],
                  1ull << (j & 63));
         atomicOr((unsigned long long *)&w.lsum[u], 1ull << (j >> 6));
@@ -471,7 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_clean(DWWindow w, DWWindow o) {
           const int bb = __ffsll((unsigned long long)m) - 1;
           m &= m - 1;
           const int64_t jj = (int64_t)q * 64 + bb;
-          if ((uint64_t)w.td[jj * n + u] + o.td[jj * n + rk] <= d) {
+          if ((uint64_t)wdist(w, jj * n + u) + wdist(o, jj * n + rk) <= d) {
             drop = true;
             break;
           }
@@ -534,7 +559,10 @@ __global__ void __launch_bounds__(kBlock) k_ww_commit_alloc(DWWindow w, DWStore 
       m &= m - 1;
       const int32_t ln = __shfl(len, l);
       const int64_t so = __shfl(oo, l), dn = __shfl(no, l);
-      for (int32_t e = lane_id(); e < ln; e += kWave) st.ent[dn + e] = st.ent[so + e];
+      for (int32_t e = lane_id(); e < ln; e += kWave) {
+        st.ent[dn + e] = st.ent[so + e];
+        if (st.par) st.par[dn + e] = st.par[so + e];
+      }
     }
     if (reloc) {
       st.off[u] = no;
@@ -565,6 +593,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_commit_write(DWWindow w, DWStore 
     }
     const int64_t o = st.off[u] + st.len[u] - 1 - above;
     st.ent[o] = ((uint64_t)(uint32_t)(w.s + k) << 32) | w.cd[c];
+    if (st.par) st.par[o] = w.cp[c];
   }
 }
 
@@ -595,7 +624,10 @@ __global__ void __launch_bounds__(kBlock) k_ww_reset(DWWindow w) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)tc;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t idx = (int64_t)w.tj[i] * w.n + w.tu[i];
-    w.td[idx] = kWInf;
+    if (w.tdp)
+      w.tdp[idx] = ~0ull;
+    else
+      w.td[idx] = kWInf;
     w.fl[idx] = 0;
   }
 }
@@ -607,7 +639,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_landmarks(DWWindow w, uint16_t *o
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t v = i / kWLand, h = i % kWLand;
-    const uint32_t d = w.td[h * w.n + v];
+    const uint32_t d = wdist(w, h * w.n + v);
     out[i] = (uint16_t)(d < 0xFFFFu ? d : 0xFFFFu);
   }
 }
@@ -630,14 +662,21 @@ __global__ void k_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n) {
 }
 
 __global__ void __launch_bounds__(kBlock) k_wfinal_copy(DWStore st, const int64_t *foff,
-                                                        uint64_t *fent, int32_t n) {
+                                                        uint64_t *fent, uint32_t *fpar,
+                                                        int32_t n) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t r = wid; r < n; r += nw) {
     const int64_t o = st.off[r], fo = foff[r];
     const int32_t len = st.len[r];
-    for (int32_t e = lane_id(); e < len; e += kWave) fent[fo + e] = st.ent[o + e];
-    if (lane_id() == 0) fent[fo + len] = kEmptyW;
+    for (int32_t e = lane_id(); e < len; e += kWave) {
+      fent[fo + e] = st.ent[o + e];
+      if (fpar) fpar[fo + e] = st.par[o + e];
+    }
+    if (lane_id() == 0) {
+      fent[fo + len] = kEmptyW;
+      if (fpar) fpar[fo + len] = kSentinel;
+    }
   }
 }
 
@@ -712,6 +751,99 @@ __global__ void __launch_bounds__(kBlock) k_wquery_group(DIndex ix, const int32_
       best = v < best ? v : best;
     }
     if (gr == 0) out[i] = (uint32_t)best;
+  }
+}
+
+// entry of hub h in the packed label of rank c, or -1
+__device__ int64_t wfind_hub(const int64_t *off, const uint64_t *ent, int32_t c, uint32_t h) {
+  int64_t lo = off[c], hi = off[c + 1] - 1;  // sentinel excluded
+  const int64_t end = hi;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if ((uint32_t)(ent[mid] >> 32) < h)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < end && (uint32_t)(ent[lo] >> 32) == h) ? lo : -1;
+}
+
+// Vertices from rank c up the search tree of hub h (c first, h last):
+// written at out[pos + dir * i] while i < room; returns the count, or -1 on
+// a broken index.
+__device__ int64_t wascend(const DIndex &ix, const int64_t *off, const uint64_t *ent,
+                           const uint32_t *par, int32_t c, uint32_t h, int32_t *out, int64_t pos,
+                           int64_t dir, int64_t room) {
+  int64_t cnt = 0;
+  for (;;) {
+    if (out && cnt < room) out[pos + dir * cnt] = ix.ord[c];
+    cnt++;
+    if ((uint32_t)c == h) return cnt;
+    if (cnt > ix.n) return -1;
+    const int64_t e = wfind_hub(off, ent, c, h);
+    if (e < 0) return -1;
+    c = (int32_t)par[e];
+  }
+}
+
+// Shortest paths of a weighted index kept with parents, one thread per
+// pair: the best hub of the merge (first on ties), then the two search
+// trees of the hub ascended (counted first, so a path that does not fit
+// writes nothing).  lens = vertices on the path, 0 if unreachable,
+// -(vertices) if maxlen is too small, INT32_MIN for a broken index.
+__global__ void __launch_bounds__(kBlock) k_wquery_path(DIndex ix, const int32_t *pairs, int64_t q,
+                                                        int32_t maxlen, int32_t *paths,
+                                                        int32_t *lens, const int32_t *err) {
+  if (err && *err) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = pairs[2 * i], t = pairs[2 * i + 1];
+    const int32_t rs = ix.rank[s], rt = ix.rank[t];
+    int32_t *out = paths + i * (int64_t)maxlen;
+    if (rs == rt) {
+      if (maxlen >= 1) out[0] = s;
+      lens[i] = maxlen >= 1 ? 1 : -1;
+      continue;
+    }
+    uint64_t best = kWInf;
+    uint32_t h = kSentinel;
+    int64_t a = ix.off[rs], b = ix.toff[rt];
+    for (;;) {
+      const uint64_t ea = ix.went[a], eb = ix.twent[b];
+      const uint32_t ha = (uint32_t)(ea >> 32), hb = (uint32_t)(eb >> 32);
+      if (ha == hb) {
+        if (ha == kSentinel) break;
+        const uint64_t v = (ea & 0xFFFFFFFFull) + (eb & 0xFFFFFFFFull);
+        if (v < best) {
+          best = v;
+          h = ha;
+        }
+        a++;
+        b++;
+      } else if (ha < hb) {
+        a++;
+      } else {
+        b++;
+      }
+    }
+    if (best >= kWInf) {
+      lens[i] = 0;
+      continue;
+    }
+    const int64_t cs = wascend(ix, ix.off, ix.went, ix.par, rs, h, nullptr, 0, 1, 0);
+    const int64_t ct = wascend(ix, ix.toff, ix.twent, ix.tpar, rt, h, nullptr, 0, 1, 0);
+    if (cs < 0 || ct < 0) {
+      lens[i] = INT32_MIN;
+      continue;
+    }
+    const int64_t total = cs + ct - 1;
+    if (total > maxlen) {
+      lens[i] = (int32_t)-total;
+      continue;
+    }
+    wascend(ix, ix.off, ix.went, ix.par, rs, h, out, 0, 1, total);
+    wascend(ix, ix.toff, ix.twent, ix.tpar, rt, h, out, total - 1, -1, total);
+    lens[i] = (int32_t)total;
   }
 }
 
@@ -824,11 +956,19 @@ hipError_t launch_wfinal_count(const int32_t *len, int64_t *cnt, int32_t n, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, int32_t n,
-                              hipStream_t st) {
+hipError_t launch_wfinal_copy(DWStore s, const int64_t *foff, uint64_t *fent, uint32_t *fpar,
+                              int32_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_wfinal_copy, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
-                     dim3(kBlock), 0, st, s, foff, fent, n);
+                     dim3(kBlock), 0, st, s, foff, fent, fpar, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_wquery_path(DIndex ix, const int32_t *pairs, int64_t q, int32_t maxlen,
+                              int32_t *paths, int32_t *lens, const int32_t *err, hipStream_t st) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wquery_path, dim3(grid_for(q, kBlock, 16384)), dim3(kBlock), 0, st, ix,
+                     pairs, q, maxlen, paths, lens, err);
   return hipGetLastError();
 }
 

@@ -183,8 +183,7 @@ def test_weighted_entry_points_reject_bad_arguments():
                                   binding.VALIDATE, None, C.byref(h)) == binding.E_INVAL
     assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), None, ptr(order), 0, None,
                                   C.byref(h)) == binding.E_INVAL
-    assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(g.w), ptr(order),
-                                  binding.PARENTS, None, C.byref(h)) == binding.E_UNSUPPORTED
+    assert lib.pll_export_weighted_parents(None, 0, ptr(np.zeros(1, np.uint32))) == binding.E_INVAL
     assert lib.pll_build_weighted(-1, None, None, None, None, 0, None, C.byref(h)) == binding.E_INVAL
     assert lib.pll_build_weighted(g.n, ptr(g.row_ptr), ptr(g.col), ptr(g.w), ptr(order), 0, None,
                                   None) == binding.E_INVAL

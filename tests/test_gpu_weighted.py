@@ -274,3 +274,58 @@ def test_weighted_without_landmarks():
         gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
     assert_same_weighted(gx, ox, "no landmarks")
     assert gx.stats()["land_checks"] == 0
+
+
+WPATH = [("rmat10_w50", gen.uniform_weights(gen.rmat_graph(10, seed=21), 1, 50, 22), False),
+         ("ba600_w9", gen.uniform_weights(gen.ba_graph(600, 3, 5), 1, 9, 23), False),
+         ("grid_w3", gen.uniform_weights(graphs.grid(12, 15), 1, 3, 24), False),
+         ("er150d_w20", gen.uniform_weights(gen.er_digraph(150, 0.03, 25), 1, 20, 26), True),
+         ("rmat9d_w30", gen.uniform_weights(gen.rmat_digraph(9, 8, seed=27), 1, 30, 28), True)]
+
+
+@pytest.mark.parametrize("name,g,directed", WPATH, ids=[w[0] for w in WPATH])
+@pytest.mark.parametrize("window", [1, 64, 4096])
+def test_weighted_paths(name, g, directed, window):
+    # Section 7 paths on weighted graphs: labels as without parents; every
+    # restored path follows edges (arcs) from s to t with weights summing to
+    # the distance; parents are tight predecessors in the hub's search tree
+    from test_oracle_weighted import edge_weights
+    _require_gpu()
+    order = gen.degree_order_directed(g) if directed else gen.degree_order(g)
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order, directed=directed)
+    with Tuned(window=window, wwork=0):
+        gx = binding.build_weighted(g.row_ptr, g.col, g.w, order, directed=directed,
+                                    parents=True)
+    assert_same_weighted(gx, ox, f"{name} window={window}")
+    ew = edge_weights(g)
+    pairs = all_pairs(g.n) if g.n <= 200 else gen.random_pairs(g.n, 40_000, 5)
+    want = oracle.query_weighted(ox, pairs).astype(np.int64)
+    paths, lens = gx.query_path(pairs, max_len=g.n + 1)
+    reach = want < WINF
+    assert np.all(lens[~reach] == 0) and np.all(lens[reach] > 0)
+    for i in np.flatnonzero(reach):
+        p = paths[i, :lens[i]].tolist()
+        hops = list(zip(p, p[1:]))
+        assert p[0] == pairs[i, 0] and p[-1] == pairs[i, 1]
+        assert all(x in ew for x in hops) and sum(ew[x] for x in hops) == want[i], (pairs[i], p)
+    # too little room: nothing written, -(vertices) reported
+    short = gx.query_path(pairs[:2000], max_len=1)[1]
+    long_ = lens[:2000]
+    assert np.all(short[long_ > 1] == -long_[long_ > 1])
+    # parents: tight predecessors (L / L_IN) or successors (L_OUT)
+    a = csr_matrix((g.w.astype(np.float64), g.col, g.row_ptr), shape=(g.n, g.n))
+    D = dijkstra(a, directed=directed)
+    sides = [(0, "out" if directed else "in")] + ([(1, "in")] if directed else [])
+    for side, kind in sides:
+        e = gx.export_weighted(side)
+        par = gx.export_weighted_parents(side)
+        owner = np.repeat(np.arange(g.n), np.diff(e["off"]))
+        v, h, pp = order[owner], order[e["hub"]], order[par]
+        d = e["dist"].astype(np.float64)
+        z = d == 0
+        assert np.all(pp[z] == v[z])
+        for vv, hh, p_, dd in zip(v[~z].tolist(), h[~z].tolist(), pp[~z].tolist(), d[~z].tolist()):
+            if kind == "out":
+                assert (vv, p_) in ew and ew[(vv, p_)] + D[p_, hh] == dd
+            else:
+                assert (p_, vv) in ew and D[hh, p_] + ew[(p_, vv)] == dd
