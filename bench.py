@@ -390,8 +390,9 @@ def main():
             "query_per_s": rates, "build_s_ba2000": bt,
         }
         out["query_latency_host_us"] = lat
-        if not batch and not directed:
-            out["shortest_paths"] = path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream)
+        if not batch:
+            out["shortest_paths"] = path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream,
+                                               directed=directed)
 
     binding.set_tuning("profile", 0)
     if not args.no_cpu_baseline:
@@ -638,16 +639,19 @@ def sweep(args):
                 f.write("| " + " | ".join(fmt(r[c]) for c in cols) + " |\n")
 
 
-def path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream, nq=100_000, max_len=32):
+def path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream, nq=100_000, max_len=32,
+               directed=False):
     """Build with parents (Section 7) and restore nq shortest paths on the
     device; inputs and outputs in HBM, timed with events on the stream."""
     import torch
 
     from paper_1304_4661_amd import binding
 
-    binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True).close()
+    binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True,
+                         directed=directed).close()
     t1 = time.perf_counter()
-    ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True)
+    ix = binding.build_device(d_row, d_col, d_order, t_bp, stream=stream, parents=True,
+                              directed=directed)
     bs = time.perf_counter() - t1
     pairs = d_pairs[:nq].contiguous()
     paths = torch.empty((len(pairs), max_len), dtype=torch.int32, device=pairs.device)
