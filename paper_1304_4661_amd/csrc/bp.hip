@@ -29,6 +29,7 @@ namespace pll {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kUnroll = 4;  // neighbours whose rows a wave reads per round
 
 __global__ void k_bpv_count_items(DGraph g, int chunk, int64_t *cnt) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,10 +86,18 @@ __global__ void __launch_bounds__(kBlock) k_bpv_e0(DGraph g, DBpW b, const int32
     const int64_t e0 = rb + (int64_t)c * chunk;
     const int64_t e1 = e0 + chunk < re ? e0 + chunk : re;
     uint64_t acc = 0;
-    for (int64_t e = e0; e < e1; e++) {
-      const int32_t y = g.col[e];
-      const int dy = lane_ok ? b.d[(int64_t)y * b.tpad + s] : kInf8;
-      if (act && dy == L) acc |= b.m[2 * ((int64_t)y * b.t + s)];
+    // kUnroll neighbours per round, so their row reads are in flight together
+    for (int64_t e = e0; e < e1; e += kUnroll) {
+      int32_t y[kUnroll];
+      int dy[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++) y[q] = e + q < e1 ? g.col[e + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++)
+        dy[q] = (lane_ok && y[q] >= 0) ? b.d[(int64_t)y[q] * b.tpad + s] : kInf8;
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++)
+        if (act && dy[q] == L) acc |= b.m[2 * ((int64_t)y[q] * b.t + s)];
     }
     if (act && acc) {
       uint64_t *dst = &b.m[2 * ((int64_t)v * b.t + s) + 1];
@@ -117,14 +126,22 @@ __global__ void __launch_bounds__(kBlock) k_bpv_e1(DGraph g, DBpW b, const int32
     const int64_t e1 = e0 + chunk < re ? e0 + chunk : re;
     bool found = false;
     uint64_t a1 = 0, a0 = 0;
-    for (int64_t e = e0; e < e1; e++) {
-      const int32_t y = g.col[e];
-      const int dy = lane_ok ? b.d[(int64_t)y * b.tpad + s] : kInf8;
-      if (act && dy == L) {
-        found = true;
-        const uint64_t *my = b.m + 2 * ((int64_t)y * b.t + s);
-        a1 |= my[0];
-        a0 |= my[1];
+    for (int64_t e = e0; e < e1; e += kUnroll) {
+      int32_t y[kUnroll];
+      int dy[kUnroll];
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++) y[q] = e + q < e1 ? g.col[e + q] : -1;
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++)
+        dy[q] = (lane_ok && y[q] >= 0) ? b.d[(int64_t)y[q] * b.tpad + s] : kInf8;
+#pragma unroll
+      for (int q = 0; q < kUnroll; q++) {
+        if (act && dy[q] == L) {
+          found = true;
+          const ulonglong2 my = reinterpret_cast<const ulonglong2 *>(b.m)[(int64_t)y[q] * b.t + s];
+          a1 |= my.x;
+          a0 |= my.y;
+        }
       }
     }
     const uint64_t fm = __ballot(found);
