@@ -1300,7 +1300,7 @@ struct WBuilder {
         bool more = false;
         for (int k = 0; k < nsides; k++) {
           flags |= sides[k].mirror.p->ctl.flags;
-          more |= sides[k].mirror.p->ctl.fcnt[cur] != 0;
+          more |= sides[k].mirror.p->ctl.fcnt[cur].v != 0;
         }
         if (flags || !more) break;
       }

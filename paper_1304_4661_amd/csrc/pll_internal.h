@@ -42,6 +42,23 @@ __device__ __forceinline__ int64_t wave_append(bool pred, unsigned long long *ct
   return (int64_t)(base + (unsigned long long)__popcll(m & lanes_below_mask()));
 }
 
+// Wave-aggregated reservation of v >= 0 slots per lane at *ctr, one atomic
+// per wave; returns this lane's first slot.  All 64 lanes must call it
+// together (converged code).
+__device__ __forceinline__ unsigned long long wave_reserve(unsigned long long v,
+                                                           unsigned long long *ctr) {
+  long long x = (long long)v;  // inclusive prefix sum over the lanes
+  for (int o = 1; o < kWave; o <<= 1) {
+    const long long y = __shfl_up(x, o);
+    if (lane_id() >= o) x += y;
+  }
+  const unsigned long long tot = (unsigned long long)__shfl(x, kWave - 1);
+  unsigned long long base = 0;
+  if (lane_id() == 0 && tot) base = atomicAdd(ctr, tot);
+  base = __shfl(base, 0);
+  return base + (unsigned long long)x - v;
+}
+
 // Wave-private staging of (a, b) pairs in LDS, written out to a global
 // list with one atomic reservation per flush.  Every method must be called
 // by all 64 lanes of the wave together (converged code): the fill count is
@@ -85,6 +102,29 @@ struct WaveStage {
     return __shfl(base, 0);
   }
 };
+
+// End of a staged kernel, block-wide: one reservation at *ctr for what all
+// waves of the block still hold, in place of one per wave (see kCtrLine).
+// Every thread of the block must call it, in block-uniform control flow.
+// s_n: LDS [waves per block]; s_base: LDS.  Returns this wave's base.
+template <int CAP>
+__device__ __forceinline__ unsigned long long block_reserve(const WaveStage<CAP> &sg,
+                                                            unsigned long long *ctr,
+                                                            int32_t *s_n,
+                                                            unsigned long long *s_base) {
+  const int wv = threadIdx.x / kWave, nwv = blockDim.x / kWave;
+  if (lane_id() == 0) s_n[wv] = sg.n;
+  __syncthreads();  // also makes every lane's staged entries visible
+  if (threadIdx.x == 0) {
+    int32_t tot = 0;
+    for (int i = 0; i < nwv; i++) tot += s_n[i];
+    *s_base = tot ? atomicAdd(ctr, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long b = *s_base;
+  for (int i = 0; i < wv; i++) b += (unsigned long long)s_n[i];
+  return b;
+}
 
 // Groups of G consecutive lanes inside a wave.
 template <int G>
@@ -182,6 +222,15 @@ struct DBpW {
 };
 __host__ __device__ inline int32_t bp_pad(int32_t t) { return (t + 15) & ~15; }
 
+// Device-wide atomics that fall on one cache line are carried out one at a
+// time (about 12 ns apiece on MI355X, returning or not), so counters that
+// many waves update each get a line of their own, and kernels sum per block
+// before they add.
+constexpr int kCtrLine = 128;
+struct alignas(kCtrLine) LineCtr {
+  unsigned long long v;
+};
+
 // Per-level control block of a level-synchronous frontier whose levels are
 // stored one after another: level L occupies [base[L], base[L] + cnt[L]).
 struct LevelCtl {
@@ -190,18 +239,19 @@ struct LevelCtl {
   unsigned long long hcnt[kMaxLevels + 2];  // heavy expansion tasks per level
   unsigned long long hcnt2[kMaxLevels + 2]; // second task list (bit-parallel E1)
   unsigned long long cmark[kMaxLevels + 2]; // first candidate found at each level
-  unsigned long long ccnt;                  // candidate labels of the window
-  unsigned long long httotal;               // entries of the window's root tables
-  unsigned long long visited;               // (root, vertex) entries tested
-  unsigned long long ntests;                // ... that reached the normal-label test
-  unsigned long long lscanned;              // label entries read by those tests
-  unsigned long long labeled;               // entries labeled (candidates)
-  unsigned long long edges;                 // adjacency entries expanded inline
-  unsigned long long hedges;                // adjacency entries expanded as tasks
-  unsigned long long bp_direct;             // reached neighbours pruned by distances alone
-  unsigned long long bp_sets;               // entries whose test read slot sets
-  unsigned long long bp_checks;             // slot-set pairs read
-  int32_t flags;
+  // each counter below sits on a cache line of its own (kCtrLine)
+  alignas(kCtrLine) unsigned long long ccnt;       // candidate labels of the window
+  alignas(kCtrLine) unsigned long long httotal;    // entries of the window's root tables
+  alignas(kCtrLine) unsigned long long visited;    // (root, vertex) entries tested
+  alignas(kCtrLine) unsigned long long ntests;     // ... that reached the normal-label test
+  alignas(kCtrLine) unsigned long long lscanned;   // label entries read by those tests
+  alignas(kCtrLine) unsigned long long labeled;    // entries labeled (candidates)
+  alignas(kCtrLine) unsigned long long edges;      // adjacency entries expanded inline
+  alignas(kCtrLine) unsigned long long hedges;     // adjacency entries expanded as tasks
+  alignas(kCtrLine) unsigned long long bp_direct;  // reached neighbours pruned by distances alone
+  alignas(kCtrLine) unsigned long long bp_sets;    // entries whose test read slot sets
+  alignas(kCtrLine) unsigned long long bp_checks;  // slot-set pairs read
+  alignas(kCtrLine) int32_t flags;
   int32_t pad;
 };
 
@@ -289,20 +339,20 @@ struct DWStore {
 };
 
 // Control block of one weighted window (device).
-struct WCtl {
-  unsigned long long fcnt[2];  // entries of the two frontier lists
-  unsigned long long tcnt;     // touched (root slot, vertex) entries
-  unsigned long long ccnt;     // candidate labels
-  unsigned long long httotal;  // entries of the window's root tables
-  unsigned long long survivors;
-  unsigned long long tests;    // entries that ran the prune test
-  unsigned long long scanned;  // label entries read by prune tests
-  unsigned long long edges;    // edges relaxed
-  unsigned long long improved; // tentative distances lowered
-  unsigned long long processed;  // frontier entries processed
-  unsigned long long filtered;   // relaxations skipped by the landmark bound
-  unsigned long long checked;    // relaxations checked against it
-  int32_t flags;
+struct WCtl {  // one cache line per counter (kCtrLine)
+  LineCtr fcnt[2];                                 // entries of the two frontier lists
+  alignas(kCtrLine) unsigned long long tcnt;       // touched (root slot, vertex) entries
+  alignas(kCtrLine) unsigned long long ccnt;       // candidate labels
+  alignas(kCtrLine) unsigned long long httotal;    // entries of the window's root tables
+  alignas(kCtrLine) unsigned long long survivors;
+  alignas(kCtrLine) unsigned long long tests;      // entries that ran the prune test
+  alignas(kCtrLine) unsigned long long scanned;    // label entries read by prune tests
+  alignas(kCtrLine) unsigned long long edges;      // edges relaxed
+  alignas(kCtrLine) unsigned long long improved;   // tentative distances lowered
+  alignas(kCtrLine) unsigned long long processed;  // frontier entries processed
+  alignas(kCtrLine) unsigned long long filtered;   // relaxations skipped by the landmark bound
+  alignas(kCtrLine) unsigned long long checked;    // relaxations checked against it
+  alignas(kCtrLine) int32_t flags;
   int32_t pad;
 };
 enum : int32_t {

@@ -90,14 +90,20 @@ __global__ void k_win_ht_size(DWindow w, DStore st, int64_t *sizes) {
 }
 
 // Wave j (of the grid): root k = s + j.  Build the root's table of L(k)
-// and the 256-bit signature of its hubs, mark k visited and put (j, k) on
-// level 0.  Bit-parallel roots and neighbours run no pruned BFS (they would
+// and the 256-bit signature of its hubs, mark k visited, put (j, k) on
+// level 0 and label it: (k, 0) becomes a candidate of L(k) without a test.  Bit-parallel roots and neighbours run no pruned BFS (they would
 // prune themselves at distance 0).  The first wave publishes the tables'
 // total size and flags a window whose tables do not fit (it is then run
 // again after the host grows the table area).
-__global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore st, DFrontier f) {
+constexpr int kInitBlock = 1024;  // 16 roots per block share one list reservation
+
+__global__ void __launch_bounds__(kInitBlock) k_win_init(DGraph g, DWindow w, DStore st,
+                                                         DFrontier f) {
+  __shared__ unsigned int s_n;
+  __shared__ unsigned long long s_base, s_cbase;
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
   const int32_t j = (int32_t)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
-  if (j >= w.W) return;
   const int lane = lane_id();
   const int32_t k = w.s + j;
   const int64_t total = w.htoff[w.W];
@@ -105,39 +111,70 @@ __global__ void __launch_bounds__(kBlock) k_win_init(DGraph g, DWindow w, DStore
     f.ctl->httotal = (unsigned long long)total;
     if (total > w.htcap) atomicOr(&f.ctl->flags, kFlagOvfHash);
   }
-  if (w.used[k]) {
-    if (lane < 4) w.sig[4 * (int64_t)j + lane] = 0ull;
-    return;
-  }
-  const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
-  const bool fits = total <= w.htcap;
-  if (fits)
-    for (int64_t e = lane; e < sz; e += kWave) w.ht[a + e] = kEmpty;
-  __threadfence_block();  // the wave's clears land before its inserts
-  const int64_t o = st.off[k];
-  const int32_t len = st.len[k];
-  uint64_t sg[4] = {0ull, 0ull, 0ull, 0ull};
-  for (int32_t e = lane; e < len; e += kWave) {
-    const uint32_t h = st.hub[o + e];
-    const uint32_t b = sig_bit(h);
+  const bool live = j < w.W && !w.used[k];
+  if (j < w.W && !live && lane < 4) w.sig[4 * (int64_t)j + lane] = 0ull;
+  unsigned int local = 0;
+  if (live) {
+    const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
+    const bool fits = total <= w.htcap;
+    if (fits)
+      for (int64_t e = lane; e < sz; e += kWave) w.ht[a + e] = kEmpty;
+    __threadfence_block();  // the wave's clears land before its inserts
+    const int64_t o = st.off[k];
+    const int32_t len = st.len[k];
+    uint64_t sg[4] = {0ull, 0ull, 0ull, 0ull};
+    for (int32_t e = lane; e < len; e += kWave) {
+      const uint32_t h = st.hub[o + e];
+      const uint32_t b = sig_bit(h);
 #pragma unroll
-    for (int q = 0; q < 4; q++) sg[q] |= (uint32_t)q == (b >> 6) ? 1ull << (b & 63) : 0ull;
-    if (!fits) continue;
-    const unsigned long long ent = ((unsigned long long)st.dist[o + e] << 32) | h;
-    uint32_t slot = ht_hash(h) & (uint32_t)(sz - 1);
-    while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmpty, ent) !=
-           (unsigned long long)kEmpty)
-      slot = (slot + 1) & (uint32_t)(sz - 1);
-  }
+      for (int q = 0; q < 4; q++) sg[q] |= (uint32_t)q == (b >> 6) ? 1ull << (b & 63) : 0ull;
+      if (!fits) continue;
+      const unsigned long long ent = ((unsigned long long)st.dist[o + e] << 32) | h;
+      uint32_t slot = ht_hash(h) & (uint32_t)(sz - 1);
+      while (atomicCAS((unsigned long long *)&w.ht[a + slot], (unsigned long long)kEmpty, ent) !=
+             (unsigned long long)kEmpty)
+        slot = (slot + 1) & (uint32_t)(sz - 1);
+    }
 #pragma unroll
-  for (int q = 0; q < 4; q++) sg[q] = Group<kWave>::or_reduce(sg[q]);
-  if (lane < 4) w.sig[4 * (int64_t)j + lane] = lane == 0 ? sg[0] : lane == 1 ? sg[1] : lane == 2 ? sg[2] : sg[3];
-  if (lane == 0) {
-    atomicOr(&w.vis[(int64_t)j * g.nwords + (k >> 5)], 1u << (k & 31));
-    const unsigned long long p = atomicAdd(&f.ctl->cnt[0], 1ull);
+    for (int q = 0; q < 4; q++) sg[q] = Group<kWave>::or_reduce(sg[q]);
+    if (lane < 4)
+      w.sig[4 * (int64_t)j + lane] = lane == 0 ? sg[0] : lane == 1 ? sg[1] : lane == 2 ? sg[2] : sg[3];
+    if (lane == 0) {
+      atomicOr(&w.vis[(int64_t)j * g.nwords + (k >> 5)], 1u << (k & 31));
+      // level 0 is decided here: (k, 0) is never pruned, since every hub
+      // already in L(k) lies at a positive distance from k and the
+      // bit-parallel slots that could give 0 belong to used vertices
+      w.wd[(int64_t)k * (w.words * 64) + j] = 0;
+      atomicOr((unsigned long long *)&w.cmask[(int64_t)k * w.words + (j >> 6)], 1ull << (j & 63));
+      atomicOr((unsigned long long *)&w.csum[4 * (int64_t)k + (j >> 12)], 1ull << ((j >> 6) & 63));
+      local = atomicAdd(&s_n, 1u);
+    }
+  }
+  // one reservation per block on the level-0 list and on the candidate
+  // list: a device-wide counter takes its atomics one at a time
+  __syncthreads();
+  if (threadIdx.x == 0 && s_n) {
+    LevelCtl *ctl = f.ctl;
+    s_base = atomicAdd(&ctl->cnt[0], (unsigned long long)s_n);
+    s_cbase = atomicAdd(&ctl->ccnt, (unsigned long long)s_n);
+    atomicAdd(&ctl->visited, (unsigned long long)s_n);
+    atomicAdd(&ctl->labeled, (unsigned long long)s_n);
+  }
+  __syncthreads();
+  if (live && lane == 0) {
+    const unsigned long long p = s_base + local;
     f.slot[p] = j;
     f.v[p] = k;
     if (f.par) f.par[p] = k;
+    const unsigned long long c = s_cbase + local;
+    if (c < (unsigned long long)w.ccap) {
+      w.cu[c] = k;
+      w.cj[c] = j;
+      w.cd[c] = 0;
+      if (w.cp) w.cp[c] = k;
+    } else {
+      atomicOr(&f.ctl->flags, kFlagOvfCand);
+    }
   }
 }
 
@@ -389,12 +426,22 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
+  __shared__ int32_t s_n[kWavesPerBlock];
+  __shared__ unsigned long long s_base, s_sum[6];
+  __shared__ bool s_go;
   LevelCtl *ctl = f.ctl;
   const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
   const unsigned long long nbase = beg + cnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->base[d + 1] = nbase;
-  // after an overflow the window is redone; never read past the buffer
-  if (cnt == 0 || (ctl->flags & kOverflowFlags) || nbase > (unsigned long long)f.cap) return;
+  // the roots (level 0) were labeled by k_win_init;
+  // after an overflow the window is redone; never read past the buffer.
+  // One thread decides for the block (the flags may change meanwhile).
+  if (threadIdx.x < 6) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x == 0)
+    s_go = !(d == 0 || cnt == 0 || (ctl->flags & kOverflowFlags) ||
+             nbase > (unsigned long long)f.cap);
+  __syncthreads();
+  if (!s_go) return;
   const int gr = Group<G>::rank();
   constexpr int kPerWave = kWave / G;
   const int wv = threadIdx.x / kWave;
@@ -402,9 +449,8 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], w.cp ? s_c[wv] : nullptr);
-  // candidates (u, j[, parent]): reserve list slots and write them
-  auto flush = [&](WaveStage<kStage> &sg) {
-    const unsigned long long c0 = sg.reserve(&ctl->ccnt);
+  // candidates (u, j[, parent]): write them at list slots from c0
+  auto write_out = [&](WaveStage<kStage> &sg, unsigned long long c0) {
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long c = c0 + i;
       if (c < (unsigned long long)w.ccap) {
@@ -417,6 +463,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       }
     }
   };
+  auto flush = [&](WaveStage<kStage> &sg) { write_out(sg, sg.reserve(&ctl->ccnt)); };
   unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
   BpTally tally;
   // the wave steps through the level in lockstep, kPerWave entries at a time
@@ -451,20 +498,20 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
     }
     stage.push(labeled, u, j, flush, par);
   }
-  if (stage.n) flush(stage);
-  c_visit = Group<kWave>::sum_reduce(c_visit);
-  c_test = Group<kWave>::sum_reduce(c_test);
-  c_scan = Group<kWave>::sum_reduce(c_scan);
-  c_lab = Group<kWave>::sum_reduce(c_lab);
-  tally.sets = Group<kWave>::sum_reduce(tally.sets);
-  tally.checks = Group<kWave>::sum_reduce(tally.checks);
-  if (lane_id() == 0 && c_visit) {
-    atomicAdd(&ctl->visited, c_visit);
-    atomicAdd(&ctl->ntests, c_test);
-    atomicAdd(&ctl->lscanned, c_scan);
-    atomicAdd(&ctl->labeled, c_lab);
-    atomicAdd(&ctl->bp_sets, tally.sets);
-    atomicAdd(&ctl->bp_checks, tally.checks);
+  write_out(stage, block_reserve(stage, &ctl->ccnt, s_n, &s_base));
+  const unsigned long long sums[6] = {
+      Group<kWave>::sum_reduce(c_visit),     Group<kWave>::sum_reduce(c_test),
+      Group<kWave>::sum_reduce(c_scan),      Group<kWave>::sum_reduce(c_lab),
+      Group<kWave>::sum_reduce(tally.sets), Group<kWave>::sum_reduce(tally.checks)};
+  if (lane_id() == 0)
+    for (int q = 0; q < 6; q++)
+      if (sums[q]) atomicAdd(&s_sum[q], sums[q]);
+  __syncthreads();
+  // one thread per counter, each counter on its own line
+  if (threadIdx.x < 6 && s_sum[threadIdx.x]) {
+    unsigned long long *dst[6] = {&ctl->visited, &ctl->ntests, &ctl->lscanned,
+                                  &ctl->labeled, &ctl->bp_sets, &ctl->bp_checks};
+    atomicAdd(dst[threadIdx.x], s_sum[threadIdx.x]);
   }
 }
 
@@ -475,7 +522,10 @@ struct FrontierFlush {
   unsigned long long nbase;
   int d;
   __device__ void operator()(WaveStage<kStage> &sg) const {
-    const unsigned long long q0 = sg.reserve(&ctl->cnt[d + 1]);
+    write_out(sg, sg.reserve(&ctl->cnt[d + 1]));
+  }
+  // the staged entries go to level d+1 from its slot q0 on
+  __device__ void write_out(const WaveStage<kStage> &sg, unsigned long long q0) const {
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long q = nbase + q0 + i;
       if (q < (unsigned long long)f.cap) {
@@ -513,11 +563,18 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
+  __shared__ int32_t s_n[kWavesPerBlock];
+  __shared__ unsigned long long s_base, s_sum[2];
+  __shared__ bool s_go;
   LevelCtl *ctl = f.ctl;
   const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
   const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
-  if (cend <= cbeg || (ctl->flags & kOverflowFlags)) return;
+  // one thread decides for the block (the flags may change meanwhile)
+  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_go = !(cend <= cbeg || (ctl->flags & kOverflowFlags));
+  __syncthreads();
+  if (!s_go) return;
   const unsigned long long nbase = ctl->base[d + 1];
   const int gr = Group<G>::rank();
   constexpr int kPerWave = kWave / G;
@@ -572,11 +629,12 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       }
       stage.push(claimed, j, x, flush, u);
     }
-    if (act && deg > lim) {
-      const int64_t extra = (deg - lim + chunk - 1) / chunk;
-      unsigned long long tb = 0;
-      if (gr == 0) tb = atomicAdd(&ctl->hcnt[d], (unsigned long long)extra);
-      tb = __shfl(tb, Group<G>::base());
+    // chunks of long lists become heavy tasks (one reservation per wave)
+    const int64_t extra = act && deg > lim ? (deg - lim + chunk - 1) / chunk : 0;
+    unsigned long long tb =
+        wave_reserve(gr == 0 ? (unsigned long long)extra : 0ull, &ctl->hcnt[d]);
+    tb = __shfl(tb, Group<G>::base());
+    if (extra > 0) {
       for (int64_t q = gr; q < extra; q += G) {
         if ((int64_t)tb + q < f.hcap) {
           f.hslot[tb + q] = j;
@@ -588,11 +646,14 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       }
     }
   }
-  if (stage.n) flush(stage);
+  flush.write_out(stage, block_reserve(stage, &ctl->cnt[d + 1], s_n, &s_base));
   c_edge = Group<kWave>::sum_reduce(c_edge);
   c_direct = Group<kWave>::sum_reduce(c_direct);
-  if (lane_id() == 0 && c_edge) atomicAdd(&ctl->edges, c_edge);
-  if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
+  if (lane_id() == 0 && c_edge) atomicAdd(&s_sum[0], c_edge);
+  if (lane_id() == 0 && c_direct) atomicAdd(&s_sum[1], c_direct);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&ctl->edges, s_sum[0]);
+  if (threadIdx.x == 1 && s_sum[1]) atomicAdd(&ctl->bp_direct, s_sum[1]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
@@ -786,12 +847,12 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
         nc = 2 * (int64_t)need;
         if (nc < 16) nc = 16;
         nc = (nc + 15) & ~(int64_t)15;
-        no = (int64_t)atomicAdd(st.top, (unsigned long long)nc);
         oo = st.off[u];
         reloc = true;
       }
       st.len[u] = need;
     }
+    no = (int64_t)wave_reserve((unsigned long long)nc, st.top);
     uint64_t m = __ballot(reloc);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
@@ -915,8 +976,9 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
   hipLaunchKernelGGL(k_win_ht_size, dim3((nroots + 1 + 255) / 256), dim3(256), 0, st, w, s, sizes);
   hipError_t e = launch_exclusive_scan(sizes, w.htoff, (int64_t)nroots, scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_win_init, dim3((nroots + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock),
-                     0, st, g, w, s, f);
+  constexpr int kInitWaves = kInitBlock / kWave;
+  hipLaunchKernelGGL(k_win_init, dim3((nroots + kInitWaves - 1) / kInitWaves), dim3(kInitBlock), 0,
+                     st, g, w, s, f);
   return hipGetLastError();
 }
 

@@ -55,6 +55,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr unsigned kGrid = 2048;
+constexpr int kWStage = 256;  // staged list entries per wave
 constexpr uint64_t kEmptyW = ~0ull;
 
 constexpr uint32_t kQ0 = 1, kQ1 = 2, kTouched = 4, kLabeled = 8;
@@ -203,7 +204,7 @@ __global__ void k_ww_reset_ctl(WCtl *ctl) {
 }
 
 __global__ void k_ww_zero_list(WCtl *ctl, int list) {
-  if (threadIdx.x == 0) ctl->fcnt[list] = 0;
+  if (threadIdx.x == 0) ctl->fcnt[list].v = 0;
 }
 
 __global__ void k_ww_ht_size(DWStore src, DWWindow w, int64_t *sizes) {
@@ -235,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_ww_init(DWStore src, DWWindow w) {
   if (j == 0 && lane == 0) {
     w.ctl->httotal = (unsigned long long)total;
     if (!fits) atomicOr(&w.ctl->flags, kWOvfHash);
-    w.ctl->fcnt[0] = (unsigned long long)w.W;
+    w.ctl->fcnt[0].v = (unsigned long long)w.W;
     w.ctl->tcnt = (unsigned long long)w.W;
   }
   const int64_t a = w.htoff[j], sz = w.htoff[j + 1] - a;
@@ -283,175 +284,214 @@ __global__ void __launch_bounds__(kBlock) k_ww_init(DWStore src, DWWindow w) {
 // they are reached, to the touched list.
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWindow w, int cur) {
-  if (w.ctl->flags) return;
-  unsigned long long cnt = w.ctl->fcnt[cur];
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ int32_t s_nj[kWaves][kWStage], s_nu[kWaves][kWStage];
+  __shared__ int32_t s_tj[kWaves][kWStage], s_tu[kWaves][kWStage];
+  __shared__ int32_t s_n1[kWaves], s_n2[kWaves];
+  __shared__ unsigned long long s_b1, s_b2, s_sum[7];
+  __shared__ bool s_go;
+  // one thread decides for the block (the flags may change meanwhile)
+  if (threadIdx.x < 7) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x == 0) s_go = w.ctl->flags == 0;
+  __syncthreads();
+  if (!s_go) return;
+  unsigned long long cnt = w.ctl->fcnt[cur].v;
   if (cnt > (unsigned long long)w.fcap) cnt = (unsigned long long)w.fcap;
   const int32_t *inj = cur ? w.fj1 : w.fj0;
   const int32_t *inu = cur ? w.fu1 : w.fu0;
   int32_t *outj = cur ? w.fj0 : w.fj1;
   int32_t *outu = cur ? w.fu0 : w.fu1;
-  unsigned long long *outc = &w.ctl->fcnt[cur ^ 1];
+  unsigned long long *outc = &w.ctl->fcnt[cur ^ 1].v;
   const uint32_t qc = qbit(cur), qn = qbit(cur ^ 1);
   const int gr = Group<G>::rank(), gb = Group<G>::base();
-  const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
-  const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
+  constexpr int kPerWave = kWave / G;
+  const int wv = threadIdx.x / kWave;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int32_t n = w.n;
+  // entries for the next frontier list and for the touched list are staged
+  // per wave and written with one reservation per stage
+  WaveStage<kWStage> sn, stt;
+  sn.init(s_nj[wv], s_nu[wv]);
+  stt.init(s_tj[wv], s_tu[wv]);
+  auto write_n = [&](const WaveStage<kWStage> &sg, unsigned long long q0) {
+    for (int i = lane_id(); i < sg.n; i += kWave) {
+      const unsigned long long q = q0 + i;
+      if (q < (unsigned long long)w.fcap) {
+        outj[q] = sg.a[i];
+        outu[q] = sg.b[i];
+      } else {
+        atomicOr(&w.ctl->flags, kWOvfFrontier);
+      }
+    }
+  };
+  auto write_t = [&](const WaveStage<kWStage> &sg, unsigned long long q0) {
+    for (int i = lane_id(); i < sg.n; i += kWave) {
+      const unsigned long long q = q0 + i;
+      if (q < (unsigned long long)w.tcap) {
+        w.tj[q] = sg.a[i];
+        w.tu[q] = sg.b[i];
+      } else {
+        atomicOr(&w.ctl->flags, kWOvfTouched);
+      }
+    }
+  };
+  auto flush_n = [&](WaveStage<kWStage> &sg) { write_n(sg, sg.reserve(outc)); };
+  auto flush_t = [&](WaveStage<kWStage> &sg) { write_t(sg, sg.reserve(&w.ctl->tcnt)); };
   unsigned long long c_tests = 0, c_scanned = 0, c_edges = 0, c_improved = 0, c_proc = 0,
                      c_filtered = 0, c_checked = 0;
-  for (int64_t i = gid; i < (int64_t)cnt; i += ngroups) {
-    const int32_t j = inj[i], u = inu[i];
-    const int64_t idx = (int64_t)j * n + u;
-    uint32_t f = 0, d = 0;
-    if (gr == 0) {
-      f = fl_clear(w.fl, idx, qc);
-      d = w.tdp ? (uint32_t)(ld_acquire_agent(&w.tdp[idx]) >> 32) : ld_acquire_agent(&w.td[idx]);
-      c_proc++;
-    }
-    f = (uint32_t)__shfl((int)f, gb);
-    d = (uint32_t)__shfl((int)d, gb);
-    if (!(f & kLabeled)) {
-      if (gr == 0) c_tests++;
-      // entries of landmark hubs cannot prune here (see above): the entry
-      // was reached below the 16-bit bound, and a hub left out of that
-      // bound is at least 65535 away, so below 65535 none of them can
-      const int32_t b0 = (w.lroot && d < 0xFFFFu) ? (int32_t)w.lskip[u] : 0;
-      const bool pr = wlabel_prunes<G>(s, wroot_table(w, j), w.sig + 4 * (int64_t)j, u, d, b0,
-                                       &c_scanned);
-      if (pr) continue;
-      if (gr == 0) fl_or(w.fl, idx, kLabeled);
-    }
-    // the root's distances to the landmark hubs (see the filter above)
-    uint32_t rl[kWLand / 2];  // pairs of 16-bit distances
-    if (w.lroot) {
-      const uint4 *p = reinterpret_cast<const uint4 *>(w.lroot + (int64_t)(w.s + j) * kWLand);
+  // the wave steps through the list in lockstep, kPerWave entries at a time
+  for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
+    const int64_t i = base + lane_id() / G;
+    int32_t j = 0, u = 0;
+    uint32_t d = 0;
+    int64_t a = 0, b = 0;  // u's edges to relax (none if pruned)
+    uint32_t rl[kWLand / 2];  // the root's distances to the landmark hubs, in pairs
+    if (i < (int64_t)cnt) {
+      j = inj[i];
+      u = inu[i];
+      const int64_t idx = (int64_t)j * n + u;
+      uint32_t f = 0;
+      if (gr == 0) {
+        f = fl_clear(w.fl, idx, qc);
+        d = w.tdp ? (uint32_t)(ld_acquire_agent(&w.tdp[idx]) >> 32) : ld_acquire_agent(&w.td[idx]);
+        c_proc++;
+      }
+      f = (uint32_t)__shfl((int)f, gb);
+      d = (uint32_t)__shfl((int)d, gb);
+      bool pr = false;
+      if (!(f & kLabeled)) {
+        if (gr == 0) c_tests++;
+        // entries of landmark hubs cannot prune here (see above): the entry
+        // was reached below the 16-bit bound, and a hub left out of that
+        // bound is at least 65535 away, so below 65535 none of them can
+        const int32_t b0 = (w.lroot && d < 0xFFFFu) ? (int32_t)w.lskip[u] : 0;
+        pr = wlabel_prunes<G>(s, wroot_table(w, j), w.sig + 4 * (int64_t)j, u, d, b0,
+                              &c_scanned);
+        if (!pr && gr == 0) fl_or(w.fl, idx, kLabeled);
+      }
+      if (!pr) {
+        if (w.lroot) {
+          const uint4 *p = reinterpret_cast<const uint4 *>(w.lroot + (int64_t)(w.s + j) * kWLand);
 #pragma unroll
-      for (int q = 0; q < kWLand / 8; q++) {
-        const uint4 x = p[q];
-        rl[4 * q] = x.x;
-        rl[4 * q + 1] = x.y;
-        rl[4 * q + 2] = x.z;
-        rl[4 * q + 3] = x.w;
+          for (int q = 0; q < kWLand / 8; q++) {
+            const uint4 x = p[q];
+            rl[4 * q] = x.x;
+            rl[4 * q + 1] = x.y;
+            rl[4 * q + 2] = x.z;
+            rl[4 * q + 3] = x.w;
+          }
+        }
+        a = g.row[u];
+        b = g.row[u + 1];
       }
     }
-    const int64_t a = g.row[u], b = g.row[u + 1];
-    for (int64_t e = a + gr; e < b; e += G) {
-      const int32_t v = g.col[e];
-      const uint64_t nd = (uint64_t)d + g.wt[e];
+    const int64_t wl = Group<kWave>::max_reduce64(b - a);
+    for (int64_t e0 = 0; e0 < wl; e0 += G) {
+      const int64_t e = a + e0 + gr;
       bool push_n = false, push_t = false;
-      c_edges++;
-      bool useful = nd < (uint64_t)kWInf;
-      if (useful && w.lroot) {
-        c_checked++;
-        const uint4 *p = reinterpret_cast<const uint4 *>(w.lvert + (int64_t)v * kWLand);
-        uint32_t lb = kWInf;
+      int32_t v = 0;
+      if (e < b) {
+        v = g.col[e];
+        const uint64_t nd = (uint64_t)d + g.wt[e];
+        c_edges++;
+        bool useful = nd < (uint64_t)kWInf;
+        if (useful && w.lroot) {
+          c_checked++;
+          const uint4 *p = reinterpret_cast<const uint4 *>(w.lvert + (int64_t)v * kWLand);
+          uint32_t lb = kWInf;
 #pragma unroll
-        for (int q = 0; q < kWLand / 8; q++) {
-          const uint4 x = p[q];
-          const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+          for (int q = 0; q < kWLand / 8; q++) {
+            const uint4 x = p[q];
+            const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-          for (int i = 0; i < 4; i++) {
+            for (int i = 0; i < 4; i++) {
 #pragma unroll
-            for (int half = 0; half < 2; half++) {
-              const uint32_t a16 = (rl[4 * q + i] >> (16 * half)) & 0xFFFFu;
-              const uint32_t b16 = (xv[i] >> (16 * half)) & 0xFFFFu;
-              const uint32_t t = (a16 == 0xFFFFu || b16 == 0xFFFFu) ? kWInf : a16 + b16;
-              lb = t < lb ? t : lb;
+              for (int half = 0; half < 2; half++) {
+                const uint32_t a16 = (rl[4 * q + i] >> (16 * half)) & 0xFFFFu;
+                const uint32_t b16 = (xv[i] >> (16 * half)) & 0xFFFFu;
+                const uint32_t t = (a16 == 0xFFFFu || b16 == 0xFFFFu) ? kWInf : a16 + b16;
+                lb = t < lb ? t : lb;
+              }
             }
           }
-        }
-        if ((uint64_t)lb <= nd) {
-          useful = false;
-          c_filtered++;
-        }
-      }
-      if (useful) {
-        const int64_t vi = (int64_t)j * n + v;
-        bool lowered = false;
-        if (w.tdp) {
-          // distance and parent in one atomic; an equal distance with a
-          // lower-ranked parent only updates the parent
-          const unsigned long long key = (nd << 32) | (uint32_t)u;
-          if (key < w.tdp[vi]) {
-            const unsigned long long old =
-                atomicMin((unsigned long long *)&w.tdp[vi], key);
-            lowered = key < old && (uint32_t)(old >> 32) > (uint32_t)nd;
+          if ((uint64_t)lb <= nd) {
+            useful = false;
+            c_filtered++;
           }
-        } else if ((uint32_t)nd < w.td[vi]) {
-          lowered = (uint32_t)nd < atomicMin(&w.td[vi], (uint32_t)nd);
         }
-        if (lowered) {
-          c_improved++;
-          const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
-          push_t = !(of & kTouched);
-          push_n = !(of & qn);
-        }
-      }
-      const int64_t pn = wave_append(push_n, outc);
-      if (push_n) {
-        if (pn < w.fcap) {
-          outj[pn] = j;
-          outu[pn] = v;
-        } else {
-          atomicOr(&w.ctl->flags, kWOvfFrontier);
-        }
-      }
-      const int64_t pt = wave_append(push_t, &w.ctl->tcnt);
-      if (push_t) {
-        if (pt < w.tcap) {
-          w.tj[pt] = j;
-          w.tu[pt] = v;
-        } else {
-          atomicOr(&w.ctl->flags, kWOvfTouched);
+        if (useful) {
+          const int64_t vi = (int64_t)j * n + v;
+          bool lowered = false;
+          if (w.tdp) {
+            // distance and parent in one atomic; an equal distance with a
+            // lower-ranked parent only updates the parent
+            const unsigned long long key = (nd << 32) | (uint32_t)u;
+            if (key < w.tdp[vi]) {
+              const unsigned long long old =
+                  atomicMin((unsigned long long *)&w.tdp[vi], key);
+              lowered = key < old && (uint32_t)(old >> 32) > (uint32_t)nd;
+            }
+          } else if ((uint32_t)nd < w.td[vi]) {
+            lowered = (uint32_t)nd < atomicMin(&w.td[vi], (uint32_t)nd);
+          }
+          if (lowered) {
+            c_improved++;
+            const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
+            push_t = !(of & kTouched);
+            push_n = !(of & qn);
+          }
         }
       }
+      sn.push(push_n, j, v, flush_n);
+      stt.push(push_t, j, v, flush_t);
     }
   }
-  c_tests = wave_sum(c_tests);
-  c_scanned = wave_sum(c_scanned);
-  c_edges = wave_sum(c_edges);
-  c_improved = wave_sum(c_improved);
-  c_proc = wave_sum(c_proc);
-  c_filtered = wave_sum(c_filtered);
-  c_checked = wave_sum(c_checked);
-  if (lane_id() == 0) {
-    if (c_checked) atomicAdd(&w.ctl->checked, c_checked);
-    if (c_filtered) atomicAdd(&w.ctl->filtered, c_filtered);
-    if (c_tests) atomicAdd(&w.ctl->tests, c_tests);
-    if (c_scanned) atomicAdd(&w.ctl->scanned, c_scanned);
-    if (c_edges) atomicAdd(&w.ctl->edges, c_edges);
-    if (c_improved) atomicAdd(&w.ctl->improved, c_improved);
-    if (c_proc) atomicAdd(&w.ctl->processed, c_proc);
+  write_n(sn, block_reserve(sn, outc, s_n1, &s_b1));
+  write_t(stt, block_reserve(stt, &w.ctl->tcnt, s_n2, &s_b2));
+  const unsigned long long sums[7] = {wave_sum(c_checked), wave_sum(c_filtered),
+                                      wave_sum(c_tests),   wave_sum(c_scanned),
+                                      wave_sum(c_edges),   wave_sum(c_improved),
+                                      wave_sum(c_proc)};
+  if (lane_id() == 0)
+    for (int q = 0; q < 7; q++)
+      if (sums[q]) atomicAdd(&s_sum[q], sums[q]);
+  __syncthreads();
+  // one thread per counter, each counter on its own line
+  if (threadIdx.x < 7 && s_sum[threadIdx.x]) {
+    unsigned long long *dst[7] = {&w.ctl->checked, &w.ctl->filtered, &w.ctl->tests,
+                                  &w.ctl->scanned, &w.ctl->edges,    &w.ctl->improved,
+                                  &w.ctl->processed};
+    atomicAdd(dst[threadIdx.x], s_sum[threadIdx.x]);
   }
 }
 
 // Labeled touched entries become candidates (root slot, vertex, final
 // distance); the vertex's mask row and summary get the root's bit.
 __global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
+  constexpr int kWaves = kBlock / kWave;
+  __shared__ int32_t s_j[kWaves][kWStage], s_u[kWaves][kWStage];
+  __shared__ int32_t s_n[kWaves];
+  __shared__ unsigned long long s_base;
   unsigned long long tc = w.ctl->tcnt;
   if (tc > (unsigned long long)w.tcap) tc = (unsigned long long)w.tcap;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nloop = ((int64_t)tc + stride - 1) / stride;
-  for (int64_t it = 0; it < nloop; it++) {  // wave-uniform trip count
-    const int64_t i = t0 + it * stride;
-    bool lab = false;
-    int32_t j = 0, u = 0;
-    uint32_t d = 0, par = 0;
-    if (i < (int64_t)tc) {
-      j = w.tj[i];
-      u = w.tu[i];
-      const int64_t idx = (int64_t)j * w.n + u;
-      lab = (w.fl[idx] & kLabeled) != 0;
-      d = wdist(w, idx);
-      if (w.cp) par = w.tdp ? (uint32_t)w.tdp[idx] : 0u;
-    }
-    const int64_t p = wave_append(lab, &w.ctl->ccnt);
-    if (lab) {
-      if (p < w.ccap) {
+  // labeled entries (j, u) are staged per wave; the write-out reads their
+  // final distance and parent again
+  WaveStage<kWStage> sg;
+  sg.init(s_j[threadIdx.x / kWave], s_u[threadIdx.x / kWave]);
+  auto write_out = [&](const WaveStage<kWStage> &st, unsigned long long p0) {
+    for (int i = lane_id(); i < st.n; i += kWave) {
+      const unsigned long long p = p0 + i;
+      const int32_t j = st.a[i], u = st.b[i];
+      if (p < (unsigned long long)w.ccap) {
+        const int64_t idx = (int64_t)j * w.n + u;
         w.cj[p] = j;
         w.cu[p] = u;
-        w.cd[p] = d;
-        if (w.cp) w.cp[p] = par;
+        w.cd[p] = wdist(w, idx);
+        if (w.cp) w.cp[p] = w.tdp ? (uint32_t)w.tdp[idx] : 0u;
         atomicOr((unsigned long long *)&w.lm[(int64_t)u * w.words + (j >> 6)],
                  1ull << (j & 63));
         atomicOr((unsigned long long *)&w.lsum[u], 1ull << (j >> 6));
@@ -459,7 +499,20 @@ __global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
         atomicOr(&w.ctl->flags, kWOvfCand);
       }
     }
+  };
+  auto flush = [&](WaveStage<kWStage> &st) { write_out(st, st.reserve(&w.ctl->ccnt)); };
+  for (int64_t it = 0; it < nloop; it++) {  // wave-uniform trip count
+    const int64_t i = t0 + it * stride;
+    bool lab = false;
+    int32_t j = 0, u = 0;
+    if (i < (int64_t)tc) {
+      j = w.tj[i];
+      u = w.tu[i];
+      lab = (w.fl[(int64_t)j * w.n + u] & kLabeled) != 0;
+    }
+    sg.push(lab, j, u, flush);
   }
+  write_out(sg, block_reserve(sg, &w.ctl->ccnt, s_n, &s_base));
 }
 
 // Cleaning: candidate (k, d) of u is dropped iff a window root j < k labeled
@@ -468,6 +521,10 @@ __global__ void __launch_bounds__(kBlock) k_ww_collect(DWWindow w) {
 // d(j, u) + d(j, v_k) <= d.  Survivors set their bit in the km row; the
 // candidate of u's lowest window root is u's designated committer.
 __global__ void __launch_bounds__(kBlock) k_ww_clean(DWWindow w, DWWindow o) {
+  __shared__ unsigned long long s_keep;
+  if (threadIdx.x == 0) s_keep = 0;
+  __syncthreads();
+  unsigned long long kept = 0;
   unsigned long long cc = w.ctl->ccnt;
   if (cc > (unsigned long long)w.ccap) cc = (unsigned long long)w.ccap;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -510,9 +567,13 @@ __global__ void __launch_bounds__(kBlock) k_ww_clean(DWWindow w, DWWindow o) {
       const int low = q0 * 64 + __ffsll((unsigned long long)lu[q0]) - 1;
       w.cdes[c] = low == k ? 1 : 0;
     }
-    const unsigned long long ks = wave_sum(keep ? 1ull : 0ull);
-    if (lane_id() == 0 && ks) atomicAdd(&w.ctl->survivors, ks);
+    kept += keep ? 1ull : 0ull;
   }
+  // one addition per block (see kCtrLine)
+  kept = wave_sum(kept);
+  if (lane_id() == 0 && kept) atomicAdd(&s_keep, kept);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_keep) atomicAdd(&w.ctl->survivors, s_keep);
 }
 
 // Commit pass 1, one lane per designated candidate: count the vertex's
@@ -547,12 +608,12 @@ __global__ void __launch_bounds__(kBlock) k_ww_commit_alloc(DWWindow w, DWStore 
         nc = 2 * (int64_t)need;
         if (nc < 16) nc = 16;
         nc = (nc + 15) & ~(int64_t)15;
-        no = (int64_t)atomicAdd(st.top, (unsigned long long)nc);
         oo = st.off[u];
         reloc = true;
       }
       st.len[u] = need;
     }
+    no = (int64_t)wave_reserve((unsigned long long)nc, st.top);
     uint64_t m = __ballot(reloc);
     while (m) {
       const int l = __ffsll((unsigned long long)m) - 1;
