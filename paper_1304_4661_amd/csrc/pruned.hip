@@ -234,9 +234,11 @@ struct BpTally {
   unsigned long long direct = 0, sets = 0, checks = 0;
 };
 
+// zk, zu: bp.z[k] and bp.z[u] (read by the caller together with its other
+// loads).
 template <int G>
 __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, int d,
-                                          BpTally &tally) {
+                                          uint64_t zk, uint64_t zu, BpTally &tally) {
   const int gr = Group<G>::rank();
   const int nv = bp.tpad >> 4;
   bool direct = false;
@@ -265,12 +267,9 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
   if (!(need1 | need2)) return false;
   // -2 needs S^{-1} non-empty on both sides; -1 (with S^0 on one side)
   // needs it on at least one
-  {
-    const uint64_t zk = bp.z[k], zu = bp.z[u];
-    need1 &= zk & zu;
-    need2 &= zk | zu;
-    if (!(need1 | need2)) return false;
-  }
+  need1 &= zk & zu;
+  need2 &= zk | zu;
+  if (!(need1 | need2)) return false;
   if (gr == 0) tally.sets++;
   const ulonglong2 *pk = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)k * bp.t;
   const ulonglong2 *pu = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)u * bp.t;
@@ -314,20 +313,17 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
 // hub is probed only when its bit is set in the 256-bit signature of the
 // root's label (held in registers): with short root labels most hubs of
 // L(u) cost no probe.  An empty root label prunes nothing.
+// o, len: L(u)'s place in the store; s01, s23: the root's signature (all
+// read by the caller together with its other loads).
 template <int G>
-__device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, const uint64_t *sig,
-                                             int32_t u, int d, int32_t *len_out) {
+__device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, ulonglong2 s01,
+                                             ulonglong2 s23, int64_t o, int32_t len, int d) {
   constexpr int U = 4;
   constexpr uint32_t kNoHub = 0xFFFFFFFFu;
   const int gr = Group<G>::rank();
-  const int64_t o = st.off[u];
-  const int32_t len = st.len[u];
-  *len_out = len;
   if (len == 0 || Tj.empty) return false;
   const uint32_t *hp = st.hub + o;
   const uint8_t *dp = st.dist + o;
-  const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
-  const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
   for (int32_t base = 0; base < len; base += G * U) {
     uint32_t hh[U];
 #pragma unroll
@@ -476,14 +472,21 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       u = f.v[beg + p];
       if (f.par) par = f.par[beg + p];
       if (gr == 0) c_visit++;
+      // everything both tests may read that depends only on (j, u) is
+      // loaded now, so the loads are in flight together
+      const uint64_t zk = bp.t ? bp.z[w.s + j] : 0ull, zu = bp.t ? bp.z[u] : 0ull;
+      const int64_t lo = st.off[u];
+      const int32_t llen = st.len[u];
+      const RootTable Tj = root_table(w, j);
+      const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
+      const ulonglong2 s01 = sg[0], s23 = sg[1];
       // bit-parallel labels first (Section 5.4)
-      bool pr = bp_prunes<G>(bp, w.s + j, u, d, tally);
+      bool pr = bp_prunes<G>(bp, w.s + j, u, d, zk, zu, tally);
       if (!pr) {
-        int32_t len;
-        pr = label_prunes<G>(st, root_table(w, j), w.sig + 4 * (int64_t)j, u, d, &len);
+        pr = label_prunes<G>(st, Tj, s01, s23, lo, llen, d);
         if (gr == 0) {
           c_test++;
-          c_scan += (unsigned long long)len;
+          c_scan += (unsigned long long)llen;
         }
       }
       labeled = !pr && gr == 0;

@@ -113,17 +113,16 @@ __device__ __forceinline__ uint32_t wsig_bit(uint32_t h) { return (h * 265443576
 // hub of L(u) (from entry b0 on) give T[h] + d(h, u) <= d?  G lanes, U
 // entries per lane per round, signature check before each probe; adds the
 // entries read to *scanned (lane 0).
+// o, len: L(u)'s place in the store; s01, s23: the root's signature (read
+// by the caller together with its other loads).
 template <int G>
 __device__ __forceinline__ bool wlabel_prunes(const DWStore &s, const WRootTable &T,
-                                              const uint64_t *sig, int32_t u, uint32_t d,
-                                              int32_t b0, unsigned long long *scanned) {
+                                              ulonglong2 s01, ulonglong2 s23, int64_t o,
+                                              int32_t len, uint32_t d, int32_t b0,
+                                              unsigned long long *scanned) {
   constexpr int U = 2;
   const int gr = Group<G>::rank();
-  const int64_t o = s.off[u];
-  const int32_t len = s.len[u];
   if (T.empty || len <= b0) return false;
-  const ulonglong2 s01 = reinterpret_cast<const ulonglong2 *>(sig)[0];
-  const ulonglong2 s23 = reinterpret_cast<const ulonglong2 *>(sig)[1];
   for (int32_t base = b0; base < len; base += G * U) {
     if (gr == 0) *scanned += (unsigned long long)(len - base < G * U ? len - base : G * U);
     uint64_t ent[U];
@@ -357,6 +356,14 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
         d = w.tdp ? (uint32_t)(ld_acquire_agent(&w.tdp[idx]) >> 32) : ld_acquire_agent(&w.td[idx]);
         c_proc++;
       }
+      // what the prune test may read that depends only on (j, u) is loaded
+      // now, in flight with the flag and distance
+      const int64_t lo = s.off[u];
+      const int32_t llen = s.len[u];
+      const int32_t skip = w.lroot ? (int32_t)w.lskip[u] : 0;
+      const WRootTable T = wroot_table(w, j);
+      const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
+      const ulonglong2 s01 = sg[0], s23 = sg[1];
       f = (uint32_t)__shfl((int)f, gb);
       d = (uint32_t)__shfl((int)d, gb);
       bool pr = false;
@@ -365,9 +372,8 @@ __global__ void __launch_bounds__(kBlock) k_ww_step(DWGraph g, DWStore s, DWWind
         // entries of landmark hubs cannot prune here (see above): the entry
         // was reached below the 16-bit bound, and a hub left out of that
         // bound is at least 65535 away, so below 65535 none of them can
-        const int32_t b0 = (w.lroot && d < 0xFFFFu) ? (int32_t)w.lskip[u] : 0;
-        pr = wlabel_prunes<G>(s, wroot_table(w, j), w.sig + 4 * (int64_t)j, u, d, b0,
-                              &c_scanned);
+        const int32_t b0 = (w.lroot && d < 0xFFFFu) ? skip : 0;
+        pr = wlabel_prunes<G>(s, T, s01, s23, lo, llen, d, b0, &c_scanned);
         if (!pr && gr == 0) fl_or(w.fl, idx, kLabeled);
       }
       if (!pr) {
