@@ -289,7 +289,8 @@ def main():
         ix.close()
     # query tiles autotuned on a sample of the pairs, before the timed region
     ix = build()
-    qgroup = ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
+    qgroup = (ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
+              if q > 0 else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
 
@@ -436,7 +437,8 @@ def bench_weighted(args):
         ix.sync()
         ix.close()
     ix = binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True)
-    qgroup = ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
+    qgroup = (ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
+              if q > 0 else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
     build_s, query_ms, stats = [], [], []
