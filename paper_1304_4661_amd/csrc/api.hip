@@ -24,7 +24,7 @@ struct Tuning {
   int64_t window_mem_mb = 65536;  // device memory allowed for per-root state
   int64_t list_cap = 0;   // cap on frontier / candidate / task lists (0: sized from W)
   int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
-  int group = 4;      // lanes per frontier entry (prune tests)
+  int group = 0;      // lanes per frontier entry (prune tests; 0: chosen per window)
   int xgroup = 16;    // lanes per candidate expanding its adjacency list
   int wgroup = 64;    // lanes per frontier entry of a weighted search step
   int64_t wwork = 2000000;  // touched entries aimed at per weighted window
@@ -768,7 +768,7 @@ struct Builder {
       for (; d < upto; d++) {
         hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
         hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
-        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, tu.group, tu.xgroup, tu.chunk, st,
+        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk, st,
                                e0, e1));
         stat_levels++;
         stat_level_launches++;
@@ -805,8 +805,14 @@ struct Builder {
   DBuf<int64_t> irow;  // in-edges of a directed graph (rank space)
   DBuf<int32_t> icol;
 
+  // Lanes per prune test for an average scan of `len` label entries: short
+  // labels keep many tests in flight per wave, long ones split a scan.
+  static int group_for_scan(int64_t len) { return len < 32 ? 4 : len < 64 ? 8 : 16; }
+  int test_group = 4;
+
   void pruned(pll_index *ix) {
     const int nsides = directed ? 2 : 1;
+    test_group = tu.group > 0 ? tu.group : 4;
     // per-root window state per side: distance column of wd (n B), visited
     // bits (n/8 B) and two mask bits per vertex (n/4 B)
     const int64_t per_root = nsides * ((int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1);
@@ -948,6 +954,7 @@ struct Builder {
       for (int k = 0; k < nsides; k++)
         check(launch_win_clean(w[k], w[nsides - 1 - k], ncand[k], st));
       double work = 0;
+      int64_t wtests = 0, wscanned = 0;
       for (int k = 0; k < nsides; k++) {
         check(launch_win_commit(w[k], sides[k].own->view(), ncand[k], st));
         const LevelCtl &h = sides[k].mirror.p->ctl;
@@ -962,7 +969,12 @@ struct Builder {
         stat_bp_checks += (int64_t)h.bp_checks;
         stat_cand += ncand[k];
         work += (double)h.visited + (double)h.bp_direct;
+        wtests += (int64_t)h.ntests;
+        wscanned += (int64_t)h.lscanned;
       }
+      // "group" 0: lanes per prune test follow the label entries a test
+      // scanned in this window (labels grow as roots commit)
+      if (tu.group == 0 && wtests >= 1024) test_group = group_for_scan(wscanned / wtests);
       stat_windows++;
       trace_mark = level_trace.size();
       s = e;
@@ -2312,7 +2324,7 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
     if (value < 1 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.window_mem_mb = value;
   } else if (k == "group") {
-    if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;
+    if (value != 0 && !pow2_in(value, 4, 64)) return PLL_E_INVAL;
     g_tune.group = (int)value;
   } else if (k == "xgroup") {
     if (!pow2_in(value, 4, 64)) return PLL_E_INVAL;

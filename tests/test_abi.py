@@ -45,6 +45,8 @@ def test_strerror_and_tuning():
         binding.set_tuning("window", 0)
     with pytest.raises(binding.PllError):
         binding.set_tuning("group", 12)
+    binding.set_tuning("group", 0)  # chosen per window
+    assert binding.get_tuning("group") == 0
     with pytest.raises(binding.PllError):
         binding.set_tuning("nope", 1)
     for key, good, bad in [("xgroup", 32, 24), ("window_work", 0, -1), ("window_mem_mb", 64, 0),

@@ -320,3 +320,18 @@ def test_landmark_rows_without_bit_parallel(landmarks, name, order_fn):
         assert gx.stats()["bp_direct"] == 0
     elif name == "degree":
         assert gx.stats()["bp_direct"] > 0
+
+
+def test_adaptive_test_group_on_long_labels():
+    # t_bp = 0 under a random order gives labels long enough (hundreds of
+    # entries) that the per-window choice of lanes per prune test moves
+    # past 4; labels stay the oracle's
+    _require_gpu()
+    g = gen.rmat_graph(11, seed=6)
+    order = gen.random_order(g.n, 5)
+    ox = oracle.build(g.row_ptr, g.col, order, 0)
+    with Tuned(group=0, window_work=100000, landmarks=0):
+        gx = binding.build(g.row_ptr, g.col, order, 0)
+    st = gx.stats()
+    assert st["windows"] > 4 and st["label_scanned"] > 32 * st["normal_tests"]
+    assert_same_index(gx, ox, "adaptive group")
