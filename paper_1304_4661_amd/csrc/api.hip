@@ -774,8 +774,6 @@ struct Builder {
         stat_level_launches++;
       }
       check(hipMemcpyAsync(&h, D.ctl.p, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
-      check(hipMemcpyAsync(&D.mirror.p->top, D.own->top.p, sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, st));
       check(hipStreamSynchronize(st));
       for (int i = 0; !evs.empty() && i < d - d0; i++) {
         float ms = 0.f;
@@ -957,6 +955,10 @@ struct Builder {
       int64_t wtests = 0, wscanned = 0;
       for (int k = 0; k < nsides; k++) {
         check(launch_win_commit(w[k], sides[k].own->view(), ncand[k], st));
+        // the pool top only moves in commits: read back once per window (the
+        // next window's first synchronisation completes the copy)
+        check(hipMemcpyAsync(&sides[k].mirror.p->top, sides[k].own->top.p,
+                             sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
         const LevelCtl &h = sides[k].mirror.p->ctl;
         entries_bound[k] += ncand[k];
         stat_visited += (int64_t)h.visited;

@@ -94,6 +94,35 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const int64_t *in, 
   }
 }
 
+// Whole scan in one block for short inputs (a few tiles, walked in order
+// with a running carry): one launch instead of three.
+constexpr int64_t kScanSmallTiles = 4;
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_small(const int64_t *in, int64_t *out,
+                                                             int64_t n) {
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += kScanTile) {
+    int64_t v[kScanItems];
+    int64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+      v[k] = i < n ? in[i] : 0;
+      acc += v[k];
+    }
+    int64_t tot;
+    int64_t pre = block_excl_scan<kScanThreads>(acc, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+      const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+      if (i < n) out[i] = pre;
+      if (i == n - 1) out[n] = pre + v[k];
+      pre += v[k];
+    }
+    carry += tot;
+  }
+}
+
 // Device-side argument checks for inputs given as device pointers: CSR
 // offsets non-decreasing from 0, neighbours inside the vertex's own graph
 // and not the vertex itself, and each graph's order a permutation of its
@@ -361,6 +390,10 @@ hipError_t launch_exclusive_scan(const int64_t *in, int64_t *out, int64_t n, int
     return hipMemsetAsync(out, 0, sizeof(int64_t), st);
   }
   int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (nb <= kScanSmallTiles) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScanThreads), 0, st, in, out, n);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, n, tmp);
   hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(kScanThreads), 0, st, tmp, nb);
   hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, in, out, n,
