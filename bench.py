@@ -71,18 +71,21 @@ def file_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def level_kernel_bytes(st, t_bp):
+def level_kernel_bytes(st, t_bp, sides=1):
     """Algorithmic bytes of the pruned-phase prune-test kernel (k_win_test),
     summed over all its launches in one build (per-unit figures of the byte
     model in DESIGN.md):
-      per level entry (root slot, vertex): 8 B entry + t_bp B distance row,
+      per level entry (root slot, vertex) past level 0: 8 B entry + t_bp B
+        distance row (the roots themselves are labeled by the window's init
+        kernel and never reach this kernel; a digraph's two search
+        directions each label every root),
       per (S^{-1}, S^{0}) slot pair read by a set check: 32 B (root's and
         vertex's pair),
       per normal-label test: 12 B label offset and length, plus 5 B (hub +
         distance) per label entry scanned,
       per candidate label: 18 B (list entry 9 B, window distance 1 B, mask
         word 8 B)."""
-    return (st["visited"] * (8 + t_bp) + 32 * st["bp_checks"] + 12 * st["normal_tests"]
+    return ((st["visited"] - sides * st["roots"]) * (8 + t_bp) + 32 * st["bp_checks"] + 12 * st["normal_tests"]
             + 5 * st["label_scanned"] + 18 * st["candidates"])
 
 
@@ -310,7 +313,7 @@ def main():
     ms_per_step = 1e3 * total / args.steps
 
     st = stats[-1]
-    lvl_bytes = level_kernel_bytes(st, t_bp)
+    lvl_bytes = level_kernel_bytes(st, t_bp, 2 if directed else 1)
     lvl_s = st["level_ns"] * 1e-9
     launches = st["level_launches"]
     achieved = lvl_bytes / lvl_s / 1e9 if lvl_s > 0 else None

@@ -20,9 +20,9 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_level_kernel_byte_model():
-    st = {"visited": 10, "bp_checks": 3, "normal_tests": 4, "label_scanned": 100,
+    st = {"visited": 10, "roots": 3, "bp_checks": 3, "normal_tests": 4, "label_scanned": 100,
           "candidates": 2}
-    assert bench.level_kernel_bytes(st, 50) == 10 * 58 + 32 * 3 + 12 * 4 + 5 * 100 + 18 * 2
+    assert bench.level_kernel_bytes(st, 50) == 7 * 58 + 32 * 3 + 12 * 4 + 5 * 100 + 18 * 2
 
 
 def test_weighted_step_byte_model():
