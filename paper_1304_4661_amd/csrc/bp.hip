@@ -29,7 +29,7 @@ namespace pll {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kUnroll = 4;  // neighbours whose rows a wave reads per round
+constexpr int kUnroll = 8;  // neighbours whose rows a wave reads per round
 
 __global__ void k_bpv_count_items(DGraph g, int chunk, int64_t *cnt) {
   const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
