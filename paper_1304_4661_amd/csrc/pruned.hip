@@ -416,8 +416,16 @@ struct RootRow {
   }
 };
 
+// Groups of 8 or more lanes serve long label scans, which want every wave
+// the CU can hold (measured: R-MAT 18 with t_bp = 0 builds 13% faster at 8
+// waves per SIMD, a few registers spilled); 4-lane groups keep all their
+// registers (short scans, many tests per wave).
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DWindow w,
+constexpr int kTestWavesPerSimd = G >= 8 ? 8 : 1;
+
+template <int G>
+__global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test(DGraph g, DBp bp,
+                                                                         DStore st, DWindow w,
                                                      DFrontier f, int d) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
