@@ -805,7 +805,7 @@ struct Builder {
 
   // Lanes per prune test for an average scan of `len` label entries: short
   // labels keep many tests in flight per wave, long ones split a scan.
-  static int group_for_scan(int64_t len) { return len < 32 ? 4 : len < 64 ? 8 : 16; }
+  static int group_for_scan(int64_t len) { return len < 48 ? 4 : len < 96 ? 8 : 16; }
   int test_group = 4;
 
   void pruned(pll_index *ix) {

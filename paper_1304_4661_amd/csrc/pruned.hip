@@ -230,8 +230,10 @@ __device__ __forceinline__ void swar_word(uint32_t aw, uint32_t bw, uint32_t K1,
   n1 = ((z2[0] >> 15) & 1u) | ((z2[1] >> 14) & 2u) | ((z2[0] >> 29) & 4u) | ((z2[1] >> 28) & 8u);
 }
 
+// per-lane counts stay far below 2^32 within one launch; 32-bit keeps them
+// to one register each (the wave sums are 64-bit)
 struct BpTally {
-  unsigned long long direct = 0, sets = 0, checks = 0;
+  uint32_t direct = 0, sets = 0, checks = 0;
 };
 
 // zk, zu: bp.z[k] and bp.z[u] (read by the caller together with its other
@@ -468,7 +470,7 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test(DGrap
     }
   };
   auto flush = [&](WaveStage<kStage> &sg) { write_out(sg, sg.reserve(&ctl->ccnt)); };
-  unsigned long long c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
+  uint32_t c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
   BpTally tally;
   // the wave steps through the level in lockstep, kPerWave entries at a time
   for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
@@ -494,7 +496,7 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test(DGrap
         pr = label_prunes<G>(st, Tj, s01, s23, lo, llen, d);
         if (gr == 0) {
           c_test++;
-          c_scan += (unsigned long long)llen;
+          c_scan += (uint32_t)llen;
         }
       }
       labeled = !pr && gr == 0;
@@ -557,7 +559,7 @@ struct FrontierFlush {
 // spread over W·n/8 bytes, so the row test goes first and most edges never
 // touch the visited bits.
 __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t *vs, int32_t x,
-                                      int d, unsigned long long &direct) {
+                                      int d, uint32_t &direct) {
   if (rr.direct(vb, x, d + 1)) {
     direct++;
     return false;
@@ -611,7 +613,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
-  unsigned long long c_edge = 0, c_direct = 0;
+  uint32_t c_edge = 0, c_direct = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
     const bool act = c < (int64_t)cend;
@@ -625,7 +627,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       e0 = g.row[u];
       deg = g.row[u + 1] - e0;
       lim = deg < chunk ? deg : chunk;
-      if (gr == 0) c_edge += (unsigned long long)lim;
+      if (gr == 0) c_edge += (uint32_t)lim;
       rr.load(rb, w.s + j);
     }
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
@@ -658,10 +660,10 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
     }
   }
   flush.write_out(stage, block_reserve(stage, &ctl->cnt[d + 1], s_n, &s_base));
-  c_edge = Group<kWave>::sum_reduce(c_edge);
-  c_direct = Group<kWave>::sum_reduce(c_direct);
-  if (lane_id() == 0 && c_edge) atomicAdd(&s_sum[0], c_edge);
-  if (lane_id() == 0 && c_direct) atomicAdd(&s_sum[1], c_direct);
+  const unsigned long long w_edge = Group<kWave>::sum_reduce(c_edge);
+  const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
+  if (lane_id() == 0 && w_edge) atomicAdd(&s_sum[0], w_edge);
+  if (lane_id() == 0 && w_direct) atomicAdd(&s_sum[1], w_direct);
   __syncthreads();
   if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&ctl->edges, s_sum[0]);
   if (threadIdx.x == 1 && s_sum[1]) atomicAdd(&ctl->bp_direct, s_sum[1]);
@@ -684,7 +686,8 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
-  unsigned long long c_edge = 0, c_direct = 0;
+  unsigned long long c_edge = 0;  // the same in every lane (whole-wave tasks)
+  uint32_t c_direct = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
     const int32_t j = f.hslot[tk], u = f.hv[tk], c = f.hchunk[tk];
     const int64_t e0 = g.row[u], e1 = g.row[u + 1];
@@ -706,9 +709,9 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
     }
   }
   if (stage.n) flush(stage);
-  c_direct = Group<kWave>::sum_reduce(c_direct);
+  const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
-  if (lane_id() == 0 && c_direct) atomicAdd(&ctl->bp_direct, c_direct);
+  if (lane_id() == 0 && w_direct) atomicAdd(&ctl->bp_direct, w_direct);
 }
 
 // Landmark rows (see launch_win_landmarks): out[u * 16 + j] = d(root j, u)
