@@ -112,6 +112,29 @@ def edges_of(g):
     return len(g.col) if g.meta.get("directed") else g.m
 
 
+def query_threads():
+    """Host threads for the all-core oracle query rate: the cores this process
+    may use, at most 16 (one GPU's share of a box)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_query_rate_mt(fn, ox, pairs, threads):
+    """Pairs answered per second by the oracle's query function `fn`, with
+    the pairs split over `threads` host threads (the C oracle's queries only
+    read the index, and ctypes releases the GIL during the call)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    parts = [p for p in np.array_split(np.ascontiguousarray(pairs), threads) if len(p)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(lambda p: fn(ox, p), parts))
+    return len(pairs) / (time.perf_counter() - t0)
+
+
 def cpu_baseline(g, order, t_bp, pairs):
     """The oracle as it stands: single thread on a host core, full workload."""
     import oracle
@@ -125,11 +148,14 @@ def cpu_baseline(g, order, t_bp, pairs):
     (oracle.query_directed if directed else oracle.query)(ox, pairs)
     tq = time.perf_counter() - t0
     entries = (len(ox.out_hub) + len(ox.in_hub)) if directed else ox.counters["entries"]
+    nt = query_threads()
+    qmt = oracle_query_rate_mt(oracle.query_directed if directed else oracle.query, ox, pairs, nt)
     return {
         "value": edges_of(g) / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
         "sample": (f"whole step on the same workload: oracle index build ({tb:.2f} s) + "
                    f"{len(pairs)} queries ({tq:.2f} s), one thread"),
         "build_s": tb, "queries_per_s": len(pairs) / tq,
+        "query_threads": nt, "queries_per_s_threads": qmt,
         "entries": entries,
     }
 
@@ -542,11 +568,14 @@ def cpu_baseline_weighted(g, order, pairs, budget_q=200_000):
     oracle.query_weighted(ox, sub)
     tq = time.perf_counter() - t0 if len(sub) else 0.0
     tq_all = tq * len(pairs) / max(len(sub), 1)
+    nt = query_threads()
+    qmt = oracle_query_rate_mt(oracle.query_weighted, ox, sub, nt) if len(sub) else None
     return {
         "value": g.m / (tb + tq_all), "unit": "edges/s", "cores": 1, "kind": "oracle",
         "sample": (f"oracle index build of the whole graph ({tb:.2f} s) + {len(sub)} of the "
                    f"{len(pairs)} queries ({tq:.2f} s, scaled to all), one thread"),
         "build_s": tb, "queries_per_s": len(sub) / tq if tq > 0 else None,
+        "query_threads": nt, "queries_per_s_threads": qmt,
         "entries": ox.counters["entries"],
     }
 
