@@ -135,6 +135,30 @@ def oracle_query_rate_mt(fn, ox, pairs, threads):
     return len(pairs) / (time.perf_counter() - t0)
 
 
+def copy_bandwidth_gbs(dev):
+    """Achievable HBM bandwidth on this GPU: a 1 GiB device-to-device copy
+    (read + write bytes over the copy time, best of 5, HIP events), measured
+    outside the timed region as the reference for the kernels' fractions."""
+    import torch
+
+    a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * a.numel() * 4 / (best * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline(g, order, t_bp, pairs):
     """The oracle as it stands: single thread on a host core, full workload."""
     import oracle
@@ -322,6 +346,7 @@ def main():
               if q > 0 else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
+    copy_gbs = copy_bandwidth_gbs(dev)
 
     build_s, query_ms, stats = [], [], []
     torch.cuda.synchronize()
@@ -354,6 +379,7 @@ def main():
         "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
         "achieved": achieved, "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
         "traffic": traffic,
+        "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if achieved else None,
         "launches": launches, "avg_launch_us": (lvl_s / launches * 1e6) if launches else None,
         "algorithmic_bytes_per_launch": lvl_bytes / launches if launches else None,
         "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
@@ -470,6 +496,7 @@ def bench_weighted(args):
               if q > 0 else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
+    copy_gbs = copy_bandwidth_gbs(dev)
     build_s, query_ms, stats = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -516,6 +543,7 @@ def bench_weighted(args):
             "kernel": "k_ww_step (weighted search step, all roots of a window, one step)",
             "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": achieved,
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+            "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if achieved else None,
             "launches": launches, "avg_launch_us": (lvl_s / launches * 1e6) if launches else None,
             "algorithmic_bytes_per_launch": step_bytes / launches if launches else None,
             "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
