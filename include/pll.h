@@ -358,6 +358,14 @@ enum {
                             distances through 16 exact landmark hubs already
                             prune the vertex at the new distance */
   PLL_STAT_LAND_CHECKS,  /* weighted builds: relaxations checked that way */
+  PLL_STAT_EARLIER_ROOT, /* unweighted builds: adjacency entries that lead to
+                            a vertex ranked before the window: an earlier root
+                            (or bit-parallel vertex), whose committed labels
+                            already give its exact distance from every later
+                            root (Section 4.2), so its test would prune it; it
+                            is left unvisited without one (counted per edge;
+                            weighted builds leave this to the landmark bound,
+                            which already stops these relaxations) */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);

@@ -490,7 +490,7 @@ struct Builder {
   int64_t stat_levels = 0, stat_bp_visited = 0, stat_visited = 0, stat_cand = 0,
           stat_windows = 0, stat_retries = 0, stat_roots = 0, stat_tests = 0, stat_scanned = 0,
           stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0,
-          stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0;
+          stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0, stat_earlier = 0;
   // with the "profile" knob: one row per level, kTraceCols values each
   std::vector<int64_t> level_trace;
   size_t trace_mark = 0;
@@ -967,6 +967,7 @@ struct Builder {
         stat_edges += (int64_t)h.edges;
         stat_hedges += (int64_t)h.hedges;
         stat_bp_direct += (int64_t)h.bp_direct;
+        stat_earlier += (int64_t)h.earlier;
         stat_bp_sets += (int64_t)h.bp_sets;
         stat_bp_checks += (int64_t)h.bp_checks;
         stat_cand += ncand[k];
@@ -1641,6 +1642,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   S[PLL_STAT_BP_DIRECT] = b.stat_bp_direct;
   S[PLL_STAT_BP_SETS] = b.stat_bp_sets;
   S[PLL_STAT_BP_CHECKS] = b.stat_bp_checks;
+  S[PLL_STAT_EARLIER_ROOT] = b.stat_earlier;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }

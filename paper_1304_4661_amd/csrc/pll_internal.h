@@ -251,6 +251,7 @@ struct LevelCtl {
   alignas(kCtrLine) unsigned long long bp_direct;  // reached neighbours pruned by distances alone
   alignas(kCtrLine) unsigned long long bp_sets;    // entries whose test read slot sets
   alignas(kCtrLine) unsigned long long bp_checks;  // slot-set pairs read
+  alignas(kCtrLine) unsigned long long earlier;    // neighbours ranked before the window
   alignas(kCtrLine) int32_t flags;
   int32_t pad;
 };

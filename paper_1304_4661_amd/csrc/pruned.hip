@@ -558,8 +558,18 @@ struct FrontierFlush {
 // bytes per vertex) mostly stay in cache while a root's visited bits are
 // spread over W·n/8 bytes, so the row test goes first and most edges never
 // touch the visited bits.
+//
+// A neighbour ranked before the window (x < s) was a root itself, or a
+// bit-parallel root or neighbour: the committed labels already give its exact
+// distance from every later root (Section 4.2; Section 5.3 for the
+// bit-parallel ones), so the test at any level would prune it.  It is left
+// unvisited before any memory is read (counted in `earlier`).
 __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t *vs, int32_t x,
-                                      int d, uint32_t &direct) {
+                                      int d, int32_t s, uint32_t &direct, uint32_t &earlier) {
+  if (x < s) {
+    earlier++;
+    return false;
+  }
   if (rr.direct(vb, x, d + 1)) {
     direct++;
     return false;
@@ -577,14 +587,14 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
   __shared__ int32_t s_n[kWavesPerBlock];
-  __shared__ unsigned long long s_base, s_sum[2];
+  __shared__ unsigned long long s_base, s_sum[3];
   __shared__ bool s_go;
   LevelCtl *ctl = f.ctl;
   const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
   const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
   // one thread decides for the block (the flags may change meanwhile)
-  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_go = !(cend <= cbeg || (ctl->flags & kOverflowFlags));
   __syncthreads();
   if (!s_go) return;
@@ -613,7 +623,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
-  uint32_t c_edge = 0, c_direct = 0;
+  uint32_t c_edge = 0, c_direct = 0, c_earlier = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
     const bool act = c < (int64_t)cend;
@@ -638,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       int32_t x = 0;
       if (idx < lim) {
         x = g.col[e0 + idx];
-        claimed = reach(vb, rr, vs, x, d, c_direct);
+        claimed = reach(vb, rr, vs, x, d, w.s, c_direct, c_earlier);
       }
       stage.push(claimed, j, x, flush, u);
     }
@@ -662,11 +672,14 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   flush.write_out(stage, block_reserve(stage, &ctl->cnt[d + 1], s_n, &s_base));
   const unsigned long long w_edge = Group<kWave>::sum_reduce(c_edge);
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
+  const unsigned long long w_earlier = Group<kWave>::sum_reduce(c_earlier);
   if (lane_id() == 0 && w_edge) atomicAdd(&s_sum[0], w_edge);
   if (lane_id() == 0 && w_direct) atomicAdd(&s_sum[1], w_direct);
+  if (lane_id() == 0 && w_earlier) atomicAdd(&s_sum[2], w_earlier);
   __syncthreads();
   if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&ctl->edges, s_sum[0]);
   if (threadIdx.x == 1 && s_sum[1]) atomicAdd(&ctl->bp_direct, s_sum[1]);
+  if (threadIdx.x == 2 && s_sum[2]) atomicAdd(&ctl->earlier, s_sum[2]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
@@ -687,7 +700,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
   unsigned long long c_edge = 0;  // the same in every lane (whole-wave tasks)
-  uint32_t c_direct = 0;
+  uint32_t c_direct = 0, c_earlier = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
     const int32_t j = f.hslot[tk], u = f.hv[tk], c = f.hchunk[tk];
     const int64_t e0 = g.row[u], e1 = g.row[u + 1];
@@ -703,15 +716,17 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
       int32_t x = 0;
       if (e < b) {
         x = g.col[e];
-        claimed = reach(vb, rr, vs, x, d, c_direct);
+        claimed = reach(vb, rr, vs, x, d, w.s, c_direct, c_earlier);
       }
       stage.push(claimed, j, x, flush, u);
     }
   }
   if (stage.n) flush(stage);
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
+  const unsigned long long w_earlier = Group<kWave>::sum_reduce(c_earlier);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
   if (lane_id() == 0 && w_direct) atomicAdd(&ctl->bp_direct, w_direct);
+  if (lane_id() == 0 && w_earlier) atomicAdd(&ctl->earlier, w_earlier);
 }
 
 // Landmark rows (see launch_win_landmarks): out[u * 16 + j] = d(root j, u)

@@ -335,3 +335,20 @@ def test_adaptive_test_group_on_long_labels():
     st = gx.stats()
     assert st["windows"] > 4 and st["label_scanned"] > 32 * st["normal_tests"]
     assert_same_index(gx, ox, "adaptive group")
+
+
+@pytest.mark.parametrize("t_bp", [0, 16])
+def test_earlier_roots_skipped_at_expansion(t_bp):
+    # neighbours ranked before the window are left unvisited (their labels
+    # already answer exactly); later windows see many such edges, and the
+    # labels stay the oracle's
+    _require_gpu()
+    g = gen.rmat_graph(12, seed=8)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    with Tuned(window_work=50000):
+        gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    st = gx.stats()
+    assert st["windows"] > 3 and st["earlier_root"] > 0
+    assert_same_index(gx, ox, f"t_bp={t_bp}")
+    gx.close()
