@@ -399,10 +399,16 @@ const char *pll_strerror(int code);
  *   while others run on the GPU are admitted as slots free up and run
  *   concurrently with them.  Every request gets exactly the answers
  *   pll_query would give it alone.
+ *   On a weighted index (pll_build_weighted) the answers are pll_query_
+ *   weighted's 32-bit distances.
  * pll_server_submit: queue q (1..slot_pairs) pairs from host memory; the
  *   answers go to out[q] (host).  The caller keeps pairs and out alive until
  *   the request is done.  *ticket identifies the request.  Ids are checked
- *   on submission (PLL_E_INVAL).
+ *   on submission (PLL_E_INVAL).  PLL_E_UNSUPPORTED on a server of a
+ *   weighted index.
+ * pll_server_submit_weighted: the same for a server of a weighted index,
+ *   answers as uint32 (PLL_WINF = unreachable); PLL_E_UNSUPPORTED on a
+ *   server of an unweighted index.
  * pll_server_done: 1 if the request is answered (optionally waiting), 0 if
  *   not yet; *latency_us = answer time - submission time.
  * pll_server_stop: answer everything queued, stop the worker, free the
@@ -418,6 +424,8 @@ typedef struct pll_server pll_server;
 int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, pll_server **out);
 int pll_server_submit(pll_server *srv, const int32_t *pairs, int64_t q, uint8_t *out,
                       int64_t *ticket);
+int pll_server_submit_weighted(pll_server *srv, const int32_t *pairs, int64_t q, uint32_t *out,
+                               int64_t *ticket);
 int pll_server_done(pll_server *srv, int64_t ticket, int32_t wait, double *latency_us);
 int pll_server_stop(pll_server *srv, int64_t *stats, int32_t nstats);
 int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max_batch,

@@ -35,7 +35,8 @@ EXPORTED = [
     "pll_set_tuning", "pll_get_tuning", "pll_server_start", "pll_server_submit",
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
-    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents", "pll_export_weighted_parents",
+    "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents",
+    "pll_export_weighted_parents", "pll_server_submit_weighted",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -111,6 +112,8 @@ def _lib():
         lib.pll_server_start.restype = C.c_int
         lib.pll_server_submit.argtypes = [P, P, C.c_int64, P, C.POINTER(C.c_int64)]
         lib.pll_server_submit.restype = C.c_int
+        lib.pll_server_submit_weighted.argtypes = [P, P, C.c_int64, P, C.POINTER(C.c_int64)]
+        lib.pll_server_submit_weighted.restype = C.c_int
         lib.pll_server_done.argtypes = [P, C.c_int64, C.c_int32, C.POINTER(C.c_double)]
         lib.pll_server_done.restype = C.c_int
         lib.pll_server_stop.argtypes = [P, P, C.c_int32]
@@ -180,8 +183,9 @@ def use_torch_allocator(enable: bool = True):
 class Index:
     """A device-resident index made by :func:`build`."""
 
-    def __init__(self, handle: C.c_void_p):
+    def __init__(self, handle: C.c_void_p, weighted: bool = False):
         self._h = handle
+        self.weighted = weighted  # made by build_weighted (32-bit distances)
 
     @property
     def handle(self):
@@ -505,7 +509,7 @@ def build_weighted(row_ptr, col, wgt, order, directed: bool = False, plain: bool
         args = [_ptr(row_ptr), _ptr(col), _ptr(wgt), _ptr(order)]
     s = None if stream is None else C.c_void_p(stream.cuda_stream)
     _check(_lib().pll_build_weighted(n, *args, flags, s, C.byref(h)), "build_weighted")
-    return Index(h)
+    return Index(h, weighted=True)
 
 
 class Server:
@@ -521,11 +525,17 @@ class Server:
         self._keep = {}
 
     def submit(self, pairs) -> int:
+        """Queue pairs; answers are uint8 (uint32 on a weighted index)."""
         pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
-        out = np.zeros(len(pairs), np.uint8)
         t = C.c_int64()
-        _check(_lib().pll_server_submit(self._h, _ptr(pairs), len(pairs), _ptr(out), C.byref(t)),
-               "server_submit")
+        if self.index.weighted:
+            out = np.zeros(len(pairs), np.uint32)
+            _check(_lib().pll_server_submit_weighted(self._h, _ptr(pairs), len(pairs), _ptr(out),
+                                                     C.byref(t)), "server_submit_weighted")
+        else:
+            out = np.zeros(len(pairs), np.uint8)
+            _check(_lib().pll_server_submit(self._h, _ptr(pairs), len(pairs), _ptr(out),
+                                            C.byref(t)), "server_submit")
         self._keep[t.value] = (pairs, out)
         return t.value
 

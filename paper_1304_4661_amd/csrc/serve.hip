@@ -1,5 +1,6 @@
 // Serving over a device-resident index: continuous batching of distance
-// queries (Sections 3.3 and 5.3 answered by the library's query kernel).
+// queries (Sections 3.3 and 5.3 answered by the library's query kernel; on a
+// weighted index, Section 7's, with 32-bit answers).
 //
 // A worker thread owns `nslots` slots, each a HIP stream with pinned host
 // staging and device buffers for up to `slot_pairs` pairs.  Requests queue
@@ -46,7 +47,7 @@ int64_t now_ns() {
 
 struct Req {
   const int32_t *pairs = nullptr;
-  uint8_t *out = nullptr;
+  void *out = nullptr;  // es bytes per answer (the server's answer size)
   int64_t q = 0;
   int64_t t_arrive = 0;             // ns, steady clock
   std::atomic<int64_t> t_done{0};   // 0 until answered
@@ -56,9 +57,9 @@ struct Slot {
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   int32_t *hp = nullptr;   // pinned pairs
-  uint8_t *ho = nullptr;   // pinned answers
+  uint8_t *ho = nullptr;   // pinned answers (es bytes each)
   int32_t *dp = nullptr;   // device pairs
-  uint8_t *dout = nullptr; // device answers
+  uint8_t *dout = nullptr; // device answers (es bytes each)
   std::vector<Req *> reqs;
   int64_t n = 0;
   bool busy = false;
@@ -70,6 +71,8 @@ struct pll_server {
   const pll_index *idx = nullptr;
   DIndex view{};
   int32_t n = 0;
+  bool weighted = false;  // 32-bit answers of a weighted index
+  int es = 1;             // bytes per answer
   int qgroup = 64;
   bool coalesce = true;  // false: one request per launch (the plain form)
   int64_t slot_pairs = 0;
@@ -112,9 +115,12 @@ bool dispatch(pll_server *sv, Slot &sl) {
   hipError_t e = hipMemcpyAsync(sl.dp, sl.hp, (size_t)sl.n * 2 * sizeof(int32_t),
                                 hipMemcpyHostToDevice, sl.s);
   if (e == hipSuccess)
-    e = launch_query(sv->view, sl.dp, sl.n, sl.dout, nullptr, false, sv->qgroup, sl.s);
+    e = sv->weighted ? launch_wquery(sv->view, sl.dp, sl.n, reinterpret_cast<uint32_t *>(sl.dout),
+                                     nullptr, false, sv->qgroup, sl.s)
+                     : launch_query(sv->view, sl.dp, sl.n, sl.dout, nullptr, false, sv->qgroup,
+                                    sl.s);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(sl.ho, sl.dout, (size_t)sl.n, hipMemcpyDeviceToHost, sl.s);
+    e = hipMemcpyAsync(sl.ho, sl.dout, (size_t)sl.n * sv->es, hipMemcpyDeviceToHost, sl.s);
   if (e == hipSuccess) e = hipEventRecord(sl.ev, sl.s);
   if (e != hipSuccess) sv->err = PLL_E_DEVICE;
   sl.busy = true;
@@ -131,7 +137,7 @@ bool complete(pll_server *sv, Slot &sl) {
   const int64_t t = now_ns();
   int64_t off = 0;
   for (Req *r : sl.reqs) {
-    std::copy(sl.ho + off, sl.ho + off + r->q, r->out);
+    std::copy(sl.ho + off * sv->es, sl.ho + (off + r->q) * sv->es, static_cast<uint8_t *>(r->out));
     off += r->q;
     r->t_done.store(t, std::memory_order_release);
   }
@@ -182,10 +188,11 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
   *out = nullptr;
   if (!idx || nslots < 1 || nslots > 32 || slot_pairs < 1 || slot_pairs > (1ll << 30))
     return PLL_E_INVAL;
-  if (index_weighted(idx)) return PLL_E_UNSUPPORTED;  // 8-bit answers only
   pll_server *sv = new (std::nothrow) pll_server();
   if (!sv) return PLL_E_NOMEM;
   sv->idx = idx;
+  sv->weighted = index_weighted(idx);
+  sv->es = sv->weighted ? 4 : 1;
   sv->view = index_view(idx);
   sv->n = index_n(idx);
   sv->qgroup = (int)query_group_size();
@@ -197,11 +204,11 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
               hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess &&
               hipHostMalloc((void **)&sl.hp, (size_t)slot_pairs * 2 * sizeof(int32_t),
                             hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc((void **)&sl.ho, (size_t)slot_pairs, hipHostMallocDefault) ==
+              hipHostMalloc((void **)&sl.ho, (size_t)slot_pairs * sv->es, hipHostMallocDefault) ==
                   hipSuccess &&
               hipMalloc((void **)&sl.dp, (size_t)slot_pairs * 2 * sizeof(int32_t)) ==
                   hipSuccess &&
-              hipMalloc((void **)&sl.dout, (size_t)slot_pairs) == hipSuccess;
+              hipMalloc((void **)&sl.dout, (size_t)slot_pairs * sv->es) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       sv->release();
@@ -221,7 +228,7 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
 }
 
 // Internal: submit with an explicit arrival time (ns, steady clock).
-static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, uint8_t *out,
+static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
                      int64_t t_arrive, int64_t *ticket) {
   if (!sv || q < 1 || q > sv->slot_pairs || !pairs || !out) return PLL_E_INVAL;
   for (int64_t i = 0; i < 2 * q; i++)
@@ -242,6 +249,13 @@ static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, uint8_t *o
 
 int pll_server_submit(pll_server *sv, const int32_t *pairs, int64_t q, uint8_t *out,
                       int64_t *ticket) {
+  if (sv && sv->weighted) return PLL_E_UNSUPPORTED;  // 32-bit answers: the call below
+  return submit_at(sv, pairs, q, out, now_ns(), ticket);
+}
+
+int pll_server_submit_weighted(pll_server *sv, const int32_t *pairs, int64_t q, uint32_t *out,
+                               int64_t *ticket) {
+  if (sv && !sv->weighted) return PLL_E_UNSUPPORTED;  // 8-bit answers: the call above
   return submit_at(sv, pairs, q, out, now_ns(), ticket);
 }
 
@@ -310,7 +324,8 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
   }
   std::vector<int32_t> pairs((size_t)off[nreq] * 2);
   for (auto &p : pairs) p = (int32_t)(next() % (uint64_t)n);
-  std::vector<uint8_t> outb((size_t)off[nreq]);
+  // answers: 1 byte each (4 on a weighted index)
+  std::vector<uint8_t> outb((size_t)off[nreq] * (index_weighted(idx) ? 4 : 1));
   pll_server *sv = nullptr;
   int rc = pll_server_start(idx, nslots, slot_pairs, &sv);
   if (rc != PLL_OK) return rc;
@@ -319,7 +334,8 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
     const int64_t due = t0 + (int64_t)(at[k] * 1e9);
     while (now_ns() < due) {
     }
-    rc = submit_at(sv, pairs.data() + 2 * off[k], size[k], outb.data() + off[k], due, nullptr);
+    rc = submit_at(sv, pairs.data() + 2 * off[k], size[k], outb.data() + off[k] * sv->es, due,
+                   nullptr);
     if (rc != PLL_OK) break;
   }
   std::vector<double> lat((size_t)nreq);

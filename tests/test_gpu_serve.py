@@ -57,3 +57,57 @@ def test_serve_bench_runs():
     assert sat["pairs_per_s"] > 0 and sat["launches"] >= 1
     low = binding.serve_bench(gx, sat["requests_per_s"] * 0.25, 3000, max_batch=4096, seed=8)
     assert low["p50_us"] > 0 and low["p99_us"] >= low["p50_us"]
+
+
+@pytest.mark.parametrize("name", ["ba2000w", "digraph"])
+def test_weighted_alone_vs_mix(name):
+    # a server of a weighted index answers with 32-bit distances, each
+    # request the same in a busy mix as alone and as the oracle
+    import ctypes as C
+
+    import torch
+    assert torch.cuda.is_available()
+    directed = name == "digraph"
+    if directed:
+        g = gen.uniform_weights(gen.rmat_digraph(10, 8, seed=5), 1, 50, 6)
+        order = gen.degree_order_directed(g)
+    else:
+        g, order, _, _ = gen.config_graph(name)
+    gx = binding.build_weighted(g.row_ptr, g.col, g.w, order, directed=directed)
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order, directed=directed)
+    rng = np.random.Generator(np.random.PCG64(43))
+    reqs = [rng.integers(0, g.n, (int(np.exp(rng.uniform(0, np.log(2000)))), 2)).astype(np.int32)
+            for _ in range(200)]
+    srv = binding.Server(gx, nslots=3, slot_pairs=2048)
+    tickets = [srv.submit(p) for p in reqs]
+    for k, p in enumerate(reqs):
+        ans, us = srv.result(tickets[k])
+        assert ans.dtype == np.uint32 and us > 0
+        assert np.array_equal(ans, gx.query_weighted(p)), f"request {k} differs from alone"
+        assert np.array_equal(ans, oracle.query_weighted(ox, p)), f"request {k} differs from oracle"
+    # the 8-bit submission refuses a weighted server, the 32-bit one an
+    # unweighted server
+    lib = binding.library()
+    one = np.zeros(2, np.int32)
+    o8 = np.zeros(1, np.uint8)
+    t = C.c_int64()
+    assert lib.pll_server_submit(srv._h, one.ctypes.data, 1, o8.ctypes.data,
+                                 C.byref(t)) == binding.E_UNSUPPORTED
+    st = srv.stop()
+    assert st["pairs"] == sum(len(p) for p in reqs)
+    gb = gen.ba_graph(300, 3, 1)
+    gu = binding.build(gb.row_ptr, gb.col, gen.degree_order(gb), 4)
+    su = binding.Server(gu, nslots=1, slot_pairs=16)
+    o32 = np.zeros(1, np.uint32)
+    assert lib.pll_server_submit_weighted(su._h, one.ctypes.data, 1, o32.ctypes.data,
+                                          C.byref(t)) == binding.E_UNSUPPORTED
+    su.stop()
+
+
+def test_weighted_serve_bench_runs():
+    import torch
+    assert torch.cuda.is_available()
+    g, order, _, _ = gen.config_graph("ba2000w")
+    gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
+    sat = binding.serve_bench(gx, 0.0, 2000, max_batch=4096, seed=9)
+    assert sat["pairs_per_s"] > 0 and sat["launches"] >= 1

@@ -203,8 +203,6 @@ def test_weighted_device_pointers_and_errors():
         gx.query(pairs)
     with pytest.raises(binding.PllError):
         gx.export()
-    with pytest.raises(binding.PllError):
-        binding.Server(gx)
     gu = binding.build(g.row_ptr, g.col, order, 0)
     with pytest.raises(binding.PllError):
         gu.query_weighted(pairs)
