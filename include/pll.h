@@ -44,7 +44,7 @@ enum {
   PLL_E_NOMEM = -2,       /* host or device allocation failed */
   PLL_E_RANGE = -3,       /* a stored distance would reach 255 */
   PLL_E_DEVICE = -4,      /* a HIP call failed */
-  PLL_E_UNSUPPORTED = -5  /* valid request this build does not handle */
+  PLL_E_UNSUPPORTED = -5  /* valid request the library does not handle */
 };
 
 #define PLL_INF 255u

@@ -57,7 +57,7 @@ def _lib():
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1304_4661_amd.build_lib first")
         lib = C.CDLL(LIB_PATH)
         P = C.c_void_p
         lib.pll_build.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, P, C.POINTER(C.c_void_p)]

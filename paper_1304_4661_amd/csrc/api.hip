@@ -1966,7 +1966,7 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
       check(hipStreamSynchronize(st));
       return herr ? PLL_E_INVAL : PLL_OK;
     }
-    // fold this call's verdict into the index's sticky error
+    // fold this call's outcome into the index's sticky error
     check(launch_or_flag(err, idx->err.p, st));
     check(hipFreeAsync(err, st));
     return PLL_OK;
