@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PLL index build s & edges/s; queries/s + p99 latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_test_traffic_rmat18.json")
+XTRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_expand_traffic_rmat18.json")
 LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip")
 WTRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ww_step_traffic_rmat18w.json")
 WSTEP_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "weighted.hip")
@@ -87,6 +88,21 @@ def level_kernel_bytes(st, t_bp, sides=1):
         word 8 B)."""
     return ((st["visited"] - sides * st["roots"]) * (8 + t_bp) + 32 * st["bp_checks"] + 12 * st["normal_tests"]
             + 5 * st["label_scanned"] + 18 * st["candidates"])
+
+
+def expand_kernel_bytes(st, t_bp):
+    """Algorithmic bytes of the pruned-phase expansion kernel (k_win_expand),
+    summed over its launches in one build:
+      per candidate expanded: 8 B list entry + 8 B row offsets + t_bp B root
+        distance row,
+      per adjacency entry expanded inline: 4 B neighbour; unless the
+        neighbour is ranked before the window, + t_bp B its distance row;
+        unless that row prunes it too, + 4 B visited word,
+      per neighbour claimed: 8 B next-level list entry."""
+    e = st["edges"]
+    rest = e - st["expand_earlier"]
+    return (st["candidates"] * (16 + t_bp) + 4 * e + rest * t_bp
+            + 4 * (rest - st["expand_direct"]) + 8 * st["expand_claims"])
 
 
 def weighted_step_bytes(st):
@@ -380,7 +396,7 @@ def main():
             tr = json.load(f)
         if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
             traffic = tr.get("bytes_per_launch")
-    roofline = {
+    roofline_test = {
         "kernel": "k_win_test (pruned-BFS prune tests, all roots of a window, one level)",
         "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
         "achieved": achieved, "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
@@ -390,6 +406,32 @@ def main():
         "algorithmic_bytes_per_launch": lvl_bytes / launches if launches else None,
         "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
     }
+    # the expansion kernel: one launch per level, like the test kernel
+    x_bytes = expand_kernel_bytes(st, t_bp)
+    x_s = st["expand_ns"] * 1e-9
+    x_ach = x_bytes / x_s / 1e9 if x_s > 0 else None
+    x_traffic = None
+    if os.path.exists(XTRAFFIC_FILE):
+        with open(XTRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
+            x_traffic = tr.get("bytes_per_launch")
+    roofline_expand = {
+        "kernel": "k_win_expand (pruned-BFS expansion, all roots of a window, one level)",
+        "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+        "achieved": x_ach, "frac": (x_ach / HBM_PEAK_GBS) if x_ach else None,
+        "traffic": x_traffic,
+        "copy_gbs": copy_gbs, "frac_of_copy": (x_ach / copy_gbs) if x_ach else None,
+        "launches": launches, "avg_launch_us": (x_s / launches * 1e6) if launches else None,
+        "algorithmic_bytes_per_launch": x_bytes / launches if launches else None,
+        "share_of_build": x_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
+    }
+    # "roofline" is the kernel with the larger share of the build; the
+    # other one is reported beside it
+    if (roofline_expand["share_of_build"] or 0) > (roofline_test["share_of_build"] or 0):
+        roofline, other = roofline_expand, ("roofline_prune_test", roofline_test)
+    else:
+        roofline, other = roofline_test, ("roofline_expand", roofline_expand)
 
     out = {
         "metric": METRIC,
@@ -412,6 +454,7 @@ def main():
         "counters": {k: int(v) for k, v in st.items()},
         "phases_s": {"bit_parallel": st["bp_ns"] * 1e-9, "pruned": st["pruned_ns"] * 1e-9},
         "roofline": roofline,
+        other[0]: other[1],
     }
 
     if not args.no_extras:

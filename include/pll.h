@@ -366,6 +366,12 @@ enum {
                             is left unvisited without one (counted per edge;
                             weighted builds leave this to the landmark bound,
                             which already stops these relaxations) */
+  PLL_STAT_EXPAND_NS,    /* summed duration of the expansion kernel
+                            (k_win_expand, lists up to "chunk" entries) from
+                            HIP events, ns; only with the "profile" knob */
+  PLL_STAT_EXPAND_DIRECT,  /* PLL_STAT_BP_DIRECT's share of that kernel */
+  PLL_STAT_EXPAND_EARLIER, /* PLL_STAT_EARLIER_ROOT's share of that kernel */
+  PLL_STAT_EXPAND_CLAIMS,  /* neighbours that kernel claimed for the next level */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);

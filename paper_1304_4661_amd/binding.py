@@ -26,7 +26,7 @@ STAT_NAMES = [
     "retries", "bp_visited", "levels", "index_bytes", "build_ns", "bp_ns", "pruned_ns",
     "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
     "bp_direct", "bp_sets", "bp_checks", "improved", "touched", "filtered", "land_checks",
-    "earlier_root",
+    "earlier_root", "expand_ns", "expand_direct", "expand_earlier", "expand_claims",
 ]
 
 EXPORTED = [

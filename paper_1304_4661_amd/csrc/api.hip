@@ -490,7 +490,8 @@ struct Builder {
   int64_t stat_levels = 0, stat_bp_visited = 0, stat_visited = 0, stat_cand = 0,
           stat_windows = 0, stat_retries = 0, stat_roots = 0, stat_tests = 0, stat_scanned = 0,
           stat_edges = 0, stat_hedges = 0, stat_level_launches = 0, stat_level_ns = 0,
-          stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0, stat_earlier = 0;
+          stat_bp_direct = 0, stat_bp_sets = 0, stat_bp_checks = 0, stat_earlier = 0,
+          stat_expand_ns = 0, stat_x_direct = 0, stat_x_earlier = 0, stat_x_claims = 0;
   // with the "profile" knob: one row per level, kTraceCols values each
   std::vector<int64_t> level_trace;
   size_t trace_mark = 0;
@@ -766,19 +767,22 @@ struct Builder {
       const int d0 = d;
       const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
       for (; d < upto; d++) {
-        hipEvent_t e0 = evs.empty() ? nullptr : evs[2 * (d - d0)];
-        hipEvent_t e1 = evs.empty() ? nullptr : evs[2 * (d - d0) + 1];
+        hipEvent_t e0 = evs.empty() ? nullptr : evs[3 * (d - d0)];
+        hipEvent_t e1 = evs.empty() ? nullptr : evs[3 * (d - d0) + 1];
+        hipEvent_t e2 = evs.empty() ? nullptr : evs[3 * (d - d0) + 2];
         check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk, st,
-                               e0, e1));
+                               e0, e1, e2));
         stat_levels++;
         stat_level_launches++;
       }
       check(hipMemcpyAsync(&h, D.ctl.p, sizeof(LevelCtl), hipMemcpyDeviceToHost, st));
       check(hipStreamSynchronize(st));
       for (int i = 0; !evs.empty() && i < d - d0; i++) {
-        float ms = 0.f;
-        check(hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]));
+        float ms = 0.f, xms = 0.f;
+        check(hipEventElapsedTime(&ms, evs[3 * i], evs[3 * i + 1]));
+        check(hipEventElapsedTime(&xms, evs[3 * i + 1], evs[3 * i + 2]));
         stat_level_ns += (int64_t)(ms * 1e6);
+        stat_expand_ns += (int64_t)(xms * 1e6);
         const int lv = d0 + i;
         level_trace.insert(level_trace.end(), {window_index, (int64_t)w.s, (int64_t)w.W,
                                                (int64_t)lv, (int64_t)h.cnt[lv], 0,
@@ -857,7 +861,7 @@ struct Builder {
     // optional timing of each level kernel (events on the build stream)
     std::vector<hipEvent_t> evs;
     if (tu.profile) {
-      evs.resize(2 * (size_t)tu.levels_per_sync);
+      evs.resize(3 * (size_t)tu.levels_per_sync);
       for (auto &e : evs) check(hipEventCreate(&e));
     }
     struct EvGuard {
@@ -966,8 +970,11 @@ struct Builder {
         stat_scanned += (int64_t)h.lscanned;
         stat_edges += (int64_t)h.edges;
         stat_hedges += (int64_t)h.hedges;
-        stat_bp_direct += (int64_t)h.bp_direct;
-        stat_earlier += (int64_t)h.earlier;
+        stat_bp_direct += (int64_t)(h.bp_direct + h.hdirect);
+        stat_earlier += (int64_t)(h.earlier + h.hearlier);
+        stat_x_direct += (int64_t)h.bp_direct;
+        stat_x_earlier += (int64_t)h.earlier;
+        stat_x_claims += (int64_t)h.xclaims;
         stat_bp_sets += (int64_t)h.bp_sets;
         stat_bp_checks += (int64_t)h.bp_checks;
         stat_cand += ncand[k];
@@ -1643,6 +1650,10 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   S[PLL_STAT_BP_SETS] = b.stat_bp_sets;
   S[PLL_STAT_BP_CHECKS] = b.stat_bp_checks;
   S[PLL_STAT_EARLIER_ROOT] = b.stat_earlier;
+  S[PLL_STAT_EXPAND_NS] = b.stat_expand_ns;
+  S[PLL_STAT_EXPAND_DIRECT] = b.stat_x_direct;
+  S[PLL_STAT_EXPAND_EARLIER] = b.stat_x_earlier;
+  S[PLL_STAT_EXPAND_CLAIMS] = b.stat_x_claims;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }

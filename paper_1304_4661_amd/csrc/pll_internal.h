@@ -252,6 +252,9 @@ struct LevelCtl {
   alignas(kCtrLine) unsigned long long bp_sets;    // entries whose test read slot sets
   alignas(kCtrLine) unsigned long long bp_checks;  // slot-set pairs read
   alignas(kCtrLine) unsigned long long earlier;    // neighbours ranked before the window
+  alignas(kCtrLine) unsigned long long xclaims;    // neighbours claimed by k_win_expand
+  alignas(kCtrLine) unsigned long long hdirect;    // bp_direct's share of k_win_heavy
+  alignas(kCtrLine) unsigned long long hearlier;   // earlier's share of k_win_heavy
   alignas(kCtrLine) int32_t flags;
   int32_t pad;
 };
@@ -458,9 +461,11 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 // expansion-time prune, root side and reached-vertex side (the bit-parallel
 // rows for an undirected graph with t > 0; landmark rows otherwise, or
 // tpad = 0 for none).
+// ev0 / ev1 / ev2 (optional): recorded before the test kernel, between the
+// test and the expansion kernels, and after the expansion kernel.
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
                             int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1);
+                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2);
 // Landmark rows out uint8[n][kLandmarks] of a window whose searches pruned
 // nothing (W >= kLandmarks): distance from its j-th root to every vertex,
 // 255 if not reached.  Run before the window's commit clears its masks.

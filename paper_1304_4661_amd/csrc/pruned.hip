@@ -587,14 +587,14 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
   __shared__ int32_t s_n[kWavesPerBlock];
-  __shared__ unsigned long long s_base, s_sum[3];
+  __shared__ unsigned long long s_base, s_sum[4];
   __shared__ bool s_go;
   LevelCtl *ctl = f.ctl;
   const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
   const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
   // one thread decides for the block (the flags may change meanwhile)
-  if (threadIdx.x < 3) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x < 4) s_sum[threadIdx.x] = 0;
   if (threadIdx.x == 0) s_go = !(cend <= cbeg || (ctl->flags & kOverflowFlags));
   __syncthreads();
   if (!s_go) return;
@@ -623,7 +623,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
-  uint32_t c_edge = 0, c_direct = 0, c_earlier = 0;
+  uint32_t c_edge = 0, c_direct = 0, c_earlier = 0, c_claim = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
     const bool act = c < (int64_t)cend;
@@ -649,6 +649,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       if (idx < lim) {
         x = g.col[e0 + idx];
         claimed = reach(vb, rr, vs, x, d, w.s, c_direct, c_earlier);
+        c_claim += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush, u);
     }
@@ -673,13 +674,16 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   const unsigned long long w_edge = Group<kWave>::sum_reduce(c_edge);
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
   const unsigned long long w_earlier = Group<kWave>::sum_reduce(c_earlier);
+  const unsigned long long w_claim = Group<kWave>::sum_reduce(c_claim);
   if (lane_id() == 0 && w_edge) atomicAdd(&s_sum[0], w_edge);
   if (lane_id() == 0 && w_direct) atomicAdd(&s_sum[1], w_direct);
   if (lane_id() == 0 && w_earlier) atomicAdd(&s_sum[2], w_earlier);
+  if (lane_id() == 0 && w_claim) atomicAdd(&s_sum[3], w_claim);
   __syncthreads();
   if (threadIdx.x == 0 && s_sum[0]) atomicAdd(&ctl->edges, s_sum[0]);
   if (threadIdx.x == 1 && s_sum[1]) atomicAdd(&ctl->bp_direct, s_sum[1]);
   if (threadIdx.x == 2 && s_sum[2]) atomicAdd(&ctl->earlier, s_sum[2]);
+  if (threadIdx.x == 3 && s_sum[3]) atomicAdd(&ctl->xclaims, s_sum[3]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
@@ -725,8 +729,8 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
   const unsigned long long w_earlier = Group<kWave>::sum_reduce(c_earlier);
   if (lane_id() == 0 && c_edge) atomicAdd(&ctl->hedges, c_edge);
-  if (lane_id() == 0 && w_direct) atomicAdd(&ctl->bp_direct, w_direct);
-  if (lane_id() == 0 && w_earlier) atomicAdd(&ctl->earlier, w_earlier);
+  if (lane_id() == 0 && w_direct) atomicAdd(&ctl->hdirect, w_direct);
+  if (lane_id() == 0 && w_earlier) atomicAdd(&ctl->hearlier, w_earlier);
 }
 
 // Landmark rows (see launch_win_landmarks): out[u * 16 + j] = d(root j, u)
@@ -1013,7 +1017,7 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
                             int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1) {
+                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
   if (ev0) (void)hipEventRecord(ev0, st);
@@ -1032,6 +1036,7 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow 
     case 32: hipLaunchKernelGGL(k_win_expand<32>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
     default: hipLaunchKernelGGL(k_win_expand<64>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
   }
+  if (ev2) (void)hipEventRecord(ev2, st);
   hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk);
   return hipGetLastError();
 }

@@ -30,3 +30,10 @@ def test_weighted_step_byte_model():
           "land_checks": 40, "filtered": 30, "improved": 7}
     assert bench.weighted_step_bytes(st) == (16 * 10 + 12 * 4 + 8 * 100 + 12 * 50 + 32 * 40
                                              - 4 * 30 + 16 * 7)
+
+
+def test_expand_kernel_byte_model():
+    st = {"candidates": 5, "edges": 100, "expand_earlier": 40, "expand_direct": 30,
+          "expand_claims": 20}
+    assert bench.expand_kernel_bytes(st, 50) == (5 * 66 + 4 * 100 + 60 * 50 + 4 * 30
+                                                 + 8 * 20)
