@@ -30,6 +30,7 @@ struct Tuning {
   int64_t wwork = 2000000;  // touched entries aimed at per weighted window
   int64_t pool_keep_mb = 16384;  // freed device memory kept for reuse by later builds
   int landmarks = 1;  // landmark rows for builds without bit-parallel labels
+  int live_adjacency = 1;  // drop neighbours ranked below the window from the expansion's CSR
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
   int levels_per_sync = 4;
@@ -650,6 +651,8 @@ struct Builder {
   // window state.
   struct Side {
     DGraph g;
+    DBuf<int64_t> lrow;  // live adjacency (g points here once compacted)
+    DBuf<int32_t> lcol;
     Store *own = nullptr, *roots = nullptr;
     int64_t htcap = 0, fcap = 0, hcap = 0, ccap = 0;
     DBuf<uint32_t> vis;
@@ -877,7 +880,22 @@ struct Builder {
     int32_t s = 0;
     const bool adaptive = tu.window_work > 0 && wmax > 1;
     int W = adaptive ? std::min(wmax, 256) : wmax;
+    // live adjacency: rebuilt without the neighbours ranked below s each
+    // time s has doubled (the expansion skips them anyway)
+    int32_t live_s = 0;
     while (s < n) {
+      if (!plain && tu.live_adjacency && s >= 1024 && s >= 2 * live_s) {
+        for (int k = 0; k < nsides; k++) {
+          Side &D = sides[k];
+          DBuf<int64_t> nrow((size_t)n + 1), cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
+          DBuf<int32_t> ncol((size_t)std::max<int64_t>(nnz, 1));
+          check(launch_live_adjacency(D.g, s, nrow.p, ncol.p, cnt.p, tmp.p, st));
+          D.lrow = std::move(nrow);
+          D.lcol = std::move(ncol);
+          D.g = DGraph{n, nwords, D.lrow.p, D.lcol.p};
+        }
+        live_s = s;
+      }
       const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
       const int32_t nr = e - s;
       DWindow w[2];
@@ -2350,6 +2368,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "landmarks") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.landmarks = (int)value;
+  } else if (k == "live_adjacency") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.live_adjacency = (int)value;
   } else if (k == "pool_keep_mb") {
     if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.pool_keep_mb = value;
@@ -2396,6 +2417,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "wwork") return g_tune.wwork;
   if (k == "pool_keep_mb") return g_tune.pool_keep_mb;
   if (k == "landmarks") return g_tune.landmarks;
+  if (k == "live_adjacency") return g_tune.live_adjacency;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

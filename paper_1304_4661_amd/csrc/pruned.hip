@@ -1041,6 +1041,52 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow 
   return hipGetLastError();
 }
 
+// Live adjacency: g's rows without the neighbours ranked below s (which
+// the expansion skips anyway, see reach), and empty rows for the vertices
+// below s (never expanded again: they are never visited).  One wave per
+// row; the fill keeps each row's order.
+__global__ void __launch_bounds__(kBlock) k_live_count(DGraph g, int32_t s, int64_t *cnt) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wave; r < g.n; r += nwaves) {
+    int64_t c = 0;
+    if (r >= s)
+      for (int64_t e = g.row[r] + lane_id(); e < g.row[r + 1]; e += kWave) c += g.col[e] >= s;
+    c = (int64_t)Group<kWave>::sum_reduce((unsigned long long)c);
+    if (lane_id() == 0) cnt[r] = c;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_live_fill(DGraph g, int32_t s, const int64_t *nrow,
+                                                      int32_t *ncol) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t r = wave; r < g.n; r += nwaves) {
+    if (r < s) continue;
+    int64_t o = nrow[r];
+    const int64_t b = g.row[r + 1];
+    for (int64_t e0 = g.row[r]; e0 < b; e0 += kWave) {
+      const int64_t e = e0 + lane_id();
+      const int32_t x = e < b ? g.col[e] : -1;
+      const bool keep = x >= s;
+      const uint64_t m = __ballot(keep);
+      if (keep) ncol[o + __popcll(m & lanes_below_mask())] = x;
+      o += __popcll(m);
+    }
+  }
+}
+
+hipError_t launch_live_adjacency(DGraph g, int32_t s, int64_t *nrow, int32_t *ncol, int64_t *cnt,
+                                 int64_t *scan_tmp, hipStream_t st) {
+  if (g.n <= 0) return hipSuccess;
+  const unsigned blocks = grid_for((int64_t)g.n * kWave, kBlock, 8192);
+  hipLaunchKernelGGL(k_live_count, dim3(blocks), dim3(kBlock), 0, st, g, s, cnt);
+  hipError_t e = launch_exclusive_scan(cnt, nrow, (int64_t)g.n, scan_tmp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_live_fill, dim3(blocks), dim3(kBlock), 0, st, g, s, nrow, ncol);
+  return hipGetLastError();
+}
+
 hipError_t launch_win_landmarks(DWindow w, int32_t n, uint8_t *out, hipStream_t st) {
   if (n <= 0 || w.W < kLandmarks) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_win_landmarks, dim3(grid_for((int64_t)n * kLandmarks, kBlock, 8192)),

@@ -52,7 +52,8 @@ def test_strerror_and_tuning():
     for key, good, bad in [("xgroup", 32, 24), ("window_work", 0, -1), ("window_mem_mb", 64, 0),
                            ("list_cap", 100, -1), ("table_cap", 100, -1),
                            ("window", 16384, 16385), ("group", 64, 128),
-                           ("wgroup", 8, 12), ("wwork", 0, -1)]:
+                           ("wgroup", 8, 12), ("wwork", 0, -1),
+                           ("live_adjacency", 0, 2)]:
         old = binding.get_tuning(key)
         binding.set_tuning(key, good)
         assert binding.get_tuning(key) == good

@@ -352,3 +352,28 @@ def test_earlier_roots_skipped_at_expansion(t_bp):
     assert st["windows"] > 3 and st["earlier_root"] > 0
     assert_same_index(gx, ox, f"t_bp={t_bp}")
     gx.close()
+
+
+@pytest.mark.parametrize("live", [0, 1])
+@pytest.mark.parametrize("t_bp", [0, 32])
+def test_live_adjacency(live, t_bp):
+    # the expansion's adjacency is rebuilt without earlier-ranked neighbours
+    # as the windows advance (knob 1) or kept whole (0): same labels, and
+    # the compacted runs expand fewer entries
+    _require_gpu()
+    g = gen.rmat_graph(13, seed=11)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    # fixed windows of 1024 roots: rebuilt at s = 1024, 2048, 4096
+    with Tuned(live_adjacency=live, window=1024, window_work=0):
+        gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    assert_same_index(gx, ox, f"t_bp={t_bp} live={live}")
+    st = gx.stats()
+    gx.close()
+    with Tuned(live_adjacency=1 - live, window=1024, window_work=0):
+        gy = binding.build(g.row_ptr, g.col, order, t_bp)
+    sy = gy.stats()
+    gy.close()
+    assert st["windows"] == sy["windows"] and st["windows"] > 4 and g.n > 4096
+    on, off = (st, sy) if live else (sy, st)
+    assert on["edges"] + on["task_edges"] < off["edges"] + off["task_edges"]
