@@ -465,8 +465,9 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * t_bp = 0, directed, weighted -- keep exact distances from their first 16
  * roots and skip expansions those already prune; the labels do not
  * change).  "live_adjacency" (0/1: each time the window start s has
- * doubled, the expansion's adjacency is rebuilt without the neighbours
- * ranked below s, which it would skip anyway; same labels).  Memory: "pool_keep_mb" (device memory of freed build
+ * doubled, the expansion's adjacency (a weighted build's relaxation
+ * adjacency, weights included) is rebuilt without the neighbours ranked
+ * below s, which would be pruned anyway; same labels).  Memory: "pool_keep_mb" (device memory of freed build
  * scratch and indexes kept for reuse by later builds, MB; reuse on another
  * stream waits for the stream that freed it; lowering the value releases
  * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64),

@@ -1101,6 +1101,9 @@ struct WBuilder {
   // store its root tables come from, and its window state.
   struct WSide {
     DWGraph g;
+    DBuf<int64_t> lrow;  // live adjacency (g points here once compacted)
+    DBuf<int32_t> lcol;
+    DBuf<uint32_t> lwt;
     WStore *own = nullptr, *roots = nullptr;
     int64_t htcap = 0, fcap = 0, tcap = 0, ccap = 0;
     int32_t wmax = 0;
@@ -1295,7 +1298,26 @@ struct WBuilder {
     DBuf<uint8_t> lskip[2];
     bool have_land = false;
     int32_t s = 0;
+    // live adjacency as in the unweighted build: relaxations toward
+    // vertices ranked below s would be pruned, so each time s has doubled
+    // the CSR is rebuilt without them
+    int32_t live_s = 0;
     while (s < n) {
+      if (!plain && tu.live_adjacency && s >= 1024 && s >= 2 * live_s) {
+        for (int k = 0; k < nsides; k++) {
+          WSide &D = sides[k];
+          DBuf<int64_t> nrow((size_t)n + 1), cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
+          DBuf<int32_t> ncol((size_t)std::max<int64_t>(nnz, 1));
+          DBuf<uint32_t> nwt((size_t)std::max<int64_t>(nnz, 1));
+          check(launch_live_adjacency(DGraph{n, 0, D.g.row, D.g.col}, s, nrow.p, ncol.p, cnt.p,
+                                      tmp.p, st, D.g.wt, nwt.p));
+          D.lrow = std::move(nrow);
+          D.lcol = std::move(ncol);
+          D.lwt = std::move(nwt);
+          D.g = DWGraph{n, D.lrow.p, D.lcol.p, D.lwt.p};
+        }
+        live_s = s;
+      }
       const int32_t nr = std::min<int32_t>(W, n - s);
       DWWindow win[2];
       for (int k = 0; k < nsides; k++) {

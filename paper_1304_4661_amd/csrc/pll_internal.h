@@ -472,9 +472,10 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow 
 hipError_t launch_win_landmarks(DWindow w, int32_t n, uint8_t *out, hipStream_t st);
 // nrow[n+1] / ncol[<= g's entries]: g without the neighbours ranked below s
 // and with empty rows below s (cnt: n scratch values; scan_tmp as for
-// launch_exclusive_scan).
+// launch_exclusive_scan).  wt / nwt (optional): edge weights, carried along.
 hipError_t launch_live_adjacency(DGraph g, int32_t s, int64_t *nrow, int32_t *ncol, int64_t *cnt,
-                                 int64_t *scan_tmp, hipStream_t st);
+                                 int64_t *scan_tmp, hipStream_t st, const uint32_t *wt = nullptr,
+                                 uint32_t *nwt = nullptr);
 hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t nroots,
                             int64_t nvisited, hipStream_t st);
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);

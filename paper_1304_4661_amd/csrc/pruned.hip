@@ -1058,7 +1058,8 @@ __global__ void __launch_bounds__(kBlock) k_live_count(DGraph g, int32_t s, int6
 }
 
 __global__ void __launch_bounds__(kBlock) k_live_fill(DGraph g, int32_t s, const int64_t *nrow,
-                                                      int32_t *ncol) {
+                                                      int32_t *ncol, const uint32_t *wt,
+                                                      uint32_t *nwt) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t r = wave; r < g.n; r += nwaves) {
@@ -1070,20 +1071,25 @@ __global__ void __launch_bounds__(kBlock) k_live_fill(DGraph g, int32_t s, const
       const int32_t x = e < b ? g.col[e] : -1;
       const bool keep = x >= s;
       const uint64_t m = __ballot(keep);
-      if (keep) ncol[o + __popcll(m & lanes_below_mask())] = x;
+      if (keep) {
+        const int64_t q = o + __popcll(m & lanes_below_mask());
+        ncol[q] = x;
+        if (wt) nwt[q] = wt[e];  // a weighted graph keeps each edge's weight
+      }
       o += __popcll(m);
     }
   }
 }
 
 hipError_t launch_live_adjacency(DGraph g, int32_t s, int64_t *nrow, int32_t *ncol, int64_t *cnt,
-                                 int64_t *scan_tmp, hipStream_t st) {
+                                 int64_t *scan_tmp, hipStream_t st, const uint32_t *wt,
+                                 uint32_t *nwt) {
   if (g.n <= 0) return hipSuccess;
   const unsigned blocks = grid_for((int64_t)g.n * kWave, kBlock, 8192);
   hipLaunchKernelGGL(k_live_count, dim3(blocks), dim3(kBlock), 0, st, g, s, cnt);
   hipError_t e = launch_exclusive_scan(cnt, nrow, (int64_t)g.n, scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_live_fill, dim3(blocks), dim3(kBlock), 0, st, g, s, nrow, ncol);
+  hipLaunchKernelGGL(k_live_fill, dim3(blocks), dim3(kBlock), 0, st, g, s, nrow, ncol, wt, nwt);
   return hipGetLastError();
 }
 
