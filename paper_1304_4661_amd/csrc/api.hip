@@ -770,11 +770,10 @@ struct Builder {
       const int d0 = d;
       const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
       for (; d < upto; d++) {
-        hipEvent_t e0 = evs.empty() ? nullptr : evs[3 * (d - d0)];
-        hipEvent_t e1 = evs.empty() ? nullptr : evs[3 * (d - d0) + 1];
-        hipEvent_t e2 = evs.empty() ? nullptr : evs[3 * (d - d0) + 2];
+        hipEvent_t *e = evs.empty() ? nullptr : &evs[4 * (size_t)(d - d0)];
         check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk, st,
-                               e0, e1, e2));
+                               e ? e[0] : nullptr, e ? e[1] : nullptr, e ? e[2] : nullptr,
+                               e ? e[3] : nullptr));
         stat_levels++;
         stat_level_launches++;
       }
@@ -782,8 +781,8 @@ struct Builder {
       check(hipStreamSynchronize(st));
       for (int i = 0; !evs.empty() && i < d - d0; i++) {
         float ms = 0.f, xms = 0.f;
-        check(hipEventElapsedTime(&ms, evs[3 * i], evs[3 * i + 1]));
-        check(hipEventElapsedTime(&xms, evs[3 * i + 1], evs[3 * i + 2]));
+        check(hipEventElapsedTime(&ms, evs[4 * i], evs[4 * i + 1]));
+        check(hipEventElapsedTime(&xms, evs[4 * i + 2], evs[4 * i + 3]));
         stat_level_ns += (int64_t)(ms * 1e6);
         stat_expand_ns += (int64_t)(xms * 1e6);
         const int lv = d0 + i;
@@ -864,7 +863,7 @@ struct Builder {
     // optional timing of each level kernel (events on the build stream)
     std::vector<hipEvent_t> evs;
     if (tu.profile) {
-      evs.resize(3 * (size_t)tu.levels_per_sync);
+      evs.resize(4 * (size_t)tu.levels_per_sync);
       for (auto &e : evs) check(hipEventCreate(&e));
     }
     struct EvGuard {
@@ -1341,9 +1340,9 @@ struct WBuilder {
         for (int b = 0; b < tu.levels_per_sync; b++) {
           for (int k = 0; k < nsides; k++) {
             check(launch_ww_zero_list(sides[k].ctl.p, cur ^ 1, st));
-            if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne], st));
-            check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.wgroup, st));
-            if (!evp.ev.empty()) check(hipEventRecord(evp.ev[ne + 1], st));
+            check(launch_ww_step(sides[k].g, sides[k].own->view(), win[k], cur, tu.wgroup, st,
+                                 evp.ev.empty() ? nullptr : evp.ev[ne],
+                                 evp.ev.empty() ? nullptr : evp.ev[ne + 1]));
             ne += 2;
             stat_step_launches++;
           }

@@ -3,6 +3,7 @@
 // Nothing here is part of the public ABI (include/pll.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -125,6 +126,16 @@ __device__ __forceinline__ unsigned long long block_reserve(const WaveStage<CAP>
   for (int i = 0; i < wv; i++) b += (unsigned long long)s_n[i];
   return b;
 }
+
+// Kernel launch that, given timing events, has the dispatch itself record
+// them at the kernel's start and end (no marker packets between kernels).
+#define PLL_LAUNCH_TIMED(K, gd, bd, st, e0, e1, ...)                    \
+  do {                                                                 \
+    if (e0)                                                            \
+      hipExtLaunchKernelGGL(K, gd, bd, 0, st, e0, e1, 0, __VA_ARGS__); \
+    else                                                               \
+      hipLaunchKernelGGL(K, gd, bd, 0, st, __VA_ARGS__);               \
+  } while (0)
 
 // Groups of G consecutive lanes inside a wave.
 template <int G>
@@ -461,11 +472,11 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 // expansion-time prune, root side and reached-vertex side (the bit-parallel
 // rows for an undirected graph with t > 0; landmark rows otherwise, or
 // tpad = 0 for none).
-// ev0 / ev1 / ev2 (optional): recorded before the test kernel, between the
-// test and the expansion kernels, and after the expansion kernel.
+// ev0 / ev1 and ev2 / ev3 (optional): start and end of the test kernel and
+// of the expansion kernel, recorded by their dispatches.
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
                             int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2);
+                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3);
 // Landmark rows out uint8[n][kLandmarks] of a window whose searches pruned
 // nothing (W >= kLandmarks): distance from its j-th root to every vertex,
 // 255 if not reached.  Run before the window's commit clears its masks.
@@ -545,7 +556,8 @@ hipError_t launch_ww_zero_list(WCtl *ctl, int list, hipStream_t st);
 // sizes: int64[W + 1]; scan_tmp: scan_tmp_elems(W + 1) int64
 hipError_t launch_ww_init(DWStore tabsrc, DWWindow w, int64_t *sizes, int64_t *scan_tmp,
                           hipStream_t st);
-hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st);
+hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 hipError_t launch_ww_collect(DWWindow w, hipStream_t st);
 hipError_t launch_ww_clean(DWWindow w, DWWindow o, hipStream_t st);
 hipError_t launch_ww_commit(DWWindow w, DWStore s, hipStream_t st);

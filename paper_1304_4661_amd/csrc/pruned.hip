@@ -1017,26 +1017,33 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
                             int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2) {
+                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
-  if (ev0) (void)hipEventRecord(ev0, st);
   switch (group) {
-    case 4: hipLaunchKernelGGL(k_win_test<4>, gd, bd, 0, st, g, bp, s, w, f, d); break;
-    case 8: hipLaunchKernelGGL(k_win_test<8>, gd, bd, 0, st, g, bp, s, w, f, d); break;
-    case 16: hipLaunchKernelGGL(k_win_test<16>, gd, bd, 0, st, g, bp, s, w, f, d); break;
-    case 32: hipLaunchKernelGGL(k_win_test<32>, gd, bd, 0, st, g, bp, s, w, f, d); break;
-    default: hipLaunchKernelGGL(k_win_test<64>, gd, bd, 0, st, g, bp, s, w, f, d); break;
+    case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    default: PLL_LAUNCH_TIMED(k_win_test<64>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
   }
-  if (ev1) (void)hipEventRecord(ev1, st);
   switch (xgroup) {
-    case 4: hipLaunchKernelGGL(k_win_expand<4>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
-    case 8: hipLaunchKernelGGL(k_win_expand<8>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
-    case 16: hipLaunchKernelGGL(k_win_expand<16>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
-    case 32: hipLaunchKernelGGL(k_win_expand<32>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
-    default: hipLaunchKernelGGL(k_win_expand<64>, gd, bd, 0, st, g, bp, rb, vb, s, w, f, d, chunk); break;
+    case 4:
+      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      break;
+    case 8:
+      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      break;
+    case 16:
+      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      break;
+    case 32:
+      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      break;
+    default:
+      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      break;
   }
-  if (ev2) (void)hipEventRecord(ev2, st);
   hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk);
   return hipGetLastError();
 }

@@ -964,22 +964,23 @@ hipError_t launch_ww_init(DWStore tabsrc, DWWindow w, int64_t *sizes, int64_t *s
   return hipGetLastError();
 }
 
-hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st) {
+hipError_t launch_ww_step(DWGraph g, DWStore s, DWWindow w, int cur, int group, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   switch (group) {
     case 4:
-      hipLaunchKernelGGL(k_ww_step<4>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      PLL_LAUNCH_TIMED(k_ww_step<4>, dim3(kGrid), dim3(kBlock), st, ev0, ev1, g, s, w, cur);
       break;
     case 8:
-      hipLaunchKernelGGL(k_ww_step<8>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      PLL_LAUNCH_TIMED(k_ww_step<8>, dim3(kGrid), dim3(kBlock), st, ev0, ev1, g, s, w, cur);
       break;
     case 32:
-      hipLaunchKernelGGL(k_ww_step<32>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      PLL_LAUNCH_TIMED(k_ww_step<32>, dim3(kGrid), dim3(kBlock), st, ev0, ev1, g, s, w, cur);
       break;
     case 64:
-      hipLaunchKernelGGL(k_ww_step<64>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      PLL_LAUNCH_TIMED(k_ww_step<64>, dim3(kGrid), dim3(kBlock), st, ev0, ev1, g, s, w, cur);
       break;
     default:
-      hipLaunchKernelGGL(k_ww_step<16>, dim3(kGrid), dim3(kBlock), 0, st, g, s, w, cur);
+      PLL_LAUNCH_TIMED(k_ww_step<16>, dim3(kGrid), dim3(kBlock), st, ev0, ev1, g, s, w, cur);
       break;
   }
   return hipGetLastError();
