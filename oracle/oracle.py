@@ -47,6 +47,11 @@ def _configure(lib):
         P = C.c_void_p
         lib.orc_build.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, C.POINTER(C.c_void_p)]
         lib.orc_build.restype = C.c_int
+        lib.orc_build_prefix.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, C.c_int32,
+                                         C.POINTER(C.c_void_p)]
+        lib.orc_build_prefix.restype = C.c_int
+        lib.orc_times.argtypes = [C.c_void_p, P, P, P, P, C.c_int32]
+        lib.orc_times.restype = C.c_int32
         lib.orc_query.argtypes = [C.c_void_p, P, C.c_int64, P]
         lib.orc_query.restype = C.c_int
         lib.orc_free.argtypes = [C.c_void_p]
@@ -141,6 +146,9 @@ class OracleIndex:
     counters: dict = field(default_factory=dict)
     root_visited: np.ndarray | None = None  # int32[n] per rank (pruned phase)
     root_labeled: np.ndarray | None = None  # int32[n] per rank
+    # wall clock of the build: {"bp_s", "pruned_s", "ck_step", "ck_s"} where
+    # ck_s[i] is the pruned-phase time before the root of rank i*ck_step
+    times: dict = field(default_factory=dict)
     _handle: C.c_void_p | None = None
 
     def label(self, r: int):
@@ -162,7 +170,11 @@ class OracleIndex:
             pass
 
 
-def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None) -> OracleIndex:
+def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None,
+          root_limit: int | None = None) -> OracleIndex:
+    """Oracle index of an undirected graph.  ``root_limit``: run the pruned
+    BFSs of ranks ``0..root_limit-1`` only (Theorem 4.1: the result is the
+    full labels' entries whose hub ranks below ``root_limit``)."""
     lib = lib or _load()
     row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
     col = np.ascontiguousarray(col, dtype=np.int32)
@@ -171,8 +183,12 @@ def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None
     if len(row_ptr) != n + 1:
         raise OracleError(-1)
     h = C.c_void_p()
-    rc = lib.orc_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp),
-                       1 if check_symmetric else 0, C.byref(h))
+    if root_limit is None:
+        rc = lib.orc_build(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp),
+                           1 if check_symmetric else 0, C.byref(h))
+    else:
+        rc = lib.orc_build_prefix(n, _ptr(row_ptr), _ptr(col), _ptr(order), int(t_bp),
+                                  1 if check_symmetric else 0, int(root_limit), C.byref(h))
     if rc != 0:
         raise OracleError(rc)
     ne = lib.orc_num_entries(h)
@@ -198,6 +214,12 @@ def build(row_ptr, col, order, t_bp: int, check_symmetric: bool = True, lib=None
     idx.root_visited = np.zeros(n, np.int32)
     idx.root_labeled = np.zeros(n, np.int32)
     lib.orc_root_counts(h, _ptr(idx.root_visited), _ptr(idx.root_labeled))
+    if hasattr(lib, "orc_times"):
+        bp_ns, pr_ns, step = C.c_int64(), C.c_int64(), C.c_int32()
+        ck = np.zeros(1025, np.int64)
+        nck = lib.orc_times(h, C.byref(bp_ns), C.byref(pr_ns), C.byref(step), _ptr(ck), 1025)
+        idx.times = {"bp_s": bp_ns.value * 1e-9, "pruned_s": pr_ns.value * 1e-9,
+                     "ck_step": int(step.value), "ck_s": (ck[:max(nck, 0)] * 1e-9).tolist()}
     return idx
 
 

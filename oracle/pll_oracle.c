@@ -71,9 +71,11 @@
  *     distances of the slot, towards a chosen neighbour w with w in S^{-1}
  *     (one step closer to w per level) or S^{0} (same distance as to r).
  */
+#define _POSIX_C_SOURCE 199309L
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #define ORC_INF 255u
 #define ORC_SENTINEL 0xFFFFFFFFu
@@ -125,6 +127,10 @@ typedef struct orc_index {
   int32_t *root_visited; /* [n]: vertices dequeued by the pruned BFS of rank k */
   int32_t *root_labeled; /* [n]: vertices it labeled (Figure 4 quantities) */
   int32_t *ord;          /* [n]: input id of rank r */
+  /* wall-clock timing of the build (reporting only; no effect on labels) */
+  int64_t ns_bp, ns_pruned;   /* bit-parallel phase, pruned phase */
+  int32_t ck_step, nck;       /* checkpoint every ck_step roots, nck taken */
+  int64_t *ck_ns;             /* [nck]: pruned-phase ns elapsed before rank i*ck_step */
   int64_t *off;          /* [n+1] rank-space adjacency (kept for paths) */
   int32_t *adj;
   int64_t cnt[ORC_NCOUNTERS];
@@ -156,6 +162,7 @@ void orc_free(orc_index *x) {
   free(x->root_visited);
   free(x->root_labeled);
   free(x->ord);
+  free(x->ck_ns);
   free(x->off);
   free(x->adj);
   free(x);
@@ -387,10 +394,19 @@ static int pruned_at(orc_index *x, int32_t k, int32_t u, int d, const uint8_t *T
   return best <= d;
 }
 
+static int64_t now_ns(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (int64_t)ts.tv_sec * 1000000000 + ts.tv_nsec;
+}
+
+/* root_limit: pruned BFSs run from ranks 0..root_limit-1 only. */
 static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
-                        const char *used) {
+                        const char *used, int32_t root_limit) {
   int32_t n = x->n;
-  uint8_t *P = (uint8_t *)malloc((size_t)n);
+  /* visit distances in 16 bits, so that a vertex can be reached (and
+   * tested) at distance 255; only labeling it there is out of range */
+  uint16_t *P = (uint16_t *)malloc((size_t)n * sizeof(uint16_t));
   uint8_t *T = (uint8_t *)malloc((size_t)n);
   int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
   int32_t *PP = (int32_t *)malloc((size_t)n * sizeof(int32_t)); /* enqueuing parent */
@@ -399,9 +415,11 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
     rc = ORC_E_NOMEM;
     goto done;
   }
-  memset(P, (int)ORC_INF, (size_t)n); /* once, before the first BFS */
+  memset(P, 0xFF, (size_t)n * sizeof(uint16_t)); /* once, before the first BFS */
   memset(T, (int)ORC_INF, (size_t)n);
-  for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
+  int64_t t0 = now_ns();
+  for (int32_t k = 0; k < root_limit && rc == ORC_OK; k++) {
+    if (k % x->ck_step == 0) x->ck_ns[x->nck++] = now_ns() - t0;
     if (used[k]) continue;
     x->cnt[C_ROOTS]++;
     int64_t vis0 = x->cnt[C_VISITED], lab0 = x->cnt[C_LABELED];
@@ -417,6 +435,10 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
       int d = P[u];
       x->cnt[C_VISITED]++;
       if (pruned_at(x, k, u, d, T)) continue;
+      if (d >= (int)ORC_INF) { /* (k, 255) cannot be stored */
+        rc = ORC_E_RANGE;
+        break;
+      }
       rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);
       if (rc != ORC_OK) break;
       x->cnt[C_LABELED]++;
@@ -424,23 +446,14 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
       for (int64_t j = off[u]; j < off[u + 1]; j++) {
         int32_t w = adj[j];
         x->cnt[C_EDGES]++;
-        if (P[w] != ORC_INF) continue;
-        if (d + 1 >= (int)ORC_INF) {
-          /* w sits at distance 255: fine only if it would be pruned */
-          if (!pruned_at(x, k, w, d + 1, T)) {
-            rc = ORC_E_RANGE;
-            break;
-          }
-          continue;
-        }
-        P[w] = (uint8_t)(d + 1);
+        if (P[w] != 0xFFFF) continue;
+        P[w] = (uint16_t)(d + 1);
         PP[w] = u;
         queue[qt++] = w;
       }
-      if (rc != ORC_OK) break;
     }
     /* reset only what this BFS touched (Section 4.5.1, "Initialization") */
-    for (int64_t i = 0; i < qt; i++) P[queue[i]] = (uint8_t)ORC_INF;
+    for (int64_t i = 0; i < qt; i++) P[queue[i]] = 0xFFFF;
     for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = (uint8_t)ORC_INF;
     x->root_visited[k] = (int32_t)(x->cnt[C_VISITED] - vis0);
     x->root_labeled[k] = (int32_t)(x->cnt[C_LABELED] - lab0);
@@ -456,13 +469,19 @@ done:
 /* ------------------------------------------------------------------------ */
 /* Public entry points                                                       */
 
-/* Build the index.  flags bit 0: check that the graph is symmetric. */
-int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
-              const int32_t *order, int32_t t_bp, uint32_t flags, orc_index **out) {
+/* Build the index.  flags bit 0: check that the graph is symmetric.
+ * root_limit (0..n): the pruned phase stops before the root of that rank.
+ * By Theorem 4.1 the labels are then exactly the entries of the full
+ * labels whose hub ranks below root_limit; root_limit = n is the full
+ * build (orc_build). */
+int orc_build_prefix(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                     const int32_t *order, int32_t t_bp, uint32_t flags, int32_t root_limit,
+                     orc_index **out) {
   if (!out) return ORC_E_INVAL;
   *out = NULL;
   int rc = validate(n, row_ptr, col, order, t_bp);
   if (rc != ORC_OK) return rc;
+  if (root_limit < 0 || root_limit > n) return ORC_E_INVAL;
 
   orc_index *x = (orc_index *)calloc(1, sizeof(orc_index));
   if (!x) return ORC_E_NOMEM;
@@ -480,6 +499,8 @@ int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
   x->bp_sel = (int32_t *)malloc((size_t)(tt * ORC_BPW) * sizeof(int32_t));
   x->root_visited = (int32_t *)calloc((size_t)nn, sizeof(int32_t));
   x->root_labeled = (int32_t *)calloc((size_t)nn, sizeof(int32_t));
+  x->ck_step = (int32_t)((nn + 1023) / 1024);
+  x->ck_ns = (int64_t *)calloc(1025, sizeof(int64_t));
   int64_t *off = (int64_t *)malloc((size_t)(nn + 1) * sizeof(int64_t));
   int32_t *adj = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
   char *used = (char *)calloc((size_t)nn, 1);
@@ -491,7 +512,7 @@ int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
   int32_t *e0 = (int32_t *)malloc((size_t)(2 * (nnz > 0 ? nnz : 1)) * sizeof(int32_t));
   int32_t *e1 = (int32_t *)malloc((size_t)(2 * (nnz > 0 ? nnz : 1)) * sizeof(int32_t));
   if (!x->rank || !x->lab || !x->bp_d || !x->bp_m1 || !x->bp_0 || !x->bp_root ||
-      !x->bp_nsel || !x->bp_sel || !x->root_visited || !x->root_labeled || !off || !adj || !used || !P || !s1 || !s0 || !q0 ||
+      !x->bp_nsel || !x->bp_sel || !x->root_visited || !x->root_labeled || !x->ck_ns || !off || !adj || !used || !P || !s1 || !s0 || !q0 ||
       !q1 || !e0 || !e1) {
     rc = ORC_E_NOMEM;
     goto fail;
@@ -513,16 +534,20 @@ int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
   }
 
   /* O1 + O2 */
+  int64_t tb0 = now_ns();
   choose_bp_roots(x, off, adj, used);
   for (int32_t i = 0; i < n; i++) x->cnt[C_BP_USED] += used[i] ? 1 : 0;
   for (int32_t s = 0; s < t_bp; s++) {
     rc = bp_bfs(x, s, off, adj, P, s1, s0, q0, q1, e0, e1);
     if (rc != ORC_OK) goto fail;
   }
+  int64_t tb1 = now_ns();
+  x->ns_bp = tb1 - tb0;
 
   /* O3 + O4 */
-  rc = pruned_phase(x, off, adj, used);
+  rc = pruned_phase(x, off, adj, used, root_limit);
   if (rc != ORC_OK) goto fail;
+  x->ns_pruned = now_ns() - tb1;
   for (int32_t v = 0; v < n; v++) x->cnt[C_ENTRIES] += x->lab[v].len;
   /* a vertex with an empty label still gets its sentinel */
   for (int32_t v = 0; v < n; v++) {
@@ -565,6 +590,24 @@ fail:
   free(q0); free(q1); free(e0); free(e1);
   orc_free(x);
   return rc;
+}
+
+int orc_build(int32_t n, const int32_t *row_ptr, const int32_t *col,
+              const int32_t *order, int32_t t_bp, uint32_t flags, orc_index **out) {
+  return orc_build_prefix(n, row_ptr, col, order, t_bp, flags, n, out);
+}
+
+/* Wall-clock times of a build (ns): bit-parallel phase, pruned phase, and
+ * the pruned-phase time elapsed before every ck_step-th root.  Returns the
+ * number of checkpoints (at most max_ck are copied). */
+int32_t orc_times(const orc_index *x, int64_t *bp_ns, int64_t *pruned_ns, int32_t *ck_step,
+                  int64_t *ck_ns, int32_t max_ck) {
+  if (!x) return ORC_E_INVAL;
+  if (bp_ns) *bp_ns = x->ns_bp;
+  if (pruned_ns) *pruned_ns = x->ns_pruned;
+  if (ck_step) *ck_step = x->ck_step;
+  for (int32_t i = 0; ck_ns && i < x->nck && i < max_ck; i++) ck_ns[i] = x->ck_ns[i];
+  return x->nck;
 }
 
 /* O5: one query by ids.  Bit-parallel part (Section 5.3) and the merge join
@@ -970,7 +1013,7 @@ static int t_query(const orc_label *L, const uint8_t *T) {
  * in-edges for the reverse one).  T holds the root's label on the other
  * side; `own` receives (k, d) at every vertex it does not prune. */
 static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32_t *adj,
-                        orc_label *own, const orc_label *root_side, uint8_t *P, uint8_t *T,
+                        orc_label *own, const orc_label *root_side, uint16_t *P, uint8_t *T,
                         int32_t *queue, int32_t *PP) {
   const orc_label *Lk = &root_side[k];
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
@@ -987,6 +1030,10 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
     x->cnt[C_NORMAL_TESTS]++;
     x->cnt[C_LABEL_SCANNED] += own[u].len;
     if (t_query(&own[u], T) <= d) continue;
+    if (d >= (int)ORC_INF) { /* (k, 255) cannot be stored */
+      rc = ORC_E_RANGE;
+      break;
+    }
     /* the parent is the vertex that enqueued u: its predecessor on the
      * path from k for the search along the arcs, its successor on the path
      * to k for the search against them */
@@ -997,21 +1044,13 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
     for (int64_t j = off[u]; j < off[u + 1]; j++) {
       int32_t w = adj[j];
       x->cnt[C_EDGES]++;
-      if (P[w] != ORC_INF) continue;
-      if (d + 1 >= (int)ORC_INF) {
-        /* w sits at distance 255: fine only if it would be pruned */
-        if (t_query(&own[w], T) > d + 1) {
-          rc = ORC_E_RANGE;
-          break;
-        }
-        continue;
-      }
-      P[w] = (uint8_t)(d + 1);
+      if (P[w] != 0xFFFF) continue;
+      P[w] = (uint16_t)(d + 1);
       PP[w] = u;
       queue[qt++] = w;
     }
   }
-  for (int64_t i = 0; i < qt; i++) P[queue[i]] = (uint8_t)ORC_INF;
+  for (int64_t i = 0; i < qt; i++) P[queue[i]] = 0xFFFF;
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = (uint8_t)ORC_INF;
   return rc;
 }
@@ -1048,7 +1087,7 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   int64_t *ioff = (int64_t *)calloc((size_t)(nn + 1), sizeof(int64_t));
   int32_t *iadj = (int32_t *)malloc((size_t)mm * sizeof(int32_t));
   int64_t *fill = (int64_t *)calloc((size_t)nn, sizeof(int64_t));
-  uint8_t *P = (uint8_t *)malloc((size_t)nn);
+  uint16_t *P = (uint16_t *)malloc((size_t)nn * sizeof(uint16_t));
   uint8_t *T = (uint8_t *)malloc((size_t)nn);
   int32_t *queue = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   int32_t *PP = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
@@ -1074,7 +1113,7 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   for (int32_t r = 0; r < n; r++) ioff[r + 1] += ioff[r];
   for (int32_t r = 0; r < n; r++) /* sources in ascending rank: rows come out sorted */
     for (int64_t j = off[r]; j < off[r + 1]; j++) iadj[ioff[adj[j]] + fill[adj[j]]++] = r;
-  memset(P, (int)ORC_INF, (size_t)nn);
+  memset(P, 0xFF, (size_t)nn * sizeof(uint16_t));
   memset(T, (int)ORC_INF, (size_t)nn);
   for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
     x->cnt[C_ROOTS]++;

@@ -1,0 +1,113 @@
+"""Write the oracle's digests of the full-size workloads.
+
+    python tests/golden/make_full_digests.py rmat20|rmat22|ba256 [--jobs J]
+
+writes ``tests/golden/full_<name>.json``: the SHA-256 of the input CSR and
+order, the digests of the oracle's exported index (``tests/digest.py``), the
+digest and histogram of its answers to the workload's query pairs, its work
+counters and its build time on this machine.  It calls only ``oracle/`` and
+the seeded input generators; nothing here comes from the GPU library.
+
+Workloads (the generators' named recipes):
+  rmat20  R-MAT scale 20, seed 3, Degree order, t_bp = 64, 1e7 pairs (seed 103)
+  rmat22  R-MAT scale 22, seed 5, Degree order, t_bp = 64, 1e7 pairs (seed 105)
+  ba256   256 Barabasi-Albert graphs (n log-uniform in [1e3, 2e5], m in 2..8,
+          seeds 4000+i), each indexed alone with t_bp = 16 (independent builds),
+          1e4 pairs inside each graph (seeds 14000+i)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path[:0] = [ROOT, os.path.dirname(HERE)]
+
+import numpy as np  # noqa: E402
+
+import digest  # noqa: E402
+import oracle  # noqa: E402
+from paper_1304_4661_amd import gen  # noqa: E402
+
+PAIRS = {"rmat20": (10_000_000, 103), "rmat22": (10_000_000, 105)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def one_graph(g, order, t_bp, pairs) -> dict:
+    t0 = time.perf_counter()
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp, check_symmetric=False)
+    build_s = time.perf_counter() - t0
+    d = digest.index_digests(ox.off, ox.hub, ox.dist, ox.bp_d, ox.bp_m1, ox.bp_0)
+    d["rank_sha256"] = __import__("hashlib").sha256(
+        np.ascontiguousarray(ox.rank, "<i4").tobytes()).hexdigest()
+    t1 = time.perf_counter()
+    ans = oracle.query(ox, pairs)
+    query_s = time.perf_counter() - t1
+    rec = {"csr_sha256": gen.csr_sha256(g, order), "n": int(g.n), "m": int(g.m),
+           "t_bp": int(t_bp), "index": d, "answers": digest.answers_digest(ans),
+           "pairs": int(len(pairs)), "counters": ox.counters,
+           "build_s": build_s, "query_s": query_s, "times": ox.times}
+    ox.close()
+    return rec
+
+
+def _ba_job(i: int) -> dict:
+    n, m, seed = gen.batch_spec(256)[i]
+    g = gen.ba_graph(n, m, seed)
+    rec = one_graph(g, gen.degree_order(g), 16, gen.random_pairs(g.n, 10_000, 14000 + i))
+    rec["graph"] = i
+    rec["spec"] = [n, m, seed]
+    rec["index"].pop("blocks")
+    print(f"graph {i}: n={g.n} entries={rec['index']['entries']} build {rec['build_s']:.1f} s",
+          flush=True)
+    return rec
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("name", choices=["rmat20", "rmat22", "ba256"])
+    ap.add_argument("--jobs", type=int, default=1)
+    a = ap.parse_args()
+    head = {"made_by": "python tests/golden/make_full_digests.py " + a.name,
+            "cpu_model": cpu_model(), "threads_per_build": 1,
+            "host_threads": os.cpu_count()}
+    if a.name == "ba256":
+        if a.jobs > 1:
+            from multiprocessing import Pool
+            with Pool(a.jobs) as p:
+                recs = p.map(_ba_job, range(256), chunksize=1)
+        else:
+            recs = [_ba_job(i) for i in range(256)]
+        out = dict(head, workload="ba256", t_bp=16, graphs=recs,
+                   build_s_total=sum(r["build_s"] for r in recs))
+    else:
+        g, order, t_bp, _ = gen.config_graph(a.name)
+        q, seed = PAIRS[a.name]
+        pairs = gen.random_pairs(g.n, q, seed)
+        print(f"{a.name}: n={g.n} m={g.m} t_bp={t_bp}", flush=True)
+        out = dict(head, workload=a.name, pair_seed=seed, **one_graph(g, order, t_bp, pairs))
+        print(f"build {out['build_s']:.1f} s, entries {out['index']['entries']}", flush=True)
+    path = os.path.join(HERE, f"full_{a.name}.json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

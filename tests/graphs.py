@@ -91,3 +91,24 @@ def families():
         ("single", empty(1)),
         ("star70", star(70)),
     ]
+
+
+def level_255_pruned():
+    """A graph whose pruned BFS reaches a vertex at distance 255 that the
+    prune test then drops, so the build must succeed (8-bit distances,
+    Section 4.5.1).  Path a_0..a_254 (ids 0..254), w = 255 joined to a_254,
+    x = 256 joined to a_253 and w, and three leaves 257..259 on x.  With the
+    order x, a_0, a_1, ..., w, leaves: the BFS from a_0 labels a_254 at 254
+    and reaches w at 255, where d(a_0, x) + d(x, w) = 254 + 1 prunes it; the
+    leaves (255 away through x) are never reached because x prunes itself.
+    Returns (graph, order)."""
+    edges = [(i, i + 1) for i in range(254)] + [(254, 255), (256, 253), (256, 255)]
+    edges += [(256, 257), (256, 258), (256, 259)]
+    g = from_edges(260, edges)
+    order = np.array([256] + list(range(256)) + [257, 258, 259], np.int32)
+    return g, order
+
+
+def directed_from_undirected(g) -> gen.Graph:
+    """The symmetric digraph with both arcs of every edge (same CSR)."""
+    return gen.Graph(g.n, g.row_ptr.copy(), g.col.copy(), dict(g.meta))

@@ -178,12 +178,15 @@ MUTATIONS = [
      "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue, PP);",
      "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab_in, P, T, queue, PP);"),
     ("directed parent recorded as the search root",
-     "      PP[w] = u;\n      queue[qt++] = w;", "      PP[w] = k;\n      queue[qt++] = w;"),
+     "      PP[w] = u;\n      queue[qt++] = w;\n    }\n  }\n  for", "      PP[w] = k;\n      queue[qt++] = w;\n    }\n  }\n  for"),
     ("directed path ascends L_OUT from the target",
      "    int64_t e = find_hub(&x->lab_in[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab_in[c].par[e];",
      "    int64_t e = find_hub(&x->lab[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab[c].par[e];"),
     ("query merges L_OUT(s) with L_OUT(t)",
      "*B = x->lab_in ? &x->lab_in[rt] : &x->lab[rt];", "*B = &x->lab[rt];"),
+    ("any directed BFS level reaching 255 is a range error",
+     "    if (t_query(&own[u], T) <= d) continue;\n",
+     "    if (d < (int)ORC_INF && t_query(&own[u], T) <= d) continue;\n"),
     ("transpose keeps the arcs' direction",
      "iadj[ioff[adj[j]] + fill[adj[j]]++] = r;", "iadj[ioff[adj[j]] + fill[adj[j]]++] = adj[j];"),
 ]
@@ -195,9 +198,11 @@ def test_directed_pins_catch_planted_mistake(desc, old, new, tmp_path):
     assert src.count(old) == 1, desc
     lib = oracle.load_variant(src.replace(old, new), str(tmp_path))
     caught = False
-    for name, g in DG[:4]:
+    cases = [(g, gen.degree_order_directed(g)) for _, g in DG[:4]]
+    cases.append(graphs.level_255_pruned())
+    for g, order in cases:
         try:
-            caught |= bool(check_directed(g, gen.degree_order_directed(g), lib=lib))
+            caught |= bool(check_directed(g, order, lib=lib))
         except oracle.OracleError:
             caught = True
     assert caught, desc

@@ -48,18 +48,23 @@ MUTATIONS = [
      "    for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = (uint8_t)ORC_INF;\n    x->root_visited",
      "    x->root_visited"),
     ("P not reset after a root",
-     "    for (int64_t i = 0; i < qt; i++) P[queue[i]] = (uint8_t)ORC_INF;\n", ""),
+     "    /* reset only what this BFS touched (Section 4.5.1, \"Initialization\") */\n    for (int64_t i = 0; i < qt; i++) P[queue[i]] = 0xFFFF;\n", ""),
     ("next level one too far",
-     "        P[w] = (uint8_t)(d + 1);\n", "        P[w] = (uint8_t)(d + 2);\n"),
+     "        P[w] = (uint16_t)(d + 1);\n        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset",
+     "        P[w] = (uint16_t)(d + 2);\n        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset"),
     ("S^0 left as the raw dynamic programme",
      "x->bp_0[(int64_t)v * t + slot] = s0[v] & ~s1[v];",
      "x->bp_0[(int64_t)v * t + slot] = s0[v];"),
     ("path parent recorded as the BFS root",
-     "        PP[w] = u;\n", "        PP[w] = k;\n"),
+     "        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset",
+     "        PP[w] = k;\n        queue[qt++] = w;\n      }\n    }\n    /* reset"),
     ("walk towards a neighbour follows S^0 instead of S^-1",
      "      c = bp_step(x, c, i, -1, bit, 1);\n", "      c = bp_step(x, c, i, -1, bit, 0);\n"),
     ("bit-parallel path ignores the -1/-2 witnesses",
      "      kind = (int)ds + (int)dt - v;\n", "      kind = 0;\n"),
+    ("any BFS level reaching 255 is a range error",
+     "      if (pruned_at(x, k, u, d, T)) continue;\n      if (d >= (int)ORC_INF) {",
+     "      if (d < (int)ORC_INF && pruned_at(x, k, u, d, T)) continue;\n      if (d >= (int)ORC_INF) {"),
     ("pruned BFS also run from bit-parallel vertices",
      "    if (used[k]) continue;\n    x->cnt[C_ROOTS]++;", "    x->cnt[C_ROOTS]++;"),
 ]
@@ -71,6 +76,7 @@ CASES = [
     ("grid4x5", graphs.grid(4, 5), 1),
     ("union", graphs.disjoint_union(graphs.cycle(5), graphs.star(6), graphs.path(4)), 2),
     ("ba200", gen.ba_graph(200, 2, 5), 0),
+    ("level255", graphs.level_255_pruned(), 0),
 ]
 
 
@@ -81,8 +87,9 @@ def test_pins_catch_planted_mistake(desc, old, new, tmp_path):
     lib = oracle.load_variant(src.replace(old, new), str(tmp_path))
     caught = []
     for name, g, t in CASES:
+        g, order = g if isinstance(g, tuple) else (g, gen.degree_order(g))
         try:
-            f = pins.run_all(g, gen.degree_order(g), t, lib=lib)
+            f = pins.run_all(g, order, t, lib=lib)
         except oracle.OracleError as e:  # a crash-free error also counts
             f = [str(e)]
         if f:

@@ -203,6 +203,45 @@ def test_range_error_path():
         assert e.value.code == -3
 
 
+def test_level_255_reached_but_pruned():
+    # Section 4.5.1 stores distances in 8 bits (255 = infinity).  A pruned BFS
+    # may still *reach* a vertex at distance 255 as long as the prune test
+    # drops it there: the build must succeed with every stored distance <= 254.
+    g, order = graphs.level_255_pruned()
+    D = brute.apsp(g.row_ptr, g.col)
+    assert D[0, 255] == 255 and D[0, 257] == 255  # a_0 -> w, a_0 -> leaf
+    for t in (0, 1):
+        ix = oracle.build(g.row_ptr, g.col, order, t)
+        assert ix.counters["max_dist"] == 254
+        assert not pins.run_all(g, order, t), t
+        q = oracle.query(ix, np.array([[0, 255], [0, 257], [1, 255], [0, 254]], np.int32))
+        assert q.tolist() == [255, 255, 254, 254]
+    # without bit-parallel labels a_254 (rank 255) keeps the entry of a_0 (rank 1)
+    # at 254, and the BFS from a_0 visits a_0..a_254, x and w (w at 255, where
+    # it is pruned), not the leaves
+    ix = oracle.build(g.row_ptr, g.col, order, 0)
+    h, d = ix.label(255)
+    assert (1, 254) in list(zip(h.tolist(), d.tolist()))
+    assert ix.root_visited[1] == 257
+
+
+def test_level_255_reached_but_pruned_directed():
+    # the same graph as a digraph with both arcs of every edge: the forward
+    # and the reverse search from a_0 both reach w at 255 and prune it there
+    g, order = graphs.level_255_pruned()
+    ux = oracle.build(g.row_ptr, g.col, order, 0)
+    dx = oracle.build_directed(g.row_ptr, g.col, order)
+    assert dx.counters["max_dist"] == 254
+    for off, hub, dist in ((dx.out_off, dx.out_hub, dx.out_dist),
+                           (dx.in_off, dx.in_hub, dx.in_dist)):
+        assert np.array_equal(off, ux.off) and np.array_equal(hub, ux.hub)
+        assert np.array_equal(dist, ux.dist)
+    D = np.minimum(brute.apsp(g.row_ptr, g.col), 255)
+    s, t = np.meshgrid(np.arange(g.n), np.arange(g.n), indexing="ij")
+    p = np.stack([s.ravel(), t.ravel()], 1).astype(np.int32)
+    assert np.array_equal(oracle.query_directed(dx, p).reshape(g.n, g.n), D)
+
+
 def test_validation_errors():
     g = graphs.cycle(5)
     order = gen.degree_order(g)
@@ -311,3 +350,26 @@ def test_paths_cover_every_bit_parallel_case():
         s, u = np.meshgrid(np.arange(g.n), np.arange(g.n), indexing="ij")
         kinds |= _bp_path_kinds(ix, np.stack([s.ravel(), u.ravel()], 1).astype(np.int32))
     assert kinds == {0, 1, 2}
+
+
+@pytest.mark.parametrize("name,g,t", [("ba300", gen.ba_graph(300, 3, 21), 4),
+                                      ("er60", graphs.erdos_renyi(60, 0.05, 4), 0),
+                                      ("rmat10", gen.rmat_graph(10, seed=3), 8)])
+def test_prefix_build_is_the_full_labels_below_the_limit(name, g, t):
+    # Theorem 4.1: after the pruned BFSs of ranks < K the labels answer
+    # exactly what the full labels restricted to hubs < K answer; with the
+    # canonical-label lemma the entries themselves are that restriction.
+    order = gen.degree_order(g)
+    full = oracle.build(g.row_ptr, g.col, order, t)
+    for K in (0, 1, 2, 7, g.n // 3, g.n - 1, g.n):
+        px = oracle.build(g.row_ptr, g.col, order, t, root_limit=K)
+        keep = full.hub < K
+        assert np.array_equal(px.hub, full.hub[keep]), K
+        assert np.array_equal(px.dist, full.dist[keep]), K
+        want_off = np.concatenate([[0], np.cumsum(keep)])[full.off]
+        assert np.array_equal(px.off, want_off), K
+        assert np.array_equal(px.bp_d, full.bp_d) and np.array_equal(px.bp_m1, full.bp_m1)
+        assert px.counters["roots"] == sum(1 for r in range(K) if r not in
+                                           set(pins.bp_used_ranks(full)))
+    with pytest.raises(oracle.OracleError):
+        oracle.build(g.row_ptr, g.col, order, t, root_limit=g.n + 1)
