@@ -467,7 +467,13 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * change).  "live_adjacency" (0/1: each time the window start s has
  * doubled, the expansion's adjacency (a weighted build's relaxation
  * adjacency, weights included) is rebuilt without the neighbours ranked
- * below s, which would be pruned anyway; same labels).  Memory: "pool_keep_mb" (device memory of freed build
+ * below s, which would be pruned anyway; same labels).  "expand_prune"
+ * (0/1, unweighted builds: a candidate's expansion leaves a neighbour
+ * unvisited when the neighbour ranks before the window or its distance row
+ * already prunes it at the next level; 0 visits and tests every reached
+ * neighbour as Algorithm 1 does, and also turns "live_adjacency" and the
+ * landmark rows off, so that a PLL_PLAIN build's visits, labels and
+ * scanned edges are the sequential algorithm's; same labels).  Memory: "pool_keep_mb" (device memory of freed build
  * scratch and indexes kept for reuse by later builds, MB; reuse on another
  * stream waits for the stream that freed it; lowering the value releases
  * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64),

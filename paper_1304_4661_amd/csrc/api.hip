@@ -37,6 +37,7 @@ struct Tuning {
   int profile = 0;
   int bp_chunk = 64;  // adjacency entries per bit-parallel work item
   int serve_coalesce = 1;  // servers pack several requests per launch
+  int expand_prune = 1;  // expansion leaves neighbours unvisited that a test would prune
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -771,9 +772,9 @@ struct Builder {
       const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
       for (; d < upto; d++) {
         hipEvent_t *e = evs.empty() ? nullptr : &evs[4 * (size_t)(d - d0)];
-        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk, st,
-                               e ? e[0] : nullptr, e ? e[1] : nullptr, e ? e[2] : nullptr,
-                               e ? e[3] : nullptr));
+        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk,
+                               tu.expand_prune ? w.s : 0, st, e ? e[0] : nullptr,
+                               e ? e[1] : nullptr, e ? e[2] : nullptr, e ? e[3] : nullptr));
         stat_levels++;
         stat_level_launches++;
       }
@@ -883,7 +884,7 @@ struct Builder {
     // time s has doubled (the expansion skips them anyway)
     int32_t live_s = 0;
     while (s < n) {
-      if (!plain && tu.live_adjacency && s >= 1024 && s >= 2 * live_s) {
+      if (!plain && tu.live_adjacency && tu.expand_prune && s >= 1024 && s >= 2 * live_s) {
         for (int k = 0; k < nsides; k++) {
           Side &D = sides[k];
           DBuf<int64_t> nrow((size_t)n + 1), cnt((size_t)n), tmp((size_t)scan_tmp_elems(n));
@@ -903,8 +904,8 @@ struct Builder {
       int flags = 0;
       for (int k = 0; k < nsides && !flags; k++) {  // after an overflow the window is redone
         w[k] = sides[k].window(s, nr, words, used.p);
-        DBp rb = t > 0 ? bp : no_rows, vb = t > 0 ? bp : no_rows;
-        if (t == 0 && have_land && s >= kLandmarks) {
+        DBp rb = t > 0 && tu.expand_prune ? bp : no_rows, vb = rb;
+        if (t == 0 && have_land && s >= kLandmarks && tu.expand_prune) {
           rb = DBp{kLandmarks, kLandmarks, land[nsides - 1 - k].p, nullptr, nullptr};
           vb = DBp{kLandmarks, kLandmarks, land[k].p, nullptr, nullptr};
         }
@@ -2392,6 +2393,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "live_adjacency") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.live_adjacency = (int)value;
+  } else if (k == "expand_prune") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.expand_prune = (int)value;
   } else if (k == "pool_keep_mb") {
     if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.pool_keep_mb = value;
@@ -2439,6 +2443,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "pool_keep_mb") return g_tune.pool_keep_mb;
   if (k == "landmarks") return g_tune.landmarks;
   if (k == "live_adjacency") return g_tune.live_adjacency;
+  if (k == "expand_prune") return g_tune.expand_prune;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

@@ -472,11 +472,14 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 // expansion-time prune, root side and reached-vertex side (the bit-parallel
 // rows for an undirected graph with t > 0; landmark rows otherwise, or
 // tpad = 0 for none).
+// skip_below: neighbours ranked below it are left unvisited (the window
+// start; 0 visits every neighbour, as the paper's algorithm does).
 // ev0 / ev1 and ev2 / ev3 (optional): start and end of the test kernel and
 // of the expansion kernel, recorded by their dispatches.
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
-                            int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3);
+                            int d, int group, int xgroup, int chunk, int32_t skip_below,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2,
+                            hipEvent_t ev3);
 // Landmark rows out uint8[n][kLandmarks] of a window whose searches pruned
 // nothing (W >= kLandmarks): distance from its j-th root to every vertex,
 // 255 if not reached.  Run before the window's commit clears its masks.

@@ -566,7 +566,7 @@ struct FrontierFlush {
 // unvisited before any memory is read (counted in `earlier`).
 __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t *vs, int32_t x,
                                       int d, int32_t s, uint32_t &direct, uint32_t &earlier) {
-  if (x < s) {
+  if (x < s) {  // s: the window start, or 0 when this skip is switched off
     earlier++;
     return false;
   }
@@ -582,7 +582,7 @@ __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb, DBp vb,
                                                        DStore st, DWindow w, DFrontier f, int d,
-                                                       int chunk) {
+                                                       int chunk, int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
@@ -648,7 +648,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       int32_t x = 0;
       if (idx < lim) {
         x = g.col[e0 + idx];
-        claimed = reach(vb, rr, vs, x, d, w.s, c_direct, c_earlier);
+        claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
         c_claim += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush, u);
@@ -688,7 +688,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
                                                       DFrontier f, int d, int chunk,
-                                                      int lim_inline) {
+                                                      int lim_inline, int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
@@ -720,7 +720,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
       int32_t x = 0;
       if (e < b) {
         x = g.col[e];
-        claimed = reach(vb, rr, vs, x, d, w.s, c_direct, c_earlier);
+        claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
       }
       stage.push(claimed, j, x, flush, u);
     }
@@ -1016,8 +1016,9 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 }
 
 hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
-                            int d, int group, int xgroup, int chunk, hipStream_t st,
-                            hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2, hipEvent_t ev3) {
+                            int d, int group, int xgroup, int chunk, int32_t skip_below,
+                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2,
+                            hipEvent_t ev3) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
   switch (group) {
@@ -1029,22 +1030,22 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow 
   }
   switch (xgroup) {
     case 4:
-      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
       break;
     case 8:
-      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
       break;
     case 16:
-      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
       break;
     case 32:
-      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
       break;
     default:
-      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk);
+      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
       break;
   }
-  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk);
+  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk, skip_below);
   return hipGetLastError();
 }
 

@@ -169,3 +169,46 @@ def bp_query(d, m1, m0, a: int, b: int) -> int:
                 return dx + 1
             best = min(best, via(da, m1[a, i], m0[a, i]) + via(db, m1[b, i], m0[b, i]))
     return best
+
+
+def _frontier_edges(row_ptr, frontier):
+    """(source, edge index) of every adjacency entry of the frontier's rows."""
+    starts = row_ptr[frontier]
+    deg = row_ptr[frontier + 1] - starts
+    tot = int(deg.sum())
+    if tot == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    first = np.cumsum(deg) - deg
+    idx = np.arange(tot, dtype=np.int64) - np.repeat(first, deg) + np.repeat(starts, deg)
+    return np.repeat(frontier, deg), idx
+
+
+def canonical_label_one(row_ptr, col, rank, bp, u: int) -> dict[int, int]:
+    """``canonical_labels`` for one vertex ``u`` (input id) of a large graph:
+    one BFS from u with the min-key recurrence, touching only the rows of
+    each frontier.  ``rank`` int64[n] (id -> rank), ``bp`` bool[n] (used by
+    the bit-parallel phase).  Returns {hub_rank: dist}; empty for u in B."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    n = len(rank)
+    if bp[u]:
+        return {}
+    key = np.where(bp, -1, rank).astype(np.int64)
+    dist = np.full(n, INF, np.int64)
+    M = np.full(n, np.iinfo(np.int64).max, np.int64)
+    dist[u] = 0
+    M[u] = key[u]
+    frontier = np.array([u], np.int64)
+    lvl = 0
+    while len(frontier):
+        p, idx = _frontier_edges(row_ptr, frontier)
+        w = np.asarray(col[idx], np.int64)
+        fresh = (dist[w] == INF) | (dist[w] == lvl + 1)
+        p, w = p[fresh], w[fresh]
+        newv = np.unique(w[dist[w] == INF])
+        dist[newv] = lvl + 1
+        np.minimum.at(M, w, M[p])
+        M[newv] = np.minimum(M[newv], key[newv])
+        frontier = newv
+        lvl += 1
+    hit = np.nonzero((dist < INF) & (~bp) & (M == key))[0]
+    return {int(rank[h]): int(dist[h]) for h in hit}

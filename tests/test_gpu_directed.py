@@ -4,6 +4,7 @@ on an MI355X (``-m gpu``)."""
 import numpy as np
 import pytest
 
+import graphs
 import oracle
 from paper_1304_4661_amd import binding, gen
 from test_gpu_parity import Tuned, all_pairs
@@ -169,3 +170,18 @@ def test_directed_paths(name, g, window):
         else:
             assert all((y, x) in arcs for x, y in zip(v[nz].tolist(), p[nz].tolist()))
             assert np.array_equal(D[h[nz], p[nz]], d[nz] - 1)
+
+
+def test_directed_level_255_reached_but_pruned():
+    # both searches from a_0 reach w at 255 and prune it there (the graph as
+    # a digraph with both arcs of every edge); windows re-run on the range
+    # flag, the plain form does not need to
+    _require_gpu()
+    g, order = graphs.level_255_pruned()
+    ox = oracle.build_directed(g.row_ptr, g.col, order)
+    p = all_pairs(g.n)
+    want = oracle.query_directed(ox, p)
+    for kw in ({}, {"plain": True}):
+        gx = binding.build(g.row_ptr, g.col, order, 0, directed=True, **kw)
+        assert_same_directed(gx, ox, f"level255 {kw}")
+        assert np.array_equal(gx.query(p), want)

@@ -377,3 +377,60 @@ def test_live_adjacency(live, t_bp):
     assert st["windows"] == sy["windows"] and st["windows"] > 4 and g.n > 4096
     on, off = (st, sy) if live else (sy, st)
     assert on["edges"] + on["task_edges"] < off["edges"] + off["task_edges"]
+
+
+@pytest.mark.parametrize("t_bp", [0, 1])
+def test_level_255_reached_but_pruned(t_bp):
+    # Section 4.5.1's 8-bit distances: the BFS from a_0 reaches w at 255 and
+    # must prune it there.  With the default windows x and a_0 share the first
+    # window, where a_0 cannot yet prune with x's labels: the window's test at
+    # 255 flags a range error and the window is run again with fewer roots
+    # until a_0 runs after x is committed.  The plain form runs one root at a
+    # time from the start.
+    _require_gpu()
+    g, order = graphs.level_255_pruned()
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    assert ox.counters["max_dist"] == 254
+    p = all_pairs(g.n)
+    want = oracle.query(ox, p)
+    for tag, kw, knobs in (("windows", {}, {}), ("plain", {"plain": True}, {}),
+                           ("window 2", {}, {"window": 2, "window_work": 0})):
+        with Tuned(**knobs):
+            gx = binding.build(g.row_ptr, g.col, order, t_bp, **kw)
+        assert_same_index(gx, ox, f"level255 t_bp={t_bp} {tag}")
+        assert np.array_equal(gx.query(p), want), tag
+        if tag == "windows" and t_bp == 0:
+            assert gx.stats()["retries"] > 0  # the range flag re-ran the window
+
+
+P9_CASES = [("ba2000", gen.ba_graph(2000, 4, 1), 16), ("rmat11", gen.rmat_graph(11, seed=5), 8),
+            ("rmat11t0", gen.rmat_graph(11, seed=5), 0), ("grid", graphs.grid(9, 11), 2),
+            ("union", graphs.disjoint_union(graphs.cycle(7), graphs.star(9), graphs.empty(2)), 1)]
+
+
+@pytest.mark.parametrize("name,g,t_bp", P9_CASES, ids=[c[0] for c in P9_CASES])
+def test_plain_counters_equal_the_oracle(name, g, t_bp):
+    # Work counters are canonical (the visited set of root k is {v_k} plus the
+    # neighbours of what k labels), so the plain GPU form, with the
+    # expansion-time shortcuts off, does exactly the sequential algorithm's
+    # work.  Offsets: the GPU labels a root at distance 0 without its test
+    # (the oracle tests it and always keeps it), so its normal tests and
+    # scanned entries lack one test and |L(v_k)| entries per root.
+    _require_gpu()
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    c = ox.counters
+    with Tuned(expand_prune=0):
+        gx = binding.build(g.row_ptr, g.col, order, t_bp, plain=True)
+    assert_same_index(gx, ox, name)
+    s = gx.stats()
+    assert s["roots"] == c["roots"]
+    assert s["visited"] == c["visited"]
+    assert s["candidates"] == c["labeled"] == c["entries"]
+    assert s["edges"] + s["task_edges"] == c["edges"]
+    assert s["normal_tests"] + c["roots"] == c["normal_tests"]
+    assert s["label_scanned"] + c["root_staged"] == c["label_scanned"]
+    assert s["earlier_root"] == 0 and s["bp_direct"] == 0
+    # the same knob on the windowed form changes the work, not the labels
+    with Tuned(expand_prune=0):
+        assert_same_index(binding.build(g.row_ptr, g.col, order, t_bp), ox, name + " windows")
