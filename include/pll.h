@@ -162,6 +162,30 @@ int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8
                     uint32_t flags, void *stream);
 
 /*
+ * pll_query without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, answers and errors as pll_query.
+ * pll_query allocates per call a 4-byte error flag (device pointers) or
+ * device staging for the pairs and answers (host pointers); here both live
+ * in one static device array of pll_query_noalloc_max_pairs() * 9 + 256
+ * bytes (about 18.9 MB) that every GPU the library runs on holds until the
+ * process ends.
+ *   - Host pointers: q may not exceed pll_query_noalloc_max_pairs()
+ *     (2,097,152): larger q is PLL_E_INVAL, nothing written.  The call
+ *     synchronises the stream.
+ *   - Device pointers: no limit on q (nothing is staged); the flag is
+ *     cleared by a kernel (no memset), so the call may be captured in a HIP
+ *     graph when PLL_SYNC is not set.
+ * The array is shared by every call on the same GPU and keeps the last
+ * call's contents: calls on one GPU that overlap in time (other streams or
+ * host threads) race on it and must be serialised by the caller.  Call it
+ * with the index's device current.
+ */
+int pll_query_noalloc(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+                      uint32_t flags, void *stream);
+int64_t pll_query_noalloc_max_pairs(void);
+
+/*
  * Autotuner of the batched query kernels: times every lane group size
  * (16, 32 and 64 lanes per pair) on q sample pairs of this index (3 timed
  * launches each after a warm-up, HIP events on stream), sets the

@@ -36,7 +36,8 @@ EXPORTED = [
     "pll_server_done", "pll_server_stop", "pll_serve_bench", "pll_set_allocator",
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
     "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents",
-    "pll_export_weighted_parents", "pll_server_submit_weighted",
+    "pll_export_weighted_parents", "pll_server_submit_weighted", "pll_query_noalloc",
+    "pll_query_noalloc_max_pairs",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -69,6 +70,10 @@ def _lib():
         lib.pll_build_batch.restype = C.c_int
         lib.pll_query_batch.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
         lib.pll_query_batch.restype = C.c_int
+        lib.pll_query_noalloc.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
+        lib.pll_query_noalloc.restype = C.c_int
+        lib.pll_query_noalloc_max_pairs.argtypes = []
+        lib.pll_query_noalloc_max_pairs.restype = C.c_int64
         lib.pll_sync.argtypes = [P, P]
         lib.pll_sync.restype = C.c_int
         lib.pll_export_sizes.argtypes = [P, C.c_int32, P, P, P]
@@ -137,6 +142,11 @@ def _ptr(a):
 def _check(rc: int, what: str):
     if rc != OK:
         raise PllError(rc, what)
+
+
+def noalloc_max_pairs() -> int:
+    """Largest host-pointer request of pll_query_noalloc."""
+    return int(_lib().pll_query_noalloc_max_pairs())
 
 
 def set_tuning(key: str, value: int):
@@ -225,6 +235,32 @@ class Index:
         _check(_lib().pll_query(self._h, C.c_void_p(pairs.data_ptr()), q,
                                 C.c_void_p(out.data_ptr()), flags,
                                 C.c_void_p(stream.cuda_stream)), "query_device")
+
+    def query_noalloc(self, pairs, out=None, stream=None, plain: bool = False,
+                      sync: bool = True):
+        """pll_query_noalloc: host arrays (``pairs`` int32[q, 2] -> new
+        uint8[q]) or, with ``out`` given, torch device tensors as in
+        query_device."""
+        flags = PLAIN if plain else 0
+        if out is None:
+            pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+            res = np.zeros(len(pairs), np.uint8)
+            _check(_lib().pll_query_noalloc(self._h, _ptr(pairs), len(pairs), _ptr(res), flags,
+                                            None), "query_noalloc")
+            return res
+        import torch
+
+        assert pairs.dtype == torch.int32 and out.dtype == torch.uint8
+        assert pairs.is_cuda and out.is_cuda and pairs.is_contiguous() and out.is_contiguous()
+        q = out.numel()
+        assert pairs.numel() == 2 * q
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        flags |= DEVICE_PTRS | (SYNC if sync else 0)
+        _check(_lib().pll_query_noalloc(self._h, C.c_void_p(pairs.data_ptr()), q,
+                                        C.c_void_p(out.data_ptr()), flags,
+                                        C.c_void_p(stream.cuda_stream)), "query_noalloc")
+        return out
 
     def sync(self, stream=None):
         s = None if stream is None else C.c_void_p(stream.cuda_stream)

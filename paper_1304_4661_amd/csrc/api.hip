@@ -1719,6 +1719,7 @@ namespace pll {
 DIndex index_view(const pll_index *idx) { return idx->view(); }
 int32_t index_n(const pll_index *idx) { return idx->n; }
 bool index_weighted(const pll_index *idx) { return idx->weighted; }
+int32_t *index_err(const pll_index *idx) { return idx->err.p; }
 int64_t query_group_size() { return tuning().qgroup; }
 int64_t serve_coalesce() { return tuning().serve_coalesce; }
 }  // namespace pll

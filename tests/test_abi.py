@@ -205,3 +205,12 @@ def test_autotune_rejects_bad_arguments():
     pairs = np.zeros(2, np.int32)
     best = C.c_int32()
     assert lib.pll_autotune_query(None, pairs.ctypes.data, 1, 0, None, C.byref(best)) == binding.E_INVAL
+
+
+def test_query_noalloc_rejects_bad_arguments_without_device_work():
+    lib = binding.library()
+    p = np.zeros(4, np.int32)
+    out = np.zeros(2, np.uint8)
+    assert lib.pll_query_noalloc(None, p.ctypes.data, 2, out.ctypes.data, 0, None) == binding.E_INVAL
+    assert lib.pll_query_noalloc(None, p.ctypes.data, -1, out.ctypes.data, 0, None) == binding.E_INVAL
+    assert binding.noalloc_max_pairs() == 1 << 21
