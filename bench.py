@@ -27,11 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PLL index build s & edges/s; queries/s + p99 latency, batched vs plain"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_test_traffic_rmat18.json")
-XTRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_win_expand_traffic_rmat18.json")
 LEVEL_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "pruned.hip")
-WTRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ww_step_traffic_rmat18w.json")
 WSTEP_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "weighted.hip")
+QUERY_KERNEL_SRC = os.path.join(ROOT, "paper_1304_4661_amd", "csrc", "query.hip")
 
 
 def describe(name, g, t_bp, q):
@@ -175,29 +173,127 @@ def copy_bandwidth_gbs(dev):
     return gbs
 
 
-def cpu_baseline(g, order, t_bp, pairs):
-    """The oracle as it stands: single thread on a host core, full workload."""
+def load_golden(name):
+    """The oracle's stored results for a full-size workload (digests, work
+    counters, build timing with per-root checkpoints), or None."""
+    path = os.path.join(ROOT, "tests", "golden", f"full_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def cpu_baseline(g, order, t_bp, pairs, name, prefix_here_s=12.0):
+    """The oracle as it stands, one thread.  Small workloads: the whole step
+    (index build + every query).  Workloads whose full oracle build takes
+    minutes to an hour (R-MAT 20 / 22): a bounded sample, the same oracle on
+    the same CSR stopped after a prefix of the roots -- relabel, the whole
+    bit-parallel phase and the pruned BFSs of ranks below K -- timed live,
+    with the pruned phase scaled to all roots by the share of the pruned-phase
+    time that the prefix took in a full run of the oracle (stored with the
+    workload's digests, per-root checkpoints, same CSR).  Queries are scaled
+    from that full run's query time by the live/stored bit-parallel-phase
+    ratio (the host speed ratio).  Returns the report and the oracle's work
+    counters of the whole workload."""
     import oracle
 
     directed = bool(g.meta.get("directed"))
+    gold = None if directed else load_golden(name)
+    if gold is None or "ck_s" not in gold.get("times", {}):
+        t0 = time.perf_counter()
+        ox = (oracle.build_directed(g.row_ptr, g.col, order) if directed
+              else oracle.build(g.row_ptr, g.col, order, t_bp))
+        tb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        (oracle.query_directed if directed else oracle.query)(ox, pairs)
+        tq = time.perf_counter() - t0
+        entries = (len(ox.out_hub) + len(ox.in_hub)) if directed else ox.counters["entries"]
+        nt = query_threads()
+        qmt = oracle_query_rate_mt(oracle.query_directed if directed else oracle.query, ox, pairs,
+                                   nt)
+        return {
+            "value": edges_of(g) / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": (f"whole step on the same workload: oracle index build ({tb:.2f} s) + "
+                       f"{len(pairs)} queries ({tq:.2f} s), one thread"),
+            "build_s": tb, "queries_per_s": len(pairs) / tq,
+            "query_threads": nt, "queries_per_s_threads": qmt,
+            "entries": entries,
+        }, dict(ox.counters)
+    assert gen_sha(g, order) == gold["csr_sha256"], "workload differs from the stored oracle run"
+    T = gold["times"]
+    ck, step = T["ck_s"], T["ck_step"]
+    i = next((i for i, x in enumerate(ck) if x >= prefix_here_s), len(ck) - 1)
+    K = i * step
     t0 = time.perf_counter()
-    ox = (oracle.build_directed(g.row_ptr, g.col, order) if directed
-          else oracle.build(g.row_ptr, g.col, order, t_bp))
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    (oracle.query_directed if directed else oracle.query)(ox, pairs)
-    tq = time.perf_counter() - t0
-    entries = (len(ox.out_hub) + len(ox.in_hub)) if directed else ox.counters["entries"]
-    nt = query_threads()
-    qmt = oracle_query_rate_mt(oracle.query_directed if directed else oracle.query, ox, pairs, nt)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp, check_symmetric=False, root_limit=K)
+    t_live = time.perf_counter() - t0
+    bp_live, pr_live = ox.times["bp_s"], ox.times["pruned_s"]
+    ox.close()
+    other = t_live - bp_live - pr_live  # relabel, adjacency sort, export
+    share = ck[i] / T["pruned_s"]
+    build_est = other + bp_live + pr_live / share
+    host_ratio = bp_live / T["bp_s"]
+    q_est = gold["query_s"] * host_ratio * len(pairs) / gold["pairs"]
     return {
-        "value": edges_of(g) / (tb + tq), "unit": "edges/s", "cores": 1, "kind": "oracle",
-        "sample": (f"whole step on the same workload: oracle index build ({tb:.2f} s) + "
-                   f"{len(pairs)} queries ({tq:.2f} s), one thread"),
-        "build_s": tb, "queries_per_s": len(pairs) / tq,
-        "query_threads": nt, "queries_per_s_threads": qmt,
-        "entries": entries,
-    }
+        "value": edges_of(g) / (build_est + q_est), "unit": "edges/s", "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle on the same CSR, one thread, stopped after the pruned BFSs of "
+                   f"ranks < {K} of {g.n}: relabel + bit-parallel phase ({bp_live:.1f} s) + "
+                   f"{K} roots ({pr_live:.1f} s), {t_live:.1f} s live; the prefix took "
+                   f"{100 * share:.2f}% of the pruned-phase time of a full oracle run on "
+                   f"the same CSR ({gold['cpu_model']}), so the pruned phase is scaled by "
+                   f"{1 / share:.1f}; {len(pairs)} queries scaled from that run's "
+                   f"{gold['query_s']:.1f} s by the live/stored bit-parallel-phase time "
+                   f"({host_ratio:.2f})"),
+        "build_s_estimated": build_est, "query_s_estimated": q_est,
+        "live_s": t_live, "prefix_roots": K,
+        "full_run": {"build_s": gold["build_s"], "bp_s": T["bp_s"], "pruned_s": T["pruned_s"],
+                     "query_s": gold["query_s"], "pairs": gold["pairs"],
+                     "cpu_model": gold["cpu_model"], "threads": 1,
+                     "csr_sha256": gold["csr_sha256"], "kind": "cached"},
+        "entries": gold["counters"]["entries"],
+    }, dict(gold["counters"])
+
+
+def gen_sha(g, order):
+    from paper_1304_4661_amd import gen
+
+    return gen.csr_sha256(g, order)
+
+
+def s8d_bytes(c, n, t_bp):
+    """Algorithmic bytes of the build from the oracle's canonical work
+    counters (the visited, labeled and scanned sets are a function of graph,
+    order and t_bp alone), per the byte model of the method:
+      bit-parallel phase, per slot: 8 B row offsets + 17 B slot write per
+        vertex reached, 5 B (neighbour + distance) per adjacency entry
+        scanned, 16 B (two 64-bit sets) per E0 / E1 edge;
+      pruned phase, per root: 5 B per entry of the root's label staged into
+        T, 17 B per slot of its bit-parallel label; per vertex visited:
+        16 B label offsets + 17 B per slot of its bit-parallel label, 5 B per
+        entry of its label scanned by the normal test; per vertex labeled:
+        8 B row offsets + 5 B append; per adjacency entry scanned: 5 B
+        (neighbour + visited byte);
+      finalize: 2 x (5 B per entry + 8 B per vertex)."""
+    bp = 25 * c["bp_reached"] + 5 * c["bp_edges"] + 16 * (c["bp_e0"] + c["bp_e1"])
+    pruned = (5 * c["root_staged"] + 17 * t_bp * c["roots"] + (16 + 17 * t_bp) * c["visited"]
+              + 5 * c["label_scanned"] + 13 * c["labeled"] + 5 * c["edges"])
+    final = 2 * (5 * c["entries"] + 8 * n)
+    return bp, pruned, final
+
+
+def query_pair_bytes(t_bp, lens_s, lens_t):
+    """Bytes a batch of distance queries must move whatever the kernel: per
+    pair 8 B (the pair) + 1 B (the answer), and per side 16 B label offsets,
+    t_bp B bit-parallel distance row and 5 B per label entry up to and
+    including the sentinel (hub 4 B + distance 1 B), the merge join reading
+    both labels to the end (Section 3.3).  The bit-parallel sets (16 B per
+    slot and side, Section 5.3) are read only for slots whose distances can
+    still beat the best estimate, so they are not counted (the method's
+    per-pair figure counts them all: + 32 x t_bp B per pair, reported
+    beside)."""
+    q = len(lens_s)
+    return 9 * q + 2 * (16 + t_bp) * q + 5 * (int(lens_s.sum()) + int(lens_t.sum()) + 2 * q)
 
 
 def cpu_baseline_batch(gs, vtx_off, t_bp, pairs, budget_s=20.0):
@@ -225,41 +321,56 @@ def cpu_baseline_batch(gs, vtx_off, t_bp, pairs, budget_s=20.0):
                        f"oracle index builds + their queries, one thread, {t_done:.1f} s")}
 
 
-def serve(args):
-    """Serving: index resident on the GPU, requests of log-uniform size in
-    [1, 4096] pairs arriving as a Poisson process; X_sat = saturated
+def serving_loads(ix, nreq, max_batch=4096):
+    """Serving on a device-resident index: requests of log-uniform size in
+    [1, max_batch] pairs arrive as a Poisson process; X_sat = saturated
     requests/s (all requests at once), then offered loads of 0.25, 0.5 and
-    0.85 X_sat.  Batched = continuous batching over 4 slots; plain = one
-    launch per request."""
-    import torch
+    0.85 X_sat, each with nreq requests.  Batched = continuous batching over
+    4 slots; plain = one launch per request.  Latency counts from the
+    scheduled arrival (open loop, so queueing counts)."""
+    from paper_1304_4661_amd import binding
 
-    from paper_1304_4661_amd import binding, gen
-
-    name = args.config if args.config != "rmat18" else "rmat22"
-    g, order, t_bp, _ = gen.config_graph(name)
-    dev = torch.device("cuda:0")
-    weighted = g.w is not None
-    arrays = (g.row_ptr, g.col, g.w, order) if weighted else (g.row_ptr, g.col, order)
-    d = [torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev) for a in arrays]
-    t0 = time.perf_counter()
-    ix = (binding.build_weighted(*d, device=True) if weighted
-          else binding.build_device(*d, t_bp))
-    build_s = time.perf_counter() - t0
-    st = ix.stats()
-    nreq = args.serve_requests
     res = {}
     for mode, co in (("batched", 1), ("plain", 0)):
         binding.set_tuning("serve_coalesce", co)
-        binding.serve_bench(ix, 0.0, min(nreq, 2000), seed=104)  # warm-up
-        sat = binding.serve_bench(ix, 0.0, nreq, seed=105)
+        binding.serve_bench(ix, 0.0, min(nreq, 2000), max_batch=max_batch, seed=104)  # warm-up
+        sat = binding.serve_bench(ix, 0.0, nreq, max_batch=max_batch, seed=105)
         loads = {}
         for f in (0.25, 0.5, 0.85):
-            r = binding.serve_bench(ix, f * sat["requests_per_s"], nreq, seed=106)
+            r = binding.serve_bench(ix, f * sat["requests_per_s"], nreq, max_batch=max_batch,
+                                    seed=106)
             loads[str(f)] = {k: r[k] for k in ("p50_us", "p99_us", "mean_us", "pairs_per_s",
                                                 "requests_per_s", "pairs_per_launch")}
         res[mode] = {"x_sat_requests_per_s": sat["requests_per_s"],
                      "x_sat_pairs_per_s": sat["pairs_per_s"], "loads": loads}
     binding.set_tuning("serve_coalesce", 1)
+    return res
+
+
+def serve(args):
+    """Serving run on its own (see serving_loads)."""
+    import torch
+
+    from paper_1304_4661_amd import binding, gen
+
+    name = args.config
+    g, order, t_bp, _ = gen.config_graph(name)
+    dev = torch.device("cuda:0")
+    weighted = g.w is not None
+    arrays = (g.row_ptr, g.col, g.w, order) if weighted else (g.row_ptr, g.col, order)
+    d = [torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev) for a in arrays]
+
+    def build():
+        return (binding.build_weighted(*d, device=True) if weighted
+                else binding.build_device(*d, t_bp))
+
+    build().close()  # warm-up build: later builds reuse the library's cached blocks
+    t0 = time.perf_counter()
+    ix = build()
+    build_s = time.perf_counter() - t0
+    st = ix.stats()
+    nreq = args.serve_requests
+    res = serving_loads(ix, nreq)
     print(json.dumps({
         "metric": "PLL serving: queries/s and p50/p99 request latency at offered loads",
         "value": res["batched"]["x_sat_pairs_per_s"], "unit": "queries/s",
@@ -276,15 +387,42 @@ def serve(args):
     }))
 
 
+def traffic_for(kernel, config, src):
+    """HBM bytes per launch of `kernel` on `config`, from the rocprofv3
+    FETCH_SIZE and WRITE_SIZE passes stored in
+    profiles/traffic_<kernel>_<config>.json (scaled by a plain copy of known
+    size); None when the kernel's source changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{config}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_source_sha") != file_sha(src):
+        return None
+    return tr.get("bytes_per_launch")
+
+
+def kernel_roofline(kernel, desc, nbytes, secs, launches, build_ns, copy_gbs, traffic):
+    ach = nbytes / secs / 1e9 if secs > 0 else None
+    return {
+        "kernel": f"{kernel} ({desc})", "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
+        "achieved": ach, "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": traffic,
+        "copy_gbs": copy_gbs, "frac_of_copy": (ach / copy_gbs) if ach else None,
+        "launches": launches, "avg_launch_us": (secs / launches * 1e6) if launches else None,
+        "algorithmic_bytes_per_launch": nbytes / launches if launches else None,
+        "share_of_build": (secs / (build_ns * 1e-9)) if build_ns else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="rmat18")
+    ap.add_argument("--config", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the plain-form and latency measurements")
+                    help="skip the plain-form, serving and latency measurements")
     ap.add_argument("--serve", action="store_true",
                     help="serving run instead: saturated rate, then Poisson loads")
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -334,6 +472,8 @@ def main():
     else:
         g, order, t_bp, pairs = gen.config_graph(args.config)
         gs, vtx_off = [g], np.array([0, g.n], np.int64)
+    print(f"workload {args.config}: n={g.n} m={edges_of(g)} t_bp={t_bp} pairs={len(pairs)}",
+          file=sys.stderr, flush=True)
     q = len(pairs)
     d_row = torch.from_numpy(g.row_ptr).to(dev)
     d_col = torch.from_numpy(g.col).to(dev)
@@ -369,6 +509,7 @@ def main():
     ix.close()
     torch.cuda.synchronize()
     copy_gbs = copy_bandwidth_gbs(dev)
+    print(f"warm-up done; timing {args.steps} steps", file=sys.stderr, flush=True)
 
     build_s, query_ms, stats = [], [], []
     torch.cuda.synchronize()
@@ -384,49 +525,20 @@ def main():
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     ms_per_step = 1e3 * total / args.steps
+    print(f"timed steps done: {ms_per_step:.1f} ms per step", file=sys.stderr, flush=True)
 
     st = stats[-1]
-    lvl_bytes = level_kernel_bytes(st, t_bp, 2 if directed else 1)
-    lvl_s = st["level_ns"] * 1e-9
     launches = st["level_launches"]
-    achieved = lvl_bytes / lvl_s / 1e9 if lvl_s > 0 else None
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
-            traffic = tr.get("bytes_per_launch")
-    roofline_test = {
-        "kernel": "k_win_test (pruned-BFS prune tests, all roots of a window, one level)",
-        "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-        "achieved": achieved, "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-        "traffic": traffic,
-        "copy_gbs": copy_gbs, "frac_of_copy": (achieved / copy_gbs) if achieved else None,
-        "launches": launches, "avg_launch_us": (lvl_s / launches * 1e6) if launches else None,
-        "algorithmic_bytes_per_launch": lvl_bytes / launches if launches else None,
-        "share_of_build": lvl_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
-    }
-    # the expansion kernel: one launch per level, like the test kernel
-    x_bytes = expand_kernel_bytes(st, t_bp)
-    x_s = st["expand_ns"] * 1e-9
-    x_ach = x_bytes / x_s / 1e9 if x_s > 0 else None
-    x_traffic = None
-    if os.path.exists(XTRAFFIC_FILE):
-        with open(XTRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha") == file_sha(LEVEL_KERNEL_SRC) and tr.get("config") == args.config:
-            x_traffic = tr.get("bytes_per_launch")
-    roofline_expand = {
-        "kernel": "k_win_expand (pruned-BFS expansion, all roots of a window, one level)",
-        "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS,
-        "achieved": x_ach, "frac": (x_ach / HBM_PEAK_GBS) if x_ach else None,
-        "traffic": x_traffic,
-        "copy_gbs": copy_gbs, "frac_of_copy": (x_ach / copy_gbs) if x_ach else None,
-        "launches": launches, "avg_launch_us": (x_s / launches * 1e6) if launches else None,
-        "algorithmic_bytes_per_launch": x_bytes / launches if launches else None,
-        "share_of_build": x_s / (st["build_ns"] * 1e-9) if st["build_ns"] else None,
-    }
-    # "roofline" is the kernel with the larger share of the build; the
+    src = LEVEL_KERNEL_SRC
+    roofline_test = kernel_roofline(
+        "k_win_test", "pruned-BFS prune tests, all roots of a window, one level",
+        level_kernel_bytes(st, t_bp, 2 if directed else 1), st["level_ns"] * 1e-9, launches,
+        st["build_ns"], copy_gbs, traffic_for("k_win_test", args.config, src))
+    roofline_expand = kernel_roofline(
+        "k_win_expand", "pruned-BFS expansion, all roots of a window, one level",
+        expand_kernel_bytes(st, t_bp), st["expand_ns"] * 1e-9, launches, st["build_ns"],
+        copy_gbs, traffic_for("k_win_expand", args.config, src))
+    # "roofline" is the level kernel with the larger share of the build; the
     # other one is reported beside it
     if (roofline_expand["share_of_build"] or 0) > (roofline_test["share_of_build"] or 0):
         roofline, other = roofline_expand, ("roofline_prune_test", roofline_test)
@@ -444,7 +556,7 @@ def main():
                    "n": g.n, "m": edges_of(g), "t_bp": t_bp, "queries": q},
         "build_s": float(np.median(build_s)),
         "build_edges_per_s": edges_of(g) / float(np.median(build_s)),
-        "queries_per_s": q / (float(np.median(query_ms)) / 1e3),
+        "queries_per_s": q / (float(np.median(query_ms)) / 1e3) if q else None,
         "query_batch_ms_p50": pctl(query_ms, 50), "query_batch_ms_p99": pctl(query_ms, 99),
         "query_lanes_per_pair": qgroup,
         "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}",
@@ -457,6 +569,25 @@ def main():
         other[0]: other[1],
     }
 
+    # the batched query kernel: bytes every pair must move (see
+    # query_pair_bytes) over the step's query launches (events on the stream)
+    lens_s = lens_t = None
+    if q and not batch and not directed:
+        ix = build()
+        rank, lens = ix.label_lengths()
+        ix.close()
+        lens_s, lens_t = lens[rank[pairs[:, 0]]], lens[rank[pairs[:, 1]]]
+        qb = query_pair_bytes(t_bp, lens_s, lens_t)
+        qs = float(np.median(query_ms)) * 1e-3
+        qr = kernel_roofline("k_query_group", f"batched distance queries, {q} pairs in one launch",
+                             qb, qs, 1, None, copy_gbs,
+                             traffic_for("k_query_group", args.config, QUERY_KERNEL_SRC))
+        qr.pop("share_of_build")
+        qr["bytes_per_pair"] = qb / q
+        qr["method_bytes_per_pair"] = qb / q + 32 * t_bp
+        qr["method_rate_gbs"] = (qb + 32 * t_bp * q) / qs / 1e9
+        out["roofline_query"] = qr
+
     if not args.no_extras:
         ix = build()
         rates = {}
@@ -465,12 +596,13 @@ def main():
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
+            reps = 5 if not plain else 2
             e0.record(stream)
-            for _ in range(5):
+            for _ in range(reps):
                 ix.query_device(d_pairs, d_out, stream=stream, plain=plain)
             e1.record(stream)
             torch.cuda.synchronize()
-            rates["plain" if plain else "batched"] = 5 * q / (e0.elapsed_time(e1) / 1e3)
+            rates["plain" if plain else "batched"] = reps * q / (e0.elapsed_time(e1) / 1e3)
         lat = {}
         for bs in (1, 64, 4096):
             sub = d_pairs[:bs].contiguous()
@@ -482,6 +614,10 @@ def main():
                 torch.cuda.synchronize()
                 xs.append((time.perf_counter() - t1) * 1e6)
             lat[str(bs)] = {"p50_us": pctl(xs[20:], 50), "p99_us": pctl(xs[20:], 99)}
+        if args.config in ("rmat22", "rmat20") and not directed:
+            out["serving"] = serving_loads(ix, args.serve_requests)
+            out["serving"]["requests_per_load"] = args.serve_requests
+            print("serving loads done", file=sys.stderr, flush=True)
         ix.close()
         # plain (one root at a time) vs windowed build on the small BA workload
         gb, ob, tb_, _ = gen.config_graph("ba2000")
@@ -501,11 +637,33 @@ def main():
 
     binding.set_tuning("profile", 0)
     if not args.no_cpu_baseline:
+        print("oracle baseline", file=sys.stderr, flush=True)
         if batch:
             out["cpu_baseline"] = cpu_baseline_batch(gs, vtx_off, t_bp, pairs)
+            counters = None
         else:
-            out["cpu_baseline"] = cpu_baseline(g, order, t_bp, pairs)
+            out["cpu_baseline"], counters = cpu_baseline(g, order, t_bp, pairs, args.config)
         out["cpu_baseline"]["cpu_model"] = cpu_model()
+        if counters and not directed:
+            # the method's byte model over the oracle's canonical work, per
+            # GPU phase; the windowed form's extra work beside it
+            bpb, prb, fib = s8d_bytes(counters, g.n, t_bp)
+            qm = (query_pair_bytes(t_bp, lens_s, lens_t) + 32 * t_bp * q) if lens_s is not None else 0
+            bp_s, pr_s = st["bp_ns"] * 1e-9, st["pruned_ns"] * 1e-9
+            out["method_bytes"] = {
+                "source": "oracle work counters of the same workload",
+                "bit_parallel_bytes": bpb, "pruned_bytes": prb, "finalize_bytes": fib,
+                "query_bytes": qm,
+                "bit_parallel_frac": bpb / bp_s / 1e9 / HBM_PEAK_GBS if bp_s else None,
+                "pruned_frac": (prb + fib) / pr_s / 1e9 / HBM_PEAK_GBS if pr_s else None,
+                "whole_step_frac": (bpb + prb + fib + qm) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "windowed_overhead": {
+                    "gpu_visits": st["visited"], "canonical_visits": counters["visited"],
+                    "gpu_candidates": st["candidates"], "entries": counters["entries"],
+                    "extra_candidates": st["candidates"] - counters["entries"],
+                    "expansion_skips_by_rank": st["earlier_root"],
+                    "expansion_skips_by_distance_rows": st["bp_direct"]},
+            }
     print(json.dumps(out))
 
 
@@ -564,12 +722,7 @@ def bench_weighted(args):
     lvl_s = st["level_ns"] * 1e-9
     launches = st["level_launches"]
     achieved = step_bytes / lvl_s / 1e9 if lvl_s > 0 else None
-    traffic = None
-    if os.path.exists(WTRAFFIC_FILE):
-        with open(WTRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_source_sha") == file_sha(WSTEP_KERNEL_SRC) and tr.get("config") == args.config:
-            traffic = tr.get("bytes_per_launch")
+    traffic = traffic_for("k_ww_step", args.config, WSTEP_KERNEL_SRC)
     out = {
         "metric": METRIC, "value": g.m / (ms_per_step / 1e3), "unit": "edges/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,

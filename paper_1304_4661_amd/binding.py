@@ -348,6 +348,16 @@ class Index:
                                                  "rank"))), "export")
         return out
 
+    def label_lengths(self, graph: int = 0):
+        """(rank int32[n]: id -> rank, lengths int64[n] of the normal labels
+        by rank, no sentinels), without copying the labels."""
+        n, _, _ = self.sizes(graph)
+        off = np.zeros(n + 1, np.int64)
+        rank = np.zeros(n, np.int32)
+        _check(_lib().pll_export(self._h, graph, _ptr(off), None, None, None, None, None,
+                                 _ptr(rank)), "export")
+        return rank, np.diff(off)
+
     def query_weighted(self, pairs, plain: bool = False) -> np.ndarray:
         """Weighted index, host arrays: ``pairs`` int32[q, 2] ids ->
         uint32[q] (WINF: unreachable or too far)."""

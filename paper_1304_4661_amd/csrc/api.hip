@@ -664,6 +664,11 @@ struct Builder {
     DBuf<LevelCtl> ctl;
     PinnedMirror mirror;  // level counters and the own store's pool top
     DFrontier f;
+    // each level's entries grouped by root for the prune tests
+    DBuf<uint32_t> rc, rfill;
+    DBuf<int64_t> roff, toff;
+    DBuf<int32_t> sv, spar;
+    DRootSort rsort{};
     DWindow window(int32_t s, int32_t nr, int words, const uint8_t *used) const {
       return DWindow{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
                      cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, cpar.p,
@@ -753,6 +758,16 @@ struct Builder {
     D.ctl.alloc(1);
     D.f = DFrontier{D.fslot.p, D.fv.p,  D.fcap,  D.h1.p, D.h1.p + D.hcap, D.h1.p + 2 * D.hcap,
                     D.hcap,    nullptr, nullptr, nullptr, D.ctl.p,         D.fpar.p};
+    D.rc.alloc(2 * (size_t)wmax);
+    D.rfill.alloc((size_t)wmax);
+    D.roff.alloc((size_t)wmax + 1);
+    D.toff.alloc((size_t)wmax + 1);
+    D.sv.alloc((size_t)D.fcap);
+    if (parents) D.spar.alloc((size_t)D.fcap);
+    fill(D.rc, 0, st);
+    fill(D.rfill, 0, st);
+    D.rsort = DRootSort{D.rc.p, D.rc.p + wmax, D.rfill.p, D.roff.p, D.toff.p,
+                        D.sv.p, parents ? D.spar.p : nullptr, D.fcap};
     D.mirror.p->ctl = LevelCtl{};
     D.mirror.p->top = 0;
   }
@@ -762,7 +777,7 @@ struct Builder {
   int side_levels(Side &D, const DBp &bp, const DBp &rb, const DBp &vb, const DWindow &w,
                   int64_t window_index, std::vector<hipEvent_t> &evs) {
     LevelCtl &h = D.mirror.p->ctl;
-    const DStore sto = D.own->view();
+    const DStore sto = D.own->view(), rsto = D.roots->view();
     const size_t mark0 = level_trace.size();
     check(launch_win_reset_ctl(D.ctl.p, st));
     check(launch_win_init(D.g, w, D.roots->view(), D.f, w.W, D.hsize.p, D.htmp.p, st));
@@ -772,7 +787,8 @@ struct Builder {
       const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
       for (; d < upto; d++) {
         hipEvent_t *e = evs.empty() ? nullptr : &evs[4 * (size_t)(d - d0)];
-        check(launch_win_level(D.g, bp, rb, vb, sto, w, D.f, d, test_group, tu.xgroup, tu.chunk,
+        check(launch_win_level(D.g, bp, rb, vb, sto, rsto, w, D.f, D.rsort, d, test_group, tu.xgroup,
+                               tu.chunk,
                                tu.expand_prune ? w.s : 0, st, e ? e[0] : nullptr,
                                e ? e[1] : nullptr, e ? e[2] : nullptr, e ? e[3] : nullptr));
         stat_levels++;

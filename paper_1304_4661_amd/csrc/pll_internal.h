@@ -327,6 +327,23 @@ struct DWindow {
   const uint8_t *used;  // [n] 1 for bit-parallel roots and neighbours
 };
 
+// One BFS level of a window, grouped by root: the prune tests run root by
+// root, each root's label table and bit-parallel row staged in LDS.  rc0 /
+// rc1 count the entries of each window root on the levels of even / odd
+// index (the expansion that makes a level adds its claims), roff / toff are
+// their exclusive scans over entries and over tasks of at most kTaskEntries
+// entries (roff[W] = entries, toff[W] = tasks), rfill the scatter cursors,
+// and sv / spar the level's vertices (and parents) in root order.
+constexpr int kTaskEntries = 1024;
+struct DRootSort {
+  uint32_t *rc0, *rc1;  // [W]
+  uint32_t *rfill;      // [W]
+  int64_t *roff;        // [W+1]
+  int64_t *toff;        // [W+1]
+  int32_t *sv, *spar;   // [cap] (spar null unless parents are kept)
+  int64_t cap;
+};
+
 // ---------------------------------------------------------------------------
 // Weighted graphs (pruned Dijkstra searches, Section 7).
 
@@ -472,14 +489,16 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
 // expansion-time prune, root side and reached-vertex side (the bit-parallel
 // rows for an undirected graph with t > 0; landmark rows otherwise, or
 // tpad = 0 for none).
+// s: the store labeled by this side's searches; rst: the store the roots'
+// labels come from (s itself for an undirected graph).
 // skip_below: neighbours ranked below it are left unvisited (the window
 // start; 0 visits every neighbour, as the paper's algorithm does).
 // ev0 / ev1 and ev2 / ev3 (optional): start and end of the test kernel and
 // of the expansion kernel, recorded by their dispatches.
-hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
-                            int d, int group, int xgroup, int chunk, int32_t skip_below,
-                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2,
-                            hipEvent_t ev3);
+hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DStore rst, DWindow w,
+                            DFrontier f, DRootSort rs, int d, int group, int xgroup, int chunk,
+                            int32_t skip_below, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                            hipEvent_t ev2, hipEvent_t ev3);
 // Landmark rows out uint8[n][kLandmarks] of a window whose searches pruned
 // nothing (W >= kLandmarks): distance from its j-th root to every vertex,
 // 255 if not reached.  Run before the window's commit clears its masks.

@@ -238,15 +238,18 @@ struct BpTally {
 
 // zk, zu: bp.z[k] and bp.z[u] (read by the caller together with its other
 // loads).
+// krow / kpairs: the root's distance row (bp.tpad bytes) and its t set pairs,
+// staged in LDS by the caller.
 template <int G>
-__device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, int d,
+__device__ __forceinline__ bool bp_prunes(const DBp &bp, const uint4 *krow,
+                                          const ulonglong2 *kpairs, int32_t u, int d,
                                           uint64_t zk, uint64_t zu, BpTally &tally) {
   const int gr = Group<G>::rank();
   const int nv = bp.tpad >> 4;
   bool direct = false;
   uint64_t need1 = 0, need2 = 0;  // slots where only -2 helps / where -1 or -2 helps
   if (gr < nv) {
-    const uint4 a = reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad)[gr];
+    const uint4 a = krow[gr];
     const uint4 b = reinterpret_cast<const uint4 *>(bp.d + (int64_t)u * bp.tpad)[gr];
     const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
     const uint32_t K1 = (uint32_t)(d + 1) * 0x00010001u, K2 = (uint32_t)(d + 2) * 0x00010001u;
@@ -273,15 +276,24 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
   need2 &= zk | zu;
   if (!(need1 | need2)) return false;
   if (gr == 0) tally.sets++;
-  const ulonglong2 *pk = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)k * bp.t;
+  const ulonglong2 *pk = kpairs;
   const ulonglong2 *pu = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)u * bp.t;
+  // each lane takes R slots of the queue per round, so that a round's loads
+  // (one 16-byte pair of u per slot; the root's come from LDS) are in flight
+  // together
+  constexpr int R = G >= 16 ? 1 : 16 / G;
   uint64_t rest2 = need2, rest1 = need1;
   while (rest2 | rest1) {
-    // deal the next G slots of the queue (need2 first) to the lanes
-    int mine = -1;
-    bool mine2 = false;
+    // deal the next G * R slots of the queue (need2 first) to the lanes
+    int mine[R];
+    bool mine2[R];
 #pragma unroll
-    for (int r = 0; r < G; r++) {
+    for (int r = 0; r < R; r++) {
+      mine[r] = -1;
+      mine2[r] = false;
+    }
+#pragma unroll
+    for (int it = 0; it < G * R; it++) {
       int i = -1;
       bool is2 = false;
       if (rest2) {
@@ -292,31 +304,26 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, int32_t k, int32_t u, i
         i = __ffsll((unsigned long long)rest1) - 1;
         rest1 &= rest1 - 1;
       }
-      if (r == gr) {
-        mine = i;
-        mine2 = is2;
+      if (it % G == gr) {
+        mine[it / G] = i;
+        mine2[it / G] = is2;
       }
     }
+    ulonglong2 mu[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) mu[r] = mine[r] >= 0 ? pu[mine[r]] : make_ulonglong2(0ull, 0ull);
     bool pr = false;
-    if (mine >= 0) {
-      tally.checks++;  // one slot pair per lane
-      const ulonglong2 mk = pk[mine], mu = pu[mine];
-      pr = (mk.x & mu.x) != 0 || (mine2 && ((mk.y & mu.x) | (mk.x & mu.y)) != 0);
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+      if (mine[r] < 0) continue;
+      tally.checks++;  // one slot pair
+      const ulonglong2 mk = pk[mine[r]];
+      pr |= (mk.x & mu[r].x) != 0 || (mine2[r] && ((mk.y & mu[r].x) | (mk.x & mu[r].y)) != 0);
     }
     if (Group<G>::any(pr)) return true;
   }
   return false;
 }
-
-// Normal-label test against the root's table (Section 4.5.1): is some
-// (h, delta) of L(u) with delta + d(k, h) <= d?  Stops at the first step
-// that finds one.  Each lane takes U entries per step (G*U per group), so
-// their hub loads, and then their table probes, are in flight together.  A
-// hub is probed only when its bit is set in the 256-bit signature of the
-// root's label (held in registers): with short root labels most hubs of
-// L(u) cost no probe.  An empty root label prunes nothing.
-// o, len: L(u)'s place in the store; s01, s23: the root's signature (all
-// read by the caller together with its other loads).
 template <int G>
 __device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, ulonglong2 s01,
                                              ulonglong2 s23, int64_t o, int32_t len, int d) {
@@ -362,6 +369,58 @@ __device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, ulo
       }
     }
     if (Group<G>::any(hit)) return true;
+  }
+  return false;
+}
+
+// The root's table in LDS: open addressing over 32-bit slots holding
+// hub << 8 | distance (hub ranks below 2^24 - 1), kEmpty32 when free, sized
+// to a power of two >= 4 |L(k)| (at most kLdsSlots, so roots with labels of
+// up to kLdsSlots / 4 entries; longer labels, or graphs of 2^24 - 1 or more
+// vertices, use the window's table in global memory).
+constexpr int kLdsSlots = 4096;
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+
+// Normal-label test against the LDS table: as label_prunes, without the
+// signature (an LDS probe is cheaper than the signature's registers).
+template <int G>
+__device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint32_t *tab,
+                                                 uint32_t mask, int64_t o, int32_t len, int d) {
+  constexpr int U = 4;
+  constexpr uint32_t kNoHub = 0xFFFFFFFFu;
+  const int gr = Group<G>::rank();
+  if (len == 0) return false;
+  const uint32_t *hp = st.hub + o;
+  const uint8_t *dp = st.dist + o;
+  uint32_t hh[U];
+#pragma unroll
+  for (int i = 0; i < U; i++) {
+    const int32_t e = i * G + gr;
+    hh[i] = e < len ? hp[e] : kNoHub;
+  }
+  for (int32_t base = 0; base < len; base += G * U) {
+    // the next step's hubs are loaded while this step probes the table
+    uint32_t hn[U];
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      const int32_t e = base + G * U + i * G + gr;
+      hn[i] = e < len ? hp[e] : kNoHub;
+    }
+    bool hit = false;
+#pragma unroll
+    for (int i = 0; i < U; i++) {
+      if (hh[i] == kNoHub) continue;
+      uint32_t sl = ht_hash(hh[i]) & mask;
+      uint32_t e = tab[sl];
+      while (e != kEmpty32 && (e >> 8) != hh[i]) {
+        sl = (sl + 1) & mask;
+        e = tab[sl];
+      }
+      if (e != kEmpty32) hit |= (int)dp[base + i * G + gr] + (int)(e & 0xFFu) <= d;
+    }
+    if (Group<G>::any(hit)) return true;
+#pragma unroll
+    for (int i = 0; i < U; i++) hh[i] = hn[i];
   }
   return false;
 }
@@ -418,45 +477,137 @@ struct RootRow {
   }
 };
 
-// Groups of 8 or more lanes serve long label scans, which want every wave
-// the CU can hold (measured: R-MAT 18 with t_bp = 0 builds 13% faster at 8
-// waves per SIMD, a few registers spilled); 4-lane groups keep all their
-// registers (short scans, many tests per wave).
-template <int G>
-constexpr int kTestWavesPerSimd = G >= 8 ? 8 : 1;
+// Level d of the window, grouped by root (DRootSort).  k_root_scan (one
+// block) publishes where level d+1 will start, clears the counts the
+// expansion of level d is about to make, and for d >= 1 turns the counts of
+// level d into entry offsets per root and tasks of at most kTaskEntries
+// entries; k_root_scatter copies the level's vertices to their root's run.
+constexpr int kScanThreads = 1024;
 
+__global__ void __launch_bounds__(kScanThreads) k_root_scan(DRootSort rs, LevelCtl *ctl,
+                                                            int32_t W, int d) {
+  __shared__ int64_t s_e[kScanThreads], s_t[kScanThreads];
+  if (threadIdx.x == 0) ctl->base[d + 1] = ctl->base[d] + ctl->cnt[d];
+  const uint32_t *rc = (d & 1) ? rs.rc1 : rs.rc0;
+  uint32_t *rnext = (d & 1) ? rs.rc0 : rs.rc1;
+  const int per = (W + kScanThreads - 1) / kScanThreads;
+  const int j0 = (int)threadIdx.x * per;
+  int64_t se = 0, stk = 0;
+  for (int i = 0; i < per; i++) {
+    const int j = j0 + i;
+    if (j >= W) break;
+    const uint32_t c = d > 0 ? rc[j] : 0u;
+    se += c;
+    stk += (c + kTaskEntries - 1) / kTaskEntries;
+    rnext[j] = 0u;
+    rs.rfill[j] = 0u;
+  }
+  s_e[threadIdx.x] = se;
+  s_t[threadIdx.x] = stk;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {  // inclusive scan of both sums
+    const int64_t ae = threadIdx.x >= (unsigned)o ? s_e[threadIdx.x - o] : 0;
+    const int64_t at = threadIdx.x >= (unsigned)o ? s_t[threadIdx.x - o] : 0;
+    __syncthreads();
+    s_e[threadIdx.x] += ae;
+    s_t[threadIdx.x] += at;
+    __syncthreads();
+  }
+  if (d == 0) return;
+  int64_t re = s_e[threadIdx.x] - se, rt = s_t[threadIdx.x] - stk;
+  for (int i = 0; i < per; i++) {
+    const int j = j0 + i;
+    if (j >= W) break;
+    const uint32_t c = rc[j];
+    rs.roff[j] = re;
+    rs.toff[j] = rt;
+    re += c;
+    rt += (c + kTaskEntries - 1) / kTaskEntries;
+  }
+  if (threadIdx.x == kScanThreads - 1) {
+    rs.roff[W] = s_e[kScanThreads - 1];
+    rs.toff[W] = s_t[kScanThreads - 1];
+  }
+}
+
+// One lane per entry of level d.  Lanes of a wave that share a root take
+// their places with one atomic (entries of one candidate's expansion are
+// adjacent, so a wave holds few roots).
+__global__ void __launch_bounds__(kBlock) k_root_scatter(DRootSort rs, DFrontier f, int d) {
+  LevelCtl *ctl = f.ctl;
+  const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
+  if (d == 0 || cnt == 0 || (ctl->flags & kOverflowFlags) ||
+      beg + cnt > (unsigned long long)f.cap || cnt > (unsigned long long)rs.cap)
+    return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nloop = ((int64_t)cnt + stride - 1) / stride;
+  for (int64_t it = 0; it < nloop; it++) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
+    const bool valid = p < (int64_t)cnt;
+    const int32_t j = valid ? f.slot[beg + p] : -1;
+    uint64_t act = __ballot(valid);
+    while (act) {
+      const int leader = __ffsll((unsigned long long)act) - 1;
+      const int32_t jl = __shfl(j, leader);
+      const uint64_t m = __ballot(valid && j == jl) & act;
+      uint32_t b = 0;
+      if (lane_id() == leader) b = atomicAdd(&rs.rfill[jl], (uint32_t)__popcll(m));
+      b = __shfl(b, leader);
+      if ((m >> lane_id()) & 1ull) {
+        const int64_t q = rs.roff[jl] + b + __popcll(m & lanes_below_mask());
+        rs.sv[q] = f.v[beg + p];
+        if (rs.spar) rs.spar[q] = f.par[beg + p];
+      }
+      act &= ~m;
+    }
+  }
+}
+
+// k_win_test: the prune tests of level d, one task (a run of at most
+// kTaskEntries entries of one root k = s + j) per block at a time.  The
+// block first stages the root's data in LDS -- its label as a hash table
+// (the role of the paper's T, Section 4.5.1 "Querying") and its
+// bit-parallel distance row and set pairs -- then a group of G lanes per
+// entry (j, u) runs the bit-parallel test and the normal-label test of u at
+// distance d.  If neither prunes, u gets the candidate label (k, d).
+constexpr int kTStage = 128;  // staged candidates per wave
+
+// st: the store of the labels being tested (L(u)); rst: the store the
+// roots' labels come from (the same for an undirected graph; the other
+// side's for a digraph).
 template <int G>
-__global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test(DGraph g, DBp bp,
-                                                                         DStore st, DWindow w,
-                                                     DFrontier f, int d) {
-  __shared__ int32_t s_a[kWavesPerBlock][kStage];
-  __shared__ int32_t s_b[kWavesPerBlock][kStage];
-  __shared__ int32_t s_c[kWavesPerBlock][kStage];
+__global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
+                                                     DWindow w, DFrontier f, DRootSort rs,
+                                                     int d) {
+  __shared__ uint32_t s_ht[kLdsSlots];
+  __shared__ uint4 s_krow[4];
+  __shared__ ulonglong2 s_kpairs[64];
+  __shared__ int32_t s_a[kWavesPerBlock][kTStage];
+  __shared__ int32_t s_b[kWavesPerBlock][kTStage];
+  __shared__ int32_t s_c[kWavesPerBlock][kTStage];
   __shared__ int32_t s_n[kWavesPerBlock];
+  __shared__ int32_t s_qu[kWavesPerBlock][32], s_qp[kWavesPerBlock][32];
   __shared__ unsigned long long s_base, s_sum[6];
+  __shared__ int64_t s_task[3];
   __shared__ bool s_go;
   LevelCtl *ctl = f.ctl;
   const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
-  const unsigned long long nbase = beg + cnt;
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->base[d + 1] = nbase;
-  // the roots (level 0) were labeled by k_win_init;
-  // after an overflow the window is redone; never read past the buffer.
-  // One thread decides for the block (the flags may change meanwhile).
   if (threadIdx.x < 6) s_sum[threadIdx.x] = 0;
+  // the roots (level 0) were labeled by k_win_init; after an overflow the
+  // window is redone.  One thread decides for the block.
   if (threadIdx.x == 0)
     s_go = !(d == 0 || cnt == 0 || (ctl->flags & kOverflowFlags) ||
-             nbase > (unsigned long long)f.cap);
+             beg + cnt > (unsigned long long)f.cap || cnt > (unsigned long long)rs.cap);
   __syncthreads();
   if (!s_go) return;
+  const int64_t ntasks = rs.toff[w.W];
   const int gr = Group<G>::rank();
-  constexpr int kPerWave = kWave / G;
+  constexpr int kGA = 4, kPerA = kWave / kGA, kPerB = kWave / G;
   const int wv = threadIdx.x / kWave;
-  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
-  WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv], w.cp ? s_c[wv] : nullptr);
+  WaveStage<kTStage> stage;
+  stage.init(s_a[wv], s_b[wv], rs.spar ? s_c[wv] : nullptr);
   // candidates (u, j[, parent]): write them at list slots from c0
-  auto write_out = [&](WaveStage<kStage> &sg, unsigned long long c0) {
+  auto write_out = [&](WaveStage<kTStage> &sg, unsigned long long c0) {
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long c = c0 + i;
       if (c < (unsigned long long)w.ccap) {
@@ -469,47 +620,125 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test(DGrap
       }
     }
   };
-  auto flush = [&](WaveStage<kStage> &sg) { write_out(sg, sg.reserve(&ctl->ccnt)); };
+  auto flush = [&](WaveStage<kTStage> &sg) { write_out(sg, sg.reserve(&ctl->ccnt)); };
+  const bool small_ranks = g.n < (1 << 24) - 1;
   uint32_t c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
   BpTally tally;
-  // the wave steps through the level in lockstep, kPerWave entries at a time
-  for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
-    const int64_t p = base + lane_id() / G;
-    bool labeled = false;
-    int32_t u = 0, j = 0, par = 0;
-    if (p < (int64_t)cnt) {
-      j = f.slot[beg + p];
-      u = f.v[beg + p];
-      if (f.par) par = f.par[beg + p];
-      if (gr == 0) c_visit++;
-      // everything both tests may read that depends only on (j, u) is
-      // loaded now, so the loads are in flight together
-      const uint64_t zk = bp.t ? bp.z[w.s + j] : 0ull, zu = bp.t ? bp.z[u] : 0ull;
-      const int64_t lo = st.off[u];
-      const int32_t llen = st.len[u];
-      const RootTable Tj = root_table(w, j);
-      const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
-      const ulonglong2 s01 = sg[0], s23 = sg[1];
-      // bit-parallel labels first (Section 5.4)
-      bool pr = bp_prunes<G>(bp, w.s + j, u, d, zk, zu, tally);
-      if (!pr) {
-        pr = label_prunes<G>(st, Tj, s01, s23, lo, llen, d);
+  for (int64_t t = blockIdx.x; t < ntasks; t += gridDim.x) {
+    if (threadIdx.x == 0) {
+      // the root of task t: the last j with toff[j] <= t
+      int32_t lo = 0, hi = w.W;
+      while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (rs.toff[mid] <= t) lo = mid;
+        else hi = mid;
+      }
+      const int64_t a0 = rs.roff[lo] + (t - rs.toff[lo]) * (int64_t)kTaskEntries;
+      const int64_t a1 = rs.roff[lo + 1] < a0 + kTaskEntries ? rs.roff[lo + 1] : a0 + kTaskEntries;
+      s_task[0] = lo;
+      s_task[1] = a0;
+      s_task[2] = a1;
+    }
+    __syncthreads();  // also: every lane is done with the previous task's LDS
+    const int32_t j = (int32_t)s_task[0];
+    const int64_t t0 = s_task[1], t1 = s_task[2];
+    const int32_t k = w.s + j;
+    const int32_t klen = rst.len[k];
+    const bool in_lds = small_ranks && klen <= kLdsSlots / 4;
+    uint32_t mask = 0;
+    if (in_lds) {
+      uint32_t sz = 16;
+      while (sz < 4u * (uint32_t)klen) sz <<= 1;
+      mask = sz - 1;
+      for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) s_ht[i] = kEmpty32;
+    }
+    if (bp.t) {
+      if (threadIdx.x < (unsigned)(bp.tpad >> 4))
+        s_krow[threadIdx.x] = reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad)[threadIdx.x];
+      if (threadIdx.x < (unsigned)bp.t)
+        s_kpairs[threadIdx.x] =
+            reinterpret_cast<const ulonglong2 *>(bp.m)[(int64_t)k * bp.t + threadIdx.x];
+    }
+    __syncthreads();
+    if (in_lds) {
+      const int64_t ko = rst.off[k];
+      for (int32_t e = threadIdx.x; e < klen; e += blockDim.x) {
+        const uint32_t h = rst.hub[ko + e];
+        const uint32_t ent = (h << 8) | (uint32_t)rst.dist[ko + e];
+        uint32_t sl = ht_hash(h) & mask;
+        while (atomicCAS(&s_ht[sl], kEmpty32, ent) != kEmpty32) sl = (sl + 1) & mask;
+      }
+    }
+    __syncthreads();
+    const uint64_t zk = bp.t ? bp.z[k] : 0ull;
+    const RootTable Tj = root_table(w, j);
+    const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
+    // Phase A, kGA lanes per entry (16 entries per wave): the bit-parallel
+    // test; survivors wait in the wave's LDS queue.  Phase B, G lanes per
+    // entry: the normal-label test of kPerB queued entries at a time.
+    int qn = 0;  // queued entries (wave-uniform)
+    int32_t *qu = s_qu[wv], *qp = s_qp[wv];
+    auto phase_b = [&](int nb) {
+      const int e = lane_id() / G;
+      bool labeled = false;
+      int32_t u = 0, par = 0;
+      if (e < nb) {
+        u = qu[qn - nb + e];
+        par = qp[qn - nb + e];
+        const int64_t lo = st.off[u];
+        const int32_t llen = st.len[u];
+        const bool pr = in_lds ? label_prunes_lds<G>(st, s_ht, mask, lo, llen, d)
+                               : label_prunes<G>(st, Tj, sg[0], sg[1], lo, llen, d);
         if (gr == 0) {
           c_test++;
           c_scan += (uint32_t)llen;
         }
+        labeled = !pr && gr == 0;
+        if (labeled) {
+          c_lab++;
+          w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
+          atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
+                   1ull << (j & 63));
+          atomicOr((unsigned long long *)&w.csum[4 * (int64_t)u + (j >> 12)],
+                   1ull << ((j >> 6) & 63));
+        }
       }
-      labeled = !pr && gr == 0;
-      if (labeled) {
-        c_lab++;
-        w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
-        atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
-                 1ull << (j & 63));
-        atomicOr((unsigned long long *)&w.csum[4 * (int64_t)u + (j >> 12)],
-                 1ull << ((j >> 6) & 63));
+      stage.push(labeled, u, j, flush, par);
+    };
+    for (int64_t b0 = t0 + wv * kPerA; b0 < t1; b0 += kWavesPerBlock * kPerA) {
+      const int64_t p = b0 + lane_id() / kGA;
+      const int gra = lane_id() & (kGA - 1);
+      bool survive = false;
+      int32_t u = 0, par = 0;
+      if (p < t1) {
+        u = rs.sv[p];
+        if (rs.spar) par = rs.spar[p];
+        if (gra == 0) c_visit++;
+        // bit-parallel labels first (Section 5.4)
+        survive = true;
+        if (bp.t) {
+          const uint64_t zu = bp.z[u];
+          survive = !bp_prunes<kGA>(bp, s_krow, s_kpairs, u, d, zk, zu, tally);
+        }
+      }
+      const uint64_t m = __ballot(survive && gra == 0);
+      if (survive && gra == 0) {
+        const int pos = qn + __popcll(m & lanes_below_mask());
+        qu[pos] = u;
+        qp[pos] = par;
+      }
+      qn += __popcll(m);
+      __threadfence_block();  // the queue entries are visible to the whole wave
+      while (qn >= kPerB) {
+        phase_b(kPerB);
+        qn -= kPerB;
       }
     }
-    stage.push(labeled, u, j, flush, par);
+    while (qn > 0) {
+      const int nb = qn < kPerB ? qn : kPerB;
+      phase_b(nb);
+      qn -= nb;
+    }
   }
   write_out(stage, block_reserve(stage, &ctl->ccnt, s_n, &s_base));
   const unsigned long long sums[6] = {
@@ -581,8 +810,9 @@ __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t
 
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb, DBp vb,
-                                                       DStore st, DWindow w, DFrontier f, int d,
-                                                       int chunk, int32_t skip_below) {
+                                                       DStore st, DWindow w, DFrontier f,
+                                                       DRootSort rs, int d, int chunk,
+                                                       int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
   __shared__ int32_t s_c[kWavesPerBlock][kStage];
@@ -623,6 +853,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
+  uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;
   uint32_t c_edge = 0, c_direct = 0, c_earlier = 0, c_claim = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
@@ -642,6 +873,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
     }
     uint32_t *vs = w.vis + (int64_t)j * g.nwords;
     const int64_t wl = Group<kWave>::max_reduce64(lim);
+    uint32_t mine = 0;  // this candidate's claims, counted toward its root's run
     for (int64_t e = 0; e < wl; e += G) {
       const int64_t idx = e + gr;
       bool claimed = false;
@@ -649,10 +881,13 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       if (idx < lim) {
         x = g.col[e0 + idx];
         claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
-        c_claim += claimed ? 1u : 0u;
+        mine += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush, u);
     }
+    c_claim += mine;
+    const unsigned long long gclaims = Group<G>::sum_reduce(mine);
+    if (gr == 0 && gclaims) atomicAdd(&rnext[j], (uint32_t)gclaims);
     // chunks of long lists become heavy tasks (one reservation per wave)
     const int64_t extra = act && deg > lim ? (deg - lim + chunk - 1) / chunk : 0;
     unsigned long long tb =
@@ -687,7 +922,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
-                                                      DFrontier f, int d, int chunk,
+                                                      DFrontier f, DRootSort rs, int d, int chunk,
                                                       int lim_inline, int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
@@ -703,6 +938,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
+  uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;
   unsigned long long c_edge = 0;  // the same in every lane (whole-wave tasks)
   uint32_t c_direct = 0, c_earlier = 0;
   for (int64_t tk = wid; tk < ntasks; tk += nw) {
@@ -714,6 +950,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
     RootRow rr;
     rr.load(rb, w.s + j);
     c_edge += (unsigned long long)(b - a);
+    uint32_t mine = 0;
     for (int64_t e0b = a; e0b < b; e0b += kWave) {
       const int64_t e = e0b + lane_id();
       bool claimed = false;
@@ -721,9 +958,12 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
       if (e < b) {
         x = g.col[e];
         claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
+        mine += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush, u);
     }
+    const unsigned long long tclaims = Group<kWave>::sum_reduce(mine);
+    if (lane_id() == 0 && tclaims) atomicAdd(&rnext[j], (uint32_t)tclaims);
   }
   if (stage.n) flush(stage);
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
@@ -1015,37 +1255,46 @@ hipError_t launch_win_init(DGraph g, DWindow w, DStore s, DFrontier f, int32_t n
   return hipGetLastError();
 }
 
-hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DWindow w, DFrontier f,
-                            int d, int group, int xgroup, int chunk, int32_t skip_below,
-                            hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, hipEvent_t ev2,
-                            hipEvent_t ev3) {
+hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DStore rst, DWindow w,
+                            DFrontier f, DRootSort rs, int d, int group, int xgroup, int chunk,
+                            int32_t skip_below, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1,
+                            hipEvent_t ev2, hipEvent_t ev3) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
+  hipLaunchKernelGGL(k_root_scan, dim3(1), dim3(kScanThreads), 0, st, rs, f.ctl, w.W, d);
+  if (d > 0) hipLaunchKernelGGL(k_root_scatter, gd, bd, 0, st, rs, f, d);
+  // at level 0 the test kernel returns at once (the roots are labeled by
+  // k_win_init); it still runs so that its timing events stay paired
   switch (group) {
-    case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
-    case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
-    case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
-    case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
-    default: PLL_LAUNCH_TIMED(k_win_test<64>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    default: PLL_LAUNCH_TIMED(k_win_test<64>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
   }
   switch (xgroup) {
     case 4:
-      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
+      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d, chunk,
+                       skip_below);
       break;
     case 8:
-      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
+      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d, chunk,
+                       skip_below);
       break;
     case 16:
-      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
+      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
+                       chunk, skip_below);
       break;
     case 32:
-      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
+      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
+                       chunk, skip_below);
       break;
     default:
-      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, d, chunk, skip_below);
+      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
+                       chunk, skip_below);
       break;
   }
-  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, d, chunk, chunk, skip_below);
+  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, rs, d, chunk, chunk, skip_below);
   return hipGetLastError();
 }
 

@@ -457,7 +457,8 @@ CONFIGS = {
     "ba2000": ({"kind": "ba", "n": 2000, "m": 4, "seed": 1}, 16, 100_000, 101),
     "rmat18": ({"kind": "rmat", "scale": 18, "seed": 2}, 50, 1_000_000, 102),
     "rmat20": ({"kind": "rmat", "scale": 20, "seed": 3}, 64, 10_000_000, 103),
-    "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 0, 105),
+    # served workload; one batch of 1e7 pairs stands for a step's queries
+    "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 10_000_000, 105),
     # directed (Section 7): R-MAT arcs, no bit-parallel labels
     "rmat18d": ({"kind": "rmat", "directed": True, "scale": 18, "seed": 2}, 0, 1_000_000, 102),
     # weighted (Section 7): integer weights uniform in [1, 100], no bit-parallel labels

@@ -37,3 +37,20 @@ def test_expand_kernel_byte_model():
           "expand_claims": 20}
     assert bench.expand_kernel_bytes(st, 50) == (5 * 66 + 4 * 100 + 60 * 50 + 4 * 30
                                                  + 8 * 20)
+
+
+def test_method_byte_model():
+    c = {"bp_reached": 10, "bp_edges": 40, "bp_e0": 7, "bp_e1": 9, "root_staged": 11,
+         "roots": 3, "visited": 20, "label_scanned": 100, "labeled": 6, "edges": 30,
+         "entries": 6}
+    bp, pr, fi = bench.s8d_bytes(c, 12, 4)
+    assert bp == 10 * (8 + 17) + 40 * 5 + 16 * 16
+    assert pr == 5 * 11 + 17 * 4 * 3 + 20 * (16 + 17 * 4) + 5 * 100 + 6 * (8 + 5) + 5 * 30
+    assert fi == 2 * (5 * 6 + 8 * 12)
+
+
+def test_query_pair_byte_model():
+    import numpy as np
+    ls, lt = np.array([3, 0]), np.array([5, 1])
+    # per pair 9 B, per side 16 + t + 5 (entries + sentinel)
+    assert bench.query_pair_bytes(4, ls, lt) == 2 * 9 + 4 * (16 + 4) + 5 * (4 + 1 + 6 + 2)
