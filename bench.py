@@ -183,23 +183,21 @@ def load_golden(name):
         return json.load(f)
 
 
-def cpu_baseline(g, order, t_bp, pairs, name, prefix_here_s=12.0):
+def cpu_baseline(g, order, t_bp, pairs, name):
     """The oracle as it stands, one thread.  Small workloads: the whole step
-    (index build + every query).  Workloads whose full oracle build takes
-    minutes to an hour (R-MAT 20 / 22): a bounded sample, the same oracle on
-    the same CSR stopped after a prefix of the roots -- relabel, the whole
-    bit-parallel phase and the pruned BFSs of ranks below K -- timed live,
-    with the pruned phase scaled to all roots by the share of the pruned-phase
-    time that the prefix took in a full run of the oracle (stored with the
-    workload's digests, per-root checkpoints, same CSR).  Queries are scaled
-    from that full run's query time by the live/stored bit-parallel-phase
-    ratio (the host speed ratio).  Returns the report and the oracle's work
-    counters of the whole workload."""
+    (index build + every query), live.  Workloads whose full oracle build
+    takes minutes to an hour (R-MAT 20 / 22): a bounded live sample of the
+    same oracle on the same CSR -- relabel plus the bit-parallel BFSs of the
+    first 8 slots, no pruned BFSs -- timed here and on the machine where the
+    full oracle run of the workload was stored with its digests; their ratio
+    (this host's speed relative to that one) scales the stored full build
+    and query times.  Returns the report and the oracle's work counters of
+    the whole workload."""
     import oracle
 
     directed = bool(g.meta.get("directed"))
     gold = None if directed else load_golden(name)
-    if gold is None or "ck_s" not in gold.get("times", {}):
+    if gold is None or "calibration" not in gold:
         t0 = time.perf_counter()
         ox = (oracle.build_directed(g.row_ptr, g.col, order) if directed
               else oracle.build(g.row_ptr, g.col, order, t_bp))
@@ -220,36 +218,32 @@ def cpu_baseline(g, order, t_bp, pairs, name, prefix_here_s=12.0):
             "entries": entries,
         }, dict(ox.counters)
     assert gen_sha(g, order) == gold["csr_sha256"], "workload differs from the stored oracle run"
-    T = gold["times"]
-    ck, step = T["ck_s"], T["ck_step"]
-    i = next((i for i, x in enumerate(ck) if x >= prefix_here_s), len(ck) - 1)
-    K = i * step
-    t0 = time.perf_counter()
-    ox = oracle.build(g.row_ptr, g.col, order, t_bp, check_symmetric=False, root_limit=K)
-    t_live = time.perf_counter() - t0
-    bp_live, pr_live = ox.times["bp_s"], ox.times["pruned_s"]
-    ox.close()
-    other = t_live - bp_live - pr_live  # relabel, adjacency sort, export
-    share = ck[i] / T["pruned_s"]
-    build_est = other + bp_live + pr_live / share
-    host_ratio = bp_live / T["bp_s"]
-    q_est = gold["query_s"] * host_ratio * len(pairs) / gold["pairs"]
+    cal = gold["calibration"]
+    ts = []
+    for _ in range(2):
+        t0 = time.perf_counter()
+        ox = oracle.build(g.row_ptr, g.col, order, cal["t_bp"], check_symmetric=False,
+                          root_limit=cal["root_limit"])
+        ts.append(time.perf_counter() - t0)
+        ox.close()
+    live = min(ts)
+    ratio = live / cal["s"]
+    build_est = gold["build_s"] * ratio
+    q_est = gold["query_s"] * ratio * len(pairs) / gold["pairs"]
     return {
         "value": edges_of(g) / (build_est + q_est), "unit": "edges/s", "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle on the same CSR, one thread, stopped after the pruned BFSs of "
-                   f"ranks < {K} of {g.n}: relabel + bit-parallel phase ({bp_live:.1f} s) + "
-                   f"{K} roots ({pr_live:.1f} s), {t_live:.1f} s live; the prefix took "
-                   f"{100 * share:.2f}% of the pruned-phase time of a full oracle run on "
-                   f"the same CSR ({gold['cpu_model']}), so the pruned phase is scaled by "
-                   f"{1 / share:.1f}; {len(pairs)} queries scaled from that run's "
-                   f"{gold['query_s']:.1f} s by the live/stored bit-parallel-phase time "
-                   f"({host_ratio:.2f})"),
-        "build_s_estimated": build_est, "query_s_estimated": q_est,
-        "live_s": t_live, "prefix_roots": K,
-        "full_run": {"build_s": gold["build_s"], "bp_s": T["bp_s"], "pruned_s": T["pruned_s"],
-                     "query_s": gold["query_s"], "pairs": gold["pairs"],
-                     "cpu_model": gold["cpu_model"], "threads": 1,
+        "sample": (f"oracle on the same CSR, one thread: relabel + bit-parallel BFSs of the "
+                   f"first {cal['t_bp']} slots, no pruned BFSs ({live:.2f} s here, best of 2; "
+                   f"{cal['s']:.2f} s on the {gold['cpu_model']} host where the full oracle "
+                   f"run of this workload took {gold['build_s']:.0f} s + {gold['query_s']:.1f} s "
+                   f"for {gold['pairs']} queries); build and query times scaled by the ratio "
+                   f"{ratio:.3f}"),
+        "build_s_estimated": build_est, "query_s_estimated": q_est, "sample_s": live,
+        "host_speed_ratio": ratio,
+        "full_run": {"build_s": gold["build_s"], "bp_s": gold["times"]["bp_s"],
+                     "pruned_s": gold["times"]["pruned_s"], "query_s": gold["query_s"],
+                     "pairs": gold["pairs"], "cpu_model": gold["cpu_model"], "threads": 1,
                      "csr_sha256": gold["csr_sha256"], "kind": "cached"},
         "entries": gold["counters"]["entries"],
     }, dict(gold["counters"])

@@ -8,6 +8,12 @@ digest and histogram of its answers to the workload's query pairs, its work
 counters and its build time on this machine.  It calls only ``oracle/`` and
 the seeded input generators; nothing here comes from the GPU library.
 
+    python tests/golden/make_full_digests.py --calibrate rmat20|rmat22
+
+adds to an existing file the time of a short oracle run on the same CSR (the
+bit-parallel phase of the first 8 slots, no pruned BFSs), the sample the
+benchmark repeats on its host to scale this machine's full-build time.
+
 Workloads (the generators' named recipes):
   rmat20  R-MAT scale 20, seed 3, Degree order, t_bp = 64, 1e7 pairs (seed 103)
   rmat22  R-MAT scale 22, seed 5, Degree order, t_bp = 64, 1e7 pairs (seed 105)
@@ -79,11 +85,40 @@ def _ba_job(i: int) -> dict:
     return rec
 
 
+CALIBRATION = {"t_bp": 8, "root_limit": 0}
+
+
+def calibrate(name: str, reps: int = 3) -> None:
+    path = os.path.join(HERE, f"full_{name}.json")
+    with open(path) as f:
+        out = json.load(f)
+    g, order, _, _ = gen.config_graph(name)
+    assert gen.csr_sha256(g, order) == out["csr_sha256"]
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ox = oracle.build(g.row_ptr, g.col, order, CALIBRATION["t_bp"], check_symmetric=False,
+                          root_limit=CALIBRATION["root_limit"])
+        ts.append(time.perf_counter() - t0)
+        ox.close()
+    out["calibration"] = dict(CALIBRATION, s=min(ts), runs=ts, cpu_model=cpu_model(),
+                              what="oracle.build of the same CSR with t_bp=8 and "
+                                   "root_limit=0 (relabel + 8 bit-parallel BFSs)")
+    with open(path + ".tmp", "w") as f:
+        json.dump(out, f, indent=1)
+    os.replace(path + ".tmp", path)
+    print(name, "calibration", ts)
+
+
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("name", choices=["rmat20", "rmat22", "ba256"])
     ap.add_argument("--jobs", type=int, default=1)
+    ap.add_argument("--calibrate", action="store_true")
     a = ap.parse_args()
+    if a.calibrate:
+        calibrate(a.name)
+        return
     head = {"made_by": "python tests/golden/make_full_digests.py " + a.name,
             "cpu_model": cpu_model(), "threads_per_build": 1,
             "host_threads": os.cpu_count()}
