@@ -469,8 +469,13 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * toward it after each window; 0 keeps every window at the maximum),
  * "window_mem_mb" (device memory the per-root window state may take; caps
  * the window at about this / (2.4 n) roots), "group" (lanes per frontier
- * entry in the prune tests: 4..64, or 0 (default): 4, 8 or 16 per window,
- * from the label entries a test scanned in the window before), "xgroup" (lanes per candidate expanding
+ * entry in the prune tests: 4..64, or 0 (default): chosen per window from
+ * the label entries a test scanned in the window before), "root_sort" (0:
+ * prune tests straight from the frontier, the root's label through a table
+ * in global memory; 1: each level's entries grouped by root first, every
+ * root's label table and bit-parallel row staged in LDS; 2 (default): 1 for
+ * windows after one that averaged at least "sort_level" (default 2^20)
+ * visits per level, else 0; same labels), "xgroup" (lanes per candidate expanding
  * its adjacency list: 4..64), "list_cap" (upper bound on the entries of
  * the frontier, candidate and task lists, never below what one root needs;
  * 0 = sized from the window; a window that overflows is re-run with a

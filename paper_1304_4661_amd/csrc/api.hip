@@ -38,6 +38,8 @@ struct Tuning {
   int bp_chunk = 64;  // adjacency entries per bit-parallel work item
   int serve_coalesce = 1;  // servers pack several requests per launch
   int expand_prune = 1;  // expansion leaves neighbours unvisited that a test would prune
+  int root_sort = 2;  // prune tests grouped by root: 0 never, 1 always, 2 for large levels
+  int64_t sort_level = 1 << 20;  // visits per level from which "root_sort" 2 groups by root
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -775,7 +777,7 @@ struct Builder {
   // One window's BFS levels in one direction, until every root's search has
   // ended or a list overflowed.  Returns the last level index.
   int side_levels(Side &D, const DBp &bp, const DBp &rb, const DBp &vb, const DWindow &w,
-                  int64_t window_index, std::vector<hipEvent_t> &evs) {
+                  int64_t window_index, std::vector<hipEvent_t> &evs, bool sorted) {
     LevelCtl &h = D.mirror.p->ctl;
     const DStore sto = D.own->view(), rsto = D.roots->view();
     const size_t mark0 = level_trace.size();
@@ -787,7 +789,8 @@ struct Builder {
       const int upto = std::min(d + tu.levels_per_sync, kMaxLevels - 1);
       for (; d < upto; d++) {
         hipEvent_t *e = evs.empty() ? nullptr : &evs[4 * (size_t)(d - d0)];
-        check(launch_win_level(D.g, bp, rb, vb, sto, rsto, w, D.f, D.rsort, d, test_group, tu.xgroup,
+        const DRootSort rs = sorted ? D.rsort : DRootSort{};
+        check(launch_win_level(D.g, bp, rb, vb, sto, rsto, w, D.f, rs, d, test_group, tu.xgroup,
                                tu.chunk,
                                tu.expand_prune ? w.s : 0, st, e ? e[0] : nullptr,
                                e ? e[1] : nullptr, e ? e[2] : nullptr, e ? e[3] : nullptr));
@@ -827,13 +830,22 @@ struct Builder {
   DBuf<int32_t> icol;
 
   // Lanes per prune test for an average scan of `len` label entries: short
-  // labels keep many tests in flight per wave, long ones split a scan.
-  static int group_for_scan(int64_t len) { return len < 48 ? 4 : len < 96 ? 8 : 16; }
+  // labels keep many tests in flight per wave, long ones split a scan.  The
+  // root-grouped kernel reads four entries per lane at a time.
+  static int group_for_scan(int64_t len, bool sorted) {
+    if (!sorted) return len < 48 ? 4 : len < 96 ? 8 : 16;
+    return len < 24 ? 4 : len < 48 ? 8 : len < 96 ? 16 : len < 160 ? 32 : 64;
+  }
   int test_group = 4;
+  // prune tests grouped by root (each root's data in LDS) pay a sort per
+  // level and win on long label scans; short ones test straight from the
+  // frontier
+  bool use_sort = false;
 
   void pruned(pll_index *ix) {
     const int nsides = directed ? 2 : 1;
     test_group = tu.group > 0 ? tu.group : 4;
+    use_sort = tu.root_sort == 1;
     // per-root window state per side: distance column of wd (n B), visited
     // bits (n/8 B) and two mask bits per vertex (n/4 B)
     const int64_t per_root = nsides * ((int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1);
@@ -925,7 +937,7 @@ struct Builder {
           rb = DBp{kLandmarks, kLandmarks, land[nsides - 1 - k].p, nullptr, nullptr};
           vb = DBp{kLandmarks, kLandmarks, land[k].p, nullptr, nullptr};
         }
-        last[k] = side_levels(sides[k], bp, rb, vb, w[k], stat_windows, evs);
+        last[k] = side_levels(sides[k], bp, rb, vb, w[k], stat_windows, evs, use_sort);
         ran[k] = true;
         flags |= sides[k].mirror.p->ctl.flags;
       }
@@ -990,7 +1002,7 @@ struct Builder {
       for (int k = 0; k < nsides; k++)
         check(launch_win_clean(w[k], w[nsides - 1 - k], ncand[k], st));
       double work = 0;
-      int64_t wtests = 0, wscanned = 0;
+      int64_t wtests = 0, wscanned = 0, wvisits = 0, wlevels = 0;
       for (int k = 0; k < nsides; k++) {
         check(launch_win_commit(w[k], sides[k].own->view(), ncand[k], st));
         // the pool top only moves in commits: read back once per window (the
@@ -1015,10 +1027,15 @@ struct Builder {
         work += (double)h.visited + (double)h.bp_direct;
         wtests += (int64_t)h.ntests;
         wscanned += (int64_t)h.lscanned;
+        wvisits += (int64_t)h.visited;
+        wlevels += last[k] + 1;
       }
       // "group" 0: lanes per prune test follow the label entries a test
       // scanned in this window (labels grow as roots commit)
-      if (tu.group == 0 && wtests >= 1024) test_group = group_for_scan(wscanned / wtests);
+      // root grouping pays a sort per level: worth it once levels are large
+      use_sort = tu.root_sort == 1 ||
+                 (tu.root_sort == 2 && wlevels > 0 && wvisits / wlevels >= tu.sort_level);
+      if (tu.group == 0 && wtests >= 1024) test_group = group_for_scan(wscanned / wtests, use_sort);
       stat_windows++;
       trace_mark = level_trace.size();
       s = e;
@@ -2413,6 +2430,12 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "expand_prune") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.expand_prune = (int)value;
+  } else if (k == "root_sort") {
+    if (value < 0 || value > 2) return PLL_E_INVAL;
+    g_tune.root_sort = (int)value;
+  } else if (k == "sort_level") {
+    if (value < 0) return PLL_E_INVAL;
+    g_tune.sort_level = value;
   } else if (k == "pool_keep_mb") {
     if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.pool_keep_mb = value;
@@ -2461,6 +2484,8 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "landmarks") return g_tune.landmarks;
   if (k == "live_adjacency") return g_tune.live_adjacency;
   if (k == "expand_prune") return g_tune.expand_prune;
+  if (k == "root_sort") return g_tune.root_sort;
+  if (k == "sort_level") return g_tune.sort_level;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

@@ -278,22 +278,15 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, const uint4 *krow,
   if (gr == 0) tally.sets++;
   const ulonglong2 *pk = kpairs;
   const ulonglong2 *pu = reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)u * bp.t;
-  // each lane takes R slots of the queue per round, so that a round's loads
-  // (one 16-byte pair of u per slot; the root's come from LDS) are in flight
-  // together
-  constexpr int R = G >= 16 ? 1 : 16 / G;
+  // one slot per lane per round, stopping at the first round that prunes
+  // (measured: fewer pair reads than dealing 16 slots per round)
   uint64_t rest2 = need2, rest1 = need1;
   while (rest2 | rest1) {
-    // deal the next G * R slots of the queue (need2 first) to the lanes
-    int mine[R];
-    bool mine2[R];
+    // deal the next G slots of the queue (need2 first) to the lanes
+    int mine = -1;
+    bool mine2 = false;
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-      mine[r] = -1;
-      mine2[r] = false;
-    }
-#pragma unroll
-    for (int it = 0; it < G * R; it++) {
+    for (int r = 0; r < G; r++) {
       int i = -1;
       bool is2 = false;
       if (rest2) {
@@ -304,21 +297,16 @@ __device__ __forceinline__ bool bp_prunes(const DBp &bp, const uint4 *krow,
         i = __ffsll((unsigned long long)rest1) - 1;
         rest1 &= rest1 - 1;
       }
-      if (it % G == gr) {
-        mine[it / G] = i;
-        mine2[it / G] = is2;
+      if (r == gr) {
+        mine = i;
+        mine2 = is2;
       }
     }
-    ulonglong2 mu[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) mu[r] = mine[r] >= 0 ? pu[mine[r]] : make_ulonglong2(0ull, 0ull);
     bool pr = false;
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-      if (mine[r] < 0) continue;
-      tally.checks++;  // one slot pair
-      const ulonglong2 mk = pk[mine[r]];
-      pr |= (mk.x & mu[r].x) != 0 || (mine2[r] && ((mk.y & mu[r].x) | (mk.x & mu[r].y)) != 0);
+    if (mine >= 0) {
+      tally.checks++;  // one slot pair per lane
+      const ulonglong2 mk = pk[mine], mu = pu[mine];
+      pr = (mk.x & mu.x) != 0 || (mine2 && ((mk.y & mu.x) | (mk.x & mu.y)) != 0);
     }
     if (Group<G>::any(pr)) return true;
   }
@@ -383,44 +371,44 @@ constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 
 // Normal-label test against the LDS table: as label_prunes, without the
 // signature (an LDS probe is cheaper than the signature's registers).
+// Labels in the build's store start at multiples of 16 entries (pool slots
+// are reserved in multiples of 16) and a slot's capacity is a multiple of
+// 16, so a lane reads 4 consecutive entries at once -- 16 bytes of hubs and
+// 4 bytes of distances, both issued before any probe -- and a quad that
+// runs past the label's end stays inside its slot (those entries are
+// masked out).
 template <int G>
 __device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint32_t *tab,
                                                  uint32_t mask, int64_t o, int32_t len, int d) {
-  constexpr int U = 4;
-  constexpr uint32_t kNoHub = 0xFFFFFFFFu;
   const int gr = Group<G>::rank();
   if (len == 0) return false;
-  const uint32_t *hp = st.hub + o;
-  const uint8_t *dp = st.dist + o;
-  uint32_t hh[U];
-#pragma unroll
-  for (int i = 0; i < U; i++) {
-    const int32_t e = i * G + gr;
-    hh[i] = e < len ? hp[e] : kNoHub;
-  }
-  for (int32_t base = 0; base < len; base += G * U) {
-    // the next step's hubs are loaded while this step probes the table
-    uint32_t hn[U];
-#pragma unroll
-    for (int i = 0; i < U; i++) {
-      const int32_t e = base + G * U + i * G + gr;
-      hn[i] = e < len ? hp[e] : kNoHub;
-    }
+  const uint4 *hq = reinterpret_cast<const uint4 *>(st.hub + o);
+  const uint32_t *dq = reinterpret_cast<const uint32_t *>(st.dist + o);
+  const int32_t nq = (len + 3) >> 2;  // quads of entries
+  uint4 h = gr < nq ? hq[gr] : make_uint4(0u, 0u, 0u, 0u);
+  uint32_t dd = gr < nq ? dq[gr] : 0u;
+  for (int32_t q0 = 0; q0 < nq; q0 += G) {
+    // the next step's quads are loaded while this step probes the table
+    const int32_t qn = q0 + G + gr;
+    const uint4 hn = qn < nq ? hq[qn] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t dn = qn < nq ? dq[qn] : 0u;
+    const int32_t e0 = (q0 + gr) * 4;
+    const uint32_t hv[4] = {h.x, h.y, h.z, h.w};
     bool hit = false;
 #pragma unroll
-    for (int i = 0; i < U; i++) {
-      if (hh[i] == kNoHub) continue;
-      uint32_t sl = ht_hash(hh[i]) & mask;
+    for (int i = 0; i < 4; i++) {
+      if (e0 + i >= len) continue;
+      uint32_t sl = ht_hash(hv[i]) & mask;
       uint32_t e = tab[sl];
-      while (e != kEmpty32 && (e >> 8) != hh[i]) {
+      while (e != kEmpty32 && (e >> 8) != hv[i]) {
         sl = (sl + 1) & mask;
         e = tab[sl];
       }
-      if (e != kEmpty32) hit |= (int)dp[base + i * G + gr] + (int)(e & 0xFFu) <= d;
+      if (e != kEmpty32) hit |= (int)((dd >> (8 * i)) & 0xFFu) + (int)(e & 0xFFu) <= d;
     }
     if (Group<G>::any(hit)) return true;
-#pragma unroll
-    for (int i = 0; i < U; i++) hh[i] = hn[i];
+    h = hn;
+    dd = dn;
   }
   return false;
 }
@@ -476,6 +464,126 @@ struct RootRow {
     return hit != 0;
   }
 };
+
+// k_win_test_flat: the prune tests of level d straight from the frontier, a
+// group of G lanes per entry (j, u), the root's label read through the
+// window's global table and its bit-parallel row from memory.  For short
+// labels this costs less than grouping the level by root; long labels go
+// through k_win_test below.
+// Groups of 8 or more lanes serve long label scans, which want every wave
+// the CU can hold (measured: R-MAT 18 with t_bp = 0 builds 13% faster at 8
+// waves per SIMD, a few registers spilled); 4-lane groups keep all their
+// registers (short scans, many tests per wave).
+template <int G>
+constexpr int kTestWavesPerSimd = G >= 8 ? 8 : 1;
+
+template <int G>
+__global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(DGraph g, DBp bp,
+                                                                              DStore st,
+                                                                              DWindow w,
+                                                                              DFrontier f,
+                                                                              int d) {
+  __shared__ int32_t s_a[kWavesPerBlock][kStage];
+  __shared__ int32_t s_b[kWavesPerBlock][kStage];
+  __shared__ int32_t s_c[kWavesPerBlock][kStage];
+  __shared__ int32_t s_n[kWavesPerBlock];
+  __shared__ unsigned long long s_base, s_sum[6];
+  __shared__ bool s_go;
+  LevelCtl *ctl = f.ctl;
+  const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
+  const unsigned long long nbase = beg + cnt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->base[d + 1] = nbase;
+  // the roots (level 0) were labeled by k_win_init;
+  // after an overflow the window is redone; never read past the buffer.
+  // One thread decides for the block (the flags may change meanwhile).
+  if (threadIdx.x < 6) s_sum[threadIdx.x] = 0;
+  if (threadIdx.x == 0)
+    s_go = !(d == 0 || cnt == 0 || (ctl->flags & kOverflowFlags) ||
+             nbase > (unsigned long long)f.cap);
+  __syncthreads();
+  if (!s_go) return;
+  const int gr = Group<G>::rank();
+  constexpr int kPerWave = kWave / G;
+  const int wv = threadIdx.x / kWave;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  WaveStage<kStage> stage;
+  stage.init(s_a[wv], s_b[wv], w.cp ? s_c[wv] : nullptr);
+  // candidates (u, j[, parent]): write them at list slots from c0
+  auto write_out = [&](WaveStage<kStage> &sg, unsigned long long c0) {
+    for (int i = lane_id(); i < sg.n; i += kWave) {
+      const unsigned long long c = c0 + i;
+      if (c < (unsigned long long)w.ccap) {
+        w.cu[c] = sg.a[i];
+        w.cj[c] = sg.b[i];
+        w.cd[c] = (uint8_t)d;
+        if (sg.c) w.cp[c] = sg.c[i];
+      } else {
+        atomicOr(&ctl->flags, kFlagOvfCand);
+      }
+    }
+  };
+  auto flush = [&](WaveStage<kStage> &sg) { write_out(sg, sg.reserve(&ctl->ccnt)); };
+  uint32_t c_visit = 0, c_test = 0, c_scan = 0, c_lab = 0;
+  BpTally tally;
+  // the wave steps through the level in lockstep, kPerWave entries at a time
+  for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
+    const int64_t p = base + lane_id() / G;
+    bool labeled = false;
+    int32_t u = 0, j = 0, par = 0;
+    if (p < (int64_t)cnt) {
+      j = f.slot[beg + p];
+      u = f.v[beg + p];
+      if (f.par) par = f.par[beg + p];
+      if (gr == 0) c_visit++;
+      // everything both tests may read that depends only on (j, u) is
+      // loaded now, so the loads are in flight together
+      const uint64_t zk = bp.t ? bp.z[w.s + j] : 0ull, zu = bp.t ? bp.z[u] : 0ull;
+      const int64_t lo = st.off[u];
+      const int32_t llen = st.len[u];
+      const RootTable Tj = root_table(w, j);
+      const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
+      const ulonglong2 s01 = sg[0], s23 = sg[1];
+      // bit-parallel labels first (Section 5.4)
+      const int32_t k = w.s + j;
+      bool pr = bp_prunes<G>(
+          bp, reinterpret_cast<const uint4 *>(bp.d + (int64_t)k * bp.tpad),
+          reinterpret_cast<const ulonglong2 *>(bp.m) + (int64_t)k * bp.t, u, d, zk, zu, tally);
+      if (!pr) {
+        pr = label_prunes<G>(st, Tj, s01, s23, lo, llen, d);
+        if (gr == 0) {
+          c_test++;
+          c_scan += (uint32_t)llen;
+        }
+      }
+      labeled = !pr && gr == 0;
+      if (labeled) {
+        c_lab++;
+        w.wd[(int64_t)u * (w.words * 64) + j] = (uint8_t)d;
+        atomicOr((unsigned long long *)&w.cmask[(int64_t)u * w.words + (j >> 6)],
+                 1ull << (j & 63));
+        atomicOr((unsigned long long *)&w.csum[4 * (int64_t)u + (j >> 12)],
+                 1ull << ((j >> 6) & 63));
+      }
+    }
+    stage.push(labeled, u, j, flush, par);
+  }
+  write_out(stage, block_reserve(stage, &ctl->ccnt, s_n, &s_base));
+  const unsigned long long sums[6] = {
+      Group<kWave>::sum_reduce(c_visit),     Group<kWave>::sum_reduce(c_test),
+      Group<kWave>::sum_reduce(c_scan),      Group<kWave>::sum_reduce(c_lab),
+      Group<kWave>::sum_reduce(tally.sets), Group<kWave>::sum_reduce(tally.checks)};
+  if (lane_id() == 0)
+    for (int q = 0; q < 6; q++)
+      if (sums[q]) atomicAdd(&s_sum[q], sums[q]);
+  __syncthreads();
+  // one thread per counter, each counter on its own line
+  if (threadIdx.x < 6 && s_sum[threadIdx.x]) {
+    unsigned long long *dst[6] = {&ctl->visited, &ctl->ntests, &ctl->lscanned,
+                                  &ctl->labeled, &ctl->bp_sets, &ctl->bp_checks};
+    atomicAdd(dst[threadIdx.x], s_sum[threadIdx.x]);
+  }
+}
 
 // Level d of the window, grouped by root (DRootSort).  k_root_scan (one
 // block) publishes where level d+1 will start, clears the counts the
@@ -853,7 +961,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
-  uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;
+  uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;  // null: the next level is not sorted
   uint32_t c_edge = 0, c_direct = 0, c_earlier = 0, c_claim = 0;
   for (int64_t base = wid * kPerWave; base < ncand; base += nw * kPerWave) {
     const int64_t c = (int64_t)cbeg + base + lane_id() / G;
@@ -887,7 +995,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
     }
     c_claim += mine;
     const unsigned long long gclaims = Group<G>::sum_reduce(mine);
-    if (gr == 0 && gclaims) atomicAdd(&rnext[j], (uint32_t)gclaims);
+    if (rnext && gr == 0 && gclaims) atomicAdd(&rnext[j], (uint32_t)gclaims);
     // chunks of long lists become heavy tasks (one reservation per wave)
     const int64_t extra = act && deg > lim ? (deg - lim + chunk - 1) / chunk : 0;
     unsigned long long tb =
@@ -963,7 +1071,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
       stage.push(claimed, j, x, flush, u);
     }
     const unsigned long long tclaims = Group<kWave>::sum_reduce(mine);
-    if (lane_id() == 0 && tclaims) atomicAdd(&rnext[j], (uint32_t)tclaims);
+    if (rnext && lane_id() == 0 && tclaims) atomicAdd(&rnext[j], (uint32_t)tclaims);
   }
   if (stage.n) flush(stage);
   const unsigned long long w_direct = Group<kWave>::sum_reduce(c_direct);
@@ -1261,16 +1369,26 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DStore r
                             hipEvent_t ev2, hipEvent_t ev3) {
   const int blocks = 2048;
   const dim3 gd(blocks), bd(kBlock);
+  // at level 0 the test kernels return at once (the roots are labeled by
+  // k_win_init); they still run so that their timing events stay paired
+  if (!rs.rc0) {
+    switch (group) {
+      case 4: PLL_LAUNCH_TIMED(k_win_test_flat<4>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+      case 8: PLL_LAUNCH_TIMED(k_win_test_flat<8>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+      case 16: PLL_LAUNCH_TIMED(k_win_test_flat<16>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+      case 32: PLL_LAUNCH_TIMED(k_win_test_flat<32>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+      default: PLL_LAUNCH_TIMED(k_win_test_flat<64>, gd, bd, st, ev0, ev1, g, bp, s, w, f, d); break;
+    }
+  } else {
   hipLaunchKernelGGL(k_root_scan, dim3(1), dim3(kScanThreads), 0, st, rs, f.ctl, w.W, d);
   if (d > 0) hipLaunchKernelGGL(k_root_scatter, gd, bd, 0, st, rs, f, d);
-  // at level 0 the test kernel returns at once (the roots are labeled by
-  // k_win_init); it still runs so that its timing events stay paired
   switch (group) {
     case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
     case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
     case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
     case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
     default: PLL_LAUNCH_TIMED(k_win_test<64>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+  }
   }
   switch (xgroup) {
     case 4:

@@ -70,6 +70,35 @@ def test_small_families(name, g, t_bp):
         assert np.array_equal(gx.query(p, plain=True), want)
 
 
+@pytest.mark.parametrize("root_sort", [0, 1])
+@pytest.mark.parametrize("name,g", FAMILIES[::2], ids=[f[0] for f in FAMILIES[::2]])
+def test_prune_test_paths(name, g, root_sort):
+    # both prune-test kernels, straight from the frontier (0) and grouped by
+    # root with the root's data in LDS (1), at every group size, give the
+    # oracle's labels
+    _require_gpu()
+    order = gen.degree_order(g)
+    for t_bp in (0, 5):
+        ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+        for group in (4, 16, 64):
+            with Tuned(root_sort=root_sort, group=group, window=7, window_work=0):
+                gx = binding.build(g.row_ptr, g.col, order, t_bp)
+            assert_same_index(gx, ox, f"{name} t_bp={t_bp} sort={root_sort} group={group}")
+
+
+def test_root_grouped_tests_with_long_root_labels():
+    # roots whose labels do not fit the LDS table (more than 1024 entries)
+    # are tested through the window's global table: under a Random order
+    # (Section 4.4) R-MAT 12 gives 164 vertices labels of 1025-1386 entries
+    _require_gpu()
+    g = gen.rmat_graph(12, seed=3)
+    order = gen.random_order(g.n, 1)
+    ox = oracle.build(g.row_ptr, g.col, order, 0)
+    assert int(np.diff(ox.off).max()) > 1024
+    with Tuned(root_sort=1):
+        assert_same_index(binding.build(g.row_ptr, g.col, order, 0), ox, "long root labels")
+
+
 @pytest.mark.parametrize("window,group,xgroup,work", [
     (1, 16, 16, 0), (3, 4, 4, 0), (17, 8, 64, 0), (64, 64, 8, 0), (1024, 32, 16, 0),
     (16384, 4, 16, 300), (4096, 4, 32, 5000), (700, 8, 4, 0)])
