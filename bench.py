@@ -662,7 +662,7 @@ def main():
 
 
 def bench_weighted(args):
-    """The weighted step (Section 7): pruned Dijkstra index build from
+    """The weighted step (Section 6): pruned Dijkstra index build from
     device-resident inputs + one batch of queries, timed like the default
     step; roofline of the search step kernel; the oracle as CPU baseline."""
     import torch
@@ -746,7 +746,7 @@ def bench_weighted(args):
         },
     }
     if not args.no_extras:
-        # Section 7 paths on the weighted index: build with parents, restore
+        # Section 6 paths on the weighted index: build with parents, restore
         # 1e5 paths on the device (events on the stream)
         binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True,
                                parents=True).close()
@@ -899,7 +899,7 @@ def sweep(args):
 
 def path_extra(g, d_row, d_col, d_order, t_bp, d_pairs, stream, nq=100_000, max_len=32,
                directed=False):
-    """Build with parents (Section 7) and restore nq shortest paths on the
+    """Build with parents (Section 6) and restore nq shortest paths on the
     device; inputs and outputs in HBM, timed with events on the stream."""
     import torch
 

@@ -7,7 +7,7 @@
  * The library builds a 2-hop distance-labeling index of an undirected,
  * unweighted graph (bit-parallel labels, Section 5, plus pruned-BFS labels,
  * Section 4) on one GPU and answers exact distance queries from it
- * (Sections 3.3 and 5.3); Section 7's extensions are here too: shortest
+ * (Sections 3.3 and 5.3); Section 6's extensions are here too: shortest
  * paths (PLL_PARENTS), directed graphs (PLL_DIRECTED) and weighted graphs
  * (pll_build_weighted).  Every step of the build and of the query runs in
  * the library's own HIP kernels; the index stays in device memory.
@@ -58,9 +58,9 @@ enum {
                               concurrent roots); query one thread per pair */
 #define PLL_PARENTS 16u    /* pll_build*: keep, with every label entry (h, d) of
                               v, the parent of v in the pruned BFS tree of h
-                              (Section 7), plus the graph, for pll_query_path */
+                              (Section 6), plus the graph, for pll_query_path */
 #define PLL_DIRECTED 32u   /* pll_build*: the CSR lists out-arcs of a directed
-                              graph (Section 7): labels L_OUT and L_IN, queries
+                              graph (Section 6): labels L_OUT and L_IN, queries
                               give the distance from s to t along the arcs;
                               needs t_bp = 0 (else PLL_E_UNSUPPORTED); no
                               symmetry is required; with PLL_PARENTS both
@@ -224,7 +224,7 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
  * id -> local rank.
  */
 /*
- * Shortest paths (Section 7, "Shortest-Path Queries") of q pairs, for an
+ * Shortest paths (Section 6, "Shortest-Path Queries") of q pairs, for an
  * index built with PLL_PARENTS (else PLL_E_UNSUPPORTED).  On a weighted
  * index lens[i] counts the vertices of the path (it is not d+1 there): 0
  * if unreachable, -(vertices) if max_len is too small.
@@ -281,7 +281,7 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
                uint8_t *bp_d, uint64_t *bp_m1, uint64_t *bp_0, int32_t *rank);
 
 /*
- * Weighted graphs (Section 7, "Weighted Graphs"): every vertex, in rank
+ * Weighted graphs (Section 6, "Weighted Graphs"): every vertex, in rank
  * order, runs a pruned Dijkstra search in place of the pruned BFS; there are
  * no bit-parallel labels and distances are uint32.
  *   n, row_ptr, col, order, stream, out: as pll_build (one graph)

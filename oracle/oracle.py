@@ -258,7 +258,7 @@ def paths(idx: OracleIndex, pairs, maxlen: int) -> tuple[np.ndarray, np.ndarray]
 
 @dataclass
 class DirectedIndex:
-    """Exported oracle index of a directed graph (Section 7): L_OUT and L_IN
+    """Exported oracle index of a directed graph (Section 6): L_OUT and L_IN
     in rank order, no sentinels."""
     n: int
     rank: np.ndarray
@@ -343,7 +343,7 @@ WINF = 0xFFFFFFFF
 
 @dataclass
 class WeightedIndex:
-    """Exported oracle index of a weighted graph (Section 7): labels in rank
+    """Exported oracle index of a weighted graph (Section 6): labels in rank
     order, no sentinels, uint32 distances; ``in_*`` only for a digraph."""
     n: int
     directed: bool

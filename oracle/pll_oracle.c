@@ -23,17 +23,17 @@
  *   O4  labels stored with a sentinel after the last entry (Section 4.5.2).
  *   O5  queries: bit-parallel part (Section 5.3) plus the merge join over
  *       sorted labels (Section 3.3).
- *   O6  shortest paths (Section 7, "Shortest-Path Queries"): every label
+ *   O6  shortest paths (Section 6, "Shortest-Path Queries"): every label
  *       entry (h, d) of v also keeps the parent of v in the pruned BFS tree
  *       of h, and a path is restored by ascending those trees.
- *   O7  directed graphs (Section 7, "Directed Graphs"): labels L_OUT(v) =
+ *   O7  directed graphs (Section 6, "Directed Graphs"): labels L_OUT(v) =
  *       {(u, d(v,u))} and L_IN(v) = {(u, d(u,v))}; from every vertex in rank
  *       order one pruned BFS along the edges (it labels L_IN of what it
  *       reaches, pruning with L_OUT(root) and L_IN(u)) and one against them
  *       (labels L_OUT, pruning with L_OUT(u) and L_IN(root)); d(s,t) is the
  *       merge of L_OUT(s) and L_IN(t).  Entries keep parents as in O6, so
  *       paths s -> t are restored through the best hub of that merge.
- *   O8  weighted graphs (Section 7, "Weighted Graphs"): the pruned BFS of
+ *   O8  weighted graphs (Section 6, "Weighted Graphs"): the pruned BFS of
  *       Algorithm 1 becomes a pruned Dijkstra search (a binary heap, a vertex
  *       is tested and, if not pruned, labeled and relaxed when it is settled);
  *       no bit-parallel labels; distances are 32-bit.  Also for digraphs,
@@ -62,10 +62,10 @@
  *     printed Algorithm 3 alone can leave S^{-1} members in it.
  *   - Query answers are min(QUERY, 255); 255 means unreachable.
  *   - The parent kept with (h, d) in L(v) is the vertex that first enqueued
- *     v in the BFS from h (the root itself for its own entry; Section 7
+ *     v in the BFS from h (the root itself for its own entry; Section 6
  *     names it the parent in the pruned BFS tree, and the printed text says
  *     "of u" where the tree is rooted at u: the parent of v is meant).
- *   - Bit-parallel labels keep no tree (Section 7 treats normal labels only).
+ *   - Bit-parallel labels keep no tree (Section 6 treats normal labels only).
  *     When a bit-parallel slot gives the distance, the path is walked by
  *     scanning neighbours in ascending rank: towards the root r with the
  *     distances of the slot, towards a chosen neighbour w with w in S^{-1}
@@ -721,7 +721,7 @@ int orc_root_counts(const orc_index *x, int32_t *visited, int32_t *labeled) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* O6: shortest paths (Section 7)                                            */
+/* O6: shortest paths (Section 6)                                            */
 
 /* entry of hub h in L(v) (labels are sorted by hub rank), or -1 */
 static int64_t find_hub(const orc_label *L, uint32_t h) {
@@ -995,7 +995,7 @@ int orc_export_parents(const orc_index *x, uint32_t *par) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* O7: directed graphs (Section 7)                                           */
+/* O7: directed graphs (Section 6)                                           */
 
 /* min over (h, delta) of L with T[h] finite of delta + T[h] */
 static int t_query(const orc_label *L, const uint8_t *T) {
@@ -1170,7 +1170,7 @@ int orc_export_in(const orc_index *x, int64_t *entries, int64_t *off, uint32_t *
 }
 
 /* ------------------------------------------------------------------------ */
-/* O8: weighted graphs (Section 7, "Weighted Graphs")                        */
+/* O8: weighted graphs (Section 6, "Weighted Graphs")                        */
 /*
  * Readings:
  *   - Edge weights are integers >= 1 (a weight of 0 is rejected); distances
@@ -1392,7 +1392,7 @@ static void weighted_adjacency(const orc_windex *x, const int32_t *row_ptr, cons
 
 /* Weighted build.  flags bit 0: check that every edge (u, v, w) has its
  * reverse (v, u, w) (undirected only); bit 1: the CSR lists out-arcs of a
- * digraph (labels L_OUT and L_IN, Section 7). */
+ * digraph (labels L_OUT and L_IN, Section 6). */
 int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
                        const uint32_t *wgt, const int32_t *order, uint32_t flags,
                        orc_windex **out) {

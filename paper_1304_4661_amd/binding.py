@@ -526,7 +526,7 @@ def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = 
 def build_weighted(row_ptr, col, wgt, order, directed: bool = False, plain: bool = False,
                    validate: bool = False, stream=None, device: bool = False,
                    parents: bool = False) -> Index:
-    """Pruned Dijkstra index of a weighted graph (Section 7; see
+    """Pruned Dijkstra index of a weighted graph (Section 6; see
     include/pll.h).  Host arrays, or torch device tensors with device=True
     (wgt as int32 or uint32-valued int32 tensor)."""
     flags = ((VALIDATE if validate else 0) | (PLAIN if plain else 0)

@@ -822,7 +822,7 @@ struct Builder {
   }
 
   // a4 + a5: pruned BFSs in root windows, cleaning, commit; final CSR.
-  // An undirected graph has one side; a directed one (Section 7) a forward
+  // An undirected graph has one side; a directed one (Section 6) a forward
   // side (follows the arcs, labels L_IN, root tables from L_OUT) and a
   // reverse side (in-edges, labels L_OUT, root tables from L_IN).
   bool directed = false;
@@ -1083,7 +1083,7 @@ struct Builder {
 };
 
 // ---------------------------------------------------------------------------
-// Weighted graphs (Section 7): pruned Dijkstra searches in root windows
+// Weighted graphs (Section 6): pruned Dijkstra searches in root windows
 // (weighted.hip), 32-bit distances, no bit-parallel labels.
 
 // Pinned host copy of a weighted window's control block and its store's

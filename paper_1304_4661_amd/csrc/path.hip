@@ -1,4 +1,4 @@
-// Shortest-path queries (Section 7, "Shortest-Path Queries"): every label
+// Shortest-path queries (Section 6, "Shortest-Path Queries"): every label
 // entry (h, d) of v keeps the parent of v in the pruned BFS tree of h, so a
 // path through the best common hub h is restored by ascending both trees.
 // Bit-parallel labels keep no tree; when a bit-parallel slot gives the

@@ -345,7 +345,7 @@ struct DRootSort {
 };
 
 // ---------------------------------------------------------------------------
-// Weighted graphs (pruned Dijkstra searches, Section 7).
+// Weighted graphs (pruned Dijkstra searches, Section 6).
 
 constexpr uint32_t kWInf = 0xFFFFFFFFu;  // "infinity" in 32-bit distances
 constexpr int kWLand = 16;               // landmark hubs of the relaxation filter

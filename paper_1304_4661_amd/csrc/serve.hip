@@ -1,6 +1,6 @@
 // Serving over a device-resident index: continuous batching of distance
 // queries (Sections 3.3 and 5.3 answered by the library's query kernel; on a
-// weighted index, Section 7's, with 32-bit answers).
+// weighted index, Section 6's, with 32-bit answers).
 //
 // A worker thread owns `nslots` slots, each a HIP stream with pinned host
 // staging and device buffers for up to `slot_pairs` pairs.  Requests queue

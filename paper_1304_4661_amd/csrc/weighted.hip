@@ -1,4 +1,4 @@
-// Weighted graphs (Section 7, "Weighted Graphs"): every root runs a pruned
+// Weighted graphs (Section 6, "Weighted Graphs"): every root runs a pruned
 // Dijkstra search instead of a pruned BFS; there are no bit-parallel labels
 // and distances are 32-bit.
 //

@@ -5,10 +5,10 @@ pairs.  It holds none of the labeling or query arithmetic, so both the CPU
 oracle and the GPU library can be fed from it without sharing any of the
 method's code.
 
-The paper measures on real social, web and computer networks (Section 6,
+The paper measures on real social, web and computer networks (Section 7,
 Table 3), which are not available here.  Barabasi-Albert and R-MAT graphs stand
 in for them: both have power-law degrees and small-world distances, the two
-traits the paper's analysis relies on (Section 6.2, degree and distance
+traits the paper's analysis relies on (Section 7.1, degree and distance
 distributions).
 
 Conventions shared by every generator:
@@ -267,7 +267,7 @@ def rmat_graph(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.
 
 
 # --------------------------------------------------------------------------
-# Directed graphs (Section 7, "Directed Graphs")
+# Directed graphs (Section 6, "Directed Graphs")
 # --------------------------------------------------------------------------
 
 def digraph_from_edges(n: int, u: np.ndarray, v: np.ndarray) -> Graph:
@@ -459,9 +459,9 @@ CONFIGS = {
     "rmat20": ({"kind": "rmat", "scale": 20, "seed": 3}, 64, 10_000_000, 103),
     # served workload; one batch of 1e7 pairs stands for a step's queries
     "rmat22": ({"kind": "rmat", "scale": 22, "seed": 5}, 64, 10_000_000, 105),
-    # directed (Section 7): R-MAT arcs, no bit-parallel labels
+    # directed (Section 6): R-MAT arcs, no bit-parallel labels
     "rmat18d": ({"kind": "rmat", "directed": True, "scale": 18, "seed": 2}, 0, 1_000_000, 102),
-    # weighted (Section 7): integer weights uniform in [1, 100], no bit-parallel labels
+    # weighted (Section 6): integer weights uniform in [1, 100], no bit-parallel labels
     "ba2000w": ({"kind": "ba", "n": 2000, "m": 4, "seed": 1, "weights": (1, 100, 7)}, 0,
                 100_000, 101),
     "rmat18w": ({"kind": "rmat", "scale": 18, "seed": 2, "weights": (1, 100, 8)}, 0,

@@ -186,7 +186,7 @@ def check_visited_counter(ix, g, order) -> list[str]:
 
 
 def check_parents(ix, g, order, D) -> list[str]:
-    """Section 7: the parent kept with (h, d) in L(v) is v's predecessor in
+    """Section 6: the parent kept with (h, d) in L(v) is v's predecessor in
     the BFS tree of h -- v itself for d = 0, else a neighbour of v whose
     plain-BFS distance to h is d - 1."""
     fails = []
@@ -207,7 +207,7 @@ def check_parents(ix, g, order, D) -> list[str]:
 
 
 def check_paths(ix, g, order, D) -> list[str]:
-    """Paths restored from the labels (Section 7) are shortest paths: from s
+    """Paths restored from the labels (Section 6) are shortest paths: from s
     to t along edges with d(s,t) edges; none for unreachable pairs; a row
     too short reports -(d+1) and s = t gives [s]."""
     n = g.n

@@ -1,4 +1,4 @@
-"""GPU directed builds (Section 7) against the oracle, array for array:
+"""GPU directed builds (Section 6) against the oracle, array for array:
 L_OUT (pll_export), L_IN (pll_export_in) and every query answer.  Runs only
 on an MI355X (``-m gpu``)."""
 import numpy as np
@@ -122,7 +122,7 @@ DPATH = [("er60", gen.er_digraph(60, 0.05, 2)), ("rmat9", gen.rmat_digraph(9, 8,
 @pytest.mark.parametrize("name,g", DPATH, ids=[d[0] for d in DPATH])
 @pytest.mark.parametrize("window", [1, 64, 4096])
 def test_directed_paths(name, g, window):
-    # Section 7 paths on a digraph: labels as without parents, every path
+    # Section 6 paths on a digraph: labels as without parents, every path
     # follows the arcs with d(s, t) + 1 vertices, parents of both labels are
     # valid BFS-tree parents
     from scipy.sparse import csr_matrix

@@ -1,4 +1,4 @@
-"""GPU shortest-path queries (Section 7) against the graph and the oracle.
+"""GPU shortest-path queries (Section 6) against the graph and the oracle.
 
 Paths are not unique: the length must equal the BFS distance exactly and
 every path must be a walk along edges from s to t.  Where a bit-parallel

@@ -1,4 +1,4 @@
-"""GPU parity of weighted graphs (Section 7): the pruned Dijkstra labels of
+"""GPU parity of weighted graphs (Section 6): the pruned Dijkstra labels of
 the library against the oracle's, bit for bit, and every query answer
 against the oracle (small graphs: all pairs) or against scipy's Dijkstra
 (the full-size workload: every target of sampled sources)."""
@@ -284,7 +284,7 @@ WPATH = [("rmat10_w50", gen.uniform_weights(gen.rmat_graph(10, seed=21), 1, 50, 
 @pytest.mark.parametrize("name,g,directed", WPATH, ids=[w[0] for w in WPATH])
 @pytest.mark.parametrize("window", [1, 64, 4096])
 def test_weighted_paths(name, g, directed, window):
-    # Section 7 paths on weighted graphs: labels as without parents; every
+    # Section 6 paths on weighted graphs: labels as without parents; every
     # restored path follows edges (arcs) from s to t with weights summing to
     # the distance; parents are tight predecessors in the hub's search tree
     from test_oracle_weighted import edge_weights

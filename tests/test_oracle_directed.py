@@ -1,4 +1,4 @@
-"""Pins of the oracle's directed labels (Section 7, "Directed Graphs").
+"""Pins of the oracle's directed labels (Section 6, "Directed Graphs").
 
 L_OUT(v) holds (h, d(v,h)) and L_IN(v) holds (h, d(h,v)); the merge of
 L_OUT(s) and L_IN(t) must give the directed BFS distance, and each label

@@ -1,4 +1,4 @@
-"""Pins of the oracle's weighted labels (Section 7, "Weighted Graphs").
+"""Pins of the oracle's weighted labels (Section 6, "Weighted Graphs").
 
 The pruned Dijkstra search must give (a) query answers equal to Dijkstra
 distances from scipy, (b) exactly the canonical labels: (h, d) is in L(v)
