@@ -361,13 +361,32 @@ __device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, ulo
   return false;
 }
 
-// The root's table in LDS: open addressing over 32-bit slots holding
-// hub << 8 | distance (hub ranks below 2^24 - 1), kEmpty32 when free, sized
-// to a power of two >= 4 |L(k)| (at most kLdsSlots, so roots with labels of
-// up to kLdsSlots / 4 entries; longer labels, or graphs of 2^24 - 1 or more
-// vertices, use the window's table in global memory).
+// The root's table in LDS: buckets of four 32-bit slots (one 16-byte LDS
+// read), each slot hub << 8 | distance (hub ranks below 2^24 - 1) or
+// kEmpty32.  A hub goes to the first free slot of bucket hash(h), or of the
+// next bucket when all four are taken, so a lookup that meets a bucket with
+// a free slot is done.  Buckets: a power of two >= |L(k)| (one entry per
+// bucket on average), at most kLdsSlots / 4, so roots with labels of up to
+// kLdsSlots / 4 entries; longer labels, or graphs of 2^24 - 1 or more
+// vertices, use the window's table in global memory.
 constexpr int kLdsSlots = 4096;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+
+// distance of hub h in the LDS table, 255 if absent (stored distances are at
+// most 254)
+__device__ __forceinline__ int lds_lookup(const uint4 *tab, uint32_t bmask, uint32_t h) {
+  uint32_t b = ht_hash(h) & bmask;
+  for (;;) {
+    const uint4 q = tab[b];
+    int dist = kInf8;
+    dist = (q.x >> 8) == h ? (int)(q.x & 0xFFu) : dist;
+    dist = (q.y >> 8) == h ? (int)(q.y & 0xFFu) : dist;
+    dist = (q.z >> 8) == h ? (int)(q.z & 0xFFu) : dist;
+    dist = (q.w >> 8) == h ? (int)(q.w & 0xFFu) : dist;
+    if (dist != kInf8 || q.w == kEmpty32) return dist;
+    b = (b + 1) & bmask;
+  }
+}
 
 // Normal-label test against the LDS table: as label_prunes, without the
 // signature (an LDS probe is cheaper than the signature's registers).
@@ -378,8 +397,8 @@ constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 // runs past the label's end stays inside its slot (those entries are
 // masked out).
 template <int G>
-__device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint32_t *tab,
-                                                 uint32_t mask, int64_t o, int32_t len, int d) {
+__device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint4 *tab,
+                                                 uint32_t bmask, int64_t o, int32_t len, int d) {
   const int gr = Group<G>::rank();
   if (len == 0) return false;
   const uint4 *hq = reinterpret_cast<const uint4 *>(st.hub + o);
@@ -398,13 +417,7 @@ __device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint32_
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       if (e0 + i >= len) continue;
-      uint32_t sl = ht_hash(hv[i]) & mask;
-      uint32_t e = tab[sl];
-      while (e != kEmpty32 && (e >> 8) != hv[i]) {
-        sl = (sl + 1) & mask;
-        e = tab[sl];
-      }
-      if (e != kEmpty32) hit |= (int)((dd >> (8 * i)) & 0xFFu) + (int)(e & 0xFFu) <= d;
+      hit |= (int)((dd >> (8 * i)) & 0xFFu) + lds_lookup(tab, bmask, hv[i]) <= d;
     }
     if (Group<G>::any(hit)) return true;
     h = hn;
@@ -687,14 +700,15 @@ template <int G>
 __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
                                                      DWindow w, DFrontier f, DRootSort rs,
                                                      int d) {
-  __shared__ uint32_t s_ht[kLdsSlots];
+  __shared__ uint4 s_ht[kLdsSlots / 4];
   __shared__ uint4 s_krow[4];
   __shared__ ulonglong2 s_kpairs[64];
   __shared__ int32_t s_a[kWavesPerBlock][kTStage];
   __shared__ int32_t s_b[kWavesPerBlock][kTStage];
   __shared__ int32_t s_c[kWavesPerBlock][kTStage];
   __shared__ int32_t s_n[kWavesPerBlock];
-  __shared__ int32_t s_qu[kWavesPerBlock][32], s_qp[kWavesPerBlock][32];
+  __shared__ int32_t s_qu[kWavesPerBlock][32], s_qp[kWavesPerBlock][32], s_ql[kWavesPerBlock][32];
+  __shared__ int64_t s_qo[kWavesPerBlock][32];
   __shared__ unsigned long long s_base, s_sum[6];
   __shared__ int64_t s_task[3];
   __shared__ bool s_go;
@@ -753,12 +767,13 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
     const int32_t k = w.s + j;
     const int32_t klen = rst.len[k];
     const bool in_lds = small_ranks && klen <= kLdsSlots / 4;
-    uint32_t mask = 0;
+    uint32_t bmask = 0;
     if (in_lds) {
-      uint32_t sz = 16;
-      while (sz < 4u * (uint32_t)klen) sz <<= 1;
-      mask = sz - 1;
-      for (uint32_t i = threadIdx.x; i < sz; i += blockDim.x) s_ht[i] = kEmpty32;
+      uint32_t nb = 4;
+      while (nb < (uint32_t)klen) nb <<= 1;
+      bmask = nb - 1;
+      for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x)
+        s_ht[i] = make_uint4(kEmpty32, kEmpty32, kEmpty32, kEmpty32);
     }
     if (bp.t) {
       if (threadIdx.x < (unsigned)(bp.tpad >> 4))
@@ -773,8 +788,15 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       for (int32_t e = threadIdx.x; e < klen; e += blockDim.x) {
         const uint32_t h = rst.hub[ko + e];
         const uint32_t ent = (h << 8) | (uint32_t)rst.dist[ko + e];
-        uint32_t sl = ht_hash(h) & mask;
-        while (atomicCAS(&s_ht[sl], kEmpty32, ent) != kEmpty32) sl = (sl + 1) & mask;
+        uint32_t *slots = reinterpret_cast<uint32_t *>(s_ht);
+        // first free slot of the bucket, else of the next one
+        for (uint32_t b = ht_hash(h) & bmask, q = 0;; q++) {
+          if (q == 4) {
+            q = 0;
+            b = (b + 1) & bmask;
+          }
+          if (atomicCAS(&slots[4 * b + q], kEmpty32, ent) == kEmpty32) break;
+        }
       }
     }
     __syncthreads();
@@ -785,7 +807,8 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
     // test; survivors wait in the wave's LDS queue.  Phase B, G lanes per
     // entry: the normal-label test of kPerB queued entries at a time.
     int qn = 0;  // queued entries (wave-uniform)
-    int32_t *qu = s_qu[wv], *qp = s_qp[wv];
+    int32_t *qu = s_qu[wv], *qp = s_qp[wv], *ql = s_ql[wv];
+    int64_t *qo = s_qo[wv];
     auto phase_b = [&](int nb) {
       const int e = lane_id() / G;
       bool labeled = false;
@@ -793,9 +816,9 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       if (e < nb) {
         u = qu[qn - nb + e];
         par = qp[qn - nb + e];
-        const int64_t lo = st.off[u];
-        const int32_t llen = st.len[u];
-        const bool pr = in_lds ? label_prunes_lds<G>(st, s_ht, mask, lo, llen, d)
+        const int64_t lo = qo[qn - nb + e];
+        const int32_t llen = ql[qn - nb + e];
+        const bool pr = in_lds ? label_prunes_lds<G>(st, s_ht, bmask, lo, llen, d)
                                : label_prunes<G>(st, Tj, sg[0], sg[1], lo, llen, d);
         if (gr == 0) {
           c_test++;
@@ -817,10 +840,15 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       const int64_t p = b0 + lane_id() / kGA;
       const int gra = lane_id() & (kGA - 1);
       bool survive = false;
-      int32_t u = 0, par = 0;
+      int32_t u = 0, par = 0, ulen = 0;
+      int64_t uoff = 0;
       if (p < t1) {
         u = rs.sv[p];
         if (rs.spar) par = rs.spar[p];
+        // u's label place, loaded with its bit-parallel row for the
+        // normal-label test it may reach
+        uoff = st.off[u];
+        ulen = st.len[u];
         if (gra == 0) c_visit++;
         // bit-parallel labels first (Section 5.4)
         survive = true;
@@ -834,6 +862,8 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
         const int pos = qn + __popcll(m & lanes_below_mask());
         qu[pos] = u;
         qp[pos] = par;
+        qo[pos] = uoff;
+        ql[pos] = ulen;
       }
       qn += __popcll(m);
       __threadfence_block();  // the queue entries are visible to the whole wave

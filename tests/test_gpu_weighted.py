@@ -327,3 +327,15 @@ def test_weighted_paths(name, g, directed, window):
                 assert (vv, p_) in ew and ew[(vv, p_)] + D[p_, hh] == dd
             else:
                 assert (p_, vv) in ew and D[hh, p_] + ew[(p_, vv)] == dd
+
+
+def test_weighted_rmat18_workload_equals_the_oracle():
+    # the benchmark's weighted workload array for array against oracle O8
+    # (pruned Dijkstra searches, about half a minute on one host core), and
+    # the benchmark's 1e6 pairs
+    _require_gpu()
+    g, order, _, pairs = gen.config_graph("rmat18w")
+    ox = oracle.build_weighted(g.row_ptr, g.col, g.w, order)
+    gx = binding.build_weighted(g.row_ptr, g.col, g.w, order)
+    assert_same_weighted(gx, ox, "rmat18w")
+    assert np.array_equal(gx.query_weighted(pairs), oracle.query_weighted(ox, pairs))
