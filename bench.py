@@ -415,6 +415,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default frontier tiles (skip the build autotuner)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain-form, serving and latency measurements")
     ap.add_argument("--serve", action="store_true",
@@ -496,7 +498,12 @@ def main():
         ix, _, _ = step()
         ix.sync()
         ix.close()
-    # query tiles autotuned on a sample of the pairs, before the timed region
+    # frontier tiles autotuned on whole builds, query tiles on a sample of the
+    # pairs, both before the timed region
+    tiles = None
+    if not args.no_autotune and not batch and not directed:
+        tiles = binding.autotune_build(d_row, d_col, d_order, t_bp, stream=stream)
+        print(f"build tiles {tiles}", file=sys.stderr, flush=True)
     ix = build()
     qgroup = (ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
               if q > 0 else binding.get_tuning("qgroup"))
@@ -553,6 +560,8 @@ def main():
         "queries_per_s": q / (float(np.median(query_ms)) / 1e3) if q else None,
         "query_batch_ms_p50": pctl(query_ms, 50), "query_batch_ms_p99": pctl(query_ms, 99),
         "query_lanes_per_pair": qgroup,
+        "query_form": "persistent" if binding.get_tuning("qpersist") else "static",
+        "build_tiles": tiles,
         "index": {"entries": st["entries"], "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}",
                   "bytes": st["index_bytes"], "windows": st["windows"],
                   "retries": st["retries"], "visited": st["visited"],

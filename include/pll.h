@@ -186,17 +186,62 @@ int pll_query_noalloc(const pll_index *idx, const int32_t *pairs, int64_t q, uin
 int64_t pll_query_noalloc_max_pairs(void);
 
 /*
+ * A batch of distance queries recorded once as a HIP graph and replayed
+ * (Sections 3.3 and 5.3, as pll_query): for callers that answer a stream of
+ * equally sized batches from fixed device buffers, a replay is one graph
+ * launch of the three recorded kernels (clear the batch's error flag, check
+ * the ids, answer the pairs) instead of three launches and an allocation.
+ *   pll_query_graph_create: records the batch for device buffers pairs
+ *     int32[2q] and out uint8[q] (flags must hold PLL_DEVICE_PTRS; PLL_PLAIN
+ *     records the plain form; otherwise the batched form the "qgroup" and
+ *     "qpersist" knobs select at this time).  The buffers' contents may
+ *     change between replays, their addresses may not; the caller keeps
+ *     them and the index alive until pll_query_graph_free.  Allocates 16
+ *     bytes of device memory (the flag and the persistent form's cursor).
+ *   pll_query_graph_launch: replays it on stream (asynchronous).
+ *   pll_query_graph_status: waits for stream; PLL_E_INVAL if the last replay
+ *     met an id outside [0, n) (then it wrote no answer), else PLL_OK.
+ *   pll_query_graph_free: releases the graph (NULL is ignored).
+ * Replays on one graph must not overlap in time (they share the flag).
+ * Errors: PLL_E_INVAL (null index or output, q < 0, host pointers),
+ * PLL_E_UNSUPPORTED (weighted index), PLL_E_NOMEM, PLL_E_DEVICE.
+ */
+typedef struct pll_qgraph pll_qgraph;
+int pll_query_graph_create(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+                           uint32_t flags, pll_qgraph **g);
+int pll_query_graph_launch(pll_qgraph *g, void *stream);
+int pll_query_graph_status(pll_qgraph *g, void *stream);
+void pll_query_graph_free(pll_qgraph *g);
+
+/*
  * Autotuner of the batched query kernels: times every lane group size
- * (16, 32 and 64 lanes per pair) on q sample pairs of this index (3 timed
+ * (16, 32 and 64 lanes per pair) on q sample pairs of this index, each in
+ * the static and (unweighted indexes) the persistent batched form (3 timed
  * launches each after a warm-up, HIP events on stream), sets the
- * process-wide "qgroup" knob to the fastest and writes it to *best (may be
- * NULL).  Works for unweighted and weighted indexes.  pairs: int32[2q] ids,
+ * process-wide "qgroup" and "qpersist" knobs to the fastest and writes the
+ * lanes per pair to *best (may be NULL).  Works for unweighted and weighted indexes.  pairs: int32[2q] ids,
  * host memory or device memory under PLL_DEVICE_PTRS (validated first).
  * Synchronises the stream.  Errors: PLL_E_INVAL (null index or pairs,
  * q <= 0, id out of range), PLL_E_NOMEM, PLL_E_DEVICE.
  */
 int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t flags,
                        void *stream, int32_t *best);
+
+/*
+ * Autotuner of the pruned phase's frontier tiles: times whole builds of
+ * this graph (arguments as pll_build, which it calls; PLL_PLAIN and
+ * PLL_PARENTS are PLL_E_INVAL) while it varies one knob at a time from the
+ * current settings -- "xgroup" (lanes per candidate expansion: 8, 16, 32),
+ * "chunk" (edges expanded inline: 128, 256, 512), "window_work" (visits
+ * per window: 64M, 128M, 256M) and "sort_level" (level size from which the
+ * prune tests are grouped by root: 2^18, 2^20, 2^22) -- keeps each knob at
+ * its fastest value (the lanes per prune test are chosen per window by the
+ * build itself) and writes the four values to best[4] (may be NULL).  The
+ * labels do not depend on these knobs.  Cost: up to 12 builds.  Errors: as
+ * pll_build; on an error the knob being tried is restored.
+ */
+int pll_autotune_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+                       int32_t t_bp, uint32_t flags, void *stream, int64_t *best);
 
 /*
  * Wait for the index's work on stream and return (and clear) the error
@@ -505,7 +550,9 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * scanned edges are the sequential algorithm's; same labels).  Memory: "pool_keep_mb" (device memory of freed build
  * scratch and indexes kept for reuse by later builds, MB; reuse on another
  * stream waits for the stream that freed it; lowering the value releases
- * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64),
+ * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64), "qpersist" (0/1: batched queries with
+ * a static pair-to-group assignment, or persistent groups that take chunks
+ * of pairs from a shared cursor; pll_autotune_query chooses both),
  * "serve_coalesce" (0/1: servers started afterwards launch one request at a
  * time / pack several).  Returns PLL_E_INVAL for an unknown key or value.
  */

@@ -37,7 +37,8 @@ EXPORTED = [
     "pll_query_path", "pll_export_parents", "pll_export_in", "pll_build_weighted",
     "pll_query_weighted", "pll_export_weighted", "pll_autotune_query", "pll_export_in_parents",
     "pll_export_weighted_parents", "pll_server_submit_weighted", "pll_query_noalloc",
-    "pll_query_noalloc_max_pairs",
+    "pll_query_noalloc_max_pairs", "pll_query_graph_create", "pll_query_graph_launch",
+    "pll_query_graph_status", "pll_query_graph_free", "pll_autotune_build",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -72,6 +73,17 @@ def _lib():
         lib.pll_query_batch.restype = C.c_int
         lib.pll_query_noalloc.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
         lib.pll_query_noalloc.restype = C.c_int
+        lib.pll_autotune_build.argtypes = [C.c_int32, P, P, P, C.c_int32, C.c_uint32, P, P]
+        lib.pll_autotune_build.restype = C.c_int
+        lib.pll_query_graph_create.argtypes = [P, P, C.c_int64, P, C.c_uint32,
+                                               C.POINTER(C.c_void_p)]
+        lib.pll_query_graph_create.restype = C.c_int
+        lib.pll_query_graph_launch.argtypes = [P, P]
+        lib.pll_query_graph_launch.restype = C.c_int
+        lib.pll_query_graph_status.argtypes = [P, P]
+        lib.pll_query_graph_status.restype = C.c_int
+        lib.pll_query_graph_free.argtypes = [P]
+        lib.pll_query_graph_free.restype = None
         lib.pll_query_noalloc_max_pairs.argtypes = []
         lib.pll_query_noalloc_max_pairs.restype = C.c_int64
         lib.pll_sync.argtypes = [P, P]
@@ -474,6 +486,24 @@ def build_device(row_ptr, col, order, t_bp: int, plain: bool = False, stream=Non
     return Index(h)
 
 
+def autotune_build(row_ptr, col, order, t_bp: int, stream=None) -> dict:
+    """pll_autotune_build on device tensors (torch, int32, on the GPU): sets
+    the frontier-tile knobs to the fastest found and returns them."""
+    import torch
+
+    for a in (row_ptr, col, order):
+        assert a.dtype == torch.int32 and a.is_cuda and a.is_contiguous()
+    n = order.numel()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    best = np.zeros(4, np.int64)
+    _check(_lib().pll_autotune_build(n, C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()),
+                                     C.c_void_p(order.data_ptr()), int(t_bp), DEVICE_PTRS,
+                                     C.c_void_p(stream.cuda_stream), _ptr(best)),
+           "autotune_build")
+    return dict(zip(("xgroup", "chunk", "window_work", "sort_level"), (int(x) for x in best)))
+
+
 def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
                 plain: bool = False, stream=None, device: bool = False,
                 parents: bool = False, directed: bool = False) -> Index:
@@ -556,6 +586,51 @@ def build_weighted(row_ptr, col, wgt, order, directed: bool = False, plain: bool
     s = None if stream is None else C.c_void_p(stream.cuda_stream)
     _check(_lib().pll_build_weighted(n, *args, flags, s, C.byref(h)), "build_weighted")
     return Index(h, weighted=True)
+
+
+class QueryGraph:
+    """A batch of queries on fixed device tensors recorded as a HIP graph
+    (pll_query_graph_*): launch() replays it, status() waits and reports an
+    out-of-range id of the last replay."""
+
+    def __init__(self, index: Index, pairs, out, plain: bool = False):
+        import torch
+
+        assert pairs.dtype == torch.int32 and out.dtype == torch.uint8
+        assert pairs.is_cuda and out.is_cuda and pairs.is_contiguous() and out.is_contiguous()
+        assert pairs.numel() == 2 * out.numel()
+        self.index, self.pairs, self.out = index, pairs, out  # kept alive with the graph
+        h = C.c_void_p()
+        flags = DEVICE_PTRS | (PLAIN if plain else 0)
+        _check(_lib().pll_query_graph_create(index.handle, C.c_void_p(pairs.data_ptr()),
+                                             out.numel(), C.c_void_p(out.data_ptr()), flags,
+                                             C.byref(h)), "query_graph_create")
+        self._h = h
+
+    def launch(self, stream=None):
+        import torch
+
+        stream = stream or torch.cuda.current_stream()
+        _check(_lib().pll_query_graph_launch(self._h, C.c_void_p(stream.cuda_stream)),
+               "query_graph_launch")
+
+    def status(self, stream=None):
+        import torch
+
+        stream = stream or torch.cuda.current_stream()
+        _check(_lib().pll_query_graph_status(self._h, C.c_void_p(stream.cuda_stream)),
+               "query_graph_status")
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h is not None:
+            _lib().pll_query_graph_free(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

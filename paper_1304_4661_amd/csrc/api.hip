@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -33,6 +34,7 @@ struct Tuning {
   int live_adjacency = 1;  // drop neighbours ranked below the window from the expansion's CSR
   int chunk = 256;    // edges expanded inline before splitting into tasks
   int qgroup = 64;    // lanes per query pair
+  int qpersist = 0;   // batched queries: 1 = persistent groups taking chunks from a cursor
   int levels_per_sync = 4;
   int profile = 0;
   int bp_chunk = 64;  // adjacency entries per bit-parallel work item
@@ -1754,6 +1756,7 @@ int32_t index_n(const pll_index *idx) { return idx->n; }
 bool index_weighted(const pll_index *idx) { return idx->weighted; }
 int32_t *index_err(const pll_index *idx) { return idx->err.p; }
 int64_t query_group_size() { return tuning().qgroup; }
+bool query_persistent() { return tuning().qpersist != 0; }
 int64_t serve_coalesce() { return tuning().serve_coalesce; }
 }  // namespace pll
 
@@ -2031,19 +2034,25 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
     return guarded([&] {
       DBuf<int32_t> dp((size_t)(2 * q));
       DBuf<uint8_t> dout((size_t)q);
+      DBuf<unsigned long long> cur(1);
       h2d(dp.p, pairs, (size_t)(2 * q), st);
-      check(launch_query(idx->view(), dp.p, q, dout.p, nullptr, plain, tu.qgroup, st));
+      check(launch_query(idx->view(), dp.p, q, dout.p, nullptr, plain, tu.qgroup, st,
+                         tu.qpersist ? cur.p : nullptr));
       d2h(out, dout.p, (size_t)q, st);
       check(hipStreamSynchronize(st));
       return PLL_OK;
     });
   }
   return guarded([&] {
+    // the call's error flag, and with the persistent form its work cursor
     int32_t *err = nullptr;
-    check(hipMallocAsync((void **)&err, sizeof(int32_t), st));
-    check(hipMemsetAsync(err, 0, sizeof(int32_t), st));
+    check(hipMallocAsync((void **)&err, 16, st));
+    check(hipMemsetAsync(err, 0, 16, st));
+    unsigned long long *cur =
+        tu.qpersist ? reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(err) + 8)
+                    : nullptr;
     check(launch_validate_pairs(pairs, q, idx->n, err, st));
-    check(launch_query(idx->view(), pairs, q, out, err, plain, tu.qgroup, st));
+    check(launch_query(idx->view(), pairs, q, out, err, plain, tu.qgroup, st, cur));
     int32_t herr = 0;
     if (flags & PLL_SYNC) {
       check(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -2062,6 +2071,78 @@ int pll_query_batch(const pll_index *idx, const int32_t *pairs, int64_t q, uint8
                     uint32_t flags, void *stream) {
   return pll_query(idx, pairs, q, out, flags, stream);
 }
+
+}  // extern "C"
+
+struct pll_qgraph {
+  int32_t *flag = nullptr;  // error flag at +0, persistent-form cursor at +8
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~pll_qgraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (flag) (void)hipFree(flag);
+  }
+};
+
+extern "C" {
+
+int pll_query_graph_create(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *out,
+                           uint32_t flags, pll_qgraph **g) {
+  if (!g) return PLL_E_INVAL;
+  *g = nullptr;
+  if (!idx || q < 0 || !(flags & PLL_DEVICE_PTRS) || (q > 0 && (!pairs || !out)))
+    return PLL_E_INVAL;
+  if (idx->weighted) return PLL_E_UNSUPPORTED;
+  const Tuning tu = tuning();
+  const bool plain = (flags & PLL_PLAIN) != 0;
+  auto qg = std::make_unique<pll_qgraph>();
+  if (hipMalloc((void **)&qg->flag, 16) != hipSuccess) {
+    (void)hipGetLastError();
+    qg->flag = nullptr;
+    return PLL_E_NOMEM;
+  }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return PLL_E_DEVICE;
+  unsigned long long *cur =
+      tu.qpersist ? reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(qg->flag) + 8)
+                  : nullptr;
+  // the recorded launches: clear the flag (a kernel, not a memset), check
+  // the ids, answer the pairs
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    ok = launch_zero_flag(qg->flag, cs) == hipSuccess &&
+         launch_validate_pairs(pairs, q, idx->n, qg->flag, cs) == hipSuccess &&
+         launch_query(idx->view(), pairs, q, out, qg->flag, plain, tu.qgroup, cs, cur) ==
+             hipSuccess;
+    ok = hipStreamEndCapture(cs, &qg->graph) == hipSuccess && ok;
+  }
+  ok = ok && hipGraphInstantiate(&qg->exec, qg->graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    (void)hipGetLastError();
+    return PLL_E_DEVICE;
+  }
+  *g = qg.release();
+  return PLL_OK;
+}
+
+int pll_query_graph_launch(pll_qgraph *g, void *stream) {
+  if (!g) return PLL_E_INVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? PLL_OK : PLL_E_DEVICE;
+}
+
+int pll_query_graph_status(pll_qgraph *g, void *stream) {
+  if (!g) return PLL_E_INVAL;
+  int32_t herr = 0;
+  if (hipMemcpyAsync(&herr, g->flag, sizeof(int32_t), hipMemcpyDeviceToHost,
+                     (hipStream_t)stream) != hipSuccess ||
+      hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    return PLL_E_DEVICE;
+  return herr ? PLL_E_INVAL : PLL_OK;
+}
+
+void pll_query_graph_free(pll_qgraph *g) { delete g; }
 
 int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint32_t flags,
                        void *stream, int32_t *best) {
@@ -2090,6 +2171,7 @@ int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, ui
       if (herr) return PLL_E_INVAL;
     }
     DBuf<uint32_t> out((size_t)q);  // room for 8- or 32-bit answers
+    DBuf<unsigned long long> cur(1);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     check(hipEventCreate(&e0));
     check(hipEventCreate(&e1));
@@ -2101,34 +2183,94 @@ int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, ui
       }
     } evg{e0, e1};
     const DIndex v = idx->view();
-    auto launch = [&](int g) {
+    auto launch = [&](int g, bool persist) {
       if (idx->weighted)
         check(launch_wquery(v, pp, q, out.p, nullptr, false, g, st));
       else
-        check(launch_query(v, pp, q, reinterpret_cast<uint8_t *>(out.p), nullptr, false, g, st));
+        check(launch_query(v, pp, q, reinterpret_cast<uint8_t *>(out.p), nullptr, false, g, st,
+                           persist ? cur.p : nullptr));
     };
+    // lanes per pair, and for unweighted indexes the static or the
+    // persistent batched form
     int32_t choice = 64;
+    bool pchoice = false;
     float best_ms = 0.f;
-    for (int g : {16, 32, 64}) {
-      launch(g);  // warm
-      check(hipEventRecord(e0, st));
-      for (int r = 0; r < 3; r++) launch(g);
-      check(hipEventRecord(e1, st));
-      check(hipEventSynchronize(e1));
-      float ms = 0.f;
-      check(hipEventElapsedTime(&ms, e0, e1));
-      if (g == 16 || ms < best_ms) {
-        best_ms = ms;
-        choice = g;
+    bool first = true;
+    for (int persist = 0; persist < (idx->weighted ? 1 : 2); persist++) {
+      for (int g : {16, 32, 64}) {
+        launch(g, persist);  // warm
+        check(hipEventRecord(e0, st));
+        for (int r = 0; r < 3; r++) launch(g, persist);
+        check(hipEventRecord(e1, st));
+        check(hipEventSynchronize(e1));
+        float ms = 0.f;
+        check(hipEventElapsedTime(&ms, e0, e1));
+        if (first || ms < best_ms) {
+          best_ms = ms;
+          choice = g;
+          pchoice = persist != 0;
+          first = false;
+        }
       }
     }
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
       g_tune.qgroup = choice;
+      if (!idx->weighted) g_tune.qpersist = pchoice ? 1 : 0;
     }
     if (best) *best = choice;
     return PLL_OK;
   });
+}
+
+int pll_autotune_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
+                       int32_t t_bp, uint32_t flags, void *stream, int64_t *best) {
+  if (flags & (PLL_PLAIN | PLL_PARENTS)) return PLL_E_INVAL;
+  // coordinate descent, one knob at a time from the current settings; every
+  // candidate is one whole build (the labels never depend on the knobs)
+  struct Knob {
+    const char *name;
+    std::vector<int64_t> cands;
+  };
+  const std::vector<Knob> knobs = {
+      {"xgroup", {8, 16, 32}},
+      {"chunk", {128, 256, 512}},
+      {"window_work", {64000000, 128000000, 256000000}},
+      {"sort_level", {1 << 18, 1 << 20, 1 << 22}},
+  };
+  std::map<std::string, int64_t> chosen;
+  for (const Knob &k : knobs) {
+    const int64_t start = pll_get_tuning(k.name);
+    int64_t pick = start;
+    double pick_s = 0;
+    bool first = true;
+    for (int64_t c : k.cands) {
+      if (pll_set_tuning(k.name, c) != PLL_OK) continue;
+      pll_index *ix = nullptr;
+      const auto t0 = Clock::now();
+      const int rc = pll_build(n, row_ptr, col, order, t_bp, flags, stream, &ix);
+      const double secs = ns_since(t0) * 1e-9;
+      pll_free(ix);
+      if (rc != PLL_OK) {
+        pll_set_tuning(k.name, start);
+        return rc;
+      }
+      if (first || secs < pick_s) {
+        pick = c;
+        pick_s = secs;
+        first = false;
+      }
+    }
+    pll_set_tuning(k.name, pick);
+    chosen[k.name] = pick;
+  }
+  if (best) {
+    best[0] = chosen["xgroup"];
+    best[1] = chosen["chunk"];
+    best[2] = chosen["window_work"];
+    best[3] = chosen["sort_level"];
+  }
+  return PLL_OK;
 }
 
 int pll_sync(const pll_index *idx, void *stream) {
@@ -2430,6 +2572,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "expand_prune") {
     if (value < 0 || value > 1) return PLL_E_INVAL;
     g_tune.expand_prune = (int)value;
+  } else if (k == "qpersist") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.qpersist = (int)value;
   } else if (k == "root_sort") {
     if (value < 0 || value > 2) return PLL_E_INVAL;
     g_tune.root_sort = (int)value;
@@ -2485,6 +2630,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "live_adjacency") return g_tune.live_adjacency;
   if (k == "expand_prune") return g_tune.expand_prune;
   if (k == "root_sort") return g_tune.root_sort;
+  if (k == "qpersist") return g_tune.qpersist;
   if (k == "sort_level") return g_tune.sort_level;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;

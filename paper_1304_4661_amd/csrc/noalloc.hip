@@ -12,11 +12,13 @@ int32_t index_n(const pll_index *idx);
 bool index_weighted(const pll_index *idx);
 int32_t *index_err(const pll_index *idx);
 int64_t query_group_size();
+bool query_persistent();
 }  // namespace pll
 
 namespace {
 
-// Layout of the array: the error flag (one 256-byte line), then staging for
+// Layout of the array: the error flag (offset 0) and the persistent query
+// form's work cursor (offset 128) in the first 256 bytes, then staging for
 // kNoAllocMaxPairs pairs (int32[2q]) and their answers (uint8[q]).
 constexpr int64_t kNoAllocMaxPairs = 1ll << 21;
 constexpr int64_t kFlagBytes = 256;
@@ -72,6 +74,8 @@ extern "C" int pll_query_noalloc(const pll_index *idx, const int32_t *pairs, int
   hipStream_t st = (hipStream_t)stream;
   const bool plain = (flags & PLL_PLAIN) != 0;
   const int qgroup = (int)query_group_size();
+  unsigned long long *cursor =
+      query_persistent() ? reinterpret_cast<unsigned long long *>(base + 128) : nullptr;
   const DIndex view = index_view(idx);
   auto ok = [](hipError_t e) { return e == hipSuccess; };
   if (!device) {
@@ -79,7 +83,7 @@ extern "C" int pll_query_noalloc(const pll_index *idx, const int32_t *pairs, int
     uint8_t *dout = base + kOutOff;
     if (!ok(hipMemcpyAsync(dp, pairs, (size_t)(2 * q) * sizeof(int32_t), hipMemcpyHostToDevice,
                            st)) ||
-        !ok(launch_query(view, dp, q, dout, nullptr, plain, qgroup, st)) ||
+        !ok(launch_query(view, dp, q, dout, nullptr, plain, qgroup, st, cursor)) ||
         !ok(hipMemcpyAsync(out, dout, (size_t)q, hipMemcpyDeviceToHost, st)) ||
         !ok(hipStreamSynchronize(st)))
       return PLL_E_DEVICE;
@@ -88,7 +92,7 @@ extern "C" int pll_query_noalloc(const pll_index *idx, const int32_t *pairs, int
   int32_t *flag = reinterpret_cast<int32_t *>(base);
   hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(64), 0, st, flag);
   if (!ok(hipGetLastError()) || !ok(launch_validate_pairs(pairs, q, n, flag, st)) ||
-      !ok(launch_query(view, pairs, q, out, flag, plain, qgroup, st)))
+      !ok(launch_query(view, pairs, q, out, flag, plain, qgroup, st, cursor)))
     return PLL_E_DEVICE;
   if (flags & PLL_SYNC) {
     int32_t herr = 0;

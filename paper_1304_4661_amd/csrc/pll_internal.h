@@ -549,8 +549,19 @@ struct DIndex {
 hipError_t launch_validate_pairs(const int32_t *pairs, int64_t q, int32_t n, int32_t *err,
                                  hipStream_t st);
 hipError_t launch_or_flag(const int32_t *src, int32_t *dst, hipStream_t st);
+// cursor (device, optional): use the persistent batched form with it as
+// the shared work cursor
 hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
-                        const int32_t *err, bool plain, int qgroup, hipStream_t st);
+                        const int32_t *err, bool plain, int qgroup, hipStream_t st,
+                        unsigned long long *cursor = nullptr);
+// *flag = 0 by a kernel (graph-capturable, unlike a memset)
+hipError_t launch_zero_flag(int32_t *flag, hipStream_t st);
+// Persistent batched queries: groups take chunks of pairs from *cursor
+// (device, zeroed by a kernel first, so the launch may be captured in a
+// graph).
+hipError_t launch_query_persist(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
+                                const int32_t *err, int qgroup, unsigned long long *cursor,
+                                hipStream_t st);
 
 // export of one graph (rows = its global ranks in local rank order)
 hipError_t launch_invert_rank(const int32_t *rank, int32_t *ord, int32_t n, hipStream_t st);

@@ -65,68 +65,103 @@ __global__ void __launch_bounds__(256) k_query_plain(DIndex ix, const int32_t *p
   }
 }
 
+// One pair by a group of G lanes (all lanes of the group call it together).
+template <int G>
+__device__ __forceinline__ void query_pair(const DIndex &ix, const int32_t *pairs, int64_t i,
+                                           uint8_t *out) {
+  const int gr = Group<G>::rank();
+  const int gb = Group<G>::base();
+  const int32_t t = ix.t;
+  const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
+  if (ix.rgid && ix.rgid[rs] != ix.rgid[rt]) {  // different graphs of a batch
+    if (gr == 0) out[i] = kInf8;
+    return;
+  }
+  // (a) bit-parallel: lane k takes slot k (and k+G, ...).  The root alone
+  // gives d_s + d_t; the sets can only take 1 or 2 off it, so a slot's
+  // (S^{-1}, S^{0}) pairs are read only if d_s + d_t - 2 beats the best
+  // root estimate of the group.
+  int ub = kInf8;
+  for (int32_t k = gr; k < t; k += G) {
+    const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
+    if (ds != kInf8 && dt != kInf8 && ds + dt < ub) ub = ds + dt;
+  }
+  ub = Group<G>::min_reduce(ub);
+  int best = ub;
+  for (int32_t k = gr; k < t; k += G) {
+    const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
+    if (ds != kInf8 && dt != kInf8 && ds + dt - 2 < best) {
+      const ulonglong2 ms = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rs * t + k];
+      const ulonglong2 mt = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rt * t + k];
+      const int v = bp_pair_dist(ds, ms.x, ms.y, dt, mt.x, mt.y);
+      best = v < best ? v : best;
+    }
+  }
+  // (b) merge join by chunks of G entries
+  int64_t a = ix.off[rs], b = ix.toff[rt];
+  const int64_t ea = ix.off[rs + 1], eb = ix.toff[rt + 1];
+  for (;;) {
+    const uint32_t ha = ix.hub[a + gr < ea ? a + gr : ea - 1];
+    const uint32_t hb = ix.thub[b + gr < eb ? b + gr : eb - 1];
+    // position of ha among this group's hb values (sorted): halving search
+    // for the first index with hb >= ha (or G-1)
+    int lo = 0;
+#pragma unroll
+    for (int s = G / 2; s >= 1; s >>= 1) {
+      const uint32_t hm = __shfl(hb, gb + lo + s - 1);
+      if (hm < ha) lo += s;
+    }
+    const uint32_t hf = __shfl(hb, gb + lo);
+    if (hf == ha && ha != kSentinel) {
+      const int v = (int)ix.dist[a + gr] + (int)ix.tdist[b + lo];
+      best = v < best ? v : best;
+    }
+    const uint32_t lastA = __shfl(ha, gb + G - 1), lastB = __shfl(hb, gb + G - 1);
+    if (lastA == kSentinel && lastB == kSentinel) break;
+    if (lastA <= lastB) a += G;
+    if (lastB <= lastA) b += G;
+  }
+  best = Group<G>::min_reduce(best);
+  if (gr == 0) out[i] = (uint8_t)(best < (int)kInf8 ? best : (int)kInf8);
+}
+
+// Batched form: pair i goes to group i mod (groups of the grid).
 template <int G>
 __global__ void __launch_bounds__(256) k_query_group(DIndex ix, const int32_t *pairs, int64_t q,
                                                      uint8_t *out, const int32_t *err) {
   if (err && *err) return;
-  const int gr = Group<G>::rank();
-  const int gb = Group<G>::base();
   const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * blockDim.x) / G;
-  const int32_t t = ix.t;
-  for (int64_t i = gid; i < q; i += ngroups) {
-    const int32_t rs = ix.rank[pairs[2 * i]], rt = ix.rank[pairs[2 * i + 1]];
-    if (ix.rgid && ix.rgid[rs] != ix.rgid[rt]) {  // different graphs of a batch
-      if (gr == 0) out[i] = kInf8;
-      continue;
-    }
-    // (a) bit-parallel: lane k takes slot k (and k+G, ...).  The root alone
-    // gives d_s + d_t; the sets can only take 1 or 2 off it, so a slot's
-    // (S^{-1}, S^{0}) pairs are read only if d_s + d_t - 2 beats the best
-    // root estimate of the group.
-    int ub = kInf8;
-    for (int32_t k = gr; k < t; k += G) {
-      const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
-      if (ds != kInf8 && dt != kInf8 && ds + dt < ub) ub = ds + dt;
-    }
-    ub = Group<G>::min_reduce(ub);
-    int best = ub;
-    for (int32_t k = gr; k < t; k += G) {
-      const int ds = ix.bpd[(int64_t)rs * ix.tpad + k], dt = ix.bpd[(int64_t)rt * ix.tpad + k];
-      if (ds != kInf8 && dt != kInf8 && ds + dt - 2 < best) {
-        const ulonglong2 ms = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rs * t + k];
-        const ulonglong2 mt = reinterpret_cast<const ulonglong2 *>(ix.bpm)[(int64_t)rt * t + k];
-        const int v = bp_pair_dist(ds, ms.x, ms.y, dt, mt.x, mt.y);
-        best = v < best ? v : best;
-      }
-    }
-    // (b) merge join by chunks of G entries
-    int64_t a = ix.off[rs], b = ix.toff[rt];
-    const int64_t ea = ix.off[rs + 1], eb = ix.toff[rt + 1];
-    for (;;) {
-      const uint32_t ha = ix.hub[a + gr < ea ? a + gr : ea - 1];
-      const uint32_t hb = ix.thub[b + gr < eb ? b + gr : eb - 1];
-      // position of ha among this group's hb values (sorted): halving search
-      // for the first index with hb >= ha (or G-1)
-      int lo = 0;
-#pragma unroll
-      for (int s = G / 2; s >= 1; s >>= 1) {
-        const uint32_t hm = __shfl(hb, gb + lo + s - 1);
-        if (hm < ha) lo += s;
-      }
-      const uint32_t hf = __shfl(hb, gb + lo);
-      if (hf == ha && ha != kSentinel) {
-        const int v = (int)ix.dist[a + gr] + (int)ix.tdist[b + lo];
-        best = v < best ? v : best;
-      }
-      const uint32_t lastA = __shfl(ha, gb + G - 1), lastB = __shfl(hb, gb + G - 1);
-      if (lastA == kSentinel && lastB == kSentinel) break;
-      if (lastA <= lastB) a += G;
-      if (lastB <= lastA) b += G;
-    }
-    best = Group<G>::min_reduce(best);
-    if (gr == 0) out[i] = (uint8_t)(best < (int)kInf8 ? best : (int)kInf8);
+  for (int64_t i = gid; i < q; i += ngroups) query_pair<G>(ix, pairs, i, out);
+}
+
+// Persistent form: a grid sized to the device; each group takes the next
+// chunk of pairs from a shared cursor until none is left, so groups that
+// meet short labels take more pairs (pairs differ by up to 100x in label
+// length).  *cursor must be 0 at launch (k_zero_u64).
+template <int G>
+__global__ void __launch_bounds__(256) k_query_persist(DIndex ix, const int32_t *pairs, int64_t q,
+                                                       uint8_t *out, const int32_t *err,
+                                                       unsigned long long *cursor, int64_t chunk) {
+  if (err && *err) return;
+  const int gr = Group<G>::rank();
+  const int gb = Group<G>::base();
+  for (;;) {
+    unsigned long long c0 = 0;
+    if (gr == 0) c0 = atomicAdd(cursor, (unsigned long long)chunk);
+    c0 = __shfl(c0, gb);
+    if ((int64_t)c0 >= q) break;
+    const int64_t c1 = (int64_t)c0 + chunk < q ? (int64_t)c0 + chunk : q;
+    for (int64_t i = (int64_t)c0; i < c1; i++) query_pair<G>(ix, pairs, i, out);
   }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) {
+  if (threadIdx.x == 0) *p = 0ull;
+}
+
+__global__ void k_zero_i32(int32_t *p) {
+  if (threadIdx.x == 0) *p = 0;
 }
 
 __global__ void k_or_flag(const int32_t *src, int32_t *dst) {
@@ -156,7 +191,9 @@ hipError_t launch_or_flag(const int32_t *src, int32_t *dst, hipStream_t st) {
 }
 
 hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
-                        const int32_t *err, bool plain, int qgroup, hipStream_t st) {
+                        const int32_t *err, bool plain, int qgroup, hipStream_t st,
+                        unsigned long long *cursor) {
+  if (!plain && cursor) return launch_query_persist(ix, pairs, q, out, err, qgroup, cursor, st);
   if (q <= 0) return hipSuccess;
   if (plain) {
     hipLaunchKernelGGL(k_query_plain, dim3(grid_for(q, 256, 65536)), dim3(256), 0, st, ix, pairs,
@@ -175,6 +212,39 @@ hipError_t launch_query(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out
     default:
       hipLaunchKernelGGL(k_query_group<64>, dim3(grid_for(q * 64, 256, 16384)), dim3(256), 0, st,
                          ix, pairs, q, out, err);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_flag(int32_t *flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_persist(DIndex ix, const int32_t *pairs, int64_t q, uint8_t *out,
+                                const int32_t *err, int qgroup, unsigned long long *cursor,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, cursor);
+  if (q <= 0) return hipGetLastError();
+  // 256 CUs x 8 blocks; chunks so that every group takes about 8 of them
+  const int blocks = 2048;
+  const int64_t groups = (int64_t)blocks * 256 / qgroup;
+  int64_t chunk = q / (groups * 8);
+  if (chunk < 1) chunk = 1;
+  if (chunk > 256) chunk = 256;
+  switch (qgroup) {
+    case 16:
+      hipLaunchKernelGGL(k_query_persist<16>, dim3(blocks), dim3(256), 0, st, ix, pairs, q, out,
+                         err, cursor, chunk);
+      break;
+    case 32:
+      hipLaunchKernelGGL(k_query_persist<32>, dim3(blocks), dim3(256), 0, st, ix, pairs, q, out,
+                         err, cursor, chunk);
+      break;
+    default:
+      hipLaunchKernelGGL(k_query_persist<64>, dim3(blocks), dim3(256), 0, st, ix, pairs, q, out,
+                         err, cursor, chunk);
       break;
   }
   return hipGetLastError();

@@ -214,3 +214,22 @@ def test_query_noalloc_rejects_bad_arguments_without_device_work():
     assert lib.pll_query_noalloc(None, p.ctypes.data, 2, out.ctypes.data, 0, None) == binding.E_INVAL
     assert lib.pll_query_noalloc(None, p.ctypes.data, -1, out.ctypes.data, 0, None) == binding.E_INVAL
     assert binding.noalloc_max_pairs() == 1 << 21
+
+
+def test_recorded_queries_and_build_autotune_reject_bad_arguments():
+    lib = binding.library()
+    h = C.c_void_p()
+    p = np.zeros(4, np.int32)
+    out = np.zeros(2, np.uint8)
+    assert lib.pll_query_graph_create(None, p.ctypes.data, 2, out.ctypes.data,
+                                      binding.DEVICE_PTRS, C.byref(h)) == binding.E_INVAL
+    assert lib.pll_query_graph_create(None, p.ctypes.data, 2, out.ctypes.data, 0,
+                                      None) == binding.E_INVAL
+    assert lib.pll_query_graph_launch(None, None) == binding.E_INVAL
+    assert lib.pll_query_graph_status(None, None) == binding.E_INVAL
+    lib.pll_query_graph_free(None)
+    g = graphs.cycle(5)
+    order = gen.degree_order(g)
+    assert lib.pll_autotune_build(g.n, g.row_ptr.ctypes.data, g.col.ctypes.data,
+                                  order.ctypes.data, 0, binding.PLAIN, None,
+                                  None) == binding.E_INVAL

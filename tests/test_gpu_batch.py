@@ -91,3 +91,87 @@ def test_batch_solo_equivalence():
         part = bx.export(i)
         for k in solo:
             assert np.array_equal(solo[k], part[k]), (i, k)
+
+
+def test_persistent_queries_and_recorded_batches():
+    # the persistent batched form (groups take chunks of pairs from a shared
+    # cursor) and a query batch recorded as a HIP graph answer exactly as the
+    # static form, for a batch index (cross-graph pairs 255) and a single
+    # graph; every replay is checked after eager work on the same stream,
+    # with the pairs changed in place between replays
+    import torch
+    _require_gpu()
+    gs = [gen.ba_graph(n, m, 900 + n) for n, m in ((300, 2), (1200, 3), (2500, 4))]
+    vtx_off, rp, col, order = gen.pack_batch(gs)
+    bx = binding.build_batch(vtx_off, rp, col, order, 8)
+    N = int(vtx_off[-1])
+    rng = np.random.Generator(np.random.PCG64(17))
+    for q in (1, 777, 200_000):
+        p = rng.integers(0, N, (q, 2)).astype(np.int32)
+        want = bx.query(p)
+        for persist in (0, 1):
+            with Tuned(qpersist=persist):
+                assert np.array_equal(bx.query(p), want), (q, persist)
+                dp = torch.from_numpy(p).cuda()
+                out = torch.full((q,), 7, dtype=torch.uint8, device="cuda")
+                bx.query_device(dp, out, sync=True)
+                assert np.array_equal(out.cpu().numpy(), want)
+                assert np.array_equal(bx.query_noalloc(p), want)
+                qg = binding.QueryGraph(bx, dp, out)
+            for r in range(3):
+                p2 = rng.integers(0, N, (q, 2)).astype(np.int32)
+                dp.copy_(torch.from_numpy(p2))
+                out.fill_(7)
+                bx.query(p2[: max(1, q // 3)])  # eager work between replays
+                qg.launch()
+                qg.status()
+                assert np.array_equal(out.cpu().numpy(), bx.query(p2)), (q, persist, r)
+            # an out-of-range id: the replay writes nothing and reports it
+            bad = p2.copy()
+            bad[-1, 0] = N
+            dp.copy_(torch.from_numpy(bad))
+            out.fill_(9)
+            qg.launch()
+            with pytest.raises(binding.PllError):
+                qg.status()
+            assert int((out != 9).sum()) == 0
+            qg.close()
+
+
+def test_query_autotune_chooses_a_form():
+    _require_gpu()
+    g = gen.ba_graph(3000, 4, 5)
+    gx = binding.build(g.row_ptr, g.col, gen.degree_order(g), 16)
+    p = gen.random_pairs(g.n, 50_000, 6)
+    want = gx.query(p)
+    old = binding.get_tuning("qpersist"), binding.get_tuning("qgroup")
+    try:
+        assert gx.autotune_query(p) in (16, 32, 64)
+        assert binding.get_tuning("qpersist") in (0, 1)
+        assert np.array_equal(gx.query(p), want)
+    finally:
+        binding.set_tuning("qpersist", old[0])
+        binding.set_tuning("qgroup", old[1])
+
+
+def test_build_autotune():
+    # the frontier-tile autotuner settles on values from its candidate sets
+    # and the build it leaves behind still gives the oracle's labels
+    import torch
+    _require_gpu()
+    g = gen.rmat_graph(13, seed=9)
+    order = gen.degree_order(g)
+    keys = ("xgroup", "chunk", "window_work", "sort_level")
+    old = {k: binding.get_tuning(k) for k in keys}
+    try:
+        d = [torch.from_numpy(a).cuda() for a in (g.row_ptr, g.col, order)]
+        best = binding.autotune_build(*d, 16)
+        assert best["xgroup"] in (8, 16, 32) and best["chunk"] in (128, 256, 512)
+        assert best["window_work"] in (64000000, 128000000, 256000000)
+        assert best["sort_level"] in (1 << 18, 1 << 20, 1 << 22)
+        assert all(binding.get_tuning(k) == best[k] for k in keys)
+        ox = oracle.build(g.row_ptr, g.col, order, 16)
+        assert_same_index(binding.build_device(*d, 16), ox, "after build autotune")
+    finally:
+        for k, v in old.items():
+            binding.set_tuning(k, v)
