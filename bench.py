@@ -417,6 +417,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default frontier tiles (skip the build autotuner)")
+    ap.add_argument("--knobs", default="",
+                    help="library tuning knobs set first, e.g. root_sort=1,window_work=64000000")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain-form, serving and latency measurements")
     ap.add_argument("--serve", action="store_true",
@@ -442,6 +444,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    for kv in filter(None, args.knobs.split(",")):
+        k, v = kv.split("=")
+        binding.set_tuning(k.strip(), int(v))
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
         b = torch.empty_like(a)

@@ -520,7 +520,8 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * in global memory; 1: each level's entries grouped by root first, every
  * root's label table and bit-parallel row staged in LDS; 2 (default): 1 for
  * windows after one that averaged at least "sort_level" (default 2^20)
- * visits per level, else 0; same labels), "xgroup" (lanes per candidate expanding
+ * visits or "sort_scan" (default 2^23) scanned label entries per level,
+ * else 0; same labels), "xgroup" (lanes per candidate expanding
  * its adjacency list: 4..64), "list_cap" (upper bound on the entries of
  * the frontier, candidate and task lists, never below what one root needs;
  * 0 = sized from the window; a window that overflows is re-run with a

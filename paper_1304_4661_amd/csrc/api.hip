@@ -42,6 +42,7 @@ struct Tuning {
   int expand_prune = 1;  // expansion leaves neighbours unvisited that a test would prune
   int root_sort = 2;  // prune tests grouped by root: 0 never, 1 always, 2 for large levels
   int64_t sort_level = 1 << 20;  // visits per level from which "root_sort" 2 groups by root
+  int64_t sort_scan = 8 << 20;   // ... or label entries scanned per level
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -1035,8 +1036,10 @@ struct Builder {
       // "group" 0: lanes per prune test follow the label entries a test
       // scanned in this window (labels grow as roots commit)
       // root grouping pays a sort per level: worth it once levels are large
+      // or their label scans long
       use_sort = tu.root_sort == 1 ||
-                 (tu.root_sort == 2 && wlevels > 0 && wvisits / wlevels >= tu.sort_level);
+                 (tu.root_sort == 2 && wlevels > 0 &&
+                  (wvisits / wlevels >= tu.sort_level || wscanned / wlevels >= tu.sort_scan));
       if (tu.group == 0 && wtests >= 1024) test_group = group_for_scan(wscanned / wtests, use_sort);
       stat_windows++;
       trace_mark = level_trace.size();
@@ -2581,6 +2584,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "sort_level") {
     if (value < 0) return PLL_E_INVAL;
     g_tune.sort_level = value;
+  } else if (k == "sort_scan") {
+    if (value < 0) return PLL_E_INVAL;
+    g_tune.sort_scan = value;
   } else if (k == "pool_keep_mb") {
     if (value < 0 || value > (1ll << 22)) return PLL_E_INVAL;
     g_tune.pool_keep_mb = value;
@@ -2632,6 +2638,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "root_sort") return g_tune.root_sort;
   if (k == "qpersist") return g_tune.qpersist;
   if (k == "sort_level") return g_tune.sort_level;
+  if (k == "sort_scan") return g_tune.sort_scan;
   if (k == "chunk") return g_tune.chunk;
   if (k == "qgroup") return g_tune.qgroup;
   if (k == "levels_per_sync") return g_tune.levels_per_sync;

@@ -692,23 +692,27 @@ __global__ void __launch_bounds__(kBlock) k_root_scatter(DRootSort rs, DFrontier
 // entry (j, u) runs the bit-parallel test and the normal-label test of u at
 // distance d.  If neither prunes, u gets the candidate label (k, d).
 constexpr int kTStage = 128;  // staged candidates per wave
+// block of the root-grouped test kernel (measured: 512 threads beat 128 and
+// 256 on R-MAT 22 and on the 256-graph batch)
+constexpr int kTBlock = 512;
+constexpr int kTWaves = kTBlock / kWave;
 
 // st: the store of the labels being tested (L(u)); rst: the store the
 // roots' labels come from (the same for an undirected graph; the other
 // side's for a digraph).
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
+__global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
                                                      DWindow w, DFrontier f, DRootSort rs,
                                                      int d) {
   __shared__ uint4 s_ht[kLdsSlots / 4];
   __shared__ uint4 s_krow[4];
   __shared__ ulonglong2 s_kpairs[64];
-  __shared__ int32_t s_a[kWavesPerBlock][kTStage];
-  __shared__ int32_t s_b[kWavesPerBlock][kTStage];
-  __shared__ int32_t s_c[kWavesPerBlock][kTStage];
-  __shared__ int32_t s_n[kWavesPerBlock];
-  __shared__ int32_t s_qu[kWavesPerBlock][32], s_qp[kWavesPerBlock][32], s_ql[kWavesPerBlock][32];
-  __shared__ int64_t s_qo[kWavesPerBlock][32];
+  __shared__ int32_t s_a[kTWaves][kTStage];
+  __shared__ int32_t s_b[kTWaves][kTStage];
+  __shared__ int32_t s_c[kTWaves][kTStage];
+  __shared__ int32_t s_n[kTWaves];
+  __shared__ int32_t s_qu[kTWaves][32], s_qp[kTWaves][32], s_ql[kTWaves][32];
+  __shared__ int64_t s_qo[kTWaves][32];
   __shared__ unsigned long long s_base, s_sum[6];
   __shared__ int64_t s_task[3];
   __shared__ bool s_go;
@@ -836,7 +840,7 @@ __global__ void __launch_bounds__(kBlock) k_win_test(DGraph g, DBp bp, DStore st
       }
       stage.push(labeled, u, j, flush, par);
     };
-    for (int64_t b0 = t0 + wv * kPerA; b0 < t1; b0 += kWavesPerBlock * kPerA) {
+    for (int64_t b0 = t0 + wv * kPerA; b0 < t1; b0 += kTWaves * kPerA) {
       const int64_t p = b0 + lane_id() / kGA;
       const int gra = lane_id() & (kGA - 1);
       bool survive = false;
@@ -973,21 +977,6 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t ncand = (int64_t)(cend - cbeg);
-  if (d + 1 >= (int)kInf8) {
-    // neighbours would sit at distance 255: fine only if all are pruned
-    for (int64_t c = (int64_t)cbeg + wid; c < (int64_t)cend; c += nw) {
-      const int32_t u = w.cu[c], j = w.cj[c];
-      const int64_t e0 = g.row[u], deg = g.row[u + 1] - e0;
-      const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
-      const RootTable Tj = root_table(w, j);
-      for (int64_t e = lane_id(); e < deg; e += kWave) {
-        const int32_t x = g.col[e0 + e];
-        if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
-        if (!prune_test_serial(bp, st, Tj, w.s + j, x, d + 1)) atomicOr(&ctl->flags, kFlagRange);
-      }
-    }
-    return;
-  }
   WaveStage<kStage> stage;
   stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
   const FrontierFlush flush{ctl, f, nbase, d};
@@ -1057,6 +1046,32 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   if (threadIdx.x == 1 && s_sum[1]) atomicAdd(&ctl->bp_direct, s_sum[1]);
   if (threadIdx.x == 2 && s_sum[2]) atomicAdd(&ctl->earlier, s_sum[2]);
   if (threadIdx.x == 3 && s_sum[3]) atomicAdd(&ctl->xclaims, s_sum[3]);
+}
+
+// In place of the expansion at level 254: the neighbours would sit at
+// distance 255, which 8-bit labels cannot store, so every unvisited one must
+// be pruned there, else the window (or, for one root, the build) fails with
+// the range flag.
+__global__ void __launch_bounds__(kBlock) k_win_range(DGraph g, DBp bp, DStore st, DWindow w,
+                                                      DFrontier f, int d) {
+  LevelCtl *ctl = f.ctl;
+  const unsigned long long cbeg = ctl->cmark[d], cend0 = ctl->ccnt;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->cmark[d + 1] = cend0;
+  const unsigned long long cend = cend0 < (unsigned long long)w.ccap ? cend0 : w.ccap;
+  if (cend <= cbeg || (ctl->flags & kOverflowFlags)) return;
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t c = (int64_t)cbeg + wid; c < (int64_t)cend; c += nw) {
+    const int32_t u = w.cu[c], j = w.cj[c];
+    const int64_t e0 = g.row[u], deg = g.row[u + 1] - e0;
+    const uint32_t *vs = w.vis + (int64_t)j * g.nwords;
+    const RootTable Tj = root_table(w, j);
+    for (int64_t e = lane_id(); e < deg; e += kWave) {
+      const int32_t x = g.col[e0 + e];
+      if ((vs[x >> 5] >> (x & 31)) & 1u) continue;
+      if (!prune_test_serial(bp, st, Tj, w.s + j, x, d + 1)) atomicOr(&ctl->flags, kFlagRange);
+    }
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
@@ -1412,13 +1427,18 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DStore r
   } else {
   hipLaunchKernelGGL(k_root_scan, dim3(1), dim3(kScanThreads), 0, st, rs, f.ctl, w.W, d);
   if (d > 0) hipLaunchKernelGGL(k_root_scatter, gd, bd, 0, st, rs, f, d);
+  const dim3 gt(blocks * kBlock / kTBlock), bt(kTBlock);
   switch (group) {
-    case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
-    case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
-    case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
-    case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
-    default: PLL_LAUNCH_TIMED(k_win_test<64>, gd, bd, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 4: PLL_LAUNCH_TIMED(k_win_test<4>, gt, bt, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 8: PLL_LAUNCH_TIMED(k_win_test<8>, gt, bt, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 16: PLL_LAUNCH_TIMED(k_win_test<16>, gt, bt, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    case 32: PLL_LAUNCH_TIMED(k_win_test<32>, gt, bt, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
+    default: PLL_LAUNCH_TIMED(k_win_test<64>, gt, bt, st, ev0, ev1, g, bp, s, rst, w, f, rs, d); break;
   }
+  }
+  if (d + 1 >= (int)kInf8) {
+    PLL_LAUNCH_TIMED(k_win_range, gd, bd, st, ev2, ev3, g, bp, s, w, f, d);
+    return hipGetLastError();
   }
   switch (xgroup) {
     case 4:
