@@ -358,7 +358,11 @@ def serve(args):
         return (binding.build_weighted(*d, device=True) if weighted
                 else binding.build_device(*d, t_bp))
 
-    build().close()  # warm-up build: later builds reuse the library's cached blocks
+    # the first build in a process also allocates the label pools and window
+    # state; later builds reuse the library's cached blocks
+    t0 = time.perf_counter()
+    build().close()
+    cold_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     ix = build()
     build_s = time.perf_counter() - t0
@@ -375,7 +379,7 @@ def serve(args):
                        "random pairs") + "; requests log-uniform in "
                    "[1, 4096] pairs, Poisson arrivals", "name": name, "n": g.n, "m": g.m,
                    "t_bp": t_bp, "requests_per_load": nreq},
-        "build_s": build_s, "index": {"entries": st["entries"], "bytes": st["index_bytes"],
+        "build_s": build_s, "first_build_s": cold_s, "index": {"entries": st["entries"], "bytes": st["index_bytes"],
                                       "LN": f"{st['entries'] / max(g.n, 1):.1f}+{t_bp}"},
         "serving": res,
     }))
@@ -416,7 +420,7 @@ def main():
     ap.add_argument("--config", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default frontier tiles (skip the build autotuner)")
+                    help="keep the frontier and query tiles as set (skip both autotuners)")
     ap.add_argument("--knobs", default="",
                     help="library tuning knobs set first, e.g. root_sort=1,window_work=64000000")
     ap.add_argument("--no-extras", action="store_true",
@@ -511,7 +515,7 @@ def main():
         print(f"build tiles {tiles}", file=sys.stderr, flush=True)
     ix = build()
     qgroup = (ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
-              if q > 0 else binding.get_tuning("qgroup"))
+              if q > 0 and not args.no_autotune else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
     copy_gbs = copy_bandwidth_gbs(dev)
@@ -708,7 +712,7 @@ def bench_weighted(args):
         ix.close()
     ix = binding.build_weighted(d_row, d_col, d_w, d_order, stream=stream, device=True)
     qgroup = (ix.autotune_query(d_pairs[: min(q, 200_000)].contiguous(), stream=stream)
-              if q > 0 else binding.get_tuning("qgroup"))
+              if q > 0 and not args.no_autotune else binding.get_tuning("qgroup"))
     ix.close()
     torch.cuda.synchronize()
     copy_gbs = copy_bandwidth_gbs(dev)

@@ -38,8 +38,8 @@
  *       is tested and, if not pruned, labeled and relaxed when it is settled);
  *       no bit-parallel labels; distances are 32-bit.  Also for digraphs,
  *       with the two searches of O7.  Entries keep the parent in the search
- *       tree of the hub (the last vertex that lowered the distance), so
- *       shortest paths come back as in O6.
+ *       tree of the hub (chosen as in O6), so shortest paths come back as in
+ *       O6.
  *
  * Readings of points the paper leaves open (each one also fixed on the GPU
  * side, so both compute the same bytes):
@@ -61,10 +61,14 @@
  *   - S^0 is stored as Section 5.1 defines it (disjoint from S^{-1}); the
  *     printed Algorithm 3 alone can leave S^{-1} members in it.
  *   - Query answers are min(QUERY, 255); 255 means unreachable.
- *   - The parent kept with (h, d) in L(v) is the vertex that first enqueued
- *     v in the BFS from h (the root itself for its own entry; Section 6
- *     names it the parent in the pruned BFS tree, and the printed text says
- *     "of u" where the tree is rooted at u: the parent of v is meant).
+ *   - The parent kept with (h, d) in L(v) is v's parent in the pruned BFS
+ *     tree of h (Section 6; the printed text says "of u" where the tree is
+ *     rooted at u: the parent of v is meant).  Every vertex that the BFS
+ *     from h labeled at d - 1 and that has an edge to v is such a parent;
+ *     the lowest-ranked one is kept, so the choice is unique (the root
+ *     itself for its own entry).  For a digraph the edge runs in the
+ *     search's direction; for weighted graphs the parent p is labeled at
+ *     d - w(p, v).
  *   - Bit-parallel labels keep no tree (Section 6 treats normal labels only).
  *     When a bit-parallel slot gives the distance, the path is walked by
  *     scanning neighbours in ascending rank: towards the root r with the
@@ -400,6 +404,23 @@ static int64_t now_ns(void) {
   return (int64_t)ts.tv_sec * 1000000000 + ts.tv_nsec;
 }
 
+/* Parent kept with (k, d) in L(u), d >= 1: the lowest-ranked p in row u of
+ * (poff, padj) -- the vertices with an edge p -> u in the search -- whose
+ * label holds (k, d - 1).  Roots run in rank order, so while the search
+ * from k runs, an entry of k is the newest one of a label, and every vertex
+ * at distance d - 1 has been labeled or pruned before u is taken. */
+static uint32_t tree_parent(const orc_label *lab, const int64_t *poff, const int32_t *padj,
+                            int32_t u, int32_t k, int d) {
+  uint32_t best = ORC_SENTINEL;
+  for (int64_t j = poff[u]; j < poff[u + 1]; j++) {
+    const orc_label *L = &lab[padj[j]];
+    if (L->len > 0 && L->hub[L->len - 1] == (uint32_t)k && L->dist[L->len - 1] == d - 1 &&
+        (uint32_t)padj[j] < best)
+      best = (uint32_t)padj[j];
+  }
+  return best;
+}
+
 /* root_limit: pruned BFSs run from ranks 0..root_limit-1 only. */
 static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
                         const char *used, int32_t root_limit) {
@@ -409,9 +430,8 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
   uint16_t *P = (uint16_t *)malloc((size_t)n * sizeof(uint16_t));
   uint8_t *T = (uint8_t *)malloc((size_t)n);
   int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
-  int32_t *PP = (int32_t *)malloc((size_t)n * sizeof(int32_t)); /* enqueuing parent */
   int rc = ORC_OK;
-  if (!P || !T || !queue || !PP) {
+  if (!P || !T || !queue) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -429,7 +449,6 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
     int64_t qh = 0, qt = 0;
     queue[qt++] = k;
     P[k] = 0;
-    PP[k] = k;
     while (qh < qt) {
       int32_t u = queue[qh++];
       int d = P[u];
@@ -439,7 +458,8 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
         rc = ORC_E_RANGE;
         break;
       }
-      rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);
+      uint32_t par = d == 0 ? (uint32_t)k : tree_parent(x->lab, off, adj, u, k, d);
+      rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, par);
       if (rc != ORC_OK) break;
       x->cnt[C_LABELED]++;
       if (d > x->cnt[C_MAX_DIST]) x->cnt[C_MAX_DIST] = d;
@@ -448,7 +468,6 @@ static int pruned_phase(orc_index *x, const int64_t *off, const int32_t *adj,
         x->cnt[C_EDGES]++;
         if (P[w] != 0xFFFF) continue;
         P[w] = (uint16_t)(d + 1);
-        PP[w] = u;
         queue[qt++] = w;
       }
     }
@@ -462,7 +481,6 @@ done:
   free(P);
   free(T);
   free(queue);
-  free(PP);
   return rc;
 }
 
@@ -855,6 +873,7 @@ static int path_one(const orc_index *x, int32_t s, int32_t t, int32_t maxlen, in
         int64_t e = find_hub(&x->lab[c], h);
         if (e < 0) return ORC_E_RANGE;
         c = (int32_t)x->lab[c].par[e];
+        if ((uint32_t)c >= (uint32_t)x->n) return ORC_E_RANGE;
       }
     }
     c = rt;
@@ -863,6 +882,7 @@ static int path_one(const orc_index *x, int32_t s, int32_t t, int32_t maxlen, in
       int64_t e = find_hub(&x->lab[c], h);
       if (e < 0) return ORC_E_RANGE;
       c = (int32_t)x->lab[c].par[e];
+      if ((uint32_t)c >= (uint32_t)x->n) return ORC_E_RANGE;
     }
     if (c != (int32_t)h) return ORC_E_RANGE;
   } else {
@@ -948,6 +968,7 @@ static int path_one_directed(const orc_index *x, int32_t s, int32_t t, int32_t m
       int64_t e = find_hub(&x->lab[c], h);
       if (e < 0) return ORC_E_RANGE;
       c = (int32_t)x->lab[c].par[e];
+      if ((uint32_t)c >= (uint32_t)x->n) return ORC_E_RANGE;
     }
   }
   c = rt;
@@ -956,6 +977,7 @@ static int path_one_directed(const orc_index *x, int32_t s, int32_t t, int32_t m
     int64_t e = find_hub(&x->lab_in[c], h);
     if (e < 0) return ORC_E_RANGE;
     c = (int32_t)x->lab_in[c].par[e];
+    if ((uint32_t)c >= (uint32_t)x->n) return ORC_E_RANGE;
   }
   if (c != (int32_t)h) return ORC_E_RANGE;
   for (int k = 0; k <= D; k++) out[k] = x->ord[out[k]];
@@ -1010,11 +1032,13 @@ static int t_query(const orc_label *L, const uint8_t *T) {
 }
 
 /* One pruned BFS from root k over adj (out-edges for the forward search,
- * in-edges for the reverse one).  T holds the root's label on the other
- * side; `own` receives (k, d) at every vertex it does not prune. */
+ * in-edges for the reverse one; poff/padj: the other direction, whose row u
+ * lists the vertices the search reaches u from).  T holds the root's label
+ * on the other side; `own` receives (k, d) at every vertex it does not
+ * prune. */
 static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32_t *adj,
-                        orc_label *own, const orc_label *root_side, uint16_t *P, uint8_t *T,
-                        int32_t *queue, int32_t *PP) {
+                        const int64_t *poff, const int32_t *padj, orc_label *own,
+                        const orc_label *root_side, uint16_t *P, uint8_t *T, int32_t *queue) {
   const orc_label *Lk = &root_side[k];
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
   x->cnt[C_ROOT_STAGED] += Lk->len;
@@ -1022,7 +1046,6 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
   int64_t qh = 0, qt = 0;
   queue[qt++] = k;
   P[k] = 0;
-  PP[k] = k;
   while (qh < qt && rc == ORC_OK) {
     int32_t u = queue[qh++];
     int d = P[u];
@@ -1034,10 +1057,10 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
       rc = ORC_E_RANGE;
       break;
     }
-    /* the parent is the vertex that enqueued u: its predecessor on the
-     * path from k for the search along the arcs, its successor on the path
-     * to k for the search against them */
-    rc = label_push(&own[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);
+    /* the parent: u's predecessor on a path from k for the search along
+     * the arcs, its successor on a path to k for the search against them */
+    uint32_t par = d == 0 ? (uint32_t)k : tree_parent(own, poff, padj, u, k, d);
+    rc = label_push(&own[u], (uint32_t)k, (uint8_t)d, par);
     if (rc != ORC_OK) break;
     x->cnt[C_LABELED]++;
     if (d > x->cnt[C_MAX_DIST]) x->cnt[C_MAX_DIST] = d;
@@ -1046,7 +1069,6 @@ static int directed_bfs(orc_index *x, int32_t k, const int64_t *off, const int32
       x->cnt[C_EDGES]++;
       if (P[w] != 0xFFFF) continue;
       P[w] = (uint16_t)(d + 1);
-      PP[w] = u;
       queue[qt++] = w;
     }
   }
@@ -1090,10 +1112,9 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   uint16_t *P = (uint16_t *)malloc((size_t)nn * sizeof(uint16_t));
   uint8_t *T = (uint8_t *)malloc((size_t)nn);
   int32_t *queue = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
-  int32_t *PP = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   if (!x->rank || !x->lab || !x->lab_in || !x->bp_d || !x->bp_m1 || !x->bp_0 || !x->bp_root ||
       !x->bp_nsel || !x->bp_sel || !x->root_visited || !x->root_labeled || !x->ord || !off ||
-      !adj || !ioff || !iadj || !fill || !P || !T || !queue || !PP) {
+      !adj || !ioff || !iadj || !fill || !P || !T || !queue) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -1118,8 +1139,8 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
     x->cnt[C_ROOTS]++;
     int64_t vis0 = x->cnt[C_VISITED], lab0 = x->cnt[C_LABELED];
-    rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue, PP);
-    if (rc == ORC_OK) rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue, PP);
+    rc = directed_bfs(x, k, off, adj, ioff, iadj, x->lab_in, x->lab, P, T, queue);
+    if (rc == ORC_OK) rc = directed_bfs(x, k, ioff, iadj, off, adj, x->lab, x->lab_in, P, T, queue);
     x->root_visited[k] = (int32_t)(x->cnt[C_VISITED] - vis0);
     x->root_labeled[k] = (int32_t)(x->cnt[C_LABELED] - lab0);
   }
@@ -1134,7 +1155,6 @@ int orc_build_directed(int32_t n, const int32_t *row_ptr, const int32_t *col,
   x = NULL;
 done:
   free(off); free(adj); free(ioff); free(iadj); free(fill); free(P); free(T); free(queue);
-  free(PP);
   if (x) orc_free(x);
   return rc;
 }
@@ -1297,22 +1317,40 @@ static uint64_t wheap_pop(wheap *h) {
   return top;
 }
 
+/* Parent kept with (k, d) in L(u) of a weighted search, d >= 1: the
+ * lowest-ranked p in row u of (poff, padj, pw) -- the edges p -> u of the
+ * search, weight pw -- whose label's newest entry is (k, d - pw).  Weights
+ * are at least 1, so every such p was settled (labeled or pruned) before
+ * u. */
+static uint32_t wtree_parent(const orc_wlabel *lab, const int64_t *poff, const int32_t *padj,
+                             const uint32_t *pw, int32_t u, int32_t k, uint32_t d) {
+  uint32_t best = ORC_SENTINEL;
+  for (int64_t j = poff[u]; j < poff[u + 1]; j++) {
+    const orc_wlabel *L = &lab[padj[j]];
+    if (pw[j] <= d && L->len > 0 && L->hub[L->len - 1] == (uint32_t)k &&
+        L->dist[L->len - 1] == d - pw[j] && (uint32_t)padj[j] < best)
+      best = (uint32_t)padj[j];
+  }
+  return best;
+}
+
 /* One pruned Dijkstra search from root k over (off, adj, wgt): settled
  * vertices are tested against T (the root's labels from tlab, indexed by
  * hub) and their own labels in `lab`; a vertex that is not pruned gets
- * (k, d) in `lab` and relaxes its edges.  D, T and settled are all-INF /
- * zero on entry and on exit. */
+ * (k, d) in `lab` and relaxes its edges.  (poff, padj, pw): the edges in
+ * the other direction (the same ones for an undirected graph), for the
+ * parents.  D, T and settled are all-INF / zero on entry and on exit. */
 static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const int32_t *adj,
-                           const uint32_t *wgt, orc_wlabel *lab, const orc_wlabel *tlab,
+                           const uint32_t *wgt, const int64_t *poff, const int32_t *padj,
+                           const uint32_t *pw, orc_wlabel *lab, const orc_wlabel *tlab,
                            uint32_t *D, uint32_t *T, char *settled, int32_t *touched,
-                           wheap *heap, int32_t *PP) {
+                           wheap *heap) {
   int rc = ORC_OK;
   const orc_wlabel *Lk = &tlab[k];
   for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = Lk->dist[i];
   int64_t nt = 0;
   heap->len = 0;
   D[k] = 0;
-  PP[k] = k;
   touched[nt++] = k;
   rc = wheap_push(heap, (uint64_t)k);
   x->cnt[W_PUSHES]++;
@@ -1332,8 +1370,8 @@ static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const i
       if (th != ORC_WINF && (uint64_t)L->dist[i] + th <= d) pruned = 1;
     }
     if (pruned) continue;
-    /* the parent is the vertex whose relaxation last lowered D[u] */
-    rc = wlabel_push(&lab[u], (uint32_t)k, d, (uint32_t)PP[u]);
+    uint32_t par = d == 0 ? (uint32_t)k : wtree_parent(lab, poff, padj, pw, u, k, d);
+    rc = wlabel_push(&lab[u], (uint32_t)k, d, par);
     if (rc != ORC_OK) break;
     x->cnt[W_LABELED]++;
     if ((int64_t)d > x->cnt[W_MAX_DIST]) x->cnt[W_MAX_DIST] = d;
@@ -1344,7 +1382,6 @@ static int weighted_search(orc_windex *x, int32_t k, const int64_t *off, const i
       if (nd >= ORC_WINF || settled[w] || nd >= D[w]) continue;
       if (D[w] == ORC_WINF) touched[nt++] = w;
       D[w] = (uint32_t)nd;
-      PP[w] = u;
       rc = wheap_push(heap, nd << 32 | (uint64_t)w);
       x->cnt[W_PUSHES]++;
     }
@@ -1426,11 +1463,10 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   uint32_t *T = (uint32_t *)malloc((size_t)nn * sizeof(uint32_t));
   char *settled = (char *)calloc((size_t)nn, 1);
   int32_t *touched = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
-  int32_t *PP = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   x->ord = (int32_t *)malloc((size_t)nn * sizeof(int32_t));
   wheap heap = {NULL, 0, 0};
   if (!x->rank || !x->out || (directed && !x->in) || !off || !adj || !aw || !tmp || !D || !T ||
-      !settled || !touched || !PP || !x->ord) {
+      !settled || !touched || !x->ord) {
     rc = ORC_E_NOMEM;
     goto done;
   }
@@ -1482,17 +1518,17 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   for (int32_t k = 0; k < n && rc == ORC_OK; k++) {
     if (!directed) {
       x->cnt[W_ROOTS]++;
-      rc = weighted_search(x, k, off, adj, aw, x->out, x->out, D, T, settled, touched, &heap,
-                           PP);
+      rc = weighted_search(x, k, off, adj, aw, off, adj, aw, x->out, x->out, D, T, settled,
+                           touched, &heap);
     } else {
       /* along the arcs: labels L_IN, root distances from L_OUT(k); then
        * against them: labels L_OUT, root distances from L_IN(k) */
       x->cnt[W_ROOTS] += 2;
-      rc = weighted_search(x, k, off, adj, aw, x->in, x->out, D, T, settled, touched, &heap,
-                           PP);
+      rc = weighted_search(x, k, off, adj, aw, ioff, iadj, iaw, x->in, x->out, D, T, settled,
+                           touched, &heap);
       if (rc == ORC_OK)
-        rc = weighted_search(x, k, ioff, iadj, iaw, x->out, x->in, D, T, settled, touched,
-                             &heap, PP);
+        rc = weighted_search(x, k, ioff, iadj, iaw, off, adj, aw, x->out, x->in, D, T, settled,
+                             touched, &heap);
     }
   }
   if (rc != ORC_OK) goto done;
@@ -1503,7 +1539,7 @@ int orc_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col,
   x = NULL;
 done:
   free(off); free(adj); free(aw); free(ioff); free(iadj); free(iaw); free(tmp);
-  free(D); free(T); free(settled); free(touched); free(heap.a); free(PP);
+  free(D); free(T); free(settled); free(touched); free(heap.a);
   if (x) orc_wfree(x);
   return rc;
 }
@@ -1593,6 +1629,7 @@ static int64_t wascend(const orc_windex *x, const orc_wlabel *lab, int32_t c, ui
     int64_t e = wfind_hub(&lab[c], h);
     if (e < 0) return -1;
     c = (int32_t)lab[c].par[e];
+    if ((uint32_t)c >= (uint32_t)x->n) return -1;
   }
 }
 

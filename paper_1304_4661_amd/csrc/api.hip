@@ -643,13 +643,11 @@ struct Builder {
   struct Store {
     DBuf<int64_t> off;
     DBuf<int32_t> len, cap;
-    DBuf<uint32_t> hub, par;  // par stays null unless parents are kept
+    DBuf<uint32_t> hub;
     DBuf<uint8_t> dist;
     DBuf<unsigned long long> top;
     int64_t pool_cap = 0;
-    DStore view() const {
-      return DStore{off.p, len.p, cap.p, hub.p, dist.p, top.p, pool_cap, par.p};
-    }
+    DStore view() const { return DStore{off.p, len.p, cap.p, hub.p, dist.p, top.p, pool_cap}; }
   };
 
   // One search direction of the pruned phase: the graph its BFSs follow,
@@ -665,19 +663,18 @@ struct Builder {
     DBuf<uint8_t> wd, cd, cdes;
     DBuf<uint64_t> ht, cmask, kmask, sig, csum;
     DBuf<int64_t> htoff, hsize, htmp;
-    DBuf<int32_t> fslot, fv, h1, cu, cj, cpar, fpar;
+    DBuf<int32_t> fslot, fv, h1, cu, cj;
     DBuf<LevelCtl> ctl;
     PinnedMirror mirror;  // level counters and the own store's pool top
     DFrontier f;
     // each level's entries grouped by root for the prune tests
     DBuf<uint32_t> rc, rfill;
     DBuf<int64_t> roff, toff;
-    DBuf<int32_t> sv, spar;
+    DBuf<int32_t> sv;
     DRootSort rsort{};
     DWindow window(int32_t s, int32_t nr, int words, const uint8_t *used) const {
-      return DWindow{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p,  wd.p,
-                     cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap, cpar.p,
-                     used};
+      return DWindow{s,       nr,      words,  vis.p, ht.p, htoff.p, htcap, sig.p, wd.p,
+                     cmask.p, kmask.p, csum.p, cu.p,  cj.p, cd.p,    cdes.p, ccap,  used};
     }
   };
 
@@ -691,7 +688,6 @@ struct Builder {
     S.pool_cap = pool_cap;
     S.hub.alloc((size_t)pool_cap);
     S.dist.alloc((size_t)pool_cap);
-    if (parents) S.par.alloc((size_t)pool_cap);
     S.top.alloc(1);
     fill(S.top, 0, st);
   }
@@ -702,19 +698,14 @@ struct Builder {
     const int64_t need = 2 * (entries_bound + ncand) + 32 * ncand + 64;
     if (S.pool_cap - (int64_t)htop >= need) return;
     const int64_t ncap = std::max<int64_t>(3 * S.pool_cap, (int64_t)htop + 2 * need);
-    DBuf<uint32_t> nh((size_t)ncap), np;
-    if (parents) np.alloc((size_t)ncap);
+    DBuf<uint32_t> nh((size_t)ncap);
     DBuf<uint8_t> nd((size_t)ncap);
     check(hipMemcpyAsync(nh.p, S.hub.p, (size_t)htop * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                          st));
     check(hipMemcpyAsync(nd.p, S.dist.p, (size_t)htop, hipMemcpyDeviceToDevice, st));
-    if (parents)
-      check(hipMemcpyAsync(np.p, S.par.p, (size_t)htop * sizeof(uint32_t),
-                           hipMemcpyDeviceToDevice, st));
     check(hipStreamSynchronize(st));
     S.hub = std::move(nh);
     S.dist = std::move(nd);
-    S.par = std::move(np);
     S.pool_cap = ncap;
   }
 
@@ -754,25 +745,19 @@ struct Builder {
     D.h1.alloc((size_t)D.hcap * 3);
     D.cu.alloc((size_t)D.ccap);
     D.cj.alloc((size_t)D.ccap);
-    if (parents) {
-      D.cpar.alloc((size_t)D.ccap);
-      D.fpar.alloc((size_t)D.fcap);
-    }
     D.cd.alloc((size_t)D.ccap);
     D.cdes.alloc((size_t)D.ccap);
     D.ctl.alloc(1);
     D.f = DFrontier{D.fslot.p, D.fv.p,  D.fcap,  D.h1.p, D.h1.p + D.hcap, D.h1.p + 2 * D.hcap,
-                    D.hcap,    nullptr, nullptr, nullptr, D.ctl.p,         D.fpar.p};
+                    D.hcap,    nullptr, nullptr, nullptr, D.ctl.p};
     D.rc.alloc(2 * (size_t)wmax);
     D.rfill.alloc((size_t)wmax);
     D.roff.alloc((size_t)wmax + 1);
     D.toff.alloc((size_t)wmax + 1);
     D.sv.alloc((size_t)D.fcap);
-    if (parents) D.spar.alloc((size_t)D.fcap);
     fill(D.rc, 0, st);
     fill(D.rfill, 0, st);
-    D.rsort = DRootSort{D.rc.p, D.rc.p + wmax, D.rfill.p, D.roff.p, D.toff.p,
-                        D.sv.p, parents ? D.spar.p : nullptr, D.fcap};
+    D.rsort = DRootSort{D.rc.p, D.rc.p + wmax, D.rfill.p, D.roff.p, D.toff.p, D.sv.p, D.fcap};
     D.mirror.p->ctl = LevelCtl{};
     D.mirror.p->top = 0;
   }
@@ -1077,10 +1062,17 @@ struct Builder {
       check(hipStreamSynchronize(st));
       fhub.alloc((size_t)std::max<int64_t>(total, 1));
       fdist.alloc((size_t)std::max<int64_t>(total, 1));
-      DBuf<uint32_t> &fpar = in_side ? ix->ipar : ix->par;
-      if (parents) fpar.alloc((size_t)std::max<int64_t>(total, 1));
-      check(launch_final_copy(S.view(), foff.p, fhub.p, fdist.p, parents ? fpar.p : nullptr, n,
-                              st));
+      check(launch_final_copy(S.view(), foff.p, fhub.p, fdist.p, n, st));
+      if (parents) {
+        // the search of side k reaches u from p over an edge p -> u of its
+        // graph: p's row in the other direction's CSR (the same CSR for an
+        // undirected graph)
+        DBuf<uint32_t> &fpar = in_side ? ix->ipar : ix->par;
+        fpar.alloc((size_t)std::max<int64_t>(total, 1));
+        const DGraph pred = !directed ? graph() : k == 0 ? DGraph{n, nwords, irow.p, icol.p}
+                                                         : graph();
+        check(launch_tree_parents(pred, foff.p, fhub.p, fdist.p, fpar.p, n, st));
+      }
       check(hipStreamSynchronize(st));
       ix->entries += total - n;
     }

@@ -1,6 +1,10 @@
 // Shortest-path queries (Section 6, "Shortest-Path Queries"): every label
 // entry (h, d) of v keeps the parent of v in the pruned BFS tree of h, so a
 // path through the best common hub h is restored by ascending both trees.
+// Of the vertices one step closer to h that the BFS from h labeled (any of
+// them is a tree parent), the lowest-ranked one is kept, chosen after the
+// build from the final labels (k_tree_parents), so parents do not depend on
+// which concurrent search reached v first.
 // Bit-parallel labels keep no tree; when a bit-parallel slot gives the
 // distance, the path is walked through neighbours in ascending rank with
 // the slot's distances and sets, always to the lowest-rank neighbour that
@@ -94,6 +98,40 @@ __device__ int bp_walk(const DIndex &ix, int32_t c, int32_t i, uint64_t bit, int
     c = y;
   }
   return -1;
+}
+
+// One wave per vertex u: for each entry (h, d) of u, the lanes test the
+// predecessors p of u (a row of `pred`) in parallel for (h, d - 1) in L(p)
+// (a binary search over L(p), sorted by hub rank) and the wave keeps the
+// lowest-ranked hit.
+__global__ void __launch_bounds__(kBlock) k_tree_parents(DGraph pred, const int64_t *foff,
+                                                         const uint32_t *fhub,
+                                                         const uint8_t *fdist, uint32_t *fpar,
+                                                         int32_t n) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t u = wid; u < n; u += nw) {
+    const int64_t a = foff[u], b = foff[u + 1] - 1;  // the sentinel sits at b
+    const int64_t r0 = pred.row[u], r1 = pred.row[u + 1];
+    for (int64_t e = a; e < b; e++) {
+      const uint32_t h = fhub[e];
+      const int d = fdist[e];
+      int best = d == 0 ? (int)u : INT_MAX;
+      for (int64_t x0 = r0; d > 0 && x0 < r1; x0 += kWave) {
+        const int64_t x = x0 + lane_id();
+        int y = INT_MAX;
+        if (x < r1) {
+          const int32_t p = pred.col[x];
+          const int64_t f = find_hub(foff, fhub, p, h);
+          if (f >= 0 && (int)fdist[f] == d - 1) y = p;
+        }
+        y = Group<kWave>::min_reduce(y);
+        best = y < best ? y : best;
+      }
+      if (lane_id() == 0) fpar[e] = best == INT_MAX ? kSentinel : (uint32_t)best;
+    }
+    if (lane_id() == 0) fpar[b] = kSentinel;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_query_path(DIndex ix, const int32_t *pairs, int64_t q,
@@ -248,6 +286,14 @@ hipError_t launch_invert_rank(const int32_t *rank, int32_t *ord, int32_t n, hipS
   if (n > 0)
     hipLaunchKernelGGL(k_invert_rank, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, rank, ord,
                        n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_parents(DGraph pred, const int64_t *foff, const uint32_t *fhub,
+                               const uint8_t *fdist, uint32_t *fpar, int32_t n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_tree_parents, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
+                       dim3(kBlock), 0, st, pred, foff, fhub, fdist, fpar, n);
   return hipGetLastError();
 }
 

@@ -289,7 +289,6 @@ struct DStore {
   uint8_t *dist;
   unsigned long long *top;  // pool bump pointer (device)
   int64_t pool_cap;
-  uint32_t *par;  // parent of the vertex in the hub's BFS tree (null: not kept)
 };
 
 // Frontier and task buffers shared by both BFS phases.
@@ -301,7 +300,6 @@ struct DFrontier {
   int64_t hcap;
   int32_t *h2slot, *h2v, *h2chunk;
   LevelCtl *ctl;
-  int32_t *par;  // [cap] vertex that reached each entry (null: not kept)
 };
 
 // State of one window of concurrently processed roots [s, s + W).
@@ -323,7 +321,6 @@ struct DWindow {
   uint8_t *cd;          // candidate distance
   uint8_t *cdes;        // 1 if this candidate commits its vertex's row
   int64_t ccap;
-  int32_t *cp;          // candidate's parent in the root's BFS tree (null: not kept)
   const uint8_t *used;  // [n] 1 for bit-parallel roots and neighbours
 };
 
@@ -333,14 +330,14 @@ struct DWindow {
 // index (the expansion that makes a level adds its claims), roff / toff are
 // their exclusive scans over entries and over tasks of at most kTaskEntries
 // entries (roff[W] = entries, toff[W] = tasks), rfill the scatter cursors,
-// and sv / spar the level's vertices (and parents) in root order.
+// and sv the level's vertices in root order.
 constexpr int kTaskEntries = 1024;
 struct DRootSort {
   uint32_t *rc0, *rc1;  // [W]
   uint32_t *rfill;      // [W]
   int64_t *roff;        // [W+1]
   int64_t *toff;        // [W+1]
-  int32_t *sv, *spar;   // [cap] (spar null unless parents are kept)
+  int32_t *sv;          // [cap]
   int64_t cap;
 };
 
@@ -516,7 +513,13 @@ hipError_t launch_win_clean(DWindow w, DWindow o, int64_t ncand, hipStream_t st)
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
-                             uint32_t *fpar, int32_t n, hipStream_t st);
+                             int32_t n, hipStream_t st);
+// Parents of the final labels (shortest paths, Section 6): for every entry
+// (h, d) of u with d >= 1, the lowest-ranked p with an edge p -> u (row u of
+// `pred`) whose label holds (h, d - 1); u itself for d = 0.  Sentinels get
+// kSentinel.
+hipError_t launch_tree_parents(DGraph pred, const int64_t *foff, const uint32_t *fhub,
+                               const uint8_t *fdist, uint32_t *fpar, int32_t n, hipStream_t st);
 
 // Queries: ranks of ids, bit-parallel labels, final CSR labels with sentinel.
 struct DIndex {

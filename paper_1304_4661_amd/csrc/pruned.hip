@@ -165,13 +165,11 @@ __global__ void __launch_bounds__(kInitBlock) k_win_init(DGraph g, DWindow w, DS
     const unsigned long long p = s_base + local;
     f.slot[p] = j;
     f.v[p] = k;
-    if (f.par) f.par[p] = k;
     const unsigned long long c = s_cbase + local;
     if (c < (unsigned long long)w.ccap) {
       w.cu[c] = k;
       w.cj[c] = j;
       w.cd[c] = 0;
-      if (w.cp) w.cp[c] = k;
     } else {
       atomicOr(&f.ctl->flags, kFlagOvfCand);
     }
@@ -498,7 +496,6 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
                                                                               int d) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
-  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   __shared__ int32_t s_n[kWavesPerBlock];
   __shared__ unsigned long long s_base, s_sum[6];
   __shared__ bool s_go;
@@ -521,8 +518,8 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv], w.cp ? s_c[wv] : nullptr);
-  // candidates (u, j[, parent]): write them at list slots from c0
+  stage.init(s_a[wv], s_b[wv]);
+  // candidates (u, j): write them at list slots from c0
   auto write_out = [&](WaveStage<kStage> &sg, unsigned long long c0) {
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long c = c0 + i;
@@ -530,7 +527,6 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
         w.cu[c] = sg.a[i];
         w.cj[c] = sg.b[i];
         w.cd[c] = (uint8_t)d;
-        if (sg.c) w.cp[c] = sg.c[i];
       } else {
         atomicOr(&ctl->flags, kFlagOvfCand);
       }
@@ -543,11 +539,10 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
   for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
     const int64_t p = base + lane_id() / G;
     bool labeled = false;
-    int32_t u = 0, j = 0, par = 0;
+    int32_t u = 0, j = 0;
     if (p < (int64_t)cnt) {
       j = f.slot[beg + p];
       u = f.v[beg + p];
-      if (f.par) par = f.par[beg + p];
       if (gr == 0) c_visit++;
       // everything both tests may read that depends only on (j, u) is
       // loaded now, so the loads are in flight together
@@ -579,7 +574,7 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
                  1ull << ((j >> 6) & 63));
       }
     }
-    stage.push(labeled, u, j, flush, par);
+    stage.push(labeled, u, j, flush);
   }
   write_out(stage, block_reserve(stage, &ctl->ccnt, s_n, &s_base));
   const unsigned long long sums[6] = {
@@ -677,7 +672,6 @@ __global__ void __launch_bounds__(kBlock) k_root_scatter(DRootSort rs, DFrontier
       if ((m >> lane_id()) & 1ull) {
         const int64_t q = rs.roff[jl] + b + __popcll(m & lanes_below_mask());
         rs.sv[q] = f.v[beg + p];
-        if (rs.spar) rs.spar[q] = f.par[beg + p];
       }
       act &= ~m;
     }
@@ -709,9 +703,8 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
   __shared__ ulonglong2 s_kpairs[64];
   __shared__ int32_t s_a[kTWaves][kTStage];
   __shared__ int32_t s_b[kTWaves][kTStage];
-  __shared__ int32_t s_c[kTWaves][kTStage];
   __shared__ int32_t s_n[kTWaves];
-  __shared__ int32_t s_qu[kTWaves][32], s_qp[kTWaves][32], s_ql[kTWaves][32];
+  __shared__ int32_t s_qu[kTWaves][32], s_ql[kTWaves][32];
   __shared__ int64_t s_qo[kTWaves][32];
   __shared__ unsigned long long s_base, s_sum[6];
   __shared__ int64_t s_task[3];
@@ -731,8 +724,8 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
   constexpr int kGA = 4, kPerA = kWave / kGA, kPerB = kWave / G;
   const int wv = threadIdx.x / kWave;
   WaveStage<kTStage> stage;
-  stage.init(s_a[wv], s_b[wv], rs.spar ? s_c[wv] : nullptr);
-  // candidates (u, j[, parent]): write them at list slots from c0
+  stage.init(s_a[wv], s_b[wv]);
+  // candidates (u, j): write them at list slots from c0
   auto write_out = [&](WaveStage<kTStage> &sg, unsigned long long c0) {
     for (int i = lane_id(); i < sg.n; i += kWave) {
       const unsigned long long c = c0 + i;
@@ -740,7 +733,6 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
         w.cu[c] = sg.a[i];
         w.cj[c] = sg.b[i];
         w.cd[c] = (uint8_t)d;
-        if (sg.c) w.cp[c] = sg.c[i];
       } else {
         atomicOr(&ctl->flags, kFlagOvfCand);
       }
@@ -811,15 +803,14 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
     // test; survivors wait in the wave's LDS queue.  Phase B, G lanes per
     // entry: the normal-label test of kPerB queued entries at a time.
     int qn = 0;  // queued entries (wave-uniform)
-    int32_t *qu = s_qu[wv], *qp = s_qp[wv], *ql = s_ql[wv];
+    int32_t *qu = s_qu[wv], *ql = s_ql[wv];
     int64_t *qo = s_qo[wv];
     auto phase_b = [&](int nb) {
       const int e = lane_id() / G;
       bool labeled = false;
-      int32_t u = 0, par = 0;
+      int32_t u = 0;
       if (e < nb) {
         u = qu[qn - nb + e];
-        par = qp[qn - nb + e];
         const int64_t lo = qo[qn - nb + e];
         const int32_t llen = ql[qn - nb + e];
         const bool pr = in_lds ? label_prunes_lds<G>(st, s_ht, bmask, lo, llen, d)
@@ -838,17 +829,16 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
                    1ull << ((j >> 6) & 63));
         }
       }
-      stage.push(labeled, u, j, flush, par);
+      stage.push(labeled, u, j, flush);
     };
     for (int64_t b0 = t0 + wv * kPerA; b0 < t1; b0 += kTWaves * kPerA) {
       const int64_t p = b0 + lane_id() / kGA;
       const int gra = lane_id() & (kGA - 1);
       bool survive = false;
-      int32_t u = 0, par = 0, ulen = 0;
+      int32_t u = 0, ulen = 0;
       int64_t uoff = 0;
       if (p < t1) {
         u = rs.sv[p];
-        if (rs.spar) par = rs.spar[p];
         // u's label place, loaded with its bit-parallel row for the
         // normal-label test it may reach
         uoff = st.off[u];
@@ -865,7 +855,6 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
       if (survive && gra == 0) {
         const int pos = qn + __popcll(m & lanes_below_mask());
         qu[pos] = u;
-        qp[pos] = par;
         qo[pos] = uoff;
         ql[pos] = ulen;
       }
@@ -915,7 +904,6 @@ struct FrontierFlush {
       if (q < (unsigned long long)f.cap) {
         f.slot[q] = sg.a[i];
         f.v[q] = sg.b[i];
-        if (sg.c) f.par[q] = sg.c[i];
       } else {
         atomicOr(&ctl->flags, kFlagOvfFrontier);
       }
@@ -957,7 +945,6 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
                                                        int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
-  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   __shared__ int32_t s_n[kWavesPerBlock];
   __shared__ unsigned long long s_base, s_sum[4];
   __shared__ bool s_go;
@@ -978,7 +965,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   const int64_t ncand = (int64_t)(cend - cbeg);
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
+  stage.init(s_a[wv], s_b[wv]);
   const FrontierFlush flush{ctl, f, nbase, d};
   uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;  // null: the next level is not sorted
   uint32_t c_edge = 0, c_direct = 0, c_earlier = 0, c_claim = 0;
@@ -1010,7 +997,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
         claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
         mine += claimed ? 1u : 0u;
       }
-      stage.push(claimed, j, x, flush, u);
+      stage.push(claimed, j, x, flush);
     }
     c_claim += mine;
     const unsigned long long gclaims = Group<G>::sum_reduce(mine);
@@ -1079,7 +1066,6 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
                                                       int lim_inline, int32_t skip_below) {
   __shared__ int32_t s_a[kWavesPerBlock][kStage];
   __shared__ int32_t s_b[kWavesPerBlock][kStage];
-  __shared__ int32_t s_c[kWavesPerBlock][kStage];
   LevelCtl *ctl = f.ctl;
   const unsigned long long ntask = ctl->hcnt[d];
   if (ntask == 0 || (ctl->flags & kOverflowFlags)) return;
@@ -1089,7 +1075,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   WaveStage<kStage> stage;
-  stage.init(s_a[wv], s_b[wv], f.par ? s_c[wv] : nullptr);
+  stage.init(s_a[wv], s_b[wv]);
   const FrontierFlush flush{ctl, f, nbase, d};
   uint32_t *rnext = ((d + 1) & 1) ? rs.rc1 : rs.rc0;
   unsigned long long c_edge = 0;  // the same in every lane (whole-wave tasks)
@@ -1113,7 +1099,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
         claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
         mine += claimed ? 1u : 0u;
       }
-      stage.push(claimed, j, x, flush, u);
+      stage.push(claimed, j, x, flush);
     }
     const unsigned long long tclaims = Group<kWave>::sum_reduce(mine);
     if (rnext && lane_id() == 0 && tclaims) atomicAdd(&rnext[j], (uint32_t)tclaims);
@@ -1288,7 +1274,6 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
       for (int32_t e = lane_id(); e < ln; e += kWave) {
         st.hub[dn + e] = st.hub[so + e];
         st.dist[dn + e] = st.dist[so + e];
-        if (st.par) st.par[dn + e] = st.par[so + e];
       }
     }
     if (reloc) {
@@ -1325,7 +1310,6 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_write(DWindow w, DStore s
       const int64_t o = st.off[u] + st.len[u] - 1 - above;
       st.hub[o] = (uint32_t)(w.s + j);
       st.dist[o] = w.cd[c];
-      if (st.par) st.par[o] = (uint32_t)w.cp[c];
     }
   }
 }
@@ -1363,7 +1347,7 @@ __global__ void k_final_count(const int32_t *len, int64_t *cnt, int32_t n) {
 // the storage-only sentinel (Section 4.5.2).
 __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t *foff,
                                                        uint32_t *fhub, uint8_t *fdist,
-                                                       uint32_t *fpar, int32_t n) {
+                                                       int32_t n) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t r = wid; r < n; r += nw) {
@@ -1372,12 +1356,10 @@ __global__ void __launch_bounds__(kBlock) k_final_copy(DStore st, const int64_t 
     for (int32_t e = lane_id(); e < len; e += kWave) {
       fhub[fo + e] = st.hub[o + e];
       fdist[fo + e] = st.dist[o + e];
-      if (fpar) fpar[fo + e] = st.par[o + e];
     }
     if (lane_id() == 0) {
       fhub[fo + len] = kSentinel;
       fdist[fo + len] = kInf8;
-      if (fpar) fpar[fo + len] = kSentinel;
     }
   }
 }
@@ -1564,10 +1546,10 @@ hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipSt
 }
 
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
-                             uint32_t *fpar, int32_t n, hipStream_t st) {
+                             int32_t n, hipStream_t st) {
   if (n > 0)
     hipLaunchKernelGGL(k_final_copy, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
-                       dim3(kBlock), 0, st, s, foff, fhub, fdist, fpar, n);
+                       dim3(kBlock), 0, st, s, foff, fhub, fdist, n);
   return hipGetLastError();
 }
 

@@ -7,7 +7,11 @@
                                                    CFETCH_DIR CWRITE_DIR COPY_BYTES
         average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of KERNEL, scaled by
         what the same counters read for a device copy of COPY_BYTES bytes
-        (read COPY_BYTES, write COPY_BYTES), as HBM bytes per launch
+        (read COPY_BYTES, write COPY_BYTES), as HBM bytes per launch;
+        with LAST after COPY_BYTES only the last LAST dispatches of KERNEL count
+    python -m paper_1304_4661_amd.rocprof_summary window KERNEL LAST DIR
+        calls / total / average duration of the last LAST dispatches whose
+        name contains KERNEL, from a --kernel-trace run (DIR/*_kernel_trace.csv)
 """
 from __future__ import annotations
 
@@ -34,10 +38,24 @@ def stats(d):
     return out
 
 
-def counter_per_dispatch(d, kernel_substr, counter):
-    vals = [float(r["Counter_Value"]) for r in _rows(d, "_counter_collection.csv")
+def counter_per_dispatch(d, kernel_substr, counter, last=None):
+    rows = [r for r in _rows(d, "_counter_collection.csv")
             if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    if last:
+        rows = rows[-last:]
+    vals = [float(r["Counter_Value"]) for r in rows]
     return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def window(d, kernel_substr, last):
+    """(calls, total ns, average ns) of the last `last` dispatches of the
+    kernels whose name contains kernel_substr, in start order."""
+    rows = [r for r in _rows(d, "_kernel_trace.csv") if kernel_substr in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[-last:]
+    ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows]
+    return len(ns), float(sum(ns)), (sum(ns) / len(ns)) if ns else None
 
 
 def copy_kib(d, counter):
@@ -48,9 +66,9 @@ def copy_kib(d, counter):
     return max(vals) if vals else None
 
 
-def traffic(kernel, fdir, wdir, cfdir, cwdir, copy_bytes):
-    f, nf = counter_per_dispatch(fdir, kernel, "FETCH_SIZE")
-    w, nw = counter_per_dispatch(wdir, kernel, "WRITE_SIZE")
+def traffic(kernel, fdir, wdir, cfdir, cwdir, copy_bytes, last=None):
+    f, nf = counter_per_dispatch(fdir, kernel, "FETCH_SIZE", last)
+    w, nw = counter_per_dispatch(wdir, kernel, "WRITE_SIZE", last)
     cf, cw = copy_kib(cfdir, "FETCH_SIZE"), copy_kib(cwdir, "WRITE_SIZE")
     kf = copy_bytes / (cf * 1024.0)  # true bytes per counted byte (reads)
     kw = copy_bytes / (cw * 1024.0)  # (writes)
@@ -70,8 +88,13 @@ def main(argv):
         for name, calls, tot, avg, pct in rows:
             print(f"{name[:70]:70s} {calls:7d} {tot / 1e6:10.3f} {avg / 1e3:10.2f} {pct:6.2f}")
     elif argv[0] == "traffic":
-        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], argv[5], float(argv[6])),
-                         indent=1))
+        last = int(argv[7]) if len(argv) > 7 else None
+        print(json.dumps(traffic(argv[1], argv[2], argv[3], argv[4], argv[5], float(argv[6]),
+                                 last), indent=1))
+    elif argv[0] == "window":
+        calls, tot, avg = window(argv[3], argv[1], int(argv[2]))
+        print(f"{argv[1]}: last {calls} dispatches, {tot / 1e6:.3f} ms, {avg / 1e3:.2f} us "
+              "per launch")
     else:
         raise SystemExit(__doc__)
 

@@ -185,22 +185,35 @@ def check_visited_counter(ix, g, order) -> list[str]:
     return fails
 
 
+def label_maps(off, hub, dist):
+    """Per rank, its label as {hub: distance}."""
+    return [dict(zip(hub[off[r]:off[r + 1]].tolist(), dist[off[r]:off[r + 1]].tolist()))
+            for r in range(len(off) - 1)]
+
+
 def check_parents(ix, g, order, D) -> list[str]:
     """Section 6: the parent kept with (h, d) in L(v) is v's predecessor in
     the BFS tree of h -- v itself for d = 0, else a neighbour of v whose
-    plain-BFS distance to h is d - 1."""
+    plain-BFS distance to h is d - 1 and which the BFS from h labeled at
+    d - 1; of those, the lowest-ranked one (ranks: positions in `order`)."""
     fails = []
+    rank = np.empty(ix.n, np.int64)
+    rank[np.asarray(order)] = np.arange(ix.n)
+    lab = label_maps(ix.off, ix.hub, ix.dist)
     for r in range(ix.n):
         a, b = int(ix.off[r]), int(ix.off[r + 1])
         v = int(order[r])
-        nb = set(int(w) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]])
+        nb = [int(rank[w]) for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]]]
         for h, d, p in zip(ix.hub[a:b], ix.dist[a:b], ix.par[a:b]):
             h, d, p = int(h), int(d), int(p)
             if d == 0:
                 if p != r:
                     fails.append(f"rank {r}: self entry has parent {p}")
-            elif not (0 <= p < ix.n) or int(order[p]) not in nb or D[order[h], order[p]] != d - 1:
+            elif not (0 <= p < ix.n) or p not in nb or D[order[h], order[p]] != d - 1:
                 fails.append(f"rank {r}: entry ({h},{d}) has parent {p}")
+            elif p != min((q for q in nb if lab[q].get(h) == d - 1), default=None):
+                fails.append(f"rank {r}: entry ({h},{d}) has parent {p}, not the lowest-ranked "
+                             "labeled one")
             if len(fails) >= 5:
                 return fails
     return fails

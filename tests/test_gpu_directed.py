@@ -138,8 +138,9 @@ def test_directed_paths(name, g, window):
     pairs = all_pairs(g.n) if g.n <= 600 else gen.random_pairs(g.n, 100_000, 4)
     want = oracle.query_directed(ox, pairs).astype(np.int64)
     paths, lens = gx.query_path(pairs, max_len=64)
-    _, olens = oracle.paths(ox, pairs, 64)
+    opaths, olens = oracle.paths(ox, pairs, 64)
     assert np.array_equal(lens, olens)
+    assert np.array_equal(paths, opaths)
     reach = want < 255
     assert np.array_equal(lens[reach], want[reach] + 1) and np.all(lens[~reach] == 0)
     for i in np.flatnonzero(reach)[:20000]:
@@ -154,6 +155,7 @@ def test_directed_paths(name, g, window):
     po = gx.export_parents()
     ei = gx.export_in()
     pi = gx.export_in_parents()
+    assert np.array_equal(po, ox.out_par) and np.array_equal(pi, ox.in_par)
     for (off, hub, dist, par, side) in ((e["off"], e["hub"], e["dist"], po, "out"),
                                         (ei["off"], ei["hub"], ei["dist"], pi, "in")):
         owner = np.repeat(np.arange(g.n), np.diff(off))

@@ -299,6 +299,8 @@ def test_weighted_paths(name, g, directed, window):
     pairs = all_pairs(g.n) if g.n <= 200 else gen.random_pairs(g.n, 40_000, 5)
     want = oracle.query_weighted(ox, pairs).astype(np.int64)
     paths, lens = gx.query_path(pairs, max_len=g.n + 1)
+    opaths, olens = oracle.paths_weighted(ox, pairs, g.n + 1)
+    assert np.array_equal(lens, olens) and np.array_equal(paths, opaths)
     reach = want < WINF
     assert np.all(lens[~reach] == 0) and np.all(lens[reach] > 0)
     for i in np.flatnonzero(reach):
@@ -317,6 +319,8 @@ def test_weighted_paths(name, g, directed, window):
     for side, kind in sides:
         e = gx.export_weighted(side)
         par = gx.export_weighted_parents(side)
+        # both sides keep the lowest-ranked tight predecessor (successor)
+        assert np.array_equal(par, ox.par if side == 0 else ox.in_par), (name, side)
         owner = np.repeat(np.arange(g.n), np.diff(e["off"]))
         v, h, pp = order[owner], order[e["hub"]], order[par]
         d = e["dist"].astype(np.float64)

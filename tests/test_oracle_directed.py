@@ -12,6 +12,7 @@ from scipy.sparse.csgraph import shortest_path
 
 import graphs
 import oracle
+import pins
 from paper_1304_4661_amd import gen
 
 INF = 255
@@ -98,15 +99,27 @@ def arcs_of(g):
 def check_directed_parents(g, order, ix, D):
     """Parent of v for (h, d) in L_IN(v): an in-neighbour p of v with
     d(h, p) = d - 1 (v itself at d = 0); in L_OUT(v): an out-neighbour p
-    with d(p, h) = d - 1.  Parents and hubs are ranks."""
+    with d(p, h) = d - 1.  Of those whose label on the same side holds
+    (h, d - 1), the lowest-ranked one.  Parents and hubs are ranks."""
     fails = []
     arcs = arcs_of(g)
+    rank = np.empty(g.n, np.int64)
+    rank[np.asarray(order)] = np.arange(g.n)
+    ins = {v: [] for v in range(g.n)}
+    outs = {v: [] for v in range(g.n)}
+    for a, b in arcs:
+        outs[a].append(b)
+        ins[b].append(a)
     for side, (off, hub, dist, par) in (("L_IN", (ix.in_off, ix.in_hub, ix.in_dist, ix.in_par)),
                                         ("L_OUT", (ix.out_off, ix.out_hub, ix.out_dist,
                                                    ix.out_par))):
+        lab = pins.label_maps(off, hub, dist)
         for r in range(g.n):
             v = int(order[r])
             for e in range(int(off[r]), int(off[r + 1])):
+                if int(par[e]) >= g.n:
+                    fails.append(f"{side} parent of rank {r}: none ({int(par[e])})")
+                    return fails
                 h, d, p = int(order[hub[e]]), int(dist[e]), int(order[par[e]])
                 if d == 0:
                     ok = p == v
@@ -114,6 +127,11 @@ def check_directed_parents(g, order, ix, D):
                     ok = (p, v) in arcs and D[h, p] == d - 1
                 else:
                     ok = (v, p) in arcs and D[p, h] == d - 1
+                if ok and d > 0:
+                    nb = ins[v] if side == "L_IN" else outs[v]
+                    ok = int(rank[p]) == min((int(rank[q]) for q in nb
+                                              if lab[rank[q]].get(int(hub[e])) == d - 1),
+                                             default=None)
                 if not ok:
                     fails.append(f"{side} parent of rank {r} for hub {h}: {p}")
                     return fails
@@ -172,13 +190,17 @@ def test_symmetric_input_reduces_to_undirected():
 
 MUTATIONS = [
     ("reverse search follows the arcs",
-     "rc = directed_bfs(x, k, ioff, iadj, x->lab, x->lab_in, P, T, queue, PP);",
-     "rc = directed_bfs(x, k, off, adj, x->lab, x->lab_in, P, T, queue, PP);"),
+     "rc = directed_bfs(x, k, ioff, iadj, off, adj, x->lab, x->lab_in, P, T, queue);",
+     "rc = directed_bfs(x, k, off, adj, ioff, iadj, x->lab, x->lab_in, P, T, queue);"),
     ("forward search prunes with the root's in-label",
-     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab, P, T, queue, PP);",
-     "rc = directed_bfs(x, k, off, adj, x->lab_in, x->lab_in, P, T, queue, PP);"),
+     "rc = directed_bfs(x, k, off, adj, ioff, iadj, x->lab_in, x->lab, P, T, queue);",
+     "rc = directed_bfs(x, k, off, adj, ioff, iadj, x->lab_in, x->lab_in, P, T, queue);"),
     ("directed parent recorded as the search root",
-     "      PP[w] = u;\n      queue[qt++] = w;\n    }\n  }\n  for", "      PP[w] = k;\n      queue[qt++] = w;\n    }\n  }\n  for"),
+     "uint32_t par = d == 0 ? (uint32_t)k : tree_parent(own, poff, padj, u, k, d);",
+     "uint32_t par = (uint32_t)k;"),
+    ("directed parents looked up along the search's own direction",
+     "rc = directed_bfs(x, k, off, adj, ioff, iadj, x->lab_in, x->lab, P, T, queue);",
+     "rc = directed_bfs(x, k, off, adj, off, adj, x->lab_in, x->lab, P, T, queue);"),
     ("directed path ascends L_OUT from the target",
      "    int64_t e = find_hub(&x->lab_in[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab_in[c].par[e];",
      "    int64_t e = find_hub(&x->lab[c], h);\n    if (e < 0) return ORC_E_RANGE;\n    c = (int32_t)x->lab[c].par[e];"),

@@ -33,8 +33,8 @@ MUTATIONS = [
     ("bit-parallel prune test strict",
      "m0u[i]) <= d) {", "m0u[i]) < d) {"),
     ("literal Algorithm 1 append: distance of the root",
-     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, (uint32_t)PP[u]);",
-     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)0, (uint32_t)PP[u]);"),
+     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)d, par);",
+     "rc = label_push(&x->lab[u], (uint32_t)k, (uint8_t)0, par);"),
     ("literal Algorithm 1 expansion: neighbours of the root",
      "      for (int64_t j = off[u]; j < off[u + 1]; j++) {\n        int32_t w = adj[j];\n        x->cnt[C_EDGES]++;",
      "      for (int64_t j = off[k]; j < off[k + 1]; j++) {\n        int32_t w = adj[j];\n        x->cnt[C_EDGES]++;"),
@@ -50,14 +50,20 @@ MUTATIONS = [
     ("P not reset after a root",
      "    /* reset only what this BFS touched (Section 4.5.1, \"Initialization\") */\n    for (int64_t i = 0; i < qt; i++) P[queue[i]] = 0xFFFF;\n", ""),
     ("next level one too far",
-     "        P[w] = (uint16_t)(d + 1);\n        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset",
-     "        P[w] = (uint16_t)(d + 2);\n        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset"),
+     "        P[w] = (uint16_t)(d + 1);\n        queue[qt++] = w;\n      }\n    }\n    /* reset",
+     "        P[w] = (uint16_t)(d + 2);\n        queue[qt++] = w;\n      }\n    }\n    /* reset"),
     ("S^0 left as the raw dynamic programme",
      "x->bp_0[(int64_t)v * t + slot] = s0[v] & ~s1[v];",
      "x->bp_0[(int64_t)v * t + slot] = s0[v];"),
     ("path parent recorded as the BFS root",
-     "        PP[w] = u;\n        queue[qt++] = w;\n      }\n    }\n    /* reset",
-     "        PP[w] = k;\n        queue[qt++] = w;\n      }\n    }\n    /* reset"),
+     "uint32_t par = d == 0 ? (uint32_t)k : tree_parent(x->lab, off, adj, u, k, d);",
+     "uint32_t par = (uint32_t)k;"),
+    ("path parent: the highest-ranked labeled neighbour",
+     "L->dist[L->len - 1] == d - 1 &&\n        (uint32_t)padj[j] < best)",
+     "L->dist[L->len - 1] == d - 1 &&\n        (best == ORC_SENTINEL || (uint32_t)padj[j] > best))"),
+    ("path parent: any neighbour the BFS labeled, at any level",
+     "if (L->len > 0 && L->hub[L->len - 1] == (uint32_t)k && L->dist[L->len - 1] == d - 1 &&",
+     "if (L->len > 0 && L->hub[L->len - 1] == (uint32_t)k &&"),
     ("walk towards a neighbour follows S^0 instead of S^-1",
      "      c = bp_step(x, c, i, -1, bit, 1);\n", "      c = bp_step(x, c, i, -1, bit, 0);\n"),
     ("bit-parallel path ignores the -1/-2 witnesses",

@@ -16,6 +16,7 @@ from scipy.sparse.csgraph import dijkstra
 
 import graphs
 import oracle
+import pins
 from paper_1304_4661_amd import gen
 
 WINF = oracle.WINF
@@ -99,16 +100,29 @@ def edge_weights(g):
 def check_weighted_parents(g, order, ix, D, directed):
     """Parent p of v for (h, d): v itself at d = 0; else an edge p -> v
     (undirected: p - v) with d(h, p) + w(p, v) = d for L (L_IN), and an arc
-    v -> p with w(v, p) + d(p, h) = d for L_OUT of a digraph."""
+    v -> p with w(v, p) + d(p, h) = d for L_OUT of a digraph; of the
+    vertices q with such an edge whose label on the same side holds
+    (h, d - w), the lowest-ranked one."""
     fails = []
     ew = edge_weights(g)
+    rank = np.empty(g.n, np.int64)
+    rank[np.asarray(order)] = np.arange(g.n)
+    ins = {v: [] for v in range(g.n)}
+    outs = {v: [] for v in range(g.n)}
+    for (a, b) in ew:
+        outs[a].append(b)
+        ins[b].append(a)
     sides = [("L" if not directed else "L_OUT", ix.off, ix.hub, ix.dist, ix.par)]
     if directed:
         sides.append(("L_IN", ix.in_off, ix.in_hub, ix.in_dist, ix.in_par))
     for side, off, hub, dist, par in sides:
+        lab = pins.label_maps(off, hub, dist)
         for r in range(g.n):
             v = int(order[r])
             for e in range(int(off[r]), int(off[r + 1])):
+                if int(par[e]) >= g.n:
+                    fails.append(f"{side} parent of rank {r}: none ({int(par[e])})")
+                    return fails
                 h, d, p = int(order[hub[e]]), int(dist[e]), int(order[par[e]])
                 if d == 0:
                     ok = p == v
@@ -116,6 +130,14 @@ def check_weighted_parents(g, order, ix, D, directed):
                     ok = (v, p) in ew and ew[(v, p)] + D[p, h] == d
                 else:
                     ok = (p, v) in ew and D[h, p] + ew[(p, v)] == d
+                if ok and d > 0:
+                    if side == "L_OUT":
+                        cand = [q for q in outs[v] if lab[rank[q]].get(int(hub[e])) ==
+                                d - ew[(v, q)]]
+                    else:
+                        cand = [q for q in ins[v] if lab[rank[q]].get(int(hub[e])) ==
+                                d - ew[(q, v)]]
+                    ok = int(rank[p]) == min((int(rank[q]) for q in cand), default=None)
                 if not ok:
                     fails.append(f"{side} parent of rank {r} for hub {h}: {p}")
                     return fails
@@ -253,8 +275,11 @@ def test_weighted_generator_is_symmetric():
 
 
 MUTATIONS = [
-    ("parent recorded as the search root", "      D[w] = (uint32_t)nd;\n      PP[w] = u;\n",
-     "      D[w] = (uint32_t)nd;\n      PP[w] = k;\n"),
+    ("parent recorded as the search root",
+     "uint32_t par = d == 0 ? (uint32_t)k : wtree_parent(lab, poff, padj, pw, u, k, d);",
+     "uint32_t par = (uint32_t)k;"),
+    ("parent of a weighted entry one edge of weight 1 closer",
+     "L->dist[L->len - 1] == d - pw[j] &&", "L->dist[L->len - 1] == d - 1 &&"),
     ("path ascends the source side from the target",
      "  int64_t ct = wascend(x, tl, rt, h, NULL, 0, 1, 0);",
      "  int64_t ct = wascend(x, x->in ? x->in : x->out, rs, h, NULL, 0, 1, 0);"),
@@ -269,8 +294,8 @@ MUTATIONS = [
      "  for (int64_t i = 0; i < Lk->len; i++) T[Lk->hub[i]] = ORC_WINF;\n  return rc;", "  return rc;"),
     ("pruned vertices also relax their edges", "    if (pruned) continue;\n", ""),
     ("reverse search prunes with the wrong root labels",
-     "rc = weighted_search(x, k, ioff, iadj, iaw, x->out, x->in,",
-     "rc = weighted_search(x, k, ioff, iadj, iaw, x->out, x->out,"),
+     "rc = weighted_search(x, k, ioff, iadj, iaw, off, adj, aw, x->out, x->in,",
+     "rc = weighted_search(x, k, ioff, iadj, iaw, off, adj, aw, x->out, x->out,"),
     ("merge join on 32-bit sums", "uint64_t v = (uint64_t)A->dist[i] + B->dist[j];",
      "uint64_t v = (uint32_t)(A->dist[i] + B->dist[j]);"),
 ]
