@@ -669,6 +669,10 @@ def main():
                 "bit_parallel_frac": bpb / bp_s / 1e9 / HBM_PEAK_GBS if bp_s else None,
                 "pruned_frac": (prb + fib) / pr_s / 1e9 / HBM_PEAK_GBS if pr_s else None,
                 "whole_step_frac": (bpb + prb + fib + qm) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                # TEPS: edges the method scans (pruned BFSs + bit-parallel
+                # BFSs, oracle counters) per second of GPU build
+                "teps": (counters["edges"] + counters["bp_edges"]) / out["build_s"],
+                "gpu_adjacency_entries_read": st["edges"] + st["task_edges"],
                 "windowed_overhead": {
                     "gpu_visits": st["visited"], "canonical_visits": counters["visited"],
                     "gpu_candidates": st["candidates"], "entries": counters["entries"],

@@ -646,8 +646,11 @@ struct Builder {
     DBuf<uint32_t> hub;
     DBuf<uint8_t> dist;
     DBuf<unsigned long long> top;
+    DBuf<uint4> hdr;
     int64_t pool_cap = 0;
-    DStore view() const { return DStore{off.p, len.p, cap.p, hub.p, dist.p, top.p, pool_cap}; }
+    DStore view() const {
+      return DStore{off.p, len.p, cap.p, hub.p, dist.p, top.p, pool_cap, hdr.p};
+    }
   };
 
   // One search direction of the pruned phase: the graph its BFSs follow,
@@ -690,6 +693,7 @@ struct Builder {
     S.dist.alloc((size_t)pool_cap);
     S.top.alloc(1);
     fill(S.top, 0, st);
+    S.hdr.alloc((size_t)std::max<int32_t>(n, 1));  // set once the bit-parallel masks exist
   }
 
   // Grow the pool so that a commit of ncand candidates cannot run out
@@ -863,6 +867,8 @@ struct Builder {
     }
     DBuf<uint64_t> bpz((size_t)std::max<int32_t>(n, 1));
     check(launch_bpv_nonempty(n, t, ix->bpm.p, bpz.p, st));
+    for (int k = 0; k < nsides; k++)
+      check(launch_store_hdr(stores[k].view(), t > 0 ? bpz.p : nullptr, n, st));
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
     int64_t entries_bound[2] = {0, 0};
     // Expansion-time prune rows.  With bit-parallel labels they are the

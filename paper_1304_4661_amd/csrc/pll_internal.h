@@ -281,6 +281,10 @@ enum : int32_t {
 
 // Growing label store used during the build: label of rank r lives at
 // hub/dist[off[r] .. off[r]+len[r]) inside a pool; cap[r] slots reserved.
+// hdr[r] repeats what a prune test of r reads first, in one 16-byte
+// record: x, y = the bit-parallel mask z[r] (slots whose sets are not both
+// empty), z = off[r] / 16 (slots are reserved in multiples of 16 entries),
+// w = len[r].
 struct DStore {
   int64_t *off;
   int32_t *len;
@@ -289,6 +293,7 @@ struct DStore {
   uint8_t *dist;
   unsigned long long *top;  // pool bump pointer (device)
   int64_t pool_cap;
+  uint4 *hdr;
 };
 
 // Frontier and task buffers shared by both BFS phases.
@@ -512,6 +517,8 @@ hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);
 hipError_t launch_win_clean(DWindow w, DWindow o, int64_t ncand, hipStream_t st);
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
+// hdr of an empty store (z: the bit-parallel masks, or null for none)
+hipError_t launch_store_hdr(DStore s, const uint64_t *z, int32_t n, hipStream_t st);
 hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint8_t *fdist,
                              int32_t n, hipStream_t st);
 // Parents of the final labels (shortest paths, Section 6): for every entry

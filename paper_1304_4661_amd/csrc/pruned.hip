@@ -546,9 +546,11 @@ __global__ void __launch_bounds__(kBlock, kTestWavesPerSimd<G>) k_win_test_flat(
       if (gr == 0) c_visit++;
       // everything both tests may read that depends only on (j, u) is
       // loaded now, so the loads are in flight together
-      const uint64_t zk = bp.t ? bp.z[w.s + j] : 0ull, zu = bp.t ? bp.z[u] : 0ull;
-      const int64_t lo = st.off[u];
-      const int32_t llen = st.len[u];
+      const uint64_t zk = bp.t ? bp.z[w.s + j] : 0ull;
+      const uint4 hd = st.hdr[u];
+      const uint64_t zu = (uint64_t)hd.y << 32 | hd.x;
+      const int64_t lo = (int64_t)hd.z << 4;
+      const int32_t llen = (int32_t)hd.w;
       const RootTable Tj = root_table(w, j);
       const ulonglong2 *sg = reinterpret_cast<const ulonglong2 *>(w.sig + 4 * (int64_t)j);
       const ulonglong2 s01 = sg[0], s23 = sg[1];
@@ -695,7 +697,7 @@ constexpr int kTWaves = kTBlock / kWave;
 // roots' labels come from (the same for an undirected graph; the other
 // side's for a digraph).
 template <int G>
-__global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
+__global__ void __launch_bounds__(kTBlock, 5) k_win_test(DGraph g, DBp bp, DStore st, DStore rst,
                                                      DWindow w, DFrontier f, DRootSort rs,
                                                      int d) {
   __shared__ uint4 s_ht[kLdsSlots / 4];
@@ -839,15 +841,16 @@ __global__ void __launch_bounds__(kTBlock) k_win_test(DGraph g, DBp bp, DStore s
       int64_t uoff = 0;
       if (p < t1) {
         u = rs.sv[p];
-        // u's label place, loaded with its bit-parallel row for the
-        // normal-label test it may reach
-        uoff = st.off[u];
-        ulen = st.len[u];
+        // u's bit-parallel mask and label place in one load, in flight
+        // with its bit-parallel row
+        const uint4 hd = st.hdr[u];
+        uoff = (int64_t)hd.z << 4;
+        ulen = (int32_t)hd.w;
         if (gra == 0) c_visit++;
         // bit-parallel labels first (Section 5.4)
         survive = true;
         if (bp.t) {
-          const uint64_t zu = bp.z[u];
+          const uint64_t zu = (uint64_t)hd.y << 32 | hd.x;
           survive = !bp_prunes<kGA>(bp, s_krow, s_kpairs, u, d, zk, zu, tally);
         }
       }
@@ -1234,10 +1237,11 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
   const int64_t nloop = (ncand + stride - 1) / stride;
   for (int64_t it = 0; it < nloop; it++) {
     const int64_t c = t0 + it * stride;
-    bool reloc = false;
-    int32_t u = 0, len = 0;
+    bool reloc = false, mine = false;
+    int32_t u = 0, len = 0, need = 0;
     int64_t oo = 0, no = 0, nc = 0;
     if (c < ncand && w.cdes[c]) {
+      mine = true;
       u = w.cu[c];
       const uint64_t *krow = w.kmask + (int64_t)u * w.words;
       uint64_t *crow = w.cmask + (int64_t)u * w.words;
@@ -1254,7 +1258,7 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
         }
       }
       len = st.len[u];
-      const int32_t need = len + total;
+      need = len + total;
       if (total > 0 && need > st.cap[u]) {
         nc = 2 * (int64_t)need;
         if (nc < 16) nc = 16;
@@ -1279,6 +1283,11 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_alloc(DWindow w, DStore s
     if (reloc) {
       st.off[u] = no;
       st.cap[u] = (int32_t)nc;
+    }
+    // the test kernels' copy of the place and length (one 8-byte store)
+    if (mine) {
+      const uint64_t o16 = (uint64_t)((reloc ? no : st.off[u]) >> 4);
+      reinterpret_cast<uint64_t *>(st.hdr + u)[1] = o16 | ((uint64_t)(uint32_t)need << 32);
     }
   }
 }
@@ -1335,6 +1344,15 @@ __global__ void __launch_bounds__(kBlock) k_win_commit_clear(DWindow w, int64_t 
     ulonglong2 *p = reinterpret_cast<ulonglong2 *>(w.csum + 4 * (int64_t)u);
     p[0] = make_ulonglong2(0ull, 0ull);
     p[1] = make_ulonglong2(0ull, 0ull);
+  }
+}
+
+// hdr of an empty store: the bit-parallel masks, place 0, length 0
+__global__ void k_store_hdr(uint4 *hdr, const uint64_t *z, int32_t n) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t m = z ? z[r] : 0ull;
+    hdr[r] = make_uint4((uint32_t)m, (uint32_t)(m >> 32), 0u, 0u);
   }
 }
 
@@ -1542,6 +1560,12 @@ hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st)
 
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(k_final_count, dim3((n + 255) / 256), dim3(256), 0, st, len, cnt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_hdr(DStore s, const uint64_t *z, int32_t n, hipStream_t st) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_store_hdr, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, s.hdr, z, n);
   return hipGetLastError();
 }
 

@@ -289,6 +289,10 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
   __shared__ int32_t s_nj[kWaves][kWStage], s_nu[kWaves][kWStage];
   __shared__ int32_t s_tj[kWaves][kWStage], s_tu[kWaves][kWStage];
   __shared__ int32_t s_n1[kWaves], s_n2[kWaves];
+  // the root's 16-bit landmark distances of each entry a wave holds, read
+  // by the entry's lanes while they relax its edges (held in registers they
+  // would spill at 8 waves per SIMD)
+  __shared__ uint4 s_rl[kWaves][kWave / G][kWLand / 8];
   __shared__ unsigned long long s_b1, s_b2, s_sum[7];
   __shared__ bool s_go;
   // one thread decides for the block (the flags may change meanwhile)
@@ -339,17 +343,19 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
   };
   auto flush_n = [&](WaveStage<kWStage> &sg) { write_n(sg, sg.reserve(outc)); };
   auto flush_t = [&](WaveStage<kWStage> &sg) { write_t(sg, sg.reserve(&w.ctl->tcnt)); };
-  // per-lane counts (far below 2^32 within one launch; the wave sums are
-  // 64-bit)
-  uint32_t c_tests = 0, c_scanned = 0, c_edges = 0, c_improved = 0, c_proc = 0, c_filtered = 0,
-           c_checked = 0;
+  // counts: labels scanned per lane, the others per wave (ballots, so they
+  // stay in scalar registers); far below 2^32 within one launch, the block
+  // sums are 64-bit
+  uint32_t c_scanned = 0;
+  uint32_t c_tests = 0, c_edges = 0, c_improved = 0, c_proc = 0, c_filtered = 0, c_checked = 0;
+  const uint4 *rl = s_rl[wv][lane_id() / G];
   // the wave steps through the list in lockstep, kPerWave entries at a time
   for (int64_t base = wid * kPerWave; base < (int64_t)cnt; base += nw * kPerWave) {
     const int64_t i = base + lane_id() / G;
     int32_t j = 0, u = 0;
     uint32_t d = 0;
     int64_t a = 0, b = 0;  // u's edges to relax (none if pruned)
-    uint32_t rl[kWLand / 2];  // the root's distances to the landmark hubs, in pairs
+    bool tested = false;
     if (i < (int64_t)cnt) {
       j = inj[i];
       u = inu[i];
@@ -358,7 +364,6 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
       if (gr == 0) {
         f = fl_clear(w.fl, idx, qc);
         d = w.tdp ? (uint32_t)(ld_acquire_agent(&w.tdp[idx]) >> 32) : ld_acquire_agent(&w.td[idx]);
-        c_proc++;
       }
       // what the prune test may read that depends only on (j, u) is loaded
       // now, in flight with the flag and distance
@@ -372,7 +377,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
       d = (uint32_t)__shfl((int)d, gb);
       bool pr = false;
       if (!(f & kLabeled)) {
-        if (gr == 0) c_tests++;
+        tested = true;
         // entries of landmark hubs cannot prune here (see above): the entry
         // was reached below the 16-bit bound, and a hub left out of that
         // bound is at least 65535 away, so below 65535 none of them can
@@ -381,44 +386,40 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
         if (!pr && gr == 0) fl_or(w.fl, idx, kLabeled);
       }
       if (!pr) {
-        if (w.lroot) {
+        if (w.lroot && gr < kWLand / 8) {
           const uint4 *p = reinterpret_cast<const uint4 *>(w.lroot + (int64_t)(w.s + j) * kWLand);
-#pragma unroll
-          for (int q = 0; q < kWLand / 8; q++) {
-            const uint4 x = p[q];
-            rl[4 * q] = x.x;
-            rl[4 * q + 1] = x.y;
-            rl[4 * q + 2] = x.z;
-            rl[4 * q + 3] = x.w;
-          }
+          s_rl[wv][lane_id() / G][gr] = p[gr];
         }
         a = g.row[u];
         b = g.row[u + 1];
       }
     }
+    c_proc += (uint32_t)__popcll(__ballot(i < (int64_t)cnt && gr == 0));
+    c_tests += (uint32_t)__popcll(__ballot(tested && gr == 0));
+    __threadfence_block();  // the landmark rows in LDS are visible to the whole wave
     const int64_t wl = Group<kWave>::max_reduce64(b - a);
     for (int64_t e0 = 0; e0 < wl; e0 += G) {
       const int64_t e = a + e0 + gr;
       bool push_n = false, push_t = false;
       int32_t v = 0;
+      bool checked = false, filtered = false, lowered_any = false;
       if (e < b) {
         v = g.col[e];
         const uint64_t nd = (uint64_t)d + g.wt[e];
-        c_edges++;
         bool useful = nd < (uint64_t)kWInf;
         if (useful && w.lroot) {
-          c_checked++;
+          checked = true;
           const uint4 *p = reinterpret_cast<const uint4 *>(w.lvert + (int64_t)v * kWLand);
           uint32_t lb = kWInf;
 #pragma unroll
           for (int q = 0; q < kWLand / 8; q++) {
-            const uint4 x = p[q];
-            const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+            const uint4 x = p[q], r = rl[q];
+            const uint32_t xv[4] = {x.x, x.y, x.z, x.w}, rv[4] = {r.x, r.y, r.z, r.w};
 #pragma unroll
             for (int i = 0; i < 4; i++) {
 #pragma unroll
               for (int half = 0; half < 2; half++) {
-                const uint32_t a16 = (rl[4 * q + i] >> (16 * half)) & 0xFFFFu;
+                const uint32_t a16 = (rv[i] >> (16 * half)) & 0xFFFFu;
                 const uint32_t b16 = (xv[i] >> (16 * half)) & 0xFFFFu;
                 const uint32_t t = (a16 == 0xFFFFu || b16 == 0xFFFFu) ? kWInf : a16 + b16;
                 lb = t < lb ? t : lb;
@@ -427,7 +428,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
           }
           if ((uint64_t)lb <= nd) {
             useful = false;
-            c_filtered++;
+            filtered = true;
           }
         }
         if (useful) {
@@ -446,23 +447,25 @@ __global__ void __launch_bounds__(kBlock, 8) k_ww_step(DWGraph g, DWStore s, DWW
             lowered = (uint32_t)nd < atomicMin(&w.td[vi], (uint32_t)nd);
           }
           if (lowered) {
-            c_improved++;
+            lowered_any = true;
             const uint32_t of = fl_or(w.fl, vi, kTouched | qn);
             push_t = !(of & kTouched);
             push_n = !(of & qn);
           }
         }
       }
+      c_edges += (uint32_t)__popcll(__ballot(e < b));
+      c_checked += (uint32_t)__popcll(__ballot(checked));
+      c_filtered += (uint32_t)__popcll(__ballot(filtered));
+      c_improved += (uint32_t)__popcll(__ballot(lowered_any));
       sn.push(push_n, j, v, flush_n);
       stt.push(push_t, j, v, flush_t);
     }
   }
   write_n(sn, block_reserve(sn, outc, s_n1, &s_b1));
   write_t(stt, block_reserve(stt, &w.ctl->tcnt, s_n2, &s_b2));
-  const unsigned long long sums[7] = {wave_sum(c_checked), wave_sum(c_filtered),
-                                      wave_sum(c_tests),   wave_sum(c_scanned),
-                                      wave_sum(c_edges),   wave_sum(c_improved),
-                                      wave_sum(c_proc)};
+  const unsigned long long sums[7] = {c_checked, c_filtered, c_tests, wave_sum(c_scanned),
+                                      c_edges,   c_improved, c_proc};
   if (lane_id() == 0)
     for (int q = 0; q < 7; q++)
       if (sums[q]) atomicAdd(&s_sum[q], sums[q]);
