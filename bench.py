@@ -5,11 +5,14 @@ MI355X.
 One step = the whole hot path on one synthetic workload with its inputs
 already in HBM: rank relabel, bit-parallel root choice, bit-parallel BFSs,
 windowed pruned BFSs with cleaning, final label CSR, then one batch of query
-pairs.  Default workload: R-MAT scale 18 (edge factor 16, a/b/c/d =
+pairs.  Default workload: R-MAT scale 22 (edge factor 16, a/b/c/d =
 .57/.19/.19/.05, symmetrized, de-duplicated, self-loops dropped, largest
-component kept), Degree order, t_bp = 50, 1e6 uniform random pairs.
+component kept), Degree order, t_bp = 64, 1e7 uniform random pairs.
 
-Prints ONE JSON line.  See DESIGN.md for the byte model behind "roofline".
+Prints ONE JSON line.  "roofline" prices the dominant kernel's launches with
+the per-unit byte model of level_kernel_bytes / expand_kernel_bytes below;
+"method_bytes" prices the whole build with the method's own model over the
+oracle's canonical work counters (s8d_bytes).
 """
 from __future__ import annotations
 
@@ -72,8 +75,7 @@ def file_sha(path):
 
 def level_kernel_bytes(st, t_bp, sides=1):
     """Algorithmic bytes of the pruned-phase prune-test kernel (k_win_test),
-    summed over all its launches in one build (per-unit figures of the byte
-    model in DESIGN.md):
+    summed over all its launches in one build (per-unit figures):
       per level entry (root slot, vertex) past level 0: 8 B entry + t_bp B
         distance row (the roots themselves are labeled by the window's init
         kernel and never reach this kernel; a digraph's two search
@@ -334,7 +336,9 @@ def serving_loads(ix, nreq, max_batch=4096):
             r = binding.serve_bench(ix, f * sat["requests_per_s"], nreq, max_batch=max_batch,
                                     seed=106)
             loads[str(f)] = {k: r[k] for k in ("p50_us", "p99_us", "mean_us", "pairs_per_s",
-                                                "requests_per_s", "pairs_per_launch")}
+                                                "requests_per_s", "pairs_per_launch",
+                                                "launches", "max_launch_us", "max_launch_at",
+                                                "max_worker_pause_us")}
         res[mode] = {"x_sat_requests_per_s": sat["requests_per_s"],
                      "x_sat_pairs_per_s": sat["pairs_per_s"], "loads": loads}
     binding.set_tuning("serve_coalesce", 1)

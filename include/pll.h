@@ -286,10 +286,10 @@ int pll_export_sizes(const pll_index *idx, int32_t graph, int64_t *n, int64_t *e
  * and the path follows the arcs).  When only a bit-parallel slot gives it (lowest slot on
  * ties), the path is walked through neighbours in ascending rank: to the
  * slot's root, or to its chosen neighbour w in S^{-1} / S^{0} (Section 5.1
- * sets) of both ends.  Paths over normal labels depend on which parent a
- * concurrent build recorded: any shortest path may come back, its length
- * is always d+1.  Memory kinds, validation, errors and PLL_SYNC as
- * pll_query.
+ * sets) of both ends.  Parents are chosen by a fixed rule (see
+ * pll_export_parents), so the same index and pair always give the same
+ * path, whatever the window sizes of the build.  Memory kinds,
+ * validation, errors and PLL_SYNC as pll_query.
  */
 int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_t max_len,
                    int32_t *paths, int32_t *lens, uint32_t flags, void *stream);
@@ -297,17 +297,20 @@ int pll_query_path(const pll_index *idx, const int32_t *pairs, int64_t q, int32_
 /*
  * Parents of one graph's label entries (index built with PLL_PARENTS, else
  * PLL_E_UNSUPPORTED), in pll_export's entry order, as local ranks: the
- * parent of vertex v for entry (h, d) is a neighbour of v at distance d-1
- * from h, and v itself for d = 0 (for L_OUT of a digraph: an out-neighbour
- * p of v with d(p, h) = d-1).  par: host uint32[entries].
+ * parent of vertex v for entry (h, d) is the lowest-ranked neighbour p of v
+ * whose label holds (h, d-1) -- a vertex the BFS from h labeled one step
+ * closer, so v's parent in that BFS tree -- and v itself for d = 0 (for
+ * L_OUT of a digraph: the lowest-ranked out-neighbour p of v with (h, d-1)
+ * in L_OUT(p)).  par: host uint32[entries].
  */
 int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par);
 
 /*
  * Parents of the L_IN entries of a directed index built with PLL_PARENTS
  * (else PLL_E_UNSUPPORTED), in pll_export_in's entry order, as local ranks:
- * for (h, d) in L_IN(v), an in-neighbour p of v with d(h, p) = d-1, and v
- * itself for d = 0.  par: host uint32[entries of pll_export_in].
+ * for (h, d) in L_IN(v), the lowest-ranked in-neighbour p of v with (h, d-1)
+ * in L_IN(p), and v itself for d = 0.  par: host uint32[entries of
+ * pll_export_in].
  */
 int pll_export_in_parents(const pll_index *idx, int32_t graph, uint32_t *par);
 
@@ -338,8 +341,9 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
  *            time), PLL_DIRECTED (the CSR lists out-arcs; labels L_OUT and
  *            L_IN as for pll_build), PLL_PARENTS (every entry keeps the
  *            parent of its vertex in the hub's search tree: among the
- *            labeled vertices p with d(h, p) + w(p, v) = d, the lowest
- *            ranked; pll_query_path then restores paths)
+ *            vertices p with an edge p -> v whose label holds
+ *            (h, d - w(p, v)), the lowest ranked; pll_query_path then
+ *            restores paths)
  * A relaxation whose distance would reach 2^32 - 1 is dropped: a vertex that
  * far from a root counts as unreachable from it, so the labels are the
  * exact ones with distance below 2^32 - 1 and queries read 2^32 - 1
@@ -476,8 +480,10 @@ const char *pll_strerror(int code);
  *   pll_query would give it alone.
  *   On a weighted index (pll_build_weighted) the answers are pll_query_
  *   weighted's 32-bit distances.
- * pll_server_submit: queue q (1..slot_pairs) pairs from host memory; the
- *   answers go to out[q] (host).  The caller keeps pairs and out alive until
+ * pll_server_submit: queue q (>= 1) pairs from host memory; the answers go
+ *   to out[q] (host).  A request of more than slot_pairs pairs is queued as
+ *   consecutive parts of slot_pairs pairs (the last one shorter), each
+ *   dispatched like a request; it is done when its last part is.  The caller keeps pairs and out alive until
  *   the request is done.  *ticket identifies the request.  Ids are checked
  *   on submission (PLL_E_INVAL).  PLL_E_UNSUPPORTED on a server of a
  *   weighted index.
@@ -487,13 +493,18 @@ const char *pll_strerror(int code);
  * pll_server_done: 1 if the request is answered (optionally waiting), 0 if
  *   not yet; *latency_us = answer time - submission time.
  * pll_server_stop: answer everything queued, stop the worker, free the
- *   server.  stats (optional): launches, pairs launched, max queue length.
+ *   server.  stats (optional, up to 6): launches, pairs launched, max queue
+ *   length, the longest launch in ns (from its dispatch to the worker seeing
+ *   its completion event), its number among the launches, and the longest
+ *   pause in ns between two passes of the worker while it had work.
  * pll_serve_bench: open-loop load test in native code: nreq requests of
  *   log-uniform size in [1, max_batch] with uniform random pairs, Poisson
  *   arrivals at `rate` requests/s (rate <= 0: all at once = saturation),
- *   SplitMix64 randomness from seed.  stats[9]: p50 / p99 / mean latency in
- *   us (from the scheduled arrival, so queueing counts), pairs/s,
- *   requests/s, seconds, launches, mean pairs per launch, max queue length.
+ *   SplitMix64 randomness from seed.  stats[12]: p50 / p99 / mean latency
+ *   in us (from the scheduled arrival, so queueing counts), pairs/s,
+ *   requests/s, seconds, launches, mean pairs per launch, max queue length,
+ *   the longest launch in us, its launch number and the worker's longest
+ *   pause in us.
  */
 typedef struct pll_server pll_server;
 int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, pll_server **out);

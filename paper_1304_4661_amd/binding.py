@@ -42,7 +42,8 @@ EXPORTED = [
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
-               "launches", "pairs_per_launch", "max_queue"]
+               "launches", "pairs_per_launch", "max_queue", "max_launch_us", "max_launch_at",
+               "max_worker_pause_us"]
 
 
 class PllError(RuntimeError):

@@ -1077,7 +1077,16 @@ struct Builder {
         fpar.alloc((size_t)std::max<int64_t>(total, 1));
         const DGraph pred = !directed ? graph() : k == 0 ? DGraph{n, nwords, irow.p, icol.p}
                                                          : graph();
-        check(launch_tree_parents(pred, foff.p, fhub.p, fdist.p, fpar.p, n, st));
+        DBuf<int64_t> icnt((size_t)std::max(n, 1)), ioff((size_t)n + 1),
+            itmp((size_t)scan_tmp_elems((int64_t)n + 1));
+        check(launch_tree_count(pred, icnt.p, n, st));
+        check(launch_exclusive_scan(icnt.p, ioff.p, n, itmp.p, st));
+        int64_t nitems = 0;
+        if (n > 0) d2h(&nitems, ioff.p + n, 1, st);
+        check(hipStreamSynchronize(st));
+        DBuf<int32_t> items((size_t)std::max<int64_t>(nitems, 1));
+        check(launch_tree_parents(pred, foff.p, fhub.p, fdist.p, fpar.p, n, ioff.p, items.p,
+                                  nitems, st));
       }
       check(hipStreamSynchronize(st));
       ix->entries += total - n;

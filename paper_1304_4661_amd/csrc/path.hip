@@ -100,37 +100,125 @@ __device__ int bp_walk(const DIndex &ix, int32_t c, int32_t i, uint64_t bit, int
   return -1;
 }
 
-// One wave per vertex u: for each entry (h, d) of u, the lanes test the
-// predecessors p of u (a row of `pred`) in parallel for (h, d - 1) in L(p)
-// (a binary search over L(p), sorted by hub rank) and the wave keeps the
-// lowest-ranked hit.
-__global__ void __launch_bounds__(kBlock) k_tree_parents(DGraph pred, const int64_t *foff,
-                                                         const uint32_t *fhub,
-                                                         const uint8_t *fdist, uint32_t *fpar,
-                                                         int32_t n) {
+// Parents of the final labels.  The predecessors of a vertex u (row u of
+// `pred`) are cut into chunks of kParChunk, one work item per chunk, so a
+// high-degree vertex spreads over many waves.  k_tree_init gives the self
+// entries their vertex and every other entry kSentinel; an item then takes
+// the minimum, over its predecessors p, of p for each entry (h, d) of u with
+// (h, d - 1) in L(p), and writes it (an atomic minimum when u has several
+// items).  Labels of up to kParLds entries: L(u) is copied to LDS with a
+// best-parent slot per entry and each predecessor's label streams through
+// the wave, a lane per entry (h', d'): a binary search of h' in L(u) in
+// LDS, and if u holds (h', d'+1), an LDS atomic minimum of p.  Longer
+// labels: per entry of u, the lanes test the chunk's predecessors for
+// (h, d - 1) by a binary search in global memory.
+constexpr int kParLds = 1024;
+constexpr int kParChunk = 64;
+constexpr int kParWaves = kBlock / kWave;
+
+__global__ void __launch_bounds__(kBlock) k_tree_init(const int64_t *foff, const uint8_t *fdist,
+                                                      uint32_t *fpar, int32_t n) {
   const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
   for (int64_t u = wid; u < n; u += nw) {
+    const int64_t a = foff[u], b = foff[u + 1];  // sentinel at b - 1
+    for (int64_t e = a + lane_id(); e < b; e += kWave)
+      fpar[e] = (e < b - 1 && fdist[e] == 0) ? (uint32_t)u : kSentinel;
+  }
+}
+
+__global__ void k_tree_count(DGraph pred, int64_t *cnt, int32_t n) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t deg = pred.row[u + 1] - pred.row[u];
+    cnt[u] = deg > 0 ? (deg + kParChunk - 1) / kParChunk : 0;
+  }
+}
+
+// items[ioff[u] .. ioff[u+1]) = u
+__global__ void __launch_bounds__(kBlock) k_tree_items(const int64_t *ioff, int32_t *items,
+                                                       int32_t n) {
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t u = wid; u < n; u += nw)
+    for (int64_t t = ioff[u] + lane_id(); t < ioff[u + 1]; t += kWave) items[t] = (int32_t)u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_tree_parents(DGraph pred, const int64_t *foff,
+                                                         const uint32_t *fhub,
+                                                         const uint8_t *fdist, uint32_t *fpar,
+                                                         const int64_t *ioff,
+                                                         const int32_t *items, int64_t nitems) {
+  __shared__ uint32_t s_h[kParWaves][kParLds];
+  __shared__ int32_t s_best[kParWaves][kParLds];
+  __shared__ uint8_t s_d[kParWaves][kParLds];
+  const int wv = threadIdx.x / kWave;
+  uint32_t *lh = s_h[wv];
+  int32_t *lb = s_best[wv];
+  uint8_t *ld = s_d[wv];
+  const int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / kWave;
+  for (int64_t t = wid; t < nitems; t += nw) {
+    const int32_t u = items[t];
+    const bool single = ioff[u + 1] - ioff[u] == 1;  // no other item writes u's entries
     const int64_t a = foff[u], b = foff[u + 1] - 1;  // the sentinel sits at b
-    const int64_t r0 = pred.row[u], r1 = pred.row[u + 1];
-    for (int64_t e = a; e < b; e++) {
-      const uint32_t h = fhub[e];
-      const int d = fdist[e];
-      int best = d == 0 ? (int)u : INT_MAX;
-      for (int64_t x0 = r0; d > 0 && x0 < r1; x0 += kWave) {
-        const int64_t x = x0 + lane_id();
+    const int32_t len = (int32_t)(b - a);
+    const int64_t r0 = pred.row[u] + (t - ioff[u]) * kParChunk;
+    const int64_t r1 = r0 + kParChunk < pred.row[u + 1] ? r0 + kParChunk : pred.row[u + 1];
+    if (len <= kParLds) {
+      for (int32_t i = lane_id(); i < len; i += kWave) {
+        lh[i] = fhub[a + i];
+        ld[i] = fdist[a + i];
+        lb[i] = INT_MAX;
+      }
+      __threadfence_block();  // L(u) in LDS is visible to the whole wave
+      for (int64_t x = r0; x < r1; x++) {
+        const int32_t p = pred.col[x];
+        const int64_t pa = foff[p], pb = foff[p + 1] - 1;
+        for (int64_t e = pa + lane_id(); e < pb; e += kWave) {
+          const uint32_t h = fhub[e];
+          const int dp = fdist[e];
+          int32_t lo = 0, hi = len;  // first entry of L(u) with hub >= h
+          while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (lh[mid] < h)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          if (lo < len && lh[lo] == h && (int)ld[lo] == dp + 1) atomicMin(&lb[lo], p);
+        }
+      }
+      __threadfence_block();
+      for (int32_t i = lane_id(); i < len; i += kWave) {
+        if (lb[i] == INT_MAX) continue;
+        if (single)
+          fpar[a + i] = (uint32_t)lb[i];
+        else
+          atomicMin(&fpar[a + i], (uint32_t)lb[i]);
+      }
+      __threadfence_block();  // done with this wave's LDS before the next item
+    } else {
+      for (int64_t e = a; e < b; e++) {
+        const uint32_t h = fhub[e];
+        const int d = fdist[e];
+        if (d == 0) continue;
         int y = INT_MAX;
+        const int64_t x = r0 + lane_id();
         if (x < r1) {
           const int32_t p = pred.col[x];
           const int64_t f = find_hub(foff, fhub, p, h);
           if (f >= 0 && (int)fdist[f] == d - 1) y = p;
         }
         y = Group<kWave>::min_reduce(y);
-        best = y < best ? y : best;
+        if (lane_id() == 0 && y != INT_MAX) {
+          if (single)
+            fpar[e] = (uint32_t)y;
+          else
+            atomicMin(&fpar[e], (uint32_t)y);
+        }
       }
-      if (lane_id() == 0) fpar[e] = best == INT_MAX ? kSentinel : (uint32_t)best;
     }
-    if (lane_id() == 0) fpar[b] = kSentinel;
   }
 }
 
@@ -289,11 +377,24 @@ hipError_t launch_invert_rank(const int32_t *rank, int32_t *ord, int32_t n, hipS
   return hipGetLastError();
 }
 
-hipError_t launch_tree_parents(DGraph pred, const int64_t *foff, const uint32_t *fhub,
-                               const uint8_t *fdist, uint32_t *fpar, int32_t n, hipStream_t st) {
+hipError_t launch_tree_count(DGraph pred, int64_t *cnt, int32_t n, hipStream_t st) {
   if (n > 0)
-    hipLaunchKernelGGL(k_tree_parents, dim3(grid_for((int64_t)n * kWave, kBlock, 8192)),
-                       dim3(kBlock), 0, st, pred, foff, fhub, fdist, fpar, n);
+    hipLaunchKernelGGL(k_tree_count, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, pred, cnt, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_parents(DGraph pred, const int64_t *foff, const uint32_t *fhub,
+                               const uint8_t *fdist, uint32_t *fpar, int32_t n,
+                               const int64_t *ioff, int32_t *items, int64_t nitems,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const unsigned gw = grid_for((int64_t)n * kWave, kBlock, 8192);
+  hipLaunchKernelGGL(k_tree_init, dim3(gw), dim3(kBlock), 0, st, foff, fdist, fpar, n);
+  if (nitems > 0) {
+    hipLaunchKernelGGL(k_tree_items, dim3(gw), dim3(kBlock), 0, st, ioff, items, n);
+    hipLaunchKernelGGL(k_tree_parents, dim3(grid_for(nitems * kWave, kBlock, 8192)),
+                       dim3(kBlock), 0, st, pred, foff, fhub, fdist, fpar, ioff, items, nitems);
+  }
   return hipGetLastError();
 }
 

@@ -524,9 +524,14 @@ hipError_t launch_final_copy(DStore s, const int64_t *foff, uint32_t *fhub, uint
 // Parents of the final labels (shortest paths, Section 6): for every entry
 // (h, d) of u with d >= 1, the lowest-ranked p with an edge p -> u (row u of
 // `pred`) whose label holds (h, d - 1); u itself for d = 0.  Sentinels get
-// kSentinel.
+// kSentinel.  Work items: chunks of a vertex's predecessors; cnt[u] = items
+// of u (launch_tree_count), ioff = its exclusive scan (n + 1 values, nitems
+// in total), items: int32[nitems] scratch.
+hipError_t launch_tree_count(DGraph pred, int64_t *cnt, int32_t n, hipStream_t st);
 hipError_t launch_tree_parents(DGraph pred, const int64_t *foff, const uint32_t *fhub,
-                               const uint8_t *fdist, uint32_t *fpar, int32_t n, hipStream_t st);
+                               const uint8_t *fdist, uint32_t *fpar, int32_t n,
+                               const int64_t *ioff, int32_t *items, int64_t nitems,
+                               hipStream_t st);
 
 // Queries: ranks of ids, bit-parallel labels, final CSR labels with sentinel.
 struct DIndex {

@@ -10,7 +10,8 @@
 // run, so requests that arrive while earlier ones are on the GPU are
 // admitted as soon as a slot (and its memory) frees up, and their work
 // overlaps on the device.  Completed batches are scattered back to each
-// request's output and stamped.
+// request's output and stamped.  A request larger than a slot is queued as
+// slot-sized parts and stamped when its last part completes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,12 +46,16 @@ int64_t now_ns() {
       .count();
 }
 
+// A request, or one slot-sized part of a request larger than a slot (then
+// `parent` is the request; it is answered when its last part is).
 struct Req {
   const int32_t *pairs = nullptr;
   void *out = nullptr;  // es bytes per answer (the server's answer size)
   int64_t q = 0;
   int64_t t_arrive = 0;             // ns, steady clock
   std::atomic<int64_t> t_done{0};   // 0 until answered
+  Req *parent = nullptr;
+  std::atomic<int64_t> parts_left{0};  // parts not yet answered (split requests)
 };
 
 struct Slot {
@@ -63,6 +68,8 @@ struct Slot {
   std::vector<Req *> reqs;
   int64_t n = 0;
   bool busy = false;
+  int64_t t_dispatch = 0;  // ns, when the batch was queued on the stream
+  int64_t launch = 0;      // its number among the server's launches
 };
 
 }  // namespace
@@ -80,12 +87,15 @@ struct pll_server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Req> reqs;          // owned requests; ticket = position
+  std::deque<Req> parts;         // owned parts of requests larger than a slot
   std::deque<Req *> pending;     // FIFO of submitted, not yet dispatched
   std::atomic<bool> stopping{false};
   std::atomic<int> err{0};
   std::thread worker;
-  // statistics
-  int64_t launches = 0, batched_pairs = 0, max_pending = 0;
+  // statistics; the longest launch is timed from its dispatch to the host
+  // seeing its event
+  int64_t launches = 0, batched_pairs = 0, max_pending = 0, max_launch_ns = 0,
+          max_launch_at = -1, max_gap_ns = 0;
 
   void run();
   void release();
@@ -124,6 +134,8 @@ bool dispatch(pll_server *sv, Slot &sl) {
   if (e == hipSuccess) e = hipEventRecord(sl.ev, sl.s);
   if (e != hipSuccess) sv->err = PLL_E_DEVICE;
   sl.busy = true;
+  sl.t_dispatch = now_ns();
+  sl.launch = sv->launches;
   sv->launches++;
   sv->batched_pairs += sl.n;
   return true;
@@ -135,11 +147,18 @@ bool complete(pll_server *sv, Slot &sl) {
   if (e == hipErrorNotReady) return false;
   if (e != hipSuccess) sv->err = PLL_E_DEVICE;
   const int64_t t = now_ns();
+  if (t - sl.t_dispatch > sv->max_launch_ns) {
+    sv->max_launch_ns = t - sl.t_dispatch;
+    sv->max_launch_at = sl.launch;
+  }
   int64_t off = 0;
   for (Req *r : sl.reqs) {
     std::copy(sl.ho + off * sv->es, sl.ho + (off + r->q) * sv->es, static_cast<uint8_t *>(r->out));
     off += r->q;
-    r->t_done.store(t, std::memory_order_release);
+    if (!r->parent)
+      r->t_done.store(t, std::memory_order_release);
+    else if (r->parent->parts_left.fetch_sub(1) == 1)  // its last part
+      r->parent->t_done.store(t, std::memory_order_release);
   }
   sl.reqs.clear();
   sl.busy = false;
@@ -149,7 +168,13 @@ bool complete(pll_server *sv, Slot &sl) {
 }  // namespace
 
 void pll_server::run() {
+  int64_t t_prev = now_ns();
   for (;;) {
+    // the longest time between two passes of the worker while it had work
+    // (a pause here delays every request in flight)
+    const int64_t t_now = now_ns();
+    if (t_now - t_prev > max_gap_ns) max_gap_ns = t_now - t_prev;
+    t_prev = t_now;
     bool progress = false;
     for (Slot &sl : slots) progress |= complete(this, sl);
     for (Slot &sl : slots)
@@ -161,6 +186,7 @@ void pll_server::run() {
       if (pending.empty()) {
         if (stopping.load()) return;
         cv.wait_for(lk, std::chrono::microseconds(200));
+        t_prev = now_ns();  // an idle wait is not a pause
       }
     } else if (!progress) {
       std::this_thread::yield();
@@ -209,6 +235,13 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
               hipMalloc((void **)&sl.dp, (size_t)slot_pairs * 2 * sizeof(int32_t)) ==
                   hipSuccess &&
               hipMalloc((void **)&sl.dout, (size_t)slot_pairs * sv->es) == hipSuccess;
+    // one copy and one kernel per slot stream now, so that the runtime sets
+    // up the stream's hardware queue here and not on the first request (a
+    // first dispatch on a new stream was measured to stall the worker for
+    // up to 9 ms)
+    ok = ok && hipMemcpyAsync(sl.dp, sl.hp, sizeof(int32_t), hipMemcpyHostToDevice, sl.s) ==
+                   hipSuccess &&
+         launch_zero_flag(sl.dp, sl.s) == hipSuccess && hipStreamSynchronize(sl.s) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       sv->release();
@@ -227,10 +260,11 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
   return PLL_OK;
 }
 
-// Internal: submit with an explicit arrival time (ns, steady clock).
+// Internal: submit with an explicit arrival time (ns, steady clock).  A
+// request larger than a slot is queued as consecutive slot-sized parts.
 static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
                      int64_t t_arrive, int64_t *ticket) {
-  if (!sv || q < 1 || q > sv->slot_pairs || !pairs || !out) return PLL_E_INVAL;
+  if (!sv || q < 1 || !pairs || !out) return PLL_E_INVAL;
   for (int64_t i = 0; i < 2 * q; i++)
     if (pairs[i] < 0 || pairs[i] >= sv->n) return PLL_E_INVAL;
   std::lock_guard<std::mutex> lk(sv->mu);
@@ -240,7 +274,21 @@ static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
   r.out = out;
   r.q = q;
   r.t_arrive = t_arrive;
-  sv->pending.push_back(&r);
+  if (q <= sv->slot_pairs) {
+    sv->pending.push_back(&r);
+  } else {
+    r.parts_left = (q + sv->slot_pairs - 1) / sv->slot_pairs;
+    for (int64_t o = 0; o < q; o += sv->slot_pairs) {
+      sv->parts.emplace_back();
+      Req &p = sv->parts.back();
+      p.pairs = pairs + 2 * o;
+      p.out = static_cast<uint8_t *>(out) + o * sv->es;
+      p.q = std::min<int64_t>(sv->slot_pairs, q - o);
+      p.t_arrive = t_arrive;
+      p.parent = &r;
+      sv->pending.push_back(&p);
+    }
+  }
   sv->max_pending = std::max<int64_t>(sv->max_pending, (int64_t)sv->pending.size());
   if (ticket) *ticket = (int64_t)sv->reqs.size() - 1;
   sv->cv.notify_one();
@@ -284,8 +332,9 @@ int pll_server_stop(pll_server *sv, int64_t *stats, int32_t nstats) {
   sv->cv.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   const int rc = sv->err.load();
-  const int64_t st[3] = {sv->launches, sv->batched_pairs, sv->max_pending};
-  for (int32_t i = 0; stats && i < nstats && i < 3; i++) stats[i] = st[i];
+  const int64_t st[6] = {sv->launches,      sv->batched_pairs, sv->max_pending,
+                         sv->max_launch_ns, sv->max_launch_at, sv->max_gap_ns};
+  for (int32_t i = 0; stats && i < nstats && i < 6; i++) stats[i] = st[i];
   sv->release();
   delete sv;
   return rc;
@@ -297,7 +346,8 @@ int pll_server_stop(pll_server *sv, int64_t *stats, int32_t nstats) {
 // measures the saturated throughput).  Randomness: SplitMix64 from `seed`.
 // Latency = answer time - scheduled arrival (queueing counts).
 // stats: [p50 us, p99 us, mean us, pairs/s, requests/s, seconds, launches,
-//         mean pairs per launch, max queued requests]
+//         mean pairs per launch, max queued requests, longest launch us,
+//         its launch number, the longest pause of the worker us]
 int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max_batch,
                     uint64_t seed, int32_t nslots, int64_t slot_pairs, double *stats,
                     int32_t nstats) {
@@ -350,8 +400,8 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
     lat[k] = us;
     t_last = std::max<int64_t>(t_last, sv->reqs[(size_t)k].t_done.load());
   }
-  int64_t sst[3] = {0, 0, 0};
-  const int rc2 = pll_server_stop(sv, sst, 3);
+  int64_t sst[6] = {0, 0, 0, 0, -1, -1};
+  const int rc2 = pll_server_stop(sv, sst, 6);
   if (rc != PLL_OK) return rc;
   if (rc2 != PLL_OK) return rc2;
   std::vector<double> sorted(lat);
@@ -366,10 +416,19 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
   for (double v : lat) mean += v;
   mean /= (double)nreq;
   const double secs = (double)(t_last - t0) * 1e-9;
-  const double st[9] = {pct(50), pct(99), mean, (double)off[nreq] / secs, (double)nreq / secs,
-                        secs, (double)sst[0], sst[0] ? (double)sst[1] / (double)sst[0] : 0.0,
-                        (double)sst[2]};
-  for (int32_t i = 0; stats && i < nstats && i < 9; i++) stats[i] = st[i];
+  const double st[12] = {pct(50),
+                         pct(99),
+                         mean,
+                         (double)off[nreq] / secs,
+                         (double)nreq / secs,
+                         secs,
+                         (double)sst[0],
+                         sst[0] ? (double)sst[1] / (double)sst[0] : 0.0,
+                         (double)sst[2],
+                         (double)sst[3] * 1e-3,
+                         (double)sst[4],
+                         (double)sst[5] * 1e-3};
+  for (int32_t i = 0; stats && i < nstats && i < 12; i++) stats[i] = st[i];
   return PLL_OK;
 }
 

@@ -48,6 +48,27 @@ def test_alone_vs_mix():
     assert min(lat) > 0
 
 
+def test_request_larger_than_a_slot():
+    # a request of more pairs than a slot holds is served in slot-sized
+    # parts; its answers equal the same pairs answered alone, also when
+    # other requests queue around it
+    import torch
+    assert torch.cuda.is_available()
+    g, order, t_bp, _ = gen.config_graph("ba2000")
+    gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    rng = np.random.Generator(np.random.PCG64(44))
+    big = rng.integers(0, g.n, (10_000, 2)).astype(np.int32)
+    small = [rng.integers(0, g.n, (q, 2)).astype(np.int32) for q in (5, 700, 1024, 1)]
+    srv = binding.Server(gx, nslots=2, slot_pairs=1024)
+    tickets = [srv.submit(small[0]), srv.submit(big)] + [srv.submit(p) for p in small[1:]]
+    for t, p in zip(tickets, [small[0], big] + small[1:]):
+        ans, us = srv.result(t)
+        assert us > 0 and np.array_equal(ans, gx.query(p))
+    st = srv.stop()
+    assert st["pairs"] == len(big) + sum(len(p) for p in small)
+    assert st["launches"] >= 10  # the big request took at least 10 slot loads
+
+
 def test_serve_bench_runs():
     import torch
     assert torch.cuda.is_available()
@@ -55,6 +76,9 @@ def test_serve_bench_runs():
     gx = binding.build(g.row_ptr, g.col, order, t_bp)
     sat = binding.serve_bench(gx, 0.0, 3000, max_batch=4096, seed=7)
     assert sat["pairs_per_s"] > 0 and sat["launches"] >= 1
+    # the longest launch (its number and time) and the worker's longest pause
+    assert 0 <= sat["max_launch_at"] < sat["launches"] and sat["max_launch_us"] > 0
+    assert sat["max_worker_pause_us"] >= 0
     low = binding.serve_bench(gx, sat["requests_per_s"] * 0.25, 3000, max_batch=4096, seed=8)
     assert low["p50_us"] > 0 and low["p99_us"] >= low["p50_us"]
 
