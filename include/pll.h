@@ -231,13 +231,13 @@ int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, ui
  * Autotuner of the pruned phase's frontier tiles: times whole builds of
  * this graph (arguments as pll_build, which it calls; PLL_PLAIN and
  * PLL_PARENTS are PLL_E_INVAL) while it varies one knob at a time from the
- * current settings -- "xgroup" (lanes per candidate expansion: 8, 16, 32),
+ * current settings, in two passes over the knobs -- "xgroup" (lanes per candidate expansion: 8, 16, 32),
  * "chunk" (edges expanded inline: 128, 256, 512), "window_work" (visits
  * per window: 64M, 128M, 256M) and "sort_level" (level size from which the
  * prune tests are grouped by root: 2^18, 2^20, 2^22) -- keeps each knob at
  * its fastest value (the lanes per prune test are chosen per window by the
  * build itself) and writes the four values to best[4] (may be NULL).  The
- * labels do not depend on these knobs.  Cost: up to 12 builds.  Errors: as
+ * labels do not depend on these knobs.  Cost: up to 24 builds.  Errors: as
  * pll_build; on an error the knob being tried is restored.
  */
 int pll_autotune_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
@@ -491,12 +491,16 @@ const char *pll_strerror(int code);
  *   answers as uint32 (PLL_WINF = unreachable); PLL_E_UNSUPPORTED on a
  *   server of an unweighted index.
  * pll_server_done: 1 if the request is answered (optionally waiting), 0 if
- *   not yet; *latency_us = answer time - submission time.
+ *   not yet; *latency_us = answer time - submission time.  Once it has
+ *   returned 1 the request's record is recycled and the ticket is no longer
+ *   valid (PLL_E_INVAL), so a ticket is waited for by one thread; the
+ *   server's host memory stays bounded by the requests in flight.
  * pll_server_stop: answer everything queued, stop the worker, free the
- *   server.  stats (optional, up to 6): launches, pairs launched, max queue
+ *   server.  stats (optional, up to 7): launches, pairs launched, max queue
  *   length, the longest launch in ns (from its dispatch to the worker seeing
- *   its completion event), its number among the launches, and the longest
- *   pause in ns between two passes of the worker while it had work.
+ *   its completion event), its number among the launches, the longest
+ *   pause in ns between two passes of the worker while it had work, and the
+ *   request records ever allocated (records are recycled).
  * pll_serve_bench: open-loop load test in native code: nreq requests of
  *   log-uniform size in [1, max_batch] with uniform random pairs, Poisson
  *   arrivals at `rate` requests/s (rate <= 0: all at once = saturation),

@@ -669,14 +669,17 @@ class Server:
             raise PllError(r, "server_done")
         if r == 0:
             return None, None
-        return self._keep[ticket][1], lat.value
+        # answered: the library recycles the request's record, and the
+        # arrays are no longer needed here
+        return self._keep.pop(ticket)[1], lat.value
 
     def stop(self) -> dict:
-        st = np.zeros(3, np.int64)
+        st = np.zeros(7, np.int64)
         h, self._h = self._h, None
         if h is not None:
-            _check(_lib().pll_server_stop(h, _ptr(st), 3), "server_stop")
-        return {"launches": int(st[0]), "pairs": int(st[1]), "max_queue": int(st[2])}
+            _check(_lib().pll_server_stop(h, _ptr(st), 7), "server_stop")
+        return {"launches": int(st[0]), "pairs": int(st[1]), "max_queue": int(st[2]),
+                "records": int(st[6])}
 
     def __del__(self):
         try:

@@ -2236,8 +2236,9 @@ int pll_autotune_query(const pll_index *idx, const int32_t *pairs, int64_t q, ui
 int pll_autotune_build(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *order,
                        int32_t t_bp, uint32_t flags, void *stream, int64_t *best) {
   if (flags & (PLL_PLAIN | PLL_PARENTS)) return PLL_E_INVAL;
-  // coordinate descent, one knob at a time from the current settings; every
-  // candidate is one whole build (the labels never depend on the knobs)
+  // coordinate descent, one knob at a time from the current settings, two
+  // passes over the knobs; every candidate is one whole build (the labels
+  // never depend on the knobs)
   struct Knob {
     const char *name;
     std::vector<int64_t> cands;
@@ -2249,6 +2250,8 @@ int pll_autotune_build(int32_t n, const int32_t *row_ptr, const int32_t *col, co
       {"sort_level", {1 << 18, 1 << 20, 1 << 22}},
   };
   std::map<std::string, int64_t> chosen;
+  // two passes: a knob's best value can move once the others have moved
+  for (int pass = 0; pass < 2; pass++)
   for (const Knob &k : knobs) {
     const int64_t start = pll_get_tuning(k.name);
     int64_t pick = start;

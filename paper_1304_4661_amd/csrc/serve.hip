@@ -47,8 +47,14 @@ int64_t now_ns() {
 }
 
 // A request, or one slot-sized part of a request larger than a slot (then
-// `parent` is the request; it is answered when its last part is).
+// `parent` is the request; it is answered when its last part is).  Records
+// are recycled: a request's record is freed once pll_server_done has
+// reported it answered, a part's once its answers are copied out; a ticket
+// carries the record's index and its generation, so a stale ticket is
+// rejected.
 struct Req {
+  int64_t idx = 0;   // position in the server's records
+  uint32_t gen = 0;  // bumped each time the record is freed
   const int32_t *pairs = nullptr;
   void *out = nullptr;  // es bytes per answer (the server's answer size)
   int64_t q = 0;
@@ -86,12 +92,30 @@ struct pll_server {
   std::vector<Slot> slots;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Req> reqs;          // owned requests; ticket = position
-  std::deque<Req> parts;         // owned parts of requests larger than a slot
+  std::deque<Req> recs;          // request and part records (addresses stay put)
+  std::vector<int64_t> free_recs;  // indices of free records
   std::deque<Req *> pending;     // FIFO of submitted, not yet dispatched
   std::atomic<bool> stopping{false};
   std::atomic<int> err{0};
   std::thread worker;
+  Req *take() {  // a free record (the caller holds mu)
+    if (free_recs.empty()) {
+      recs.emplace_back();
+      recs.back().idx = (int64_t)recs.size() - 1;
+      return &recs.back();
+    }
+    Req *r = &recs[(size_t)free_recs.back()];
+    free_recs.pop_back();
+    return r;
+  }
+  void give_back(Req *r) {  // the caller holds mu
+    r->gen++;
+    r->pairs = nullptr;
+    r->out = nullptr;
+    r->parent = nullptr;
+    r->t_done.store(0, std::memory_order_relaxed);
+    free_recs.push_back(r->idx);
+  }
   // statistics; the longest launch is timed from its dispatch to the host
   // seeing its event
   int64_t launches = 0, batched_pairs = 0, max_pending = 0, max_launch_ns = 0,
@@ -152,13 +176,22 @@ bool complete(pll_server *sv, Slot &sl) {
     sv->max_launch_at = sl.launch;
   }
   int64_t off = 0;
+  bool parts = false;
   for (Req *r : sl.reqs) {
     std::copy(sl.ho + off * sv->es, sl.ho + (off + r->q) * sv->es, static_cast<uint8_t *>(r->out));
     off += r->q;
-    if (!r->parent)
+    if (!r->parent) {
       r->t_done.store(t, std::memory_order_release);
-    else if (r->parent->parts_left.fetch_sub(1) == 1)  // its last part
-      r->parent->t_done.store(t, std::memory_order_release);
+    } else {
+      parts = true;
+      if (r->parent->parts_left.fetch_sub(1) == 1)  // its last part
+        r->parent->t_done.store(t, std::memory_order_release);
+    }
+  }
+  if (parts) {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (Req *r : sl.reqs)
+      if (r->parent) sv->give_back(r);
   }
   sl.reqs.clear();
   sl.busy = false;
@@ -268,8 +301,7 @@ static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
   for (int64_t i = 0; i < 2 * q; i++)
     if (pairs[i] < 0 || pairs[i] >= sv->n) return PLL_E_INVAL;
   std::lock_guard<std::mutex> lk(sv->mu);
-  sv->reqs.emplace_back();
-  Req &r = sv->reqs.back();
+  Req &r = *sv->take();
   r.pairs = pairs;
   r.out = out;
   r.q = q;
@@ -279,8 +311,7 @@ static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
   } else {
     r.parts_left = (q + sv->slot_pairs - 1) / sv->slot_pairs;
     for (int64_t o = 0; o < q; o += sv->slot_pairs) {
-      sv->parts.emplace_back();
-      Req &p = sv->parts.back();
+      Req &p = *sv->take();
       p.pairs = pairs + 2 * o;
       p.out = static_cast<uint8_t *>(out) + o * sv->es;
       p.q = std::min<int64_t>(sv->slot_pairs, q - o);
@@ -290,7 +321,7 @@ static int submit_at(pll_server *sv, const int32_t *pairs, int64_t q, void *out,
     }
   }
   sv->max_pending = std::max<int64_t>(sv->max_pending, (int64_t)sv->pending.size());
-  if (ticket) *ticket = (int64_t)sv->reqs.size() - 1;
+  if (ticket) *ticket = (int64_t)r.gen << 32 | r.idx;
   sv->cv.notify_one();
   return PLL_OK;
 }
@@ -309,11 +340,14 @@ int pll_server_submit_weighted(pll_server *sv, const int32_t *pairs, int64_t q, 
 
 int pll_server_done(pll_server *sv, int64_t ticket, int32_t wait, double *latency_us) {
   if (!sv) return PLL_E_INVAL;
+  const int64_t i = ticket & 0xFFFFFFFFll;
+  const uint32_t gen = (uint32_t)((uint64_t)ticket >> 32);
   Req *r;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (ticket < 0 || ticket >= (int64_t)sv->reqs.size()) return PLL_E_INVAL;
-    r = &sv->reqs[(size_t)ticket];
+    if (ticket < 0 || i >= (int64_t)sv->recs.size()) return PLL_E_INVAL;
+    r = &sv->recs[(size_t)i];
+    if (r->gen != gen || r->parent || !r->out) return PLL_E_INVAL;  // stale or not a request
   }
   int64_t t = r->t_done.load(std::memory_order_acquire);
   while (wait && !t) {
@@ -322,8 +356,11 @@ int pll_server_done(pll_server *sv, int64_t ticket, int32_t wait, double *latenc
     t = r->t_done.load(std::memory_order_acquire);
   }
   if (sv->err.load()) return sv->err.load();
-  if (t && latency_us) *latency_us = (double)(t - r->t_arrive) * 1e-3;
-  return t ? 1 : 0;
+  if (!t) return 0;
+  if (latency_us) *latency_us = (double)(t - r->t_arrive) * 1e-3;
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (r->gen == gen) sv->give_back(r);  // answered and reported: the record is free
+  return 1;
 }
 
 int pll_server_stop(pll_server *sv, int64_t *stats, int32_t nstats) {
@@ -332,9 +369,10 @@ int pll_server_stop(pll_server *sv, int64_t *stats, int32_t nstats) {
   sv->cv.notify_all();
   if (sv->worker.joinable()) sv->worker.join();
   const int rc = sv->err.load();
-  const int64_t st[6] = {sv->launches,      sv->batched_pairs, sv->max_pending,
-                         sv->max_launch_ns, sv->max_launch_at, sv->max_gap_ns};
-  for (int32_t i = 0; stats && i < nstats && i < 6; i++) stats[i] = st[i];
+  const int64_t st[7] = {sv->launches,      sv->batched_pairs, sv->max_pending,
+                         sv->max_launch_ns, sv->max_launch_at, sv->max_gap_ns,
+                         (int64_t)sv->recs.size()};
+  for (int32_t i = 0; stats && i < nstats && i < 7; i++) stats[i] = st[i];
   sv->release();
   delete sv;
   return rc;
@@ -380,25 +418,27 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
   int rc = pll_server_start(idx, nslots, slot_pairs, &sv);
   if (rc != PLL_OK) return rc;
   const int64_t t0 = now_ns() + 1000000;  // start 1 ms from now
+  std::vector<int64_t> tickets((size_t)nreq, -1);
   for (int64_t k = 0; k < nreq; k++) {
     const int64_t due = t0 + (int64_t)(at[k] * 1e9);
     while (now_ns() < due) {
     }
     rc = submit_at(sv, pairs.data() + 2 * off[k], size[k], outb.data() + off[k] * sv->es, due,
-                   nullptr);
+                   &tickets[(size_t)k]);
     if (rc != PLL_OK) break;
   }
   std::vector<double> lat((size_t)nreq);
   int64_t t_last = t0;
   for (int64_t k = 0; rc == PLL_OK && k < nreq; k++) {
     double us = 0;
-    const int r = pll_server_done(sv, k, 1, &us);
+    const int r = pll_server_done(sv, tickets[(size_t)k], 1, &us);
     if (r < 0) {
       rc = r;
       break;
     }
     lat[k] = us;
-    t_last = std::max<int64_t>(t_last, sv->reqs[(size_t)k].t_done.load());
+    // answered at its scheduled arrival + its latency
+    t_last = std::max<int64_t>(t_last, t0 + (int64_t)(at[k] * 1e9) + (int64_t)(us * 1e3));
   }
   int64_t sst[6] = {0, 0, 0, 0, -1, -1};
   const int rc2 = pll_server_stop(sv, sst, 6);

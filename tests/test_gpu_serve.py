@@ -69,6 +69,28 @@ def test_request_larger_than_a_slot():
     assert st["launches"] >= 10  # the big request took at least 10 slot loads
 
 
+def test_request_records_are_recycled():
+    # a server keeps no record of answered requests: 3000 requests in turn
+    # use a handful of records, and an answered ticket is no longer valid
+    import torch
+    assert torch.cuda.is_available()
+    g, order, t_bp, _ = gen.config_graph("ba2000")
+    gx = binding.build(g.row_ptr, g.col, order, t_bp)
+    rng = np.random.Generator(np.random.PCG64(45))
+    srv = binding.Server(gx, nslots=2, slot_pairs=256)
+    last = None
+    for k in range(3000):
+        p = rng.integers(0, g.n, (1 + k % 600, 2)).astype(np.int32)  # some split in parts
+        t = srv.submit(p)
+        ans, _ = srv.result(t)
+        assert np.array_equal(ans, gx.query(p))
+        last = t
+    with pytest.raises(binding.PllError):
+        srv.result(last)
+    st = srv.stop()
+    assert st["records"] <= 8, st
+
+
 def test_serve_bench_runs():
     import torch
     assert torch.cuda.is_available()
