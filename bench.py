@@ -585,6 +585,29 @@ def main():
         other[0]: other[1],
     }
 
+    if batch:
+        # the small graphs built whole in one persistent launch (one
+        # workgroup per graph) against the same batch with every graph in
+        # the shared windows (whole_n = 0), one build each after the steps
+        old_whole = binding.get_tuning("whole_n")
+        wt = {}
+        for lim in (old_whole, 0):
+            binding.set_tuning("whole_n", lim)
+            build().close()
+            t1 = time.perf_counter()
+            bx = build()
+            wt[lim] = (time.perf_counter() - t1, bx.stats())
+            bx.close()
+        binding.set_tuning("whole_n", old_whole)
+        sw = wt[old_whole][1]
+        out["whole_graph_launch"] = {
+            "whole_n": old_whole, "graphs": sw["whole_graphs"],
+            "vertices": int(sum(x.n for x in gs if 1 <= x.n <= old_whole)),
+            "launch_s": sw["whole_ns"] * 1e-9, "build_s": wt[old_whole][0],
+            "windows": sw["windows"], "build_s_all_windowed": wt[0][0],
+            "windows_all_windowed": wt[0][1]["windows"]}
+        print(f"whole-graph launch {out['whole_graph_launch']}", file=sys.stderr, flush=True)
+
     # the batched query kernel: bytes every pair must move (see
     # query_pair_bytes) over the step's query launches (events on the stream)
     lens_s = lens_t = None

@@ -141,10 +141,16 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
  *            within graph g) of graph g's vertex of local rank i
  *   t_bp, flags, stream, out: as pll_build (PLL_DEVICE_PTRS applies to
  *            row_ptr, col and order; vtx_off is always host memory)
- * All graphs share the launches: their roots are interleaved by local rank
- * into one build over the disjoint union, which yields every graph's own
- * labels.  Export and statistics take the graph index; pll_stats reports
- * the whole batch.
+ * Graphs of 1 .. "whole_n" vertices (a tuning knob, at most 16384; 0 turns
+ * this off) are built whole, one workgroup per graph, in one persistent
+ * launch: each workgroup takes graphs from a shared cursor, largest first,
+ * and runs the graph's pruned BFSs root after root with the root's label
+ * table, visited bits and BFS queue in LDS (Section 4.2's loop, Section
+ * 4.5.1's T array).  The other graphs share the windowed launches: their
+ * roots are interleaved by local rank into one build over their disjoint
+ * union.  Either way every graph gets its own labels.  Export and
+ * statistics take the graph index; pll_stats reports the whole batch.
+ * Not used by a directed batch or under PLL_PLAIN.
  * Errors: as pll_build, plus PLL_E_INVAL for a bad vtx_off, an edge leaving
  * its graph, or an order entry outside its graph.
  */
@@ -445,6 +451,10 @@ enum {
   PLL_STAT_EXPAND_DIRECT,  /* PLL_STAT_BP_DIRECT's share of that kernel */
   PLL_STAT_EXPAND_EARLIER, /* PLL_STAT_EARLIER_ROOT's share of that kernel */
   PLL_STAT_EXPAND_CLAIMS,  /* neighbours that kernel claimed for the next level */
+  PLL_STAT_WHOLE_GRAPHS,   /* graphs of a batch whose pruned phase ran whole in
+                              one workgroup (see pll_build_batch) */
+  PLL_STAT_WHOLE_NS,       /* wall time of that launch, ns (with any re-run
+                              after the label pool ran out) */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
@@ -551,7 +561,11 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * after the first at the maximum), and "window", "window_mem_mb", "list_cap",
  * "table_cap", "levels_per_sync" (steps between host checks) and "profile"
  * as above.  Bit-parallel phase: "bp_chunk" (adjacency entries per
- * work item).  "landmarks" (0/1: builds without bit-parallel labels --
+ * work item).  Batches: "whole_n" (graphs of up to this many vertices,
+ * 0..16384, default 16384, are built one workgroup per graph; 0 never) and
+ * "whole_pool" (label pool entries first reserved per vertex of those
+ * graphs, default 256; the launch is redone with twice the pool if it runs
+ * out; same labels).  "landmarks" (0/1: builds without bit-parallel labels --
  * t_bp = 0, directed, weighted -- keep exact distances from their first 16
  * roots and skip expansions those already prune; the labels do not
  * change).  "live_adjacency" (0/1: each time the window start s has

@@ -27,6 +27,7 @@ STAT_NAMES = [
     "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
     "bp_direct", "bp_sets", "bp_checks", "improved", "touched", "filtered", "land_checks",
     "earlier_root", "expand_ns", "expand_direct", "expand_earlier", "expand_claims",
+    "whole_graphs", "whole_ns",
 ]
 
 EXPORTED = [

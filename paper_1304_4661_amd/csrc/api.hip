@@ -43,6 +43,9 @@ struct Tuning {
   int root_sort = 2;  // prune tests grouped by root: 0 never, 1 always, 2 for large levels
   int64_t sort_level = 1 << 20;  // visits per level from which "root_sort" 2 groups by root
   int64_t sort_scan = 8 << 20;   // ... or label entries scanned per level
+  int64_t whole_n = kGMaxN;  // batch graphs of at most this many vertices are built
+                             // whole, one workgroup each (0: never)
+  int64_t whole_pool = 256;  // label pool entries reserved per vertex of those graphs
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -279,10 +282,15 @@ struct pll_index {
   int32_t n = 0, t = 0, tpad = 0;
   // graphs of a batch (one for pll_build): graph g owns ids
   // [vtx_off[g], vtx_off[g+1]); its vertex of local rank l has global rank
+  // grank(g, l): gblk[g] + l for a graph built whole by one workgroup (a
+  // block of consecutive ranks after the interleaved ones), else
   // lbase[l] + gpos[g]
   int32_t G = 1;
-  std::vector<int64_t> vtx_off, lbase, g_entries;
+  std::vector<int64_t> vtx_off, lbase, g_entries, gblk;
   std::vector<int32_t> gpos;
+  int64_t grank(int32_t g, int64_t l) const {
+    return gblk[g] >= 0 ? gblk[g] + l : lbase[l] + gpos[g];
+  }
   std::vector<int32_t> lrank_h;  // local rank of every global rank (host copy)
   std::vector<int64_t> hoff;     // host copy of off
   DBuf<int32_t> rgid;   // graph of every global rank (batches only)
@@ -415,22 +423,56 @@ int validate_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, co
 // graph's own order, so the union's labels are each graph's labels.  It also
 // puts every graph's early (heavy) roots in the same windows, where roots of
 // different graphs never interact.
-void interleave(int32_t G, const std::vector<int64_t> &vtx_off, std::vector<int32_t> &gpos,
-                std::vector<int64_t> &lbase) {
-  std::vector<int32_t> idx((size_t)G);
-  for (int32_t g = 0; g < G; g++) idx[g] = g;
+//
+// Graphs listed in `whole` (built by one workgroup each, largest first)
+// take no part in the interleaving: they get blocks of consecutive ranks
+// after it, in list order (gblk[g] = first rank, -1 for the others), which
+// keeps each graph's order just the same.  Returns the interleaved ranks'
+// count (the windows' range).
+int64_t interleave(int32_t G, const std::vector<int64_t> &vtx_off,
+                   const std::vector<int32_t> &whole, std::vector<int32_t> &gpos,
+                   std::vector<int64_t> &lbase, std::vector<int64_t> &gblk) {
   auto size = [&](int32_t g) { return vtx_off[g + 1] - vtx_off[g]; };
+  gblk.assign((size_t)G, -1);
+  for (int32_t g : whole) gblk[g] = 0;
+  std::vector<int32_t> idx;
+  for (int32_t g = 0; g < G; g++)
+    if (gblk[g] < 0) idx.push_back(g);
   std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) { return size(a) > size(b); });
   gpos.assign((size_t)G, 0);
-  for (int32_t i = 0; i < G; i++) gpos[idx[i]] = i;
-  const int64_t maxn = G ? size(idx[0]) : 0;
+  const int32_t K = (int32_t)idx.size();
+  for (int32_t i = 0; i < K; i++) gpos[idx[i]] = i;
+  const int64_t maxn = K ? size(idx[0]) : 0;
   lbase.assign((size_t)maxn + 1, 0);
   // graphs with size > l form the prefix idx[0 .. cnt) of the size order
-  int32_t cnt = G;
+  int32_t cnt = K;
   for (int64_t l = 0; l < maxn; l++) {
     while (cnt > 0 && size(idx[cnt - 1]) <= l) cnt--;
     lbase[l + 1] = lbase[l] + cnt;
   }
+  int64_t next = lbase[maxn];
+  for (int32_t g : whole) {
+    gblk[g] = next;
+    next += size(g);
+  }
+  return lbase[maxn];
+}
+
+// Graphs of a batch built whole by one workgroup each: those of 1 ..
+// min(limit, kGMaxN) vertices, largest first (ties by index).  None for a
+// single graph, a directed batch or the plain form.
+std::vector<int32_t> whole_graphs(int32_t G, const std::vector<int64_t> &vtx_off, int64_t limit) {
+  std::vector<int32_t> w;
+  if (G < 2) return w;
+  const int64_t lim = std::min<int64_t>(limit, kGMaxN);
+  for (int32_t g = 0; g < G; g++) {
+    const int64_t ng = vtx_off[g + 1] - vtx_off[g];
+    if (ng >= 1 && ng <= lim) w.push_back(g);
+  }
+  std::stable_sort(w.begin(), w.end(), [&](int32_t a, int32_t b) {
+    return vtx_off[a + 1] - vtx_off[a] > vtx_off[b + 1] - vtx_off[b];
+  });
+  return w;
 }
 
 // Reads a LevelCtl back to the host (synchronising the stream).
@@ -487,7 +529,7 @@ constexpr size_t kTraceCols = PLL_TRACE_COLS;
 struct Builder {
   hipStream_t st;
   Tuning tu;
-  bool plain;
+  bool plain = false;
   bool parents = false;  // keep the BFS-tree parent of every label entry
   int32_t n, t, nwords;
   int64_t nnz;
@@ -510,8 +552,12 @@ struct Builder {
   // (already validated) when `device` is set.
   int32_t G = 1;
   std::vector<int64_t> vtx_off;
-  DBuf<int64_t> d_vtx_off, d_lbase;
+  DBuf<int64_t> d_vtx_off, d_lbase, d_gblk;
   DBuf<int32_t> d_gpos;
+  // graphs built whole by one workgroup each (largest first) and the
+  // interleaved ranks' count: the windows run roots [0, nwin)
+  std::vector<int32_t> whole;
+  int64_t nwin = 0;
 
   void relabel(const int32_t *in_row_p, const int32_t *in_col_p, const int32_t *order_p,
                bool device, pll_index *ix, DBuf<int32_t> *gid_in) {
@@ -527,7 +573,8 @@ struct Builder {
       in_col_p = in_col.p;
       order_p = order.p;
     }
-    interleave(G, vtx_off, ix->gpos, ix->lbase);
+    if (!plain && !directed && tu.whole_n > 0) whole = whole_graphs(G, vtx_off, tu.whole_n);
+    nwin = interleave(G, vtx_off, whole, ix->gpos, ix->lbase, ix->gblk);
     ix->G = G;
     ix->vtx_off = vtx_off;
     if (!d_vtx_off.p) {
@@ -536,8 +583,10 @@ struct Builder {
     }
     d_lbase.alloc(ix->lbase.size());
     d_gpos.alloc((size_t)std::max(G, 1));
+    d_gblk.alloc((size_t)std::max(G, 1));
     h2d(d_lbase.p, ix->lbase.data(), ix->lbase.size(), st);
     h2d(d_gpos.p, ix->gpos.data(), (size_t)G, st);
+    h2d(d_gblk.p, ix->gblk.data(), (size_t)G, st);
     DBuf<int32_t> gid_own;
     DBuf<int32_t> *gid = gid_in;
     if (!gid || !gid->p) {
@@ -549,7 +598,8 @@ struct Builder {
     ix->lrank.alloc((size_t)n);
     ix->rgid.alloc((size_t)n);
     DBuf<int32_t> gorder((size_t)n);
-    check(launch_batch_rank(n, gid->p, d_vtx_off.p, order_p, d_lbase.p, d_gpos.p, ix->rank.p,
+    check(launch_batch_rank(n, gid->p, d_vtx_off.p, order_p, d_lbase.p, d_gpos.p, d_gblk.p,
+                            ix->rank.p,
                             gorder.p, ix->lrank.p, ix->rgid.p, st));
     DBuf<int64_t> deg((size_t)n), tmp((size_t)scan_tmp_elems(n));
     row.alloc((size_t)n + 1);
@@ -582,7 +632,8 @@ struct Builder {
     fill(used_bits, 0, st);
     fill(tmp_bits, 0, st);
     fill(sel, 0xFF, st);
-    check(launch_bp_select(graph(), G, t, d_vtx_off.p, d_lbase.p, d_gpos.p, ix->lrank.p,
+    check(launch_bp_select(graph(), G, t, d_vtx_off.p, d_lbase.p, d_gpos.p, d_gblk.p,
+                           ix->lrank.p,
                            used_bits.p, tmp_bits.p, used.p, root.p, nsel.p, sel.p, st));
     d2h(ix->bp_root.data(), root.p, nrec, st);
     d2h(ix->bp_nsel.data(), nsel.p, nrec, st);
@@ -766,6 +817,71 @@ struct Builder {
     D.mirror.p->top = 0;
   }
 
+  // The pruned phase of the graphs in `whole`, one workgroup per graph, in
+  // an empty store (before any window commits).  The pool is sized from
+  // whole_pool entries per vertex of those graphs; if it runs out the store
+  // is cleared and the launch redone with twice the pool.
+  int64_t stat_whole_ns = 0;
+  void whole_phase(Store &S, Side &D, const DBp &bp) {
+    const auto t0 = Clock::now();
+    const int32_t ng = (int32_t)whole.size();
+    std::vector<int64_t> hb((size_t)ng);
+    std::vector<int32_t> hn((size_t)ng);
+    int64_t verts = 0;
+    for (int32_t i = 0; i < ng; i++) {
+      const int32_t g = whole[i];
+      hb[i] = nwin + verts;
+      hn[i] = (int32_t)(vtx_off[g + 1] - vtx_off[g]);
+      verts += hn[i];
+    }
+    DBuf<int64_t> dbase((size_t)ng);
+    DBuf<int32_t> dn((size_t)ng);
+    DBuf<GraphCtl> ctl(1);
+    h2d(dbase.p, hb.data(), (size_t)ng, st);
+    h2d(dn.p, hn.data(), (size_t)ng, st);
+    int dev = 0, cus = 0;
+    check(hipGetDevice(&dev));
+    check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int32_t grid = std::max(1, std::min(ng, 2 * cus));
+    // whole_pool entries per vertex here, and the windows' first share (as
+    // store_init gives every vertex of a single graph)
+    int64_t want = verts * tu.whole_pool + 32 * nwin + 64;
+    for (;;) {
+      if (want != S.pool_cap) {  // nothing to keep: the windows have not run
+        S.hub.alloc((size_t)want);
+        S.dist.alloc((size_t)want);
+        S.pool_cap = want;
+      }
+      fill(ctl, 0, st);
+      check(launch_graph_pruned(graph(), bp, used.p, S.view(), dbase.p, dn.p, ng, ctl.p, grid,
+                                st));
+      GraphCtl h{};
+      unsigned long long top = 0;
+      d2h(&h, ctl.p, 1, st);
+      d2h(&top, S.top.p, 1, st);
+      check(hipStreamSynchronize(st));
+      if (h.flags & kFlagRange) throw Fail{PLL_E_RANGE};
+      if (h.flags & kFlagOvfPool) {
+        // start over: no labels, an empty pool twice as large
+        fill(S.off, 0, st);
+        fill(S.len, 0, st);
+        fill(S.cap, 0, st);
+        fill(S.top, 0, st);
+        want = 2 * S.pool_cap;
+        stat_retries++;
+        continue;
+      }
+      D.mirror.p->top = top;
+      stat_visited += (int64_t)h.visited;
+      stat_tests += (int64_t)h.tests;
+      stat_scanned += (int64_t)h.scanned;
+      stat_edges += (int64_t)h.edges;
+      stat_cand += (int64_t)h.labeled;
+      break;
+    }
+    stat_whole_ns = ns_since(t0);
+  }
+
   // One window's BFS levels in one direction, until every root's search has
   // ended or a list overflowed.  Returns the last level index.
   int side_levels(Side &D, const DBp &bp, const DBp &rb, const DBp &vb, const DWindow &w,
@@ -896,6 +1012,10 @@ struct Builder {
       }
     } ev_guard{evs};
 
+    // graphs built whole, one workgroup each, before the windows: their
+    // ranks follow the windows' range and no window root reaches them
+    if (!whole.empty()) whole_phase(stores[0], sides[0], bp);
+
     // Window size: fixed at wmax, or adapted so that each window does about
     // window_work visits (early roots have large pruned BFSs, late ones
     // tiny; one launch per level must still fill the device).
@@ -905,7 +1025,7 @@ struct Builder {
     // live adjacency: rebuilt without the neighbours ranked below s each
     // time s has doubled (the expansion skips them anyway)
     int32_t live_s = 0;
-    while (s < n) {
+    while (s < nwin) {
       if (!plain && tu.live_adjacency && tu.expand_prune && s >= 1024 && s >= 2 * live_s) {
         for (int k = 0; k < nsides; k++) {
           Side &D = sides[k];
@@ -918,7 +1038,7 @@ struct Builder {
         }
         live_s = s;
       }
-      const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, n);
+      const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + W, nwin);
       const int32_t nr = e - s;
       DWindow w[2];
       int last[2] = {0, 0};
@@ -1695,7 +1815,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
     for (int32_t g = 0; g < G; g++) {
       const int64_t ng = vtx_off[g + 1] - vtx_off[g];
       for (int64_t l = 0; l < ng; l++) {
-        const int64_t r = ix->lbase[l] + ix->gpos[g];
+        const int64_t r = ix->grank(g, l);
         ix->g_entries[g] += hoff[r + 1] - hoff[r] - 1;
       }
     }
@@ -1739,6 +1859,8 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   S[PLL_STAT_EXPAND_DIRECT] = b.stat_x_direct;
   S[PLL_STAT_EXPAND_EARLIER] = b.stat_x_earlier;
   S[PLL_STAT_EXPAND_CLAIMS] = b.stat_x_claims;
+  S[PLL_STAT_WHOLE_GRAPHS] = (int64_t)b.whole.size();
+  S[PLL_STAT_WHOLE_NS] = b.stat_whole_ns;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }
@@ -2363,14 +2485,13 @@ int pll_export_in(const pll_index *idx, int32_t graph, int64_t *entries, int64_t
   return guarded([&] {
     const int64_t g0 = idx->vtx_off[graph];
     const int64_t ng = idx->vtx_off[graph + 1] - g0;
-    const int32_t gp = idx->gpos[graph];
     hipStream_t st = nullptr;
     std::vector<int64_t> hio((size_t)idx->n + 1);
     if (idx->n) d2h(hio.data(), idx->ioff.p, (size_t)idx->n + 1, st);
     check(hipStreamSynchronize(st));
     std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
     for (int64_t l = 0; l < ng; l++) {
-      rows[l] = idx->lbase[l] + gp;
+      rows[l] = idx->grank(graph, l);
       oo[l + 1] = oo[l] + hio[rows[l] + 1] - 1 - hio[rows[l]];
     }
     const int64_t ne = oo[ng];
@@ -2397,11 +2518,10 @@ int pll_export_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
   return guarded([&] {
     const int64_t g0 = idx->vtx_off[graph];
     const int64_t ng = idx->vtx_off[graph + 1] - g0;
-    const int32_t gp = idx->gpos[graph];
     hipStream_t st = nullptr;
     std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
     for (int64_t l = 0; l < ng; l++) {
-      rows[l] = idx->lbase[l] + gp;
+      rows[l] = idx->grank(graph, l);
       oo[l + 1] = oo[l] + idx->hoff[rows[l] + 1] - 1 - idx->hoff[rows[l]];
     }
     const int64_t ne = oo[ng];
@@ -2425,14 +2545,13 @@ int pll_export_in_parents(const pll_index *idx, int32_t graph, uint32_t *par) {
   if (!idx->parents || !idx->directed || idx->weighted) return PLL_E_UNSUPPORTED;
   return guarded([&] {
     const int64_t ng = idx->vtx_off[graph + 1] - idx->vtx_off[graph];
-    const int32_t gp = idx->gpos[graph];
     hipStream_t st = nullptr;
     std::vector<int64_t> hio((size_t)idx->n + 1);
     if (idx->n) d2h(hio.data(), idx->ioff.p, (size_t)idx->n + 1, st);
     check(hipStreamSynchronize(st));
     std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
     for (int64_t l = 0; l < ng; l++) {
-      rows[l] = idx->lbase[l] + gp;
+      rows[l] = idx->grank(graph, l);
       oo[l + 1] = oo[l] + hio[rows[l] + 1] - 1 - hio[rows[l]];
     }
     const int64_t ne = oo[ng];
@@ -2459,12 +2578,11 @@ int pll_export(const pll_index *idx, int32_t graph, int64_t *off, uint32_t *hub,
     const int32_t t = idx->t, tp = idx->tpad;
     const int64_t g0 = idx->vtx_off[graph];
     const int64_t ng = idx->vtx_off[graph + 1] - g0;
-    const int32_t gp = idx->gpos[graph];
     hipStream_t st = nullptr;
     // the graph's rows (global ranks) in local rank order, and output offsets
     std::vector<int64_t> rows((size_t)ng), oo((size_t)ng + 1, 0);
     for (int64_t l = 0; l < ng; l++) {
-      rows[l] = idx->lbase[l] + gp;
+      rows[l] = idx->grank(graph, l);
       oo[l + 1] = oo[l] + idx->hoff[rows[l] + 1] - 1 - idx->hoff[rows[l]];
     }
     const int64_t ne = oo[ng];
@@ -2622,6 +2740,12 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "bp_chunk") {
     if (value < 1 || value > (1 << 20)) return PLL_E_INVAL;
     g_tune.bp_chunk = (int)value;
+  } else if (k == "whole_n") {
+    if (value < 0 || value > kGMaxN) return PLL_E_INVAL;
+    g_tune.whole_n = value;
+  } else if (k == "whole_pool") {
+    if (value < 1 || value > (1 << 20)) return PLL_E_INVAL;
+    g_tune.whole_pool = value;
   } else {
     return PLL_E_INVAL;
   }
@@ -2655,6 +2779,8 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "profile") return g_tune.profile;
   if (k == "bp_chunk") return g_tune.bp_chunk;
   if (k == "serve_coalesce") return g_tune.serve_coalesce;
+  if (k == "whole_n") return g_tune.whole_n;
+  if (k == "whole_pool") return g_tune.whole_pool;
   return PLL_E_INVAL;
 }
 

@@ -277,6 +277,21 @@ enum : int32_t {
   kFlagRange = 8,  // a vertex at distance 255 would be labeled (or reached, BP)
   kFlagOvfHash = 16,  // the root tables need more room than allocated
   kOverflowFlags = kFlagOvfFrontier | kFlagOvfHeavy | kFlagOvfCand | kFlagOvfHash,
+  kFlagOvfPool = 32,  // a whole-graph build ran out of label pool
+};
+
+// Whole small graphs of a batch, one workgroup per graph (graphs.hip): the
+// largest graph such a workgroup takes (its T array, visited bits and BFS
+// queue live in LDS), and the control block of one launch.
+constexpr int32_t kGMaxN = 16384;
+struct GraphCtl {
+  alignas(kCtrLine) int32_t cursor;  // next graph of the list
+  alignas(kCtrLine) int32_t flags;   // kFlagRange | kFlagOvfPool
+  alignas(kCtrLine) unsigned long long visited;  // (root, vertex) entries tested
+  unsigned long long tests;     // ... that reached the normal-label test
+  unsigned long long scanned;   // label entries read by those tests
+  unsigned long long labeled;   // entries added
+  unsigned long long edges;     // adjacency entries expanded
 };
 
 // Growing label store used during the build: label of rank r lives at
@@ -443,7 +458,8 @@ hipError_t launch_validate_graph(int32_t n, const int32_t *row, const int32_t *c
 hipError_t launch_fill_gid(const int64_t *vtx_off, int32_t G, int32_t *gid, hipStream_t st);
 hipError_t launch_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
                              const int32_t *order, const int64_t *lbase, const int32_t *gpos,
-                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid,
+                             const int64_t *gblk, int32_t *rank, int32_t *gorder,
+                             int32_t *lrank, int32_t *rgid,
                              hipStream_t st);
 hipError_t launch_iota_rank(const int32_t *order, int32_t *rank, int32_t n, hipStream_t st);
 hipError_t launch_degrees(const int32_t *in_row, const int32_t *order, int64_t *deg, int32_t n,
@@ -464,7 +480,8 @@ hipError_t launch_transpose(const int64_t *row, const int32_t *col, int32_t n, i
                             int32_t *icol, int64_t *work, int64_t *tmp, hipStream_t st,
                             const uint32_t *wt = nullptr, uint32_t *iwt = nullptr);
 hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
-                            const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
+                            const int64_t *lbase, const int32_t *gpos, const int64_t *gblk,
+                            const int32_t *lrank,
                             uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
                             int32_t *root, int32_t *nsel, int32_t *sel, hipStream_t st);
 // bit-parallel BFS: work items = (vertex, chunk of its adjacency list)
@@ -516,6 +533,16 @@ hipError_t launch_win_reset(DGraph g, DWindow w, DStore s, DFrontier f, int32_t 
 hipError_t launch_win_abort(DGraph g, DWindow w, int64_t ncand, hipStream_t st);
 hipError_t launch_win_clean(DWindow w, DWindow o, int64_t ncand, hipStream_t st);
 hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st);
+// Pruned phase of whole graphs: graph i of the list owns the global ranks
+// [gbase[i], gbase[i] + gn[i]), gn[i] <= kGMaxN, listed largest first; the
+// list's workgroups label them in s, which must hold no entries of them
+// yet.  ctl must be zeroed before the launch; afterwards its flags hold
+// kFlagRange (a vertex at distance 255 would be labeled) or kFlagOvfPool
+// (the pool is too small: the labels of the listed graphs are then
+// incomplete and must be cleared before a retry).
+hipError_t launch_graph_pruned(DGraph g, DBp bp, const uint8_t *used, DStore s,
+                               const int64_t *gbase, const int32_t *gn, int32_t ngraphs,
+                               GraphCtl *ctl, int32_t grid, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 // hdr of an empty store (z: the bit-parallel masks, or null for none)
 hipError_t launch_store_hdr(DStore s, const uint64_t *z, int32_t n, hipStream_t st);

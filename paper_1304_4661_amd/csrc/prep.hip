@@ -164,19 +164,27 @@ __global__ void k_fill_gid(const int64_t *vtx_off, int32_t *gid) {
   for (int64_t v = vtx_off[g] + threadIdx.x; v < vtx_off[g + 1]; v += blockDim.x) gid[v] = g;
 }
 
-// Ranks of a batch of independent graphs.  Graph g's vertex of local rank l
-// gets global rank lbase[l] + gpos[g] (graphs interleaved by local rank; see
-// the batch notes in api.hip).  Also the inverse order, the local rank of
-// every global rank and the graph of every global rank.
+// Global rank of graph g's vertex of local rank l: gblk[g] + l for a graph
+// given a block of consecutive ranks (gblk[g] >= 0), else lbase[l] + gpos[g]
+// (graphs interleaved by local rank; see the batch notes in api.hip).
+__device__ __forceinline__ int32_t batch_grank(const int64_t *lbase, const int32_t *gpos,
+                                               const int64_t *gblk, int32_t g, int64_t l) {
+  const int64_t b = gblk[g];
+  return (int32_t)(b >= 0 ? b + l : lbase[l] + gpos[g]);
+}
+
+// Ranks of a batch of independent graphs (batch_grank), the inverse order,
+// the local rank of every global rank and the graph of every global rank.
 __global__ void k_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
                              const int32_t *order, const int64_t *lbase, const int32_t *gpos,
-                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid) {
+                             const int64_t *gblk, int32_t *rank, int32_t *gorder,
+                             int32_t *lrank, int32_t *rgid) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t g = gid[p];
     const int64_t l = p - vtx_off[g];
     const int32_t v = (int32_t)(vtx_off[g] + order[p]);
-    const int32_t r = (int32_t)(lbase[l] + gpos[g]);
+    const int32_t r = batch_grank(lbase, gpos, gblk, g, l);
     rank[v] = r;
     gorder[r] = v;
     lrank[r] = (int32_t)l;
@@ -242,21 +250,21 @@ __global__ void __launch_bounds__(kSelThreads) k_bp_select(DGraph g, int32_t t,
                                                            const int64_t *vtx_off,
                                                            const int64_t *lbase,
                                                            const int32_t *gpos,
+                                                           const int64_t *gblk,
                                                            const int32_t *lrank,
                                                            uint32_t *used_bits,
                                                            uint32_t *tmp_bits,
                                                            uint8_t *used_bytes, int32_t *root,
                                                            int32_t *nsel, int32_t *sel) {
   // block gi handles graph gi; its vertex of local rank l has global rank
-  // lbase[l] + gpos[gi]; temporary bits are kept per local rank at
+  // batch_grank(.., gi, l); temporary bits are kept per local rank at
   // vtx_off[gi] + l (boundary words are shared with the next graph, hence
   // atomics for setting and clearing)
   const int tid = threadIdx.x;
   const int32_t gi = blockIdx.x;
   const int64_t g0 = vtx_off[gi];
   const int32_t ng = (int32_t)(vtx_off[gi + 1] - g0);
-  const int32_t gp = gpos[gi];
-  auto grank = [&](int32_t l) { return (int32_t)(lbase[l] + gp); };
+  auto grank = [&](int32_t l) { return batch_grank(lbase, gpos, gblk, gi, l); };
   int32_t cursor = 0;  // every local rank below cursor is used
   for (int32_t i = 0; i < t; i++) {
     const int64_t si = (int64_t)gi * t + i;
@@ -421,13 +429,13 @@ hipError_t launch_fill_gid(const int64_t *vtx_off, int32_t G, int32_t *gid, hipS
 
 hipError_t launch_batch_rank(int32_t N, const int32_t *gid, const int64_t *vtx_off,
                              const int32_t *order, const int64_t *lbase, const int32_t *gpos,
-                             int32_t *rank, int32_t *gorder, int32_t *lrank, int32_t *rgid,
-                             hipStream_t st) {
+                             const int64_t *gblk, int32_t *rank, int32_t *gorder,
+                             int32_t *lrank, int32_t *rgid, hipStream_t st) {
   if (N == 0) return hipSuccess;
   int64_t blocks = ((int64_t)N + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_batch_rank, dim3((unsigned)blocks), dim3(256), 0, st, N, gid, vtx_off,
-                     order, lbase, gpos, rank, gorder, lrank, rgid);
+                     order, lbase, gpos, gblk, rank, gorder, lrank, rgid);
   return hipGetLastError();
 }
 
@@ -475,12 +483,13 @@ hipError_t launch_relabel_cols(const int32_t *in_row, const int32_t *in_col, con
 }
 
 hipError_t launch_bp_select(DGraph g, int32_t G, int32_t t, const int64_t *vtx_off,
-                            const int64_t *lbase, const int32_t *gpos, const int32_t *lrank,
-                            uint32_t *used_bits, uint32_t *tmp_bits, uint8_t *used_bytes,
-                            int32_t *root, int32_t *nsel, int32_t *sel, hipStream_t st) {
+                            const int64_t *lbase, const int32_t *gpos, const int64_t *gblk,
+                            const int32_t *lrank, uint32_t *used_bits, uint32_t *tmp_bits,
+                            uint8_t *used_bytes, int32_t *root, int32_t *nsel, int32_t *sel,
+                            hipStream_t st) {
   if (t == 0 || G == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bp_select, dim3(G), dim3(kSelThreads), 0, st, g, t, vtx_off, lbase, gpos,
-                     lrank, used_bits, tmp_bits, used_bytes, root, nsel, sel);
+                     gblk, lrank, used_bits, tmp_bits, used_bytes, root, nsel, sel);
   return hipGetLastError();
 }
 

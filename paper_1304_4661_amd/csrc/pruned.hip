@@ -370,17 +370,32 @@ __device__ __forceinline__ bool label_prunes(const DStore &st, RootTable Tj, ulo
 constexpr int kLdsSlots = 4096;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
 
-// distance of hub h in the LDS table, 255 if absent (stored distances are at
-// most 254)
-__device__ __forceinline__ int lds_lookup(const uint4 *tab, uint32_t bmask, uint32_t h) {
-  uint32_t b = ht_hash(h) & bmask;
+// Bucket of hub h in the LDS table.  Hub ranks there are below 2^24 - 1, so
+// a 24-bit multiply (a full-rate instruction, unlike the 32-bit one) mixes
+// them; the table is small (at most 1024 buckets), and the shift brings the
+// product's well-mixed middle bits down.
+__device__ __forceinline__ uint32_t lds_hash(uint32_t h) {
+  const uint32_t x = __umul24(h, 0x9E3779u);
+  return x ^ (x >> 13);
+}
+
+// Distance of hub h in one bucket q, or 255: a slot holds h << 8 | dist, so
+// slot ^ (h << 8) is the distance exactly when the hubs match and at least
+// 256 otherwise (an empty slot included, hub ranks being below 2^24 - 1).
+__device__ __forceinline__ int lds_bucket_dist(const uint4 q, uint32_t hk) {
+  const uint32_t a = min(min(q.x ^ hk, q.y ^ hk), q.z ^ hk);
+  return (int)min(min(a, q.w ^ hk), 255u);
+}
+
+// distance of hub h in the LDS table from bucket b on, 255 if absent
+// (stored distances are at most 254): a bucket with a free slot ends the
+// probe
+__device__ __forceinline__ int lds_lookup_from(const uint4 *tab, uint32_t bmask, uint32_t h,
+                                               uint32_t b) {
+  const uint32_t hk = h << 8;
   for (;;) {
     const uint4 q = tab[b];
-    int dist = kInf8;
-    dist = (q.x >> 8) == h ? (int)(q.x & 0xFFu) : dist;
-    dist = (q.y >> 8) == h ? (int)(q.y & 0xFFu) : dist;
-    dist = (q.z >> 8) == h ? (int)(q.z & 0xFFu) : dist;
-    dist = (q.w >> 8) == h ? (int)(q.w & 0xFFu) : dist;
+    const int dist = lds_bucket_dist(q, hk);
     if (dist != kInf8 || q.w == kEmpty32) return dist;
     b = (b + 1) & bmask;
   }
@@ -393,7 +408,9 @@ __device__ __forceinline__ int lds_lookup(const uint4 *tab, uint32_t bmask, uint
 // 16, so a lane reads 4 consecutive entries at once -- 16 bytes of hubs and
 // 4 bytes of distances, both issued before any probe -- and a quad that
 // runs past the label's end stays inside its slot (those entries are
-// masked out).
+// masked out).  The four first buckets are read together; a hub absent
+// from a full bucket (rare: one entry per bucket on average) continues into
+// the next buckets.
 template <int G>
 __device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint4 *tab,
                                                  uint32_t bmask, int64_t o, int32_t len, int d) {
@@ -411,11 +428,20 @@ __device__ __forceinline__ bool label_prunes_lds(const DStore &st, const uint4 *
     const uint32_t dn = qn < nq ? dq[qn] : 0u;
     const int32_t e0 = (q0 + gr) * 4;
     const uint32_t hv[4] = {h.x, h.y, h.z, h.w};
+    uint32_t b[4];
+    uint4 q[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) b[i] = lds_hash(hv[i]) & bmask;
+#pragma unroll
+    for (int i = 0; i < 4; i++) q[i] = tab[b[i]];
     bool hit = false;
 #pragma unroll
     for (int i = 0; i < 4; i++) {
       if (e0 + i >= len) continue;
-      hit |= (int)((dd >> (8 * i)) & 0xFFu) + lds_lookup(tab, bmask, hv[i]) <= d;
+      int dist = lds_bucket_dist(q[i], hv[i] << 8);
+      if (dist == kInf8 && q[i].w != kEmpty32)
+        dist = lds_lookup_from(tab, bmask, hv[i], (b[i] + 1) & bmask);
+      hit |= (int)((dd >> (8 * i)) & 0xFFu) + dist <= d;
     }
     if (Group<G>::any(hit)) return true;
     h = hn;
@@ -788,7 +814,7 @@ __global__ void __launch_bounds__(kTBlock, 5) k_win_test(DGraph g, DBp bp, DStor
         const uint32_t ent = (h << 8) | (uint32_t)rst.dist[ko + e];
         uint32_t *slots = reinterpret_cast<uint32_t *>(s_ht);
         // first free slot of the bucket, else of the next one
-        for (uint32_t b = ht_hash(h) & bmask, q = 0;; q++) {
+        for (uint32_t b = lds_hash(h) & bmask, q = 0;; q++) {
           if (q == 4) {
             q = 0;
             b = (b + 1) & bmask;

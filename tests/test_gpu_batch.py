@@ -66,11 +66,73 @@ def test_batch_of_families():
 
 
 def test_batch_of_ba_graphs_small_windows():
+    # every graph is small enough to be built whole by one workgroup; with
+    # whole_n = 0 the same batch goes through the shared windows
     _require_gpu()
     spec = gen.batch_spec(24, seed_base=500, n_lo=50, n_hi=1500)
     gs = [gen.ba_graph(n, m, s) for n, m, s in spec]
-    _check_batch(gs, 16, seed=3)
-    _check_batch(gs, 16, seed=4, window=7, group=8)
+    bx = _check_batch(gs, 16, seed=3)
+    assert bx.stats()["whole_graphs"] == 24 and bx.stats()["windows"] == 0
+    bx = _check_batch(gs, 16, seed=4, window=7, group=8, whole_n=0)
+    assert bx.stats()["whole_graphs"] == 0 and bx.stats()["windows"] > 0
+
+
+def test_batch_whole_and_windowed_graphs_mixed():
+    # graphs of at most whole_n vertices are built whole (one workgroup per
+    # graph, ranks after the interleaved ones), the others share windows;
+    # each equals its oracle, and queries across the two kinds answer 255
+    _require_gpu()
+    gs = [gen.ba_graph(n, m, 40 + i) for i, (n, m) in
+          enumerate([(1800, 3), (300, 2), (2500, 5), (64, 1), (900, 4), (4000, 2)])]
+    gs.insert(3, graphs.disjoint_union(graphs.cycle(9), graphs.star(12), graphs.empty(3)))
+    gs.insert(6, graphs.empty(1))
+    gs.append(gen.rmat_graph(11, seed=8))
+    for t_bp, lim in ((16, 1000), (0, 1000), (64, 2048), (5, 16384)):
+        bx = _check_batch(gs, t_bp, seed=t_bp, whole_n=lim)
+        want = sum(1 for g in gs if g.n <= lim)
+        assert bx.stats()["whole_graphs"] == want, (t_bp, lim)
+        assert (bx.stats()["windows"] > 0) == (want < len(gs)), (t_bp, lim)
+
+
+def test_batch_whole_pool_runs_out():
+    # a pool of one entry per vertex cannot hold the labels: the launch is
+    # redone with twice the pool until it fits, and the labels are the same
+    _require_gpu()
+    gs = [gen.ba_graph(n, 3, 70 + n) for n in (700, 1500, 250)]
+    bx = _check_batch(gs, 8, seed=9, whole_pool=1)
+    assert bx.stats()["retries"] >= 2 and bx.stats()["whole_graphs"] == 3
+
+
+def test_batch_whole_graph_distance_255():
+    # Section 4.5.1's 8-bit distances inside one workgroup: the BFS from a_0
+    # reaches w at 255 and prunes it there (the build succeeds, as the
+    # oracle's does); a path of 257 vertices has a pair 256 apart and fails
+    # with PLL_E_RANGE
+    _require_gpu()
+    g255, o255 = graphs.level_255_pruned()
+    gs = [gen.ba_graph(500, 3, 11), g255, graphs.path(40)]
+    orders = [gen.degree_order(gs[0]), o255, gen.degree_order(gs[2])]
+    vtx_off = np.zeros(len(gs) + 1, np.int64)
+    vtx_off[1:] = np.cumsum([g.n for g in gs])
+    _, rp, col, _ = gen.pack_batch(gs)
+    order = np.concatenate(orders).astype(np.int32)
+    for t_bp in (0, 1):
+        bx = binding.build_batch(vtx_off, rp, col, order, t_bp, validate=True)
+        assert bx.stats()["whole_graphs"] == 3
+        for i, (g, o) in enumerate(zip(gs, orders)):
+            ox = oracle.build(g.row_ptr, g.col, o, t_bp)
+            assert_same_index(_GraphView(bx, i), ox, f"graph {i} t_bp={t_bp}")
+        p = np.stack(np.meshgrid(np.arange(260), np.arange(260)), -1).reshape(-1, 2)
+        p = (p + vtx_off[1]).astype(np.int32)
+        want = oracle.query(oracle.build(g255.row_ptr, g255.col, o255, t_bp),
+                             (p - vtx_off[1]).astype(np.int32))
+        assert np.array_equal(bx.query(p), want)
+    bad = [gen.ba_graph(300, 2, 12), graphs.path(257)]
+    vtx_off, rp, col, order = gen.pack_batch(bad)
+    for t_bp in (0, 1):
+        with pytest.raises(binding.PllError) as e:
+            binding.build_batch(vtx_off, rp, col, order, t_bp)
+        assert e.value.code == binding.E_RANGE
 
 
 def test_batch_device_pointers_and_single_graph_batch():
