@@ -599,13 +599,29 @@ def main():
             wt[lim] = (time.perf_counter() - t1, bx.stats())
             bx.close()
         binding.set_tuning("whole_n", old_whole)
+        # the same step in one call: build and answer every graph's pairs
+        # (graphs built whole answer theirs inside the whole-graph launch)
+        qoff = np.arange(len(gs) + 1, dtype=np.int64) * (q // len(gs))
+        fused = []
+        for r in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            bx, ans = binding.build_query_batch(vtx_off, d_row, d_col, d_order, t_bp, qoff,
+                                                d_pairs, out=d_out, stream=stream, device=True)
+            fused.append((time.perf_counter() - t1, bx.stats()["whole_pairs"]))
+            bx.query_device(d_pairs, d_out2 := torch.empty_like(d_out), stream=stream)
+            torch.cuda.synchronize()
+            assert torch.equal(ans, d_out2), "fused answers differ from pll_query"
+            bx.close()
         sw = wt[old_whole][1]
         out["whole_graph_launch"] = {
             "whole_n": old_whole, "graphs": sw["whole_graphs"],
             "vertices": int(sum(x.n for x in gs if 1 <= x.n <= old_whole)),
             "launch_s": sw["whole_ns"] * 1e-9, "build_s": wt[old_whole][0],
             "windows": sw["windows"], "build_s_all_windowed": wt[0][0],
-            "windows_all_windowed": wt[0][1]["windows"]}
+            "windows_all_windowed": wt[0][1]["windows"],
+            "build_and_query_one_call_s": fused[-1][0], "pairs_answered_in_launch": fused[-1][1],
+            "step_s_build_then_query": float(np.median(build_s)) + float(np.median(query_ms)) / 1e3}
         print(f"whole-graph launch {out['whole_graph_launch']}", file=sys.stderr, flush=True)
 
     # the batched query kernel: bytes every pair must move (see

@@ -141,8 +141,8 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
  *            within graph g) of graph g's vertex of local rank i
  *   t_bp, flags, stream, out: as pll_build (PLL_DEVICE_PTRS applies to
  *            row_ptr, col and order; vtx_off is always host memory)
- * Graphs of 1 .. "whole_n" vertices (a tuning knob, at most 16384; 0 turns
- * this off) are built whole, one workgroup per graph, in one persistent
+ * Graphs of 1 .. "whole_n" vertices (a tuning knob, default 4096, at most
+ * 16384; 0 turns this off) are built whole, one workgroup per graph, in one persistent
  * launch: each workgroup takes graphs from a shared cursor, largest first,
  * and runs the graph's pruned BFSs root after root with the root's label
  * table, visited bits and BFS queue in LDS (Section 4.2's loop, Section
@@ -157,6 +157,31 @@ int pll_query(const pll_index *idx, const int32_t *pairs, int64_t q, uint8_t *ou
 int pll_build_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, const int32_t *col,
                     const int32_t *order, int32_t t_bp, uint32_t flags, void *stream,
                     pll_index **out);
+
+/*
+ * pll_build_batch plus one batch of distance queries per graph (QUERY of
+ * Section 3.3 with the bit-parallel rule of Section 5.3, clamped to 255),
+ * answered in the same call: a graph built whole answers its pairs inside
+ * the whole-graph launch, by the workgroup that built it, as soon as its
+ * labels are complete; the pairs of the other graphs are answered after the
+ * build by the batched query kernel.  The answers equal pll_query's on the
+ * returned index.
+ *   G, vtx_off, row_ptr, col, order, t_bp, stream, idx: as pll_build_batch
+ *   qoff   host int64[G+1]: graph g's pairs are pairs[2 qoff[g] ..
+ *          2 qoff[g+1]) (global ids of graph g; qoff[0] = 0, non-decreasing)
+ *   pairs  int32[2 qoff[G]], out uint8[qoff[G]]: host memory, or device
+ *          memory under PLL_DEVICE_PTRS (like row_ptr, col and order; then
+ *          the answers are complete when the stream passes the call, or on
+ *          return under PLL_SYNC; the caller keeps both buffers alive)
+ * Errors: as pll_build_batch, plus PLL_E_INVAL for a bad qoff, a null
+ * pairs/out with pairs to answer, or an id outside its graph (host
+ * pointers) or outside [0, N) (device pointers: a pair across graphs then
+ * answers 255).  On an error nothing is returned in idx.
+ */
+int pll_build_query_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr,
+                          const int32_t *col, const int32_t *order, int32_t t_bp,
+                          const int64_t *qoff, const int32_t *pairs, uint8_t *out,
+                          uint32_t flags, void *stream, pll_index **idx);
 
 /*
  * Queries on an index from pll_build_batch, by global ids: pairs inside one
@@ -455,6 +480,8 @@ enum {
                               one workgroup (see pll_build_batch) */
   PLL_STAT_WHOLE_NS,       /* wall time of that launch, ns (with any re-run
                               after the label pool ran out) */
+  PLL_STAT_WHOLE_PAIRS,    /* query pairs that launch answered
+                              (pll_build_query_batch) */
   PLL_NSTATS
 };
 int pll_stats(const pll_index *idx, int32_t graph, int64_t *counters, int32_t ncounters);
@@ -562,7 +589,7 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * "table_cap", "levels_per_sync" (steps between host checks) and "profile"
  * as above.  Bit-parallel phase: "bp_chunk" (adjacency entries per
  * work item).  Batches: "whole_n" (graphs of up to this many vertices,
- * 0..16384, default 16384, are built one workgroup per graph; 0 never) and
+ * 0..16384, default 4096, are built one workgroup per graph; 0 never) and
  * "whole_pool" (label pool entries first reserved per vertex of those
  * graphs, default 256; the launch is redone with twice the pool if it runs
  * out; same labels).  "landmarks" (0/1: builds without bit-parallel labels --

@@ -27,7 +27,7 @@ STAT_NAMES = [
     "normal_tests", "label_scanned", "edges", "task_edges", "level_launches", "level_ns",
     "bp_direct", "bp_sets", "bp_checks", "improved", "touched", "filtered", "land_checks",
     "earlier_root", "expand_ns", "expand_direct", "expand_earlier", "expand_claims",
-    "whole_graphs", "whole_ns",
+    "whole_graphs", "whole_ns", "whole_pairs",
 ]
 
 EXPORTED = [
@@ -40,6 +40,7 @@ EXPORTED = [
     "pll_export_weighted_parents", "pll_server_submit_weighted", "pll_query_noalloc",
     "pll_query_noalloc_max_pairs", "pll_query_graph_create", "pll_query_graph_launch",
     "pll_query_graph_status", "pll_query_graph_free", "pll_autotune_build",
+    "pll_build_query_batch",
 ]
 
 SERVE_STATS = ["p50_us", "p99_us", "mean_us", "pairs_per_s", "requests_per_s", "seconds",
@@ -71,6 +72,9 @@ def _lib():
         lib.pll_build_batch.argtypes = [C.c_int32, P, P, P, P, C.c_int32, C.c_uint32, P,
                                         C.POINTER(C.c_void_p)]
         lib.pll_build_batch.restype = C.c_int
+        lib.pll_build_query_batch.argtypes = [C.c_int32, P, P, P, P, C.c_int32, P, P, P,
+                                              C.c_uint32, P, C.POINTER(C.c_void_p)]
+        lib.pll_build_query_batch.restype = C.c_int
         lib.pll_query_batch.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
         lib.pll_query_batch.restype = C.c_int
         lib.pll_query_noalloc.argtypes = [P, P, C.c_int64, P, C.c_uint32, P]
@@ -534,6 +538,47 @@ def build_batch(vtx_off, row_ptr, col, order, t_bp: int, validate: bool = False,
     rc = _lib().pll_build_batch(G, _ptr(vtx_off), *args, int(t_bp), flags, s, C.byref(h))
     _check(rc, "build_batch")
     return Index(h)
+
+
+def build_query_batch(vtx_off, row_ptr, col, order, t_bp: int, qoff, pairs, out=None,
+                      validate: bool = False, stream=None, device: bool = False):
+    """Build a batch and answer each graph's pairs in the same call (see
+    include/pll.h): returns (Index, answers).  qoff: int64[G+1] offsets of
+    each graph's pairs.  With device=True, row_ptr/col/order/pairs (and out,
+    if given) are torch device tensors and the answers are a device tensor
+    complete when the call returns."""
+    vtx_off = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    qoff = np.ascontiguousarray(qoff, dtype=np.int64)
+    G = len(vtx_off) - 1
+    flags = VALIDATE if validate else 0
+    h = C.c_void_p()
+    if device:
+        import torch
+
+        for a in (row_ptr, col, order, pairs):
+            assert a.dtype == torch.int32 and a.is_cuda and a.is_contiguous()
+        if out is None:
+            out = torch.empty(int(qoff[-1]) if G > 0 else 0, dtype=torch.uint8,
+                              device=pairs.device)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        args = [C.c_void_p(a.data_ptr()) for a in (row_ptr, col, order)]
+        pq, po = C.c_void_p(pairs.data_ptr()), C.c_void_p(out.data_ptr())
+        flags |= DEVICE_PTRS | SYNC
+    else:
+        row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        order = np.ascontiguousarray(order, dtype=np.int32)
+        pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+        if out is None:
+            out = np.empty(int(qoff[-1]) if G > 0 else 0, np.uint8)
+        args = [_ptr(row_ptr), _ptr(col), _ptr(order)]
+        pq, po = _ptr(pairs), _ptr(out)
+    s = None if stream is None else C.c_void_p(stream.cuda_stream)
+    rc = _lib().pll_build_query_batch(G, _ptr(vtx_off), *args, int(t_bp), _ptr(qoff), pq, po,
+                                      flags, s, C.byref(h))
+    _check(rc, "build_query_batch")
+    return Index(h), out
 
 
 def build(row_ptr, col, order, t_bp: int, validate: bool = False, plain: bool = False,

@@ -43,8 +43,8 @@ struct Tuning {
   int root_sort = 2;  // prune tests grouped by root: 0 never, 1 always, 2 for large levels
   int64_t sort_level = 1 << 20;  // visits per level from which "root_sort" 2 groups by root
   int64_t sort_scan = 8 << 20;   // ... or label entries scanned per level
-  int64_t whole_n = kGMaxN;  // batch graphs of at most this many vertices are built
-                             // whole, one workgroup each (0: never)
+  int64_t whole_n = 4096;  // batch graphs of at most this many vertices are built
+                           // whole, one workgroup each (0: never; at most kGMaxN)
   int64_t whole_pool = 256;  // label pool entries reserved per vertex of those graphs
 };
 Tuning g_tune;
@@ -558,7 +558,15 @@ struct Builder {
   // interleaved ranks' count: the windows run roots [0, nwin)
   std::vector<int32_t> whole;
   int64_t nwin = 0;
+  // query pairs answered by the whole-graph launch (pll_build_query_batch):
+  // graph g's pairs at qpairs[2 qoff[g] ..), answers at qout[qoff[g] ..)
+  // (device memory); qpairs null: none
+  const int32_t *qpairs = nullptr;
+  uint8_t *qout = nullptr;
+  std::vector<int64_t> qoff;
+  int64_t stat_whole_pairs = 0;
 
+  const int32_t *rank_p = nullptr;  // id -> rank (the index's array)
   void relabel(const int32_t *in_row_p, const int32_t *in_col_p, const int32_t *order_p,
                bool device, pll_index *ix, DBuf<int32_t> *gid_in) {
     DBuf<int32_t> in_row, in_col, order;
@@ -595,6 +603,7 @@ struct Builder {
       gid = &gid_own;
     }
     ix->rank.alloc((size_t)n);
+    rank_p = ix->rank.p;
     ix->lrank.alloc((size_t)n);
     ix->rgid.alloc((size_t)n);
     DBuf<int32_t> gorder((size_t)n);
@@ -839,6 +848,20 @@ struct Builder {
     DBuf<GraphCtl> ctl(1);
     h2d(dbase.p, hb.data(), (size_t)ng, st);
     h2d(dn.p, hn.data(), (size_t)ng, st);
+    GraphPairs qp{nullptr, nullptr, nullptr, nullptr};
+    DBuf<int64_t> qrange;
+    if (qpairs) {
+      std::vector<int64_t> hr(2 * (size_t)ng);
+      stat_whole_pairs = 0;
+      for (int32_t i = 0; i < ng; i++) {
+        hr[2 * i] = qoff[whole[i]];
+        hr[2 * i + 1] = qoff[whole[i] + 1];
+        stat_whole_pairs += hr[2 * i + 1] - hr[2 * i];
+      }
+      qrange.alloc(hr.size());
+      h2d(qrange.p, hr.data(), hr.size(), st);
+      qp = GraphPairs{qpairs, qrange.p, rank_p, qout};
+    }
     int dev = 0, cus = 0;
     check(hipGetDevice(&dev));
     check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -853,8 +876,8 @@ struct Builder {
         S.pool_cap = want;
       }
       fill(ctl, 0, st);
-      check(launch_graph_pruned(graph(), bp, used.p, S.view(), dbase.p, dn.p, ng, ctl.p, grid,
-                                st));
+      check(launch_graph_pruned(graph(), bp, used.p, S.view(), dbase.p, dn.p, ng, ctl.p, qp,
+                                grid, st));
       GraphCtl h{};
       unsigned long long top = 0;
       d2h(&h, ctl.p, 1, st);
@@ -1767,10 +1790,18 @@ int build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
   return PLL_OK;
 }
 
+// Query pairs handed to a batch build (pll_build_query_batch): device
+// memory, graph g's pairs at pairs[2 qoff[g] ..), answers at out[qoff[g] ..).
+struct QueryJob {
+  const int32_t *pairs = nullptr;
+  uint8_t *out = nullptr;
+  std::vector<int64_t> qoff;
+};
+
 int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *row_ptr,
                  const int32_t *col, const int32_t *order, int64_t nnz, int32_t t_bp,
                  uint32_t flags, hipStream_t st, pll_index *ix, DBuf<int64_t> *d_vtx_off,
-                 DBuf<int32_t> *gid) {
+                 DBuf<int32_t> *gid, const QueryJob *job = nullptr) {
   const auto t0 = Clock::now();
   const int32_t n = (int32_t)vtx_off[G];
   Builder b;
@@ -1789,6 +1820,11 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   b.nnz = nnz;
   ix->n = n;
   ix->t = t_bp;
+  if (job) {
+    b.qpairs = job->pairs;
+    b.qout = job->out;
+    b.qoff = job->qoff;
+  }
   b.relabel(row_ptr, col, order, (flags & PLL_DEVICE_PTRS) != 0, ix, gid);
   const auto t1 = Clock::now();
   b.bit_parallel(ix);
@@ -1861,6 +1897,7 @@ int build_graphs(int32_t G, const std::vector<int64_t> &vtx_off, const int32_t *
   S[PLL_STAT_EXPAND_CLAIMS] = b.stat_x_claims;
   S[PLL_STAT_WHOLE_GRAPHS] = (int64_t)b.whole.size();
   S[PLL_STAT_WHOLE_NS] = b.stat_whole_ns;
+  S[PLL_STAT_WHOLE_PAIRS] = b.stat_whole_pairs;
   S[PLL_STAT_BUILD_NS] = ns_since(t0);
   return PLL_OK;
 }
@@ -1899,7 +1936,7 @@ extern "C" {
 
 static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr,
                        const int32_t *col, const int32_t *order, int32_t t_bp, uint32_t flags,
-                       void *stream, pll_index **out) {
+                       void *stream, pll_index **out, const QueryJob *job = nullptr) {
   if (!out) return PLL_E_INVAL;
   *out = nullptr;
   hipStream_t st = (hipStream_t)stream;
@@ -1958,7 +1995,8 @@ static int build_entry(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr
   const int32_t Gb = G > 0 ? G : 1;
   if (G == 0) voff.push_back(0);
   int rc = guarded([&] {
-    return build_graphs(Gb, voff, row_ptr, col, order, nnz, t_bp, flags, st, ix, &d_voff, &gid);
+    return build_graphs(Gb, voff, row_ptr, col, order, nnz, t_bp, flags, st, ix, &d_voff, &gid,
+                        job);
   });
   if (rc != PLL_OK) {
     (void)hipStreamSynchronize(st);
@@ -1988,6 +2026,93 @@ int pll_build_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr, c
                     const int32_t *order, int32_t t_bp, uint32_t flags, void *stream,
                     pll_index **out) {
   return build_entry(G, vtx_off, row_ptr, col, order, t_bp, flags, stream, out);
+}
+
+int pll_build_query_batch(int32_t G, const int64_t *vtx_off, const int32_t *row_ptr,
+                          const int32_t *col, const int32_t *order, int32_t t_bp,
+                          const int64_t *qoff, const int32_t *pairs, uint8_t *out,
+                          uint32_t flags, void *stream, pll_index **idx) {
+  if (!idx) return PLL_E_INVAL;
+  *idx = nullptr;
+  if (G < 0 || (G > 0 && (!vtx_off || !qoff))) return PLL_E_INVAL;
+  if (G > 0 && qoff[0] != 0) return PLL_E_INVAL;
+  for (int32_t g = 0; g < G; g++)
+    if (qoff[g + 1] < qoff[g]) return PLL_E_INVAL;
+  const int64_t q = G > 0 ? qoff[G] : 0;
+  if (q > 0 && (!pairs || !out)) return PLL_E_INVAL;
+  if (q > INT64_MAX / 4) return PLL_E_INVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const AllocStream alloc_stream(st);
+  const bool device = (flags & PLL_DEVICE_PTRS) != 0;
+  if (!device) {
+    // every pair inside its graph (before any device work)
+    for (int32_t g = 0; g < G; g++) {
+      if (vtx_off[g + 1] < vtx_off[g]) return PLL_E_INVAL;
+      for (int64_t i = 2 * qoff[g]; i < 2 * qoff[g + 1]; i++)
+        if (pairs[i] < vtx_off[g] || pairs[i] >= vtx_off[g + 1]) return PLL_E_INVAL;
+    }
+  } else if (q > 0) {
+    const int64_t N = vtx_off[G];
+    if (N <= 0 || N > INT32_MAX - 1) return PLL_E_INVAL;
+    int rc = guarded([&] {
+      DBuf<int32_t> err(1);
+      fill(err, 0, st);
+      check(launch_validate_pairs(pairs, q, (int32_t)N, err.p, st));
+      int32_t herr = 0;
+      d2h(&herr, err.p, 1, st);
+      check(hipStreamSynchronize(st));
+      return herr ? PLL_E_INVAL : PLL_OK;
+    });
+    if (rc != PLL_OK) return rc;
+  }
+  pll_index *ix = nullptr;
+  int rc = guarded([&]() -> int {
+    DBuf<int32_t> hp;
+    DBuf<uint8_t> hout;
+    QueryJob job;
+    job.qoff.assign(qoff, qoff + (G > 0 ? G + 1 : 0));
+    job.pairs = pairs;
+    job.out = out;
+    if (!device && q > 0) {
+      hp.alloc((size_t)(2 * q));
+      hout.alloc((size_t)q);
+      h2d(hp.p, pairs, (size_t)(2 * q), st);
+      job.pairs = hp.p;
+      job.out = hout.p;
+    }
+    if (q == 0) job.pairs = nullptr;
+    int brc = build_entry(G, vtx_off, row_ptr, col, order, t_bp, flags, stream, &ix,
+                          job.pairs ? &job : nullptr);
+    if (brc != PLL_OK) return brc;
+    // pairs of the graphs not built whole: one batched launch per run of
+    // consecutive such graphs, over the finished index
+    const Tuning tu = tuning();
+    for (int32_t g = 0; q > 0 && g < G;) {
+      if (ix->gblk[g] >= 0) {
+        g++;
+        continue;
+      }
+      int32_t g1 = g;
+      while (g1 < G && ix->gblk[g1] < 0) g1++;
+      const int64_t a = qoff[g], nq = qoff[g1] - qoff[g];
+      if (nq > 0)
+        check(launch_query(ix->view(), job.pairs + 2 * a, nq, job.out + a, nullptr, false,
+                           tu.qgroup, st, nullptr));
+      g = g1;
+    }
+    if (!device && q > 0) d2h(out, job.out, (size_t)q, st);
+    if (!device || (flags & PLL_SYNC)) check(hipStreamSynchronize(st));
+    return PLL_OK;
+  });
+  if (rc != PLL_OK) {
+    if (ix) {
+      (void)hipStreamSynchronize(st);
+      pll_free(ix);
+    }
+    return rc;
+  }
+  *idx = ix;
+  return PLL_OK;
 }
 
 int pll_build_weighted(int32_t n, const int32_t *row_ptr, const int32_t *col, const uint32_t *wgt,

@@ -12,7 +12,8 @@
 // it belongs to, already answers its distance to the root exactly).
 //
 // The grid is persistent: workgroups take graphs from a cursor, largest
-// first, until the list is done.  Labels grow in the build's label store
+// first, until the list is done.  Given query pairs, a workgroup answers a
+// graph's pairs as soon as the graph's labels are complete.  Labels grow in the build's label store
 // (reservations of 16-entry multiples from the shared pool top, doubled
 // when full), so the finalisation and every query path read them as they
 // read the labels of the windowed path.
@@ -27,9 +28,49 @@ constexpr int kGWaves = kGThreads / kWave;
 constexpr int32_t kStop = 1 << 30;  // above any queue length
 static_assert(kGMaxN % 32 == 0 && kGMaxN <= 65536, "LDS tables index with 16 bits");
 
+// QUERY(s, t) over a graph's finished labels (in the store, sorted by hub,
+// no sentinel), by one wave: the bit-parallel slots one per lane (Section
+// 5.3), then a merge join of L(s) and L(t) by chunks of 64 hubs, each lane
+// finding its hub of the L(s) chunk in the L(t) chunk by a halving search
+// across the lanes (Section 3.3); clamped to 255.
+__device__ __forceinline__ uint8_t wave_query(const DBp &bp, const DStore &st, int32_t rs,
+                                              int32_t rt) {
+  const int lane = lane_id();
+  int best = kInf8;
+  if (lane < bp.t) {
+    const int ds = bp.d[(int64_t)rs * bp.tpad + lane], dt = bp.d[(int64_t)rt * bp.tpad + lane];
+    if (ds != kInf8 && dt != kInf8) {
+      const uint64_t *ms = bp.m + 2 * ((int64_t)rs * bp.t + lane);
+      const uint64_t *mt = bp.m + 2 * ((int64_t)rt * bp.t + lane);
+      best = bp_pair_dist(ds, ms[0], ms[1], dt, mt[0], mt[1]);
+    }
+  }
+  constexpr uint32_t kPast = 0xFFFFFFFFu;  // above every hub rank
+  const int64_t a = st.off[rs], b = st.off[rt];
+  const int32_t la = st.len[rs], lb = st.len[rt];
+  int32_t ia = 0, ib = 0;
+  while (ia < la && ib < lb) {
+    const uint32_t ha = ia + lane < la ? st.hub[a + ia + lane] : kPast;
+    const uint32_t hb = ib + lane < lb ? st.hub[b + ib + lane] : kPast;
+    int lo = 0;  // first lane whose hb >= ha (or 63)
+#pragma unroll
+    for (int s = kWave / 2; s >= 1; s >>= 1)
+      if (__shfl(hb, lo + s - 1) < ha) lo += s;
+    if (__shfl(hb, lo) == ha && ha != kPast) {
+      const int v = (int)st.dist[a + ia + lane] + (int)st.dist[b + ib + lo];
+      best = v < best ? v : best;
+    }
+    const uint32_t lastA = __shfl(ha, kWave - 1), lastB = __shfl(hb, kWave - 1);
+    if (lastA <= lastB) ia += kWave;
+    if (lastB <= lastA) ib += kWave;
+  }
+  best = Group<kWave>::min_reduce(best);
+  return (uint8_t)(best < (int)kInf8 ? best : (int)kInf8);
+}
+
 __global__ void __launch_bounds__(kGThreads)
     k_graph_pruned(DGraph g, DBp bp, const uint8_t *used, DStore st, const int64_t *gbase,
-                   const int32_t *gn, int32_t ngraphs, GraphCtl *ctl) {
+                   const int32_t *gn, int32_t ngraphs, GraphCtl *ctl, GraphPairs qp) {
   __shared__ uint32_t s_T4[kGMaxN / 4];   // T: distance from the root per local hub, 255 = none
   __shared__ uint32_t s_vis[kGMaxN / 32];  // vertices reached by the current BFS
   __shared__ uint16_t s_q[kGMaxN];         // BFS queue (local ranks), levels one after another
@@ -217,6 +258,13 @@ __global__ void __launch_bounds__(kGThreads)
       __syncthreads();
       if (stop) break;
     }
+    // the graph's labels are complete: answer its pairs, a wave per pair
+    if (qp.pairs && !s_abort) {
+      for (int64_t i = qp.range[2 * gi] + wv; i < qp.range[2 * gi + 1]; i += kGWaves) {
+        const uint8_t v = wave_query(bp, st, qp.rank[qp.pairs[2 * i]], qp.rank[qp.pairs[2 * i + 1]]);
+        if (lane == 0) qp.out[i] = v;
+      }
+    }
   }
   if (lane == 0) {
     atomicAdd(&ctl->visited, c_vis);
@@ -231,13 +279,13 @@ __global__ void __launch_bounds__(kGThreads)
 
 hipError_t launch_graph_pruned(DGraph g, DBp bp, const uint8_t *used, DStore s,
                                const int64_t *gbase, const int32_t *gn, int32_t ngraphs,
-                               GraphCtl *ctl, int32_t grid, hipStream_t st) {
+                               GraphCtl *ctl, GraphPairs qp, int32_t grid, hipStream_t st) {
   if (ngraphs <= 0) return hipSuccess;
   if (bp.t > 64) return hipErrorInvalidValue;
   if (grid < 1) grid = 1;
   if (grid > ngraphs) grid = ngraphs;
   hipLaunchKernelGGL(k_graph_pruned, dim3((unsigned)grid), dim3(kGThreads), 0, st, g, bp, used,
-                     s, gbase, gn, ngraphs, ctl);
+                     s, gbase, gn, ngraphs, ctl, qp);
   return hipGetLastError();
 }
 

@@ -540,9 +540,18 @@ hipError_t launch_win_commit(DWindow w, DStore s, int64_t ncand, hipStream_t st)
 // kFlagRange (a vertex at distance 255 would be labeled) or kFlagOvfPool
 // (the pool is too small: the labels of the listed graphs are then
 // incomplete and must be cleared before a retry).
+// qp (optional, pairs = null for none): graph i's pairs are
+// pairs[range[2i] .. range[2i+1]) (vertex ids, rank maps them to ranks),
+// answered into out at the same index once the graph's labels are done.
+struct GraphPairs {
+  const int32_t *pairs;
+  const int64_t *range;
+  const int32_t *rank;
+  uint8_t *out;
+};
 hipError_t launch_graph_pruned(DGraph g, DBp bp, const uint8_t *used, DStore s,
                                const int64_t *gbase, const int32_t *gn, int32_t ngraphs,
-                               GraphCtl *ctl, int32_t grid, hipStream_t st);
+                               GraphCtl *ctl, GraphPairs qp, int32_t grid, hipStream_t st);
 hipError_t launch_final_count(const int32_t *len, int64_t *cnt, int32_t n, hipStream_t st);
 // hdr of an empty store (z: the bit-parallel masks, or null for none)
 hipError_t launch_store_hdr(DStore s, const uint64_t *z, int32_t n, hipStream_t st);

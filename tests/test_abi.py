@@ -53,7 +53,8 @@ def test_strerror_and_tuning():
                            ("list_cap", 100, -1), ("table_cap", 100, -1),
                            ("window", 16384, 16385), ("group", 64, 128),
                            ("wgroup", 8, 12), ("wwork", 0, -1),
-                           ("live_adjacency", 0, 2)]:
+                           ("live_adjacency", 0, 2), ("whole_n", 2048, 16385),
+                           ("whole_pool", 1, 0)]:
         old = binding.get_tuning(key)
         binding.set_tuning(key, good)
         assert binding.get_tuning(key) == good
@@ -233,3 +234,33 @@ def test_recorded_queries_and_build_autotune_reject_bad_arguments():
     assert lib.pll_autotune_build(g.n, g.row_ptr.ctypes.data, g.col.ctypes.data,
                                   order.ctypes.data, 0, binding.PLAIN, None,
                                   None) == binding.E_INVAL
+
+
+def test_build_query_batch_rejects_bad_input_before_device_work():
+    # qoff must start at 0 and not decrease, and every pair (host memory)
+    # must lie inside its own graph; all checked before any device work
+    lib = binding.library()
+    vtx_off, rp, col, order = gen.pack_batch([graphs.cycle(4), graphs.path(3)])
+    out = np.zeros(8, np.uint8)
+
+    def rc(qoff, pairs):
+        h = C.c_void_p()
+        qoff = np.ascontiguousarray(qoff, np.int64)
+        pairs = np.ascontiguousarray(pairs, np.int32)
+        r = lib.pll_build_query_batch(2, vtx_off.ctypes.data, rp.ctypes.data, col.ctypes.data,
+                                      order.ctypes.data, 0, qoff.ctypes.data, pairs.ctypes.data,
+                                      out.ctypes.data, 0, None, C.byref(h))
+        assert h.value is None
+        return r
+
+    good = np.array([[0, 3], [1, 2], [4, 6]], np.int32)
+    assert rc([1, 2, 3], good) == binding.E_INVAL        # qoff[0] != 0
+    assert rc([0, 3, 2], good) == binding.E_INVAL        # decreasing
+    assert rc([0, 1, 3], good) == binding.E_INVAL        # [1, 2] counted in graph 1
+    assert rc([0, 2, 3], [[0, 3], [1, 4], [4, 6]]) == binding.E_INVAL  # across graphs
+    assert rc([0, 2, 3], [[0, 3], [1, 2], [4, 7]]) == binding.E_INVAL  # past the end
+    h = C.c_void_p()
+    q = np.array([0, 1, 1], np.int64)
+    assert lib.pll_build_query_batch(2, vtx_off.ctypes.data, rp.ctypes.data, col.ctypes.data,
+                                     order.ctypes.data, 0, q.ctypes.data, None, None, 0, None,
+                                     C.byref(h)) == binding.E_INVAL  # pairs to answer, no buffers

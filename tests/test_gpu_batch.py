@@ -237,3 +237,47 @@ def test_build_autotune():
     finally:
         for k, v in old.items():
             binding.set_tuning(k, v)
+
+
+def test_build_and_query_in_one_call():
+    # pll_build_query_batch: a graph built whole answers its own pairs inside
+    # the whole-graph launch, the others are answered after the build; every
+    # answer equals the graph's oracle and pll_query on the returned index,
+    # with host and device pointers, with and without whole graphs, and a
+    # graph without pairs in the middle
+    import torch
+    _require_gpu()
+    gs = [gen.ba_graph(n, m, 80 + i) for i, (n, m) in
+          enumerate([(6000, 3), (300, 2), (1500, 4), (5000, 2), (64, 1), (900, 3)])]
+    gs.insert(2, graphs.disjoint_union(graphs.cycle(9), graphs.star(12), graphs.empty(3)))
+    vtx_off, rp, col, order = gen.pack_batch(gs)
+    rng = np.random.Generator(np.random.PCG64(31))
+    counts = [0 if i == 4 else 700 + 150 * i for i in range(len(gs))]
+    qoff = np.zeros(len(gs) + 1, np.int64)
+    qoff[1:] = np.cumsum(counts)
+    pairs = np.concatenate([rng.integers(vtx_off[i], vtx_off[i + 1], (c, 2))
+                            for i, c in enumerate(counts)]).astype(np.int32)
+    want = np.concatenate([oracle.query(oracle.build(g.row_ptr, g.col, gen.degree_order(g), 16),
+                                        (pairs[qoff[i]:qoff[i + 1]] - vtx_off[i]).astype(np.int32))
+                           for i, g in enumerate(gs)])
+    for lim in (4096, 0):
+        with Tuned(whole_n=lim):
+            ix, got = binding.build_query_batch(vtx_off, rp, col, order, 16, qoff, pairs,
+                                                validate=True)
+            st = ix.stats()
+            assert np.array_equal(got, want), lim
+            assert np.array_equal(ix.query(pairs), want), lim
+            whole = [i for i, g in enumerate(gs) if g.n <= lim]
+            assert st["whole_graphs"] == len(whole)
+            assert st["whole_pairs"] == sum(counts[i] for i in whole)
+            ix.close()
+            d = [torch.from_numpy(a).cuda() for a in (rp, col, order, pairs)]
+            out = torch.full((len(pairs),), 7, dtype=torch.uint8, device="cuda")
+            ix, got = binding.build_query_batch(vtx_off, *d[:3], 16, qoff, d[3], out=out,
+                                                device=True)
+            assert np.array_equal(got.cpu().numpy(), want), lim
+            ix.close()
+    with pytest.raises(binding.PllError):  # an id past the batch (device pointers)
+        bad = torch.from_numpy(pairs).cuda()
+        bad[5, 1] = int(vtx_off[-1])
+        binding.build_query_batch(vtx_off, *d[:3], 16, qoff, bad, device=True)
