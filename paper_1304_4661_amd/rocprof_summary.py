@@ -12,6 +12,11 @@
     python -m paper_1304_4661_amd.rocprof_summary window KERNEL LAST DIR
         calls / total / average duration of the last LAST dispatches whose
         name contains KERNEL, from a --kernel-trace run (DIR/*_kernel_trace.csv)
+    python -m paper_1304_4661_amd.rocprof_summary busy DIR
+        for every build in a --kernel-trace run (from its k_validate_graph
+        dispatch to its k_final_copy), the span and the time some kernel ran
+        (dispatch intervals merged): how much the host-driven loop leaves
+        the device idle
 """
 from __future__ import annotations
 
@@ -81,6 +86,29 @@ def traffic(kernel, fdir, wdir, cfdir, cwdir, copy_bytes, last=None):
     }
 
 
+def busy(d):
+    ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+                for r in _rows(d, "_kernel_trace.csv"))
+    starts = [i for i, e in enumerate(ev) if "k_validate_graph" in e[2]]
+    out = []
+    for j, a in enumerate(starts):
+        seg = ev[a:starts[j + 1] if j + 1 < len(starts) else len(ev)]
+        ends = [i for i, e in enumerate(seg) if "k_final_copy" in e[2]]
+        if not ends:
+            continue
+        seg = seg[:ends[0] + 1]
+        run, cs, ce = 0, seg[0][0], seg[0][1]
+        for s, e, _ in seg[1:]:
+            if s > ce:
+                run += ce - cs
+                cs, ce = s, e
+            else:
+                ce = max(ce, e)
+        run += ce - cs
+        out.append((seg[-1][1] - seg[0][0], run))
+    return out
+
+
 def main(argv):
     if argv[0] == "stats":
         rows = stats(argv[1])
@@ -95,6 +123,13 @@ def main(argv):
         calls, tot, avg = window(argv[3], argv[1], int(argv[2]))
         print(f"{argv[1]}: last {calls} dispatches, {tot / 1e6:.3f} ms, {avg / 1e3:.2f} us "
               "per launch")
+    elif argv[0] == "busy":
+        rows = busy(argv[1])
+        for span, run in rows:
+            print(f"  span {span / 1e6:9.1f} ms, kernels {run / 1e6:9.1f} ms, busy {run / span:.3f}")
+        fr = [run / span for span, run in rows]
+        if fr:
+            print(f"  {len(rows)} builds, busy {min(fr):.3f} .. {max(fr):.3f}")
     else:
         raise SystemExit(__doc__)
 

@@ -210,3 +210,24 @@ def test_ba256_answers(ba256):
     gof = np.searchsorted(vtx_off, p, side="right") - 1
     cross = gof[:, 0] != gof[:, 1]
     assert np.all(ix.query(p[cross]) == 255)
+
+
+def test_ba256_build_and_query_in_one_call(ba256):
+    # pll_build_query_batch on the full batch: the graphs built whole answer
+    # their pairs inside the whole-graph launch, the rest after the build;
+    # every graph's answers equal its oracle's
+    gold, gs, vtx_off = ba256["gold"], ba256["gs"], ba256["vtx_off"]
+    _, row_ptr, col, order = gen.pack_batch(gs)
+    d_row, d_col, d_order = _device(row_ptr, col, order)
+    per = len(ba256["pairs"]) // 256
+    qoff = np.arange(257, dtype=np.int64) * per
+    ix, out = binding.build_query_batch(vtx_off, d_row, d_col, d_order, ba256["t_bp"], qoff,
+                                        ba256["d_pairs"], device=True)
+    st = ix.stats()
+    ix.close()
+    whole = [i for i, g in enumerate(gs) if g.n <= binding.get_tuning("whole_n")]
+    assert st["whole_graphs"] == len(whole) > 0 and st["whole_pairs"] == per * len(whole)
+    a = out.cpu().numpy()
+    for i in range(256):
+        got = digest.answers_digest(a[i * per:(i + 1) * per])
+        assert got["sha256"] == gold["graphs"][i]["answers"]["sha256"], f"graph {i}"
