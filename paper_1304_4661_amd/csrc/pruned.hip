@@ -674,34 +674,58 @@ __global__ void __launch_bounds__(kScanThreads) k_root_scan(DRootSort rs, LevelC
   }
 }
 
-// One lane per entry of level d.  Lanes of a wave that share a root take
-// their places with one atomic (entries of one candidate's expansion are
-// adjacent, so a wave holds few roots).
+// One lane per entry of level d.  A wave sorts its 64 (root, lane) keys
+// with a bitonic network in registers, so lanes of one root become
+// neighbours; the first lane of each root's run reserves the run's places
+// with one atomic, all runs at once, and every entry goes to its root's
+// run in lane order.
 __global__ void __launch_bounds__(kBlock) k_root_scatter(DRootSort rs, DFrontier f, int d) {
   LevelCtl *ctl = f.ctl;
   const unsigned long long beg = ctl->base[d], cnt = ctl->cnt[d];
   if (d == 0 || cnt == 0 || (ctl->flags & kOverflowFlags) ||
       beg + cnt > (unsigned long long)f.cap || cnt > (unsigned long long)rs.cap)
     return;
+  const int lane = lane_id();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t nloop = ((int64_t)cnt + stride - 1) / stride;
   for (int64_t it = 0; it < nloop; it++) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + it * stride;
     const bool valid = p < (int64_t)cnt;
-    const int32_t j = valid ? f.slot[beg + p] : -1;
-    uint64_t act = __ballot(valid);
-    while (act) {
-      const int leader = __ffsll((unsigned long long)act) - 1;
-      const int32_t jl = __shfl(j, leader);
-      const uint64_t m = __ballot(valid && j == jl) & act;
-      uint32_t b = 0;
-      if (lane_id() == leader) b = atomicAdd(&rs.rfill[jl], (uint32_t)__popcll(m));
-      b = __shfl(b, leader);
-      if ((m >> lane_id()) & 1ull) {
-        const int64_t q = rs.roff[jl] + b + __popcll(m & lanes_below_mask());
-        rs.sv[q] = f.v[beg + p];
+    // key: root slot << 6 | lane (distinct; no entry sorts past INT32_MAX)
+    int32_t key = valid ? (f.slot[beg + p] << 6) | lane : INT32_MAX;
+    const int32_t v = valid ? f.v[beg + p] : 0;
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+      for (int s = k >> 1; s > 0; s >>= 1) {
+        const int32_t o = __shfl_xor(key, s);
+        // ascending where lane & k is 0 (k = 64: everywhere); the lower
+        // lane of a pair keeps the smaller key in an ascending run
+        const bool asc = (lane & k) == 0, lower = (lane & s) == 0;
+        key = (lower == asc) ? (o < key ? o : key) : (o > key ? o : key);
       }
-      act &= ~m;
+    }
+    const bool real = key != INT32_MAX;
+    const int32_t j = key >> 6, src = key & (kWave - 1);
+    const int32_t jprev = __shfl_up(j, 1);
+    const bool first = real && (lane == 0 || jprev != j);
+    const uint64_t starts = __ballot(first);
+    const uint64_t reals = __ballot(real);
+    // run of this lane: from the last start at or below it to the next start
+    const uint64_t below = starts & (lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1));
+    const int r0 = below ? 63 - __clzll((long long)below) : 0;
+    uint32_t b = 0;
+    if (first) {
+      const uint64_t after = starts & ~((2ull << lane) - 1 | (lane == kWave - 1 ? ~0ull : 0ull));
+      const int r1 = after ? __ffsll((unsigned long long)after) - 1 : kWave;
+      const int r1r = __popcll(reals) < r1 ? __popcll(reals) : r1;  // invalid lanes sort last
+      b = atomicAdd(&rs.rfill[j], (uint32_t)(r1r - lane));
+    }
+    b = __shfl(b, r0);
+    const int32_t vv = __shfl(v, src);
+    if (real) {
+      const int64_t q = rs.roff[j] + b + (lane - r0);
+      rs.sv[q] = vv;
     }
   }
 }
