@@ -90,18 +90,30 @@ def level_kernel_bytes(st, t_bp, sides=1):
             + 5 * st["label_scanned"] + 18 * st["candidates"])
 
 
+def expand_row_bytes(t_bp):
+    """Bytes of a reached neighbour's distance row as the expansion reads
+    it: the 4-bit copy (half the padded row) when rows have 32 or 64 slots
+    and the "packed_rows" knob is on, else t_bp."""
+    from paper_1304_4661_amd import binding
+
+    tpad = (t_bp + 15) & ~15
+    if t_bp > 0 and tpad % 32 == 0 and binding.get_tuning("packed_rows"):
+        return tpad // 2
+    return t_bp
+
+
 def expand_kernel_bytes(st, t_bp):
     """Algorithmic bytes of the pruned-phase expansion kernel (k_win_expand),
     summed over its launches in one build:
       per candidate expanded: 8 B list entry + 8 B row offsets + t_bp B root
         distance row,
       per adjacency entry expanded inline: 4 B neighbour; unless the
-        neighbour is ranked before the window, + t_bp B its distance row;
-        unless that row prunes it too, + 4 B visited word,
+        neighbour is ranked before the window, + its distance row
+        (expand_row_bytes); unless that row prunes it too, + 4 B visited word,
       per neighbour claimed: 8 B next-level list entry."""
     e = st["edges"]
     rest = e - st["expand_earlier"]
-    return (st["candidates"] * (16 + t_bp) + 4 * e + rest * t_bp
+    return (st["candidates"] * (16 + t_bp) + 4 * e + rest * expand_row_bytes(t_bp)
             + 4 * (rest - st["expand_direct"]) + 8 * st["expand_claims"])
 
 

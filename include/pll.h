@@ -604,7 +604,11 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * already prunes it at the next level; 0 visits and tests every reached
  * neighbour as Algorithm 1 does, and also turns "live_adjacency" and the
  * landmark rows off, so that a PLL_PLAIN build's visits, labels and
- * scanned edges are the sequential algorithm's; same labels).  Memory: "pool_keep_mb" (device memory of freed build
+ * scanned edges are the sequential algorithm's; same labels).
+ * "packed_rows" (0/1, default 1: with t_bp giving rows of 32 or 64 slots,
+ * the expansion's prune reads 4-bit copies of the reached vertices'
+ * bit-parallel distance rows, distances of 15 or more counting as none;
+ * same labels).  Memory: "pool_keep_mb" (device memory of freed build
  * scratch and indexes kept for reuse by later builds, MB; reuse on another
  * stream waits for the stream that freed it; lowering the value releases
  * the excess at once, 0 keeps nothing).  Queries: "qgroup" (lanes per pair: 16, 32, 64), "qpersist" (0/1: batched queries with

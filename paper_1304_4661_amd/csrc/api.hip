@@ -46,6 +46,7 @@ struct Tuning {
   int64_t whole_n = 4096;  // batch graphs of at most this many vertices are built
                            // whole, one workgroup each (0: never; at most kGMaxN)
   int64_t whole_pool = 256;  // label pool entries reserved per vertex of those graphs
+  int packed_rows = 1;  // the expansion reads 4-bit copies of the distance rows
 };
 Tuning g_tune;
 std::mutex g_tune_mu;
@@ -1009,6 +1010,13 @@ struct Builder {
     for (int k = 0; k < nsides; k++)
       check(launch_store_hdr(stores[k].view(), t > 0 ? bpz.p : nullptr, n, st));
     DBp bp{t, ix->tpad, ix->bpd.p, ix->bpm.p, bpz.p};
+    // 4-bit distance rows for the expansion's prune (half the bytes per
+    // reached neighbour; same labels: a saturated distance never prunes)
+    DBuf<uint4> bpq;
+    if (t > 0 && ix->tpad % 32 == 0 && tu.packed_rows && n > 0) {
+      bpq.alloc((size_t)n * (ix->tpad / 32));
+      check(launch_bp_pack(ix->bpd.p, n, ix->tpad, bpq.p, st));
+    }
     int64_t entries_bound[2] = {0, 0};
     // Expansion-time prune rows.  With bit-parallel labels they are the
     // bit-parallel distance rows (Section 5.4).  Without them (t = 0, and
@@ -1070,6 +1078,7 @@ struct Builder {
       for (int k = 0; k < nsides && !flags; k++) {  // after an overflow the window is redone
         w[k] = sides[k].window(s, nr, words, used.p);
         DBp rb = t > 0 && tu.expand_prune ? bp : no_rows, vb = rb;
+        if (t > 0 && tu.expand_prune) vb.q = bpq.p;
         if (t == 0 && have_land && s >= kLandmarks && tu.expand_prune) {
           rb = DBp{kLandmarks, kLandmarks, land[nsides - 1 - k].p, nullptr, nullptr};
           vb = DBp{kLandmarks, kLandmarks, land[k].p, nullptr, nullptr};
@@ -2868,6 +2877,9 @@ static int set_tuning_locked(const std::string &k, int64_t value, int64_t &trim_
   } else if (k == "whole_n") {
     if (value < 0 || value > kGMaxN) return PLL_E_INVAL;
     g_tune.whole_n = value;
+  } else if (k == "packed_rows") {
+    if (value < 0 || value > 1) return PLL_E_INVAL;
+    g_tune.packed_rows = (int)value;
   } else if (k == "whole_pool") {
     if (value < 1 || value > (1 << 20)) return PLL_E_INVAL;
     g_tune.whole_pool = value;
@@ -2906,6 +2918,7 @@ int64_t pll_get_tuning(const char *key) {
   if (k == "serve_coalesce") return g_tune.serve_coalesce;
   if (k == "whole_n") return g_tune.whole_n;
   if (k == "whole_pool") return g_tune.whole_pool;
+  if (k == "packed_rows") return g_tune.packed_rows;
   return PLL_E_INVAL;
 }
 

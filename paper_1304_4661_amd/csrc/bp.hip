@@ -207,6 +207,35 @@ __global__ void k_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t
   }
 }
 
+// 4-bit copy of the distance rows (DBp::q): one thread per packed 16 bytes
+// of a vertex; byte k of packed uint4 qi takes slot 16 qi + k (low nibble)
+// and slot tpad/2 + 16 qi + k (high nibble), each saturated at 15.
+__global__ void k_bp_pack(const uint8_t *d, int32_t n, int32_t tpad, uint4 *q) {
+  const int32_t per = tpad / 32;  // packed uint4 per vertex
+  const int32_t half = tpad / 32;  // uint4 of the low half of a row
+  const int64_t total = (int64_t)n * per;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t v = i / per;
+    const int32_t qi = (int32_t)(i % per);
+    const uint4 *row = reinterpret_cast<const uint4 *>(d + v * tpad);
+    const uint4 lo = row[qi], hi = row[qi + half];
+    const uint32_t lw[4] = {lo.x, lo.y, lo.z, lo.w}, hw[4] = {hi.x, hi.y, hi.z, hi.w};
+    uint32_t o[4];
+    for (int w = 0; w < 4; w++) {
+      uint32_t r = 0;
+      for (int b = 0; b < 4; b++) {
+        uint32_t a = (lw[w] >> (8 * b)) & 0xFFu, c = (hw[w] >> (8 * b)) & 0xFFu;
+        a = a < 15u ? a : 15u;
+        c = c < 15u ? c : 15u;
+        r |= (a | (c << 4)) << (8 * b);
+      }
+      o[w] = r;
+    }
+    q[i] = make_uint4(o[0], o[1], o[2], o[3]);
+  }
+}
+
 unsigned grid_for(int64_t items, int per_block, int64_t cap) {
   int64_t bl = (items + per_block - 1) / per_block;
   if (bl < 1) bl = 1;
@@ -255,6 +284,14 @@ hipError_t launch_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t
                                hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_bpv_nonempty, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, n, t, m, z);
+  return hipGetLastError();
+}
+
+hipError_t launch_bp_pack(const uint8_t *d, int32_t n, int32_t tpad, uint4 *q, hipStream_t st) {
+  if (n == 0 || tpad == 0) return hipSuccess;
+  if (tpad % 32) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)n * (tpad / 32);
+  hipLaunchKernelGGL(k_bp_pack, dim3(grid_for(total, 256, 8192)), dim3(256), 0, st, d, n, tpad, q);
   return hipGetLastError();
 }
 

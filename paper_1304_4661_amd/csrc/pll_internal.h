@@ -222,6 +222,12 @@ struct DBp {
   const uint8_t *d;
   const uint64_t *m;
   const uint64_t *z;  // [n] slots whose S^{-1} is non-empty (bit per slot)
+  // optional (tpad a multiple of 32): the distances again in 4 bits, tpad/2
+  // bytes per vertex; byte k holds slot k in its low nibble and slot
+  // k + tpad/2 in its high nibble, each min(d, 15) (15: 15 or more, or
+  // unreachable).  Read by the expansion's distance-row prune, which only
+  // needs to know whether d_k + d_x <= D.
+  const uint4 *q = nullptr;
 };
 // The same, writable, plus per-vertex "found at the next level" slot bits
 // used while the bit-parallel BFS runs.
@@ -498,6 +504,9 @@ hipError_t launch_bpv_level(DGraph g, DBpW b, const int32_t *it_v, const int32_t
 hipError_t launch_bpv_finish(int64_t total, uint64_t *m, hipStream_t st);
 hipError_t launch_bpv_nonempty(int32_t n, int32_t t, const uint64_t *m, uint64_t *z,
                                hipStream_t st);
+// DBp::q from the 8-bit rows d ([n][tpad], tpad a multiple of 32): q holds
+// n * tpad / 32 uint4
+hipError_t launch_bp_pack(const uint8_t *d, int32_t n, int32_t tpad, uint4 *q, hipStream_t st);
 
 hipError_t launch_win_reset_ctl(LevelCtl *ctl, hipStream_t st);
 // sizes: int64[nroots + 1]; scan_tmp: scan_tmp_elems(nroots + 1) int64

@@ -481,8 +481,50 @@ struct RootRow {
   // Is d_k + d_x <= D for some slot?  Byte sums are formed two at a time in
   // 16-bit fields (at most 510) and compared with D+1 by one subtraction per
   // field; 255 (unreachable, padding) never counts: 255 + anything > 254 >= D.
+  __device__ __forceinline__ static void sum_hits(uint4 a, uint4 b, uint32_t K, uint32_t &hit) {
+    const uint32_t aw[4] = {a.x, a.y, a.z, a.w}, bw[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int y = 0; y < 4; y++) {
+      const uint32_t se = (aw[y] & 0x00FF00FFu) + (bw[y] & 0x00FF00FFu);
+      const uint32_t so = ((aw[y] >> 8) & 0x00FF00FFu) + ((bw[y] >> 8) & 0x00FF00FFu);
+      hit |= ~((se | 0x80008000u) - K) & 0x80008000u;
+      hit |= ~((so | 0x80008000u) - K) & 0x80008000u;
+    }
+  }
+  // the 4-bit row's low (hi = false) or high nibbles as bytes; a nibble of
+  // 15 (15 or more, or unreachable) becomes 255, which never counts
+  __device__ __forceinline__ static uint4 unpack(uint4 b, bool hi) {
+    const uint32_t w[4] = {b.x, b.y, b.z, b.w};
+    uint32_t o[4];
+#pragma unroll
+    for (int y = 0; y < 4; y++) {
+      const uint32_t c = (hi ? w[y] >> 4 : w[y]) & 0x0F0F0F0Fu;
+      o[y] = c | ((((c + 0x01010101u) >> 4) & 0x01010101u) * 0xF0u);
+    }
+    return make_uint4(o[0], o[1], o[2], o[3]);
+  }
+  // P: the reached vertex's row from the 4-bit copy bp.q (then tpad is 32
+  // or 64)
+  template <bool P>
   __device__ __forceinline__ bool direct(const DBp &bp, int32_t x, int D) const {
     const uint32_t K = (uint32_t)(D + 1) * 0x00010001u;
+    if constexpr (P) {
+      // half the bytes: slot k and slot k + tpad/2 share a byte
+      uint32_t hit = 0;
+      if (nv == 4) {
+        const uint4 *p = bp.q + (int64_t)x * 2;
+        const uint4 b0 = p[0], b1 = p[1];
+        sum_hits(v[0], unpack(b0, false), K, hit);
+        sum_hits(v[2], unpack(b0, true), K, hit);
+        sum_hits(v[1], unpack(b1, false), K, hit);
+        sum_hits(v[3], unpack(b1, true), K, hit);
+      } else {
+        const uint4 b0 = bp.q[x];
+        sum_hits(v[0], unpack(b0, false), K, hit);
+        sum_hits(v[1], unpack(b0, true), K, hit);
+      }
+      return hit != 0;
+    } else {
     const uint4 *p = reinterpret_cast<const uint4 *>(bp.d + (int64_t)x * bp.tpad);
     uint32_t hit = 0;
 #pragma unroll
@@ -499,6 +541,7 @@ struct RootRow {
       }
     }
     return hit != 0;
+    }
   }
 };
 
@@ -976,13 +1019,14 @@ struct FrontierFlush {
 // distance from every later root (Section 4.2; Section 5.3 for the
 // bit-parallel ones), so the test at any level would prune it.  It is left
 // unvisited before any memory is read (counted in `earlier`).
+template <bool P>
 __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t *vs, int32_t x,
                                       int d, int32_t s, uint32_t &direct, uint32_t &earlier) {
   if (x < s) {  // s: the window start, or 0 when this skip is switched off
     earlier++;
     return false;
   }
-  if (rr.direct(vb, x, d + 1)) {
+  if (rr.template direct<P>(vb, x, d + 1)) {
     direct++;
     return false;
   }
@@ -991,8 +1035,8 @@ __device__ __forceinline__ bool reach(const DBp &vb, const RootRow &rr, uint32_t
   return !(atomicOr(&vs[x >> 5], bit) & bit);
 }
 
-template <int G>
-__global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb, DBp vb,
+template <int G, bool P>
+__global__ void __launch_bounds__(kBlock, P ? 4 : 1) k_win_expand(DGraph g, DBp bp, DBp rb, DBp vb,
                                                        DStore st, DWindow w, DFrontier f,
                                                        DRootSort rs, int d, int chunk,
                                                        int32_t skip_below) {
@@ -1047,7 +1091,7 @@ __global__ void __launch_bounds__(kBlock) k_win_expand(DGraph g, DBp bp, DBp rb,
       int32_t x = 0;
       if (idx < lim) {
         x = g.col[e0 + idx];
-        claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
+        claimed = reach<P>(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
         mine += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush);
@@ -1114,6 +1158,7 @@ __global__ void __launch_bounds__(kBlock) k_win_range(DGraph g, DBp bp, DStore s
   }
 }
 
+template <bool P>
 __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, DWindow w,
                                                       DFrontier f, DRootSort rs, int d, int chunk,
                                                       int lim_inline, int32_t skip_below) {
@@ -1149,7 +1194,7 @@ __global__ void __launch_bounds__(kBlock) k_win_heavy(DGraph g, DBp rb, DBp vb, 
       int32_t x = 0;
       if (e < b) {
         x = g.col[e];
-        claimed = reach(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
+        claimed = reach<P>(vb, rr, vs, x, d, skip_below, c_direct, c_earlier);
         mine += claimed ? 1u : 0u;
       }
       stage.push(claimed, j, x, flush);
@@ -1490,29 +1535,31 @@ hipError_t launch_win_level(DGraph g, DBp bp, DBp rb, DBp vb, DStore s, DStore r
     PLL_LAUNCH_TIMED(k_win_range, gd, bd, st, ev2, ev3, g, bp, s, w, f, d);
     return hipGetLastError();
   }
+  // the 4-bit rows when the caller made them (tpad 32 or 64)
+  const bool packed = vb.q && (vb.tpad == 32 || vb.tpad == 64);
+#define PLL_EXPAND(GG)                                                                       \
+  do {                                                                                       \
+    if (packed)                                                                              \
+      PLL_LAUNCH_TIMED((k_win_expand<GG, true>), gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, \
+                       rs, d, chunk, skip_below);                                            \
+    else                                                                                     \
+      PLL_LAUNCH_TIMED((k_win_expand<GG, false>), gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w,   \
+                       f, rs, d, chunk, skip_below);                                         \
+  } while (0)
   switch (xgroup) {
-    case 4:
-      PLL_LAUNCH_TIMED(k_win_expand<4>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d, chunk,
-                       skip_below);
-      break;
-    case 8:
-      PLL_LAUNCH_TIMED(k_win_expand<8>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d, chunk,
-                       skip_below);
-      break;
-    case 16:
-      PLL_LAUNCH_TIMED(k_win_expand<16>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
-                       chunk, skip_below);
-      break;
-    case 32:
-      PLL_LAUNCH_TIMED(k_win_expand<32>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
-                       chunk, skip_below);
-      break;
-    default:
-      PLL_LAUNCH_TIMED(k_win_expand<64>, gd, bd, st, ev2, ev3, g, bp, rb, vb, s, w, f, rs, d,
-                       chunk, skip_below);
-      break;
+    case 4: PLL_EXPAND(4); break;
+    case 8: PLL_EXPAND(8); break;
+    case 16: PLL_EXPAND(16); break;
+    case 32: PLL_EXPAND(32); break;
+    default: PLL_EXPAND(64); break;
   }
-  hipLaunchKernelGGL(k_win_heavy, gd, bd, 0, st, g, rb, vb, w, f, rs, d, chunk, chunk, skip_below);
+#undef PLL_EXPAND
+  if (packed)
+    hipLaunchKernelGGL(k_win_heavy<true>, gd, bd, 0, st, g, rb, vb, w, f, rs, d, chunk, chunk,
+                       skip_below);
+  else
+    hipLaunchKernelGGL(k_win_heavy<false>, gd, bd, 0, st, g, rb, vb, w, f, rs, d, chunk, chunk,
+                       skip_below);
   return hipGetLastError();
 }
 

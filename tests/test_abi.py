@@ -54,7 +54,7 @@ def test_strerror_and_tuning():
                            ("window", 16384, 16385), ("group", 64, 128),
                            ("wgroup", 8, 12), ("wwork", 0, -1),
                            ("live_adjacency", 0, 2), ("whole_n", 2048, 16385),
-                           ("whole_pool", 1, 0)]:
+                           ("whole_pool", 1, 0), ("packed_rows", 0, 2)]:
         old = binding.get_tuning(key)
         binding.set_tuning(key, good)
         assert binding.get_tuning(key) == good

@@ -33,10 +33,24 @@ def test_weighted_step_byte_model():
 
 
 def test_expand_kernel_byte_model():
+    # a reached neighbour's row: 32 B from the 4-bit copy of a 64-slot row
+    # (t_bp = 50 pads to 64), t_bp B from the 8-bit rows (knob off, or a
+    # 48-slot row)
+    from paper_1304_4661_amd import binding
     st = {"candidates": 5, "edges": 100, "expand_earlier": 40, "expand_direct": 30,
           "expand_claims": 20}
-    assert bench.expand_kernel_bytes(st, 50) == (5 * 66 + 4 * 100 + 60 * 50 + 4 * 30
-                                                 + 8 * 20)
+    old = binding.get_tuning("packed_rows")
+    try:
+        binding.set_tuning("packed_rows", 1)
+        assert bench.expand_kernel_bytes(st, 50) == (5 * 66 + 4 * 100 + 60 * 32 + 4 * 30
+                                                     + 8 * 20)
+        assert bench.expand_kernel_bytes(st, 40) == (5 * 56 + 4 * 100 + 60 * 40 + 4 * 30
+                                                     + 8 * 20)
+        binding.set_tuning("packed_rows", 0)
+        assert bench.expand_kernel_bytes(st, 50) == (5 * 66 + 4 * 100 + 60 * 50 + 4 * 30
+                                                     + 8 * 20)
+    finally:
+        binding.set_tuning("packed_rows", old)
 
 
 def test_method_byte_model():

@@ -383,6 +383,26 @@ def test_earlier_roots_skipped_at_expansion(t_bp):
     gx.close()
 
 
+@pytest.mark.parametrize("t_bp", [17, 32, 50, 64])
+def test_packed_distance_rows(t_bp):
+    # the expansion's distance-row prune reads 4-bit copies of the rows
+    # (tpad 32 or 64) or the 8-bit rows (knob off, or tpad 48): the same
+    # labels either way (a saturated 4-bit distance prunes nothing, so a
+    # neighbour the 4-bit row cannot rule out is left to the tests)
+    _require_gpu()
+    g = gen.rmat_graph(13, seed=12)
+    order = gen.degree_order(g)
+    ox = oracle.build(g.row_ptr, g.col, order, t_bp)
+    st = {}
+    for packed in (1, 0):
+        with Tuned(packed_rows=packed):
+            gx = binding.build(g.row_ptr, g.col, order, t_bp)
+        assert_same_index(gx, ox, f"t_bp={t_bp} packed={packed}")
+        st[packed] = gx.stats()
+        gx.close()
+    assert st[1]["bp_direct"] > 0 and st[0]["bp_direct"] > 0  # both forms prune by rows
+
+
 @pytest.mark.parametrize("live", [0, 1])
 @pytest.mark.parametrize("t_bp", [0, 32])
 def test_live_adjacency(live, t_bp):
