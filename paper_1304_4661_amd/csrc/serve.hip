@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <mutex>
 #include <new>
@@ -268,13 +269,27 @@ int pll_server_start(const pll_index *idx, int32_t nslots, int64_t slot_pairs, p
               hipMalloc((void **)&sl.dp, (size_t)slot_pairs * 2 * sizeof(int32_t)) ==
                   hipSuccess &&
               hipMalloc((void **)&sl.dout, (size_t)slot_pairs * sv->es) == hipSuccess;
-    // one copy and one kernel per slot stream now, so that the runtime sets
-    // up the stream's hardware queue here and not on the first request (a
-    // first dispatch on a new stream was measured to stall the worker for
-    // up to 9 ms)
-    ok = ok && hipMemcpyAsync(sl.dp, sl.hp, sizeof(int32_t), hipMemcpyHostToDevice, sl.s) ==
-                   hipSuccess &&
-         launch_zero_flag(sl.dp, sl.s) == hipSuccess && hipStreamSynchronize(sl.s) == hipSuccess;
+    // One request's worth of work per slot now, over the whole staging
+    // buffers, so that neither the runtime's set-up of the stream's queues
+    // nor the first touch of the pinned pages (by the host and by the copy
+    // engines) lands on a request: a first dispatch on a new stream was
+    // measured to stall the worker for up to 9 ms, and the first launch that
+    // used a larger part of the staging than any before it for 6.5 ms.
+    // The staged pairs are (0, 0), a valid query of any non-empty index.
+    if (ok) {
+      std::memset(sl.hp, 0, (size_t)slot_pairs * 2 * sizeof(int32_t));
+      std::memset(sl.ho, 0, (size_t)slot_pairs * sv->es);
+    }
+    ok = ok && hipMemcpyAsync(sl.dp, sl.hp, (size_t)slot_pairs * 2 * sizeof(int32_t),
+                              hipMemcpyHostToDevice, sl.s) == hipSuccess;
+    if (ok && sv->n > 0)
+      ok = (sv->weighted ? launch_wquery(sv->view, sl.dp, 1, reinterpret_cast<uint32_t *>(sl.dout),
+                                         nullptr, false, sv->qgroup, sl.s)
+                         : launch_query(sv->view, sl.dp, 1, sl.dout, nullptr, false, sv->qgroup,
+                                        sl.s)) == hipSuccess;
+    ok = ok && hipMemcpyAsync(sl.ho, sl.dout, (size_t)slot_pairs * sv->es, hipMemcpyDeviceToHost,
+                              sl.s) == hipSuccess &&
+         hipEventRecord(sl.ev, sl.s) == hipSuccess && hipStreamSynchronize(sl.s) == hipSuccess;
     if (!ok) {
       (void)hipGetLastError();
       sv->release();
