@@ -564,8 +564,10 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * count.  Pruned phase: "window" (most concurrent roots, 1..16384),
  * "window_work" (visits aimed at per window: the window grows or shrinks
  * toward it after each window; 0 keeps every window at the maximum),
- * "window_mem_mb" (device memory the per-root window state may take; caps
- * the window at about this / (2.4 n) roots), "group" (lanes per frontier
+ * "window_mem_mb" (device memory the per-root window state may take, about
+ * 1.4 n bytes per root, twice that for a directed graph; default 65536,
+ * and never more than the device's free memory less a fifth of the device
+ * (at least 8 GB) kept for the label pool and lists), "group" (lanes per frontier
  * entry in the prune tests: 4..64, or 0 (default): chosen per window from
  * the label entries a test scanned in the window before), "root_sort" (0:
  * prune tests straight from the frontier, the root's label through a table

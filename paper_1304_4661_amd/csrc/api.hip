@@ -981,7 +981,19 @@ struct Builder {
     // per-root window state per side: distance column of wd (n B), visited
     // bits (n/8 B) and two mask bits per vertex (n/4 B)
     const int64_t per_root = nsides * ((int64_t)n + (n + 7) / 8 + (n + 3) / 4 + 1);
-    const int64_t wmem = std::max<int64_t>(64, (tu.window_mem_mb << 20) / per_root);
+    // window_mem_mb, but no more than the device has free beyond a reserve
+    // for the label pool and the lists (a fifth of the device, at least 8 GB)
+    int64_t wbytes = tu.window_mem_mb << 20;
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot > 0) {
+        const int64_t reserve = std::max<int64_t>(8ll << 30, (int64_t)(tot / 5));
+        wbytes = std::min<int64_t>(wbytes, std::max<int64_t>((int64_t)fr - reserve, 0));
+      } else {
+        (void)hipGetLastError();
+      }
+    }
+    const int64_t wmem = std::max<int64_t>(64, wbytes / per_root);
     const int wmax =
         plain ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>({tu.window, kMaxWindow, wmem}));
     const int words = (wmax + 63) / 64;
