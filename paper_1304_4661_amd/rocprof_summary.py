@@ -12,6 +12,9 @@
     python -m paper_1304_4661_amd.rocprof_summary window KERNEL LAST DIR
         calls / total / average duration of the last LAST dispatches whose
         name contains KERNEL, from a --kernel-trace run (DIR/*_kernel_trace.csv)
+    python -m paper_1304_4661_amd.rocprof_summary counters DIR
+        every counter of a --pmc run summed over its dispatches
+        (DIR/*_counter_collection.csv), with the number of dispatches
     python -m paper_1304_4661_amd.rocprof_summary busy DIR
         for every build in a --kernel-trace run (from its k_validate_graph
         dispatch to its k_final_copy), the span and the time some kernel ran
@@ -86,6 +89,15 @@ def traffic(kernel, fdir, wdir, cfdir, cwdir, copy_bytes, last=None):
     }
 
 
+def counters(d):
+    tot, cnt = {}, {}
+    for r in _rows(d, "_counter_collection.csv"):
+        k = r["Counter_Name"]
+        tot[k] = tot.get(k, 0.0) + float(r["Counter_Value"])
+        cnt[k] = cnt.get(k, 0) + 1
+    return {k: (tot[k], cnt[k]) for k in sorted(tot)}
+
+
 def busy(d):
     ev = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
                 for r in _rows(d, "_kernel_trace.csv"))
@@ -123,6 +135,9 @@ def main(argv):
         calls, tot, avg = window(argv[3], argv[1], int(argv[2]))
         print(f"{argv[1]}: last {calls} dispatches, {tot / 1e6:.3f} ms, {avg / 1e3:.2f} us "
               "per launch")
+    elif argv[0] == "counters":
+        for k, (v, c) in counters(argv[1]).items():
+            print(f"{k:26s} {v:20.0f}  ({c} dispatches)")
     elif argv[0] == "busy":
         rows = busy(argv[1])
         for span, run in rows:
