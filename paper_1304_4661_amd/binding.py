@@ -550,6 +550,13 @@ def build_query_batch(vtx_off, row_ptr, col, order, t_bp: int, qoff, pairs, out=
     vtx_off = np.ascontiguousarray(vtx_off, dtype=np.int64)
     qoff = np.ascontiguousarray(qoff, dtype=np.int64)
     G = len(vtx_off) - 1
+    if len(qoff) != G + 1:
+        raise ValueError("qoff needs one offset per graph plus one")
+    q = int(qoff[-1]) if G > 0 else 0
+    if pairs is not None and (pairs.numel() if device else np.size(pairs)) < 2 * q:
+        raise ValueError(f"pairs holds fewer than qoff[-1] = {q} pairs")
+    if out is not None and (out.numel() if device else np.size(out)) < q:
+        raise ValueError(f"out holds fewer than qoff[-1] = {q} answers")
     flags = VALIDATE if validate else 0
     h = C.c_void_p()
     if device:

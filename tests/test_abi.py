@@ -264,3 +264,15 @@ def test_build_query_batch_rejects_bad_input_before_device_work():
     assert lib.pll_build_query_batch(2, vtx_off.ctypes.data, rp.ctypes.data, col.ctypes.data,
                                      order.ctypes.data, 0, q.ctypes.data, None, None, 0, None,
                                      C.byref(h)) == binding.E_INVAL  # pairs to answer, no buffers
+
+
+def test_build_query_batch_binding_checks_buffer_sizes():
+    # the binding refuses arrays shorter than qoff says before any call
+    vtx_off, rp, col, order = gen.pack_batch([graphs.cycle(4), graphs.path(3)])
+    with pytest.raises(ValueError):
+        binding.build_query_batch(vtx_off, rp, col, order, 0, [0, 2, 3], np.zeros((2, 2), np.int32))
+    with pytest.raises(ValueError):
+        binding.build_query_batch(vtx_off, rp, col, order, 0, [0, 3], np.zeros((3, 2), np.int32))
+    with pytest.raises(ValueError):
+        binding.build_query_batch(vtx_off, rp, col, order, 0, [0, 2, 3], np.zeros((3, 2), np.int32),
+                                  out=np.zeros(2, np.uint8))
