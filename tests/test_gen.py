@@ -105,3 +105,16 @@ def test_closeness_order():
     o = gen.closeness_order(g, samples=16, seed=1)
     assert sorted(o.tolist()) == list(range(g.n))
     assert np.array_equal(o, gen.closeness_order(g, samples=16, seed=1))
+
+
+def test_batch_workload_recipe():
+    # the 256-graph batch as stated for the benchmark: sizes drawn
+    # log-uniformly in [1e3, 2e5] (seeds 4000 + i), 8,888,217 vertices and
+    # 41,301,184 undirected edges in all; 72 graphs have at most 4,096
+    # vertices (the ones built whole by default)
+    spec = gen.batch_spec(256, seed_base=4000)
+    assert len(spec) == 256 and all(1000 <= n <= 200_000 and 2 <= m <= 8 for n, m, _ in spec)
+    assert sum(n for n, _, _ in spec) == 8_888_217
+    assert sum(1 for n, _, _ in spec if n <= 4096) == 72
+    gs = [gen.ba_graph(n, m, s) for n, m, s in spec]
+    assert sum(int(g.row_ptr[-1]) for g in gs) // 2 == 41_301_184
