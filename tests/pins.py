@@ -109,6 +109,23 @@ def check_canonical_labels(ix, g, order) -> list[str]:
     return fails
 
 
+def check_hubs_not_above_vertex(ix, g, order) -> list[str]:
+    """No vertex holds a hub ranked after itself: when the search from v_k
+    reaches a vertex of lower rank, that vertex was a root already (or a
+    bit-parallel root or neighbour), so the labels of roots < k answer its
+    distance to v_k exactly and the test prunes it (Theorem 4.1's argument,
+    Section 5.3 for the bit-parallel vertices).  This is what lets the GPU
+    leave such neighbours unvisited without testing them."""
+    fails = []
+    for r in range(g.n):
+        h, _ = ix.label(r)
+        if len(h) and int(h.max()) > r:
+            fails.append(f"L(rank {r}) holds hub {int(h.max())}")
+            if len(fails) > 3:
+                break
+    return fails
+
+
 def check_query_parts(ix, g, order, D) -> list[str]:
     """Bit-parallel part = explicit minimum over {r} and S_r (Section 5.3);
     normal part = 2-hop query over the labels (Section 3.3)."""
@@ -257,8 +274,8 @@ def check_paths(ix, g, order, D) -> list[str]:
 
 
 ALL = (check_queries_vs_apsp, check_bp_selection, check_bp_closed_form,
-       check_canonical_labels, check_query_parts, check_visited_counter,
-       check_parents, check_paths)
+       check_canonical_labels, check_hubs_not_above_vertex, check_query_parts,
+       check_visited_counter, check_parents, check_paths)
 
 
 def run_all(g, order, t_bp, lib=None, checks=ALL) -> list[str]:
