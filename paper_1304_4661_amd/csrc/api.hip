@@ -868,8 +868,19 @@ struct Builder {
     check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int32_t grid = std::max(1, std::min(ng, 2 * cus));
     // whole_pool entries per vertex here, and the windows' first share (as
-    // store_init gives every vertex of a single graph)
+    // store_init gives every vertex of a single graph); at most half the
+    // free device memory (5 bytes an entry), at least 16 entries a vertex
+    // (a pool that runs out is doubled below)
     int64_t want = verts * tu.whole_pool + 32 * nwin + 64;
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        const int64_t cap = std::max<int64_t>((int64_t)(fr / 2 / 5), 16 * verts + 32 * nwin + 64);
+        want = std::min<int64_t>(want, cap);
+      } else {
+        (void)hipGetLastError();
+      }
+    }
     for (;;) {
       if (want != S.pool_cap) {  // nothing to keep: the windows have not run
         S.hub.alloc((size_t)want);
