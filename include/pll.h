@@ -576,7 +576,7 @@ int pll_serve_bench(const pll_index *idx, double rate, int64_t nreq, int64_t max
  * windows after one that averaged at least "sort_level" (default 2^20)
  * visits or "sort_scan" (default 2^23) scanned label entries per level,
  * else 0; same labels), "xgroup" (lanes per candidate expanding
- * its adjacency list: 4..64), "list_cap" (upper bound on the entries of
+ * its adjacency list: 4..64, default 8), "list_cap" (upper bound on the entries of
  * the frontier, candidate and task lists, never below what one root needs;
  * 0 = sized from the window; a window that overflows is re-run with a
  * quarter of the roots), "table_cap" (first size of the root-table area in

@@ -26,7 +26,7 @@ struct Tuning {
   int64_t list_cap = 0;   // cap on frontier / candidate / task lists (0: sized from W)
   int64_t table_cap = 0;  // first size of the root-table area (0: sized from W)
   int group = 0;      // lanes per frontier entry (prune tests; 0: chosen per window)
-  int xgroup = 16;    // lanes per candidate expanding its adjacency list
+  int xgroup = 8;     // lanes per candidate expanding its adjacency list
   int wgroup = 64;    // lanes per frontier entry of a weighted search step
   int64_t wwork = 2000000;  // touched entries aimed at per weighted window
   int64_t pool_keep_mb = 16384;  // freed device memory kept for reuse by later builds
