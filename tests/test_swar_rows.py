@@ -4,7 +4,9 @@ per 16-bit field, 255 never counting) and the 4-bit copy (byte k of a packed
 row holds slot k and slot k + tpad/2, each min(d, 15); a nibble of 15 is
 widened to 255).  The 4-bit form must never claim a prune the 8-bit rows do
 not (so labels cannot change), and must claim exactly those whose reached
-vertex's slot distance is below 15."""
+vertex's slot distance is below 15.  Also the prune test's bit-parallel
+screen per word (which slots prune by distances alone, which need the sets
+for a -1 or -2 correction)."""
 import numpy as np
 import pytest
 
@@ -85,3 +87,46 @@ def test_saturated_nibble_never_counts():
     x = np.full(64, 15, np.uint8)  # 15 or more
     assert direct_full(root, x, 15)  # the 8-bit rows know 0 + 15 <= 15
     assert not direct_packed(root, pack(x), 254)  # the 4-bit copy claims nothing
+
+
+def swar_word(aw, bw, D):
+    """The prune test's per-word bit-parallel screen (k_win_test): byte
+    sums a + c of the root's and the vertex's distances, two at a time in
+    16-bit fields; hit when some sum is at most D, and per byte the slots
+    whose sum is exactly D + 1 (n2: a -1 or -2 correction would prune) or
+    D + 2 (n1: only -2 would), both distances finite."""
+    K1 = ((D + 1) * 0x00010001) & M32
+    K2 = ((D + 2) * 0x00010001) & M32
+    hit = 0
+    z1, z2 = [0, 0], [0, 0]
+    for h in range(2):
+        a = (aw >> (8 * h)) & 0x00FF00FF
+        c = (bw >> (8 * h)) & 0x00FF00FF
+        s = a + c
+        hit |= ~(((s | 0x80008000) - K1) & M32) & 0x80008000
+        inf = ((((a + 0x00010001) | (c + 0x00010001)) >> 8) & 0x00010001)
+        s |= inf * 0x1FF
+        x1, x2 = s ^ K1, s ^ K2
+        z1[h] = ~(((x1 | 0x80008000) - 0x00010001) & M32) & 0x80008000
+        z2[h] = ~(((x2 | 0x80008000) - 0x00010001) & M32) & 0x80008000
+    n2 = ((z1[0] >> 15) & 1) | ((z1[1] >> 14) & 2) | ((z1[0] >> 29) & 4) | ((z1[1] >> 28) & 8)
+    n1 = ((z2[0] >> 15) & 1) | ((z2[1] >> 14) & 2) | ((z2[0] >> 29) & 4) | ((z2[1] >> 28) & 8)
+    return hit != 0, n1, n2
+
+
+def test_bit_parallel_screen_words():
+    rng = np.random.default_rng(11)
+    for it in range(20000):
+        a = rng.integers(0, 130, 4)
+        c = rng.integers(0, 130, 4)
+        a[rng.random(4) < 0.15] = 255
+        c[rng.random(4) < 0.15] = 255
+        D = int(rng.integers(0, 255))
+        aw = int(np.asarray(a, np.uint8).view("<u4")[0])
+        bw = int(np.asarray(c, np.uint8).view("<u4")[0])
+        hit, n1, n2 = swar_word(aw, bw, D)
+        fin = (a != 255) & (c != 255)
+        s = a.astype(np.int64) + c
+        assert hit == bool(np.any(s <= D)), it
+        assert n2 == sum(1 << i for i in range(4) if fin[i] and s[i] == D + 1), it
+        assert n1 == sum(1 << i for i in range(4) if fin[i] and s[i] == D + 2), it
