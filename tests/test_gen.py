@@ -1,9 +1,13 @@
 """Input generators: determinism and the CSR conventions every input obeys."""
+import os
+
 import numpy as np
 from scipy.sparse import csr_matrix
 from scipy.sparse.csgraph import connected_components
 
 from paper_1304_4661_amd import gen
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _check_csr(g):
@@ -118,3 +122,18 @@ def test_batch_workload_recipe():
     assert sum(1 for n, _, _ in spec if n <= 4096) == 72
     gs = [gen.ba_graph(n, m, s) for n, m, s in spec]
     assert sum(int(g.row_ptr[-1]) for g in gs) // 2 == 41_301_184
+
+
+def test_generators_reproduce_the_full_size_digests():
+    # the stored full-size oracle results were made from these exact CSRs
+    # (tests/golden/make_full_digests.py); the GPU's full-size parity
+    # tests compare against them, so the inputs must not drift
+    import json
+    gold = json.load(open(os.path.join(GOLDEN, "full_rmat20.json")))
+    g, order, _, _ = gen.config_graph("rmat20")
+    assert gen.csr_sha256(g, order) == gold["csr_sha256"]
+    gold = json.load(open(os.path.join(GOLDEN, "full_ba256.json")))
+    spec = gen.batch_spec(256, seed_base=4000)
+    for i, (n, m, s) in enumerate(spec):
+        g = gen.ba_graph(n, m, s)
+        assert gen.csr_sha256(g, gen.degree_order(g)) == gold["graphs"][i]["csr_sha256"], i
